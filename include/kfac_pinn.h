@@ -1,0 +1,227 @@
+/*
+ * kfac_pinn.h -- C ABI of the MI355X (gfx950) KFAC-PINN library.
+ *
+ * One KFAC step for a physics-informed neural network loss, as defined in
+ * Dangel, Mueller & Zeinhofer, "Kronecker-Factored Approximate Curvature for
+ * Physics-Informed Neural Networks" (NeurIPS 2024):
+ *   forward Laplacian of a tanh MLP (Section 3.1, Eq. forward-laplacian-main),
+ *   PDE residual and loss (Section 2.1, Eq. pinn-loss), output gradients by a
+ *   backward pass (Algorithm 1), Kronecker factors (Section 3.2, Eq. KFAC-PINN;
+ *   Eq. kfac-linear for the boundary term), EMA + damping and the inverse of
+ *   the Kronecker sum (Section 3.4), momentum and grid line search (Section 3.4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Network: L = n_layers linear layers with widths[0] = d inputs, widths[L] = 1
+ *   output, tanh between layers.  Parameters theta follow Section 2: layer l's
+ *   augmented matrix [W | b] (h_out x (h_in+1)) is stacked column by column
+ *   (bias is the last column), layers are concatenated; D = sum h_out (h_in+1).
+ * Element type "real": double for KP_F64, float for KP_F32 and KP_MIXED_BF16
+ *   (FP32 master parameters).  Points are row-major n x d reals, targets are n
+ *   reals.  Factors, gradients and preconditioners are always double.
+ * Residuals: interior r = c_t du/dx_t + c_lap sum_{i in mask} d2u/dx_i^2 - y
+ *   (Poisson -Lap u = f: c_t = 0, c_lap = -1, y = f; heat u_t = kappa Lap_x u:
+ *   c_t = 1, c_lap = -kappa, t excluded from the mask); boundary r = u - y.
+ *   Loss L = sum r^2/(2N) + sum r_b^2/(2M).
+ * Pointers: every array argument is DEVICE memory owned by the caller unless
+ *   the comment says "host".  It must stay valid until the work enqueued on the
+ *   context's stream has finished.  The context owns all workspaces (allocated
+ *   once in kfac_pinn_create); no other entry point allocates.
+ * Errors: invalid arguments return KP_ERR_ARG synchronously and enqueue
+ *   nothing.  HIP launch failures return KP_ERR_HIP.  Failures found on the
+ *   device (a factor that is not positive definite, non-finite losses) set the
+ *   context's device status word; the parameter update is then skipped (theta
+ *   and the momentum stay untouched) and kfac_pinn_sync returns the code.
+ * Threads: a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef KFAC_PINN_H
+#define KFAC_PINN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kfac_pinn_ctx kfac_pinn_ctx;
+
+typedef enum {
+  KP_OK = 0,
+  KP_ERR_ARG = 1,
+  KP_ERR_OOM = 2,
+  KP_ERR_HIP = 3,
+  KP_ERR_NOT_PD = 4,
+  KP_ERR_NONFINITE = 5,
+  KP_ERR_STATE = 6
+} kp_status;
+
+typedef enum {
+  KP_F64 = 0,        /* everything in FP64 (the paper's precision)                 */
+  KP_F32 = 1,        /* FP32 slabs and matrix products, FP64 factors and inversion */
+  KP_MIXED_BF16 = 2  /* BF16 slabs, BF16 MFMA with FP32 accumulation (parameters
+                        enter the products as a BF16 hi + lo pair), FP32 elementwise
+                        work, FP64 factors and inversion                            */
+} kp_precision;
+
+typedef struct {
+  int32_t n_layers;             /* L >= 1                                          */
+  const int32_t* widths;        /* host, L+1 entries; widths[L] must be 1           */
+  int32_t time_coord;           /* input index of t for c_t, or -1                  */
+  double coef_time;             /* c_t                                              */
+  double coef_lap;              /* c_lap                                            */
+  const uint8_t* lap_mask;      /* host, d entries (1 = in the Laplacian row); NULL = all */
+  int32_t precision;            /* kp_precision                                     */
+  int32_t max_interior;         /* capacity in interior points per call             */
+  int32_t max_boundary;         /* capacity in boundary points per call             */
+  size_t workspace_limit_bytes; /* 0 = unlimited.  When the stored slabs of
+                                   kfac_pinn_forward_laplacian would exceed it, the
+                                   forward keeps no intermediates and the VJP
+                                   recomputes each layer's input from x.            */
+} kp_problem;
+
+typedef struct {
+  double lambda;        /* damping added to all four factors (Section 3.4)          */
+  double beta;          /* EMA factor in [0, 1)                                     */
+  double momentum;      /* mu                                                       */
+  int32_t lr_mode;      /* 0: fixed alpha = lr; 1: grid line search                 */
+  double lr;            /* fixed step (lr_mode 0)                                   */
+  int32_t grid_min_exp; /* grid alpha = 2^k, k = grid_max_exp .. grid_min_exp       */
+  int32_t grid_max_exp; /* (the paper: -30 .. 0)                                    */
+} kp_hparams;
+
+/* Written on the device by kfac_pinn_step (when the pointer is non-NULL). */
+typedef struct {
+  double loss_interior;  /* L_Omega at theta_t                                     */
+  double loss_boundary;  /* L_dOmega at theta_t                                    */
+  double lr_chosen;      /* alpha* (0 when no step was taken)                      */
+  double loss_after;     /* L(theta_t + delta_t) (grid mode; NaN in fixed mode)     */
+  int32_t status;        /* kp_status of this step                                  */
+  int32_t step;          /* step counter after this step                            */
+} kp_step_info;
+
+/* Seeded sampler (kfac_pinn_sample).  Values come from SplitMix64 (Steele, Lea &
+   Flood 2014) used as a counter-based generator, u = (z >> 11) * 2^-53. */
+typedef struct {
+  uint64_t seed_interior, seed_boundary, seed_initial;
+  int32_t n_interior, n_boundary, n_initial;
+  int32_t face_lo;      /* faces x_k in {0,1} for k >= face_lo (1 for heat: t is free) */
+  int32_t target_kind;  /* 0: f = c pi^2 sum sin(pi x_i), g = c sum sin(pi x_i)
+                           1: f = 2 pi^2 sin(pi x0) sin(pi x1), g = 0
+                           2: heat, f = 0, g = exp(-kappa pi^2 x0) sum_{i>=1} sin(pi x_i) */
+  double scale;         /* c                                                        */
+  double kappa;
+} kp_sampler;
+
+/* ---- lifetime --------------------------------------------------------------
+ * kfac_pinn_create: validates `problem`, allocates every workspace for the
+ * stated capacities on the current HIP device, and binds `stream` (a
+ * hipStream_t; NULL = the default stream).  *out receives the handle.
+ * Factors start at the identity, the momentum at zero.  KP_ERR_OOM if the
+ * workspaces do not fit. */
+kp_status kfac_pinn_create(const kp_problem* problem, void* stream, kfac_pinn_ctx** out);
+kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx);
+
+/* Algorithm 1, step 0: every Kronecker factor to I (init_identity != 0) or 0;
+   momentum and step counter to zero. */
+kp_status kfac_pinn_reset_state(kfac_pinn_ctx* ctx, int32_t init_identity);
+
+/* Number of parameters D for the given widths (host, n_layers+1 entries). */
+int64_t kfac_pinn_num_params(const int32_t* widths, int32_t n_layers);
+
+/* ---- a1: sampling ----------------------------------------------------------
+ * Draws one batch for training step `step` (counter offset step * count *
+ * draws-per-point) into x_int (n_interior x d), y_int, x_bnd and y_bnd
+ * ((n_initial + n_boundary) x d; initial points first), all "real".
+ * Interior points are uniform in [0,1)^d.  A boundary point picks a face with
+ * one draw (f = floor(u * 2(d - face_lo)); coordinate face_lo + f/2 is set to
+ * f mod 2) and its coordinates with d more.  Initial points have x_0 = 0.
+ * Targets follow the manufactured solutions of Section 4 / Appendix A. */
+kp_status kfac_pinn_sample(kfac_pinn_ctx* ctx, const kp_sampler* sampler, int64_t step,
+                           void* x_int, void* y_int, void* x_bnd, void* y_bnd);
+
+/* ---- a2: forward Laplacian (Section 3.1, Eq. forward-laplacian-main) -------
+ * For n points x (n x d) computes the network value u (n), the gradient
+ * du/dx (n x d, row-major; may be NULL) and the operator's second-order row
+ * sum_{i in mask} d2u/dx_i^2 (n; may be NULL).  Keeps the layer slabs for a
+ * following kfac_pinn_forward_laplacian_vjp unless the workspace limit forbids
+ * it.  n <= max_interior. */
+kp_status kfac_pinn_forward_laplacian(kfac_pinn_ctx* ctx, const void* theta, const void* x,
+                                      int32_t n, void* u_out, void* grad_out, void* lap_out);
+
+/* Vector-Jacobian product of kfac_pinn_forward_laplacian at (theta, x): given
+ * cotangents u_bar (n), grad_bar (n x d) and lap_bar (n) (any may be NULL =
+ * zero) writes theta_bar (D, double) and x_bar (n x d real; may be NULL).
+ * It is the backward pass of Algorithm 1 with a general seed; layer inputs come
+ * from the slabs of the preceding forward call on the same (theta, x, n), or
+ * are recomputed from x under a workspace limit. */
+kp_status kfac_pinn_forward_laplacian_vjp(kfac_pinn_ctx* ctx, const void* theta, const void* x,
+                                          int32_t n, const void* u_bar, const void* grad_bar,
+                                          const void* lap_bar, double* theta_bar, void* x_bar);
+
+/* ---- a2-a7: curvature (Algorithm 1, steps 1-2 and 4) ------------------------
+ * Forward Laplacian over the interior points, plain forward over the boundary
+ * points, residuals, one backward pass per term for the output gradients g,
+ * the Kronecker factors of Eq. KFAC-PINN (interior: A = sum Z~Z~^T/(N S),
+ * B = sum g g^T/N) and Eq. kfac-linear (boundary: A = sum z~z~^T/M,
+ * B = sum g g^T/M), folded into the context's factors by the EMA
+ * A <- beta A + (1 - beta) A_new.  Optionally writes the loss gradient
+ * (grad_out, D doubles, Algorithm 1 step 4) and {L_Omega, L_dOmega}
+ * (loss_out, 2 doubles). */
+kp_status kfac_pinn_factors(kfac_pinn_ctx* ctx, const void* theta,
+                            const void* x_int, const void* y_int, int32_t n_int,
+                            const void* x_bnd, const void* y_bnd, int32_t n_bnd,
+                            double beta, double* grad_out, double* loss_out);
+
+/* ---- a8: damped Kronecker-sum factorisation (Section 3.4) -------------------
+ * For every layer and side, damps the EMA factors (+ lambda I) and computes,
+ * in FP64, P and e with P^T F1 P = I and P^T F2 P = diag(e) for the pair
+ * (F1, F2) = (interior, boundary) factor: a Cholesky factor of F1, then a
+ * Jacobi eigendecomposition of the whitened F2.  The inverse of the Kronecker
+ * sum is then (P_A (x) P_B) (I + e_A (x) e_B)^-1 (P_A (x) P_B)^T.  Sets
+ * KP_ERR_NOT_PD in the device status when a damped interior factor is not
+ * positive definite. */
+kp_status kfac_pinn_invert(kfac_pinn_ctx* ctx, double lambda);
+
+/* Delta = -(A_i (x) B_i + A_b (x) B_b)^-1 g per layer with the preconditioner of
+ * the last kfac_pinn_invert (grad_in, delta_out: D doubles each). */
+kp_status kfac_pinn_precondition(kfac_pinn_ctx* ctx, const double* grad_in, double* delta_out);
+
+/* ---- a1-a9: one full KFAC step (Algorithm 1, one iteration) -----------------
+ * Factors and gradient at theta_inout, EMA (beta), damping and inversion
+ * (lambda), Delta = -C g, momentum delta^ = mu delta_{t-1} + Delta (delta_{-1} =
+ * 0), the learning rate (fixed, or argmin of L(theta + 2^k delta^) over the grid
+ * with ties to the larger step and non-finite losses skipped), then
+ * theta_inout += alpha delta^ and delta_t = alpha delta^.  Nothing is read back
+ * to the host; `info` (device, may be NULL) receives the step's summary. */
+kp_status kfac_pinn_step(kfac_pinn_ctx* ctx, void* theta_inout,
+                         const void* x_int, const void* y_int, int32_t n_int,
+                         const void* x_bnd, const void* y_bnd, int32_t n_bnd,
+                         const kp_hparams* hp, kp_step_info* info);
+
+/* ---- state access (tests, checkpoints) -------------------------------------
+ * term: 0 interior, 1 boundary; side: 0 A ((h_in+1)^2), 1 B (h_out^2);
+ * row-major dense doubles. */
+kp_status kfac_pinn_get_factor(kfac_pinn_ctx* ctx, int32_t layer, int32_t term, int32_t side,
+                               double* dev_out);
+kp_status kfac_pinn_set_factor(kfac_pinn_ctx* ctx, int32_t layer, int32_t term, int32_t side,
+                               const double* dev_in);
+/* P (n x n row-major) and e (n) of the last kfac_pinn_invert for layer/side. */
+kp_status kfac_pinn_get_preconditioner(kfac_pinn_ctx* ctx, int32_t layer, int32_t side,
+                                       double* p_out, double* e_out);
+/* The 1 + grid_max_exp - grid_min_exp candidate losses of the last grid step. */
+kp_status kfac_pinn_get_line_search(kfac_pinn_ctx* ctx, double* dev_out);
+/* Momentum buffer delta_{t} (D reals) and step counter. */
+kp_status kfac_pinn_get_momentum(kfac_pinn_ctx* ctx, void* dev_out);
+kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* ctx, const void* dev_in, int64_t step);
+
+/* Waits for the context's stream; returns the device status word (and clears it). */
+kp_status kfac_pinn_sync(kfac_pinn_ctx* ctx);
+const char* kfac_pinn_status_string(kp_status status);
+/* Text of the last host-side error (thread-local). */
+const char* kfac_pinn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFAC_PINN_H */

@@ -1,0 +1,249 @@
+"""MI355X (gfx950) KFAC for PINN losses.
+
+Python binding of libkfac_pinn.so (include/kfac_pinn.h).  PyTorch provides device
+memory and the HIP stream; every step of the computation runs in the library's
+HIP kernels.  Method names follow the C entry points without the `kfac_pinn_`
+prefix; the raw entry points are in `paper_2405_15603_amd._native`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as N
+from ._native import KP_F32, KP_F64, KP_MIXED_BF16, KfacPinnError
+
+PRECISIONS = {"f64": KP_F64, "f32": KP_F32, "bf16": KP_MIXED_BF16}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class HParams:
+    """Hyper-parameters of one step (Section 3.4): damping lambda, EMA beta,
+    momentum mu, and the learning rate: a grid line search over 2^k,
+    k = grid_max_exp .. grid_min_exp, or a fixed step."""
+    lam: float = 1e-3
+    beta: float = 0.0
+    momentum: float = 0.0
+    lr_mode: str = "grid"
+    lr: float = 1.0
+    grid_min_exp: int = -30
+    grid_max_exp: int = 0
+
+    def c(self) -> N.kp_hparams:
+        return N.kp_hparams(self.lam, self.beta, self.momentum, 1 if self.lr_mode == "grid" else 0,
+                            self.lr, self.grid_min_exp, self.grid_max_exp)
+
+
+class KfacPinn:
+    """One KFAC-PINN context: a tanh MLP with the given widths, an interior
+    operator c_t d/dx_t + c_lap sum_{i in mask} d2/dx_i^2 and capacities."""
+
+    def __init__(self, widths: Sequence[int], precision: str = "f32", time_coord: int = -1,
+                 coef_time: float = 0.0, coef_lap: float = -1.0, lap_mask=None,
+                 max_interior: int = 4096, max_boundary: int = 4096,
+                 workspace_limit_bytes: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("KfacPinn needs a GPU (HIP device); there is no CPU path")
+        self.lib = N.lib()
+        self.widths = [int(w) for w in widths]
+        self.L = len(self.widths) - 1
+        self.d = self.widths[0]
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._w = (C.c_int32 * len(self.widths))(*self.widths)
+        self._mask = None
+        if lap_mask is not None:
+            self._mask = (C.c_uint8 * self.d)(*[1 if m else 0 for m in lap_mask])
+        prob = N.kp_problem(self.L, self._w, time_coord, coef_time, coef_lap,
+                            self._mask if self._mask is not None else None,
+                            PRECISIONS[precision], max_interior, max_boundary,
+                            workspace_limit_bytes)
+        h = C.c_void_p()
+        N.check(self.lib.kfac_pinn_create(C.byref(prob), C.c_void_p(self.stream.cuda_stream),
+                                          C.byref(h)), "kfac_pinn_create")
+        self.h = h
+        self.D = int(self.lib.kfac_pinn_num_params(self._w, self.L))
+        self.max_interior, self.max_boundary = max_interior, max_boundary
+
+    @classmethod
+    def for_problem(cls, problem, precision="f32", **kw):
+        """Context for a problem description (synthetic workloads carry widths,
+        operator coefficients and point counts)."""
+        kw.setdefault("max_interior", problem.n_interior)
+        kw.setdefault("max_boundary", problem.n_cond)
+        return cls(problem.widths, precision, problem.time_coord, problem.coef_time,
+                   problem.coef_lap, list(problem.lap_mask), **kw)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize()
+                self.lib.kfac_pinn_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    # -- helpers -------------------------------------------------------------
+    def _real(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        if t.device.type != "cuda" or t.dtype != self.dtype or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {self.dtype} CUDA tensor")
+        return t
+
+    def empty(self, *shape, dtype=None) -> torch.Tensor:
+        return torch.empty(*shape, dtype=dtype or self.dtype, device=self.device)
+
+    # -- entry points --------------------------------------------------------
+    def reset_state(self, init_identity: bool = True) -> None:
+        N.check(self.lib.kfac_pinn_reset_state(self.h, 1 if init_identity else 0),
+                "kfac_pinn_reset_state")
+
+    def sample(self, sampler: N.kp_sampler, step: int, n_int: int, n_cond: int):
+        xi, yi = self.empty(n_int, self.d), self.empty(n_int)
+        xb, yb = self.empty(n_cond, self.d), self.empty(n_cond)
+        N.check(self.lib.kfac_pinn_sample(self.h, C.byref(sampler), step, _ptr(xi), _ptr(yi),
+                                          _ptr(xb), _ptr(yb)), "kfac_pinn_sample")
+        return xi, yi, xb, yb
+
+    def forward_laplacian(self, theta: torch.Tensor, x: torch.Tensor):
+        theta, x = self._real(theta, "theta"), self._real(x, "x")
+        n = x.shape[0]
+        u, g, lap = self.empty(n), self.empty(n, self.d), self.empty(n)
+        N.check(self.lib.kfac_pinn_forward_laplacian(self.h, _ptr(theta), _ptr(x), n, _ptr(u),
+                                                     _ptr(g), _ptr(lap)),
+                "kfac_pinn_forward_laplacian")
+        return u, g, lap
+
+    def forward_laplacian_vjp(self, theta, x, u_bar=None, grad_bar=None, lap_bar=None,
+                              want_x_bar=True):
+        theta, x = self._real(theta, "theta"), self._real(x, "x")
+        n = x.shape[0]
+        tb = self.empty(self.D, dtype=torch.float64)
+        xb = self.empty(n, self.d) if want_x_bar else None
+        args = [None if a is None else self._real(a, nm)
+                for a, nm in ((u_bar, "u_bar"), (grad_bar, "grad_bar"), (lap_bar, "lap_bar"))]
+        N.check(self.lib.kfac_pinn_forward_laplacian_vjp(self.h, _ptr(theta), _ptr(x), n,
+                                                         *[_ptr(a) for a in args], _ptr(tb),
+                                                         _ptr(xb)),
+                "kfac_pinn_forward_laplacian_vjp")
+        return tb, xb
+
+    def factors(self, theta, xi, yi, xb, yb, beta: float = 0.0):
+        grad = self.empty(self.D, dtype=torch.float64)
+        loss = self.empty(2, dtype=torch.float64)
+        N.check(self.lib.kfac_pinn_factors(self.h, _ptr(theta), _ptr(xi), _ptr(yi), xi.shape[0],
+                                           _ptr(xb), _ptr(yb), xb.shape[0], beta, _ptr(grad),
+                                           _ptr(loss)), "kfac_pinn_factors")
+        return grad, loss
+
+    def invert(self, lam: float) -> None:
+        N.check(self.lib.kfac_pinn_invert(self.h, lam), "kfac_pinn_invert")
+
+    def precondition(self, grad: torch.Tensor) -> torch.Tensor:
+        out = self.empty(self.D, dtype=torch.float64)
+        N.check(self.lib.kfac_pinn_precondition(self.h, _ptr(grad), _ptr(out)),
+                "kfac_pinn_precondition")
+        return out
+
+    def step(self, theta, xi, yi, xb, yb, hp: HParams, info: Optional[torch.Tensor] = None):
+        """One KFAC step; theta is updated in place.  Returns the device step
+        summary as 6 doubles' worth of bytes (use `decode_info`)."""
+        self._real(theta, "theta")
+        if info is None:
+            info = self.empty(C.sizeof(N.kp_step_info), dtype=torch.uint8)
+        hpc = hp.c()
+        N.check(self.lib.kfac_pinn_step(self.h, _ptr(theta), _ptr(xi), _ptr(yi), xi.shape[0],
+                                        _ptr(xb), _ptr(yb), xb.shape[0], C.byref(hpc),
+                                        _ptr(info)), "kfac_pinn_step")
+        return info
+
+    @staticmethod
+    def decode_info(info: torch.Tensor) -> dict:
+        raw = bytes(info.cpu().numpy().tobytes())
+        s = N.kp_step_info.from_buffer_copy(raw)
+        return {"loss_interior": s.loss_interior, "loss_boundary": s.loss_boundary,
+                "lr": s.lr_chosen, "loss_after": s.loss_after, "status": s.status,
+                "step": s.step}
+
+    def get_factor(self, layer: int, term: int, side: int) -> torch.Tensor:
+        n = self.widths[layer] + 1 if side == 0 else self.widths[layer + 1]
+        out = self.empty(n, n, dtype=torch.float64)
+        N.check(self.lib.kfac_pinn_get_factor(self.h, layer, term, side, _ptr(out)),
+                "kfac_pinn_get_factor")
+        return out
+
+    def set_factor(self, layer: int, term: int, side: int, value: torch.Tensor) -> None:
+        value = value.to(device=self.device, dtype=torch.float64).contiguous()
+        N.check(self.lib.kfac_pinn_set_factor(self.h, layer, term, side, _ptr(value)),
+                "kfac_pinn_set_factor")
+        self.sync()
+
+    def get_preconditioner(self, layer: int, side: int):
+        n = self.widths[layer] + 1 if side == 0 else self.widths[layer + 1]
+        P, e = self.empty(n, n, dtype=torch.float64), self.empty(n, dtype=torch.float64)
+        N.check(self.lib.kfac_pinn_get_preconditioner(self.h, layer, side, _ptr(P), _ptr(e)),
+                "kfac_pinn_get_preconditioner")
+        return P, e
+
+    def get_line_search(self, ncand: int = 31) -> torch.Tensor:
+        out = self.empty(ncand, dtype=torch.float64)
+        N.check(self.lib.kfac_pinn_get_line_search(self.h, _ptr(out)), "kfac_pinn_get_line_search")
+        return out
+
+    def get_momentum(self) -> torch.Tensor:
+        out = self.empty(self.D)
+        N.check(self.lib.kfac_pinn_get_momentum(self.h, _ptr(out)), "kfac_pinn_get_momentum")
+        return out
+
+    def set_momentum(self, delta: torch.Tensor, step: int) -> None:
+        N.check(self.lib.kfac_pinn_set_momentum(self.h, _ptr(self._real(delta, "delta")), step),
+                "kfac_pinn_set_momentum")
+
+    def sync(self) -> int:
+        """Waits for the stream; returns (and clears) the device status word."""
+        return int(self.lib.kfac_pinn_sync(self.h))
+
+
+class ForwardLaplacian(torch.autograd.Function):
+    """(u, du/dx, masked Laplacian) = forward Laplacian of the network at x, with
+    the hand-written adjoint of the library as its backward."""
+
+    @staticmethod
+    def forward(ctx, theta, x, kp: KfacPinn):
+        u, g, lap = kp.forward_laplacian(theta.detach().contiguous(), x.detach().contiguous())
+        ctx.kp = kp
+        ctx.save_for_backward(theta, x)
+        return u, g, lap
+
+    @staticmethod
+    def backward(ctx, u_bar, grad_bar, lap_bar):
+        theta, x = ctx.saved_tensors
+        kp = ctx.kp
+        cast = lambda t: None if t is None else t.to(kp.dtype).contiguous()
+        tb, xb = kp.forward_laplacian_vjp(theta.detach().contiguous(), x.detach().contiguous(),
+                                          cast(u_bar), cast(grad_bar), cast(lap_bar),
+                                          want_x_bar=ctx.needs_input_grad[1])
+        return tb.to(theta.dtype), (xb if ctx.needs_input_grad[1] else None), None
+
+
+def forward_laplacian(kp: KfacPinn, theta: torch.Tensor, x: torch.Tensor):
+    return ForwardLaplacian.apply(theta, x, kp)
+
+
+def sampler_for(problem, step_counts=None) -> N.kp_sampler:
+    """The GPU sampler's description of a synthetic problem's point sets."""
+    from synth import PURPOSE_BOUNDARY, PURPOSE_INITIAL, PURPOSE_INTERIOR
+    kind = 2 if problem.kind == "heat" else (1 if problem.name == "poisson2d" else 0)
+    return N.kp_sampler(problem.seed(PURPOSE_INTERIOR), problem.seed(PURPOSE_BOUNDARY),
+                        problem.seed(PURPOSE_INITIAL), problem.n_interior, problem.n_boundary,
+                        problem.n_initial, 1 if problem.kind == "heat" else 0, kind,
+                        problem.scale, problem.kappa)

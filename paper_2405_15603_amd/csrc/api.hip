@@ -1,0 +1,836 @@
+// Host side of the C ABI (include/kfac_pinn.h): context, workspace plan, and the
+// order of the launches that make up one KFAC step (Algorithm 1).  Everything
+// is enqueued on the context's stream; nothing here reads device data back
+// except kfac_pinn_sync.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kfac_pinn.h"
+#include "launch.h"
+
+using namespace kp;
+
+static thread_local std::string g_last_error;
+void kp_set_last_error(const char* msg, const char* file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s (%s:%d)", msg, file, line);
+  g_last_error = buf;
+}
+#define KP_ARG(cond, msg)                                  \
+  do {                                                     \
+    if (!(cond)) {                                         \
+      kp_set_last_error(msg, __FILE__, __LINE__);          \
+      return KP_ERR_ARG;                                   \
+    }                                                      \
+  } while (0)
+#define KP_TRY(expr)                                       \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) {                                \
+      kp_set_last_error(hipGetErrorString(_e), __FILE__, __LINE__); \
+      return KP_ERR_HIP;                                   \
+    }                                                      \
+  } while (0)
+
+namespace {
+
+constexpr int kMaxLayers = 8;
+constexpr int kMaxCand = 64;
+constexpr int kMaxSplits = 64;
+constexpr int kJacobiSweeps = 15;
+
+struct Slabs {            // one term (interior or boundary)
+  int S = 1, nd = 0, has_lap = 0, cap = 0;   // rows per point, derivative rows, capacity (points)
+  std::vector<void*> zin, pre, g;            // stored mode: per layer
+  void* zr[2] = {nullptr, nullptr};          // recompute mode: layer inputs (ping-pong)
+  void* prer = nullptr;                      // recompute mode: one pre-activation slab
+  void* gr[2] = {nullptr, nullptr};          // recompute mode: output gradients (ping-pong)
+  bool store = true;
+  double* r = nullptr;                       // residual per point
+};
+
+}  // namespace
+
+struct kfac_pinn_ctx {
+  int L = 0, d = 0;
+  std::vector<int> w;
+  int time_coord = -1;
+  double c_t = 0.0, c_lap = -1.0;
+  Prec P = P_F32;
+  size_t esz_p = 4, esz_s = 4, esz_c = 4;
+  int max_i = 0, max_b = 0;
+  size_t ws_limit = 0;
+  hipStream_t st = nullptr;
+  long D = 0;
+  NetDesc nd{};
+  std::vector<long> off, ldz, ldp, ldg;
+  int hmax = 0;
+  long ldz_max = 0, ldp_max = 0;
+
+  std::vector<void*> allocs;
+  uint8_t* mask = nullptr;
+  void *w_hi = nullptr, *w_lo = nullptr;
+  Slabs si, sb;
+  void* zbar = nullptr;
+  void* ls_z[2] = {nullptr, nullptr};
+  void* ls_pre = nullptr;
+  double* partial = nullptr;
+  int partial_n = 0;
+  double* loss = nullptr;              // [0] L_int [1] L_bnd [2..] candidates
+  int last_ncand = 0;
+  std::vector<double*> F[2][2];        // F[term][side][layer]
+  void* part = nullptr;
+  double* grad = nullptr;
+  double* Delta = nullptr;
+  void* dhat = nullptr;
+  void* delta = nullptr;
+  std::vector<EigProblem> probs;
+  EigProblem* probs_dev = nullptr;
+  G64* kdesc = nullptr;
+  int k_mmax = 0, k_nmax = 0;
+  int* ctl = nullptr;                  // [0] status [1] step [4..5] alpha [8..] Jacobi flags
+};
+
+namespace {
+
+hipError_t dmalloc(kfac_pinn_ctx* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) {
+    c->allocs.push_back(*p);
+    e = hipMemset(*p, 0, bytes);
+  }
+  return e;
+}
+
+size_t slab_bytes(const kfac_pinn_ctx* c, const Slabs& s, bool store) {
+  const size_t R = (size_t)s.cap * s.S;
+  size_t b = 0;
+  if (store) {
+    for (int l = 0; l < c->L; l++)
+      b += R * (c->ldz[l] * c->esz_s + c->ldp[l] * c->esz_c + c->ldg[l] * c->esz_s);
+  } else {
+    b = R * (2 * c->ldz_max * c->esz_s + c->ldp_max * c->esz_c + 2 * c->ldp_max * c->esz_s);
+  }
+  return b;
+}
+
+hipError_t alloc_slabs(kfac_pinn_ctx* c, Slabs& s) {
+  const size_t R = (size_t)s.cap * s.S;
+  if (s.store) {
+    s.zin.resize(c->L);
+    s.pre.resize(c->L);
+    s.g.resize(c->L);
+    for (int l = 0; l < c->L; l++) {
+      hipError_t e;
+      if ((e = dmalloc(c, &s.zin[l], R * c->ldz[l] * c->esz_s)) != hipSuccess) return e;
+      if ((e = dmalloc(c, &s.pre[l], R * c->ldp[l] * c->esz_c)) != hipSuccess) return e;
+      if ((e = dmalloc(c, &s.g[l], R * c->ldg[l] * c->esz_s)) != hipSuccess) return e;
+    }
+  } else {
+    hipError_t e;
+    for (int k = 0; k < 2; k++) {
+      if ((e = dmalloc(c, &s.zr[k], R * c->ldz_max * c->esz_s)) != hipSuccess) return e;
+      if ((e = dmalloc(c, &s.gr[k], R * c->ldp_max * c->esz_s)) != hipSuccess) return e;
+    }
+    if ((e = dmalloc(c, &s.prer, R * c->ldp_max * c->esz_c)) != hipSuccess) return e;
+  }
+  return dmalloc(c, (void**)&s.r, sizeof(double) * (s.cap > 0 ? s.cap : 1));
+}
+
+inline char* wptr(void* base, long elems, size_t esz) { return (char*)base + elems * esz; }
+
+// Forward through layers [0, upto] for one term.  Layer inputs go to zdst(l),
+// pre-activations to pdst(l).  Returns the launch status.
+template <class ZD, class PD>
+hipError_t forward_layers(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, int upto,
+                          ZD zdst, PD pdst) {
+  hipError_t e;
+  const int R = n * s.S;
+  if ((e = input_slab(c->P, x, n, c->d, s.S, zdst(0), c->ldz[0], c->st)) != hipSuccess) return e;
+  for (int l = 0; l <= upto; l++) {
+    const LayerDesc& ld = c->nd.l[l];
+    void* lo = c->w_lo ? wptr(c->w_lo, ld.wrm, c->esz_s) : nullptr;
+    if ((e = gemm_nt(c->P, zdst(l), c->ldz[l], wptr(c->w_hi, ld.wrm, c->esz_s), lo, ld.ldk_in, R,
+                     ld.h_out, ld.h_in + 1, pdst(l), c->ldp[l], nullptr, s.S, c->st)) != hipSuccess)
+      return e;
+    if (l < upto) {
+      if ((e = act_fwd(c->P, pdst(l), c->ldp[l], zdst(l + 1), c->ldz[l + 1], n, s.S, s.nd,
+                       s.has_lap, c->mask, ld.h_out, c->st)) != hipSuccess)
+        return e;
+    }
+  }
+  return hipSuccess;
+}
+
+int lap_row_of(const Slabs& s) { return s.has_lap ? s.S - 1 : -1; }
+int time_row_of(const kfac_pinn_ctx* c, const Slabs& s) {
+  return (s.has_lap && c->time_coord >= 0 && c->c_t != 0.0) ? 1 + c->time_coord : -1;
+}
+
+// Full forward for the curvature pass (stores what the backward sweep needs).
+hipError_t forward_store(kfac_pinn_ctx* c, Slabs& s, const void* x, int n) {
+  if (s.store)
+    return forward_layers(c, s, x, n, c->L - 1, [&](int l) { return s.zin[l]; },
+                          [&](int l) { return s.pre[l]; });
+  // recompute mode: only the output layer's pre-activations are kept (in prer)
+  return forward_layers(c, s, x, n, c->L - 1, [&](int l) { return s.zr[l & 1]; },
+                        [&](int l) { return s.prer; });
+}
+
+// residual, loss[slot] and the seed rows of the last layer
+hipError_t residual_and_seed(kfac_pinn_ctx* c, Slabs& s, const void* pre_last, const void* y,
+                             int n, void* g_last, int slot, int accumulate) {
+  hipError_t e;
+  const int nb = residual_blocks(n);
+  if ((e = residual(c->P, pre_last, c->ldp[c->L - 1], y, n, s.S, time_row_of(c, s), c->c_t,
+                    c->c_lap, lap_row_of(s), s.r, g_last, c->ldg[c->L - 1], c->partial, c->st)) !=
+      hipSuccess)
+    return e;
+  return finalize_loss(c->partial, nb, 0.5 / (double)n, c->loss, slot, accumulate, c->st);
+}
+
+// Consumer of one layer during the backward sweep.
+struct LayerConsumer {
+  virtual hipError_t operator()(int l, const void* zin, const void* g) = 0;
+};
+
+// Backward sweep from the last layer's seed (already in g(L-1)).  For each
+// layer l (last to first) hands (Z~^(l), g^(l)) to `use`, then forms
+// g^(l-1) = tanh-adjoint(W^T g^(l)).  Recompute mode re-runs the forward up to
+// layer l-1 from x whenever layer inputs are needed.
+hipError_t backward_sweep(kfac_pinn_ctx* c, Slabs& s, const void* x, int n, LayerConsumer& use) {
+  hipError_t e;
+  const int R = n * s.S;
+  for (int l = c->L - 1; l >= 0; l--) {
+    const void* zin;
+    const void* g = s.store ? s.g[l] : s.gr[l & 1];
+    const void* pre_prev = nullptr;
+    if (s.store) {
+      zin = s.zin[l];
+      pre_prev = l > 0 ? s.pre[l - 1] : nullptr;
+    } else {
+      // recompute layers 0..l-1: Z~^(l) = act(pre^(l-1)), pre^(l-1) kept in prer
+      if (l == 0) {
+        if ((e = input_slab(c->P, x, n, c->d, s.S, s.zr[0], c->ldz[0], c->st)) != hipSuccess)
+          return e;
+        zin = s.zr[0];
+      } else {
+        if ((e = forward_layers(c, s, x, n, l - 1, [&](int k) { return s.zr[k & 1]; },
+                                [&](int k) { return s.prer; })) != hipSuccess)
+          return e;
+        if ((e = act_fwd(c->P, s.prer, c->ldp[l - 1], s.zr[l & 1], c->ldz[l], n, s.S, s.nd,
+                         s.has_lap, c->mask, c->nd.l[l - 1].h_out, c->st)) != hipSuccess)
+          return e;
+        zin = s.zr[l & 1];
+        pre_prev = s.prer;
+      }
+    }
+    if ((e = use(l, zin, g)) != hipSuccess) return e;
+    if (l == 0) break;
+    const LayerDesc& ld = c->nd.l[l];
+    void* lo = c->w_lo ? wptr(c->w_lo, ld.wcm, c->esz_s) : nullptr;
+    if ((e = gemm_nt(c->P, g, c->ldg[l], wptr(c->w_hi, ld.wcm, c->esz_s), lo, ld.ldk_out, R,
+                     ld.h_in, ld.h_out, c->zbar, c->ldp_max, nullptr, s.S, c->st)) != hipSuccess)
+      return e;
+    void* gprev = s.store ? s.g[l - 1] : s.gr[(l - 1) & 1];
+    if ((e = act_bwd(c->P, c->zbar, c->ldp_max, pre_prev, c->ldp[l - 1], gprev, c->ldg[l - 1], n,
+                     s.S, s.nd, s.has_lap, c->mask, ld.h_in, c->st)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// Factors (EMA) and gradient of one term, from the backward sweep.
+struct FactorGrad : LayerConsumer {
+  kfac_pinn_ctx* c;
+  int term, n, S;
+  double beta;
+  bool want_factors;
+  hipError_t operator()(int l, const void* zin, const void* g) override {
+    hipError_t e;
+    const LayerDesc& ld = c->nd.l[l];
+    const int K = n * S;
+    int sp = 1;
+    if (want_factors) {
+      const double sa = term == 0 ? 1.0 / ((double)n * S) : 1.0 / n;
+      const double sbf = 1.0 / n;
+      if ((e = gemm_tn_splitk(c->P, zin, c->ldz[l], zin, c->ldz[l], ld.h_in + 1, ld.h_in + 1, K,
+                              nullptr, S, true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+        return e;
+      if ((e = reduce_splitk(c->P, c->part, sp, ld.h_in + 1, ld.h_in + 1, true, c->F[term][0][l],
+                             ld.h_in + 1, 1, (1.0 - beta) * sa, beta, c->st)) != hipSuccess)
+        return e;
+      if ((e = gemm_tn_splitk(c->P, g, c->ldg[l], g, c->ldg[l], ld.h_out, ld.h_out, K, nullptr, S,
+                              true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+        return e;
+      if ((e = reduce_splitk(c->P, c->part, sp, ld.h_out, ld.h_out, true, c->F[term][1][l],
+                             ld.h_out, 1, (1.0 - beta) * sbf, beta, c->st)) != hipSuccess)
+        return e;
+    }
+    // gradient: sum_rows (r_n / n) g (x) z~, column-major into theta
+    const Slabs& s = term == 0 ? c->si : c->sb;
+    if ((e = gemm_tn_splitk(c->P, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1, K, s.r, S,
+                            false, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+      return e;
+    return reduce_splitk(c->P, c->part, sp, ld.h_out, ld.h_in + 1, false, c->grad + ld.off, 1,
+                         ld.h_out, 1.0 / n, term == 0 ? 0.0 : 1.0, c->st);
+  }
+};
+
+// theta_bar of a general cotangent
+struct ThetaBar : LayerConsumer {
+  kfac_pinn_ctx* c;
+  int n, S;
+  double* out;
+  hipError_t operator()(int l, const void* zin, const void* g) override {
+    const LayerDesc& ld = c->nd.l[l];
+    int sp = 1;
+    hipError_t e = gemm_tn_splitk(c->P, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1,
+                                  n * S, nullptr, S, false, c->part, kMaxSplits, &sp, c->st);
+    if (e != hipSuccess) return e;
+    return reduce_splitk(c->P, c->part, sp, ld.h_out, ld.h_in + 1, false, out + ld.off, 1,
+                         ld.h_out, 1.0, 0.0, c->st);
+  }
+};
+
+hipError_t curvature_term(kfac_pinn_ctx* c, int term, const void* x, const void* y, int n,
+                          double beta, bool want_factors) {
+  Slabs& s = term == 0 ? c->si : c->sb;
+  hipError_t e;
+  if (n <= 0) return hipSuccess;
+  if ((e = forward_store(c, s, x, n)) != hipSuccess) return e;
+  const void* pre_last = s.store ? s.pre[c->L - 1] : s.prer;
+  void* g_last = s.store ? s.g[c->L - 1] : s.gr[(c->L - 1) & 1];
+  if ((e = residual_and_seed(c, s, pre_last, y, n, g_last, term, 0)) != hipSuccess) return e;
+  FactorGrad fg;
+  fg.c = c; fg.term = term; fg.n = n; fg.S = s.S; fg.beta = beta; fg.want_factors = want_factors;
+  return backward_sweep(c, s, x, n, fg);
+}
+
+// total loss of (theta + alpha * dir) into loss[slot]; forward only
+hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, const void* xb,
+                     const void* yb, int nb, int slot) {
+  hipError_t e;
+  int acc = 0;
+  if (ni > 0) {
+    if ((e = forward_layers(c, c->si, xi, ni, c->L - 1, [&](int l) { return c->ls_z[l & 1]; },
+                            [&](int l) { return c->ls_pre; })) != hipSuccess)
+      return e;
+    if ((e = residual_and_seed(c, c->si, c->ls_pre, yi, ni, nullptr, slot, 0)) != hipSuccess)
+      return e;
+    acc = 1;
+  }
+  if (nb > 0) {
+    if ((e = forward_layers(c, c->sb, xb, nb, c->L - 1, [&](int l) { return c->ls_z[l & 1]; },
+                            [&](int l) { return c->ls_pre; })) != hipSuccess)
+      return e;
+    if ((e = residual_and_seed(c, c->sb, c->ls_pre, yb, nb, nullptr, slot, acc)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t prep(kfac_pinn_ctx* c, const void* theta, const void* dir, double alpha) {
+  return prep_weights(c->P, theta, dir, alpha, c->nd, c->w_hi, c->w_lo, nullptr, 0, c->st);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* kfac_pinn_last_error(void) { return g_last_error.c_str(); }
+
+const char* kfac_pinn_status_string(kp_status s) {
+  switch (s) {
+    case KP_OK: return "ok";
+    case KP_ERR_ARG: return "invalid argument";
+    case KP_ERR_OOM: return "out of device memory";
+    case KP_ERR_HIP: return "HIP error";
+    case KP_ERR_NOT_PD: return "damped factor not positive definite";
+    case KP_ERR_NONFINITE: return "non-finite loss for every step size";
+    case KP_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+int64_t kfac_pinn_num_params(const int32_t* widths, int32_t n_layers) {
+  if (!widths || n_layers < 1) return -1;
+  int64_t D = 0;
+  for (int l = 0; l < n_layers; l++) D += (int64_t)widths[l + 1] * (widths[l] + 1);
+  return D;
+}
+
+kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx) {
+  if (!ctx) return KP_ERR_ARG;
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  delete ctx;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** out) {
+  KP_ARG(pb && out, "null argument");
+  *out = nullptr;
+  KP_ARG(pb->n_layers >= 1 && pb->n_layers <= kMaxLayers, "n_layers must be in [1, 8]");
+  KP_ARG(pb->widths != nullptr, "widths is null");
+  for (int l = 0; l <= pb->n_layers; l++)
+    KP_ARG(pb->widths[l] >= 1 && pb->widths[l] <= 4096, "widths must be in [1, 4096]");
+  KP_ARG(pb->widths[pb->n_layers] == 1, "the network output must be scalar (widths[L] == 1)");
+  KP_ARG(pb->widths[0] <= 1024, "at most 1024 inputs");
+  KP_ARG(pb->precision >= KP_F64 && pb->precision <= KP_MIXED_BF16, "unknown precision");
+  KP_ARG(pb->max_interior >= 0 && pb->max_boundary >= 0, "negative capacity");
+  KP_ARG(pb->time_coord >= -1 && pb->time_coord < pb->widths[0], "time_coord out of range");
+
+  kfac_pinn_ctx* c = new kfac_pinn_ctx();
+  c->L = pb->n_layers;
+  c->w.assign(pb->widths, pb->widths + pb->n_layers + 1);
+  c->d = c->w[0];
+  c->time_coord = pb->time_coord;
+  c->c_t = pb->coef_time;
+  c->c_lap = pb->coef_lap;
+  c->P = (Prec)pb->precision;
+  c->esz_p = c->P == P_F64 ? 8 : 4;
+  c->esz_s = c->P == P_F64 ? 8 : (c->P == P_F32 ? 4 : 2);
+  c->esz_c = c->P == P_F64 ? 8 : 4;
+  c->max_i = pb->max_interior;
+  c->max_b = pb->max_boundary;
+  c->ws_limit = pb->workspace_limit_bytes;
+  c->st = (hipStream_t)stream;
+  c->D = kfac_pinn_num_params(pb->widths, pb->n_layers);
+
+  // layer geometry
+  c->nd.L = c->L;
+  long woff = 0, toff = 0;
+  for (int l = 0; l < c->L; l++) {
+    const int hi = c->w[l], ho = c->w[l + 1];
+    LayerDesc& ld = c->nd.l[l];
+    ld.h_in = hi;
+    ld.h_out = ho;
+    ld.off = toff;
+    ld.ldk_in = kp_roundup(hi + 1, 8);
+    ld.ldk_out = kp_roundup(ho, 8);
+    ld.wrm = woff;
+    woff += (long)ho * ld.ldk_in;
+    ld.wcm = woff;
+    woff += (long)hi * ld.ldk_out;
+    c->off.push_back(toff);
+    c->ldz.push_back(ld.ldk_in);
+    c->ldp.push_back(kp_roundup(ho, 8));
+    c->ldg.push_back(ld.ldk_out);
+    toff += (long)ho * (hi + 1);
+    c->hmax = std::max(c->hmax, std::max(hi, ho));
+    c->ldz_max = std::max(c->ldz_max, (long)ld.ldk_in);
+    c->ldp_max = std::max(c->ldp_max, kp_roundup(std::max(hi, ho), 8));
+  }
+  c->si.S = c->d + 2;
+  c->si.nd = c->d;
+  c->si.has_lap = 1;
+  c->si.cap = c->max_i;
+  c->sb.S = 1;
+  c->sb.nd = 0;
+  c->sb.has_lap = 0;
+  c->sb.cap = c->max_b;
+  c->si.store = !(c->ws_limit > 0 && slab_bytes(c, c->si, true) > c->ws_limit);
+  c->sb.store = true;
+
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, bytes)                                          \
+  if ((e = dmalloc(c, (void**)&(ptr), (bytes))) != hipSuccess) {  \
+    kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);   \
+    kfac_pinn_destroy(c);                                          \
+    return e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_HIP;    \
+  }
+  // Laplacian mask (per input coordinate)
+  ALLOC(c->mask, (size_t)c->d);
+  {
+    std::vector<uint8_t> m(c->d, 1);
+    if (pb->lap_mask)
+      for (int i = 0; i < c->d; i++) m[i] = pb->lap_mask[i] ? 1 : 0;
+    if ((e = hipMemcpy(c->mask, m.data(), c->d, hipMemcpyHostToDevice)) != hipSuccess) {
+      kfac_pinn_destroy(c);
+      return KP_ERR_HIP;
+    }
+  }
+  ALLOC(c->w_hi, (size_t)woff * c->esz_s);
+  if (c->P == P_BF16) ALLOC(c->w_lo, (size_t)woff * c->esz_s);
+  if ((e = alloc_slabs(c, c->si)) != hipSuccess || (e = alloc_slabs(c, c->sb)) != hipSuccess) {
+    kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+    kfac_pinn_destroy(c);
+    return e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_HIP;
+  }
+  const size_t Rmax = std::max((size_t)c->max_i * c->si.S, (size_t)c->max_b);
+  ALLOC(c->zbar, Rmax * c->ldp_max * c->esz_c);
+  ALLOC(c->ls_z[0], Rmax * c->ldz_max * c->esz_s);
+  ALLOC(c->ls_z[1], Rmax * c->ldz_max * c->esz_s);
+  ALLOC(c->ls_pre, Rmax * c->ldp_max * c->esz_c);
+  c->partial_n = residual_blocks(std::max(c->max_i, c->max_b));
+  ALLOC(c->partial, sizeof(double) * c->partial_n);
+  ALLOC(c->loss, sizeof(double) * (2 + kMaxCand + 2));
+  for (int t = 0; t < 2; t++)
+    for (int sd = 0; sd < 2; sd++) {
+      c->F[t][sd].resize(c->L);
+      for (int l = 0; l < c->L; l++) {
+        const long n = sd == 0 ? c->w[l] + 1 : c->w[l + 1];
+        ALLOC(c->F[t][sd][l], sizeof(double) * n * n);
+      }
+    }
+  {
+    long mn = 0;   // largest product output: A (h_in+1)^2, B h_out^2, gradient h_out (h_in+1)
+    for (int l = 0; l < c->L; l++) {
+      const long a = c->w[l] + 1, b = c->w[l + 1];
+      mn = std::max(mn, std::max(a * a, std::max(b * b, a * b)));
+    }
+    ALLOC(c->part, (size_t)kMaxSplits * mn * c->esz_c);
+  }
+  ALLOC(c->grad, sizeof(double) * c->D);
+  ALLOC(c->Delta, sizeof(double) * c->D);
+  ALLOC(c->dhat, c->esz_p * c->D);
+  ALLOC(c->delta, c->esz_p * c->D);
+  ALLOC(c->ctl, sizeof(int) * 128);
+
+  // eigenproblems: layer l side A (h_in+1) and side B (h_out)
+  for (int l = 0; l < c->L; l++)
+    for (int sd = 0; sd < 2; sd++) {
+      EigProblem p{};
+      p.n = sd == 0 ? c->w[l] + 1 : c->w[l + 1];
+      p.n_pad = (int)kp_roundup(p.n, 64);
+      p.f1 = c->F[0][sd][l];
+      p.f2 = c->F[1][sd][l];
+      const size_t np2 = (size_t)p.n_pad * p.n_pad * sizeof(double);
+      ALLOC(p.M1, np2);
+      ALLOC(p.M2, np2);
+      ALLOC(p.Lb, np2);
+      ALLOC(p.Li, np2);
+      ALLOC(p.C[0], np2);
+      ALLOC(p.C[1], np2);
+      ALLOC(p.P[0], np2);
+      ALLOC(p.P[1], np2);
+      ALLOC(p.V, (size_t)(p.n_pad / 64) * 64 * 64 * sizeof(double));
+      ALLOC(p.Pout, (size_t)p.n * p.n * sizeof(double));
+      ALLOC(p.eout, (size_t)p.n * sizeof(double));
+      c->probs.push_back(p);
+    }
+  ALLOC(c->probs_dev, sizeof(EigProblem) * c->probs.size());
+  if ((e = hipMemcpy(c->probs_dev, c->probs.data(), sizeof(EigProblem) * c->probs.size(),
+                     hipMemcpyHostToDevice)) != hipSuccess) {
+    kfac_pinn_destroy(c);
+    return KP_ERR_HIP;
+  }
+  {
+    std::vector<KronApply> ka(c->L);
+    long tstride = 0;
+    for (int l = 0; l < c->L; l++) {
+      ka[l].nA = c->w[l] + 1;
+      ka[l].nB = c->w[l + 1];
+      ka[l].off = c->off[l];
+      ka[l].PA = c->probs[2 * l].Pout;
+      ka[l].a = c->probs[2 * l].eout;
+      ka[l].PB = c->probs[2 * l + 1].Pout;
+      ka[l].b = c->probs[2 * l + 1].eout;
+      tstride = std::max(tstride, 2L * ka[l].nA * ka[l].nB);
+    }
+    double* ktmp = nullptr;
+    ALLOC(ktmp, sizeof(double) * tstride * c->L);
+    std::vector<G64> h(4 * c->L);
+    kron_apply_descs(ka.data(), c->L, c->grad, c->Delta, ktmp, tstride, h.data(), &c->k_mmax,
+                     &c->k_nmax);
+    ALLOC(c->kdesc, sizeof(G64) * h.size());
+    if ((e = hipMemcpy(c->kdesc, h.data(), sizeof(G64) * h.size(), hipMemcpyHostToDevice)) !=
+        hipSuccess) {
+      kfac_pinn_destroy(c);
+      return KP_ERR_HIP;
+    }
+  }
+#undef ALLOC
+  // Algorithm 1, step 0: identity factors, zero momentum
+  for (int t = 0; t < 2; t++)
+    for (int sd = 0; sd < 2; sd++)
+      for (int l = 0; l < c->L; l++) {
+        const long n = sd == 0 ? c->w[l] + 1 : c->w[l + 1];
+        if ((e = ema_fill(c->F[t][sd][l], n * n, (int)n, 1, nullptr)) != hipSuccess) {
+          kfac_pinn_destroy(c);
+          return KP_ERR_HIP;
+        }
+      }
+  if ((e = hipDeviceSynchronize()) != hipSuccess) {
+    kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+    kfac_pinn_destroy(c);
+    return KP_ERR_HIP;
+  }
+  *out = c;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_reset_state(kfac_pinn_ctx* c, int32_t init_identity) {
+  KP_ARG(c, "null context");
+  for (int t = 0; t < 2; t++)
+    for (int sd = 0; sd < 2; sd++)
+      for (int l = 0; l < c->L; l++) {
+        const long n = sd == 0 ? c->w[l] + 1 : c->w[l + 1];
+        KP_TRY(ema_fill(c->F[t][sd][l], n * n, (int)n, init_identity ? 1 : 0, c->st));
+      }
+  KP_TRY(hipMemsetAsync(c->delta, 0, c->esz_p * c->D, c->st));
+  KP_TRY(hipMemsetAsync(c->ctl, 0, sizeof(int) * 8, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_sample(kfac_pinn_ctx* c, const kp_sampler* s, int64_t step, void* x_int,
+                           void* y_int, void* x_bnd, void* y_bnd) {
+  KP_ARG(c && s, "null argument");
+  KP_ARG(s->n_interior >= 0 && s->n_boundary >= 0 && s->n_initial >= 0, "negative count");
+  KP_ARG(s->face_lo >= 0 && s->face_lo < c->d, "face_lo out of range");
+  KP_ARG(s->target_kind >= 0 && s->target_kind <= 2, "unknown target kind");
+  KP_ARG(s->target_kind != 1 || c->d >= 2, "target kind 1 needs d >= 2");
+  KP_ARG(s->n_interior == 0 || (x_int && y_int), "interior buffers are null");
+  KP_ARG(s->n_boundary + s->n_initial == 0 || (x_bnd && y_bnd), "boundary buffers are null");
+  KP_ARG(step >= 0, "negative step");
+  SamplerDesc sd;
+  sd.seed_i = s->seed_interior;
+  sd.seed_b = s->seed_boundary;
+  sd.seed_0 = s->seed_initial;
+  sd.n_i = s->n_interior;
+  sd.n_b = s->n_boundary;
+  sd.n_0 = s->n_initial;
+  sd.d = c->d;
+  sd.face_lo = s->face_lo;
+  sd.kind = s->target_kind;
+  sd.scale = s->scale;
+  sd.kappa = s->kappa;
+  sd.step = (long)step;
+  KP_TRY(sample(c->P, sd, x_int, y_int, x_bnd, y_bnd, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_forward_laplacian(kfac_pinn_ctx* c, const void* theta, const void* x,
+                                      int32_t n, void* u_out, void* grad_out, void* lap_out) {
+  KP_ARG(c && theta && x, "null argument");
+  KP_ARG(n >= 0 && n <= c->max_i, "n exceeds max_interior");
+  if (n == 0) return KP_OK;
+  KP_TRY(prep(c, theta, nullptr, 0.0));
+  KP_TRY(forward_store(c, c->si, x, n));
+  const void* pre_last = c->si.store ? c->si.pre[c->L - 1] : c->si.prer;
+  KP_TRY(extract_outputs(c->P, pre_last, c->ldp[c->L - 1], n, c->si.S, c->d, c->si.S - 1, u_out,
+                         grad_out, lap_out, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_forward_laplacian_vjp(kfac_pinn_ctx* c, const void* theta, const void* x,
+                                          int32_t n, const void* u_bar, const void* grad_bar,
+                                          const void* lap_bar, double* theta_bar, void* x_bar) {
+  KP_ARG(c && theta && x && theta_bar, "null argument");
+  KP_ARG(n >= 0 && n <= c->max_i, "n exceeds max_interior");
+  if (n == 0) {
+    KP_TRY(hipMemsetAsync(theta_bar, 0, sizeof(double) * c->D, c->st));
+    return KP_OK;
+  }
+  Slabs& s = c->si;
+  KP_TRY(prep(c, theta, nullptr, 0.0));
+  if (s.store) KP_TRY(forward_store(c, s, x, n));
+  void* g_last = s.store ? s.g[c->L - 1] : s.gr[(c->L - 1) & 1];
+  KP_TRY(seed_rows(c->P, u_bar, grad_bar, lap_bar, n, s.S, c->d, s.S - 1, g_last,
+                   c->ldg[c->L - 1], c->st));
+  ThetaBar tb;
+  tb.c = c;
+  tb.n = n;
+  tb.S = s.S;
+  tb.out = theta_bar;
+  KP_TRY(backward_sweep(c, s, x, n, tb));
+  if (x_bar) {
+    const void* g0 = s.store ? s.g[0] : s.gr[0];
+    KP_TRY(input_vjp(c->P, theta, c->w[1], c->d, g0, c->ldg[0], n, s.S, x_bar, c->st));
+  }
+  return KP_OK;
+}
+
+static kp_status check_batch(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni,
+                             const void* xb, const void* yb, int nb) {
+  KP_ARG(ni >= 0 && ni <= c->max_i, "n_int exceeds max_interior");
+  KP_ARG(nb >= 0 && nb <= c->max_b, "n_bnd exceeds max_boundary");
+  KP_ARG(ni == 0 || (xi && yi), "interior buffers are null");
+  KP_ARG(nb == 0 || (xb && yb), "boundary buffers are null");
+  KP_ARG(ni + nb > 0, "empty batch");
+  return KP_OK;
+}
+
+// EMA of one term's factors toward zero (a term without points contributes 0)
+static hipError_t decay_term(kfac_pinn_ctx* c, int term, double beta) {
+  for (int sd = 0; sd < 2; sd++)
+    for (int l = 0; l < c->L; l++) {
+      const int n = sd == 0 ? c->w[l] + 1 : c->w[l + 1];
+      hipError_t e = reduce_splitk(c->P, c->part, 0, n, n, true, c->F[term][sd][l], n, 1, 0.0,
+                                   beta, c->st);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+static kp_status factors_impl(kfac_pinn_ctx* c, const void* theta, const void* xi, const void* yi,
+                              int ni, const void* xb, const void* yb, int nb, double beta) {
+  KP_TRY(prep(c, theta, nullptr, 0.0));
+  KP_TRY(hipMemsetAsync(c->grad, 0, sizeof(double) * c->D, c->st));
+  KP_TRY(hipMemsetAsync(c->loss, 0, sizeof(double) * 2, c->st));
+  // interior term first: it overwrites the gradient, the boundary term adds to it
+  if (ni > 0) KP_TRY(curvature_term(c, 0, xi, yi, ni, beta, true));
+  else KP_TRY(decay_term(c, 0, beta));
+  if (nb > 0) KP_TRY(curvature_term(c, 1, xb, yb, nb, beta, true));
+  else KP_TRY(decay_term(c, 1, beta));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_factors(kfac_pinn_ctx* c, const void* theta, const void* xi, const void* yi,
+                            int32_t ni, const void* xb, const void* yb, int32_t nb, double beta,
+                            double* grad_out, double* loss_out) {
+  KP_ARG(c && theta, "null argument");
+  KP_ARG(beta >= 0.0 && beta < 1.0, "beta must be in [0, 1)");
+  kp_status s = check_batch(c, xi, yi, ni, xb, yb, nb);
+  if (s != KP_OK) return s;
+  s = factors_impl(c, theta, xi, yi, ni, xb, yb, nb, beta);
+  if (s != KP_OK) return s;
+  if (grad_out)
+    KP_TRY(hipMemcpyAsync(grad_out, c->grad, sizeof(double) * c->D, hipMemcpyDeviceToDevice,
+                          c->st));
+  if (loss_out)
+    KP_TRY(hipMemcpyAsync(loss_out, c->loss, sizeof(double) * 2, hipMemcpyDeviceToDevice, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_invert(kfac_pinn_ctx* c, double lambda) {
+  KP_ARG(c, "null context");
+  KP_ARG(lambda >= 0.0 && isfinite(lambda), "lambda must be finite and >= 0");
+  KP_TRY(kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
+                          nullptr, kJacobiSweeps, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_precondition(kfac_pinn_ctx* c, const double* grad_in, double* delta_out) {
+  KP_ARG(c && grad_in && delta_out, "null argument");
+  if (grad_in != c->grad)
+    KP_TRY(hipMemcpyAsync(c->grad, grad_in, sizeof(double) * c->D, hipMemcpyDeviceToDevice, c->st));
+  KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
+  KP_TRY(hipMemcpyAsync(delta_out, c->Delta, sizeof(double) * c->D, hipMemcpyDeviceToDevice,
+                        c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const void* yi, int32_t ni,
+                         const void* xb, const void* yb, int32_t nb, const kp_hparams* hp,
+                         kp_step_info* info) {
+  KP_ARG(c && theta && hp, "null argument");
+  KP_ARG(hp->beta >= 0.0 && hp->beta < 1.0, "beta must be in [0, 1)");
+  KP_ARG(hp->lambda >= 0.0 && isfinite(hp->lambda), "lambda must be finite and >= 0");
+  KP_ARG(isfinite(hp->momentum), "momentum must be finite");
+  KP_ARG(hp->lr_mode == 0 || hp->lr_mode == 1, "lr_mode must be 0 or 1");
+  int ncand = 0;
+  if (hp->lr_mode == 1) {
+    KP_ARG(hp->grid_max_exp >= hp->grid_min_exp, "empty line-search grid");
+    ncand = hp->grid_max_exp - hp->grid_min_exp + 1;
+    KP_ARG(ncand <= kMaxCand, "at most 64 line-search candidates");
+    KP_ARG(hp->grid_max_exp <= 60 && hp->grid_min_exp >= -1000, "grid exponents out of range");
+  } else {
+    KP_ARG(hp->lr >= 0.0 && isfinite(hp->lr), "lr must be finite and >= 0");
+  }
+  kp_status s = check_batch(c, xi, yi, ni, xb, yb, nb);
+  if (s != KP_OK) return s;
+  // 1-2) factors, EMA, losses and gradient at theta_t
+  s = factors_impl(c, theta, xi, yi, ni, xb, yb, nb, hp->beta);
+  if (s != KP_OK) return s;
+  // 3) preconditioner
+  KP_TRY(kron_eig_batched(c->probs.data(), (int)c->probs.size(), hp->lambda, c->probs_dev,
+                          c->ctl, nullptr, kJacobiSweeps, c->st));
+  // 4) Delta = -C g, momentum
+  KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
+  KP_TRY(momentum(c->P, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
+  // 5) learning rate and update
+  if (hp->lr_mode == 1) {
+    for (int k = 0; k < ncand; k++) {
+      const double alpha = ldexp(1.0, hp->grid_max_exp - k);
+      KP_TRY(prep(c, theta, c->dhat, alpha));
+      KP_TRY(eval_loss(c, xi, yi, ni, xb, yb, nb, 2 + k));
+    }
+    c->last_ncand = ncand;
+  }
+  KP_TRY(finish_step(c->P, c->loss + 2, ncand, hp->grid_max_exp,
+                     hp->lr_mode == 1 ? -1.0 : hp->lr, c->loss, theta, c->dhat, c->delta, c->D,
+                     c->ctl, c->ctl + 1, info, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_get_factor(kfac_pinn_ctx* c, int32_t layer, int32_t term, int32_t side,
+                               double* out) {
+  KP_ARG(c && out, "null argument");
+  KP_ARG(layer >= 0 && layer < c->L && (term == 0 || term == 1) && (side == 0 || side == 1),
+         "index out of range");
+  const long n = side == 0 ? c->w[layer] + 1 : c->w[layer + 1];
+  KP_TRY(hipMemcpyAsync(out, c->F[term][side][layer], sizeof(double) * n * n,
+                        hipMemcpyDeviceToDevice, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_set_factor(kfac_pinn_ctx* c, int32_t layer, int32_t term, int32_t side,
+                               const double* in) {
+  KP_ARG(c && in, "null argument");
+  KP_ARG(layer >= 0 && layer < c->L && (term == 0 || term == 1) && (side == 0 || side == 1),
+         "index out of range");
+  const long n = side == 0 ? c->w[layer] + 1 : c->w[layer + 1];
+  KP_TRY(hipMemcpyAsync(c->F[term][side][layer], in, sizeof(double) * n * n,
+                        hipMemcpyDeviceToDevice, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_get_preconditioner(kfac_pinn_ctx* c, int32_t layer, int32_t side, double* P,
+                                       double* e) {
+  KP_ARG(c, "null context");
+  KP_ARG(layer >= 0 && layer < c->L && (side == 0 || side == 1), "index out of range");
+  const EigProblem& p = c->probs[2 * layer + side];
+  if (P)
+    KP_TRY(hipMemcpyAsync(P, p.Pout, sizeof(double) * p.n * p.n, hipMemcpyDeviceToDevice, c->st));
+  if (e) KP_TRY(hipMemcpyAsync(e, p.eout, sizeof(double) * p.n, hipMemcpyDeviceToDevice, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_get_line_search(kfac_pinn_ctx* c, double* out) {
+  KP_ARG(c && out, "null argument");
+  if (c->last_ncand > 0)
+    KP_TRY(hipMemcpyAsync(out, c->loss + 2, sizeof(double) * c->last_ncand,
+                          hipMemcpyDeviceToDevice, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_get_momentum(kfac_pinn_ctx* c, void* out) {
+  KP_ARG(c && out, "null argument");
+  KP_TRY(hipMemcpyAsync(out, c->delta, c->esz_p * c->D, hipMemcpyDeviceToDevice, c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* c, const void* in, int64_t step) {
+  KP_ARG(c && in, "null argument");
+  KP_ARG(step >= 0 && step < (1LL << 30), "step out of range");
+  KP_TRY(hipMemcpyAsync(c->delta, in, c->esz_p * c->D, hipMemcpyDeviceToDevice, c->st));
+  static thread_local int stepv;
+  stepv = (int)step;
+  KP_TRY(hipMemcpyAsync(c->ctl + 1, &stepv, sizeof(int), hipMemcpyHostToDevice, c->st));
+  KP_TRY(hipStreamSynchronize(c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_sync(kfac_pinn_ctx* c) {
+  KP_ARG(c, "null context");
+  KP_TRY(hipStreamSynchronize(c->st));
+  int st = 0;
+  KP_TRY(hipMemcpy(&st, c->ctl, sizeof(int), hipMemcpyDeviceToHost));
+  if (st != 0) {
+    int zero = 0;
+    KP_TRY(hipMemcpy(c->ctl, &zero, sizeof(int), hipMemcpyHostToDevice));
+  }
+  return (kp_status)st;
+}
+
+}  // extern "C"

@@ -1,0 +1,633 @@
+// Elementwise and per-point kernels of the hot path.
+//
+// Slab layout (all slabs): row r = n*S + s holds point n's shared column s of
+// Z_n (Section 3.2): s = 0 the value, s = 1..d the first derivatives, s = S-1
+// the (masked) Laplacian row.  A boundary slab has S = 1 (value row only).
+// Columns are neurons; layer inputs carry the bias feature in column h
+// (1 in the value row, 0 elsewhere, Eq. forward-laplacian-linear-layer-compact)
+// and zeros up to the padded row length.
+#include "common.h"
+#include "launch.h"
+
+namespace kp {
+
+// ---------------------------------------------------------------------------
+// Product-layout copies of the augmented weights W~ = [W | b]
+// ---------------------------------------------------------------------------
+template <typename TP, typename TS>
+__global__ void k_prep_weights(const TP* __restrict__ theta, const TP* __restrict__ dir,
+                               double alpha, NetDesc nd, TS* __restrict__ whi,
+                               TS* __restrict__ wlo, typename Acc<TS>::type* __restrict__ bias,
+                               long bias_stride) {
+  typedef typename Acc<TS>::type TC;
+  const int l = blockIdx.y;
+  if (l >= nd.L) return;
+  const LayerDesc ld = nd.l[l];
+  const long nf = (long)ld.h_out * ld.ldk_in;    // forward copy elements
+  const long nb = (long)ld.h_in * ld.ldk_out;    // backward copy elements
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nf + nb + ld.h_out;
+       e += (long)gridDim.x * blockDim.x) {
+    long src = -1, dst;
+    if (e < nf) {                         // forward: row i (output), column j (input, bias at h_in)
+      int i = (int)(e / ld.ldk_in), j = (int)(e % ld.ldk_in);
+      dst = ld.wrm + e;
+      if (j <= ld.h_in) src = ld.off + (long)j * ld.h_out + i;
+    } else if (e < nf + nb) {             // backward: row j (input), column i (output)
+      long f = e - nf;
+      int j = (int)(f / ld.ldk_out), i = (int)(f % ld.ldk_out);
+      dst = ld.wcm + f;
+      if (i < ld.h_out) src = ld.off + (long)j * ld.h_out + i;
+    } else {                              // bias (compute type)
+      int i = (int)(e - nf - nb);
+      double w = (double)theta[ld.off + (long)ld.h_in * ld.h_out + i];
+      if (dir) w = (double)(TP)((TP)w + (TP)(alpha * (double)dir[ld.off + (long)ld.h_in * ld.h_out + i]));
+      if (bias) bias[l * bias_stride + i] = (TC)w;
+      continue;
+    }
+    double w = 0.0;
+    if (src >= 0) {
+      TP t = theta[src];
+      if (dir) t = (TP)(t + (TP)(alpha * (double)dir[src]));
+      w = (double)t;
+    }
+    TS hi = cvt<TS>(w);
+    whi[dst] = hi;
+    if (wlo) wlo[dst] = cvt<TS>(w - to_d(hi));
+  }
+}
+
+hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha, NetDesc nd,
+                        void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st) {
+  dim3 g(256, nd.L);
+  switch (p) {
+    case P_F64:
+      k_prep_weights<double, double><<<g, 256, 0, st>>>((const double*)theta, (const double*)dir,
+                                                        alpha, nd, (double*)w_hi, nullptr,
+                                                        (double*)bias, bias_stride);
+      break;
+    case P_F32:
+      k_prep_weights<float, float><<<g, 256, 0, st>>>((const float*)theta, (const float*)dir,
+                                                      alpha, nd, (float*)w_hi, nullptr,
+                                                      (float*)bias, bias_stride);
+      break;
+    case P_BF16:
+      k_prep_weights<float, bf16><<<g, 256, 0, st>>>((const float*)theta, (const float*)dir,
+                                                     alpha, nd, (bf16*)w_hi, (bf16*)w_lo,
+                                                     (float*)bias, bias_stride);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Input slab Z~^(0) (Section 3.1: z = x, d_i z = e_i, Lap z = 0)
+// ---------------------------------------------------------------------------
+template <typename TP, typename TS>
+__global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S, TS* __restrict__ z,
+                             long ldz) {
+  const long R = (long)n * S;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < R * ldz;
+       e += (long)gridDim.x * blockDim.x) {
+    long r = e / ldz;
+    int j = (int)(e % ldz);
+    int pt = (int)(r / S), s = (int)(r % S);
+    double v = 0.0;
+    if (s == 0) v = j < d ? (double)x[(long)pt * d + j] : (j == d ? 1.0 : 0.0);
+    else if (s <= d && S > 1 && s < S - 1) v = (j == s - 1) ? 1.0 : 0.0;
+    z[e] = cvt<TS>(v);
+  }
+}
+
+hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long ldz,
+                      hipStream_t st) {
+  long tot = (long)n * S * ldz;
+  int nb = (int)((tot + 255) / 256);
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  switch (p) {
+    case P_F64:
+      k_input_slab<double, double><<<nb, 256, 0, st>>>((const double*)x, n, d, S, (double*)z, ldz);
+      break;
+    case P_F32:
+      k_input_slab<float, float><<<nb, 256, 0, st>>>((const float*)x, n, d, S, (float*)z, ldz);
+      break;
+    case P_BF16:
+      k_input_slab<float, bf16><<<nb, 256, 0, st>>>((const float*)x, n, d, S, (bf16*)z, ldz);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// tanh layer, forward Laplacian rule (Eq. forward-laplacian-main, second line):
+//   v = tanh(a0);  d_i v = s1 d_i a;  Lv = s1 La + s2 sum_{i in M} (d_i a)^2
+// One thread per (point, column); nd derivative rows, optional Laplacian row.
+// ---------------------------------------------------------------------------
+template <typename TC, typename TS>
+__global__ void k_act_fwd(const TC* __restrict__ pre, long ldp, TS* __restrict__ z, long ldz,
+                          int npts, int S, int nd, int has_lap, const uint8_t* __restrict__ mask,
+                          int h) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pt = blockIdx.y + blockIdx.z * gridDim.y;
+  if (j >= ldz || pt >= npts) return;
+  const long r0 = (long)pt * S;
+  if (j >= h) {   // bias feature and padding
+    for (int s = 0; s < S; s++) z[(r0 + s) * ldz + j] = cvt<TS>((j == h && s == 0) ? 1.0 : 0.0);
+    return;
+  }
+  const TC a0 = pre[r0 * ldp + j];
+  const TC t = act_tanh(a0);
+  const TC s1 = (TC)1 - t * t;
+  const TC s2 = (TC)-2 * t * s1;
+  z[r0 * ldz + j] = cvt<TS>((double)t);
+  TC sq = 0;
+  for (int i = 0; i < nd; i++) {
+    const TC da = pre[(r0 + 1 + i) * ldp + j];
+    z[(r0 + 1 + i) * ldz + j] = cvt<TS>((double)(s1 * da));
+    if (mask[i]) sq += da * da;
+  }
+  if (has_lap) {
+    const TC la = pre[(r0 + S - 1) * ldp + j];
+    z[(r0 + S - 1) * ldz + j] = cvt<TS>((double)(s1 * la + s2 * sq));
+  }
+}
+
+static dim3 pt_grid(int cols, int npts) {
+  int gy = npts, gz = 1;
+  while (gy > 65535) { gz *= 2; gy = (npts + gz - 1) / gz; }
+  return dim3((cols + 63) / 64, gy, gz);
+}
+
+hipError_t act_fwd(Prec p, const void* pre, long ldp, void* z, long ldz, int npts, int S, int nd,
+                   int has_lap, const uint8_t* mask, int h, hipStream_t st) {
+  if (npts <= 0) return hipSuccess;
+  dim3 g = pt_grid((int)ldz, npts);
+  switch (p) {
+    case P_F64:
+      k_act_fwd<double, double><<<g, 64, 0, st>>>((const double*)pre, ldp, (double*)z, ldz, npts,
+                                                  S, nd, has_lap, mask, h);
+      break;
+    case P_F32:
+      k_act_fwd<float, float><<<g, 64, 0, st>>>((const float*)pre, ldp, (float*)z, ldz, npts, S,
+                                                nd, has_lap, mask, h);
+      break;
+    case P_BF16:
+      k_act_fwd<float, bf16><<<g, 64, 0, st>>>((const float*)pre, ldp, (bf16*)z, ldz, npts, S,
+                                               nd, has_lap, mask, h);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the tanh rows.  With t = tanh(a0), s1 = 1-t^2, s2 = -2 t s1,
+// s3 = -2 s1 (1 - 3 t^2) and output cotangents vbar, dbar_i, Lbar:
+//   abar_0 = s1 vbar + s2 sum_i d_i a dbar_i + (s2 La + s3 sum_{i in M} (d_i a)^2) Lbar
+//   abar_i = s1 dbar_i + 2 [i in M] s2 d_i a Lbar
+//   abar_L = s1 Lbar
+// ---------------------------------------------------------------------------
+template <typename TC, typename TS>
+__global__ void k_act_bwd(const TC* __restrict__ zb, long ldzb, const TC* __restrict__ pre,
+                          long ldp, TS* __restrict__ g, long ldg, int npts, int S, int nd,
+                          int has_lap, const uint8_t* __restrict__ mask, int h) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pt = blockIdx.y + blockIdx.z * gridDim.y;
+  if (j >= ldg || pt >= npts) return;
+  const long r0 = (long)pt * S;
+  if (j >= h) {
+    for (int s = 0; s < S; s++) g[(r0 + s) * ldg + j] = cvt<TS>(0.0);
+    return;
+  }
+  const TC a0 = pre[r0 * ldp + j];
+  const TC t = act_tanh(a0);
+  const TC s1 = (TC)1 - t * t;
+  const TC s2 = (TC)-2 * t * s1;
+  const TC s3 = (TC)-2 * s1 * ((TC)1 - (TC)3 * t * t);
+  const TC lb = has_lap ? zb[(r0 + S - 1) * ldzb + j] : (TC)0;
+  const TC la = has_lap ? pre[(r0 + S - 1) * ldp + j] : (TC)0;
+  TC sum1 = 0, sq = 0;
+  for (int i = 0; i < nd; i++) {
+    const TC da = pre[(r0 + 1 + i) * ldp + j];
+    const TC db = zb[(r0 + 1 + i) * ldzb + j];
+    const TC m = mask[i] ? (TC)1 : (TC)0;
+    sum1 += da * db;
+    sq += m * da * da;
+    g[(r0 + 1 + i) * ldg + j] = cvt<TS>((double)(s1 * db + (TC)2 * m * s2 * da * lb));
+  }
+  const TC vb = zb[r0 * ldzb + j];
+  g[r0 * ldg + j] = cvt<TS>((double)(s1 * vb + s2 * sum1 + (s2 * la + s3 * sq) * lb));
+  if (has_lap) g[(r0 + S - 1) * ldg + j] = cvt<TS>((double)(s1 * lb));
+}
+
+hipError_t act_bwd(Prec p, const void* zbar, long ldzb, const void* pre, long ldp, void* g,
+                   long ldg, int npts, int S, int nd, int has_lap, const uint8_t* mask, int h,
+                   hipStream_t st) {
+  if (npts <= 0) return hipSuccess;
+  dim3 gr = pt_grid((int)ldg, npts);
+  switch (p) {
+    case P_F64:
+      k_act_bwd<double, double><<<gr, 64, 0, st>>>((const double*)zbar, ldzb, (const double*)pre,
+                                                   ldp, (double*)g, ldg, npts, S, nd, has_lap,
+                                                   mask, h);
+      break;
+    case P_F32:
+      k_act_bwd<float, float><<<gr, 64, 0, st>>>((const float*)zbar, ldzb, (const float*)pre, ldp,
+                                                 (float*)g, ldg, npts, S, nd, has_lap, mask, h);
+      break;
+    case P_BF16:
+      k_act_bwd<float, bf16><<<gr, 64, 0, st>>>((const float*)zbar, ldzb, (const float*)pre, ldp,
+                                                (bf16*)g, ldg, npts, S, nd, has_lap, mask, h);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Residual (Eq. pinn-loss), loss partials and the output seed d r / d U
+// ---------------------------------------------------------------------------
+int residual_blocks(int npts) { return npts > 0 ? (npts + 255) / 256 : 1; }
+
+template <typename TC, typename TP, typename TS>
+__global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, long ldp,
+                                                  const TP* __restrict__ y, int npts, int S,
+                                                  int time_row, double c_t, double c_lap,
+                                                  int lap_row, double* __restrict__ r,
+                                                  TS* __restrict__ g, long ldg,
+                                                  double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double sq = 0.0;
+  if (n < npts) {
+    const long r0 = (long)n * S;
+    double v;
+    if (lap_row >= 0 || time_row >= 0) {
+      v = -(double)y[n];
+      if (lap_row >= 0) v += c_lap * (double)pre[(r0 + lap_row) * ldp];
+      if (time_row >= 0) v += c_t * (double)pre[(r0 + time_row) * ldp];
+    } else {
+      v = (double)pre[r0 * ldp] - (double)y[n];   // boundary: r = u - g
+    }
+    if (r) r[n] = v;
+    sq = v * v;
+    if (g) {
+      for (int s = 0; s < S; s++) {
+        double sv = 0.0;
+        if (lap_row < 0 && time_row < 0) sv = (s == 0) ? 1.0 : 0.0;
+        else {
+          if (s == lap_row) sv += c_lap;
+          if (s == time_row) sv += c_t;
+        }
+        g[(r0 + s) * ldg] = cvt<TS>(sv);
+        for (int c = 1; c < ldg; c++) g[(r0 + s) * ldg + c] = cvt<TS>(0.0);
+      }
+    }
+  }
+  sq = warp_sum(sq);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t residual(Prec p, const void* pre, long ldp, const void* y, int npts, int S,
+                    int time_row, double c_t, double c_lap, int lap_row, double* r, void* g,
+                    long ldg, double* partial, hipStream_t st) {
+  int nb = residual_blocks(npts);
+  switch (p) {
+    case P_F64:
+      k_residual<double, double, double><<<nb, 256, 0, st>>>(
+          (const double*)pre, ldp, (const double*)y, npts, S, time_row, c_t, c_lap, lap_row, r,
+          (double*)g, ldg, partial);
+      break;
+    case P_F32:
+      k_residual<float, float, float><<<nb, 256, 0, st>>>((const float*)pre, ldp,
+                                                          (const float*)y, npts, S, time_row, c_t,
+                                                          c_lap, lap_row, r, (float*)g, ldg,
+                                                          partial);
+      break;
+    case P_BF16:
+      k_residual<float, float, bf16><<<nb, 256, 0, st>>>((const float*)pre, ldp, (const float*)y,
+                                                         npts, S, time_row, c_t, c_lap, lap_row,
+                                                         r, (bf16*)g, ldg, partial);
+      break;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_finalize_loss(const double* __restrict__ partial, int nb,
+                                                       double scale, double* loss, int slot,
+                                                       int accumulate) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+  s = warp_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = scale * (red[0] + red[1] + red[2] + red[3]);
+    loss[slot] = accumulate ? loss[slot] + v : v;
+  }
+}
+
+hipError_t finalize_loss(const double* partial, int nb, double scale, double* loss, int slot,
+                         int accumulate, hipStream_t st) {
+  k_finalize_loss<<<1, 256, 0, st>>>(partial, nb, scale, loss, slot, accumulate);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Forward-Laplacian outputs and general seeds (autograd entry points)
+// ---------------------------------------------------------------------------
+template <typename TC, typename TP>
+__global__ void k_extract(const TC* __restrict__ pre, long ldp, int npts, int S, int d,
+                          int lap_row, TP* u, TP* grad, TP* lap) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= npts) return;
+  const long r0 = (long)n * S;
+  if (u) u[n] = (TP)pre[r0 * ldp];
+  if (grad)
+    for (int i = 0; i < d; i++) grad[(long)n * d + i] = (TP)pre[(r0 + 1 + i) * ldp];
+  if (lap) lap[n] = lap_row >= 0 ? (TP)pre[(r0 + lap_row) * ldp] : (TP)0;
+}
+
+hipError_t extract_outputs(Prec p, const void* pre, long ldp, int npts, int S, int d, int lap_row,
+                           void* u, void* grad, void* lap, hipStream_t st) {
+  int nb = (npts + 255) / 256;
+  if (nb < 1) return hipSuccess;
+  if (p == P_F64)
+    k_extract<double, double><<<nb, 256, 0, st>>>((const double*)pre, ldp, npts, S, d, lap_row,
+                                                  (double*)u, (double*)grad, (double*)lap);
+  else
+    k_extract<float, float><<<nb, 256, 0, st>>>((const float*)pre, ldp, npts, S, d, lap_row,
+                                                (float*)u, (float*)grad, (float*)lap);
+  return hipGetLastError();
+}
+
+template <typename TP, typename TS>
+__global__ void k_seed(const TP* __restrict__ ub, const TP* __restrict__ gb,
+                       const TP* __restrict__ lb, int npts, int S, int d, int lap_row, TS* g,
+                       long ldg) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= npts) return;
+  const long r0 = (long)n * S;
+  for (int s = 0; s < S; s++) {
+    double v = 0.0;
+    if (s == 0) v = ub ? (double)ub[n] : 0.0;
+    else if (s == lap_row) v = lb ? (double)lb[n] : 0.0;
+    else if (s <= d) v = gb ? (double)gb[(long)n * d + s - 1] : 0.0;
+    g[(r0 + s) * ldg] = cvt<TS>(v);
+    for (int c = 1; c < ldg; c++) g[(r0 + s) * ldg + c] = cvt<TS>(0.0);
+  }
+}
+
+hipError_t seed_rows(Prec p, const void* u_bar, const void* grad_bar, const void* lap_bar,
+                     int npts, int S, int d, int lap_row, void* g, long ldg, hipStream_t st) {
+  int nb = (npts + 255) / 256;
+  if (nb < 1) return hipSuccess;
+  switch (p) {
+    case P_F64:
+      k_seed<double, double><<<nb, 256, 0, st>>>((const double*)u_bar, (const double*)grad_bar,
+                                                 (const double*)lap_bar, npts, S, d, lap_row,
+                                                 (double*)g, ldg);
+      break;
+    case P_F32:
+      k_seed<float, float><<<nb, 256, 0, st>>>((const float*)u_bar, (const float*)grad_bar,
+                                               (const float*)lap_bar, npts, S, d, lap_row,
+                                               (float*)g, ldg);
+      break;
+    case P_BF16:
+      k_seed<float, bf16><<<nb, 256, 0, st>>>((const float*)u_bar, (const float*)grad_bar,
+                                              (const float*)lap_bar, npts, S, d, lap_row,
+                                              (bf16*)g, ldg);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TP, typename TS>
+__global__ void k_input_vjp(const TP* __restrict__ theta, int h_out, int d,
+                            const TS* __restrict__ g1, long ldg, int npts, int S, TP* xb) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)npts * d) return;
+  const int n = (int)(e / d), k = (int)(e % d);
+  double s = 0.0;
+  const TS* gr = g1 + (long)n * S * ldg;
+  for (int j = 0; j < h_out; j++) s += (double)theta[(long)k * h_out + j] * to_d(gr[j]);
+  xb[e] = (TP)s;
+}
+
+hipError_t input_vjp(Prec p, const void* theta, int h_out, int d, const void* g1, long ldg,
+                     int npts, int S, void* x_bar, hipStream_t st) {
+  long tot = (long)npts * d;
+  int nb = (int)((tot + 255) / 256);
+  if (nb < 1) return hipSuccess;
+  switch (p) {
+    case P_F64:
+      k_input_vjp<double, double><<<nb, 256, 0, st>>>((const double*)theta, h_out, d,
+                                                      (const double*)g1, ldg, npts, S,
+                                                      (double*)x_bar);
+      break;
+    case P_F32:
+      k_input_vjp<float, float><<<nb, 256, 0, st>>>((const float*)theta, h_out, d,
+                                                    (const float*)g1, ldg, npts, S,
+                                                    (float*)x_bar);
+      break;
+    case P_BF16:
+      k_input_vjp<float, bf16><<<nb, 256, 0, st>>>((const float*)theta, h_out, d, (const bf16*)g1,
+                                                   ldg, npts, S, (float*)x_bar);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Optimizer state (Section 3.4; Algorithm 1 steps 0, 4 and 5)
+// ---------------------------------------------------------------------------
+__global__ void k_ema_fill(double* a, long n, int dim, int identity) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  a[e] = (identity && (e / dim) == (e % dim)) ? 1.0 : 0.0;
+}
+
+hipError_t ema_fill(double* a, long n, int dim, int identity, hipStream_t st) {
+  k_ema_fill<<<(int)((n + 255) / 256), 256, 0, st>>>(a, n, dim, identity);
+  return hipGetLastError();
+}
+
+template <typename TP>
+__global__ void k_momentum(const double* __restrict__ Delta, const TP* __restrict__ delta,
+                           double mu, const int* __restrict__ step, TP* __restrict__ dhat,
+                           long D) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D) return;
+  const bool mom = *step > 0;
+  double v = Delta[e] + (mom ? mu * (double)delta[e] : 0.0);
+  dhat[e] = (TP)v;
+}
+
+hipError_t momentum(Prec p, const double* Delta, const void* delta, double mu, const int* step,
+                    void* dhat, long D, hipStream_t st) {
+  int nb = (int)((D + 255) / 256);
+  if (p == P_F64)
+    k_momentum<double><<<nb, 256, 0, st>>>(Delta, (const double*)delta, mu, step, (double*)dhat, D);
+  else
+    k_momentum<float><<<nb, 256, 0, st>>>(Delta, (const float*)delta, mu, step, (float*)dhat, D);
+  return hipGetLastError();
+}
+
+struct StepInfoDev {
+  double loss_interior, loss_boundary, lr_chosen, loss_after;
+  int status, step;
+};
+
+// alpha* = first strict minimum over candidates ordered from the largest step
+// (ties go to the larger alpha); non-finite losses are skipped.
+__global__ void k_select(const double* __restrict__ losses, int ncand, int kmax, double fixed_lr,
+                         const double* __restrict__ base, int* status, int* step, double* alpha,
+                         StepInfoDev* info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, after = __builtin_nan("");
+  int st = *status;
+  if (st == 0) {
+    if (fixed_lr >= 0.0) {
+      a = fixed_lr;
+    } else {
+      int best = -1;
+      double bv = 0.0;
+      for (int c = 0; c < ncand; c++) {
+        double v = losses[c];
+        if (isfinite(v) && (best < 0 || v < bv)) { best = c; bv = v; }
+      }
+      if (best < 0) st = 5;
+      else { a = ldexp(1.0, kmax - best); after = bv; }
+    }
+  }
+  if (st != 0) a = 0.0;
+  *status = st;
+  *alpha = a;
+  if (st == 0) *step += 1;
+  if (info) {
+    info->loss_interior = base[0];
+    info->loss_boundary = base[1];
+    info->lr_chosen = a;
+    info->loss_after = after;
+    info->status = st;
+    info->step = *step;
+  }
+}
+
+template <typename TP>
+__global__ void k_apply_update(const int* __restrict__ status, const double* __restrict__ alpha,
+                               TP* __restrict__ theta, const TP* __restrict__ dhat,
+                               TP* __restrict__ delta, long D) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D || *status != 0) return;
+  const TP d = (TP)(*alpha * (double)dhat[e]);
+  delta[e] = d;
+  theta[e] = theta[e] + d;
+}
+
+hipError_t finish_step(Prec p, const double* losses, int ncand, int kmax, double fixed_lr,
+                       const double* base_loss, void* theta, void* dhat, void* delta, long D,
+                       int* status, int* step, void* info, hipStream_t st) {
+  double* alpha = (double*)(status + 4);   // scalar slot next to the status word
+  k_select<<<1, 64, 0, st>>>(losses, ncand, kmax, fixed_lr, base_loss, status, step, alpha,
+                             (StepInfoDev*)info);
+  int nb = (int)((D + 255) / 256);
+  if (p == P_F64)
+    k_apply_update<double><<<nb, 256, 0, st>>>(status, alpha, (double*)theta,
+                                               (const double*)dhat, (double*)delta, D);
+  else
+    k_apply_update<float><<<nb, 256, 0, st>>>(status, alpha, (float*)theta, (const float*)dhat,
+                                              (float*)delta, D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sampler: SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sm64_uniform(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * 0x1.0p-53;
+}
+
+// Targets of the manufactured solutions, from the running sums of one point:
+// ssum = sum sin(pi x_i) over all coordinates, hsum = the same over i >= 1.
+__device__ __forceinline__ double target_f(double x0, double x1, double ssum, int kind,
+                                          double scale) {
+  const double pi = 3.14159265358979323846;
+  if (kind == 1) return 2.0 * pi * pi * sin(pi * x0) * sin(pi * x1);
+  if (kind == 2) return 0.0;
+  return scale * pi * pi * ssum;
+}
+__device__ __forceinline__ double target_g(double x0, double ssum, double hsum, int kind,
+                                          double scale, double kappa) {
+  const double pi = 3.14159265358979323846;
+  if (kind == 1) return 0.0;
+  if (kind == 2) return exp(-kappa * pi * pi * x0) * hsum;
+  return scale * ssum;
+}
+
+template <typename TP>
+__global__ void k_sample(SamplerDesc s, TP* xi, TP* yi, TP* xb, TP* yb) {
+  const double pi = 3.14159265358979323846;
+  const int d = s.d;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double x0 = 0.0, x1 = 0.0, ssum = 0.0, hsum = 0.0;
+  if (n < s.n_i) {
+    const uint64_t base = (uint64_t)s.step * s.n_i * d + (uint64_t)n * d;
+    for (int j = 0; j < d; j++) {
+      const double v = sm64_uniform(s.seed_i, base + j);
+      xi[(long)n * d + j] = (TP)v;
+      if (j == 0) x0 = v;
+      if (j == 1) x1 = v;
+      const double sv = sin(pi * v);
+      ssum += sv;
+      if (j >= 1) hsum += sv;
+    }
+    yi[n] = (TP)target_f(x0, x1, ssum, s.kind, s.scale);
+  } else if (n < s.n_i + s.n_0) {      // initial points: x_0 = 0
+    const int m = n - s.n_i;
+    const uint64_t base = (uint64_t)s.step * s.n_0 * d + (uint64_t)m * d;
+    for (int j = 0; j < d; j++) {
+      const double v = j == 0 ? 0.0 : sm64_uniform(s.seed_0, base + j);
+      xb[(long)m * d + j] = (TP)v;
+      const double sv = sin(pi * v);
+      ssum += sv;
+      if (j >= 1) hsum += sv;
+    }
+    yb[m] = (TP)target_g(0.0, ssum, hsum, s.kind, s.scale, s.kappa);
+  } else if (n < s.n_i + s.n_0 + s.n_b) {
+    const int m = n - s.n_i - s.n_0;
+    const uint64_t base = (uint64_t)s.step * s.n_b * (d + 1) + (uint64_t)m * (d + 1);
+    const int nf = 2 * (d - s.face_lo);
+    int f = (int)floor(sm64_uniform(s.seed_b, base) * nf);
+    if (f > nf - 1) f = nf - 1;
+    const int fc = s.face_lo + f / 2;
+    const int row = s.n_0 + m;
+    for (int j = 0; j < d; j++) {
+      const double v = j == fc ? (double)(f % 2) : sm64_uniform(s.seed_b, base + 1 + j);
+      xb[(long)row * d + j] = (TP)v;
+      if (j == 0) x0 = v;
+      const double sv = sin(pi * v);
+      ssum += sv;
+      if (j >= 1) hsum += sv;
+    }
+    yb[row] = (TP)target_g(x0, ssum, hsum, s.kind, s.scale, s.kappa);
+  }
+}
+
+hipError_t sample(Prec p, SamplerDesc s, void* xi, void* yi, void* xb, void* yb, hipStream_t st) {
+  int tot = s.n_i + s.n_0 + s.n_b;
+  int nb = (tot + 127) / 128;
+  if (nb < 1) return hipSuccess;
+  if (p == P_F64)
+    k_sample<double><<<nb, 128, 0, st>>>(s, (double*)xi, (double*)yi, (double*)xb, (double*)yb);
+  else
+    k_sample<float><<<nb, 128, 0, st>>>(s, (float*)xi, (float*)yi, (float*)xb, (float*)yb);
+  return hipGetLastError();
+}
+
+}  // namespace kp

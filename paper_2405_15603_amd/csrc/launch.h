@@ -1,0 +1,157 @@
+// Internal launcher interface between the host orchestration (api.cpp) and the
+// kernel translation units.  Every launcher enqueues on `st` and returns the
+// hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kp {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+// ---- layer products ---------------------------------------------------------
+// C[M x N] = A[M x K] * B[N x K]^T (+ B2 for the low part of a split operand),
+// rows of A and B hold K contiguous elements (lda, ldb >= K, K a multiple of the
+// 16-byte vector and zero beyond the true width).  Result in the compute type
+// (double for P_F64, float otherwise) at out[row*ldo + col], plus bias[col] on
+// rows with row % S == 0 when bias != nullptr.
+hipError_t gemm_nt(Prec p, const void* A, long lda, const void* B, const void* B2, long ldb,
+                   int M, int N, int K, void* out, long ldo, const void* bias, int S,
+                   hipStream_t st);
+
+// ---- factor / gradient products --------------------------------------------
+// part[s][m*N + n] = sum_{k in split s} w(k) A[k][m] B[k][n] for the tiles the
+// kernel covers (sym: only tiles at or above the diagonal).  w(k) = rw[k / S]
+// when rw != nullptr, else 1.  A and B are row-major K x (>= M / N) with lda/ldb.
+// part is double for P_F64, float otherwise.  Returns the number of splits used
+// through *splits_out (chosen by the launcher, <= max_splits).
+hipError_t gemm_tn_splitk(Prec p, const void* A, long lda, const void* B, long ldb, int M, int N,
+                          int K, const double* rw, int S, bool sym, void* part, int max_splits,
+                          int* splits_out, hipStream_t st);
+// out[m*so_m + n*so_n] = c_prev*out + alpha * sum_s part[s][m*N+n]  (double out);
+// with sym the lower triangle is mirrored from the upper.
+hipError_t reduce_splitk(Prec p, const void* part, int splits, int M, int N, bool sym,
+                         double* out, long so_m, long so_n, double alpha, double c_prev,
+                         hipStream_t st);
+
+// ---- elementwise ------------------------------------------------------------
+struct LayerDesc {
+  int h_in, h_out;
+  long off;          // offset of the layer in theta
+  long ldk_in;       // row length of the forward weight copy (>= h_in+1)
+  long ldk_out;      // row length of the backward weight copy (>= h_out)
+  long wrm, wcm;     // element offsets of the two copies in the weight buffer
+};
+struct NetDesc {
+  int L;
+  LayerDesc l[8];
+};
+// Builds the product-layout copies of W~ = theta (+ alpha*dir) for all layers:
+// forward copy (h_out x ldk_in, bias in column h_in) and backward copy
+// (h_in x ldk_out, W transposed, no bias), plus biases (compute type) and, for
+// BF16, the residual low parts.
+hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha, NetDesc nd,
+                        void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st);
+
+// Input slab Z~^(0): S rows per point (value x, unit rows e_i, zero Laplacian row)
+// plus the bias column; n points, d inputs, row length ldz.
+hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long ldz,
+                      hipStream_t st);
+
+// tanh rows (forward Laplacian activation rule): pre (compute type, ldp) ->
+// z (storage type, ldz) with the bias column at h and zeros beyond.
+hipError_t act_fwd(Prec p, const void* pre, long ldp, void* z, long ldz, int npts, int S, int nd,
+                   int has_lap, const uint8_t* mask, int h, hipStream_t st);
+// Adjoint of the tanh rows: zbar (compute type, ldzb) and pre -> g (storage, ldg).
+hipError_t act_bwd(Prec p, const void* zbar, long ldzb, const void* pre, long ldp, void* g,
+                   long ldg, int npts, int S, int nd, int has_lap, const uint8_t* mask, int h,
+                   hipStream_t st);
+
+// Residual, loss partials and the output seed.  pre: last layer output rows
+// (compute type, ldp); y: targets (real); r: residual per point (double);
+// g: seed rows (storage type, ldg; nullptr = not written); partial: per-block
+// sums of r^2 (double, grid size returned by residual_blocks).
+int residual_blocks(int npts);
+hipError_t residual(Prec p, const void* pre, long ldp, const void* y, int npts, int S,
+                    int time_row, double c_t, double c_lap, int lap_row, double* r, void* g,
+                    long ldg, double* partial, hipStream_t st);
+// loss[slot] = scale * sum(partial[0..nb)) (+ loss[slot] if accumulate)
+hipError_t finalize_loss(const double* partial, int nb, double scale, double* loss, int slot,
+                         int accumulate, hipStream_t st);
+
+// Network outputs for the forward-Laplacian entry point: u, grad, lap (real).
+hipError_t extract_outputs(Prec p, const void* pre, long ldp, int npts, int S, int d, int lap_row,
+                           void* u, void* grad, void* lap, hipStream_t st);
+// Output seed rows of a general cotangent (u_bar, grad_bar, lap_bar; real, nullable).
+hipError_t seed_rows(Prec p, const void* u_bar, const void* grad_bar, const void* lap_bar,
+                     int npts, int S, int d, int lap_row, void* g, long ldg, hipStream_t st);
+// x_bar[n][k] = sum_j W1[j][k] g1[n*S][j]  (value row of the first layer)
+hipError_t input_vjp(Prec p, const void* theta, int h_out, int d, const void* g1, long ldg,
+                     int npts, int S, void* x_bar, hipStream_t st);
+
+// ---- optimizer --------------------------------------------------------------
+hipError_t ema_fill(double* a, long n, int dim, int identity, hipStream_t st);
+// dhat = mu*delta + Delta  (real dhat, real delta, double Delta); use_mom = 0 -> dhat = Delta
+hipError_t momentum(Prec p, const double* Delta, const void* delta, double mu, const int* step,
+                    void* dhat, long D, hipStream_t st);
+// alpha* from candidate losses; then theta += alpha*dhat, delta = alpha*dhat;
+// writes info and status.  fixed_lr >= 0 -> fixed mode.
+hipError_t finish_step(Prec p, const double* losses, int ncand, int kmax, double fixed_lr,
+                       const double* base_loss, void* theta, void* dhat, void* delta, long D,
+                       int* status, int* step, void* info, hipStream_t st);
+
+// ---- sampler ----------------------------------------------------------------
+struct SamplerDesc {
+  uint64_t seed_i, seed_b, seed_0;
+  int n_i, n_b, n_0, d, face_lo, kind;
+  double scale, kappa;
+  long step;
+};
+hipError_t sample(Prec p, SamplerDesc s, void* xi, void* yi, void* xb, void* yb, hipStream_t st);
+
+// ---- FP64 linear algebra for the Kronecker-sum inverse ---------------------
+// All problems are padded to n_pad (multiple of 64) square, row-major.
+struct EigProblem {
+  int n, n_pad;
+  const double* f1;   // interior factor (n x n, row-major, EMA state)
+  const double* f2;   // boundary factor
+  double* M1;         // n_pad^2 work: damped F1, trailing updates
+  double* M2;         // n_pad^2 work: damped F2, then scratch
+  double* Lb;         // n_pad^2: Cholesky factor L
+  double* Li;         // n_pad^2: L^-1
+  double* C[2];       // n_pad^2 ping-pong: whitened F2 during Jacobi
+  double* P[2];       // n_pad^2 ping-pong: accumulated transform
+  double* V;          // (n_pad/64) * 64*64: pair rotations of one round
+  double* Pout;       // n x n result P (row-major)
+  double* eout;       // n eigenvalues
+};
+hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
+                            EigProblem* probs_dev, int* status, double* scratch, int max_sweeps,
+                            hipStream_t st);
+// Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T for every layer, V = gradient
+// (column-major h_out x (h_in+1) inside the theta layout).  Four strided FP64
+// products per layer, described once (descriptors in device memory).
+struct KronApply {
+  int nA, nB;
+  long off;                 // layer offset in theta
+  const double *PA, *a, *PB, *b;
+};
+struct G64 {                // C[i*sci + j*scj] = alpha sum_k A(i,k) B(k,j) [/(1 + eb_i ea_j)]
+  const double* A;
+  long sai, sak;
+  const double* B;
+  long sbk, sbj;
+  double* C;
+  long sci, scj;
+  int M, N, K;
+  double alpha;
+  const double* ea;
+  const double* eb;
+};
+// fills h[4*L] (host) for the given buffers; tmp needs L * tmp_stride doubles,
+// tmp_stride >= 2 * nA * nB of every layer
+void kron_apply_descs(const KronApply* layers, int L, const double* grad, double* delta,
+                      double* tmp, long tmp_stride, G64* h, int* mmax, int* nmax);
+hipError_t kron_apply_batched(const G64* descs_dev, int L, int mmax, int nmax, hipStream_t st);
+
+}  // namespace kp

@@ -1,0 +1,626 @@
+// FP64 linear algebra for the inverse of the damped Kronecker sum (Section 3.4).
+//
+// For every layer and side the pair (F1, F2) = (damped interior factor, damped
+// boundary factor) is brought to P^T F1 P = I, P^T F2 P = diag(e):
+//   1. blocked Cholesky F1 = L L^T (64 x 64 blocks),
+//   2. blocked triangular inverse L^-1,
+//   3. C = L^-1 F2 L^-T (two products),
+//   4. two-sided block Jacobi on C (32-wide blocks, round-robin pairing of
+//      block pairs; each pair's 64 x 64 subproblem gets one cyclic Jacobi sweep
+//      in LDS, then the rotations are applied to C and accumulated into
+//      P = L^-T V), until the off-diagonal mass of C falls below 1e-15 of its
+//      diagonal,
+//   5. e = diag(C), P.
+// The inverse of A1 (x) B1 + A2 (x) B2 is then (P_A (x) P_B)(I + e_A (x) e_B)^-1
+// (P_A (x) P_B)^T.  Every problem is padded to a multiple of 64 with an identity
+// block in F1 and a zero block in F2, which stays exactly decoupled.
+// All problems of a step run in the same launches (grid.y = problem).
+#include "common.h"
+#include "launch.h"
+
+namespace kp {
+
+constexpr int BB = 64;        // Cholesky / inverse block
+constexpr int LDB = BB + 1;   // LDS row stride (doubles)
+constexpr int JB = 32;        // Jacobi block
+
+// acc[4][4] += op(A) op(B) over k in [0, 64) for the 4x4 output patch of this
+// thread (rows 4*ty.., cols 4*tx.., ty = tid/16, tx = tid%16); tiles in LDS.
+template <bool TA, bool TB>
+__device__ __forceinline__ void blk_mm(double acc[4][4], const double* A, const double* B,
+                                       int kdim = BB) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  for (int k = 0; k < kdim; k++) {
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) a[i] = TA ? A[k * LDB + ty * 4 + i] : A[(ty * 4 + i) * LDB + k];
+#pragma unroll
+    for (int j = 0; j < 4; j++) b[j] = TB ? B[(tx * 4 + j) * LDB + k] : B[k * LDB + tx * 4 + j];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) acc[i][j] += a[i] * b[j];
+  }
+}
+
+__device__ __forceinline__ void tile_load(double* dst, const double* src, long ld) {
+  for (int e = threadIdx.x; e < BB * BB; e += blockDim.x)
+    dst[(e / BB) * LDB + (e % BB)] = src[(long)(e / BB) * ld + (e % BB)];
+}
+
+__device__ __forceinline__ void zero4(double acc[4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// 0. damping and padding
+// ---------------------------------------------------------------------------
+__global__ void k_damp_pad(const EigProblem* __restrict__ pr, double lambda) {
+  const EigProblem p = pr[blockIdx.y];
+  const long np2 = (long)p.n_pad * p.n_pad;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < np2;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / p.n_pad), j = (int)(e % p.n_pad);
+    double a = 0.0, b = 0.0;
+    if (i < p.n && j < p.n) {
+      a = p.f1[(long)i * p.n + j];
+      b = p.f2[(long)i * p.n + j];
+      if (i == j) { a += lambda; b += lambda; }
+    } else if (i == j) {
+      a = 1.0;
+    }
+    p.M1[e] = a;
+    p.M2[e] = b;
+    p.Lb[e] = 0.0;
+    p.Li[e] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1. Cholesky: diagonal block (factor + inverse of the factor)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_diag(const EigProblem* __restrict__ pr, int j,
+                                                   int* status) {
+  const EigProblem p = pr[blockIdx.y];
+  const int nb = p.n_pad / BB;
+  if (j >= nb) return;
+  __shared__ double L[BB * LDB];
+  __shared__ double X[BB * LDB];
+  __shared__ int bad;
+  const long np = p.n_pad;
+  const double* src = p.M1 + (long)j * BB * np + (long)j * BB;
+  tile_load(L, src, np);
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < BB; k++) {
+    if (threadIdx.x == 0) {
+      double piv = L[k * LDB + k];
+      if (!(piv > 0.0)) { bad = 1; piv = 1.0; }
+      L[k * LDB + k] = sqrt(piv);
+    }
+    __syncthreads();
+    const double dk = L[k * LDB + k];
+    for (int i = k + 1 + threadIdx.x; i < BB; i += blockDim.x) L[i * LDB + k] /= dk;
+    __syncthreads();
+    const int rem = BB - k - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int i = k + 1 + e / rem, c = k + 1 + e % rem;
+      if (c <= i) L[i * LDB + c] -= L[i * LDB + k] * L[c * LDB + k];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular factor, one column per thread
+  if (threadIdx.x < BB) {
+    const int c = threadIdx.x;
+    for (int i = 0; i < BB; i++) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; k++) s -= L[i * LDB + k] * X[k * LDB + c];
+      X[i * LDB + c] = (i < c) ? 0.0 : s / L[i * LDB + i];
+    }
+  }
+  __syncthreads();
+  double* lb = p.Lb + (long)j * BB * np + (long)j * BB;
+  double* li = p.Li + (long)j * BB * np + (long)j * BB;
+  for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
+    const int i = e / BB, c = e % BB;
+    lb[(long)i * np + c] = c <= i ? L[i * LDB + c] : 0.0;
+    li[(long)i * np + c] = c <= i ? X[i * LDB + c] : 0.0;
+  }
+  if (threadIdx.x == 0 && bad) atomicMax(status, 4);
+}
+
+// Panel and trailing update of step j: workgroup (i, k), j <= k <= i, i > j.
+//   L_ij = A_ij (L_jj^-1)^T;  for k > j: A_ik -= L_ij L_kj^T.
+__global__ __launch_bounds__(256) void k_chol_update(const EigProblem* __restrict__ pr, int j) {
+  const EigProblem p = pr[blockIdx.y];
+  const int nb = p.n_pad / BB;
+  if (j >= nb - 1) return;
+  int w = blockIdx.x, i = j + 1, k;
+  {
+    int rowlen = 2;   // row i has (i - j + 1) blocks k = j..i
+    while (w >= rowlen) { w -= rowlen; i++; rowlen++; }
+    if (i >= nb) return;
+    k = j + w;
+  }
+  __shared__ double T[BB * LDB];   // L_jj^-1
+  __shared__ double Ai[BB * LDB];
+  __shared__ double Ak[BB * LDB];
+  const long np = p.n_pad;
+  tile_load(T, p.Li + (long)j * BB * np + (long)j * BB, np);
+  tile_load(Ai, p.M1 + (long)i * BB * np + (long)j * BB, np);
+  if (k > j && k != i) tile_load(Ak, p.M1 + (long)k * BB * np + (long)j * BB, np);
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double li[4][4], lk[4][4];
+  zero4(li);
+  blk_mm<false, true>(li, Ai, T);
+  if (k > j && k != i) {
+    zero4(lk);
+    blk_mm<false, true>(lk, Ak, T);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      Ai[(ty * 4 + a) * LDB + tx * 4 + b] = li[a][b];
+      if (k > j && k != i) Ak[(ty * 4 + a) * LDB + tx * 4 + b] = lk[a][b];
+    }
+  __syncthreads();
+  if (k == j) {
+    double* dst = p.Lb + (long)i * BB * np + (long)j * BB;
+    for (int e = threadIdx.x; e < BB * BB; e += blockDim.x)
+      dst[(long)(e / BB) * np + (e % BB)] = Ai[(e / BB) * LDB + (e % BB)];
+    return;
+  }
+  double acc[4][4];
+  zero4(acc);
+  blk_mm<false, true>(acc, Ai, (k == i) ? Ai : Ak);
+  double* dst = p.M1 + (long)i * BB * np + (long)k * BB;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) dst[(long)(ty * 4 + a) * np + tx * 4 + b] -= acc[a][b];
+}
+
+// ---------------------------------------------------------------------------
+// 2. Triangular inverse, block row i:  Li_ij = -Li_ii sum_{k=j}^{i-1} L_ik Li_kj
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trtri_row(const EigProblem* __restrict__ pr, int i) {
+  const EigProblem p = pr[blockIdx.y];
+  const int nb = p.n_pad / BB;
+  const int j = blockIdx.x;
+  if (i >= nb || j >= i) return;
+  __shared__ double A[BB * LDB];
+  __shared__ double B[BB * LDB];
+  const long np = p.n_pad;
+  double acc[4][4];
+  zero4(acc);
+  for (int k = j; k < i; k++) {
+    __syncthreads();
+    tile_load(A, p.Lb + (long)i * BB * np + (long)k * BB, np);
+    tile_load(B, p.Li + (long)k * BB * np + (long)j * BB, np);
+    __syncthreads();
+    blk_mm<false, false>(acc, A, B);
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) B[(ty * 4 + a) * LDB + tx * 4 + b] = acc[a][b];
+  tile_load(A, p.Li + (long)i * BB * np + (long)i * BB, np);
+  __syncthreads();
+  double r[4][4];
+  zero4(r);
+  blk_mm<false, false>(r, A, B);
+  double* dst = p.Li + (long)i * BB * np + (long)j * BB;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) dst[(long)(ty * 4 + a) * np + tx * 4 + b] = -r[a][b];
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP64 product  C = A B^T  over 64 x 64 tiles (n_pad x n_pad operands):
+// mode 0: C1 <- Li * F2   (F2 symmetric, so F2 = F2^T),
+// mode 1: C0 <- C1 * Li^T
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_whiten(const EigProblem* __restrict__ pr, int mode) {
+  const EigProblem p = pr[blockIdx.z];
+  const int nb = p.n_pad / BB;
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi >= nb || bj >= nb) return;
+  const long np = p.n_pad;
+  const double* A = mode == 0 ? p.Li : p.C[1];
+  const double* B = mode == 0 ? p.M2 : p.Li;
+  __shared__ double As[BB * LDB];
+  __shared__ double Bs[BB * LDB];
+  double acc[4][4];
+  zero4(acc);
+  // Li is lower triangular: only k blocks <= bi (mode 0) or <= bj (mode 1) contribute
+  const int kend = mode == 0 ? bi : bj;
+  for (int k = 0; k <= kend; k++) {
+    __syncthreads();
+    tile_load(As, A + (long)bi * BB * np + (long)k * BB, np);
+    tile_load(Bs, B + (long)bj * BB * np + (long)k * BB, np);
+    __syncthreads();
+    blk_mm<false, true>(acc, As, Bs);
+  }
+  // mode 0 writes into the C[1] buffer (scratch), mode 1 into C[0]
+  double* out = mode == 0 ? p.C[1] : p.C[0];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+      out[(long)(bi * BB + ty * 4 + a) * np + bj * BB + tx * 4 + b] = acc[a][b];
+}
+
+// C0 <- (C0 + C0^T)/2, P0 <- Li^T, flags reset
+__global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done) {
+  const EigProblem p = pr[blockIdx.y];
+  const long np = p.n_pad;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < np * np;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / np), j = (int)(e % np);
+    p.P[0][e] = p.Li[(long)j * np + i];
+    if (j > i) {
+      const double v = 0.5 * (p.C[0][e] + p.C[0][(long)j * np + i]);
+      p.C[0][e] = v;
+      p.C[0][(long)j * np + i] = v;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    done[2 * blockIdx.y] = 0;
+    done[2 * blockIdx.y + 1] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. Block Jacobi
+// ---------------------------------------------------------------------------
+// round-robin position of slot k in round r among m players (player 0 fixed)
+__device__ __forceinline__ int rr_pos(int k, int r, int m) {
+  return k == 0 ? 0 : 1 + ((k - 1 + r) % (m - 1));
+}
+// blocks (x, y), x < y, of pair i in round r with nblk blocks
+__device__ __forceinline__ void pair_blocks(int i, int r, int nblk, int& x, int& y) {
+  int a = rr_pos(i, r, nblk), b = rr_pos(nblk - 1 - i, r, nblk);
+  x = a < b ? a : b;
+  y = a < b ? b : a;
+}
+
+__device__ __forceinline__ bool jac_active(const EigProblem& p, const int* done, int q, int sweep,
+                                           int r, int& src) {
+  const int nblk = p.n_pad / JB;
+  if (done[2 * q] || r >= nblk - 1) return false;
+  src = (int)(((long)sweep * (nblk - 1) + r) & 1);
+  return true;
+}
+
+constexpr int JS = 2 * JB;      // subproblem size
+constexpr int LDJ = JS + 1;
+
+__global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict__ pr,
+                                                   const int* __restrict__ done, int sweep, int r,
+                                                   int inner) {
+  const int q = blockIdx.y;
+  const EigProblem p = pr[q];
+  int src;
+  if (!jac_active(p, done, q, sweep, r, src)) return;
+  const int nblk = p.n_pad / JB;
+  const int i = blockIdx.x;
+  if (i >= nblk / 2) return;
+  int bx, by;
+  pair_blocks(i, r, nblk, bx, by);
+  __shared__ double S[JS * LDJ];
+  __shared__ double V[JS * LDJ];
+  __shared__ double cs[JB], sn[JB];
+  __shared__ int pp[JB], qq[JB];
+  const long np = p.n_pad;
+  const double* C = p.C[src];
+  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+    const int a = e / JS, b = e % JS;
+    const int ga = (a < JB ? bx * JB + a : by * JB + a - JB);
+    const int gb = (b < JB ? bx * JB + b : by * JB + b - JB);
+    S[a * LDJ + b] = C[(long)ga * np + gb];
+    V[a * LDJ + b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < inner; sw++) {
+    for (int rr = 0; rr < JS - 1; rr++) {
+      if (threadIdx.x < JB) {
+        const int k = threadIdx.x;
+        int a = rr_pos(k, rr, JS), b = rr_pos(JS - 1 - k, rr, JS);
+        if (a > b) { int t = a; a = b; b = t; }
+        const double apq = S[a * LDJ + b];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0) {
+          const double th = (S[b * LDJ + b] - S[a * LDJ + a]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+        }
+        cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
+      }
+      __syncthreads();
+      // rows: S <- J^T S
+      for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
+        const int k = e / JS, col = e % JS;
+        const int a = pp[k], b = qq[k];
+        const double c = cs[k], s = sn[k];
+        const double xa = S[a * LDJ + col], xb = S[b * LDJ + col];
+        S[a * LDJ + col] = c * xa - s * xb;
+        S[b * LDJ + col] = s * xa + c * xb;
+      }
+      __syncthreads();
+      // columns: S <- S J, V <- V J
+      for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
+        const int k = e / JS, row = e % JS;
+        const int a = pp[k], b = qq[k];
+        const double c = cs[k], s = sn[k];
+        double xa = S[row * LDJ + a], xb = S[row * LDJ + b];
+        S[row * LDJ + a] = c * xa - s * xb;
+        S[row * LDJ + b] = s * xa + c * xb;
+        xa = V[row * LDJ + a];
+        xb = V[row * LDJ + b];
+        V[row * LDJ + a] = c * xa - s * xb;
+        V[row * LDJ + b] = s * xa + c * xb;
+      }
+      __syncthreads();
+    }
+  }
+  double* Vo = p.V + (long)i * JS * JS;
+  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) Vo[e] = V[(e / JS) * LDJ + (e % JS)];
+}
+
+// pair index and half of block X in round r
+__device__ __forceinline__ void block_pair(int X, int r, int nblk, int& pi, int& half, int& x0,
+                                           int& x1) {
+  for (int i = 0; i < nblk / 2; i++) {
+    int a, b;
+    pair_blocks(i, r, nblk, a, b);
+    if (a == X || b == X) {
+      pi = i; half = (X == a) ? 0 : 1; x0 = a; x1 = b;
+      return;
+    }
+  }
+  pi = 0; half = 0; x0 = X; x1 = X;
+}
+
+// new C[X][Y] = Vx[:, hx]^T [C(x*, y*)] Vy[:, hy]  (upper blocks, mirrored)
+// new P[R][Y] = [P(R, y0) P(R, y1)] Vy[:, hy]
+__global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict__ pr,
+                                                   const int* __restrict__ done, int sweep,
+                                                   int r) {
+  const int q = blockIdx.y;
+  const EigProblem p = pr[q];
+  int src;
+  if (!jac_active(p, done, q, sweep, r, src)) return;
+  const int nblk = p.n_pad / JB;
+  const int ncb = nblk * (nblk + 1) / 2;
+  int w = blockIdx.x;
+  if (w >= ncb + nblk * nblk) return;
+  const long np = p.n_pad;
+  __shared__ double G[JS * LDJ];
+  __shared__ double Vy[JS * (JB + 1)];
+  __shared__ double Vx[JS * (JB + 1)];
+  __shared__ double T[JS * (JB + 1)];
+  const int tid = threadIdx.x;
+  const double* Cs = p.C[src];
+  double* Cd = p.C[src ^ 1];
+  if (w < ncb) {
+    int X = 0, rowlen = nblk;
+    while (w >= rowlen) { w -= rowlen; X++; rowlen--; }
+    const int Y = X + w;
+    int px, hx, x0, x1, py, hy, y0, y1;
+    block_pair(X, r, nblk, px, hx, x0, x1);
+    block_pair(Y, r, nblk, py, hy, y0, y1);
+    const double* VX = p.V + (long)px * JS * JS;
+    const double* VY = p.V + (long)py * JS * JS;
+    for (int e = tid; e < JS * JS; e += blockDim.x) {
+      const int a = e / JS, b = e % JS;
+      const int ga = a < JB ? x0 * JB + a : x1 * JB + a - JB;
+      const int gb = b < JB ? y0 * JB + b : y1 * JB + b - JB;
+      G[a * LDJ + b] = Cs[(long)ga * np + gb];
+    }
+    for (int e = tid; e < JS * JB; e += blockDim.x) {
+      const int a = e / JB, b = e % JB;
+      Vy[a * (JB + 1) + b] = VY[a * JS + hy * JB + b];
+      Vx[a * (JB + 1) + b] = VX[a * JS + hx * JB + b];
+    }
+    __syncthreads();
+    // T = G Vy   (64 x 32): 8 outputs per thread
+    for (int e = tid; e < JS * JB; e += blockDim.x) {
+      const int a = e / JB, b = e % JB;
+      double s = 0.0;
+      for (int k = 0; k < JS; k++) s += G[a * LDJ + k] * Vy[k * (JB + 1) + b];
+      T[a * (JB + 1) + b] = s;
+    }
+    __syncthreads();
+    // out = Vx^T T (32 x 32)
+    for (int e = tid; e < JB * JB; e += blockDim.x) {
+      const int a = e / JB, b = e % JB;
+      double s = 0.0;
+      for (int k = 0; k < JS; k++) s += Vx[k * (JB + 1) + a] * T[k * (JB + 1) + b];
+      Cd[(long)(X * JB + a) * np + Y * JB + b] = s;
+      if (X != Y) Cd[(long)(Y * JB + b) * np + X * JB + a] = s;
+    }
+  } else {
+    w -= ncb;
+    const int R = w / nblk, Y = w % nblk;
+    int py, hy, y0, y1;
+    block_pair(Y, r, nblk, py, hy, y0, y1);
+    const double* VY = p.V + (long)py * JS * JS;
+    const double* Ps = p.P[src];
+    double* Pd = p.P[src ^ 1];
+    for (int e = tid; e < JB * JS; e += blockDim.x) {
+      const int a = e / JS, b = e % JS;
+      const int gb = b < JB ? y0 * JB + b : y1 * JB + b - JB;
+      G[a * LDJ + b] = Ps[(long)(R * JB + a) * np + gb];
+    }
+    for (int e = tid; e < JS * JB; e += blockDim.x) {
+      const int a = e / JB, b = e % JB;
+      Vy[a * (JB + 1) + b] = VY[a * JS + hy * JB + b];
+    }
+    __syncthreads();
+    for (int e = tid; e < JB * JB; e += blockDim.x) {
+      const int a = e / JB, b = e % JB;
+      double s = 0.0;
+      for (int k = 0; k < JS; k++) s += G[a * LDJ + k] * Vy[k * (JB + 1) + b];
+      Pd[(long)(R * JB + a) * np + Y * JB + b] = s;
+    }
+  }
+}
+
+// After a sweep: converged when off(C)^2 <= tol^2 * sum diag(C)^2 (or exact
+// diagonal).  Records the buffer that holds the result.
+__global__ __launch_bounds__(1024) void k_jac_check(const EigProblem* __restrict__ pr, int* done,
+                                                    int sweep, double tol) {
+  const int q = blockIdx.x;
+  const EigProblem p = pr[q];
+  if (done[2 * q]) return;
+  const int nblk = p.n_pad / JB;
+  const int cur = (int)(((long)(sweep + 1) * (nblk - 1)) & 1);
+  const double* C = p.C[cur];
+  const long np = p.n_pad;
+  double off = 0.0, dia = 0.0;
+  for (long e = threadIdx.x; e < np * np; e += blockDim.x) {
+    const double v = C[e];
+    if (e / np == e % np) dia += v * v;
+    else off += v * v;
+  }
+  __shared__ double r1[16], r2[16];
+  off = warp_sum(off);
+  dia = warp_sum(dia);
+  if ((threadIdx.x & 63) == 0) { r1[threadIdx.x >> 6] = off; r2[threadIdx.x >> 6] = dia; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = 0.0, d = 0.0;
+    for (int i = 0; i < (int)(blockDim.x / 64); i++) { o += r1[i]; d += r2[i]; }
+    if (o <= tol * tol * d || !(o == o)) {
+      done[2 * q] = 1;
+      done[2 * q + 1] = cur;
+    } else {
+      done[2 * q + 1] = cur;
+    }
+  }
+}
+
+__global__ void k_jac_extract(const EigProblem* __restrict__ pr, const int* __restrict__ done) {
+  const EigProblem p = pr[blockIdx.y];
+  const int cur = done[2 * blockIdx.y + 1];
+  const long np = p.n_pad;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (long)p.n * p.n;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / p.n), j = (int)(e % p.n);
+    p.Pout[e] = p.P[cur][(long)i * np + j];
+    if (i == j) p.eout[i] = p.C[cur][(long)i * np + i];
+  }
+}
+
+hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
+                            EigProblem* probs_dev, int* status, double* scratch, int max_sweeps,
+                            hipStream_t st) {
+  (void)scratch;
+  if (nprob <= 0) return hipSuccess;
+  int npmax = 0;
+  for (int q = 0; q < nprob; q++) npmax = probs_host[q].n_pad > npmax ? probs_host[q].n_pad : npmax;
+  const int nbmax = npmax / BB;
+  int* done = status + 8;   // 2 ints per problem after the status block
+  k_damp_pad<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, lambda);
+  for (int j = 0; j < nbmax; j++) {
+    k_chol_diag<<<dim3(1, nprob), 256, 0, st>>>(probs_dev, j, status);
+    const int rem = nbmax - 1 - j;
+    if (rem > 0) {
+      const int nw = rem * (rem + 3) / 2;   // sum_{i=j+1}^{nb-1} (i - j + 1)
+      k_chol_update<<<dim3(nw, nprob), 256, 0, st>>>(probs_dev, j);
+    }
+  }
+  for (int i = 1; i < nbmax; i++) k_trtri_row<<<dim3(i, nprob), 256, 0, st>>>(probs_dev, i);
+  k_whiten<<<dim3(nbmax, nbmax, nprob), 256, 0, st>>>(probs_dev, 0);
+  k_whiten<<<dim3(nbmax, nbmax, nprob), 256, 0, st>>>(probs_dev, 1);
+  k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done);
+  const int nblk = npmax / JB;
+  const int ncb = nblk * (nblk + 1) / 2 + nblk * nblk;
+  for (int sw = 0; sw < max_sweeps; sw++) {
+    for (int r = 0; r < nblk - 1; r++) {
+      k_jac_solve<<<dim3(nblk / 2, nprob), 256, 0, st>>>(probs_dev, done, sw, r, 1);
+      k_jac_apply<<<dim3(ncb, nprob), 256, 0, st>>>(probs_dev, done, sw, r);
+    }
+    k_jac_check<<<nprob, 1024, 0, st>>>(probs_dev, done, sw, 1e-15);
+  }
+  k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev, done);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Kronecker-sum apply (per layer, FP64):
+//   Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm64(const G64* __restrict__ gs) {
+  const G64 g = gs[blockIdx.z];
+  const int i0 = blockIdx.y * BB, j0 = blockIdx.x * BB;
+  if (i0 >= g.M || j0 >= g.N) return;
+  __shared__ double As[BB * LDB];
+  __shared__ double Bs[BB * LDB];
+  double acc[4][4];
+  zero4(acc);
+  for (int k0 = 0; k0 < g.K; k0 += BB) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
+      const int a = e / BB, b = e % BB;
+      As[a * LDB + b] = (i0 + a < g.M && k0 + b < g.K) ? g.A[(i0 + a) * g.sai + (k0 + b) * g.sak] : 0.0;
+      Bs[a * LDB + b] = (k0 + a < g.K && j0 + b < g.N) ? g.B[(k0 + a) * g.sbk + (j0 + b) * g.sbj] : 0.0;
+    }
+    __syncthreads();
+    blk_mm<false, false>(acc, As, Bs);
+  }
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
+      if (i < g.M && j < g.N) {
+        double v = g.alpha * acc[a][b];
+        if (g.ea) v /= (1.0 + g.eb[i] * g.ea[j]);
+        g.C[i * g.sci + j * g.scj] = v;
+      }
+    }
+}
+
+void kron_apply_descs(const KronApply* layers, int L, const double* grad, double* delta,
+                      double* tmp, long tmp_stride, G64* h, int* mmax, int* nmax) {
+  *mmax = 0;
+  *nmax = 0;
+  for (int l = 0; l < L; l++) {
+    const KronApply& k = layers[l];
+    double* T1 = tmp + (long)l * tmp_stride;             // nB x nA
+    double* T2 = T1 + (long)k.nA * k.nB;                 // nB x nA
+    const double* V = grad + k.off;                      // V[i][j] at j*nB + i
+    double* D = delta + k.off;
+    // T1 = P_B^T V
+    h[0 * L + l] = G64{k.PB, 1, k.nB, V, 1, k.nB, T1, k.nA, 1, k.nB, k.nA, k.nB, 1.0, nullptr, nullptr};
+    // T2 = (T1 P_A) / (1 + b a^T)
+    h[1 * L + l] = G64{T1, k.nA, 1, k.PA, k.nA, 1, T2, k.nA, 1, k.nB, k.nA, k.nA, 1.0, k.a, k.b};
+    // T1 = P_B T2
+    h[2 * L + l] = G64{k.PB, k.nB, 1, T2, k.nA, 1, T1, k.nA, 1, k.nB, k.nA, k.nB, 1.0, nullptr, nullptr};
+    // D = -T1 P_A^T  (column-major into the theta layout)
+    h[3 * L + l] = G64{T1, k.nA, 1, k.PA, 1, k.nA, D, 1, k.nB, k.nB, k.nA, k.nA, -1.0, nullptr, nullptr};
+    *mmax = k.nB > *mmax ? k.nB : *mmax;
+    *nmax = k.nA > *nmax ? k.nA : *nmax;
+  }
+}
+
+hipError_t kron_apply_batched(const G64* descs_dev, int L, int mmax, int nmax, hipStream_t st) {
+  dim3 g(kp_cdiv(nmax, BB), kp_cdiv(mmax, BB), L);
+  for (int s = 0; s < 4; s++) k_gemm64<<<g, 256, 0, st>>>(descs_dev + s * L);
+  return hipGetLastError();
+}
+
+}  // namespace kp

@@ -1,0 +1,168 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same
+seeded inputs.  Tolerances: FP64 path 1e-10 (1e-12 for the forward Laplacian),
+FP32 path 1e-5 for the Laplacian and factors, 1e-4 for the gradient."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import oracle_curvature, problem_inputs, rel, rounded, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def kp_for(p, precision, **kw):
+    from paper_2405_15603_amd import KfacPinn
+    return KfacPinn.for_problem(p, precision, **kw)
+
+
+CASES = {
+    "tiny_poisson": lambda: synth.small_problem("poisson", (3, 16, 12, 1), 37, 11, problem_id=71),
+    "tiny_heat": lambda: synth.small_problem("heat", (3, 20, 9, 1), 29, 7, n_init=6, problem_id=72),
+    "poisson2d": synth.poisson2d,
+    "ragged": lambda: synth.small_problem("poisson", (7, 130, 67, 33, 1), 151, 45, problem_id=73),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_forward_laplacian(case, precision, tol):
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, precision)
+    kp = kp_for(p, precision)
+    u, g, lap = kp.forward_laplacian(to_dev(th, precision), to_dev(xi, precision))
+    torch.cuda.synchronize()
+    op = oracle.operator_of(p)
+    U = oracle.forward_laplacian(oracle.unpack(torch.as_tensor(th), p.widths), torch.as_tensor(xi),
+                                 op.mask_vec(p.d)).out
+    assert rel(u, U[:, 0]) < tol
+    assert rel(g, U[:, 1:p.d + 1]) < tol
+    assert rel(lap, U[:, -1]) < tol
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision,tol,gtol", [("f64", 1e-10, 1e-10), ("f32", 1e-5, 1e-4)])
+def test_factors_gradient_loss(case, precision, tol, gtol):
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, precision)
+    kp = kp_for(p, precision)
+    grad, loss = kp.factors(*(to_dev(a, precision) for a in (th, xi, yi, xb, yb)), beta=0.0)
+    assert kp.sync() == 0
+    ref = oracle_curvature(p, th, xi, yi, xb, yb)
+    for l in range(len(p.widths) - 1):
+        for t, tn in ((0, "int"), (1, "bnd")):
+            for s, sn in ((0, "A"), (1, "B")):
+                e = rel(kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l])
+                assert e < tol, (l, tn, sn, e)
+    assert rel(grad, ref["grad"]) < gtol
+    assert rel(loss, np.array(ref["loss"])) < gtol
+
+
+def test_factors_ema_identity_init():
+    p = CASES["tiny_heat"]()
+    th, xi, yi, xb, yb = problem_inputs(p, "f64")
+    kp = kp_for(p, "f64")
+    kp.reset_state(True)
+    kp.factors(*(to_dev(a, "f64") for a in (th, xi, yi, xb, yb)), beta=0.75)
+    assert kp.sync() == 0
+    ref = oracle_curvature(p, th, xi, yi, xb, yb)
+    for l in range(len(p.widths) - 1):
+        A = ref["A_int"][l]
+        expect = 0.75 * torch.eye(A.shape[0], dtype=torch.float64) + 0.25 * A
+        assert rel(kp.get_factor(l, 0, 0), expect) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["tiny_poisson", "poisson2d", "ragged"])
+def test_invert_and_precondition(case):
+    """The applied inverse of the damped Kronecker sum equals the oracle's
+    (eigenbases are not unique, so only applied results are compared)."""
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, "f64")
+    kp = kp_for(p, "f64")
+    grad, _ = kp.factors(*(to_dev(a, "f64") for a in (th, xi, yi, xb, yb)), beta=0.0)
+    lam = 1e-3
+    kp.invert(lam)
+    delta = kp.precondition(grad)
+    assert kp.sync() == 0
+    ref = oracle_curvature(p, th, xi, yi, xb, yb)
+    gW = oracle.unpack(ref["grad"], p.widths)
+    expect = []
+    for l in range(len(gW)):
+        inv = oracle.kron_sum_inverse(oracle.damp(ref["A_int"][l], lam), oracle.damp(ref["B_int"][l], lam),
+                                      oracle.damp(ref["A_bnd"][l], lam), oracle.damp(ref["B_bnd"][l], lam))
+        expect.append(-inv.apply(gW[l]))
+        # P^T F1 P = I and P^T F2 P = diag(e) for both sides
+        for side, (f1, f2) in enumerate(((ref["A_int"][l], ref["A_bnd"][l]),
+                                         (ref["B_int"][l], ref["B_bnd"][l]))):
+            P, e = kp.get_preconditioner(l, side)
+            P, e = P.cpu(), e.cpu()
+            n = P.shape[0]
+            I = torch.eye(n, dtype=torch.float64)
+            assert rel(P.T @ oracle.damp(f1, lam) @ P, I) < 1e-10
+            assert rel(P.T @ oracle.damp(f2, lam) @ P, torch.diag(e)) < 1e-10
+    assert rel(delta, oracle.pack(expect)) < 1e-9
+
+
+@pytest.mark.parametrize("case", ["tiny_poisson", "tiny_heat", "poisson2d"])
+def test_full_step_f64(case):
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, "f64")
+    from paper_2405_15603_amd import HParams, KfacPinn
+    kp = kp_for(p, "f64")
+    for hp_o, hp_g in [
+        (oracle.HParams(lam=1e-3, beta=0.0, lr_mode="grid"), HParams(lam=1e-3, beta=0.0)),
+        (oracle.HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="fixed", lr=0.5),
+         HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="fixed", lr=0.5)),
+    ]:
+        kp.reset_state(True)
+        tht = to_dev(th, "f64")
+        info = kp.step(tht, *(to_dev(a, "f64") for a in (xi, yi, xb, yb)), hp_g)
+        assert kp.sync() == 0
+        ref, st, rinfo = oracle.kfac_step(th, p.widths, (xi, yi, xb, yb), oracle.operator_of(p),
+                                          hp_o, oracle.init_state(p.widths, True))
+        d = KfacPinn.decode_info(info)
+        assert d["lr"] == rinfo.lr
+        assert rel(tht, ref) < 1e-10
+        assert abs(d["loss_interior"] - rinfo.loss_interior) <= 1e-10 * abs(rinfo.loss_interior)
+        if hp_o.lr_mode == "grid":
+            assert rel(kp.get_line_search(31), np.array(rinfo.candidate_losses)) < 1e-10
+
+
+def test_sampler_matches_seeded_generator():
+    """GPU SplitMix64 sampler against the seeded generator: points bit-exact,
+    targets to rounding of sin/exp."""
+    from paper_2405_15603_amd import sampler_for
+    for p in (synth.poisson5d(), synth.heat4d(), synth.poisson2d()):
+        kp = kp_for(p, "f64")
+        steps = (0, 3) if p.resample else (0,)
+        for step in steps:
+            xi, yi, xb, yb = kp.sample(sampler_for(p), step, p.n_interior, p.n_cond)
+            torch.cuda.synchronize()
+            r = p.batch(step)
+            assert np.array_equal(xi.cpu().numpy(), r[0])
+            assert np.array_equal(xb.cpu().numpy(), r[2])
+            assert rel(yi, r[1]) < 1e-14 and rel(yb, r[3]) < 1e-14
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-11), ("f32", 1e-4)])
+def test_vjp_matches_autograd_of_oracle(precision, tol):
+    p = CASES["tiny_heat"]()
+    th, xi, yi, xb, yb = problem_inputs(p, precision)
+    kp = kp_for(p, precision)
+    g = torch.Generator().manual_seed(3)
+    n, d = xi.shape
+    ub, gb, lb = torch.randn(n, generator=g, dtype=torch.float64), torch.randn(n, d, generator=g, dtype=torch.float64), torch.randn(n, generator=g, dtype=torch.float64)
+    ub, gb, lb = (torch.as_tensor(rounded(a.numpy(), precision)) for a in (ub, gb, lb))
+    tb, xbar = kp.forward_laplacian_vjp(to_dev(th, precision), to_dev(xi, precision),
+                                        to_dev(ub, precision), to_dev(gb, precision), to_dev(lb, precision))
+    torch.cuda.synchronize()
+    tht = torch.as_tensor(th).clone().requires_grad_(True)
+    x = torch.as_tensor(xi).clone().requires_grad_(True)
+    U = oracle.forward_laplacian(oracle.unpack(tht, p.widths), x, oracle.operator_of(p).mask_vec(d)).out
+    obj = (U[:, 0] * ub).sum() + (U[:, 1:d + 1] * gb).sum() + (U[:, -1] * lb).sum()
+    rt, rx = torch.autograd.grad(obj, (tht, x))
+    assert rel(tb, rt) < tol
+    assert rel(xbar, rx) < tol
