@@ -1,0 +1,163 @@
+#!/usr/bin/env python
+"""KFAC steps/s on the 100-d Poisson problem (u* = sum sin(pi x_i)/100) with the
+100 -> 768 -> 768 -> 512 -> 512 -> 1 tanh MLP, 3000 interior + 1000 boundary
+points, on one MI355X.
+
+One step = one full KFAC iteration (Algorithm 1): forward Laplacian, residuals,
+backward pass, Kronecker factors with EMA, damped Kronecker-sum inverse,
+preconditioned direction with momentum, grid line search over 31 step sizes and
+the update.  The headline runs the mixed-precision path (BF16 MFMA, FP32
+accumulation, FP64 factors and inversion); the plain FP32 path is timed beside
+it.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
+KERNEL_CLASSES = {"layer_gemm": 0, "factor_gemm": 1, "invert": 2, "act": 3}
+
+
+def hparams():
+    from paper_2405_15603_amd import HParams
+    # the paper's only printed KFAC hyper-parameters (2d Poisson run): beta, mu;
+    # damping 1e-3; grid line search over 2^0 .. 2^-30
+    return HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
+
+
+def run_gpu(problem, precision, steps, warmup, kernel_class=None):
+    import numpy as np
+    import torch
+    from paper_2405_15603_amd import KfacPinn
+    dt = torch.float64 if precision == "f64" else torch.float32
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.as_tensor(np.asarray(a), dtype=dt, device=dev).contiguous()
+    th = T(problem.theta0())
+    xi, yi, xb, yb = (T(a) for a in problem.batch(0))
+    kp = KfacPinn.for_problem(problem, precision)
+    hp = hparams()
+    info = kp.empty(64, dtype=torch.uint8)
+    for _ in range(warmup):
+        kp.step(th, xi, yi, xb, yb, hp, info)
+    torch.cuda.synchronize()
+    if kernel_class is not None:
+        kp.timing_enable(kernel_class)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        kp.step(th, xi, yi, xb, yb, hp, info)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    tm = kp.timing_read() if kernel_class is not None else None
+    status = kp.sync()
+    last = KfacPinn.decode_info(info)
+    del kp
+    return ms, tm, status, last
+
+
+def cpu_baseline(problem, frac=0.05):
+    """The FP64 oracle's step on a bounded sample of the same workload (same
+    network, a fraction of the points), extrapolated to the full point count:
+    the per-point work scales with the number of points, the Kronecker-sum
+    inverse does not and is timed on its own."""
+    import torch
+    import oracle
+    ns = max(1, int(problem.n_interior * frac))
+    ms = max(1, int(problem.n_cond * frac))
+    xi, yi, xb, yb = problem.batch(0)
+    data = (xi[:ns], yi[:ns], xb[:ms], yb[:ms])
+    op = oracle.operator_of(problem)
+    h = hparams()
+    hp = oracle.HParams(lam=h.lam, beta=h.beta, momentum=h.momentum, lr_mode="grid")
+    st = oracle.init_state(problem.widths, True)
+    th = problem.theta0()
+    t0 = time.perf_counter()
+    _, st1, _ = oracle.kfac_step(th, problem.widths, data, op, hp, st)
+    t_sample = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for l in range(len(problem.widths) - 1):
+        oracle.kron_sum_inverse(*(oracle.damp(m[l], hp.lam)
+                                  for m in (st1.A_int, st1.B_int, st1.A_bnd, st1.B_bnd)))
+    t_inv = time.perf_counter() - t0
+    t_full = t_inv + max(t_sample - t_inv, 0.0) / frac
+    return {"value": 1.0 / t_full, "unit": "steps/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": (f"oracle step on {ns} of {problem.n_interior} interior and {ms} of "
+                       f"{problem.n_cond} boundary points with the full network "
+                       f"({t_sample:.1f} s, of which Kronecker-sum inverse {t_inv:.2f} s); "
+                       f"per-point work scaled by {1 / frac:.0f}")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--workload", default="poisson100d")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", default="layer_gemm", choices=list(KERNEL_CLASSES))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the method's data-parallel sharding "
+              "over collocation points is not built here (see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    problem = synth.PROBLEMS[args.workload]()
+    kc = KERNEL_CLASSES[args.kernel]
+    ms, tm, status, last = run_gpu(problem, args.precision, args.steps, args.warmup, kc)
+    if status != 0:
+        print(f"device status {status} after the timed steps", file=sys.stderr)
+        sys.exit(1)
+    out = {
+        "metric": "KFAC steps/s, d=100 Poisson 768-wide MLP: mixed-prec vs FP32, rel err<=1e-3",
+        "value": 1000.0 / ms,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "f32": "f32", "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{problem.name}: -Lap u = f on [0,1]^{problem.d}, "
+                               f"tanh MLP {'-'.join(map(str, problem.widths))}, "
+                               f"{problem.n_interior} interior + {problem.n_cond} boundary "
+                               f"points, grid line search (31 step sizes)",
+                   "precision": args.precision, "parallelism": "single GPU"},
+        "last_step": last,
+    }
+    if tm and tm["launches"] > 0:
+        ach = tm["flops"] / (tm["ms"] * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[args.precision]
+        out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                           "frac": ach / peak, "traffic": None,
+                           "kernel": f"{args.kernel} ({tm['launches']} launches, "
+                                     f"{tm['ms'] / tm['launches']:.3f} ms avg)",
+                           "share_of_step": tm["ms"] / (ms * args.steps)}
+    if not args.no_fp32 and args.precision != "f32":
+        ms32, _, st32, _ = run_gpu(problem, "f32", max(2, args.steps // 2), 1, None)
+        out["fp32"] = {"value": 1000.0 / ms32, "ms_per_step": ms32, "status": st32,
+                       "mixed_over_fp32": ms32 / ms}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problem)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

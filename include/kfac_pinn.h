@@ -129,7 +129,7 @@ kp_status kfac_pinn_reset_state(kfac_pinn_ctx* ctx, int32_t init_identity);
 /* Number of parameters D for the given widths (host, n_layers+1 entries). */
 int64_t kfac_pinn_num_params(const int32_t* widths, int32_t n_layers);
 
-/* ---- a1: sampling ----------------------------------------------------------
+/* ---- sampling ---------------------------------------------------------------
  * Draws one batch for training step `step` (counter offset step * count *
  * draws-per-point) into x_int (n_interior x d), y_int, x_bnd and y_bnd
  * ((n_initial + n_boundary) x d; initial points first), all "real".
@@ -140,7 +140,7 @@ int64_t kfac_pinn_num_params(const int32_t* widths, int32_t n_layers);
 kp_status kfac_pinn_sample(kfac_pinn_ctx* ctx, const kp_sampler* sampler, int64_t step,
                            void* x_int, void* y_int, void* x_bnd, void* y_bnd);
 
-/* ---- a2: forward Laplacian (Section 3.1, Eq. forward-laplacian-main) -------
+/* ---- forward Laplacian (Section 3.1, Eq. forward-laplacian-main) -----------
  * For n points x (n x d) computes the network value u (n), the gradient
  * du/dx (n x d, row-major; may be NULL) and the operator's second-order row
  * sum_{i in mask} d2u/dx_i^2 (n; may be NULL).  Keeps the layer slabs for a
@@ -159,7 +159,7 @@ kp_status kfac_pinn_forward_laplacian_vjp(kfac_pinn_ctx* ctx, const void* theta,
                                           int32_t n, const void* u_bar, const void* grad_bar,
                                           const void* lap_bar, double* theta_bar, void* x_bar);
 
-/* ---- a2-a7: curvature (Algorithm 1, steps 1-2 and 4) ------------------------
+/* ---- curvature (Algorithm 1, steps 1-2 and 4) --------------------------------
  * Forward Laplacian over the interior points, plain forward over the boundary
  * points, residuals, one backward pass per term for the output gradients g,
  * the Kronecker factors of Eq. KFAC-PINN (interior: A = sum Z~Z~^T/(N S),
@@ -173,7 +173,7 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* ctx, const void* theta,
                             const void* x_bnd, const void* y_bnd, int32_t n_bnd,
                             double beta, double* grad_out, double* loss_out);
 
-/* ---- a8: damped Kronecker-sum factorisation (Section 3.4) -------------------
+/* ---- damped Kronecker-sum factorisation (Section 3.4) ------------------------
  * For every layer and side, damps the EMA factors (+ lambda I) and computes,
  * in FP64, P and e with P^T F1 P = I and P^T F2 P = diag(e) for the pair
  * (F1, F2) = (interior, boundary) factor: a Cholesky factor of F1, then a
@@ -187,7 +187,7 @@ kp_status kfac_pinn_invert(kfac_pinn_ctx* ctx, double lambda);
  * the last kfac_pinn_invert (grad_in, delta_out: D doubles each). */
 kp_status kfac_pinn_precondition(kfac_pinn_ctx* ctx, const double* grad_in, double* delta_out);
 
-/* ---- a1-a9: one full KFAC step (Algorithm 1, one iteration) -----------------
+/* ---- one full KFAC step (Algorithm 1, one iteration) -------------------------
  * Factors and gradient at theta_inout, EMA (beta), damping and inversion
  * (lambda), Delta = -C g, momentum delta^ = mu delta_{t-1} + Delta (delta_{-1} =
  * 0), the learning rate (fixed, or argmin of L(theta + 2^k delta^) over the grid
@@ -214,6 +214,17 @@ kp_status kfac_pinn_get_line_search(kfac_pinn_ctx* ctx, double* dev_out);
 /* Momentum buffer delta_{t} (D reals) and step counter. */
 kp_status kfac_pinn_get_momentum(kfac_pinn_ctx* ctx, void* dev_out);
 kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* ctx, const void* dev_in, int64_t step);
+
+/* ---- measurement ---------------------------------------------------------
+ * While enabled, every launch of one kernel class is bracketed by HIP events on
+ * the context's stream: 0 layer products (forward and backward, line search
+ * included), 1 factor/gradient products, 2 the whole Kronecker-sum
+ * factorisation, 3 the tanh rows and their adjoint; -1 disables.
+ * kfac_pinn_timing_read waits for the stream and writes (host, 4 doubles):
+ * launches, total milliseconds, algorithmic FLOPs and algorithmic bytes of the
+ * timed launches, then resets the counters. */
+kp_status kfac_pinn_timing_enable(kfac_pinn_ctx* ctx, int32_t kernel_class);
+kp_status kfac_pinn_timing_read(kfac_pinn_ctx* ctx, double* out4);
 
 /* Waits for the context's stream; returns the device status word (and clears it). */
 kp_status kfac_pinn_sync(kfac_pinn_ctx* ctx);

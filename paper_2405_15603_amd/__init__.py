@@ -208,6 +208,14 @@ class KfacPinn:
         N.check(self.lib.kfac_pinn_set_momentum(self.h, _ptr(self._real(delta, "delta")), step),
                 "kfac_pinn_set_momentum")
 
+    def timing_enable(self, kernel_class: int) -> None:
+        N.check(self.lib.kfac_pinn_timing_enable(self.h, kernel_class), "kfac_pinn_timing_enable")
+
+    def timing_read(self) -> dict:
+        out = (C.c_double * 4)()
+        N.check(self.lib.kfac_pinn_timing_read(self.h, out), "kfac_pinn_timing_read")
+        return {"launches": int(out[0]), "ms": out[1], "flops": out[2], "bytes": out[3]}
+
     def sync(self) -> int:
         """Waits for the stream; returns (and clears) the device status word."""
         return int(self.lib.kfac_pinn_sync(self.h))

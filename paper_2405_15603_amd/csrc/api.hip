@@ -94,6 +94,12 @@ struct kfac_pinn_ctx {
   G64* kdesc = nullptr;
   int k_mmax = 0, k_nmax = 0;
   int* ctl = nullptr;                  // [0] status [1] step [4..5] alpha [8..] Jacobi flags
+  // measurement: launches of one kernel class bracketed by events
+  int tm_cls = -1;
+  std::vector<hipEvent_t> tm_ev;
+  int tm_used = 0;
+  double tm_flops = 0.0, tm_bytes = 0.0;
+  long tm_launches = 0;
 };
 
 namespace {
@@ -145,6 +151,31 @@ hipError_t alloc_slabs(kfac_pinn_ctx* c, Slabs& s) {
 
 inline char* wptr(void* base, long elems, size_t esz) { return (char*)base + elems * esz; }
 
+// kernel classes for timing
+enum { KC_LAYER_GEMM = 0, KC_FACTOR_GEMM = 1, KC_INVERT = 2, KC_ACT = 3 };
+
+int tm_begin(kfac_pinn_ctx* c, int cls) {
+  if (c->tm_cls != cls) return -1;
+  if (c->tm_used + 2 > (int)c->tm_ev.size()) {
+    for (int k = 0; k < 256; k++) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      c->tm_ev.push_back(e);
+    }
+  }
+  const int idx = c->tm_used;
+  c->tm_used += 2;
+  (void)hipEventRecord(c->tm_ev[idx], c->st);
+  return idx;
+}
+void tm_end(kfac_pinn_ctx* c, int idx, double flops, double bytes) {
+  if (idx < 0) return;
+  (void)hipEventRecord(c->tm_ev[idx + 1], c->st);
+  c->tm_flops += flops;
+  c->tm_bytes += bytes;
+  c->tm_launches += 1;
+}
+
 // Forward through layers [0, upto] for one term.  Layer inputs go to zdst(l),
 // pre-activations to pdst(l).  Returns the launch status.
 template <class ZD, class PD>
@@ -156,13 +187,19 @@ hipError_t forward_layers(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n
   for (int l = 0; l <= upto; l++) {
     const LayerDesc& ld = c->nd.l[l];
     void* lo = c->w_lo ? wptr(c->w_lo, ld.wrm, c->esz_s) : nullptr;
+    int ti = tm_begin(c, KC_LAYER_GEMM);
     if ((e = gemm_nt(c->P, zdst(l), c->ldz[l], wptr(c->w_hi, ld.wrm, c->esz_s), lo, ld.ldk_in, R,
                      ld.h_out, ld.h_in + 1, pdst(l), c->ldp[l], nullptr, s.S, c->st)) != hipSuccess)
       return e;
+    tm_end(c, ti, 2.0 * R * ld.h_out * (ld.h_in + 1),
+           (double)R * (ld.h_in + 1) * c->esz_s + (double)ld.h_out * (ld.h_in + 1) * c->esz_s +
+               (double)R * ld.h_out * c->esz_c);
     if (l < upto) {
+      ti = tm_begin(c, KC_ACT);
       if ((e = act_fwd(c->P, pdst(l), c->ldp[l], zdst(l + 1), c->ldz[l + 1], n, s.S, s.nd,
                        s.has_lap, c->mask, ld.h_out, c->st)) != hipSuccess)
         return e;
+      tm_end(c, ti, 0.0, (double)R * ld.h_out * (c->esz_c + c->esz_s));
     }
   }
   return hipSuccess;
@@ -235,13 +272,19 @@ hipError_t backward_sweep(kfac_pinn_ctx* c, Slabs& s, const void* x, int n, Laye
     if (l == 0) break;
     const LayerDesc& ld = c->nd.l[l];
     void* lo = c->w_lo ? wptr(c->w_lo, ld.wcm, c->esz_s) : nullptr;
+    int ti = tm_begin(c, KC_LAYER_GEMM);
     if ((e = gemm_nt(c->P, g, c->ldg[l], wptr(c->w_hi, ld.wcm, c->esz_s), lo, ld.ldk_out, R,
                      ld.h_in, ld.h_out, c->zbar, c->ldp_max, nullptr, s.S, c->st)) != hipSuccess)
       return e;
+    tm_end(c, ti, 2.0 * R * ld.h_in * ld.h_out,
+           (double)R * ld.h_out * c->esz_s + (double)ld.h_in * ld.h_out * c->esz_s +
+               (double)R * ld.h_in * c->esz_c);
     void* gprev = s.store ? s.g[l - 1] : s.gr[(l - 1) & 1];
+    ti = tm_begin(c, KC_ACT);
     if ((e = act_bwd(c->P, c->zbar, c->ldp_max, pre_prev, c->ldp[l - 1], gprev, c->ldg[l - 1], n,
                      s.S, s.nd, s.has_lap, c->mask, ld.h_in, c->st)) != hipSuccess)
       return e;
+    tm_end(c, ti, 0.0, (double)R * ld.h_in * (2 * c->esz_c + c->esz_s));
   }
   return hipSuccess;
 }
@@ -260,15 +303,19 @@ struct FactorGrad : LayerConsumer {
     if (want_factors) {
       const double sa = term == 0 ? 1.0 / ((double)n * S) : 1.0 / n;
       const double sbf = 1.0 / n;
+      int ti = tm_begin(c, KC_FACTOR_GEMM);
       if ((e = gemm_tn_splitk(c->P, zin, c->ldz[l], zin, c->ldz[l], ld.h_in + 1, ld.h_in + 1, K,
                               nullptr, S, true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
         return e;
+      tm_end(c, ti, (double)K * (ld.h_in + 1) * (ld.h_in + 2), (double)K * (ld.h_in + 1) * c->esz_s);
       if ((e = reduce_splitk(c->P, c->part, sp, ld.h_in + 1, ld.h_in + 1, true, c->F[term][0][l],
                              ld.h_in + 1, 1, (1.0 - beta) * sa, beta, c->st)) != hipSuccess)
         return e;
+      ti = tm_begin(c, KC_FACTOR_GEMM);
       if ((e = gemm_tn_splitk(c->P, g, c->ldg[l], g, c->ldg[l], ld.h_out, ld.h_out, K, nullptr, S,
                               true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
         return e;
+      tm_end(c, ti, (double)K * ld.h_out * (ld.h_out + 1), (double)K * ld.h_out * c->esz_s);
       if ((e = reduce_splitk(c->P, c->part, sp, ld.h_out, ld.h_out, true, c->F[term][1][l],
                              ld.h_out, 1, (1.0 - beta) * sbf, beta, c->st)) != hipSuccess)
         return e;
@@ -372,6 +419,7 @@ int64_t kfac_pinn_num_params(const int32_t* widths, int32_t n_layers) {
 kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx) {
   if (!ctx) return KP_ERR_ARG;
   for (void* p : ctx->allocs) (void)hipFree(p);
+  for (hipEvent_t e : ctx->tm_ev) (void)hipEventDestroy(e);
   delete ctx;
   return KP_OK;
 }
@@ -743,8 +791,12 @@ kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const vo
   s = factors_impl(c, theta, xi, yi, ni, xb, yb, nb, hp->beta);
   if (s != KP_OK) return s;
   // 3) preconditioner
-  KP_TRY(kron_eig_batched(c->probs.data(), (int)c->probs.size(), hp->lambda, c->probs_dev,
-                          c->ctl, nullptr, kJacobiSweeps, c->st));
+  {
+    int ti = tm_begin(c, KC_INVERT);
+    KP_TRY(kron_eig_batched(c->probs.data(), (int)c->probs.size(), hp->lambda, c->probs_dev,
+                            c->ctl, nullptr, kJacobiSweeps, c->st));
+    tm_end(c, ti, 0.0, 0.0);
+  }
   // 4) Delta = -C g, momentum
   KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
   KP_TRY(momentum(c->P, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
@@ -818,6 +870,35 @@ kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* c, const void* in, int64_t step)
   stepv = (int)step;
   KP_TRY(hipMemcpyAsync(c->ctl + 1, &stepv, sizeof(int), hipMemcpyHostToDevice, c->st));
   KP_TRY(hipStreamSynchronize(c->st));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_timing_enable(kfac_pinn_ctx* c, int32_t kernel_class) {
+  KP_ARG(c, "null context");
+  KP_ARG(kernel_class >= -1 && kernel_class <= 3, "unknown kernel class");
+  c->tm_cls = kernel_class;
+  c->tm_used = 0;
+  c->tm_flops = c->tm_bytes = 0.0;
+  c->tm_launches = 0;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_timing_read(kfac_pinn_ctx* c, double* out) {
+  KP_ARG(c && out, "null argument");
+  KP_TRY(hipStreamSynchronize(c->st));
+  double ms = 0.0;
+  for (int i = 0; i + 1 < c->tm_used; i += 2) {
+    float t = 0.f;
+    KP_TRY(hipEventElapsedTime(&t, c->tm_ev[i], c->tm_ev[i + 1]));
+    ms += t;
+  }
+  out[0] = (double)c->tm_launches;
+  out[1] = ms;
+  out[2] = c->tm_flops;
+  out[3] = c->tm_bytes;
+  c->tm_used = 0;
+  c->tm_flops = c->tm_bytes = 0.0;
+  c->tm_launches = 0;
   return KP_OK;
 }
 

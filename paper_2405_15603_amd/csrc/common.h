@@ -39,10 +39,11 @@ template <typename T> struct Acc { typedef float type; };
 template <> struct Acc<double> { typedef double type; };
 
 // ---------------------------------------------------------------------------
-// 16x16 MFMA tiles.  Output layout (all three): lane l holds rows 4*(l/16)+i,
-// i = 0..3, of column l%16.  Inputs: for FP32/FP64 (k = 4) lane l holds
-// A[l%16][l/16] and B[l/16][l%16]; for BF16 (k = 32) lane l holds the 8
-// consecutive k values 8*(l/16)..8*(l/16)+7 of row/column l%16.
+// 16x16 MFMA tiles.  Inputs: for FP32/FP64 (k = 4) lane l holds A[l%16][l/16]
+// and B[l/16][l%16]; for BF16 (k = 32) lane l holds 8 k values of row/column
+// l%16 (A and B use the same k assignment).  Output: lane l holds column l%16
+// and the 4 rows row(l, i), i = 0..3: for FP32 and BF16 the block 4*(l/16)+i,
+// for FP64 the interleaved l/16 + 4*i.
 // ---------------------------------------------------------------------------
 template <typename T> struct Mfma;
 
@@ -51,6 +52,7 @@ template <> struct Mfma<bf16> {
   static constexpr int KV = 8;      // k values per lane
   typedef bf16x8 frag;
   typedef f32x4 acc;
+  __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
   __device__ __forceinline__ static acc mma(const frag& a, const frag& b, const acc& c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -60,6 +62,7 @@ template <> struct Mfma<float> {
   static constexpr int KV = 1;
   typedef float frag;
   typedef f32x4 acc;
+  __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
   __device__ __forceinline__ static acc mma(const frag& a, const frag& b, const acc& c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -69,6 +72,7 @@ template <> struct Mfma<double> {
   static constexpr int KV = 1;
   typedef double frag;
   typedef f64x4 acc;
+  __device__ __forceinline__ static int row(int lane, int i) { return (lane >> 4) + 4 * i; }
   __device__ __forceinline__ static acc mma(const frag& a, const frag& b, const acc& c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }

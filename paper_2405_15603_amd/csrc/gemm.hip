@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const TS* __restrict__ A, long 
       if (col >= N) continue;
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const int row = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + e;
+        const int row = m0 + wm * WTM + i * 16 + MF::row(lane, e);
         if (row < M) {
           TC v = (TC)acc[i][j][e];
           if (bias != nullptr && row % S == 0) v += bias[col];
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const TS* __restrict__ A, long 
       if (col >= N) continue;
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const int row = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + e;
+        const int row = m0 + wm * WTM + i * 16 + MF::row(lane, e);
         if (row < M) out[(long)row * N + col] = (TC)acc[i][j][e];
       }
     }

@@ -1,0 +1,48 @@
+"""Mixed-precision path (BF16 MFMA, FP32 accumulation, FP64 factors) against the
+FP64 oracle.  The binding tolerance is 1e-3 relative (Frobenius) per Kronecker
+factor; the Laplacian, gradient and direction are reported with looser bounds
+derived from BF16's unit roundoff 2^-9 ~ 2e-3 per rounded operand."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import oracle_curvature, problem_inputs, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def kp_for(p, precision, **kw):
+    from paper_2405_15603_amd import KfacPinn
+    return KfacPinn.for_problem(p, precision, **kw)
+
+
+@pytest.mark.parametrize("case", ["poisson100d_subset", "heat_subset", "tiny"])
+def test_mixed_factors_within_1e_3(case):
+    if case == "poisson100d_subset":
+        p = synth.poisson100d(); ni, nb = 240, 80
+    elif case == "heat_subset":
+        p = synth.heat4d(); ni, nb = 800, 300
+    else:
+        p = synth.small_problem("poisson", (3, 16, 12, 1), 37, 11, problem_id=71); ni, nb = None, None
+    th, xi, yi, xb, yb = problem_inputs(p, "bf16", ni, nb)
+    kp = kp_for(p, "bf16", max_interior=xi.shape[0], max_boundary=xb.shape[0])
+    grad, loss = kp.factors(*(to_dev(a, "bf16") for a in (th, xi, yi, xb, yb)), beta=0.0)
+    u, g, lap = kp.forward_laplacian(to_dev(th, "bf16"), to_dev(xi, "bf16"))
+    assert kp.sync() == 0
+    ref = oracle_curvature(p, th, xi, yi, xb, yb)
+    worst = 0.0
+    for l in range(len(p.widths) - 1):
+        for t, tn in ((0, "int"), (1, "bnd")):
+            for s, sn in ((0, "A"), (1, "B")):
+                e = rel(kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l])
+                worst = max(worst, e)
+                assert e < 1e-3, (l, tn, sn, e)
+    op = oracle.operator_of(p)
+    U = oracle.forward_laplacian(oracle.unpack(torch.as_tensor(th), p.widths), torch.as_tensor(xi),
+                                 op.mask_vec(p.d)).out
+    print(f"{case}: worst factor {worst:.2e}  lap {rel(lap, U[:, -1]):.2e}  "
+          f"grad {rel(grad, ref['grad']):.2e}")
+    assert rel(lap, U[:, -1]) < 2e-2
+    assert rel(grad, ref["grad"]) < 2e-2
