@@ -6,10 +6,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
 #include "common.h"
+#include "fwdlap.h"
 #include "kfac_pinn.h"
 #include "launch.h"
 
@@ -42,16 +44,24 @@ namespace {
 constexpr int kMaxLayers = 8;
 constexpr int kMaxCand = 64;
 constexpr int kMaxSplits = 64;
-constexpr int kJacobiSweeps = 15;
+constexpr int kMaxChunks = 16;
+constexpr int kJacobiSweeps = 20;
 
-struct Slabs {            // one term (interior or boundary)
+struct Slabs {            // one term (interior or boundary); rows are s-major (s*N + p)
   int S = 1, nd = 0, has_lap = 0, cap = 0;   // rows per point, derivative rows, capacity (points)
-  std::vector<void*> zin, pre, g;            // stored mode: per layer
-  void* zr[2] = {nullptr, nullptr};          // recompute mode: layer inputs (ping-pong)
-  void* prer = nullptr;                      // recompute mode: one pre-activation slab
-  void* gr[2] = {nullptr, nullptr};          // recompute mode: output gradients (ping-pong)
   bool store = true;
+  std::vector<void*> zin;                    // stored: layer inputs Z~^(l) (l = 0..L-1)
+  std::vector<void*> pre;                    // stored: hidden pre-activations (l = 0..L-2)
+  std::vector<void*> g;                      // stored: output gradients (l = 0..L-1)
+  void* zr[2] = {nullptr, nullptr};          // recompute: layer inputs (ping-pong)
+  void* prer = nullptr;                      // recompute: one hidden pre-activation slab
+  void* gr[2] = {nullptr, nullptr};          // recompute: output gradients (ping-pong)
+  std::vector<void*> sq;                     // per hidden layer: N x h sum of squares
+  void* u = nullptr;                         // network output rows (compute type, R)
   double* r = nullptr;                       // residual per point
+  void* zin_at(int l) const { return store ? zin[l] : zr[l & 1]; }
+  void* g_at(int l) const { return store ? g[l] : gr[l & 1]; }
+  void* pre_at(int l) const { return store ? pre[l] : prer; }
 };
 
 }  // namespace
@@ -61,24 +71,31 @@ struct kfac_pinn_ctx {
   std::vector<int> w;
   int time_coord = -1;
   double c_t = 0.0, c_lap = -1.0;
-  Prec P = P_F32;
-  size_t esz_p = 4, esz_s = 4, esz_c = 4;
+  int precision = KP_F32;
+  Prec pp = P_F32;          // parameters and points
+  Prec sp = P_F32;          // curvature slabs
+  Prec lp = P_F32;          // line-search slabs
+  Prec wp = P_F32;          // product-layout weights
+  int cmode = M_F32;        // curvature products
+  int lmode = M_F32;        // line-search products
+  size_t esz_p = 4, esz_s = 4, esz_l = 4, esz_c = 4, esz_w = 4;
   int max_i = 0, max_b = 0;
   size_t ws_limit = 0;
   hipStream_t st = nullptr;
   long D = 0;
   NetDesc nd{};
   std::vector<long> off, ldz, ldp, ldg;
-  int hmax = 0;
   long ldz_max = 0, ldp_max = 0;
 
   std::vector<void*> allocs;
   uint8_t* mask = nullptr;
   void *w_hi = nullptr, *w_lo = nullptr;
+  void* theta_trial = nullptr;
   Slabs si, sb;
-  void* zbar = nullptr;
+  void* tab = nullptr;                 // finishing-pass tables (compute type)
+  long tab_stride = 0;                 // elements per table plane (max N * h)
   void* ls_z[2] = {nullptr, nullptr};
-  void* ls_pre = nullptr;
+  void* ls_u = nullptr;
   double* partial = nullptr;
   int partial_n = 0;
   double* loss = nullptr;              // [0] L_int [1] L_bnd [2..] candidates
@@ -116,40 +133,49 @@ hipError_t dmalloc(kfac_pinn_ctx* c, void** p, size_t bytes) {
 
 size_t slab_bytes(const kfac_pinn_ctx* c, const Slabs& s, bool store) {
   const size_t R = (size_t)s.cap * s.S;
-  size_t b = 0;
+  size_t b = R * c->esz_c;   // output rows
   if (store) {
-    for (int l = 0; l < c->L; l++)
-      b += R * (c->ldz[l] * c->esz_s + c->ldp[l] * c->esz_c + c->ldg[l] * c->esz_s);
+    for (int l = 0; l < c->L; l++) {
+      b += R * (c->ldz[l] + c->ldg[l]) * c->esz_s;
+      if (l + 1 < c->L) b += R * c->ldp[l] * c->esz_c;
+    }
   } else {
-    b = R * (2 * c->ldz_max * c->esz_s + c->ldp_max * c->esz_c + 2 * c->ldp_max * c->esz_s);
+    b += R * (2 * c->ldz_max * c->esz_s + c->ldp_max * c->esz_c + 2 * c->ldp_max * c->esz_s);
   }
   return b;
 }
 
 hipError_t alloc_slabs(kfac_pinn_ctx* c, Slabs& s) {
   const size_t R = (size_t)s.cap * s.S;
+  hipError_t e;
   if (s.store) {
-    s.zin.resize(c->L);
-    s.pre.resize(c->L);
-    s.g.resize(c->L);
+    s.zin.assign(c->L, nullptr);
+    s.pre.assign(c->L, nullptr);
+    s.g.assign(c->L, nullptr);
     for (int l = 0; l < c->L; l++) {
-      hipError_t e;
       if ((e = dmalloc(c, &s.zin[l], R * c->ldz[l] * c->esz_s)) != hipSuccess) return e;
-      if ((e = dmalloc(c, &s.pre[l], R * c->ldp[l] * c->esz_c)) != hipSuccess) return e;
       if ((e = dmalloc(c, &s.g[l], R * c->ldg[l] * c->esz_s)) != hipSuccess) return e;
+      if (l + 1 < c->L &&
+          (e = dmalloc(c, &s.pre[l], R * c->ldp[l] * c->esz_c)) != hipSuccess)
+        return e;
     }
   } else {
-    hipError_t e;
     for (int k = 0; k < 2; k++) {
       if ((e = dmalloc(c, &s.zr[k], R * c->ldz_max * c->esz_s)) != hipSuccess) return e;
       if ((e = dmalloc(c, &s.gr[k], R * c->ldp_max * c->esz_s)) != hipSuccess) return e;
     }
     if ((e = dmalloc(c, &s.prer, R * c->ldp_max * c->esz_c)) != hipSuccess) return e;
   }
+  s.sq.assign(c->L, nullptr);
+  if (s.has_lap)
+    for (int l = 0; l + 1 < c->L; l++)
+      if ((e = dmalloc(c, &s.sq[l], (size_t)s.cap * c->w[l + 1] * c->esz_c)) != hipSuccess)
+        return e;
+  if ((e = dmalloc(c, &s.u, R * c->esz_c)) != hipSuccess) return e;
   return dmalloc(c, (void**)&s.r, sizeof(double) * (s.cap > 0 ? s.cap : 1));
 }
 
-inline char* wptr(void* base, long elems, size_t esz) { return (char*)base + elems * esz; }
+inline char* wptr(const void* base, long elems, size_t esz) { return (char*)base + elems * esz; }
 
 // kernel classes for timing
 enum { KC_LAYER_GEMM = 0, KC_FACTOR_GEMM = 1, KC_INVERT = 2, KC_ACT = 3 };
@@ -176,57 +202,103 @@ void tm_end(kfac_pinn_ctx* c, int idx, double flops, double bytes) {
   c->tm_launches += 1;
 }
 
-// Forward through layers [0, upto] for one term.  Layer inputs go to zdst(l),
-// pre-activations to pdst(l).  Returns the launch status.
-template <class ZD, class PD>
-hipError_t forward_layers(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, int upto,
-                          ZD zdst, PD pdst) {
-  hipError_t e;
-  const int R = n * s.S;
-  if ((e = input_slab(c->P, x, n, c->d, s.S, zdst(0), c->ldz[0], c->st)) != hipSuccess) return e;
-  for (int l = 0; l <= upto; l++) {
-    const LayerDesc& ld = c->nd.l[l];
-    void* lo = c->w_lo ? wptr(c->w_lo, ld.wrm, c->esz_s) : nullptr;
-    int ti = tm_begin(c, KC_LAYER_GEMM);
-    if ((e = gemm_nt(c->P, zdst(l), c->ldz[l], wptr(c->w_hi, ld.wrm, c->esz_s), lo, ld.ldk_in, R,
-                     ld.h_out, ld.h_in + 1, pdst(l), c->ldp[l], nullptr, s.S, c->st)) != hipSuccess)
-      return e;
-    tm_end(c, ti, 2.0 * R * ld.h_out * (ld.h_in + 1),
-           (double)R * (ld.h_in + 1) * c->esz_s + (double)ld.h_out * (ld.h_in + 1) * c->esz_s +
-               (double)R * ld.h_out * c->esz_c);
-    if (l < upto) {
-      ti = tm_begin(c, KC_ACT);
-      if ((e = act_fwd(c->P, pdst(l), c->ldp[l], zdst(l + 1), c->ldz[l + 1], n, s.S, s.nd,
-                       s.has_lap, c->mask, ld.h_out, c->st)) != hipSuccess)
-        return e;
-      tm_end(c, ti, 0.0, (double)R * ld.h_out * (c->esz_c + c->esz_s));
-    }
-  }
-  return hipSuccess;
-}
-
 int lap_row_of(const Slabs& s) { return s.has_lap ? s.S - 1 : -1; }
 int time_row_of(const kfac_pinn_ctx* c, const Slabs& s) {
   return (s.has_lap && c->time_coord >= 0 && c->c_t != 0.0) ? 1 + c->time_coord : -1;
 }
 
-// Full forward for the curvature pass (stores what the backward sweep needs).
-hipError_t forward_store(kfac_pinn_ctx* c, Slabs& s, const void* x, int n) {
-  if (s.store)
-    return forward_layers(c, s, x, n, c->L - 1, [&](int l) { return s.zin[l]; },
-                          [&](int l) { return s.pre[l]; });
-  // recompute mode: only the output layer's pre-activations are kept (in prer)
-  return forward_layers(c, s, x, n, c->L - 1, [&](int l) { return s.zr[l & 1]; },
-                        [&](int l) { return s.prer; });
+// Where one forward pass reads its weights and writes its slabs.
+struct FwdTarget {
+  int mode;
+  Prec zp;                      // slab storage
+  size_t zesz;
+  const void* theta;            // parameters (last layer read directly)
+  std::function<void*(int)> z;  // layer-input slab of layer l
+  std::function<void*(int)> pre;   // hidden pre-activations of layer l (or nullptr)
+  std::function<void*(int)> sq;    // sum of squares table of layer l (or nullptr)
+  void* u;                      // output rows
+};
+
+// Forward through hidden layers [0, upto) and, when upto == L, the output layer.
+hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, int upto,
+                       const FwdTarget& T) {
+  hipError_t e;
+  const long R = (long)n * s.S;
+  if ((e = input_slab(T.zp, x, n, c->d, s.S, T.z(0), c->ldz[0], c->st)) != hipSuccess) return e;
+  const int nh = upto < c->L ? upto : c->L - 1;
+  for (int l = 0; l < nh; l++) {
+    const LayerDesc& ld = c->nd.l[l];
+    FwdLayerArgs a{};
+    a.zin = T.z(l);
+    a.ldz = c->ldz[l];
+    a.w = wptr(c->w_hi, ld.wrm, c->esz_w);
+    a.w2 = (T.mode == M_BF16X3) ? wptr(c->w_lo, ld.wrm, c->esz_w) : nullptr;
+    a.ldw = ld.ldk_in;
+    a.K = (int)ld.ldk_in;
+    a.N = n;
+    a.S = s.S;
+    a.nd = s.nd;
+    a.has_lap = s.has_lap;
+    a.h_out = ld.h_out;
+    a.mask = c->mask;
+    a.z = T.z(l + 1);
+    a.ldzo = c->ldz[l + 1];
+    a.pre = T.pre(l);
+    a.ldp = c->ldp[l];
+    const long ts = c->tab_stride;
+    a.tab_t = s.has_lap ? c->tab : nullptr;
+    a.tab_lap = s.has_lap ? wptr(c->tab, ts, c->esz_c) : nullptr;
+    a.tab_sq = s.has_lap ? wptr(c->tab, 2 * ts, c->esz_c) : nullptr;
+    a.sq_out = T.sq(l);
+    const int nch = fwdlap_chunks(T.mode, n, ld.h_out, s.nd, s.has_lap);
+    int ti = tm_begin(c, KC_LAYER_GEMM);
+    if ((e = fwdlap_main(T.mode, a, nch, c->st)) != hipSuccess) return e;
+    tm_end(c, ti, 2.0 * R * ld.h_out * (ld.h_in + 1),
+           (double)R * (ld.h_in + 1 + ld.h_out) * T.zesz + (double)ld.h_out * (ld.h_in + 1) * c->esz_w);
+    ti = tm_begin(c, KC_ACT);
+    if ((e = fwdlap_finish(T.mode, a, nch, c->st)) != hipSuccess) return e;
+    tm_end(c, ti, 0.0, 0.0);
+  }
+  if (upto >= c->L) {
+    const LayerDesc& ld = c->nd.l[c->L - 1];
+    if ((e = last_fwd(T.mode, T.z(c->L - 1), c->ldz[c->L - 1],
+                      wptr(T.theta, ld.off, c->esz_p), ld.h_in + 1, R, T.u, c->st)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
 }
 
-// residual, loss[slot] and the seed rows of the last layer
-hipError_t residual_and_seed(kfac_pinn_ctx* c, Slabs& s, const void* pre_last, const void* y,
-                             int n, void* g_last, int slot, int accumulate) {
+FwdTarget curvature_target(kfac_pinn_ctx* c, Slabs& s, const void* theta) {
+  FwdTarget T;
+  T.mode = c->cmode;
+  T.zp = c->sp;
+  T.zesz = c->esz_s;
+  T.theta = theta;
+  Slabs* sp = &s;
+  T.z = [sp](int l) { return sp->zin_at(l); };
+  T.pre = [sp](int l) { return sp->pre_at(l); };
+  T.sq = [sp](int l) { return sp->sq[l]; };
+  T.u = s.u;
+  return T;
+}
+
+// residual, loss[slot] and the seed rows of the output layer
+hipError_t residual_and_seed(kfac_pinn_ctx* c, Slabs& s, const void* u, const void* y, int n,
+                             void* g_last, int slot, int accumulate) {
   hipError_t e;
   const int nb = residual_blocks(n);
-  if ((e = residual(c->P, pre_last, c->ldp[c->L - 1], y, n, s.S, time_row_of(c, s), c->c_t,
-                    c->c_lap, lap_row_of(s), s.r, g_last, c->ldg[c->L - 1], c->partial, c->st)) !=
+  if ((e = residual(c->sp, u, 1, y, n, s.S, time_row_of(c, s), c->c_t, c->c_lap, lap_row_of(s),
+                    s.r, g_last, c->ldg[c->L - 1], c->partial, c->st)) != hipSuccess)
+    return e;
+  return finalize_loss(c->partial, nb, 0.5 / (double)n, c->loss, slot, accumulate, c->st);
+}
+
+hipError_t residual_loss_only(kfac_pinn_ctx* c, Slabs& s, const void* u, const void* y, int n,
+                              int slot, int accumulate) {
+  hipError_t e;
+  const int nb = residual_blocks(n);
+  if ((e = residual(c->sp == P_F64 ? P_F64 : P_F32, u, 1, y, n, s.S, time_row_of(c, s), c->c_t,
+                    c->c_lap, lap_row_of(s), nullptr, nullptr, 1, c->partial, c->st)) !=
       hipSuccess)
     return e;
   return finalize_loss(c->partial, nb, 0.5 / (double)n, c->loss, slot, accumulate, c->st);
@@ -237,54 +309,59 @@ struct LayerConsumer {
   virtual hipError_t operator()(int l, const void* zin, const void* g) = 0;
 };
 
-// Backward sweep from the last layer's seed (already in g(L-1)).  For each
-// layer l (last to first) hands (Z~^(l), g^(l)) to `use`, then forms
-// g^(l-1) = tanh-adjoint(W^T g^(l)).  Recompute mode re-runs the forward up to
-// layer l-1 from x whenever layer inputs are needed.
-hipError_t backward_sweep(kfac_pinn_ctx* c, Slabs& s, const void* x, int n, LayerConsumer& use) {
+// Backward sweep from the output seeds (already in g(L-1)).  For each layer l
+// (last to first) hands (Z~^(l), g^(l)) to `use`, then forms g^(l-1) by the
+// adjoint of the tanh rows at layer l-1.  In recompute mode the forward is
+// re-run from x up to layer l whenever layer l's input is needed.
+hipError_t backward_sweep(kfac_pinn_ctx* c, Slabs& s, const void* theta, const void* x, int n,
+                          LayerConsumer& use) {
   hipError_t e;
-  const int R = n * s.S;
+  const long R = (long)n * s.S;
+  FwdTarget T = curvature_target(c, s, theta);
   for (int l = c->L - 1; l >= 0; l--) {
-    const void* zin;
-    const void* g = s.store ? s.g[l] : s.gr[l & 1];
-    const void* pre_prev = nullptr;
-    if (s.store) {
-      zin = s.zin[l];
-      pre_prev = l > 0 ? s.pre[l - 1] : nullptr;
-    } else {
-      // recompute layers 0..l-1: Z~^(l) = act(pre^(l-1)), pre^(l-1) kept in prer
-      if (l == 0) {
-        if ((e = input_slab(c->P, x, n, c->d, s.S, s.zr[0], c->ldz[0], c->st)) != hipSuccess)
-          return e;
-        zin = s.zr[0];
-      } else {
-        if ((e = forward_layers(c, s, x, n, l - 1, [&](int k) { return s.zr[k & 1]; },
-                                [&](int k) { return s.prer; })) != hipSuccess)
-          return e;
-        if ((e = act_fwd(c->P, s.prer, c->ldp[l - 1], s.zr[l & 1], c->ldz[l], n, s.S, s.nd,
-                         s.has_lap, c->mask, c->nd.l[l - 1].h_out, c->st)) != hipSuccess)
-          return e;
-        zin = s.zr[l & 1];
-        pre_prev = s.prer;
-      }
+    if (!s.store && l < c->L - 1) {
+      // layer inputs of l (and pre-activations of l-1) from x
+      if ((e = forward_run(c, s, x, n, l, T)) != hipSuccess) return e;
     }
-    if ((e = use(l, zin, g)) != hipSuccess) return e;
+    if ((e = use(l, s.zin_at(l), s.g_at(l))) != hipSuccess) return e;
     if (l == 0) break;
     const LayerDesc& ld = c->nd.l[l];
-    void* lo = c->w_lo ? wptr(c->w_lo, ld.wcm, c->esz_s) : nullptr;
+    BwdLayerArgs a{};
+    a.N = n;
+    a.S = s.S;
+    a.nd = s.nd;
+    a.has_lap = s.has_lap;
+    a.h = ld.h_in;
+    a.mask = c->mask;
+    a.pre = s.pre_at(l - 1);
+    a.ldp = c->ldp[l - 1];
+    a.sq = s.sq[l - 1];
+    a.g = s.g_at(l - 1);
+    a.ldgo = c->ldg[l - 1];
+    if (l == c->L - 1) {
+      if ((e = bwd_last(c->cmode, a, s.g_at(l), c->ldg[l], wptr(theta, ld.off, c->esz_p),
+                        c->st)) != hipSuccess)
+        return e;
+      continue;
+    }
+    a.gin = s.g_at(l);
+    a.ldgi = c->ldg[l];
+    a.w = wptr(c->w_hi, ld.wcm, c->esz_w);
+    a.w2 = c->cmode == M_BF16X3 ? wptr(c->w_lo, ld.wcm, c->esz_w) : nullptr;
+    a.ldw = ld.ldk_out;
+    a.K = (int)ld.ldk_out;
+    const long ts = c->tab_stride;
+    a.tab_lb = c->tab;
+    a.tab_zv = wptr(c->tab, ts, c->esz_c);
+    a.tab_s1 = wptr(c->tab, 2 * ts, c->esz_c);
+    const int nch = bwdlap_chunks(c->cmode, n, ld.h_in, s.nd, s.has_lap);
     int ti = tm_begin(c, KC_LAYER_GEMM);
-    if ((e = gemm_nt(c->P, g, c->ldg[l], wptr(c->w_hi, ld.wcm, c->esz_s), lo, ld.ldk_out, R,
-                     ld.h_in, ld.h_out, c->zbar, c->ldp_max, nullptr, s.S, c->st)) != hipSuccess)
-      return e;
+    if ((e = bwdlap_main(c->cmode, a, nch, c->st)) != hipSuccess) return e;
     tm_end(c, ti, 2.0 * R * ld.h_in * ld.h_out,
-           (double)R * ld.h_out * c->esz_s + (double)ld.h_in * ld.h_out * c->esz_s +
-               (double)R * ld.h_in * c->esz_c);
-    void* gprev = s.store ? s.g[l - 1] : s.gr[(l - 1) & 1];
+           (double)R * (ld.h_in + ld.h_out) * c->esz_s + (double)R * ld.h_in * c->esz_c);
     ti = tm_begin(c, KC_ACT);
-    if ((e = act_bwd(c->P, c->zbar, c->ldp_max, pre_prev, c->ldp[l - 1], gprev, c->ldg[l - 1], n,
-                     s.S, s.nd, s.has_lap, c->mask, ld.h_in, c->st)) != hipSuccess)
-      return e;
-    tm_end(c, ti, 0.0, (double)R * ld.h_in * (2 * c->esz_c + c->esz_s));
+    if ((e = bwdlap_finish(c->cmode, a, nch, c->st)) != hipSuccess) return e;
+    tm_end(c, ti, 0.0, 0.0);
   }
   return hipSuccess;
 }
@@ -294,38 +371,36 @@ struct FactorGrad : LayerConsumer {
   kfac_pinn_ctx* c;
   int term, n, S;
   double beta;
-  bool want_factors;
   hipError_t operator()(int l, const void* zin, const void* g) override {
     hipError_t e;
     const LayerDesc& ld = c->nd.l[l];
     const int K = n * S;
+    const int m = c->cmode;
     int sp = 1;
-    if (want_factors) {
-      const double sa = term == 0 ? 1.0 / ((double)n * S) : 1.0 / n;
-      const double sbf = 1.0 / n;
-      int ti = tm_begin(c, KC_FACTOR_GEMM);
-      if ((e = gemm_tn_splitk(c->P, zin, c->ldz[l], zin, c->ldz[l], ld.h_in + 1, ld.h_in + 1, K,
-                              nullptr, S, true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
-        return e;
-      tm_end(c, ti, (double)K * (ld.h_in + 1) * (ld.h_in + 2), (double)K * (ld.h_in + 1) * c->esz_s);
-      if ((e = reduce_splitk(c->P, c->part, sp, ld.h_in + 1, ld.h_in + 1, true, c->F[term][0][l],
-                             ld.h_in + 1, 1, (1.0 - beta) * sa, beta, c->st)) != hipSuccess)
-        return e;
-      ti = tm_begin(c, KC_FACTOR_GEMM);
-      if ((e = gemm_tn_splitk(c->P, g, c->ldg[l], g, c->ldg[l], ld.h_out, ld.h_out, K, nullptr, S,
-                              true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
-        return e;
-      tm_end(c, ti, (double)K * ld.h_out * (ld.h_out + 1), (double)K * ld.h_out * c->esz_s);
-      if ((e = reduce_splitk(c->P, c->part, sp, ld.h_out, ld.h_out, true, c->F[term][1][l],
-                             ld.h_out, 1, (1.0 - beta) * sbf, beta, c->st)) != hipSuccess)
-        return e;
-    }
+    const double sa = term == 0 ? 1.0 / ((double)n * S) : 1.0 / n;
+    const double sbf = 1.0 / n;
+    int ti = tm_begin(c, KC_FACTOR_GEMM);
+    if ((e = gemm_tn_splitk(m, zin, c->ldz[l], zin, c->ldz[l], ld.h_in + 1, ld.h_in + 1, K,
+                            nullptr, n, true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+      return e;
+    tm_end(c, ti, (double)K * (ld.h_in + 1) * (ld.h_in + 2), (double)K * (ld.h_in + 1) * c->esz_s);
+    if ((e = reduce_splitk(m, c->part, sp, ld.h_in + 1, ld.h_in + 1, true, c->F[term][0][l],
+                           ld.h_in + 1, 1, (1.0 - beta) * sa, beta, c->st)) != hipSuccess)
+      return e;
+    ti = tm_begin(c, KC_FACTOR_GEMM);
+    if ((e = gemm_tn_splitk(m, g, c->ldg[l], g, c->ldg[l], ld.h_out, ld.h_out, K, nullptr, n,
+                            true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+      return e;
+    tm_end(c, ti, (double)K * ld.h_out * (ld.h_out + 1), (double)K * ld.h_out * c->esz_s);
+    if ((e = reduce_splitk(m, c->part, sp, ld.h_out, ld.h_out, true, c->F[term][1][l], ld.h_out,
+                           1, (1.0 - beta) * sbf, beta, c->st)) != hipSuccess)
+      return e;
     // gradient: sum_rows (r_n / n) g (x) z~, column-major into theta
     const Slabs& s = term == 0 ? c->si : c->sb;
-    if ((e = gemm_tn_splitk(c->P, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1, K, s.r, S,
+    if ((e = gemm_tn_splitk(m, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1, K, s.r, n,
                             false, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
       return e;
-    return reduce_splitk(c->P, c->part, sp, ld.h_out, ld.h_in + 1, false, c->grad + ld.off, 1,
+    return reduce_splitk(m, c->part, sp, ld.h_out, ld.h_in + 1, false, c->grad + ld.off, 1,
                          ld.h_out, 1.0 / n, term == 0 ? 0.0 : 1.0, c->st);
   }
 };
@@ -338,53 +413,54 @@ struct ThetaBar : LayerConsumer {
   hipError_t operator()(int l, const void* zin, const void* g) override {
     const LayerDesc& ld = c->nd.l[l];
     int sp = 1;
-    hipError_t e = gemm_tn_splitk(c->P, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1,
-                                  n * S, nullptr, S, false, c->part, kMaxSplits, &sp, c->st);
+    hipError_t e = gemm_tn_splitk(c->cmode, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1,
+                                  n * S, nullptr, n, false, c->part, kMaxSplits, &sp, c->st);
     if (e != hipSuccess) return e;
-    return reduce_splitk(c->P, c->part, sp, ld.h_out, ld.h_in + 1, false, out + ld.off, 1,
+    return reduce_splitk(c->cmode, c->part, sp, ld.h_out, ld.h_in + 1, false, out + ld.off, 1,
                          ld.h_out, 1.0, 0.0, c->st);
   }
 };
 
-hipError_t curvature_term(kfac_pinn_ctx* c, int term, const void* x, const void* y, int n,
-                          double beta, bool want_factors) {
+hipError_t prep(kfac_pinn_ctx* c, const void* theta) {
+  return prep_weights(c->wp, theta, nullptr, 0.0, c->nd, c->w_hi, c->w_lo, nullptr, 0, c->st);
+}
+
+hipError_t curvature_term(kfac_pinn_ctx* c, int term, const void* theta, const void* x,
+                          const void* y, int n, double beta) {
   Slabs& s = term == 0 ? c->si : c->sb;
   hipError_t e;
   if (n <= 0) return hipSuccess;
-  if ((e = forward_store(c, s, x, n)) != hipSuccess) return e;
-  const void* pre_last = s.store ? s.pre[c->L - 1] : s.prer;
-  void* g_last = s.store ? s.g[c->L - 1] : s.gr[(c->L - 1) & 1];
-  if ((e = residual_and_seed(c, s, pre_last, y, n, g_last, term, 0)) != hipSuccess) return e;
+  if ((e = forward_run(c, s, x, n, c->L, curvature_target(c, s, theta))) != hipSuccess) return e;
+  if ((e = residual_and_seed(c, s, s.u, y, n, s.g_at(c->L - 1), term, 0)) != hipSuccess) return e;
   FactorGrad fg;
-  fg.c = c; fg.term = term; fg.n = n; fg.S = s.S; fg.beta = beta; fg.want_factors = want_factors;
-  return backward_sweep(c, s, x, n, fg);
+  fg.c = c; fg.term = term; fg.n = n; fg.S = s.S; fg.beta = beta;
+  return backward_sweep(c, s, theta, x, n, fg);
 }
 
-// total loss of (theta + alpha * dir) into loss[slot]; forward only
+// total loss at the parameters in theta_trial (line-search precision) into loss[slot]
 hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, const void* xb,
                      const void* yb, int nb, int slot) {
   hipError_t e;
+  FwdTarget T;
+  T.mode = c->lmode;
+  T.zp = c->lp;
+  T.zesz = c->esz_l;
+  T.theta = c->theta_trial;
+  T.z = [c](int l) { return c->ls_z[l & 1]; };
+  T.pre = [](int) -> void* { return nullptr; };
+  T.sq = [](int) -> void* { return nullptr; };
+  T.u = c->ls_u;
   int acc = 0;
   if (ni > 0) {
-    if ((e = forward_layers(c, c->si, xi, ni, c->L - 1, [&](int l) { return c->ls_z[l & 1]; },
-                            [&](int l) { return c->ls_pre; })) != hipSuccess)
-      return e;
-    if ((e = residual_and_seed(c, c->si, c->ls_pre, yi, ni, nullptr, slot, 0)) != hipSuccess)
-      return e;
+    if ((e = forward_run(c, c->si, xi, ni, c->L, T)) != hipSuccess) return e;
+    if ((e = residual_loss_only(c, c->si, c->ls_u, yi, ni, slot, 0)) != hipSuccess) return e;
     acc = 1;
   }
   if (nb > 0) {
-    if ((e = forward_layers(c, c->sb, xb, nb, c->L - 1, [&](int l) { return c->ls_z[l & 1]; },
-                            [&](int l) { return c->ls_pre; })) != hipSuccess)
-      return e;
-    if ((e = residual_and_seed(c, c->sb, c->ls_pre, yb, nb, nullptr, slot, acc)) != hipSuccess)
-      return e;
+    if ((e = forward_run(c, c->sb, xb, nb, c->L, T)) != hipSuccess) return e;
+    if ((e = residual_loss_only(c, c->sb, c->ls_u, yb, nb, slot, acc)) != hipSuccess) return e;
   }
   return hipSuccess;
-}
-
-hipError_t prep(kfac_pinn_ctx* c, const void* theta, const void* dir, double alpha) {
-  return prep_weights(c->P, theta, dir, alpha, c->nd, c->w_hi, c->w_lo, nullptr, 0, c->st);
 }
 
 }  // namespace
@@ -444,10 +520,23 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   c->time_coord = pb->time_coord;
   c->c_t = pb->coef_time;
   c->c_lap = pb->coef_lap;
-  c->P = (Prec)pb->precision;
-  c->esz_p = c->P == P_F64 ? 8 : 4;
-  c->esz_s = c->P == P_F64 ? 8 : (c->P == P_F32 ? 4 : 2);
-  c->esz_c = c->P == P_F64 ? 8 : 4;
+  c->precision = pb->precision;
+  if (pb->precision == KP_F64) {
+    c->pp = c->sp = c->lp = c->wp = P_F64;
+    c->cmode = c->lmode = M_F64;
+    c->esz_p = c->esz_s = c->esz_l = c->esz_c = c->esz_w = 8;
+  } else if (pb->precision == KP_F32) {
+    c->pp = c->sp = c->lp = c->wp = P_F32;
+    c->cmode = c->lmode = M_F32;
+    c->esz_p = c->esz_s = c->esz_l = c->esz_c = c->esz_w = 4;
+  } else {   // mixed: FP32 slabs with BF16x3 products for the curvature pass, BF16 line search
+    c->pp = c->sp = P_F32;
+    c->lp = c->wp = P_BF16;
+    c->cmode = M_BF16X3;
+    c->lmode = M_BF16;
+    c->esz_p = c->esz_s = c->esz_c = 4;
+    c->esz_l = c->esz_w = 2;
+  }
   c->max_i = pb->max_interior;
   c->max_b = pb->max_boundary;
   c->ws_limit = pb->workspace_limit_bytes;
@@ -474,7 +563,6 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     c->ldp.push_back(kp_roundup(ho, 8));
     c->ldg.push_back(ld.ldk_out);
     toff += (long)ho * (hi + 1);
-    c->hmax = std::max(c->hmax, std::max(hi, ho));
     c->ldz_max = std::max(c->ldz_max, (long)ld.ldk_in);
     c->ldp_max = std::max(c->ldp_max, kp_roundup(std::max(hi, ho), 8));
   }
@@ -507,18 +595,24 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
       return KP_ERR_HIP;
     }
   }
-  ALLOC(c->w_hi, (size_t)woff * c->esz_s);
-  if (c->P == P_BF16) ALLOC(c->w_lo, (size_t)woff * c->esz_s);
+  ALLOC(c->w_hi, (size_t)woff * c->esz_w);
+  if (c->wp == P_BF16) ALLOC(c->w_lo, (size_t)woff * c->esz_w);
+  ALLOC(c->theta_trial, (size_t)c->D * c->esz_p);
   if ((e = alloc_slabs(c, c->si)) != hipSuccess || (e = alloc_slabs(c, c->sb)) != hipSuccess) {
     kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
     kfac_pinn_destroy(c);
     return e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_HIP;
   }
   const size_t Rmax = std::max((size_t)c->max_i * c->si.S, (size_t)c->max_b);
-  ALLOC(c->zbar, Rmax * c->ldp_max * c->esz_c);
-  ALLOC(c->ls_z[0], Rmax * c->ldz_max * c->esz_s);
-  ALLOC(c->ls_z[1], Rmax * c->ldz_max * c->esz_s);
-  ALLOC(c->ls_pre, Rmax * c->ldp_max * c->esz_c);
+  ALLOC(c->ls_z[0], Rmax * c->ldz_max * c->esz_l);
+  ALLOC(c->ls_z[1], Rmax * c->ldz_max * c->esz_l);
+  ALLOC(c->ls_u, Rmax * c->esz_c);
+  {
+    int hmax = 1;
+    for (int l = 1; l < c->L; l++) hmax = std::max(hmax, c->w[l]);
+    c->tab_stride = (long)std::max(c->max_i, 1) * hmax;
+    ALLOC(c->tab, (size_t)c->tab_stride * (2 + kMaxChunks) * c->esz_c);
+  }
   c->partial_n = residual_blocks(std::max(c->max_i, c->max_b));
   ALLOC(c->partial, sizeof(double) * c->partial_n);
   ALLOC(c->loss, sizeof(double) * (2 + kMaxCand + 2));
@@ -562,6 +656,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
       ALLOC(p.P[0], np2);
       ALLOC(p.P[1], np2);
       ALLOC(p.V, (size_t)(p.n_pad / 64) * 64 * 64 * sizeof(double));
+      ALLOC(p.pflag, (size_t)(p.n_pad / 64 + 1) * sizeof(int));
       ALLOC(p.Pout, (size_t)p.n * p.n * sizeof(double));
       ALLOC(p.eout, (size_t)p.n * sizeof(double));
       c->probs.push_back(p);
@@ -653,7 +748,7 @@ kp_status kfac_pinn_sample(kfac_pinn_ctx* c, const kp_sampler* s, int64_t step, 
   sd.scale = s->scale;
   sd.kappa = s->kappa;
   sd.step = (long)step;
-  KP_TRY(sample(c->P, sd, x_int, y_int, x_bnd, y_bnd, c->st));
+  KP_TRY(sample(c->pp, sd, x_int, y_int, x_bnd, y_bnd, c->st));
   return KP_OK;
 }
 
@@ -662,11 +757,10 @@ kp_status kfac_pinn_forward_laplacian(kfac_pinn_ctx* c, const void* theta, const
   KP_ARG(c && theta && x, "null argument");
   KP_ARG(n >= 0 && n <= c->max_i, "n exceeds max_interior");
   if (n == 0) return KP_OK;
-  KP_TRY(prep(c, theta, nullptr, 0.0));
-  KP_TRY(forward_store(c, c->si, x, n));
-  const void* pre_last = c->si.store ? c->si.pre[c->L - 1] : c->si.prer;
-  KP_TRY(extract_outputs(c->P, pre_last, c->ldp[c->L - 1], n, c->si.S, c->d, c->si.S - 1, u_out,
-                         grad_out, lap_out, c->st));
+  KP_TRY(prep(c, theta));
+  KP_TRY(forward_run(c, c->si, x, n, c->L, curvature_target(c, c->si, theta)));
+  KP_TRY(extract_outputs(c->pp, c->si.u, 1, n, c->si.S, c->d, c->si.S - 1, u_out, grad_out,
+                         lap_out, c->st));
   return KP_OK;
 }
 
@@ -680,21 +774,20 @@ kp_status kfac_pinn_forward_laplacian_vjp(kfac_pinn_ctx* c, const void* theta, c
     return KP_OK;
   }
   Slabs& s = c->si;
-  KP_TRY(prep(c, theta, nullptr, 0.0));
-  if (s.store) KP_TRY(forward_store(c, s, x, n));
-  void* g_last = s.store ? s.g[c->L - 1] : s.gr[(c->L - 1) & 1];
-  KP_TRY(seed_rows(c->P, u_bar, grad_bar, lap_bar, n, s.S, c->d, s.S - 1, g_last,
+  KP_TRY(prep(c, theta));
+  // stored mode: slabs of this (theta, x); recompute mode: the last hidden layer's
+  // inputs and pre-activations for the first backward step
+  KP_TRY(forward_run(c, s, x, n, c->L, curvature_target(c, s, theta)));
+  KP_TRY(seed_rows(c->sp, u_bar, grad_bar, lap_bar, n, s.S, c->d, s.S - 1, s.g_at(c->L - 1),
                    c->ldg[c->L - 1], c->st));
   ThetaBar tb;
   tb.c = c;
   tb.n = n;
   tb.S = s.S;
   tb.out = theta_bar;
-  KP_TRY(backward_sweep(c, s, x, n, tb));
-  if (x_bar) {
-    const void* g0 = s.store ? s.g[0] : s.gr[0];
-    KP_TRY(input_vjp(c->P, theta, c->w[1], c->d, g0, c->ldg[0], n, s.S, x_bar, c->st));
-  }
+  KP_TRY(backward_sweep(c, s, theta, x, n, tb));
+  if (x_bar)
+    KP_TRY(input_vjp(c->sp, theta, c->w[1], c->d, s.g_at(0), c->ldg[0], n, s.S, x_bar, c->st));
   return KP_OK;
 }
 
@@ -713,7 +806,7 @@ static hipError_t decay_term(kfac_pinn_ctx* c, int term, double beta) {
   for (int sd = 0; sd < 2; sd++)
     for (int l = 0; l < c->L; l++) {
       const int n = sd == 0 ? c->w[l] + 1 : c->w[l + 1];
-      hipError_t e = reduce_splitk(c->P, c->part, 0, n, n, true, c->F[term][sd][l], n, 1, 0.0,
+      hipError_t e = reduce_splitk(c->cmode, c->part, 0, n, n, true, c->F[term][sd][l], n, 1, 0.0,
                                    beta, c->st);
       if (e != hipSuccess) return e;
     }
@@ -722,13 +815,13 @@ static hipError_t decay_term(kfac_pinn_ctx* c, int term, double beta) {
 
 static kp_status factors_impl(kfac_pinn_ctx* c, const void* theta, const void* xi, const void* yi,
                               int ni, const void* xb, const void* yb, int nb, double beta) {
-  KP_TRY(prep(c, theta, nullptr, 0.0));
+  KP_TRY(prep(c, theta));
   KP_TRY(hipMemsetAsync(c->grad, 0, sizeof(double) * c->D, c->st));
   KP_TRY(hipMemsetAsync(c->loss, 0, sizeof(double) * 2, c->st));
   // interior term first: it overwrites the gradient, the boundary term adds to it
-  if (ni > 0) KP_TRY(curvature_term(c, 0, xi, yi, ni, beta, true));
+  if (ni > 0) KP_TRY(curvature_term(c, 0, theta, xi, yi, ni, beta));
   else KP_TRY(decay_term(c, 0, beta));
-  if (nb > 0) KP_TRY(curvature_term(c, 1, xb, yb, nb, beta, true));
+  if (nb > 0) KP_TRY(curvature_term(c, 1, theta, xb, yb, nb, beta));
   else KP_TRY(decay_term(c, 1, beta));
   return KP_OK;
 }
@@ -799,17 +892,19 @@ kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const vo
   }
   // 4) Delta = -C g, momentum
   KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
-  KP_TRY(momentum(c->P, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
+  KP_TRY(momentum(c->pp, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
   // 5) learning rate and update
   if (hp->lr_mode == 1) {
     for (int k = 0; k < ncand; k++) {
       const double alpha = ldexp(1.0, hp->grid_max_exp - k);
-      KP_TRY(prep(c, theta, c->dhat, alpha));
+      KP_TRY(axpy_theta(c->pp, theta, c->dhat, alpha, c->theta_trial, c->D, c->st));
+      KP_TRY(prep_weights(c->lp == P_BF16 ? P_BF16 : c->wp, c->theta_trial, nullptr, 0.0, c->nd,
+                          c->w_hi, c->w_lo, nullptr, 0, c->st));
       KP_TRY(eval_loss(c, xi, yi, ni, xb, yb, nb, 2 + k));
     }
     c->last_ncand = ncand;
   }
-  KP_TRY(finish_step(c->P, c->loss + 2, ncand, hp->grid_max_exp,
+  KP_TRY(finish_step(c->pp, c->loss + 2, ncand, hp->grid_max_exp,
                      hp->lr_mode == 1 ? -1.0 : hp->lr, c->loss, theta, c->dhat, c->delta, c->D,
                      c->ctl, c->ctl + 1, info, c->st));
   return KP_OK;

@@ -1,8 +1,8 @@
 // Elementwise and per-point kernels of the hot path.
 //
-// Slab layout (all slabs): row r = n*S + s holds point n's shared column s of
-// Z_n (Section 3.2): s = 0 the value, s = 1..d the first derivatives, s = S-1
-// the (masked) Laplacian row.  A boundary slab has S = 1 (value row only).
+// Slab layout (all slabs, s-major): row r = s*N + n holds point n's shared
+// column s of Z_n (Section 3.2): s = 0 the value, s = 1..d the first
+// derivatives, s = S-1 the (masked) Laplacian row.  A boundary slab has S = 1.
 // Columns are neurons; layer inputs carry the bias feature in column h
 // (1 in the value row, 0 elsewhere, Eq. forward-laplacian-linear-layer-compact)
 // and zeros up to the padded row length.
@@ -90,10 +90,10 @@ __global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S, TS* 
        e += (long)gridDim.x * blockDim.x) {
     long r = e / ldz;
     int j = (int)(e % ldz);
-    int pt = (int)(r / S), s = (int)(r % S);
+    int s = (int)(r / n), pt = (int)(r % n);
     double v = 0.0;
     if (s == 0) v = j < d ? (double)x[(long)pt * d + j] : (j == d ? 1.0 : 0.0);
-    else if (s <= d && S > 1 && s < S - 1) v = (j == s - 1) ? 1.0 : 0.0;
+    else if (S > 1 && s < S - 1) v = (j == s - 1) ? 1.0 : 0.0;
     z[e] = cvt<TS>(v);
   }
 }
@@ -119,130 +119,6 @@ hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long 
 }
 
 // ---------------------------------------------------------------------------
-// tanh layer, forward Laplacian rule (Eq. forward-laplacian-main, second line):
-//   v = tanh(a0);  d_i v = s1 d_i a;  Lv = s1 La + s2 sum_{i in M} (d_i a)^2
-// One thread per (point, column); nd derivative rows, optional Laplacian row.
-// ---------------------------------------------------------------------------
-template <typename TC, typename TS>
-__global__ void k_act_fwd(const TC* __restrict__ pre, long ldp, TS* __restrict__ z, long ldz,
-                          int npts, int S, int nd, int has_lap, const uint8_t* __restrict__ mask,
-                          int h) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int pt = blockIdx.y + blockIdx.z * gridDim.y;
-  if (j >= ldz || pt >= npts) return;
-  const long r0 = (long)pt * S;
-  if (j >= h) {   // bias feature and padding
-    for (int s = 0; s < S; s++) z[(r0 + s) * ldz + j] = cvt<TS>((j == h && s == 0) ? 1.0 : 0.0);
-    return;
-  }
-  const TC a0 = pre[r0 * ldp + j];
-  const TC t = act_tanh(a0);
-  const TC s1 = (TC)1 - t * t;
-  const TC s2 = (TC)-2 * t * s1;
-  z[r0 * ldz + j] = cvt<TS>((double)t);
-  TC sq = 0;
-  for (int i = 0; i < nd; i++) {
-    const TC da = pre[(r0 + 1 + i) * ldp + j];
-    z[(r0 + 1 + i) * ldz + j] = cvt<TS>((double)(s1 * da));
-    if (mask[i]) sq += da * da;
-  }
-  if (has_lap) {
-    const TC la = pre[(r0 + S - 1) * ldp + j];
-    z[(r0 + S - 1) * ldz + j] = cvt<TS>((double)(s1 * la + s2 * sq));
-  }
-}
-
-static dim3 pt_grid(int cols, int npts) {
-  int gy = npts, gz = 1;
-  while (gy > 65535) { gz *= 2; gy = (npts + gz - 1) / gz; }
-  return dim3((cols + 63) / 64, gy, gz);
-}
-
-hipError_t act_fwd(Prec p, const void* pre, long ldp, void* z, long ldz, int npts, int S, int nd,
-                   int has_lap, const uint8_t* mask, int h, hipStream_t st) {
-  if (npts <= 0) return hipSuccess;
-  dim3 g = pt_grid((int)ldz, npts);
-  switch (p) {
-    case P_F64:
-      k_act_fwd<double, double><<<g, 64, 0, st>>>((const double*)pre, ldp, (double*)z, ldz, npts,
-                                                  S, nd, has_lap, mask, h);
-      break;
-    case P_F32:
-      k_act_fwd<float, float><<<g, 64, 0, st>>>((const float*)pre, ldp, (float*)z, ldz, npts, S,
-                                                nd, has_lap, mask, h);
-      break;
-    case P_BF16:
-      k_act_fwd<float, bf16><<<g, 64, 0, st>>>((const float*)pre, ldp, (bf16*)z, ldz, npts, S,
-                                               nd, has_lap, mask, h);
-      break;
-  }
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Adjoint of the tanh rows.  With t = tanh(a0), s1 = 1-t^2, s2 = -2 t s1,
-// s3 = -2 s1 (1 - 3 t^2) and output cotangents vbar, dbar_i, Lbar:
-//   abar_0 = s1 vbar + s2 sum_i d_i a dbar_i + (s2 La + s3 sum_{i in M} (d_i a)^2) Lbar
-//   abar_i = s1 dbar_i + 2 [i in M] s2 d_i a Lbar
-//   abar_L = s1 Lbar
-// ---------------------------------------------------------------------------
-template <typename TC, typename TS>
-__global__ void k_act_bwd(const TC* __restrict__ zb, long ldzb, const TC* __restrict__ pre,
-                          long ldp, TS* __restrict__ g, long ldg, int npts, int S, int nd,
-                          int has_lap, const uint8_t* __restrict__ mask, int h) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int pt = blockIdx.y + blockIdx.z * gridDim.y;
-  if (j >= ldg || pt >= npts) return;
-  const long r0 = (long)pt * S;
-  if (j >= h) {
-    for (int s = 0; s < S; s++) g[(r0 + s) * ldg + j] = cvt<TS>(0.0);
-    return;
-  }
-  const TC a0 = pre[r0 * ldp + j];
-  const TC t = act_tanh(a0);
-  const TC s1 = (TC)1 - t * t;
-  const TC s2 = (TC)-2 * t * s1;
-  const TC s3 = (TC)-2 * s1 * ((TC)1 - (TC)3 * t * t);
-  const TC lb = has_lap ? zb[(r0 + S - 1) * ldzb + j] : (TC)0;
-  const TC la = has_lap ? pre[(r0 + S - 1) * ldp + j] : (TC)0;
-  TC sum1 = 0, sq = 0;
-  for (int i = 0; i < nd; i++) {
-    const TC da = pre[(r0 + 1 + i) * ldp + j];
-    const TC db = zb[(r0 + 1 + i) * ldzb + j];
-    const TC m = mask[i] ? (TC)1 : (TC)0;
-    sum1 += da * db;
-    sq += m * da * da;
-    g[(r0 + 1 + i) * ldg + j] = cvt<TS>((double)(s1 * db + (TC)2 * m * s2 * da * lb));
-  }
-  const TC vb = zb[r0 * ldzb + j];
-  g[r0 * ldg + j] = cvt<TS>((double)(s1 * vb + s2 * sum1 + (s2 * la + s3 * sq) * lb));
-  if (has_lap) g[(r0 + S - 1) * ldg + j] = cvt<TS>((double)(s1 * lb));
-}
-
-hipError_t act_bwd(Prec p, const void* zbar, long ldzb, const void* pre, long ldp, void* g,
-                   long ldg, int npts, int S, int nd, int has_lap, const uint8_t* mask, int h,
-                   hipStream_t st) {
-  if (npts <= 0) return hipSuccess;
-  dim3 gr = pt_grid((int)ldg, npts);
-  switch (p) {
-    case P_F64:
-      k_act_bwd<double, double><<<gr, 64, 0, st>>>((const double*)zbar, ldzb, (const double*)pre,
-                                                   ldp, (double*)g, ldg, npts, S, nd, has_lap,
-                                                   mask, h);
-      break;
-    case P_F32:
-      k_act_bwd<float, float><<<gr, 64, 0, st>>>((const float*)zbar, ldzb, (const float*)pre, ldp,
-                                                 (float*)g, ldg, npts, S, nd, has_lap, mask, h);
-      break;
-    case P_BF16:
-      k_act_bwd<float, bf16><<<gr, 64, 0, st>>>((const float*)zbar, ldzb, (const float*)pre, ldp,
-                                                (bf16*)g, ldg, npts, S, nd, has_lap, mask, h);
-      break;
-  }
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Residual (Eq. pinn-loss), loss partials and the output seed d r / d U
 // ---------------------------------------------------------------------------
 int residual_blocks(int npts) { return npts > 0 ? (npts + 255) / 256 : 1; }
@@ -258,14 +134,13 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   double sq = 0.0;
   if (n < npts) {
-    const long r0 = (long)n * S;
     double v;
     if (lap_row >= 0 || time_row >= 0) {
       v = -(double)y[n];
-      if (lap_row >= 0) v += c_lap * (double)pre[(r0 + lap_row) * ldp];
-      if (time_row >= 0) v += c_t * (double)pre[(r0 + time_row) * ldp];
+      if (lap_row >= 0) v += c_lap * (double)pre[((long)lap_row * npts + n) * ldp];
+      if (time_row >= 0) v += c_t * (double)pre[((long)time_row * npts + n) * ldp];
     } else {
-      v = (double)pre[r0 * ldp] - (double)y[n];   // boundary: r = u - g
+      v = (double)pre[(long)n * ldp] - (double)y[n];   // boundary: r = u - g
     }
     if (r) r[n] = v;
     sq = v * v;
@@ -277,8 +152,9 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
           if (s == lap_row) sv += c_lap;
           if (s == time_row) sv += c_t;
         }
-        g[(r0 + s) * ldg] = cvt<TS>(sv);
-        for (int c = 1; c < ldg; c++) g[(r0 + s) * ldg + c] = cvt<TS>(0.0);
+        const long row = (long)s * npts + n;
+        g[row * ldg] = cvt<TS>(sv);
+        for (int c = 1; c < ldg; c++) g[row * ldg + c] = cvt<TS>(0.0);
       }
     }
   }
@@ -342,11 +218,10 @@ __global__ void k_extract(const TC* __restrict__ pre, long ldp, int npts, int S,
                           int lap_row, TP* u, TP* grad, TP* lap) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= npts) return;
-  const long r0 = (long)n * S;
-  if (u) u[n] = (TP)pre[r0 * ldp];
+  if (u) u[n] = (TP)pre[(long)n * ldp];
   if (grad)
-    for (int i = 0; i < d; i++) grad[(long)n * d + i] = (TP)pre[(r0 + 1 + i) * ldp];
-  if (lap) lap[n] = lap_row >= 0 ? (TP)pre[(r0 + lap_row) * ldp] : (TP)0;
+    for (int i = 0; i < d; i++) grad[(long)n * d + i] = (TP)pre[((long)(1 + i) * npts + n) * ldp];
+  if (lap) lap[n] = lap_row >= 0 ? (TP)pre[((long)lap_row * npts + n) * ldp] : (TP)0;
 }
 
 hipError_t extract_outputs(Prec p, const void* pre, long ldp, int npts, int S, int d, int lap_row,
@@ -368,14 +243,14 @@ __global__ void k_seed(const TP* __restrict__ ub, const TP* __restrict__ gb,
                        long ldg) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= npts) return;
-  const long r0 = (long)n * S;
   for (int s = 0; s < S; s++) {
     double v = 0.0;
     if (s == 0) v = ub ? (double)ub[n] : 0.0;
     else if (s == lap_row) v = lb ? (double)lb[n] : 0.0;
     else if (s <= d) v = gb ? (double)gb[(long)n * d + s - 1] : 0.0;
-    g[(r0 + s) * ldg] = cvt<TS>(v);
-    for (int c = 1; c < ldg; c++) g[(r0 + s) * ldg + c] = cvt<TS>(0.0);
+    const long row = (long)s * npts + n;
+    g[row * ldg] = cvt<TS>(v);
+    for (int c = 1; c < ldg; c++) g[row * ldg + c] = cvt<TS>(0.0);
   }
 }
 
@@ -410,7 +285,7 @@ __global__ void k_input_vjp(const TP* __restrict__ theta, int h_out, int d,
   if (e >= (long)npts * d) return;
   const int n = (int)(e / d), k = (int)(e % d);
   double s = 0.0;
-  const TS* gr = g1 + (long)n * S * ldg;
+  const TS* gr = g1 + (long)n * ldg;   // value row s = 0 of point n
   for (int j = 0; j < h_out; j++) s += (double)theta[(long)k * h_out + j] * to_d(gr[j]);
   xb[e] = (TP)s;
 }
@@ -471,6 +346,26 @@ hipError_t momentum(Prec p, const double* Delta, const void* delta, double mu, c
     k_momentum<double><<<nb, 256, 0, st>>>(Delta, (const double*)delta, mu, step, (double*)dhat, D);
   else
     k_momentum<float><<<nb, 256, 0, st>>>(Delta, (const float*)delta, mu, step, (float*)dhat, D);
+  return hipGetLastError();
+}
+
+template <typename TP>
+__global__ void k_axpy_theta(const TP* __restrict__ theta, const TP* __restrict__ dir, double alpha,
+                             TP* __restrict__ out, long D) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D) return;
+  out[e] = theta[e] + (TP)(alpha * (double)dir[e]);
+}
+
+hipError_t axpy_theta(Prec p, const void* theta, const void* dir, double alpha, void* out, long D,
+                      hipStream_t st) {
+  int nb = (int)((D + 255) / 256);
+  if (p == P_F64)
+    k_axpy_theta<double><<<nb, 256, 0, st>>>((const double*)theta, (const double*)dir, alpha,
+                                             (double*)out, D);
+  else
+    k_axpy_theta<float><<<nb, 256, 0, st>>>((const float*)theta, (const float*)dir, alpha,
+                                            (float*)out, D);
   return hipGetLastError();
 }
 

@@ -1,0 +1,62 @@
+// Fused forward-Laplacian layer products (see fwdlap.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kp {
+
+// compute modes of the layer products
+enum { M_F64 = 0, M_F32 = 1, M_BF16 = 2, M_BF16X3 = 3 };
+
+struct FwdLayerArgs {
+  const void* zin;   // input slab (s-major rows s*N + p), row length ldz, zero beyond K
+  long ldz;
+  const void* w;     // weights: h_out rows of length ldw (bias in column h_in)
+  const void* w2;    // low parts (BF16x3) or nullptr
+  long ldw;
+  int K;             // h_in + 1 rounded up to 8
+  int N, S, nd, has_lap, h_out;
+  const uint8_t* mask;   // nd entries
+  void* z;           // output slab (row length ldzo): tanh rows, bias column, zeros
+  long ldzo;
+  void* pre;         // optional pre-activations (row length ldp)
+  long ldp;
+  void* tab_t;       // N*h_out: tanh of the value row
+  void* tab_sq;      // nch*N*h_out: chunk partial sums of squared derivative rows
+  void* tab_lap;     // N*h_out: Laplacian-row pre-activation
+  void* sq_out;      // optional N*h_out: total sum of squares (kept for the backward)
+};
+
+struct BwdLayerArgs {
+  const void* gin;   // output gradients of the next layer (rows s*N + p), row length ldgi
+  long ldgi;
+  const void* w;     // backward weights: h rows (this layer's width) of length ldw
+  const void* w2;
+  long ldw;
+  int K;             // next layer's width rounded up to 8
+  int N, S, nd, has_lap, h;
+  const uint8_t* mask;
+  const void* pre;   // this layer's pre-activations (row length ldp)
+  long ldp;
+  const void* sq;    // N*h: sum over masked derivative rows of pre^2
+  void* g;           // output gradients of this layer (row length ldgo)
+  long ldgo;
+  void* tab_lb;      // N*h: Laplacian-row cotangent
+  void* tab_zv;      // N*h: value-row cotangent
+  void* tab_s1;      // nch*N*h: chunk partials of sum_i d_i a zbar_i
+};
+
+int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap);
+hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
+hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
+int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap);
+hipError_t bwdlap_main(int mode, const BwdLayerArgs& a, int nch, hipStream_t st);
+hipError_t bwdlap_finish(int mode, const BwdLayerArgs& a, int nch, hipStream_t st);
+// output layer: u[row] = z[row] . w over K entries (bias column included)
+hipError_t last_fwd(int mode, const void* z, long ldz, const void* w, int K, long R, void* u,
+                    hipStream_t st);
+// gradients of the last hidden layer from output seeds sigma (row stride lds)
+hipError_t bwd_last(int mode, const BwdLayerArgs& a, const void* sigma, long lds, const void* wl,
+                    hipStream_t st);
+
+}  // namespace kp

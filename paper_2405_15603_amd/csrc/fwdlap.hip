@@ -1,0 +1,651 @@
+// Fused forward-Laplacian layer and its adjoint (Section 3.1, Eq.
+// forward-laplacian-main; backward pass of Algorithm 1).
+//
+// Slabs are s-major: row s*N + p holds shared column s of point p (s = 0 value,
+// 1..d first derivatives, S-1 the masked Laplacian).  For a fixed s the points
+// are contiguous, so one layer is S products of an N x K block with the same
+// weights.  A workgroup owns a tile of points x neurons and walks over s; the
+// tanh quantities of each (point, neuron) -- t = tanh(a_value) and the running
+// sum over derivative rows -- stay in the lane that holds that output, because
+// every s produces the same MFMA output layout.  The s range is split in chunks
+// (grid.y) for parallelism; a small finishing pass adds the chunk partials for
+// the Laplacian row (forward) and the value row (backward), in a fixed order.
+//
+// Compute modes: FP64 and FP32 MFMA; BF16 MFMA (BF16 slabs and weights, used by
+// the line search); BF16x3 (FP32 slabs split into BF16 hi + lo on the way into
+// LDS, weights as BF16 hi + lo; acc += hi*hi + lo*hi + hi*lo), used by the
+// mixed-precision curvature pass for FP32-level accuracy at BF16 MFMA rates.
+#include "common.h"
+#include "fwdlap.h"
+#include "launch.h"
+
+namespace kp {
+
+// ---------------------------------------------------------------------------
+// MFMA policies
+// ---------------------------------------------------------------------------
+template <int MODE> struct Op;
+template <> struct Op<M_F64> {
+  typedef double TA;   // A in global memory
+  typedef double TB;   // B in global memory
+  typedef double TL;   // LDS element
+  typedef double TC;   // compute / accumulate
+  static constexpr int NA = 1, NB = 1, BK = 16, PAD = 2, VA = 2;
+};
+template <> struct Op<M_F32> {
+  typedef float TA;
+  typedef float TB;
+  typedef float TL;
+  typedef float TC;
+  static constexpr int NA = 1, NB = 1, BK = 16, PAD = 4, VA = 4;
+};
+template <> struct Op<M_BF16> {
+  typedef bf16 TA;
+  typedef bf16 TB;
+  typedef bf16 TL;
+  typedef float TC;
+  static constexpr int NA = 1, NB = 1, BK = 32, PAD = 8, VA = 8;
+};
+template <> struct Op<M_BF16X3> {
+  typedef float TA;
+  typedef bf16 TB;
+  typedef bf16 TL;
+  typedef float TC;
+  static constexpr int NA = 2, NB = 2, BK = 32, PAD = 8, VA = 4;
+};
+
+typedef uint4 v16;
+
+template <typename TL>
+__device__ __forceinline__ typename Mfma<TL>::frag frag_ld(const TL* base, int lane, int ldk, int k0);
+template <>
+__device__ __forceinline__ bf16x8 frag_ld<bf16>(const bf16* base, int lane, int ldk, int k0) {
+  return *(const bf16x8*)(base + (lane & 15) * ldk + k0 + (lane >> 4) * 8);
+}
+template <>
+__device__ __forceinline__ float frag_ld<float>(const float* base, int lane, int ldk, int k0) {
+  return base[(lane & 15) * ldk + k0 + (lane >> 4)];
+}
+template <>
+__device__ __forceinline__ double frag_ld<double>(const double* base, int lane, int ldk, int k0) {
+  return base[(lane & 15) * ldk + k0 + (lane >> 4)];
+}
+
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  const int per = total / 8, rem = total % 8;
+  const int x = b % 8, i = b / 8;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+// Tile geometry: 4 waves as 2 x 2; wave tile WP points x WN neurons.
+template <int MODE> struct Geo {
+  static constexpr int WP = 32, WN = MODE == M_F64 ? 32 : 64;
+  static constexpr int BP = 2 * WP, BN = 2 * WN;
+  static constexpr int TI = WP / 16, TJ = WN / 16;
+};
+
+// One s: acc[TI][TJ] = A_s[p0:p0+BP, :K] * B[c0:c0+BN, :K]^T with LDS double
+// buffering.  A rows are arow0 + p (p < N), B rows c (c < ncols).
+template <int MODE>
+struct Mainloop {
+  typedef Op<MODE> O;
+  typedef Geo<MODE> G;
+  typedef typename O::TL TL;
+  static constexpr int BK = O::BK, LDK = O::BK + O::PAD;
+  static constexpr int VA = O::VA;                  // A elements per 16-byte load
+  static constexpr int VB = 16 / sizeof(typename O::TB);
+  static constexpr int AV = G::BP * (BK / VA) / 256;  // A vectors per thread
+  static constexpr int BV = G::BN * (BK / VB) / 256;
+  struct Smem {
+    TL a[2][O::NA][G::BP * LDK];
+    TL b[2][O::NB][G::BN * LDK];
+  };
+};
+
+template <int MODE>
+__device__ __forceinline__ void tile_product(
+    typename Mainloop<MODE>::Smem& sm, const typename Op<MODE>::TA* __restrict__ A, long lda,
+    long arow0, int p0, int N, const typename Op<MODE>::TB* __restrict__ B,
+    const typename Op<MODE>::TB* __restrict__ B2, long ldb, int c0, int ncols, int K,
+    typename Mfma<typename Op<MODE>::TL>::acc acc[Geo<MODE>::TI][Geo<MODE>::TJ]) {
+  typedef Mainloop<MODE> ML;
+  typedef Op<MODE> O;
+  typedef Geo<MODE> G;
+  typedef typename O::TL TL;
+  typedef Mfma<TL> MF;
+  constexpr int BK = ML::BK, LDK = ML::LDK, VA = ML::VA, VB = ML::VB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wp = wave >> 1, wn = wave & 1;
+  v16 ra[ML::AV], rb[O::NB][ML::BV];
+  const v16 z16 = {0u, 0u, 0u, 0u};
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < ML::AV; i++) {
+      const int v = tid + i * 256, r = v / (BK / VA), kv = (v % (BK / VA)) * VA;
+      const int p = p0 + r, k = k0 + kv;
+      ra[i] = (p < N && k < K) ? *(const v16*)(A + (arow0 + p) * lda + k) : z16;
+    }
+#pragma unroll
+    for (int i = 0; i < ML::BV; i++) {
+      const int v = tid + i * 256, r = v / (BK / VB), kv = (v % (BK / VB)) * VB;
+      const int c = c0 + r, k = k0 + kv;
+      const bool ok = c < ncols && k < K;
+      rb[0][i] = ok ? *(const v16*)(B + (long)c * ldb + k) : z16;
+      if (O::NB == 2) rb[O::NB - 1][i] = ok ? *(const v16*)(B2 + (long)c * ldb + k) : z16;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < ML::AV; i++) {
+      const int v = tid + i * 256, r = v / (BK / VA), kv = (v % (BK / VA)) * VA;
+      if (MODE == M_BF16X3) {
+        // FP32 -> BF16 hi + lo
+        const float* f = (const float*)&ra[i];
+        __attribute__((aligned(8))) bf16 hi[4], lo[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          hi[e] = (bf16)f[e];
+          lo[e] = (bf16)(f[e] - (float)hi[e]);
+        }
+        *(uint2*)(&sm.a[buf][0][r * LDK + kv]) = *(const uint2*)hi;
+        *(uint2*)(&sm.a[buf][O::NA - 1][r * LDK + kv]) = *(const uint2*)lo;
+      } else {
+        *(v16*)(&sm.a[buf][0][r * LDK + kv]) = ra[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ML::BV; i++) {
+      const int v = tid + i * 256, r = v / (BK / VB), kv = (v % (BK / VB)) * VB;
+#pragma unroll
+      for (int h = 0; h < O::NB; h++) *(v16*)(&sm.b[buf][h][r * LDK + kv]) = rb[h][i];
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < G::TI; i++)
+#pragma unroll
+    for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+  const int nk = (K + BK - 1) / BK;
+  gload(0);
+  __syncthreads();   // the previous s may still read buffer 0
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += MF::K) {
+      typename MF::frag a[O::NA][G::TI], b[O::NB][G::TJ];
+#pragma unroll
+      for (int h = 0; h < O::NA; h++)
+#pragma unroll
+        for (int i = 0; i < G::TI; i++)
+          a[h][i] = frag_ld<TL>(&sm.a[cur][h][(wp * G::WP + i * 16) * LDK], lane, LDK, kk);
+#pragma unroll
+      for (int h = 0; h < O::NB; h++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++)
+          b[h][j] = frag_ld<TL>(&sm.b[cur][h][(wn * G::WN + j * 16) * LDK], lane, LDK, kk);
+#pragma unroll
+      for (int i = 0; i < G::TI; i++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++) {
+          acc[i][j] = MF::mma(a[0][i], b[0][j], acc[i][j]);
+          if (MODE == M_BF16X3) {
+            acc[i][j] = MF::mma(a[O::NA - 1][i], b[0][j], acc[i][j]);
+            acc[i][j] = MF::mma(a[0][i], b[O::NB - 1][j], acc[i][j]);
+          }
+        }
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward layer.  Chunk c of C handles derivative rows [1 + c*len, ...), always
+// recomputes the value row (s = 0) first for t, and the last chunk also forms the
+// Laplacian row's pre-activation.  Outputs: z rows (value, derivatives) of the
+// next slab, optional pre-activations, and the tables for the finishing pass.
+// ---------------------------------------------------------------------------
+template <int MODE, typename TZ>
+__global__ __launch_bounds__(256) void k_fwdlap(FwdLayerArgs a) {
+  typedef Op<MODE> O;
+  typedef Geo<MODE> G;
+  typedef typename O::TC TC;
+  typedef Mfma<typename O::TL> MF;
+  __shared__ typename Mainloop<MODE>::Smem sm;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wp = wave >> 1, wn = wave & 1;
+  const int ntc = (a.h_out + G::BN - 1) / G::BN;
+  const int ntp = (a.N + G::BP - 1) / G::BP;
+  const int t = xcd_tile(blockIdx.x, ntp * ntc);
+  const int p0 = (t / ntc) * G::BP, c0 = (t % ntc) * G::BN;
+  const int chunk = blockIdx.y, nch = gridDim.y;
+  const int nd = a.nd;
+  const int len = (nd + nch - 1) / nch;
+  const int dbeg = 1 + chunk * len, dend = min(1 + nd, dbeg + len);
+  const bool lap_here = a.has_lap && chunk == nch - 1;
+  const int nsteps = 1 + max(0, dend - dbeg) + (lap_here ? 1 : 0);
+
+  TC tv[G::TI][G::TJ][4], sq[G::TI][G::TJ][4];
+  typename MF::acc acc[G::TI][G::TJ];
+#pragma unroll
+  for (int i = 0; i < G::TI; i++)
+#pragma unroll
+    for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) sq[i][j][e] = 0;
+
+  for (int st = 0; st < nsteps; st++) {
+    const int s = st == 0 ? 0 : (st <= dend - dbeg ? dbeg + st - 1 : a.S - 1);
+    tile_product<MODE>(sm, (const typename O::TA*)a.zin, a.ldz, (long)s * a.N, p0, a.N,
+                       (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0,
+                       a.h_out, a.K, acc);
+    const bool is_d = s >= 1 && s <= nd;
+    const TC m = (is_d && a.mask[s - 1]) ? (TC)1 : (TC)0;
+#pragma unroll
+    for (int i = 0; i < G::TI; i++)
+#pragma unroll
+      for (int j = 0; j < G::TJ; j++) {
+        const int c = c0 + wn * G::WN + j * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int p = p0 + wp * G::WP + i * 16 + MF::row(lane, e);
+          const TC v = (TC)acc[i][j][e];
+          const bool ok = p < a.N && c < a.h_out;
+          const long row = (long)s * a.N + p;
+          if (s == 0) {
+            const TC th = act_tanh(v);
+            tv[i][j][e] = th;
+            if (ok && chunk == 0) {
+              ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)th);
+              if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v;
+              if (a.tab_t) ((TC*)a.tab_t)[(long)p * a.h_out + c] = th;
+            }
+          } else if (is_d) {
+            const TC th = tv[i][j][e];
+            sq[i][j][e] += m * v * v;
+            if (ok) {
+              ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)(((TC)1 - th * th) * v));
+              if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v;
+            }
+          } else if (ok) {   // Laplacian row pre-activation
+            ((TC*)a.tab_lap)[(long)p * a.h_out + c] = v;
+            if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v;
+          }
+        }
+      }
+  }
+  if (a.has_lap) {
+#pragma unroll
+    for (int i = 0; i < G::TI; i++)
+#pragma unroll
+      for (int j = 0; j < G::TJ; j++) {
+        const int c = c0 + wn * G::WN + j * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int p = p0 + wp * G::WP + i * 16 + MF::row(lane, e);
+          if (p < a.N && c < a.h_out)
+            ((TC*)a.tab_sq)[((long)chunk * a.N + p) * a.h_out + c] = sq[i][j][e];
+        }
+      }
+  }
+}
+
+// Laplacian rows  Lz = s1 La + s2 sum_chunks sq, the bias feature and padding.
+template <typename TC, typename TZ>
+__global__ void k_fwdlap_finish(FwdLayerArgs a, int nch) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y + blockIdx.z * gridDim.y;
+  if (c >= a.ldzo || p >= a.N) return;
+  TZ* z = (TZ*)a.z;
+  if (c >= a.h_out) {
+    for (int s = 0; s < a.S; s++)
+      z[((long)s * a.N + p) * a.ldzo + c] = cvt<TZ>((c == a.h_out && s == 0) ? 1.0 : 0.0);
+    return;
+  }
+  if (!a.has_lap) return;
+  const long pc = (long)p * a.h_out + c;
+  const TC t = ((const TC*)a.tab_t)[pc];
+  const TC s1 = (TC)1 - t * t, s2 = (TC)-2 * t * s1;
+  TC sq = 0;
+  for (int k = 0; k < nch; k++) sq += ((const TC*)a.tab_sq)[(long)k * a.N * a.h_out + pc];
+  const TC la = ((const TC*)a.tab_lap)[pc];
+  z[((long)(a.S - 1) * a.N + p) * a.ldzo + c] = cvt<TZ>((double)(s1 * la + s2 * sq));
+  if (a.sq_out) ((TC*)a.sq_out)[pc] = sq;
+}
+
+// ---------------------------------------------------------------------------
+// Backward layer: zbar_s = G_s W (W: h_out_next x h_in_next as rows of W^T), then
+// the adjoint of the tanh rows at this layer's pre-activations:
+//   gL = s1 Lbar;  g_i = s1 zbar_i + 2 [i in M] s2 d_i a Lbar;
+//   g_0 = s1 zbar_0 + s2 sum_i d_i a zbar_i + (s2 La + s3 sq) Lbar   (finishing pass)
+// Every chunk first recomputes the Laplacian row's cotangent Lbar.
+// ---------------------------------------------------------------------------
+template <int MODE, typename TG>
+__global__ __launch_bounds__(256) void k_bwdlap(BwdLayerArgs a) {
+  typedef Op<MODE> O;
+  typedef Geo<MODE> G;
+  typedef typename O::TC TC;
+  typedef Mfma<typename O::TL> MF;
+  __shared__ typename Mainloop<MODE>::Smem sm;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wp = wave >> 1, wn = wave & 1;
+  const int ntc = (a.h + G::BN - 1) / G::BN;
+  const int ntp = (a.N + G::BP - 1) / G::BP;
+  const int t = xcd_tile(blockIdx.x, ntp * ntc);
+  const int p0 = (t / ntc) * G::BP, c0 = (t % ntc) * G::BN;
+  const int chunk = blockIdx.y, nch = gridDim.y;
+  const int nd = a.nd;
+  const int len = (nd + nch - 1) / nch;
+  const int dbeg = 1 + chunk * len, dend = min(1 + nd, dbeg + len);
+  const int nsteps = (a.has_lap ? 1 : 0) + max(0, dend - dbeg) + (chunk == 0 ? 1 : 0);
+  const TC* pre = (const TC*)a.pre;
+
+  TC lb[G::TI][G::TJ][4], tv[G::TI][G::TJ][4], sum1[G::TI][G::TJ][4];
+  typename MF::acc acc[G::TI][G::TJ];
+#pragma unroll
+  for (int i = 0; i < G::TI; i++)
+#pragma unroll
+    for (int j = 0; j < G::TJ; j++) {
+      const int c = c0 + wn * G::WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int p = p0 + wp * G::WP + i * 16 + MF::row(lane, e);
+        TC tt = 0;
+        if (p < a.N && c < a.h) tt = act_tanh(pre[(long)p * a.ldp + c]);
+        tv[i][j][e] = tt;
+        lb[i][j][e] = 0;
+        sum1[i][j][e] = 0;
+      }
+    }
+  for (int st = 0; st < nsteps; st++) {
+    int s;
+    if (a.has_lap && st == 0) s = a.S - 1;
+    else {
+      const int k = st - (a.has_lap ? 1 : 0);
+      s = (k < dend - dbeg) ? dbeg + k : 0;
+    }
+    tile_product<MODE>(sm, (const typename O::TA*)a.gin, a.ldgi, (long)s * a.N, p0, a.N,
+                       (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0, a.h,
+                       a.K, acc);
+    const bool is_d = s >= 1 && s <= nd;
+    const TC m = (is_d && a.mask[s - 1]) ? (TC)1 : (TC)0;
+#pragma unroll
+    for (int i = 0; i < G::TI; i++)
+#pragma unroll
+      for (int j = 0; j < G::TJ; j++) {
+        const int c = c0 + wn * G::WN + j * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int p = p0 + wp * G::WP + i * 16 + MF::row(lane, e);
+          const TC v = (TC)acc[i][j][e];
+          const bool ok = p < a.N && c < a.h;
+          const long row = (long)s * a.N + p;
+          const TC tt = tv[i][j][e];
+          const TC s1 = (TC)1 - tt * tt;
+          if (a.has_lap && s == a.S - 1) {
+            lb[i][j][e] = v;
+            if (ok && chunk == nch - 1) {
+              ((TG*)a.g)[row * a.ldgo + c] = cvt<TG>((double)(s1 * v));
+              ((TC*)a.tab_lb)[(long)p * a.h + c] = v;
+            }
+          } else if (is_d) {
+            if (ok) {
+              const TC da = pre[row * a.ldp + c];
+              const TC s2 = (TC)-2 * tt * s1;
+              sum1[i][j][e] += da * v;
+              ((TG*)a.g)[row * a.ldgo + c] =
+                  cvt<TG>((double)(s1 * v + (TC)2 * m * s2 * da * lb[i][j][e]));
+            }
+          } else if (ok) {   // value row cotangent (chunk 0)
+            if (a.has_lap) ((TC*)a.tab_zv)[(long)p * a.h + c] = v;
+            else ((TG*)a.g)[row * a.ldgo + c] = cvt<TG>((double)(s1 * v));
+          }
+        }
+      }
+  }
+  if (a.has_lap) {
+#pragma unroll
+    for (int i = 0; i < G::TI; i++)
+#pragma unroll
+      for (int j = 0; j < G::TJ; j++) {
+        const int c = c0 + wn * G::WN + j * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int p = p0 + wp * G::WP + i * 16 + MF::row(lane, e);
+          if (p < a.N && c < a.h)
+            ((TC*)a.tab_s1)[((long)chunk * a.N + p) * a.h + c] = sum1[i][j][e];
+        }
+      }
+  }
+}
+
+// value rows of g (interior) and the zero padding of g
+template <typename TC, typename TG>
+__global__ void k_bwdlap_finish(BwdLayerArgs a, int nch) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y + blockIdx.z * gridDim.y;
+  if (c >= a.ldgo || p >= a.N) return;
+  TG* g = (TG*)a.g;
+  if (c >= a.h) {
+    for (int s = 0; s < a.S; s++) g[((long)s * a.N + p) * a.ldgo + c] = cvt<TG>(0.0);
+    return;
+  }
+  if (!a.has_lap) return;
+  const TC* pre = (const TC*)a.pre;
+  const long pc = (long)p * a.h + c;
+  const TC t = act_tanh(pre[(long)p * a.ldp + c]);
+  const TC s1 = (TC)1 - t * t, s2 = (TC)-2 * t * s1, s3 = (TC)-2 * s1 * ((TC)1 - (TC)3 * t * t);
+  const TC la = pre[((long)(a.S - 1) * a.N + p) * a.ldp + c];
+  const TC sq = ((const TC*)a.sq)[pc];
+  const TC lb = ((const TC*)a.tab_lb)[pc];
+  const TC zv = ((const TC*)a.tab_zv)[pc];
+  TC s1sum = 0;
+  for (int k = 0; k < nch; k++) s1sum += ((const TC*)a.tab_s1)[(long)k * a.N * a.h + pc];
+  g[(long)p * a.ldgo + c] = cvt<TG>((double)(s1 * zv + s2 * s1sum + (s2 * la + s3 * sq) * lb));
+}
+
+// ---------------------------------------------------------------------------
+// Output layer (one neuron): U[row] = z~[row] . w~  (bias in the bias column)
+// ---------------------------------------------------------------------------
+template <typename TZ, typename TW, typename TC>
+__global__ __launch_bounds__(256) void k_last_fwd(const TZ* __restrict__ z, long ldz,
+                                                  const TW* __restrict__ w, int K, long R,
+                                                  TC* __restrict__ u) {
+  // one wave per row: lanes stride over K
+  const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= R) return;
+  TC s = 0;
+  for (int k = lane; k < K; k += 64) s += (TC)to_d(z[row * ldz + k]) * (TC)to_d(w[k]);
+  s = warp_sum(s);
+  if (lane == 0) u[row] = s;
+}
+
+// g of the last hidden layer from the output seeds sigma (zbar_s = sigma_s w):
+// the same adjoint as k_bwdlap with an outer-product zbar.
+template <typename TC, typename TSd, typename TG, typename TW>
+__global__ void k_bwd_last(BwdLayerArgs a, const TSd* __restrict__ sigma, long lds,
+                           const TW* __restrict__ wl) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y + blockIdx.z * gridDim.y;
+  if (c >= a.ldgo || p >= a.N) return;
+  TG* g = (TG*)a.g;
+  if (c >= a.h) {
+    for (int s = 0; s < a.S; s++) g[((long)s * a.N + p) * a.ldgo + c] = cvt<TG>(0.0);
+    return;
+  }
+  const TC* pre = (const TC*)a.pre;
+  const TC w = (TC)to_d(wl[c]);
+  auto sig = [&](int s) { return (TC)to_d(sigma[((long)s * a.N + p) * lds]); };
+  const TC t = act_tanh(pre[(long)p * a.ldp + c]);
+  const TC s1 = (TC)1 - t * t, s2 = (TC)-2 * t * s1, s3 = (TC)-2 * s1 * ((TC)1 - (TC)3 * t * t);
+  if (!a.has_lap) {
+    g[(long)p * a.ldgo + c] = cvt<TG>((double)(s1 * sig(0) * w));
+    return;
+  }
+  const TC lb = sig(a.S - 1) * w;
+  const TC la = pre[((long)(a.S - 1) * a.N + p) * a.ldp + c];
+  TC sum1 = 0, sq = 0;
+  for (int i = 0; i < a.nd; i++) {
+    const int s = 1 + i;
+    const long row = (long)s * a.N + p;
+    const TC da = pre[row * a.ldp + c];
+    const TC zb = sig(s) * w;
+    const TC m = a.mask[i] ? (TC)1 : (TC)0;
+    sum1 += da * zb;
+    sq += m * da * da;
+    g[row * a.ldgo + c] = cvt<TG>((double)(s1 * zb + (TC)2 * m * s2 * da * lb));
+  }
+  g[((long)(a.S - 1) * a.N + p) * a.ldgo + c] = cvt<TG>((double)(s1 * lb));
+  g[(long)p * a.ldgo + c] =
+      cvt<TG>((double)(s1 * sig(0) * w + s2 * sum1 + (s2 * la + s3 * sq) * lb));
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static dim3 pc_grid(long cols, int npts, int bs) {
+  int gy = npts, gz = 1;
+  while (gy > 65535) { gz *= 2; gy = (npts + gz - 1) / gz; }
+  return dim3((unsigned)((cols + bs - 1) / bs), gy, gz);
+}
+
+static int choose_chunks(int tiles, int nd, int has_lap) {
+  if (!has_lap || nd <= 1) return 1;
+  int ch = 1;
+  while (tiles * ch < 512 && ch * 2 <= nd && ch < 16) ch *= 2;
+  return ch;
+}
+
+int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
+  const int BP = 64, BN = mode == M_F64 ? 64 : 128;
+  const int tiles = ((N + BP - 1) / BP) * ((h_out + BN - 1) / BN);
+  return choose_chunks(tiles, nd, has_lap);
+}
+int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap) {
+  return fwdlap_chunks(mode, N, h, nd, has_lap);
+}
+
+template <int MODE>
+static dim3 tile_grid(int N, int cols, int nch) {
+  typedef Geo<MODE> G;
+  return dim3(((N + G::BP - 1) / G::BP) * ((cols + G::BN - 1) / G::BN), nch);
+}
+
+hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  switch (mode) {
+    case M_F64:
+      k_fwdlap<M_F64, double><<<tile_grid<M_F64>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      break;
+    case M_F32:
+      k_fwdlap<M_F32, float><<<tile_grid<M_F32>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      break;
+    case M_BF16:
+      k_fwdlap<M_BF16, bf16><<<tile_grid<M_BF16>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      break;
+    case M_BF16X3:
+      k_fwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  dim3 g = pc_grid(a.ldzo, a.N, 64);
+  switch (mode) {
+    case M_F64: k_fwdlap_finish<double, double><<<g, 64, 0, st>>>(a, nch); break;
+    case M_F32: k_fwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
+    case M_BF16: k_fwdlap_finish<float, bf16><<<g, 64, 0, st>>>(a, nch); break;
+    case M_BF16X3: k_fwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t bwdlap_main(int mode, const BwdLayerArgs& a, int nch, hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  switch (mode) {
+    case M_F64:
+      k_bwdlap<M_F64, double><<<tile_grid<M_F64>(a.N, a.h, nch), 256, 0, st>>>(a);
+      break;
+    case M_F32:
+      k_bwdlap<M_F32, float><<<tile_grid<M_F32>(a.N, a.h, nch), 256, 0, st>>>(a);
+      break;
+    case M_BF16X3:
+      k_bwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3>(a.N, a.h, nch), 256, 0, st>>>(a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t bwdlap_finish(int mode, const BwdLayerArgs& a, int nch, hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  dim3 g = pc_grid(a.ldgo, a.N, 64);
+  switch (mode) {
+    case M_F64: k_bwdlap_finish<double, double><<<g, 64, 0, st>>>(a, nch); break;
+    case M_F32: k_bwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
+    case M_BF16X3: k_bwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t last_fwd(int mode, const void* z, long ldz, const void* w, int K, long R, void* u,
+                    hipStream_t st) {
+  const int nb = (int)((R + 3) / 4);
+  if (R <= 0) return hipSuccess;
+  switch (mode) {
+    case M_F64:
+      k_last_fwd<double, double, double><<<nb, 256, 0, st>>>((const double*)z, ldz,
+                                                             (const double*)w, K, R, (double*)u);
+      break;
+    case M_F32:
+      k_last_fwd<float, float, float><<<nb, 256, 0, st>>>((const float*)z, ldz, (const float*)w,
+                                                          K, R, (float*)u);
+      break;
+    case M_BF16:
+      k_last_fwd<bf16, float, float><<<nb, 256, 0, st>>>((const bf16*)z, ldz, (const float*)w, K,
+                                                         R, (float*)u);
+      break;
+    case M_BF16X3:
+      k_last_fwd<float, float, float><<<nb, 256, 0, st>>>((const float*)z, ldz, (const float*)w,
+                                                          K, R, (float*)u);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t bwd_last(int mode, const BwdLayerArgs& a, const void* sigma, long lds, const void* wl,
+                    hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  dim3 g = pc_grid(a.ldgo, a.N, 64);
+  switch (mode) {
+    case M_F64:
+      k_bwd_last<double, double, double, double><<<g, 64, 0, st>>>(a, (const double*)sigma, lds,
+                                                                   (const double*)wl);
+      break;
+    case M_F32:
+      k_bwd_last<float, float, float, float><<<g, 64, 0, st>>>(a, (const float*)sigma, lds,
+                                                               (const float*)wl);
+      break;
+    case M_BF16X3:
+      k_bwd_last<float, float, float, float><<<g, 64, 0, st>>>(a, (const float*)sigma, lds,
+                                                               (const float*)wl);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace kp

@@ -9,28 +9,18 @@ namespace kp {
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
 
-// ---- layer products ---------------------------------------------------------
-// C[M x N] = A[M x K] * B[N x K]^T (+ B2 for the low part of a split operand),
-// rows of A and B hold K contiguous elements (lda, ldb >= K, K a multiple of the
-// 16-byte vector and zero beyond the true width).  Result in the compute type
-// (double for P_F64, float otherwise) at out[row*ldo + col], plus bias[col] on
-// rows with row % S == 0 when bias != nullptr.
-hipError_t gemm_nt(Prec p, const void* A, long lda, const void* B, const void* B2, long ldb,
-                   int M, int N, int K, void* out, long ldo, const void* bias, int S,
-                   hipStream_t st);
-
-// ---- factor / gradient products --------------------------------------------
+// ---- factor / gradient products (modes of fwdlap.h) -------------------------
 // part[s][m*N + n] = sum_{k in split s} w(k) A[k][m] B[k][n] for the tiles the
-// kernel covers (sym: only tiles at or above the diagonal).  w(k) = rw[k / S]
-// when rw != nullptr, else 1.  A and B are row-major K x (>= M / N) with lda/ldb.
-// part is double for P_F64, float otherwise.  Returns the number of splits used
-// through *splits_out (chosen by the launcher, <= max_splits).
-hipError_t gemm_tn_splitk(Prec p, const void* A, long lda, const void* B, long ldb, int M, int N,
-                          int K, const double* rw, int S, bool sym, void* part, int max_splits,
+// kernel covers (sym: only tiles at or above the diagonal).  w(k) = rw[k % rmod]
+// when rw != nullptr (one weight per point; slab rows are s-major), else 1.
+// A and B are row-major K x (>= M / N) with lda/ldb.  part is double for FP64,
+// float otherwise.  The launcher picks the number of splits (<= max_splits).
+hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long ldb, int M, int N,
+                          int K, const double* rw, int rmod, bool sym, void* part, int max_splits,
                           int* splits_out, hipStream_t st);
 // out[m*so_m + n*so_n] = c_prev*out + alpha * sum_s part[s][m*N+n]  (double out);
 // with sym the lower triangle is mirrored from the upper.
-hipError_t reduce_splitk(Prec p, const void* part, int splits, int M, int N, bool sym,
+hipError_t reduce_splitk(int mode, const void* part, int splits, int M, int N, bool sym,
                          double* out, long so_m, long so_n, double alpha, double c_prev,
                          hipStream_t st);
 
@@ -58,15 +48,6 @@ hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha
 hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long ldz,
                       hipStream_t st);
 
-// tanh rows (forward Laplacian activation rule): pre (compute type, ldp) ->
-// z (storage type, ldz) with the bias column at h and zeros beyond.
-hipError_t act_fwd(Prec p, const void* pre, long ldp, void* z, long ldz, int npts, int S, int nd,
-                   int has_lap, const uint8_t* mask, int h, hipStream_t st);
-// Adjoint of the tanh rows: zbar (compute type, ldzb) and pre -> g (storage, ldg).
-hipError_t act_bwd(Prec p, const void* zbar, long ldzb, const void* pre, long ldp, void* g,
-                   long ldg, int npts, int S, int nd, int has_lap, const uint8_t* mask, int h,
-                   hipStream_t st);
-
 // Residual, loss partials and the output seed.  pre: last layer output rows
 // (compute type, ldp); y: targets (real); r: residual per point (double);
 // g: seed rows (storage type, ldg; nullptr = not written); partial: per-block
@@ -90,6 +71,9 @@ hipError_t input_vjp(Prec p, const void* theta, int h_out, int d, const void* g1
                      int npts, int S, void* x_bar, hipStream_t st);
 
 // ---- optimizer --------------------------------------------------------------
+// out = theta + alpha * dir (line-search trial parameters)
+hipError_t axpy_theta(Prec p, const void* theta, const void* dir, double alpha, void* out, long D,
+                      hipStream_t st);
 hipError_t ema_fill(double* a, long n, int dim, int identity, hipStream_t st);
 // dhat = mu*delta + Delta  (real dhat, real delta, double Delta); use_mom = 0 -> dhat = Delta
 hipError_t momentum(Prec p, const double* Delta, const void* delta, double mu, const int* step,
@@ -122,6 +106,7 @@ struct EigProblem {
   double* C[2];       // n_pad^2 ping-pong: whitened F2 during Jacobi
   double* P[2];       // n_pad^2 ping-pong: accumulated transform
   double* V;          // (n_pad/64) * 64*64: pair rotations of one round
+  int* pflag;         // n_pad/64 + 1 ints: pair is identity this round; last = rotation flag
   double* Pout;       // n x n result P (row-major)
   double* eout;       // n eigenvalues
 };

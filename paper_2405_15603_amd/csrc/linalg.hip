@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_whiten(const EigProblem* __restrict__ p
       out[(long)(bi * BB + ty * 4 + a) * np + bj * BB + tx * 4 + b] = acc[a][b];
 }
 
-// C0 <- (C0 + C0^T)/2, P0 <- Li^T, flags reset
+// C <- (C + C^T)/2, P <- Li^T, flags reset
 __global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done) {
   const EigProblem p = pr[blockIdx.y];
   const long np = p.n_pad;
@@ -277,42 +277,37 @@ __global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     done[2 * blockIdx.y] = 0;
     done[2 * blockIdx.y + 1] = 0;
+    p.pflag[p.n_pad / 64] = 0;   // rotation flag of the sweep
   }
 }
 
 // ---------------------------------------------------------------------------
-// 4. Block Jacobi
+// 4. Block Jacobi (in place).  Blocks of 32; a round pairs the nblk blocks by
+// the round-robin (circle) schedule, so a sweep of nblk-1 rounds meets every
+// block pair once.  A rotation (p, q) is applied only when
+// |c_pq| > tol * sqrt(c_pp c_qq) (C is positive definite); a sweep without any
+// such rotation ends the iteration.
 // ---------------------------------------------------------------------------
-// round-robin position of slot k in round r among m players (player 0 fixed)
 __device__ __forceinline__ int rr_pos(int k, int r, int m) {
   return k == 0 ? 0 : 1 + ((k - 1 + r) % (m - 1));
 }
-// blocks (x, y), x < y, of pair i in round r with nblk blocks
 __device__ __forceinline__ void pair_blocks(int i, int r, int nblk, int& x, int& y) {
   int a = rr_pos(i, r, nblk), b = rr_pos(nblk - 1 - i, r, nblk);
   x = a < b ? a : b;
   y = a < b ? b : a;
 }
 
-__device__ __forceinline__ bool jac_active(const EigProblem& p, const int* done, int q, int sweep,
-                                           int r, int& src) {
-  const int nblk = p.n_pad / JB;
-  if (done[2 * q] || r >= nblk - 1) return false;
-  src = (int)(((long)sweep * (nblk - 1) + r) & 1);
-  return true;
-}
-
 constexpr int JS = 2 * JB;      // subproblem size
 constexpr int LDJ = JS + 1;
+constexpr double kJacTol = 1e-14;
 
 __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict__ pr,
-                                                   const int* __restrict__ done, int sweep, int r,
+                                                   const int* __restrict__ done, int r,
                                                    int inner) {
   const int q = blockIdx.y;
   const EigProblem p = pr[q];
-  int src;
-  if (!jac_active(p, done, q, sweep, r, src)) return;
   const int nblk = p.n_pad / JB;
+  if (done[2 * q] || r >= nblk - 1) return;
   const int i = blockIdx.x;
   if (i >= nblk / 2) return;
   int bx, by;
@@ -321,8 +316,10 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
   __shared__ double V[JS * LDJ];
   __shared__ double cs[JB], sn[JB];
   __shared__ int pp[JB], qq[JB];
+  __shared__ int any;
   const long np = p.n_pad;
-  const double* C = p.C[src];
+  const double* C = p.C[0];
+  if (threadIdx.x == 0) any = 0;
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
     const int a = e / JS, b = e % JS;
     const int ga = (a < JB ? bx * JB + a : by * JB + a - JB);
@@ -331,16 +328,26 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
     V[a * LDJ + b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
+  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+    const int a = e / JS, b = e % JS;
+    if (a < b && fabs(S[a * LDJ + b]) > kJacTol * sqrt(fabs(S[a * LDJ + a] * S[b * LDJ + b])))
+      any = 1;
+  }
+  __syncthreads();
+  if (!any) {
+    if (threadIdx.x == 0) p.pflag[i] = 1;
+    return;
+  }
   for (int sw = 0; sw < inner; sw++) {
     for (int rr = 0; rr < JS - 1; rr++) {
       if (threadIdx.x < JB) {
         const int k = threadIdx.x;
         int a = rr_pos(k, rr, JS), b = rr_pos(JS - 1 - k, rr, JS);
         if (a > b) { int t = a; a = b; b = t; }
-        const double apq = S[a * LDJ + b];
+        const double apq = S[a * LDJ + b], app = S[a * LDJ + a], aqq = S[b * LDJ + b];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double th = (S[b * LDJ + b] - S[a * LDJ + a]) / (2.0 * apq);
+        if (fabs(apq) > kJacTol * sqrt(fabs(app * aqq))) {
+          const double th = (aqq - app) / (2.0 * apq);
           const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           s = t * c;
@@ -348,26 +355,25 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
         cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
       }
       __syncthreads();
-      // rows: S <- J^T S
-      for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
-        const int k = e / JS, col = e % JS;
-        const int a = pp[k], b = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double xa = S[a * LDJ + col], xb = S[b * LDJ + col];
-        S[a * LDJ + col] = c * xa - s * xb;
-        S[b * LDJ + col] = s * xa + c * xb;
+      // S <- J^T S J on 2x2 groups (rows of pair kx, columns of pair ky), V <- V J
+      for (int e = threadIdx.x; e < JB * JB; e += blockDim.x) {
+        const int kx = e / JB, ky = e % JB;
+        const int a = pp[kx], b = qq[kx], f = pp[ky], g = qq[ky];
+        const double c1 = cs[kx], s1 = sn[kx], c2 = cs[ky], s2 = sn[ky];
+        const double saf = S[a * LDJ + f], sag = S[a * LDJ + g];
+        const double sbf = S[b * LDJ + f], sbg = S[b * LDJ + g];
+        const double raf = c1 * saf - s1 * sbf, rag = c1 * sag - s1 * sbg;
+        const double rbf = s1 * saf + c1 * sbf, rbg = s1 * sag + c1 * sbg;
+        S[a * LDJ + f] = c2 * raf - s2 * rag;
+        S[a * LDJ + g] = s2 * raf + c2 * rag;
+        S[b * LDJ + f] = c2 * rbf - s2 * rbg;
+        S[b * LDJ + g] = s2 * rbf + c2 * rbg;
       }
-      __syncthreads();
-      // columns: S <- S J, V <- V J
       for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
         const int k = e / JS, row = e % JS;
         const int a = pp[k], b = qq[k];
         const double c = cs[k], s = sn[k];
-        double xa = S[row * LDJ + a], xb = S[row * LDJ + b];
-        S[row * LDJ + a] = c * xa - s * xb;
-        S[row * LDJ + b] = s * xa + c * xb;
-        xa = V[row * LDJ + a];
-        xb = V[row * LDJ + b];
+        const double xa = V[row * LDJ + a], xb = V[row * LDJ + b];
         V[row * LDJ + a] = c * xa - s * xb;
         V[row * LDJ + b] = s * xa + c * xb;
       }
@@ -376,150 +382,131 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
   }
   double* Vo = p.V + (long)i * JS * JS;
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) Vo[e] = V[(e / JS) * LDJ + (e % JS)];
+  if (threadIdx.x == 0) {
+    p.pflag[i] = 0;
+    atomicOr(&p.pflag[p.n_pad / 64], 1);
+  }
 }
 
-// pair index and half of block X in round r
-__device__ __forceinline__ void block_pair(int X, int r, int nblk, int& pi, int& half, int& x0,
-                                           int& x1) {
+// pair index of block X in round r
+__device__ __forceinline__ int block_pair_index(int X, int r, int nblk) {
   for (int i = 0; i < nblk / 2; i++) {
     int a, b;
     pair_blocks(i, r, nblk, a, b);
-    if (a == X || b == X) {
-      pi = i; half = (X == a) ? 0 : 1; x0 = a; x1 = b;
-      return;
-    }
+    if (a == X || b == X) return i;
   }
-  pi = 0; half = 0; x0 = X; x1 = X;
+  return 0;
 }
 
-// new C[X][Y] = Vx[:, hx]^T [C(x*, y*)] Vy[:, hy]  (upper blocks, mirrored)
-// new P[R][Y] = [P(R, y0) P(R, y1)] Vy[:, hy]
+__device__ __forceinline__ long grow(int a, int b0, int b1) {
+  return a < JB ? (long)b0 * JB + a : (long)b1 * JB + a - JB;
+}
+
+// In place: C region (pair X rows, pair Y cols) <- V_X^T C V_Y for pX <= pY
+// (mirrored), then P[R rows, pair Y cols] <- P V_Y.  Identity pairs are skipped.
 __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict__ pr,
-                                                   const int* __restrict__ done, int sweep,
-                                                   int r) {
+                                                   const int* __restrict__ done, int r) {
   const int q = blockIdx.y;
   const EigProblem p = pr[q];
-  int src;
-  if (!jac_active(p, done, q, sweep, r, src)) return;
   const int nblk = p.n_pad / JB;
-  const int ncb = nblk * (nblk + 1) / 2;
+  if (done[2 * q] || r >= nblk - 1) return;
+  const int npair = nblk / 2;
+  const int ncg = npair * (npair + 1) / 2;
   int w = blockIdx.x;
-  if (w >= ncb + nblk * nblk) return;
+  if (w >= ncg + npair * npair) return;
   const long np = p.n_pad;
-  __shared__ double G[JS * LDJ];
-  __shared__ double Vy[JS * (JB + 1)];
-  __shared__ double Vx[JS * (JB + 1)];
-  __shared__ double T[JS * (JB + 1)];
-  const int tid = threadIdx.x;
-  const double* Cs = p.C[src];
-  double* Cd = p.C[src ^ 1];
-  if (w < ncb) {
-    int X = 0, rowlen = nblk;
-    while (w >= rowlen) { w -= rowlen; X++; rowlen--; }
-    const int Y = X + w;
-    int px, hx, x0, x1, py, hy, y0, y1;
-    block_pair(X, r, nblk, px, hx, x0, x1);
-    block_pair(Y, r, nblk, py, hy, y0, y1);
-    const double* VX = p.V + (long)px * JS * JS;
-    const double* VY = p.V + (long)py * JS * JS;
-    for (int e = tid; e < JS * JS; e += blockDim.x) {
-      const int a = e / JS, b = e % JS;
-      const int ga = a < JB ? x0 * JB + a : x1 * JB + a - JB;
-      const int gb = b < JB ? y0 * JB + b : y1 * JB + b - JB;
-      G[a * LDJ + b] = Cs[(long)ga * np + gb];
-    }
-    for (int e = tid; e < JS * JB; e += blockDim.x) {
-      const int a = e / JB, b = e % JB;
-      Vy[a * (JB + 1) + b] = VY[a * JS + hy * JB + b];
-      Vx[a * (JB + 1) + b] = VX[a * JS + hx * JB + b];
+  __shared__ double G[BB * LDB];
+  __shared__ double VX[BB * LDB];
+  __shared__ double VY[BB * LDB];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double acc[4][4];
+  if (w < ncg) {
+    int pX = 0, rowlen = npair;
+    while (w >= rowlen) { w -= rowlen; pX++; rowlen--; }
+    const int pY = pX + w;
+    const bool ix = p.pflag[pX] != 0, iy = p.pflag[pY] != 0;
+    if (ix && iy) return;
+    int x0, x1, y0, y1;
+    pair_blocks(pX, r, nblk, x0, x1);
+    pair_blocks(pY, r, nblk, y0, y1);
+    double* C = p.C[0];
+    for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
+      const int a = e / BB, b = e % BB;
+      G[a * LDB + b] = C[grow(a, x0, x1) * np + grow(b, y0, y1)];
+      if (!ix) VX[a * LDB + b] = p.V[(long)pX * BB * BB + e];
+      if (!iy) VY[a * LDB + b] = p.V[(long)pY * BB * BB + e];
     }
     __syncthreads();
-    // T = G Vy   (64 x 32): 8 outputs per thread
-    for (int e = tid; e < JS * JB; e += blockDim.x) {
-      const int a = e / JB, b = e % JB;
-      double s = 0.0;
-      for (int k = 0; k < JS; k++) s += G[a * LDJ + k] * Vy[k * (JB + 1) + b];
-      T[a * (JB + 1) + b] = s;
+    if (!iy) {
+      zero4(acc);
+      blk_mm<false, false>(acc, G, VY);
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) G[(ty * 4 + a) * LDB + tx * 4 + b] = acc[a][b];
+      __syncthreads();
     }
-    __syncthreads();
-    // out = Vx^T T (32 x 32)
-    for (int e = tid; e < JB * JB; e += blockDim.x) {
-      const int a = e / JB, b = e % JB;
-      double s = 0.0;
-      for (int k = 0; k < JS; k++) s += Vx[k * (JB + 1) + a] * T[k * (JB + 1) + b];
-      Cd[(long)(X * JB + a) * np + Y * JB + b] = s;
-      if (X != Y) Cd[(long)(Y * JB + b) * np + X * JB + a] = s;
+    if (!ix) {
+      zero4(acc);
+      blk_mm<true, false>(acc, VX, G);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = G[(ty * 4 + a) * LDB + tx * 4 + b];
     }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const long gr = grow(ty * 4 + a, x0, x1), gc = grow(tx * 4 + b, y0, y1);
+        C[gr * np + gc] = acc[a][b];
+        if (pX != pY) C[gc * np + gr] = acc[a][b];
+      }
   } else {
-    w -= ncb;
-    const int R = w / nblk, Y = w % nblk;
-    int py, hy, y0, y1;
-    block_pair(Y, r, nblk, py, hy, y0, y1);
-    const double* VY = p.V + (long)py * JS * JS;
-    const double* Ps = p.P[src];
-    double* Pd = p.P[src ^ 1];
-    for (int e = tid; e < JB * JS; e += blockDim.x) {
-      const int a = e / JS, b = e % JS;
-      const int gb = b < JB ? y0 * JB + b : y1 * JB + b - JB;
-      G[a * LDJ + b] = Ps[(long)(R * JB + a) * np + gb];
-    }
-    for (int e = tid; e < JS * JB; e += blockDim.x) {
-      const int a = e / JB, b = e % JB;
-      Vy[a * (JB + 1) + b] = VY[a * JS + hy * JB + b];
+    w -= ncg;
+    const int R = w / npair, pY = w % npair;
+    if (p.pflag[pY]) return;
+    int y0, y1;
+    pair_blocks(pY, r, nblk, y0, y1);
+    double* P = p.P[0];
+    for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
+      const int a = e / BB, b = e % BB;
+      G[a * LDB + b] = P[((long)R * BB + a) * np + grow(b, y0, y1)];
+      VY[a * LDB + b] = p.V[(long)pY * BB * BB + e];
     }
     __syncthreads();
-    for (int e = tid; e < JB * JB; e += blockDim.x) {
-      const int a = e / JB, b = e % JB;
-      double s = 0.0;
-      for (int k = 0; k < JS; k++) s += G[a * LDJ + k] * Vy[k * (JB + 1) + b];
-      Pd[(long)(R * JB + a) * np + Y * JB + b] = s;
-    }
+    zero4(acc);
+    blk_mm<false, false>(acc, G, VY);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+        P[((long)R * BB + ty * 4 + a) * np + grow(tx * 4 + b, y0, y1)] = acc[a][b];
   }
 }
 
-// After a sweep: converged when off(C)^2 <= tol^2 * sum diag(C)^2 (or exact
-// diagonal).  Records the buffer that holds the result.
-__global__ __launch_bounds__(1024) void k_jac_check(const EigProblem* __restrict__ pr, int* done,
-                                                    int sweep, double tol) {
-  const int q = blockIdx.x;
+// After a sweep: converged when no rotation exceeded the threshold.
+__global__ void k_jac_check(const EigProblem* __restrict__ pr, int* done, int nprob) {
+  const int q = threadIdx.x;
+  if (q >= nprob) return;
   const EigProblem p = pr[q];
   if (done[2 * q]) return;
-  const int nblk = p.n_pad / JB;
-  const int cur = (int)(((long)(sweep + 1) * (nblk - 1)) & 1);
-  const double* C = p.C[cur];
-  const long np = p.n_pad;
-  double off = 0.0, dia = 0.0;
-  for (long e = threadIdx.x; e < np * np; e += blockDim.x) {
-    const double v = C[e];
-    if (e / np == e % np) dia += v * v;
-    else off += v * v;
-  }
-  __shared__ double r1[16], r2[16];
-  off = warp_sum(off);
-  dia = warp_sum(dia);
-  if ((threadIdx.x & 63) == 0) { r1[threadIdx.x >> 6] = off; r2[threadIdx.x >> 6] = dia; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double o = 0.0, d = 0.0;
-    for (int i = 0; i < (int)(blockDim.x / 64); i++) { o += r1[i]; d += r2[i]; }
-    if (o <= tol * tol * d || !(o == o)) {
-      done[2 * q] = 1;
-      done[2 * q + 1] = cur;
-    } else {
-      done[2 * q + 1] = cur;
-    }
-  }
+  int* rot = &p.pflag[p.n_pad / 64];
+  if (*rot == 0) done[2 * q] = 1;
+  done[2 * q + 1] += 1;   // sweeps used
+  *rot = 0;
 }
 
-__global__ void k_jac_extract(const EigProblem* __restrict__ pr, const int* __restrict__ done) {
+__global__ void k_jac_extract(const EigProblem* __restrict__ pr) {
   const EigProblem p = pr[blockIdx.y];
-  const int cur = done[2 * blockIdx.y + 1];
   const long np = p.n_pad;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (long)p.n * p.n;
        e += (long)gridDim.x * blockDim.x) {
     const int i = (int)(e / p.n), j = (int)(e % p.n);
-    p.Pout[e] = p.P[cur][(long)i * np + j];
-    if (i == j) p.eout[i] = p.C[cur][(long)i * np + i];
+    p.Pout[e] = p.P[0][(long)i * np + j];
+    if (i == j) p.eout[i] = p.C[0][(long)i * np + i];
   }
 }
 
@@ -546,15 +533,16 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
   k_whiten<<<dim3(nbmax, nbmax, nprob), 256, 0, st>>>(probs_dev, 1);
   k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done);
   const int nblk = npmax / JB;
-  const int ncb = nblk * (nblk + 1) / 2 + nblk * nblk;
+  const int npair = nblk / 2;
+  const int nwg = npair * (npair + 1) / 2 + npair * npair;
   for (int sw = 0; sw < max_sweeps; sw++) {
     for (int r = 0; r < nblk - 1; r++) {
-      k_jac_solve<<<dim3(nblk / 2, nprob), 256, 0, st>>>(probs_dev, done, sw, r, 1);
-      k_jac_apply<<<dim3(ncb, nprob), 256, 0, st>>>(probs_dev, done, sw, r);
+      k_jac_solve<<<dim3(npair, nprob), 256, 0, st>>>(probs_dev, done, r, 1);
+      k_jac_apply<<<dim3(nwg, nprob), 256, 0, st>>>(probs_dev, done, r);
     }
-    k_jac_check<<<nprob, 1024, 0, st>>>(probs_dev, done, sw, 1e-15);
+    k_jac_check<<<1, 64, 0, st>>>(probs_dev, done, nprob);
   }
-  k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev, done);
+  k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev);
   return hipGetLastError();
 }
 
