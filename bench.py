@@ -60,8 +60,10 @@ def run_gpu(problem, precision, steps, warmup, kernel_class=None):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     tm = kp.timing_read() if kernel_class is not None else None
+    sweeps = kp.get_sweeps()
     status = kp.sync()
     last = KfacPinn.decode_info(info)
+    last["jacobi_sweeps"] = sweeps
     del kp
     return ms, tm, status, last
 

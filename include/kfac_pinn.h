@@ -226,6 +226,10 @@ kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* ctx, const void* dev_in, int64_t
 kp_status kfac_pinn_timing_enable(kfac_pinn_ctx* ctx, int32_t kernel_class);
 kp_status kfac_pinn_timing_read(kfac_pinn_ctx* ctx, double* out4);
 
+/* Jacobi sweeps used by each of the 2L eigenproblems (layer l: 2l side A, 2l+1
+   side B) in the last inversion; waits for the stream.  out: host, 2L ints. */
+kp_status kfac_pinn_get_sweeps(kfac_pinn_ctx* ctx, int32_t* out);
+
 /* Waits for the context's stream; returns the device status word (and clears it). */
 kp_status kfac_pinn_sync(kfac_pinn_ctx* ctx);
 const char* kfac_pinn_status_string(kp_status status);

@@ -216,6 +216,11 @@ class KfacPinn:
         N.check(self.lib.kfac_pinn_timing_read(self.h, out), "kfac_pinn_timing_read")
         return {"launches": int(out[0]), "ms": out[1], "flops": out[2], "bytes": out[3]}
 
+    def get_sweeps(self) -> list:
+        out = (C.c_int32 * (2 * self.L))()
+        N.check(self.lib.kfac_pinn_get_sweeps(self.h, out), "kfac_pinn_get_sweeps")
+        return list(out)
+
     def sync(self) -> int:
         """Waits for the stream; returns (and clears) the device status word."""
         return int(self.lib.kfac_pinn_sync(self.h))

@@ -657,6 +657,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
       ALLOC(p.P[1], np2);
       ALLOC(p.V, (size_t)(p.n_pad / 64) * 64 * 64 * sizeof(double));
       ALLOC(p.pflag, (size_t)(p.n_pad / 64 + 1) * sizeof(int));
+      ALLOC(p.dmax, sizeof(double));
       ALLOC(p.Pout, (size_t)p.n * p.n * sizeof(double));
       ALLOC(p.eout, (size_t)p.n * sizeof(double));
       c->probs.push_back(p);
@@ -994,6 +995,16 @@ kp_status kfac_pinn_timing_read(kfac_pinn_ctx* c, double* out) {
   c->tm_used = 0;
   c->tm_flops = c->tm_bytes = 0.0;
   c->tm_launches = 0;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_get_sweeps(kfac_pinn_ctx* c, int32_t* out) {
+  KP_ARG(c && out, "null argument");
+  KP_TRY(hipStreamSynchronize(c->st));
+  const int np = (int)c->probs.size();
+  std::vector<int> flags(2 * np);
+  KP_TRY(hipMemcpy(flags.data(), c->ctl + 8, sizeof(int) * 2 * np, hipMemcpyDeviceToHost));
+  for (int q = 0; q < np; q++) out[q] = flags[2 * q + 1];
   return KP_OK;
 }
 

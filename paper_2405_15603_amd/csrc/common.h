@@ -8,6 +8,7 @@ namespace kp {
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -78,8 +79,22 @@ template <> struct Mfma<double> {
   }
 };
 
-// 16-byte vector of a storage type
-template <typename T> struct Vec16 { static constexpr int N = 16 / sizeof(T); };
+// 16-byte vector (native clang vector type, so it stays in registers)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Global-memory views of generic pointers (lets the compiler emit global_load /
+// global_store instead of flat accesses).
+#define KP_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const KP_GLOBAL T* gmem(const T* p) {
+  return (const KP_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ KP_GLOBAL T* gmem(T* p) {
+  return (KP_GLOBAL T*)p;
+}
+__device__ __forceinline__ u32x4 ld16(const void* p) { return *gmem((const u32x4*)p); }
 
 __device__ __forceinline__ double warp_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -37,14 +37,14 @@ template <> struct Op<M_F32> {
   typedef float TB;
   typedef float TL;
   typedef float TC;
-  static constexpr int NA = 1, NB = 1, BK = 16, PAD = 4, VA = 4;
+  static constexpr int NA = 1, NB = 1, BK = 32, PAD = 4, VA = 4;
 };
 template <> struct Op<M_BF16> {
   typedef bf16 TA;
   typedef bf16 TB;
   typedef bf16 TL;
   typedef float TC;
-  static constexpr int NA = 1, NB = 1, BK = 32, PAD = 8, VA = 8;
+  static constexpr int NA = 1, NB = 1, BK = 128, PAD = 8, VA = 8;
 };
 template <> struct Op<M_BF16X3> {
   typedef float TA;
@@ -77,89 +77,106 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
-// Tile geometry: 4 waves as 2 x 2; wave tile WP points x WN neurons.
-template <int MODE> struct Geo {
-  static constexpr int WP = 32, WN = MODE == M_F64 ? 32 : 64;
-  static constexpr int BP = 2 * WP, BN = 2 * WN;
+// Tile geometry: 8 waves as 4 (points) x 2 (neurons); wave tile WP x WN.  The
+// backward kernel keeps three per-output values across s, so it uses the
+// narrower wave tile (NARROW) to stay within registers.
+constexpr int kThreads = 512;
+template <int MODE, bool NARROW = false> struct Geo {
+  static constexpr int WP = 32, WN = (MODE == M_F64 || NARROW) ? 32 : 64;
+  static constexpr int BP = 4 * WP, BN = 2 * WN;
   static constexpr int TI = WP / 16, TJ = WN / 16;
 };
 
-// One s: acc[TI][TJ] = A_s[p0:p0+BP, :K] * B[c0:c0+BN, :K]^T with LDS double
-// buffering.  A rows are arow0 + p (p < N), B rows c (c < ncols).
-template <int MODE>
+template <int MODE, bool NARROW = false>
 struct Mainloop {
   typedef Op<MODE> O;
-  typedef Geo<MODE> G;
+  typedef Geo<MODE, NARROW> G;
   typedef typename O::TL TL;
   static constexpr int BK = O::BK, LDK = O::BK + O::PAD;
   static constexpr int VA = O::VA;                  // A elements per 16-byte load
   static constexpr int VB = 16 / sizeof(typename O::TB);
-  static constexpr int AV = G::BP * (BK / VA) / 256;  // A vectors per thread
-  static constexpr int BV = G::BN * (BK / VB) / 256;
+  static constexpr int ANV = G::BP * (BK / VA), BNV = G::BN * (BK / VB);  // 16-byte vectors
+  static constexpr int AV = (ANV + kThreads - 1) / kThreads;   // per thread (last may idle)
+  static constexpr int BV = (BNV + kThreads - 1) / kThreads;
   struct Smem {
     TL a[2][O::NA][G::BP * LDK];
     TL b[2][O::NB][G::BN * LDK];
   };
 };
 
-template <int MODE>
-__device__ __forceinline__ void tile_product(
-    typename Mainloop<MODE>::Smem& sm, const typename Op<MODE>::TA* __restrict__ A, long lda,
-    long arow0, int p0, int N, const typename Op<MODE>::TB* __restrict__ B,
-    const typename Op<MODE>::TB* __restrict__ B2, long ldb, int c0, int ncols, int K,
-    typename Mfma<typename Op<MODE>::TL>::acc acc[Geo<MODE>::TI][Geo<MODE>::TJ]) {
-  typedef Mainloop<MODE> ML;
+// Software-pipelined walk over nsteps shared columns s (s = s_of(step)), each a
+// product  A_s[p0:p0+BP, :K] * B[c0:c0+BN, :K]^T  accumulated in acc; the
+// epilogue epi(step, s) runs when a column's product is complete.  The global
+// loads of the next k-tile (also across columns) are in flight while the
+// current one is multiplied; one barrier per k-tile.
+template <int MODE, bool NARROW, class SOf, class Epi>
+__device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
+                                      const typename Op<MODE>::TA* __restrict__ A, long lda,
+                                      int N, int p0, const typename Op<MODE>::TB* __restrict__ B,
+                                      const typename Op<MODE>::TB* __restrict__ B2, long ldb,
+                                      int c0, int ncols, int K, int nsteps, SOf s_of, Epi epi) {
+  typedef Mainloop<MODE, NARROW> ML;
   typedef Op<MODE> O;
-  typedef Geo<MODE> G;
+  typedef Geo<MODE, NARROW> G;
   typedef typename O::TL TL;
   typedef Mfma<TL> MF;
   constexpr int BK = ML::BK, LDK = ML::LDK, VA = ML::VA, VB = ML::VB;
+  constexpr int AV = ML::AV, BV = ML::BV, NB = O::NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wp = wave >> 1, wn = wave & 1;
-  v16 ra[ML::AV], rb[O::NB][ML::BV];
-  const v16 z16 = {0u, 0u, 0u, 0u};
-  auto gload = [&](int k0) {
+  // per-thread load coordinates (fixed for the whole loop)
+  int ar[AV], ak[AV], br[BV], bk[BV];
 #pragma unroll
-    for (int i = 0; i < ML::AV; i++) {
-      const int v = tid + i * 256, r = v / (BK / VA), kv = (v % (BK / VA)) * VA;
-      const int p = p0 + r, k = k0 + kv;
-      ra[i] = (p < N && k < K) ? *(const v16*)(A + (arow0 + p) * lda + k) : z16;
-    }
+  for (int i = 0; i < AV; i++) {
+    const int v = tid + i * kThreads;
+    ar[i] = v < ML::ANV ? v / (BK / VA) : 1 << 20;
+    ak[i] = (v % (BK / VA)) * VA;
+  }
 #pragma unroll
-    for (int i = 0; i < ML::BV; i++) {
-      const int v = tid + i * 256, r = v / (BK / VB), kv = (v % (BK / VB)) * VB;
-      const int c = c0 + r, k = k0 + kv;
-      const bool ok = c < ncols && k < K;
-      rb[0][i] = ok ? *(const v16*)(B + (long)c * ldb + k) : z16;
-      if (O::NB == 2) rb[O::NB - 1][i] = ok ? *(const v16*)(B2 + (long)c * ldb + k) : z16;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < ML::AV; i++) {
-      const int v = tid + i * 256, r = v / (BK / VA), kv = (v % (BK / VA)) * VA;
-      if (MODE == M_BF16X3) {
-        // FP32 -> BF16 hi + lo
-        const float* f = (const float*)&ra[i];
-        __attribute__((aligned(8))) bf16 hi[4], lo[4];
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-          hi[e] = (bf16)f[e];
-          lo[e] = (bf16)(f[e] - (float)hi[e]);
-        }
-        *(uint2*)(&sm.a[buf][0][r * LDK + kv]) = *(const uint2*)hi;
-        *(uint2*)(&sm.a[buf][O::NA - 1][r * LDK + kv]) = *(const uint2*)lo;
-      } else {
-        *(v16*)(&sm.a[buf][0][r * LDK + kv]) = ra[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < ML::BV; i++) {
-      const int v = tid + i * 256, r = v / (BK / VB), kv = (v % (BK / VB)) * VB;
-#pragma unroll
-      for (int h = 0; h < O::NB; h++) *(v16*)(&sm.b[buf][h][r * LDK + kv]) = rb[h][i];
-    }
-  };
+  for (int i = 0; i < BV; i++) {
+    const int v = tid + i * kThreads;
+    br[i] = v < ML::BNV ? v / (BK / VB) : 1 << 20;   // out-of-tile: never loaded or stored
+    bk[i] = (v % (BK / VB)) * VB;
+  }
+  u32x4 ra[AV], rb[NB][BV];
+  const u32x4 z16 = {0u, 0u, 0u, 0u};
+
+#define KP_GLOAD(AROW0, K0)                                                           \
+  {                                                                                   \
+    _Pragma("unroll") for (int i = 0; i < AV; i++) {                                  \
+      const int p = p0 + ar[i], k = (K0) + ak[i];                                     \
+      ra[i] = (p < N && k < K) ? ld16(A + ((AROW0) + p) * lda + k) : z16;             \
+    }                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < BV; i++) {                                  \
+      const int c = c0 + br[i], k = (K0) + bk[i];                                     \
+      const bool ok = c < ncols && k < K;                                             \
+      rb[0][i] = ok ? ld16(B + (long)c * ldb + k) : z16;                              \
+      if constexpr (NB == 2) rb[NB - 1][i] = ok ? ld16(B2 + (long)c * ldb + k) : z16; \
+    }                                                                                 \
+  }
+#define KP_SSTORE(BUF)                                                                \
+  {                                                                                   \
+    _Pragma("unroll") for (int i = 0; i < AV; i++) {                                  \
+      if (ar[i] >= G::BP) continue;                                                   \
+      if constexpr (MODE == M_BF16X3) {                                               \
+        const f32x4 fv = __builtin_bit_cast(f32x4, ra[i]);                            \
+        const bf16x4 hv = __builtin_convertvector(fv, bf16x4);                        \
+        const bf16x4 lv =                                                             \
+            __builtin_convertvector(fv - __builtin_convertvector(hv, f32x4), bf16x4); \
+        *(bf16x4*)(&sm.a[BUF][0][ar[i] * LDK + ak[i]]) = hv;                          \
+        *(bf16x4*)(&sm.a[BUF][O::NA - 1][ar[i] * LDK + ak[i]]) = lv;                  \
+      } else {                                                                        \
+        *(u32x4*)(&sm.a[BUF][0][ar[i] * LDK + ak[i]]) = ra[i];                        \
+      }                                                                               \
+    }                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < BV; i++) {                                  \
+      if (br[i] >= G::BN) continue;                                                   \
+      _Pragma("unroll") for (int h = 0; h < NB; h++)                                  \
+        *(u32x4*)(&sm.b[BUF][h][br[i] * LDK + bk[i]]) = rb[h][i];                     \
+    }                                                                                 \
+  }
+
+  typename MF::acc acc[G::TI][G::TJ];
 #pragma unroll
   for (int i = 0; i < G::TI; i++)
 #pragma unroll
@@ -167,23 +184,30 @@ __device__ __forceinline__ void tile_product(
 #pragma unroll
       for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
   const int nk = (K + BK - 1) / BK;
-  gload(0);
-  __syncthreads();   // the previous s may still read buffer 0
-  sstore(0);
+  const int total = nsteps * nk;
+  if (total <= 0) return;
+  KP_GLOAD((long)s_of(0) * N, 0);
+  KP_SSTORE(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; kt++) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+  int st = 0, kt = 0;
+  for (int g = 0; g < total; g++) {
+    const int cur = g & 1;
+    const bool more = g + 1 < total;
+    if (more) {
+      const int nkt = kt + 1 == nk ? 0 : kt + 1;
+      const int nst = kt + 1 == nk ? st + 1 : st;
+      KP_GLOAD((long)s_of(nst) * N, nkt * BK);
+    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += MF::K) {
-      typename MF::frag a[O::NA][G::TI], b[O::NB][G::TJ];
+      typename MF::frag a[O::NA][G::TI], b[NB][G::TJ];
 #pragma unroll
       for (int h = 0; h < O::NA; h++)
 #pragma unroll
         for (int i = 0; i < G::TI; i++)
           a[h][i] = frag_ld<TL>(&sm.a[cur][h][(wp * G::WP + i * 16) * LDK], lane, LDK, kk);
 #pragma unroll
-      for (int h = 0; h < O::NB; h++)
+      for (int h = 0; h < NB; h++)
 #pragma unroll
         for (int j = 0; j < G::TJ; j++)
           b[h][j] = frag_ld<TL>(&sm.b[cur][h][(wn * G::WN + j * 16) * LDK], lane, LDK, kk);
@@ -192,15 +216,30 @@ __device__ __forceinline__ void tile_product(
 #pragma unroll
         for (int j = 0; j < G::TJ; j++) {
           acc[i][j] = MF::mma(a[0][i], b[0][j], acc[i][j]);
-          if (MODE == M_BF16X3) {
+          if constexpr (MODE == M_BF16X3) {
             acc[i][j] = MF::mma(a[O::NA - 1][i], b[0][j], acc[i][j]);
-            acc[i][j] = MF::mma(a[0][i], b[O::NB - 1][j], acc[i][j]);
+            acc[i][j] = MF::mma(a[0][i], b[NB - 1][j], acc[i][j]);
           }
         }
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+    if (kt + 1 == nk) {
+      epi(st, s_of(st), acc);
+#pragma unroll
+      for (int i = 0; i < G::TI; i++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+          for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+      kt = 0;
+      st++;
+    } else {
+      kt++;
+    }
+    if (more) KP_SSTORE(cur ^ 1);
     __syncthreads();
   }
+#undef KP_GLOAD
+#undef KP_SSTORE
 }
 
 // ---------------------------------------------------------------------------
@@ -210,7 +249,7 @@ __device__ __forceinline__ void tile_product(
 // next slab, optional pre-activations, and the tables for the finishing pass.
 // ---------------------------------------------------------------------------
 template <int MODE, typename TZ>
-__global__ __launch_bounds__(256) void k_fwdlap(FwdLayerArgs a) {
+__global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
   typedef Op<MODE> O;
   typedef Geo<MODE> G;
   typedef typename O::TC TC;
@@ -226,23 +265,22 @@ __global__ __launch_bounds__(256) void k_fwdlap(FwdLayerArgs a) {
   const int nd = a.nd;
   const int len = (nd + nch - 1) / nch;
   const int dbeg = 1 + chunk * len, dend = min(1 + nd, dbeg + len);
+  const int nder = max(0, dend - dbeg);
   const bool lap_here = a.has_lap && chunk == nch - 1;
-  const int nsteps = 1 + max(0, dend - dbeg) + (lap_here ? 1 : 0);
+  const int nsteps = 1 + nder + (lap_here ? 1 : 0);
+  const int S = a.S;
 
   TC tv[G::TI][G::TJ][4], sq[G::TI][G::TJ][4];
-  typename MF::acc acc[G::TI][G::TJ];
 #pragma unroll
   for (int i = 0; i < G::TI; i++)
 #pragma unroll
     for (int j = 0; j < G::TJ; j++)
 #pragma unroll
-      for (int e = 0; e < 4; e++) sq[i][j][e] = 0;
+      for (int e = 0; e < 4; e++) { sq[i][j][e] = 0; tv[i][j][e] = 0; }
 
-  for (int st = 0; st < nsteps; st++) {
-    const int s = st == 0 ? 0 : (st <= dend - dbeg ? dbeg + st - 1 : a.S - 1);
-    tile_product<MODE>(sm, (const typename O::TA*)a.zin, a.ldz, (long)s * a.N, p0, a.N,
-                       (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0,
-                       a.h_out, a.K, acc);
+  // step 0: value row, steps 1..nder: derivative rows of this chunk, then the Laplacian row
+  auto s_of = [=](int st) { return st == 0 ? 0 : (st <= nder ? dbeg + st - 1 : S - 1); };
+  auto epi = [&](int st, int s, typename MF::acc (&acc)[G::TI][G::TJ]) {
     const bool is_d = s >= 1 && s <= nd;
     const TC m = (is_d && a.mask[s - 1]) ? (TC)1 : (TC)0;
 #pragma unroll
@@ -277,7 +315,9 @@ __global__ __launch_bounds__(256) void k_fwdlap(FwdLayerArgs a) {
           }
         }
       }
-  }
+  };
+  sloop<MODE, false>(sm, (const typename O::TA*)a.zin, a.ldz, a.N, p0, (const typename O::TB*)a.w,
+              (const typename O::TB*)a.w2, a.ldw, c0, a.h_out, a.K, nsteps, s_of, epi);
   if (a.has_lap) {
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
@@ -325,12 +365,12 @@ __global__ void k_fwdlap_finish(FwdLayerArgs a, int nch) {
 // Every chunk first recomputes the Laplacian row's cotangent Lbar.
 // ---------------------------------------------------------------------------
 template <int MODE, typename TG>
-__global__ __launch_bounds__(256) void k_bwdlap(BwdLayerArgs a) {
+__global__ __launch_bounds__(kThreads) void k_bwdlap(BwdLayerArgs a) {
   typedef Op<MODE> O;
-  typedef Geo<MODE> G;
+  typedef Geo<MODE, true> G;
   typedef typename O::TC TC;
   typedef Mfma<typename O::TL> MF;
-  __shared__ typename Mainloop<MODE>::Smem sm;
+  __shared__ typename Mainloop<MODE, true>::Smem sm;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wp = wave >> 1, wn = wave & 1;
   const int ntc = (a.h + G::BN - 1) / G::BN;
@@ -341,11 +381,13 @@ __global__ __launch_bounds__(256) void k_bwdlap(BwdLayerArgs a) {
   const int nd = a.nd;
   const int len = (nd + nch - 1) / nch;
   const int dbeg = 1 + chunk * len, dend = min(1 + nd, dbeg + len);
-  const int nsteps = (a.has_lap ? 1 : 0) + max(0, dend - dbeg) + (chunk == 0 ? 1 : 0);
+  const int nder = max(0, dend - dbeg);
+  const int hl = a.has_lap ? 1 : 0;
+  const int nsteps = hl + nder + (chunk == 0 ? 1 : 0);
+  const int S = a.S;
   const TC* pre = (const TC*)a.pre;
 
   TC lb[G::TI][G::TJ][4], tv[G::TI][G::TJ][4], sum1[G::TI][G::TJ][4];
-  typename MF::acc acc[G::TI][G::TJ];
 #pragma unroll
   for (int i = 0; i < G::TI; i++)
 #pragma unroll
@@ -361,17 +403,16 @@ __global__ __launch_bounds__(256) void k_bwdlap(BwdLayerArgs a) {
         sum1[i][j][e] = 0;
       }
     }
-  for (int st = 0; st < nsteps; st++) {
-    int s;
-    if (a.has_lap && st == 0) s = a.S - 1;
-    else {
-      const int k = st - (a.has_lap ? 1 : 0);
-      s = (k < dend - dbeg) ? dbeg + k : 0;
-    }
-    tile_product<MODE>(sm, (const typename O::TA*)a.gin, a.ldgi, (long)s * a.N, p0, a.N,
-                       (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0, a.h,
-                       a.K, acc);
-    const bool is_d = s >= 1 && s <= nd;
+  // the Laplacian row first (its cotangent enters every derivative row), then
+  // this chunk's derivative rows, then (chunk 0) the value row
+  auto s_of = [=](int st) {
+    if (hl && st == 0) return S - 1;
+    const int k = st - hl;
+    return k < nder ? dbeg + k : 0;
+  };
+  auto epi = [&](int st, int s, typename MF::acc (&acc)[G::TI][G::TJ]) {
+    const bool is_lap = hl && st == 0;
+    const bool is_d = !is_lap && s >= 1 && s <= nd;
     const TC m = (is_d && a.mask[s - 1]) ? (TC)1 : (TC)0;
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
@@ -386,7 +427,7 @@ __global__ __launch_bounds__(256) void k_bwdlap(BwdLayerArgs a) {
           const long row = (long)s * a.N + p;
           const TC tt = tv[i][j][e];
           const TC s1 = (TC)1 - tt * tt;
-          if (a.has_lap && s == a.S - 1) {
+          if (is_lap) {
             lb[i][j][e] = v;
             if (ok && chunk == nch - 1) {
               ((TG*)a.g)[row * a.ldgo + c] = cvt<TG>((double)(s1 * v));
@@ -401,13 +442,15 @@ __global__ __launch_bounds__(256) void k_bwdlap(BwdLayerArgs a) {
                   cvt<TG>((double)(s1 * v + (TC)2 * m * s2 * da * lb[i][j][e]));
             }
           } else if (ok) {   // value row cotangent (chunk 0)
-            if (a.has_lap) ((TC*)a.tab_zv)[(long)p * a.h + c] = v;
+            if (hl) ((TC*)a.tab_zv)[(long)p * a.h + c] = v;
             else ((TG*)a.g)[row * a.ldgo + c] = cvt<TG>((double)(s1 * v));
           }
         }
       }
-  }
-  if (a.has_lap) {
+  };
+  sloop<MODE, true>(sm, (const typename O::TA*)a.gin, a.ldgi, a.N, p0, (const typename O::TB*)a.w,
+              (const typename O::TB*)a.w2, a.ldw, c0, a.h, a.K, nsteps, s_of, epi);
+  if (hl) {
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
 #pragma unroll
@@ -522,17 +565,19 @@ static int choose_chunks(int tiles, int nd, int has_lap) {
 }
 
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
-  const int BP = 64, BN = mode == M_F64 ? 64 : 128;
+  const int BP = 128, BN = mode == M_F64 ? 64 : 128;
   const int tiles = ((N + BP - 1) / BP) * ((h_out + BN - 1) / BN);
   return choose_chunks(tiles, nd, has_lap);
 }
 int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap) {
-  return fwdlap_chunks(mode, N, h, nd, has_lap);
+  const int BP = 128, BN = 64;
+  const int tiles = ((N + BP - 1) / BP) * ((h + BN - 1) / BN);
+  return choose_chunks(tiles, nd, has_lap);
 }
 
-template <int MODE>
+template <int MODE, bool NARROW = false>
 static dim3 tile_grid(int N, int cols, int nch) {
-  typedef Geo<MODE> G;
+  typedef Geo<MODE, NARROW> G;
   return dim3(((N + G::BP - 1) / G::BP) * ((cols + G::BN - 1) / G::BN), nch);
 }
 
@@ -540,16 +585,16 @@ hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st)
   if (a.N <= 0) return hipSuccess;
   switch (mode) {
     case M_F64:
-      k_fwdlap<M_F64, double><<<tile_grid<M_F64>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      k_fwdlap<M_F64, double><<<tile_grid<M_F64>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
       break;
     case M_F32:
-      k_fwdlap<M_F32, float><<<tile_grid<M_F32>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      k_fwdlap<M_F32, float><<<tile_grid<M_F32>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
       break;
     case M_BF16:
-      k_fwdlap<M_BF16, bf16><<<tile_grid<M_BF16>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      k_fwdlap<M_BF16, bf16><<<tile_grid<M_BF16>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
       break;
     case M_BF16X3:
-      k_fwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3>(a.N, a.h_out, nch), 256, 0, st>>>(a);
+      k_fwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -574,13 +619,13 @@ hipError_t bwdlap_main(int mode, const BwdLayerArgs& a, int nch, hipStream_t st)
   if (a.N <= 0) return hipSuccess;
   switch (mode) {
     case M_F64:
-      k_bwdlap<M_F64, double><<<tile_grid<M_F64>(a.N, a.h, nch), 256, 0, st>>>(a);
+      k_bwdlap<M_F64, double><<<tile_grid<M_F64, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
       break;
     case M_F32:
-      k_bwdlap<M_F32, float><<<tile_grid<M_F32>(a.N, a.h, nch), 256, 0, st>>>(a);
+      k_bwdlap<M_F32, float><<<tile_grid<M_F32, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
       break;
     case M_BF16X3:
-      k_bwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3>(a.N, a.h, nch), 256, 0, st>>>(a);
+      k_bwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
       break;
     default:
       return hipErrorInvalidValue;

@@ -107,6 +107,7 @@ struct EigProblem {
   double* P[2];       // n_pad^2 ping-pong: accumulated transform
   double* V;          // (n_pad/64) * 64*64: pair rotations of one round
   int* pflag;         // n_pad/64 + 1 ints: pair is identity this round; last = rotation flag
+  double* dmax;       // largest diagonal entry of C (absolute rotation threshold)
   double* Pout;       // n x n result P (row-major)
   double* eout;       // n eigenvalues
 };

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_whiten(const EigProblem* __restrict__ p
       out[(long)(bi * BB + ty * 4 + a) * np + bj * BB + tx * 4 + b] = acc[a][b];
 }
 
-// C <- (C + C^T)/2, P <- Li^T, flags reset
+// C <- (C + C^T)/2, P <- Li^T, flags reset, largest diagonal entry of C
 __global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done) {
   const EigProblem p = pr[blockIdx.y];
   const long np = p.n_pad;
@@ -281,6 +281,18 @@ __global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done) {
   }
 }
 
+__global__ void k_jac_dmax(const EigProblem* __restrict__ pr) {
+  const EigProblem p = pr[blockIdx.x];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < p.n_pad; i += blockDim.x)
+    m = fmax(m, fabs(p.C[0][(long)i * p.n_pad + i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  __shared__ double r[4];
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) *p.dmax = fmax(fmax(r[0], r[1]), fmax(r[2], r[3]));
+}
+
 // ---------------------------------------------------------------------------
 // 4. Block Jacobi (in place).  Blocks of 32; a round pairs the nblk blocks by
 // the round-robin (circle) schedule, so a sweep of nblk-1 rounds meets every
@@ -299,7 +311,8 @@ __device__ __forceinline__ void pair_blocks(int i, int r, int nblk, int& x, int&
 
 constexpr int JS = 2 * JB;      // subproblem size
 constexpr int LDJ = JS + 1;
-constexpr double kJacTol = 1e-14;
+constexpr double kJacTol = 1e-14;      // relative to the pivots
+constexpr double kJacAbs = 1e-13;      // relative to the largest diagonal entry
 
 __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict__ pr,
                                                    const int* __restrict__ done, int r,
@@ -320,6 +333,7 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
   const long np = p.n_pad;
   const double* C = p.C[0];
   if (threadIdx.x == 0) any = 0;
+  const double floor_abs = kJacAbs * *p.dmax;
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
     const int a = e / JS, b = e % JS;
     const int ga = (a < JB ? bx * JB + a : by * JB + a - JB);
@@ -330,7 +344,8 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
   __syncthreads();
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
     const int a = e / JS, b = e % JS;
-    if (a < b && fabs(S[a * LDJ + b]) > kJacTol * sqrt(fabs(S[a * LDJ + a] * S[b * LDJ + b])))
+    if (a < b && fabs(S[a * LDJ + b]) >
+                     fmax(kJacTol * sqrt(fabs(S[a * LDJ + a] * S[b * LDJ + b])), floor_abs))
       any = 1;
   }
   __syncthreads();
@@ -346,7 +361,7 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
         if (a > b) { int t = a; a = b; b = t; }
         const double apq = S[a * LDJ + b], app = S[a * LDJ + a], aqq = S[b * LDJ + b];
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > kJacTol * sqrt(fabs(app * aqq))) {
+        if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) {
           const double th = (aqq - app) / (2.0 * apq);
           const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
@@ -532,6 +547,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
   k_whiten<<<dim3(nbmax, nbmax, nprob), 256, 0, st>>>(probs_dev, 0);
   k_whiten<<<dim3(nbmax, nbmax, nprob), 256, 0, st>>>(probs_dev, 1);
   k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done);
+  k_jac_dmax<<<nprob, 256, 0, st>>>(probs_dev);
   const int nblk = npmax / JB;
   const int npair = nblk / 2;
   const int nwg = npair * (npair + 1) / 2 + npair * npair;

@@ -32,17 +32,18 @@ def test_mixed_factors_within_1e_3(case):
     u, g, lap = kp.forward_laplacian(to_dev(th, "bf16"), to_dev(xi, "bf16"))
     assert kp.sync() == 0
     ref = oracle_curvature(p, th, xi, yi, xb, yb)
-    worst = 0.0
+    errs = {}
     for l in range(len(p.widths) - 1):
         for t, tn in ((0, "int"), (1, "bnd")):
             for s, sn in ((0, "A"), (1, "B")):
-                e = rel(kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l])
-                worst = max(worst, e)
-                assert e < 1e-3, (l, tn, sn, e)
+                errs[(l, tn, sn)] = rel(kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l])
+    worst = max(errs.values())
     op = oracle.operator_of(p)
     U = oracle.forward_laplacian(oracle.unpack(torch.as_tensor(th), p.widths), torch.as_tensor(xi),
                                  op.mask_vec(p.d)).out
     print(f"{case}: worst factor {worst:.2e}  lap {rel(lap, U[:, -1]):.2e}  "
           f"grad {rel(grad, ref['grad']):.2e}")
+    bad = {k: v for k, v in errs.items() if not v < 1e-3}
+    assert not bad, bad
     assert rel(lap, U[:, -1]) < 2e-2
     assert rel(grad, ref["grad"]) < 2e-2
