@@ -584,13 +584,13 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     kfac_pinn_destroy(c);                                          \
     return e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_HIP;    \
   }
-  // Laplacian mask (per input coordinate)
-  ALLOC(c->mask, (size_t)c->d);
+  // Laplacian mask (per input coordinate), padded to whole 32-bit words
+  const size_t mask_bytes = (size_t)kp_roundup(c->d, 4);
+  ALLOC(c->mask, mask_bytes);
   {
-    std::vector<uint8_t> m(c->d, 1);
-    if (pb->lap_mask)
-      for (int i = 0; i < c->d; i++) m[i] = pb->lap_mask[i] ? 1 : 0;
-    if ((e = hipMemcpy(c->mask, m.data(), c->d, hipMemcpyHostToDevice)) != hipSuccess) {
+    std::vector<uint8_t> m(mask_bytes, 0);
+    for (int i = 0; i < c->d; i++) m[i] = (!pb->lap_mask || pb->lap_mask[i]) ? 1 : 0;
+    if ((e = hipMemcpy(c->mask, m.data(), mask_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
       kfac_pinn_destroy(c);
       return KP_ERR_HIP;
     }

@@ -243,6 +243,197 @@ __device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
 }
 
 // ---------------------------------------------------------------------------
+// Direct-to-LDS variant of sloop for operands used as stored (BF16, FP32, FP64):
+// every k-tile row is 128 bytes (8 chunks of 16 B), loaded with
+// global_load_lds_dwordx4 into a ring of NST stages, NST-1 tiles in flight.  A
+// wave's load instruction fills 1 KB = 8 rows; chunk q of row r sits at chunk
+// position q ^ ((r >> 1) & 7), which makes the 16-row fragment reads
+// conflict-free.  Chunks outside the valid rows / k range are redirected to a
+// valid address: rows past N or ncols only feed discarded outputs, and chunks
+// past K read a 16-byte zero block.  K must be a multiple of 16 bytes.  The
+// accumulators hold the transposed tile: acc[i][j] = B_j A_i^T, i.e. MFMA rows
+// are neurons and MFMA columns are points.
+// ---------------------------------------------------------------------------
+constexpr int kStages = 4;
+__device__ __align__(16) u32x4 kZeroChunk = {0u, 0u, 0u, 0u};
+
+template <int MODE, bool NARROW>
+struct DmaCfg {
+  typedef Geo<MODE, NARROW> G;
+  typedef typename Op<MODE>::TL T;
+  static constexpr int E = 16 / sizeof(T);            // elements per chunk
+  static constexpr int BK = 128 / sizeof(T);          // k per tile (8 chunks)
+  static constexpr int ACH = G::BP / 8, BCH = G::BN / 8;   // 1 KB chunks per stage
+  static constexpr int NCH = ACH + BCH;
+  static constexpr int PER_WAVE = (NCH + 7) / 8;
+  static constexpr int STAGE = NCH * 1024;             // bytes
+  static_assert(NCH % 8 == 0, "every wave issues the same number of chunk loads");
+};
+template <int MODE> constexpr bool kDma = MODE == M_BF16;
+
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 7; }
+
+template <typename TL>
+__device__ __forceinline__ typename Mfma<TL>::frag frag_dma(const char* tile, int lane, int kk);
+// bf16: 8 consecutive k of row lane%16 starting at kk + 8*(lane/16)
+template <>
+__device__ __forceinline__ bf16x8 frag_dma<bf16>(const char* tile, int lane, int kk) {
+  const int r = lane & 15, c = (kk >> 3) + (lane >> 4);
+  return *(const bf16x8*)(tile + r * 128 + ((c ^ swz(r)) << 4));
+}
+template <>
+__device__ __forceinline__ float frag_dma<float>(const char* tile, int lane, int kk) {
+  const int r = lane & 15, k = kk + (lane >> 4);
+  return *(const float*)(tile + r * 128 + (((k >> 2) ^ swz(r)) << 4) + ((k & 3) << 2));
+}
+template <>
+__device__ __forceinline__ double frag_dma<double>(const char* tile, int lane, int kk) {
+  const int r = lane & 15, k = kk + (lane >> 4);
+  return *(const double*)(tile + r * 128 + (((k >> 1) ^ swz(r)) << 4) + ((k & 1) << 3));
+}
+
+template <int MODE, bool NARROW, class SOf, class Epi>
+__device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL* __restrict__ A,
+                                          long lda, int N, int p0,
+                                          const typename Op<MODE>::TL* __restrict__ B, long ldb,
+                                          int c0, int ncols, int K, int nsteps, SOf s_of,
+                                          Epi epi) {
+  typedef DmaCfg<MODE, NARROW> D;
+  typedef Geo<MODE, NARROW> G;
+  typedef typename Op<MODE>::TL TL;
+  typedef Mfma<TL> MF;
+  constexpr int E = D::E, BK = D::BK;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wp = wave >> 1, wn = wave & 1;
+  const int nk = (K + BK - 1) / BK;
+  const int total = nsteps * nk;
+  if (total <= 0) return;
+  const int rin = lane >> 3, pos = lane & 7;
+
+  // issue the loads of flattened tile g into its stage
+  auto issue = [&](int g) {
+    const int st = g / nk, kt = g - st * nk;
+    const long arow0 = (long)s_of(st) * N;
+    const int k0 = kt * BK;
+    char* stage = lds + (g % kStages) * D::STAGE;
+#pragma unroll
+    for (int j = 0; j < D::PER_WAVE; j++) {
+      const int q = wave + 8 * j;   // 1 KB chunk of the stage
+      const TL* src;
+      if (q < D::ACH) {
+        const int r = q * 8 + rin;
+        const int cg = pos ^ swz(r);
+        int p = p0 + r;
+        p = p < N ? p : N - 1;
+        const int k = k0 + cg * E;
+        src = k < K ? A + (arow0 + p) * lda + k : (const TL*)&kZeroChunk;
+      } else {
+        const int r = (q - D::ACH) * 8 + rin;
+        const int cg = pos ^ swz(r);
+        int c = c0 + r;
+        c = c < ncols ? c : ncols - 1;
+        const int k = k0 + cg * E;
+        src = k < K ? B + (long)c * ldb + k : (const TL*)&kZeroChunk;
+      }
+      __builtin_amdgcn_global_load_lds((const KP_GLOBAL void*)src,
+                                       (__attribute__((address_space(3))) void*)(stage + q * 1024),
+                                       16, 0, 0);
+    }
+  };
+
+  typename MF::acc acc[G::TI][G::TJ];
+#pragma unroll
+  for (int i = 0; i < G::TI; i++)
+#pragma unroll
+    for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+
+  for (int g = 0; g < kStages - 1 && g < total; g++) issue(g);
+  int st = 0, kt = 0;
+  bool drained = false;   // stores were issued: wait for everything
+  for (int g = 0; g < total; g++) {
+    // tile g must have landed: at most (tiles after g in flight) * PER_WAVE loads pending
+    const int after = min(kStages - 2, total - 1 - g);
+    if (drained || after <= 0) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    } else if (after == 1) {
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(D::PER_WAVE) : "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * D::PER_WAVE) : "memory");
+    }
+    drained = false;
+    // The waits above cover this wave's loads and the barrier the other waves'
+    // (and their reads of the stage refilled next).  A plain s_barrier: a
+    // workgroup fence would drain every load in flight.  The memory clobber
+    // keeps the compiler from moving LDS accesses across it.
+    asm volatile("s_barrier" ::: "memory");
+    if (g + kStages - 1 < total) issue(g + kStages - 1);
+    const char* stage = lds + (g % kStages) * D::STAGE;
+    const char* At = stage + (wp * G::WP) * 128;
+    const char* Bt = stage + D::ACH * 1024 + (wn * G::WN) * 128;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += MF::K) {
+      typename MF::frag a[G::TI], b[G::TJ];
+#pragma unroll
+      for (int i = 0; i < G::TI; i++) a[i] = frag_dma<TL>(At + i * 16 * 128, lane, kk);
+#pragma unroll
+      for (int j = 0; j < G::TJ; j++) b[j] = frag_dma<TL>(Bt + j * 16 * 128, lane, kk);
+#pragma unroll
+      for (int i = 0; i < G::TI; i++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++) acc[i][j] = MF::mma(b[j], a[i], acc[i][j]);
+    }
+    if (kt + 1 == nk) {
+      epi(st, s_of(st), acc);
+      drained = true;
+#pragma unroll
+      for (int i = 0; i < G::TI; i++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+          for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+      kt = 0;
+      st++;
+    } else {
+      kt++;
+    }
+  }
+  __syncthreads();
+}
+
+// Entry i of the derivative mask, read through the scalar cache (the mask is
+// read-only during a launch and its allocation is padded to whole words).
+__device__ __forceinline__ bool mask_at(const uint8_t* mask, int i) {
+  const __attribute__((address_space(4))) uint32_t* w =
+      (const __attribute__((address_space(4))) uint32_t*)mask;
+  return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu;
+}
+
+// Store x[0..3] to row[cb .. cb+3] (columns below lim); one vector store when
+// all four are in range and the row is 4-aligned.
+template <typename T, typename TC>
+__device__ __forceinline__ void put4(T* row, int cb, int lim, bool aligned, const TC (&x)[4]) {
+  if (aligned && cb + 3 < lim) {
+    if constexpr (std::is_same<T, bf16>::value) {
+      const f32x4 f = {(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
+      *gmem((bf16x4*)(row + cb)) = __builtin_convertvector(f, bf16x4);
+    } else if constexpr (std::is_same<T, float>::value) {
+      const f32x4 f = {(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
+      *gmem((f32x4*)(row + cb)) = f;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++) row[cb + e] = cvt<T>((double)x[e]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if (cb + e < lim) row[cb + e] = cvt<T>((double)x[e]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Forward layer.  Chunk c of C handles derivative rows [1 + c*len, ...), always
 // recomputes the value row (s = 0) first for t, and the last chunk also forms the
 // Laplacian row's pre-activation.  Outputs: z rows (value, derivatives) of the
@@ -253,8 +444,16 @@ __global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
   typedef Op<MODE> O;
   typedef Geo<MODE> G;
   typedef typename O::TC TC;
-  typedef Mfma<typename O::TL> MF;
-  __shared__ typename Mainloop<MODE>::Smem sm;
+  typedef typename O::TL TL;
+  typedef Mfma<TL> MF;
+  // The direct-to-LDS loop computes the transposed tile (neurons x points), so a
+  // lane holds consecutive neurons of one point and stores them as one vector
+  // (except FP64, whose MFMA rows are not consecutive within a lane).
+  constexpr bool TR = kDma<MODE>;
+  constexpr bool VEC = TR && !std::is_same<TL, double>::value;
+  constexpr int SMEM = TR ? kStages * DmaCfg<MODE, false>::STAGE
+                          : (int)sizeof(typename Mainloop<MODE>::Smem);
+  __shared__ __align__(16) char smem[SMEM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wp = wave >> 1, wn = wave & 1;
   const int ntc = (a.h_out + G::BN - 1) / G::BN;
@@ -269,6 +468,14 @@ __global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
   const bool lap_here = a.has_lap && chunk == nch - 1;
   const int nsteps = 1 + nder + (lap_here ? 1 : 0);
   const int S = a.S;
+  const bool tab_vec = (a.h_out & 3) == 0;
+  // output coordinates of accumulator element (i, j, e)
+  auto P = [&](int i, int e) {
+    return p0 + wp * G::WP + i * 16 + (TR ? (lane & 15) : MF::row(lane, e));
+  };
+  auto Cn = [&](int j, int e) {
+    return c0 + wn * G::WN + j * 16 + (TR ? MF::row(lane, e) : (lane & 15));
+  };
 
   TC tv[G::TI][G::TJ][4], sq[G::TI][G::TJ][4];
 #pragma unroll
@@ -282,53 +489,73 @@ __global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
   auto s_of = [=](int st) { return st == 0 ? 0 : (st <= nder ? dbeg + st - 1 : S - 1); };
   auto epi = [&](int st, int s, typename MF::acc (&acc)[G::TI][G::TJ]) {
     const bool is_d = s >= 1 && s <= nd;
-    const TC m = (is_d && a.mask[s - 1]) ? (TC)1 : (TC)0;
+    const TC m = (is_d && mask_at(a.mask, s - 1)) ? (TC)1 : (TC)0;
+    const int kind = s == 0 ? 0 : (is_d ? 1 : 2);
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
 #pragma unroll
       for (int j = 0; j < G::TJ; j++) {
-        const int c = c0 + wn * G::WN + j * 16 + (lane & 15);
+        TC v[4], out[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-          const int p = p0 + wp * G::WP + i * 16 + MF::row(lane, e);
-          const TC v = (TC)acc[i][j][e];
-          const bool ok = p < a.N && c < a.h_out;
-          const long row = (long)s * a.N + p;
-          if (s == 0) {
-            const TC th = act_tanh(v);
-            tv[i][j][e] = th;
-            if (ok && chunk == 0) {
-              ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)th);
-              if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v;
-              if (a.tab_t) ((TC*)a.tab_t)[(long)p * a.h_out + c] = th;
-            }
-          } else if (is_d) {
+          v[e] = (TC)acc[i][j][e];
+          if (kind == 0) {
+            out[e] = act_tanh(v[e]);
+            tv[i][j][e] = out[e];
+          } else if (kind == 1) {
             const TC th = tv[i][j][e];
-            sq[i][j][e] += m * v * v;
-            if (ok) {
-              ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)(((TC)1 - th * th) * v));
-              if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v;
-            }
-          } else if (ok) {   // Laplacian row pre-activation
-            ((TC*)a.tab_lap)[(long)p * a.h_out + c] = v;
-            if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v;
+            sq[i][j][e] += m * v[e] * v[e];
+            out[e] = ((TC)1 - th * th) * v[e];
+          }
+        }
+        if constexpr (VEC) {
+          const int p = P(i, 0), cb = Cn(j, 0);
+          if (p >= a.N) continue;
+          const long row = (long)s * a.N + p;
+          if (kind == 0 && chunk != 0) continue;
+          if (kind <= 1) put4((TZ*)a.z + row * a.ldzo, cb, a.h_out, true, out);
+          if (a.pre) put4((TC*)a.pre + row * a.ldp, cb, a.h_out, true, v);
+          if (kind == 0 && a.tab_t) put4((TC*)a.tab_t + (long)p * a.h_out, cb, a.h_out, tab_vec, out);
+          if (kind == 2) put4((TC*)a.tab_lap + (long)p * a.h_out, cb, a.h_out, tab_vec, v);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; e++) {
+            const int p = P(i, e), c = Cn(j, e);
+            if (p >= a.N || c >= a.h_out) continue;
+            const long row = (long)s * a.N + p;
+            if (kind == 0 && chunk != 0) continue;
+            if (kind <= 1) ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)out[e]);
+            if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v[e];
+            if (kind == 0 && a.tab_t) ((TC*)a.tab_t)[(long)p * a.h_out + c] = out[e];
+            if (kind == 2) ((TC*)a.tab_lap)[(long)p * a.h_out + c] = v[e];
           }
         }
       }
   };
-  sloop<MODE, false>(sm, (const typename O::TA*)a.zin, a.ldz, a.N, p0, (const typename O::TB*)a.w,
-              (const typename O::TB*)a.w2, a.ldw, c0, a.h_out, a.K, nsteps, s_of, epi);
+  if constexpr (TR)
+    sloop_dma<MODE, false>(smem, (const TL*)a.zin, a.ldz, a.N, p0, (const TL*)a.w, a.ldw, c0,
+                           a.h_out, a.K, nsteps, s_of, epi);
+  else
+    sloop<MODE, false>(*(typename Mainloop<MODE>::Smem*)smem, (const typename O::TA*)a.zin, a.ldz,
+                       a.N, p0, (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0,
+                       a.h_out, a.K, nsteps, s_of, epi);
   if (a.has_lap) {
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
 #pragma unroll
       for (int j = 0; j < G::TJ; j++) {
-        const int c = c0 + wn * G::WN + j * 16 + (lane & 15);
+        if constexpr (VEC) {
+          const int p = P(i, 0);
+          if (p < a.N)
+            put4((TC*)a.tab_sq + ((long)chunk * a.N + p) * a.h_out, Cn(j, 0), a.h_out, tab_vec,
+                 sq[i][j]);
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-          const int p = p0 + wp * G::WP + i * 16 + MF::row(lane, e);
-          if (p < a.N && c < a.h_out)
-            ((TC*)a.tab_sq)[((long)chunk * a.N + p) * a.h_out + c] = sq[i][j][e];
+          for (int e = 0; e < 4; e++) {
+            const int p = P(i, e), c = Cn(j, e);
+            if (p < a.N && c < a.h_out)
+              ((TC*)a.tab_sq)[((long)chunk * a.N + p) * a.h_out + c] = sq[i][j][e];
+          }
         }
       }
   }

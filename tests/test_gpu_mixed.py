@@ -47,3 +47,39 @@ def test_mixed_factors_within_1e_3(case):
     assert not bad, bad
     assert rel(lap, U[:, -1]) < 2e-2
     assert rel(grad, ref["grad"]) < 2e-2
+
+
+@pytest.mark.parametrize("case", ["poisson100d_subset", "heat_subset"])
+def test_mixed_line_search_losses(case):
+    """The BF16 line-search forward: every candidate loss L(theta + 2^k dhat) of a
+    mixed step against the FP64 oracle's loss at the same point (dhat recovered
+    from the applied update, delta = alpha* dhat).  BF16 rounds every slab entry
+    and weight with unit roundoff 2^-9; through four layers and the squared
+    residual this bounds the loss error at a few percent, and 5e-2 relative is
+    the bound used.  The chosen step must be within that bound of the oracle's
+    best candidate."""
+    from paper_2405_15603_amd import HParams, KfacPinn
+    if case == "poisson100d_subset":
+        p = synth.poisson100d(); ni, nb = 240, 80
+    else:
+        p = synth.heat4d(); ni, nb = 800, 300
+    th, xi, yi, xb, yb = problem_inputs(p, "bf16", ni, nb)
+    kp = kp_for(p, "bf16", max_interior=ni, max_boundary=nb)
+    theta = to_dev(th, "bf16")
+    hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
+    info = KfacPinn.decode_info(kp.step(theta, *(to_dev(a, "bf16") for a in (xi, yi, xb, yb)), hp))
+    assert kp.sync() == 0 and info["status"] == 0
+    alpha = info["lr"]
+    dhat = kp.get_momentum().cpu().double().numpy() / alpha
+    ls = kp.get_line_search(31).cpu().numpy()
+    op = oracle.operator_of(p)
+    ks = list(range(0, -31, -1))
+    ref = np.array([oracle.loss(th + 2.0 ** k * dhat, p.widths, xi, yi, xb, yb, op)[0]
+                    for k in ks])
+    err = np.abs(ls - ref) / np.abs(ref)
+    print(f"{case}: alpha* {alpha:g}, worst candidate rel err {err.max():.2e} "
+          f"(k = {ks[int(err.argmax())]})")
+    assert np.all(np.isfinite(ls))
+    assert np.all(err < 5e-2), err
+    chosen = ref[ks.index(int(round(np.log2(alpha))))]
+    assert chosen <= ref.min() * (1 + 5e-2)
