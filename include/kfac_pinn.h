@@ -178,9 +178,12 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* ctx, const void* theta,
  * in FP64, P and e with P^T F1 P = I and P^T F2 P = diag(e) for the pair
  * (F1, F2) = (interior, boundary) factor: a Cholesky factor of F1, then a
  * Jacobi eigendecomposition of the whitened F2.  The inverse of the Kronecker
- * sum is then (P_A (x) P_B) (I + e_A (x) e_B)^-1 (P_A (x) P_B)^T.  Sets
- * KP_ERR_NOT_PD in the device status when a damped interior factor is not
- * positive definite. */
+ * sum is then (P_A (x) P_B) (I + e_A (x) e_B)^-1 (P_A (x) P_B)^T.  The Jacobi
+ * iteration starts from the eigenvectors found by the previous call on this
+ * context (the identity after create/reset_state and on every 1000th call) and
+ * runs until no rotation exceeds its threshold, so the result does not depend
+ * on the start beyond rounding.  Sets KP_ERR_NOT_PD in the device status when
+ * a damped interior factor is not positive definite. */
 kp_status kfac_pinn_invert(kfac_pinn_ctx* ctx, double lambda);
 
 /* Delta = -(A_i (x) B_i + A_b (x) B_b)^-1 g per layer with the preconditioner of

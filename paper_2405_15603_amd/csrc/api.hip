@@ -46,6 +46,10 @@ constexpr int kMaxCand = 64;
 constexpr int kMaxSplits = 64;
 constexpr int kMaxChunks = 16;
 constexpr int kJacobiSweeps = 20;
+// Jacobi starts from the previous call's eigenvectors except on every
+// kEigRefresh-th call (and the first), which starts from the identity so that
+// rounding in the carried rotations cannot accumulate without bound.
+constexpr long kEigRefresh = 1000;
 
 struct Slabs {            // one term (interior or boundary); rows are s-major (s*N + p)
   int S = 1, nd = 0, has_lap = 0, cap = 0;   // rows per point, derivative rows, capacity (points)
@@ -83,6 +87,7 @@ struct kfac_pinn_ctx {
   size_t ws_limit = 0;
   hipStream_t st = nullptr;
   long D = 0;
+  long eig_calls = 0;       // calls of the Kronecker-sum eigensolver since reset
   NetDesc nd{};
   std::vector<long> off, ldz, ldp, ldg;
   long ldz_max = 0, ldp_max = 0;
@@ -723,6 +728,7 @@ kp_status kfac_pinn_reset_state(kfac_pinn_ctx* c, int32_t init_identity) {
       }
   KP_TRY(hipMemsetAsync(c->delta, 0, c->esz_p * c->D, c->st));
   KP_TRY(hipMemsetAsync(c->ctl, 0, sizeof(int) * 8, c->st));
+  c->eig_calls = 0;
   return KP_OK;
 }
 
@@ -844,11 +850,17 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* c, const void* theta, const void* xi,
   return KP_OK;
 }
 
+static hipError_t eig_all(kfac_pinn_ctx* c, double lambda) {
+  const int warm = (c->eig_calls % kEigRefresh) != 0;
+  c->eig_calls++;
+  return kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
+                          warm, kJacobiSweeps, c->st);
+}
+
 kp_status kfac_pinn_invert(kfac_pinn_ctx* c, double lambda) {
   KP_ARG(c, "null context");
   KP_ARG(lambda >= 0.0 && isfinite(lambda), "lambda must be finite and >= 0");
-  KP_TRY(kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
-                          nullptr, kJacobiSweeps, c->st));
+  KP_TRY(eig_all(c, lambda));
   return KP_OK;
 }
 
@@ -887,8 +899,7 @@ kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const vo
   // 3) preconditioner
   {
     int ti = tm_begin(c, KC_INVERT);
-    KP_TRY(kron_eig_batched(c->probs.data(), (int)c->probs.size(), hp->lambda, c->probs_dev,
-                            c->ctl, nullptr, kJacobiSweeps, c->st));
+    KP_TRY(eig_all(c, hp->lambda));
     tm_end(c, ti, 0.0, 0.0);
   }
   // 4) Delta = -C g, momentum

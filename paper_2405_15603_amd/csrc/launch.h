@@ -103,16 +103,18 @@ struct EigProblem {
   double* M2;         // n_pad^2 work: damped F2, then scratch
   double* Lb;         // n_pad^2: Cholesky factor L
   double* Li;         // n_pad^2: L^-1
-  double* C[2];       // n_pad^2 ping-pong: whitened F2 during Jacobi
-  double* P[2];       // n_pad^2 ping-pong: accumulated transform
+  double* C[2];       // n_pad^2: C[0] whitened F2 rotated by Jacobi, C[1] scratch
+  double* P[2];       // n_pad^2: P[0] accumulated rotations V (kept for warm starts),
+                      // P[1] the result L^-T V
   double* V;          // (n_pad/64) * 64*64: pair rotations of one round
   int* pflag;         // n_pad/64 + 1 ints: pair is identity this round; last = rotation flag
   double* dmax;       // largest diagonal entry of C (absolute rotation threshold)
   double* Pout;       // n x n result P (row-major)
   double* eout;       // n eigenvalues
 };
+// warm != 0: start Jacobi from the V left in P[0] by the previous call
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
-                            EigProblem* probs_dev, int* status, double* scratch, int max_sweeps,
+                            EigProblem* probs_dev, int* status, int warm, int max_sweeps,
                             hipStream_t st);
 // Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T for every layer, V = gradient
 // (column-major h_out x (h_in+1) inside the theta layout).  Four strided FP64

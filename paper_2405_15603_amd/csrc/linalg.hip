@@ -4,17 +4,21 @@
 // boundary factor) is brought to P^T F1 P = I, P^T F2 P = diag(e):
 //   1. blocked Cholesky F1 = L L^T (64 x 64 blocks),
 //   2. blocked triangular inverse L^-1,
-//   3. C = L^-1 F2 L^-T (two products),
-//   4. two-sided block Jacobi on C (32-wide blocks, round-robin pairing of
-//      block pairs; each pair's 64 x 64 subproblem gets one cyclic Jacobi sweep
-//      in LDS, then the rotations are applied to C and accumulated into
-//      P = L^-T V), until the off-diagonal mass of C falls below 1e-15 of its
-//      diagonal,
-//   5. e = diag(C), P.
+//   3. M = L^-1 F2 L^-T (two products),
+//   4. two-sided block Jacobi on C = V0^T M V0 (32-wide blocks, round-robin
+//      pairing of block pairs; each pair's 64 x 64 subproblem gets one cyclic
+//      Jacobi sweep in LDS, then the rotations are applied to C and
+//      accumulated into V), until a sweep performs no rotation above the
+//      threshold.  V0 is the identity on a cold start; on a warm start it is
+//      the previous call's V, the eigenvectors of the previous whitened
+//      matrix: the factors move slowly under the moving average, so C starts
+//      nearly diagonal and few sweeps remain,
+//   5. e = diag(C), P = L^-T V.
 // The inverse of A1 (x) B1 + A2 (x) B2 is then (P_A (x) P_B)(I + e_A (x) e_B)^-1
 // (P_A (x) P_B)^T.  Every problem is padded to a multiple of 64 with an identity
-// block in F1 and a zero block in F2, which stays exactly decoupled.
-// All problems of a step run in the same launches (grid.y = problem).
+// block in F1 and a zero block in F2, which stays exactly decoupled (V keeps
+// the block structure).  All problems of a call run in the same launches
+// (grid.y = problem).
 #include "common.h"
 #include "launch.h"
 
@@ -225,33 +229,55 @@ __global__ __launch_bounds__(256) void k_trtri_row(const EigProblem* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP64 product  C = A B^T  over 64 x 64 tiles (n_pad x n_pad operands):
-// mode 0: C1 <- Li * F2   (F2 symmetric, so F2 = F2^T),
-// mode 1: C0 <- C1 * Li^T
+// Batched FP64 products over 64 x 64 tiles (n_pad x n_pad operands):
+//   mode 0: C1 <- Li F2          (F2 symmetric; Li lower: k <= bi)
+//   mode 1: C0 <- C1 Li^T        (k <= bj)
+//   mode 2: C1 <- C0 V           (warm start, V = P0)
+//   mode 3: C0 <- V^T C1
+//   mode 4: P1 <- Li^T V         (Li^T upper: k >= bi)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_whiten(const EigProblem* __restrict__ pr, int mode) {
+__global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ pr, int mode) {
   const EigProblem p = pr[blockIdx.z];
   const int nb = p.n_pad / BB;
   const int bi = blockIdx.y, bj = blockIdx.x;
   if (bi >= nb || bj >= nb) return;
   const long np = p.n_pad;
-  const double* A = mode == 0 ? p.Li : p.C[1];
-  const double* B = mode == 0 ? p.M2 : p.Li;
   __shared__ double As[BB * LDB];
   __shared__ double Bs[BB * LDB];
   double acc[4][4];
   zero4(acc);
-  // Li is lower triangular: only k blocks <= bi (mode 0) or <= bj (mode 1) contribute
-  const int kend = mode == 0 ? bi : bj;
-  for (int k = 0; k <= kend; k++) {
+  const int kbeg = mode == 4 ? bi : 0;
+  const int kend = mode == 0 ? bi : (mode == 1 ? bj : nb - 1);
+  for (int k = kbeg; k <= kend; k++) {
     __syncthreads();
-    tile_load(As, A + (long)bi * BB * np + (long)k * BB, np);
-    tile_load(Bs, B + (long)bj * BB * np + (long)k * BB, np);
+    switch (mode) {
+      case 0:
+        tile_load(As, p.Li + (long)bi * BB * np + (long)k * BB, np);
+        tile_load(Bs, p.M2 + (long)bj * BB * np + (long)k * BB, np);
+        break;
+      case 1:
+        tile_load(As, p.C[1] + (long)bi * BB * np + (long)k * BB, np);
+        tile_load(Bs, p.Li + (long)bj * BB * np + (long)k * BB, np);
+        break;
+      case 2:
+        tile_load(As, p.C[0] + (long)bi * BB * np + (long)k * BB, np);
+        tile_load(Bs, p.P[0] + (long)k * BB * np + (long)bj * BB, np);
+        break;
+      case 3:
+        tile_load(As, p.P[0] + (long)k * BB * np + (long)bi * BB, np);
+        tile_load(Bs, p.C[1] + (long)k * BB * np + (long)bj * BB, np);
+        break;
+      default:
+        tile_load(As, p.Li + (long)k * BB * np + (long)bi * BB, np);
+        tile_load(Bs, p.P[0] + (long)k * BB * np + (long)bj * BB, np);
+        break;
+    }
     __syncthreads();
-    blk_mm<false, true>(acc, As, Bs);
+    if (mode <= 1) blk_mm<false, true>(acc, As, Bs);
+    else if (mode == 2) blk_mm<false, false>(acc, As, Bs);
+    else blk_mm<true, false>(acc, As, Bs);
   }
-  // mode 0 writes into the C[1] buffer (scratch), mode 1 into C[0]
-  double* out = mode == 0 ? p.C[1] : p.C[0];
+  double* out = (mode == 0 || mode == 2) ? p.C[1] : (mode == 4 ? p.P[1] : p.C[0]);
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
   for (int a = 0; a < 4; a++)
@@ -260,14 +286,14 @@ __global__ __launch_bounds__(256) void k_whiten(const EigProblem* __restrict__ p
       out[(long)(bi * BB + ty * 4 + a) * np + bj * BB + tx * 4 + b] = acc[a][b];
 }
 
-// C <- (C + C^T)/2, P <- Li^T, flags reset, largest diagonal entry of C
-__global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done) {
+// C <- (C + C^T)/2, V <- I on a cold start (kept on a warm start), flags reset
+__global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done, int warm) {
   const EigProblem p = pr[blockIdx.y];
   const long np = p.n_pad;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < np * np;
        e += (long)gridDim.x * blockDim.x) {
     const int i = (int)(e / np), j = (int)(e % np);
-    p.P[0][e] = p.Li[(long)j * np + i];
+    if (!warm) p.P[0][e] = i == j ? 1.0 : 0.0;
     if (j > i) {
       const double v = 0.5 * (p.C[0][e] + p.C[0][(long)j * np + i]);
       p.C[0][e] = v;
@@ -520,15 +546,14 @@ __global__ void k_jac_extract(const EigProblem* __restrict__ pr) {
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (long)p.n * p.n;
        e += (long)gridDim.x * blockDim.x) {
     const int i = (int)(e / p.n), j = (int)(e % p.n);
-    p.Pout[e] = p.P[0][(long)i * np + j];
+    p.Pout[e] = p.P[1][(long)i * np + j];
     if (i == j) p.eout[i] = p.C[0][(long)i * np + i];
   }
 }
 
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
-                            EigProblem* probs_dev, int* status, double* scratch, int max_sweeps,
+                            EigProblem* probs_dev, int* status, int warm, int max_sweeps,
                             hipStream_t st) {
-  (void)scratch;
   if (nprob <= 0) return hipSuccess;
   int npmax = 0;
   for (int q = 0; q < nprob; q++) npmax = probs_host[q].n_pad > npmax ? probs_host[q].n_pad : npmax;
@@ -544,9 +569,14 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
     }
   }
   for (int i = 1; i < nbmax; i++) k_trtri_row<<<dim3(i, nprob), 256, 0, st>>>(probs_dev, i);
-  k_whiten<<<dim3(nbmax, nbmax, nprob), 256, 0, st>>>(probs_dev, 0);
-  k_whiten<<<dim3(nbmax, nbmax, nprob), 256, 0, st>>>(probs_dev, 1);
-  k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done);
+  const dim3 gmm(nbmax, nbmax, nprob);
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 0);
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 1);
+  if (warm) {
+    k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 2);
+    k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 3);
+  }
+  k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done, warm);
   k_jac_dmax<<<nprob, 256, 0, st>>>(probs_dev);
   const int nblk = npmax / JB;
   const int npair = nblk / 2;
@@ -558,6 +588,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
     }
     k_jac_check<<<1, 64, 0, st>>>(probs_dev, done, nprob);
   }
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 4);
   k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev);
   return hipGetLastError();
 }
