@@ -63,6 +63,7 @@ struct Slabs {            // one term (interior or boundary); rows are s-major (
   std::vector<void*> sq;                     // per hidden layer: N x h sum of squares
   void* u = nullptr;                         // network output rows (compute type, R)
   double* r = nullptr;                       // residual per point
+  float* rf = nullptr;                       // its FP32 copy
   void* zin_at(int l) const { return store ? zin[l] : zr[l & 1]; }
   void* g_at(int l) const { return store ? g[l] : gr[l & 1]; }
   void* pre_at(int l) const { return store ? pre[l] : prer; }
@@ -177,7 +178,10 @@ hipError_t alloc_slabs(kfac_pinn_ctx* c, Slabs& s) {
       if ((e = dmalloc(c, &s.sq[l], (size_t)s.cap * c->w[l + 1] * c->esz_c)) != hipSuccess)
         return e;
   if ((e = dmalloc(c, &s.u, R * c->esz_c)) != hipSuccess) return e;
-  return dmalloc(c, (void**)&s.r, sizeof(double) * (s.cap > 0 ? s.cap : 1));
+  // residuals in FP64, then their FP32 copy (the BF16x3 gradient product reads it)
+  if ((e = dmalloc(c, (void**)&s.r, sizeof(double) * (s.cap > 0 ? s.cap : 1))) != hipSuccess)
+    return e;
+  return dmalloc(c, (void**)&s.rf, sizeof(float) * (s.cap > 0 ? s.cap : 1));
 }
 
 inline char* wptr(const void* base, long elems, size_t esz) { return (char*)base + elems * esz; }
@@ -293,7 +297,7 @@ hipError_t residual_and_seed(kfac_pinn_ctx* c, Slabs& s, const void* u, const vo
   hipError_t e;
   const int nb = residual_blocks(n);
   if ((e = residual(c->sp, u, 1, y, n, s.S, time_row_of(c, s), c->c_t, c->c_lap, lap_row_of(s),
-                    s.r, g_last, c->ldg[c->L - 1], c->partial, c->st)) != hipSuccess)
+                    s.r, s.rf, g_last, c->ldg[c->L - 1], c->partial, c->st)) != hipSuccess)
     return e;
   return finalize_loss(c->partial, nb, 0.5 / (double)n, c->loss, slot, accumulate, c->st);
 }
@@ -303,7 +307,7 @@ hipError_t residual_loss_only(kfac_pinn_ctx* c, Slabs& s, const void* u, const v
   hipError_t e;
   const int nb = residual_blocks(n);
   if ((e = residual(c->sp == P_F64 ? P_F64 : P_F32, u, 1, y, n, s.S, time_row_of(c, s), c->c_t,
-                    c->c_lap, lap_row_of(s), nullptr, nullptr, 1, c->partial, c->st)) !=
+                    c->c_lap, lap_row_of(s), nullptr, nullptr, nullptr, 1, c->partial, c->st)) !=
       hipSuccess)
     return e;
   return finalize_loss(c->partial, nb, 0.5 / (double)n, c->loss, slot, accumulate, c->st);
@@ -386,15 +390,16 @@ struct FactorGrad : LayerConsumer {
     const double sbf = 1.0 / n;
     int ti = tm_begin(c, KC_FACTOR_GEMM);
     if ((e = gemm_tn_splitk(m, zin, c->ldz[l], zin, c->ldz[l], ld.h_in + 1, ld.h_in + 1, K,
-                            nullptr, n, true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+                            nullptr, nullptr, n, true, c->part, kMaxSplits, &sp, c->st)) !=
+        hipSuccess)
       return e;
     tm_end(c, ti, (double)K * (ld.h_in + 1) * (ld.h_in + 2), (double)K * (ld.h_in + 1) * c->esz_s);
     if ((e = reduce_splitk(m, c->part, sp, ld.h_in + 1, ld.h_in + 1, true, c->F[term][0][l],
                            ld.h_in + 1, 1, (1.0 - beta) * sa, beta, c->st)) != hipSuccess)
       return e;
     ti = tm_begin(c, KC_FACTOR_GEMM);
-    if ((e = gemm_tn_splitk(m, g, c->ldg[l], g, c->ldg[l], ld.h_out, ld.h_out, K, nullptr, n,
-                            true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+    if ((e = gemm_tn_splitk(m, g, c->ldg[l], g, c->ldg[l], ld.h_out, ld.h_out, K, nullptr,
+                            nullptr, n, true, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
       return e;
     tm_end(c, ti, (double)K * ld.h_out * (ld.h_out + 1), (double)K * ld.h_out * c->esz_s);
     if ((e = reduce_splitk(m, c->part, sp, ld.h_out, ld.h_out, true, c->F[term][1][l], ld.h_out,
@@ -402,8 +407,8 @@ struct FactorGrad : LayerConsumer {
       return e;
     // gradient: sum_rows (r_n / n) g (x) z~, column-major into theta
     const Slabs& s = term == 0 ? c->si : c->sb;
-    if ((e = gemm_tn_splitk(m, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1, K, s.r, n,
-                            false, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+    if ((e = gemm_tn_splitk(m, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1, K, s.r,
+                            s.rf, n, false, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
       return e;
     return reduce_splitk(m, c->part, sp, ld.h_out, ld.h_in + 1, false, c->grad + ld.off, 1,
                          ld.h_out, 1.0 / n, term == 0 ? 0.0 : 1.0, c->st);
@@ -419,7 +424,8 @@ struct ThetaBar : LayerConsumer {
     const LayerDesc& ld = c->nd.l[l];
     int sp = 1;
     hipError_t e = gemm_tn_splitk(c->cmode, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1,
-                                  n * S, nullptr, n, false, c->part, kMaxSplits, &sp, c->st);
+                                  n * S, nullptr, nullptr, n, false, c->part, kMaxSplits, &sp,
+                                  c->st);
     if (e != hipSuccess) return e;
     return reduce_splitk(c->cmode, c->part, sp, ld.h_out, ld.h_in + 1, false, out + ld.off, 1,
                          ld.h_out, 1.0, 0.0, c->st);

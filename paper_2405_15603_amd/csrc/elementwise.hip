@@ -128,7 +128,8 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
                                                   const TP* __restrict__ y, int npts, int S,
                                                   int time_row, double c_t, double c_lap,
                                                   int lap_row, double* __restrict__ r,
-                                                  TS* __restrict__ g, long ldg,
+                                                  float* __restrict__ rf, TS* __restrict__ g,
+                                                  long ldg,
                                                   double* __restrict__ partial) {
   __shared__ double red[4];
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
       v = (double)pre[(long)n * ldp] - (double)y[n];   // boundary: r = u - g
     }
     if (r) r[n] = v;
+    if (rf) rf[n] = (float)v;
     sq = v * v;
     if (g) {
       for (int s = 0; s < S; s++) {
@@ -165,25 +167,25 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
 }
 
 hipError_t residual(Prec p, const void* pre, long ldp, const void* y, int npts, int S,
-                    int time_row, double c_t, double c_lap, int lap_row, double* r, void* g,
+                    int time_row, double c_t, double c_lap, int lap_row, double* r, float* rf, void* g,
                     long ldg, double* partial, hipStream_t st) {
   int nb = residual_blocks(npts);
   switch (p) {
     case P_F64:
       k_residual<double, double, double><<<nb, 256, 0, st>>>(
-          (const double*)pre, ldp, (const double*)y, npts, S, time_row, c_t, c_lap, lap_row, r,
+          (const double*)pre, ldp, (const double*)y, npts, S, time_row, c_t, c_lap, lap_row, r, rf,
           (double*)g, ldg, partial);
       break;
     case P_F32:
       k_residual<float, float, float><<<nb, 256, 0, st>>>((const float*)pre, ldp,
                                                           (const float*)y, npts, S, time_row, c_t,
-                                                          c_lap, lap_row, r, (float*)g, ldg,
+                                                          c_lap, lap_row, r, rf, (float*)g, ldg,
                                                           partial);
       break;
     case P_BF16:
       k_residual<float, float, bf16><<<nb, 256, 0, st>>>((const float*)pre, ldp, (const float*)y,
                                                          npts, S, time_row, c_t, c_lap, lap_row,
-                                                         r, (bf16*)g, ldg, partial);
+                                                         r, rf, (bf16*)g, ldg, partial);
       break;
   }
   return hipGetLastError();

@@ -208,6 +208,164 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const typename TnOp<MODE>::TA* 
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16x3 variant with the transpose done in registers.  A thread loads 8
+// consecutive slab rows x 4 consecutive columns (eight 16-byte loads, 512 bytes
+// contiguous per row across a half-wave), so for each of its 4 columns it holds
+// 8 consecutive k; it splits them into BF16 hi and lo and writes each as one
+// 16-byte LDS store into a k-contiguous [column][k] tile.  The 4 chunks of 8 k
+// in a 64-byte tile row are XOR-swizzled by (column >> 2) & 3, which makes the
+// 16-row fragment reads conflict-free.  Waves 0-1 load A, waves 2-3 load B.
+// Tile 128 x 128 x 32, four waves of 64 x 64, two LDS stages.
+// ---------------------------------------------------------------------------
+constexpr int X3_BM = 128, X3_BK = 32;
+
+__device__ __forceinline__ int x3_pos(int col, int chunk) {
+  return col * X3_BK + ((chunk ^ ((col >> 2) & 3)) << 3);
+}
+
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long lda,
+                                               const float* __restrict__ B, long ldb, int M,
+                                               int N, int K, const float* __restrict__ rw,
+                                               int rmod, int sym, int ntm, int ntn, int kchunk,
+                                               float* __restrict__ part) {
+  typedef Mfma<bf16> MF;
+  constexpr int BM = X3_BM, BK = X3_BK, TI = 4, TJ = 4;
+  // [stage][operand][plane][BM * BK]
+  __shared__ __align__(16) bf16 sm[2][2][2][BM * BK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int ti, tj;
+  {
+    int t = blockIdx.x;
+    if (sym) {
+      ti = 0;
+      int rowlen = ntm;
+      while (t >= rowlen) { t -= rowlen; ti++; rowlen--; }
+      tj = ti + t;
+    } else {
+      ti = t / ntn;
+      tj = t % ntn;
+    }
+  }
+  const int m0 = ti * BM, n0 = tj * BM;
+  const int split = blockIdx.y;
+  const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
+  float* out = part + (long)split * M * N;
+
+  // loader role: operand (0 = A, 1 = B), column group, row group
+  const int opd = tid >> 7, lt = tid & 127;
+  const int cg = lt & 31, rg = lt >> 5;
+  const float* src = opd == 0 ? A : B;
+  const long ld = opd == 0 ? lda : ldb;
+  const int col = (opd == 0 ? m0 : n0) + 4 * cg;
+  const int lim = (int)kp_roundup(opd == 0 ? M : N, 4);
+  const bool col_ok = col < lim;
+  const int colc = col_ok ? col : 0;   // loads stay in bounds; masked lanes read column 0
+  u32x4 ra[8];
+  float wr[8];   // row weights of the A rows in flight (gradient)
+
+#define KP_X3_LOAD(K0)                                                            \
+  {                                                                              \
+    _Pragma("unroll") for (int j = 0; j < 8; j++) {                              \
+      const int gk = (K0) + 8 * rg + j;                                          \
+      const int gkc = min(gk, kend - 1);                                         \
+      ra[j] = ld16(src + (long)gkc * ld + colc);                                 \
+      if (WEIGHTED && opd == 0) wr[j] = rw[gkc % rmod];                          \
+    }                                                                            \
+  }
+#define KP_X3_STORE(BUF, K0)                                                      \
+  {                                                                              \
+    float wt[8];                                                                 \
+    _Pragma("unroll") for (int j = 0; j < 8; j++) {                              \
+      const int gk = (K0) + 8 * rg + j;                                          \
+      wt[j] = (col_ok && gk < kend) ? 1.0f : 0.0f;                               \
+      if (WEIGHTED && opd == 0) wt[j] *= wr[j];                                  \
+    }                                                                            \
+    f32x4 fr[8];                                                                 \
+    _Pragma("unroll") for (int j = 0; j < 8; j++)                                \
+      fr[j] = __builtin_bit_cast(f32x4, ra[j]) * wt[j];                          \
+    _Pragma("unroll") for (int e = 0; e < 4; e++) {                              \
+      f32x4 f0, f1;                                                              \
+      _Pragma("unroll") for (int j = 0; j < 4; j++) {                            \
+        f0[j] = fr[j][e];                                                        \
+        f1[j] = fr[j + 4][e];                                                    \
+      }                                                                          \
+      const bf16x4 h0 = __builtin_convertvector(f0, bf16x4);                     \
+      const bf16x4 h1 = __builtin_convertvector(f1, bf16x4);                     \
+      const bf16x4 l0 = __builtin_convertvector(f0 - __builtin_convertvector(h0, f32x4), bf16x4); \
+      const bf16x4 l1 = __builtin_convertvector(f1 - __builtin_convertvector(h1, f32x4), bf16x4); \
+      const int pos = x3_pos(4 * cg + e, rg);                                    \
+      bf16x8 hv = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);       \
+      bf16x8 lv = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);       \
+      *(bf16x8*)&sm[BUF][opd][0][pos] = hv;                                      \
+      *(bf16x8*)&sm[BUF][opd][1][pos] = lv;                                      \
+    }                                                                            \
+  }
+
+  MF::acc acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; i++)
+#pragma unroll
+    for (int j = 0; j < TJ; j++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    KP_X3_LOAD(kbeg);
+    KP_X3_STORE(0, kbeg);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fc = lane >> 4;
+  // uniform body: the last iteration also loads (clamped rows) and stores into
+  // the unused stage, so the compiler sees no loads in flight at the loop head
+  for (int kt = 0; kt < nk; kt++) {
+    const int cur = kt & 1;
+    const int knext = kbeg + (kt + 1) * BK;
+    KP_X3_LOAD(knext);
+    // keep the loads ahead of the products (the scheduler would sink them)
+    __builtin_amdgcn_sched_barrier(0);
+    MF::frag a[2][TI], b[2][TJ];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+#pragma unroll
+      for (int i = 0; i < TI; i++)
+        a[h][i] = *(const bf16x8*)&sm[cur][0][h][x3_pos(wm * 64 + i * 16 + fr, fc)];
+#pragma unroll
+      for (int j = 0; j < TJ; j++)
+        b[h][j] = *(const bf16x8*)&sm[cur][1][h][x3_pos(wn * 64 + j * 16 + fr, fc)];
+    }
+#pragma unroll
+    for (int i = 0; i < TI; i++)
+#pragma unroll
+      for (int j = 0; j < TJ; j++) {
+        acc[i][j] = MF::mma(a[0][i], b[0][j], acc[i][j]);
+        acc[i][j] = MF::mma(a[1][i], b[0][j], acc[i][j]);
+        acc[i][j] = MF::mma(a[0][i], b[1][j], acc[i][j]);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+    KP_X3_STORE(cur ^ 1, knext);
+    __syncthreads();
+  }
+#undef KP_X3_LOAD
+#undef KP_X3_STORE
+
+#pragma unroll
+  for (int i = 0; i < TI; i++)
+#pragma unroll
+    for (int j = 0; j < TJ; j++) {
+      const int c = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (c >= N) continue;
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int r = m0 + wm * 64 + i * 16 + MF::row(lane, e);
+        if (r < M) out[(long)r * N + c] = acc[i][j][e];
+      }
+    }
+}
+
 template <int MODE>
 static void launch_tn(dim3 g, const void* A, long lda, const void* B, long ldb, int M, int N, int K,
                       const double* rw, int rmod, bool sym, int ntm, int ntn, int kchunk,
@@ -223,8 +381,8 @@ static void launch_tn(dim3 g, const void* A, long lda, const void* B, long ldb, 
 }
 
 hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long ldb, int M, int N,
-                          int K, const double* rw, int rmod, bool sym, void* part, int max_splits,
-                          int* splits_out, hipStream_t st) {
+                          int K, const double* rw, const float* rwf, int rmod, bool sym,
+                          void* part, int max_splits, int* splits_out, hipStream_t st) {
   const int BT = (mode == M_F64) ? 64 : 128;
   const int BK = (mode == M_BF16 || mode == M_BF16X3) ? 32 : 16;
   const int ntm = kp_cdiv(M, BT), ntn = kp_cdiv(N, BT);
@@ -243,7 +401,15 @@ hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long
     case M_F64: launch_tn<M_F64>(g, A, lda, B, ldb, M, N, K, rw, rmod, sym, ntm, ntn, kchunk, part, st); break;
     case M_F32: launch_tn<M_F32>(g, A, lda, B, ldb, M, N, K, rw, rmod, sym, ntm, ntn, kchunk, part, st); break;
     case M_BF16: launch_tn<M_BF16>(g, A, lda, B, ldb, M, N, K, rw, rmod, sym, ntm, ntn, kchunk, part, st); break;
-    case M_BF16X3: launch_tn<M_BF16X3>(g, A, lda, B, ldb, M, N, K, rw, rmod, sym, ntm, ntn, kchunk, part, st); break;
+    case M_BF16X3:
+      if (rw && !rwf) return hipErrorInvalidValue;
+      if (rw)
+        k_tn_x3<true><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M, N, K, rwf,
+                                         rmod, sym, ntm, ntn, kchunk, (float*)part);
+      else
+        k_tn_x3<false><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M, N, K,
+                                          nullptr, rmod, sym, ntm, ntn, kchunk, (float*)part);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -12,12 +12,13 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
 // ---- factor / gradient products (modes of fwdlap.h) -------------------------
 // part[s][m*N + n] = sum_{k in split s} w(k) A[k][m] B[k][n] for the tiles the
 // kernel covers (sym: only tiles at or above the diagonal).  w(k) = rw[k % rmod]
-// when rw != nullptr (one weight per point; slab rows are s-major), else 1.
-// A and B are row-major K x (>= M / N) with lda/ldb.  part is double for FP64,
-// float otherwise.  The launcher picks the number of splits (<= max_splits).
+// when rw != nullptr (one weight per point; slab rows are s-major), else 1;
+// the BF16x3 mode reads the FP32 copy rwf of the weights instead.  A and B are
+// row-major K x (>= M / N, rounded up to 4) with lda/ldb.  part is double for
+// FP64, float otherwise.  The launcher picks the number of splits (<= max_splits).
 hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long ldb, int M, int N,
-                          int K, const double* rw, int rmod, bool sym, void* part, int max_splits,
-                          int* splits_out, hipStream_t st);
+                          int K, const double* rw, const float* rwf, int rmod, bool sym,
+                          void* part, int max_splits, int* splits_out, hipStream_t st);
 // out[m*so_m + n*so_n] = c_prev*out + alpha * sum_s part[s][m*N+n]  (double out);
 // with sym the lower triangle is mirrored from the upper.
 hipError_t reduce_splitk(int mode, const void* part, int splits, int M, int N, bool sym,
@@ -49,13 +50,14 @@ hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long 
                       hipStream_t st);
 
 // Residual, loss partials and the output seed.  pre: last layer output rows
-// (compute type, ldp); y: targets (real); r: residual per point (double);
+// (compute type, ldp); y: targets (real); r: residual per point (double) and
+// rf its FP32 copy (either may be nullptr);
 // g: seed rows (storage type, ldg; nullptr = not written); partial: per-block
 // sums of r^2 (double, grid size returned by residual_blocks).
 int residual_blocks(int npts);
 hipError_t residual(Prec p, const void* pre, long ldp, const void* y, int npts, int S,
-                    int time_row, double c_t, double c_lap, int lap_row, double* r, void* g,
-                    long ldg, double* partial, hipStream_t st);
+                    int time_row, double c_t, double c_lap, int lap_row, double* r, float* rf,
+                    void* g, long ldg, double* partial, hipStream_t st);
 // loss[slot] = scale * sum(partial[0..nb)) (+ loss[slot] if accumulate)
 hipError_t finalize_loss(const double* partial, int nb, double scale, double* loss, int slot,
                          int accumulate, hipStream_t st);
