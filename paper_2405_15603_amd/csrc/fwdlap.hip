@@ -245,31 +245,35 @@ __device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
 // ---------------------------------------------------------------------------
 // Direct-to-LDS variant of sloop for operands used as stored (BF16, FP32, FP64):
 // every k-tile row is 128 bytes (8 chunks of 16 B), loaded with
-// global_load_lds_dwordx4 into a ring of NST stages, NST-1 tiles in flight.  A
-// wave's load instruction fills 1 KB = 8 rows; chunk q of row r sits at chunk
-// position q ^ ((r >> 1) & 7), which makes the 16-row fragment reads
-// conflict-free.  Chunks outside the valid rows / k range are redirected to a
-// valid address: rows past N or ncols only feed discarded outputs, and chunks
-// past K read a 16-byte zero block.  K must be a multiple of 16 bytes.  The
-// accumulators hold the transposed tile: acc[i][j] = B_j A_i^T, i.e. MFMA rows
-// are neurons and MFMA columns are points.
+// global_load_lds_dwordx4 into a ring of kStages stages, kStages-1 tiles in
+// flight.  A pass covers NS shared columns s at once: a stage holds NS A tiles
+// and one B tile, so the weights are fetched once per NS products.  A wave's
+// load instruction fills 1 KB = 8 rows; chunk q of row r sits at chunk position
+// q ^ ((r >> 1) & 7), which makes the 16-row fragment reads conflict-free.
+// Chunks outside the valid rows / k range are redirected to a valid address:
+// rows past N or ncols only feed discarded outputs, and chunks past K read a
+// 16-byte zero block.  K must be a multiple of 16 bytes.  The accumulators hold
+// the transposed tile: acc[q][i][j] = B_j A_{q,i}^T, i.e. MFMA rows are neurons
+// and MFMA columns are points.  epi(step, s, acc[q]) runs for the steps of a
+// pass in order once its products are complete.
 // ---------------------------------------------------------------------------
-constexpr int kStages = 4;
+constexpr int kStages = 3;
 __device__ __align__(16) u32x4 kZeroChunk = {0u, 0u, 0u, 0u};
 
-template <int MODE, bool NARROW>
+template <int MODE, bool NARROW, int NS>
 struct DmaCfg {
   typedef Geo<MODE, NARROW> G;
   typedef typename Op<MODE>::TL T;
   static constexpr int E = 16 / sizeof(T);            // elements per chunk
   static constexpr int BK = 128 / sizeof(T);          // k per tile (8 chunks)
-  static constexpr int ACH = G::BP / 8, BCH = G::BN / 8;   // 1 KB chunks per stage
-  static constexpr int NCH = ACH + BCH;
-  static constexpr int PER_WAVE = (NCH + 7) / 8;
+  static constexpr int ACH = G::BP / 8, BCH = G::BN / 8;   // 1 KB chunks per tile
+  static constexpr int NCH = NS * ACH + BCH;
+  static constexpr int PER_WAVE = NCH / 8;
   static constexpr int STAGE = NCH * 1024;             // bytes
   static_assert(NCH % 8 == 0, "every wave issues the same number of chunk loads");
 };
 template <int MODE> constexpr bool kDma = MODE == M_BF16;
+constexpr int kDmaNS = 2;
 
 __device__ __forceinline__ int swz(int r) { return (r >> 1) & 7; }
 
@@ -292,13 +296,13 @@ __device__ __forceinline__ double frag_dma<double>(const char* tile, int lane, i
   return *(const double*)(tile + r * 128 + (((k >> 1) ^ swz(r)) << 4) + ((k & 1) << 3));
 }
 
-template <int MODE, bool NARROW, class SOf, class Epi>
+template <int MODE, bool NARROW, int NS, class SOf, class Epi>
 __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL* __restrict__ A,
                                           long lda, int N, int p0,
                                           const typename Op<MODE>::TL* __restrict__ B, long ldb,
                                           int c0, int ncols, int K, int nsteps, SOf s_of,
                                           Epi epi) {
-  typedef DmaCfg<MODE, NARROW> D;
+  typedef DmaCfg<MODE, NARROW, NS> D;
   typedef Geo<MODE, NARROW> G;
   typedef typename Op<MODE>::TL TL;
   typedef Mfma<TL> MF;
@@ -307,61 +311,77 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wp = wave >> 1, wn = wave & 1;
   const int nk = (K + BK - 1) / BK;
-  const int total = nsteps * nk;
+  const int npass = (nsteps + NS - 1) / NS;
+  const int total = npass * nk;
   if (total <= 0) return;
   const int rin = lane >> 3, pos = lane & 7;
 
-  // issue the loads of flattened tile g into its stage
-  auto issue = [&](int g) {
-    const int st = g / nk, kt = g - st * nk;
-    const long arow0 = (long)s_of(st) * N;
-    const int k0 = kt * BK;
-    char* stage = lds + (g % kStages) * D::STAGE;
+  // Per-thread chunk coordinates are fixed for the whole loop: chunk slot j
+  // (q = wave + 8 j) belongs to A tile j / (ACH / 8) or, past NS A tiles, to B.
+  static_assert(D::ACH % 8 == 0 && D::BCH % 8 == 0, "chunk slots map to one operand");
+  constexpr int JA = NS * D::ACH / 8;   // slots 0..JA-1 load A tiles, the rest B
+  int off[D::PER_WAVE], kin[D::PER_WAVE];   // element offset (without k0), chunk k offset
+#pragma unroll
+  for (int j = 0; j < D::PER_WAVE; j++) {
+    const int q = wave + 8 * j;
+    if (j < JA) {
+      const int r = (q % D::ACH) * 8 + rin;
+      kin[j] = (pos ^ swz(r)) * E;
+      off[j] = min(p0 + r, N - 1) * (int)lda + kin[j];
+    } else {
+      const int r = (q - NS * D::ACH) * 8 + rin;
+      kin[j] = (pos ^ swz(r)) * E;
+      off[j] = min(c0 + r, ncols - 1) * (int)ldb + kin[j];
+    }
+  }
+  const TL* zchunk = (const TL*)&kZeroChunk;
+
+  // Issue the loads of the next tile in order (tile index gi = pass ips, k-tile
+  // ikt, stage ist); counters advance instead of dividing by nk.
+  int ips = 0, ikt = 0, ist = 0;
+  long sbase[NS];
+  auto issue = [&]() {
+    if (ikt == 0) {
+#pragma unroll
+      for (int q = 0; q < NS; q++) sbase[q] = (long)s_of(min(ips * NS + q, nsteps - 1)) * N * lda;
+    }
+    const int k0 = ikt * BK;
+    const bool last_k = k0 + BK > K;   // only the last k-tile has chunks past K
+    char* stage = lds + ist * D::STAGE;
 #pragma unroll
     for (int j = 0; j < D::PER_WAVE; j++) {
-      const int q = wave + 8 * j;   // 1 KB chunk of the stage
-      const TL* src;
-      if (q < D::ACH) {
-        const int r = q * 8 + rin;
-        const int cg = pos ^ swz(r);
-        int p = p0 + r;
-        p = p < N ? p : N - 1;
-        const int k = k0 + cg * E;
-        src = k < K ? A + (arow0 + p) * lda + k : (const TL*)&kZeroChunk;
-      } else {
-        const int r = (q - D::ACH) * 8 + rin;
-        const int cg = pos ^ swz(r);
-        int c = c0 + r;
-        c = c < ncols ? c : ncols - 1;
-        const int k = k0 + cg * E;
-        src = k < K ? B + (long)c * ldb + k : (const TL*)&kZeroChunk;
-      }
+      const TL* src = j < JA ? A + sbase[j / (D::ACH / 8)] + off[j] + k0 : B + off[j] + k0;
+      if (last_k) src = k0 + kin[j] < K ? src : zchunk;
       __builtin_amdgcn_global_load_lds((const KP_GLOBAL void*)src,
-                                       (__attribute__((address_space(3))) void*)(stage + q * 1024),
+                                       (__attribute__((address_space(3))) void*)(stage +
+                                                                                 (wave + 8 * j) * 1024),
                                        16, 0, 0);
     }
+    if (++ikt == nk) { ikt = 0; ips++; }
+    if (++ist == kStages) ist = 0;
   };
 
-  typename MF::acc acc[G::TI][G::TJ];
+  typename MF::acc acc[NS][G::TI][G::TJ];
 #pragma unroll
-  for (int i = 0; i < G::TI; i++)
+  for (int q = 0; q < NS; q++)
 #pragma unroll
-    for (int j = 0; j < G::TJ; j++)
+    for (int i = 0; i < G::TI; i++)
 #pragma unroll
-      for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+      for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc[q][i][j][e] = 0;
 
-  for (int g = 0; g < kStages - 1 && g < total; g++) issue(g);
-  int st = 0, kt = 0;
+  for (int g = 0; g < kStages - 1 && g < total; g++) issue();
+  int ps = 0, kt = 0, cst = 0;
   bool drained = false;   // stores were issued: wait for everything
   for (int g = 0; g < total; g++) {
     // tile g must have landed: at most (tiles after g in flight) * PER_WAVE loads pending
     const int after = min(kStages - 2, total - 1 - g);
     if (drained || after <= 0) {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    } else if (after == 1) {
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(D::PER_WAVE) : "memory");
     } else {
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * D::PER_WAVE) : "memory");
+      static_assert(kStages == 3, "one tile in flight behind the current one");
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(D::PER_WAVE) : "memory");
     }
     drained = false;
     // The waits above cover this wave's loads and the barrier the other waves'
@@ -369,33 +389,44 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
     // workgroup fence would drain every load in flight.  The memory clobber
     // keeps the compiler from moving LDS accesses across it.
     asm volatile("s_barrier" ::: "memory");
-    if (g + kStages - 1 < total) issue(g + kStages - 1);
-    const char* stage = lds + (g % kStages) * D::STAGE;
-    const char* At = stage + (wp * G::WP) * 128;
-    const char* Bt = stage + D::ACH * 1024 + (wn * G::WN) * 128;
+    if (g + kStages - 1 < total) issue();
+    const char* stage = lds + cst * D::STAGE;
+    if (++cst == kStages) cst = 0;
+    const char* Bt = stage + NS * D::ACH * 1024 + (wn * G::WN) * 128;
+    const bool two = NS == 1 || ps * NS + 1 < nsteps;   // second column of the pass is real
 #pragma unroll
     for (int kk = 0; kk < BK; kk += MF::K) {
-      typename MF::frag a[G::TI], b[G::TJ];
-#pragma unroll
-      for (int i = 0; i < G::TI; i++) a[i] = frag_dma<TL>(At + i * 16 * 128, lane, kk);
+      typename MF::frag b[G::TJ];
 #pragma unroll
       for (int j = 0; j < G::TJ; j++) b[j] = frag_dma<TL>(Bt + j * 16 * 128, lane, kk);
 #pragma unroll
-      for (int i = 0; i < G::TI; i++)
+      for (int q = 0; q < NS; q++) {
+        if (q > 0 && !two) break;
+        const char* At = stage + q * D::ACH * 1024 + (wp * G::WP) * 128;
+        typename MF::frag a[G::TI];
 #pragma unroll
-        for (int j = 0; j < G::TJ; j++) acc[i][j] = MF::mma(b[j], a[i], acc[i][j]);
+        for (int i = 0; i < G::TI; i++) a[i] = frag_dma<TL>(At + i * 16 * 128, lane, kk);
+#pragma unroll
+        for (int i = 0; i < G::TI; i++)
+#pragma unroll
+          for (int j = 0; j < G::TJ; j++) acc[q][i][j] = MF::mma(b[j], a[i], acc[q][i][j]);
+      }
     }
     if (kt + 1 == nk) {
-      epi(st, s_of(st), acc);
+#pragma unroll
+      for (int q = 0; q < NS; q++) {
+        const int st = ps * NS + q;
+        if (st < nsteps) epi(st, s_of(st), acc[q]);
+#pragma unroll
+        for (int i = 0; i < G::TI; i++)
+#pragma unroll
+          for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[q][i][j][e] = 0;
+      }
       drained = true;
-#pragma unroll
-      for (int i = 0; i < G::TI; i++)
-#pragma unroll
-        for (int j = 0; j < G::TJ; j++)
-#pragma unroll
-          for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
       kt = 0;
-      st++;
+      ps++;
     } else {
       kt++;
     }
@@ -451,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
   // (except FP64, whose MFMA rows are not consecutive within a lane).
   constexpr bool TR = kDma<MODE>;
   constexpr bool VEC = TR && !std::is_same<TL, double>::value;
-  constexpr int SMEM = TR ? kStages * DmaCfg<MODE, false>::STAGE
+  constexpr int SMEM = TR ? kStages * DmaCfg<MODE, false, kDmaNS>::STAGE
                           : (int)sizeof(typename Mainloop<MODE>::Smem);
   __shared__ __align__(16) char smem[SMEM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -533,8 +564,8 @@ __global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
       }
   };
   if constexpr (TR)
-    sloop_dma<MODE, false>(smem, (const TL*)a.zin, a.ldz, a.N, p0, (const TL*)a.w, a.ldw, c0,
-                           a.h_out, a.K, nsteps, s_of, epi);
+    sloop_dma<MODE, false, kDmaNS>(smem, (const TL*)a.zin, a.ldz, a.N, p0, (const TL*)a.w, a.ldw,
+                                   c0, a.h_out, a.K, nsteps, s_of, epi);
   else
     sloop<MODE, false>(*(typename Mainloop<MODE>::Smem*)smem, (const typename O::TA*)a.zin, a.ldz,
                        a.N, p0, (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0,
@@ -810,6 +841,9 @@ static dim3 tile_grid(int N, int cols, int nch) {
 
 hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
+  // the direct-to-LDS loop keeps per-point offsets in 32 bits
+  if ((long)a.N * a.ldz >= 0x7fffffffL || (long)a.h_out * a.ldw >= 0x7fffffffL)
+    return hipErrorInvalidValue;
   switch (mode) {
     case M_F64:
       k_fwdlap<M_F64, double><<<tile_grid<M_F64>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
