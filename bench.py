@@ -7,15 +7,24 @@ One step = one full KFAC iteration (Algorithm 1): forward Laplacian, residuals,
 backward pass, Kronecker factors with EMA, damped Kronecker-sum inverse,
 preconditioned direction with momentum, grid line search over 31 step sizes and
 the update.  The headline runs the mixed-precision path (BF16 MFMA, FP32
-accumulation, FP64 factors and inversion); the plain FP32 path is timed beside
-it.  Inputs are resident in HBM before the timed region.
+accumulation, FP64 factors and inversion); the plain FP32 path and the core
+step (fixed step size, no line search) are timed beside it.  Inputs are resident
+in HBM before the timed region.
+
+The roofline object describes the dominant kernel, the line-search layer
+product (k_fwdlap in BF16): algorithmic FLOPs of its launches over their
+HIP-event durations.  Its HBM traffic comes from the committed rocprofv3
+FETCH_SIZE / WRITE_SIZE summary when that summary was taken on the current
+kernel source, else it is null.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits."""
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,17 +32,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
-KERNEL_CLASSES = {"layer_gemm": 0, "factor_gemm": 1, "invert": 2, "act": 3}
+HBM_GBS = 8000.0
+KERNEL_CLASSES = {"layer_gemm": 0, "factor_gemm": 1, "invert": 2, "act": 3, "ls_layer": 4}
+KERNEL_NAMES = {"ls_layer": "k_fwdlap (line-search forward layer product)",
+                "layer_gemm": "k_fwdlap / k_bwdlap (curvature pass layer products)",
+                "factor_gemm": "k_tn (Kronecker factor and gradient products)",
+                "invert": "Kronecker-sum factorisation (Cholesky + Jacobi)",
+                "act": "forward-Laplacian finishing passes"}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fwdlap_bf16_poisson100d_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_15603_amd", "csrc", "fwdlap.hip")
 
 
-def hparams():
+def hparams(lr_mode="grid", lr=1.0):
     from paper_2405_15603_amd import HParams
     # the paper's only printed KFAC hyper-parameters (2d Poisson run): beta, mu;
     # damping 1e-3; grid line search over 2^0 .. 2^-30
-    return HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
+    return HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode=lr_mode, lr=lr)
 
 
-def run_gpu(problem, precision, steps, warmup, kernel_class=None):
+def run_gpu(problem, precision, steps, warmup, kernel_class=None, lr_mode="grid"):
     import numpy as np
     import torch
     from paper_2405_15603_amd import KfacPinn
@@ -43,7 +60,7 @@ def run_gpu(problem, precision, steps, warmup, kernel_class=None):
     th = T(problem.theta0())
     xi, yi, xb, yb = (T(a) for a in problem.batch(0))
     kp = KfacPinn.for_problem(problem, precision)
-    hp = hparams()
+    hp = hparams(lr_mode, lr=2.0 ** -5)
     info = kp.empty(64, dtype=torch.uint8)
     for _ in range(warmup):
         kp.step(th, xi, yi, xb, yb, hp, info)
@@ -68,7 +85,33 @@ def run_gpu(problem, precision, steps, warmup, kernel_class=None):
     return ms, tm, status, last
 
 
-def cpu_baseline(problem, frac=0.05):
+def copy_calibration(mib):
+    """A plain elementwise copy of `mib` MiB (read once, written once), launched
+    so that a rocprofv3 counter run can scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def measured_traffic():
+    """Bytes per launch of the dominant kernel from the committed counter summary,
+    or None when it is absent or was taken on another version of the kernel."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m and t):
+        return None
+    cur = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    return float(t.group(1)) if cur == m.group(1) else None
+
+
+def cpu_baseline(problem, frac=0.1):
     """The FP64 oracle's step on a bounded sample of the same workload (same
     network, a fraction of the points), extrapolated to the full point count:
     the per-point work scales with the number of points, the Kronecker-sum
@@ -109,8 +152,11 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
     ap.add_argument("--workload", default="poisson100d")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
+    ap.add_argument("--no-core", action="store_true", help="skip the fixed-step (core) leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel", default="layer_gemm", choices=list(KERNEL_CLASSES))
+    ap.add_argument("--kernel", default="ls_layer", choices=list(KERNEL_CLASSES))
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method's data-parallel sharding "
@@ -119,6 +165,8 @@ def main():
 
     import synth
     problem = synth.PROBLEMS[args.workload]()
+    if args.copy_calibration_mib > 0:
+        copy_calibration(args.copy_calibration_mib)
     kc = KERNEL_CLASSES[args.kernel]
     ms, tm, status, last = run_gpu(problem, args.precision, args.steps, args.warmup, kc)
     if status != 0:
@@ -145,13 +193,23 @@ def main():
         "last_step": last,
     }
     if tm and tm["launches"] > 0:
-        ach = tm["flops"] / (tm["ms"] * 1e-3) / 1e12
+        sec = tm["ms"] * 1e-3
+        ach = tm["flops"] / sec / 1e12
         peak = PEAK_TFLOPS[args.precision]
+        traffic = measured_traffic() if (args.kernel == "ls_layer" and args.precision == "bf16") else None
         out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                           "frac": ach / peak, "traffic": None,
-                           "kernel": f"{args.kernel} ({tm['launches']} launches, "
-                                     f"{tm['ms'] / tm['launches']:.3f} ms avg)",
+                           "frac": ach / peak, "traffic": traffic,
+                           "kernel": f"{KERNEL_NAMES[args.kernel]}: {tm['launches']} launches, "
+                                     f"{tm['ms'] / tm['launches']:.4f} ms average",
+                           "algorithmic_bytes_per_launch": tm["bytes"] / tm["launches"],
+                           "algorithmic_hbm_GBs": tm["bytes"] / sec / 1e9,
+                           "hbm_frac": tm["bytes"] / sec / 1e9 / HBM_GBS,
                            "share_of_step": tm["ms"] / (ms * args.steps)}
+    if not args.no_core:
+        msc, _, stc, _ = run_gpu(problem, args.precision, max(2, args.steps // 2), 1, None,
+                                 lr_mode="fixed")
+        out["core_step"] = {"value": 1000.0 / msc, "ms_per_step": msc, "status": stc,
+                            "note": "fixed step size 2^-5, no line search"}
     if not args.no_fp32 and args.precision != "f32":
         ms32, _, st32, _ = run_gpu(problem, "f32", max(2, args.steps // 2), 1, None)
         out["fp32"] = {"value": 1000.0 / ms32, "ms_per_step": ms32, "status": st32,

@@ -220,9 +220,10 @@ kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* ctx, const void* dev_in, int64_t
 
 /* ---- measurement ---------------------------------------------------------
  * While enabled, every launch of one kernel class is bracketed by HIP events on
- * the context's stream: 0 layer products (forward and backward, line search
- * included), 1 factor/gradient products, 2 the whole Kronecker-sum
- * factorisation, 3 the tanh rows and their adjoint; -1 disables.
+ * the context's stream: 0 layer products of the curvature pass (forward and
+ * backward), 1 factor/gradient products, 2 the whole Kronecker-sum
+ * factorisation, 3 the tanh rows and their adjoint, 4 the layer products of
+ * the line-search forwards; -1 disables.
  * kfac_pinn_timing_read waits for the stream and writes (host, 4 doubles):
  * launches, total milliseconds, algorithmic FLOPs and algorithmic bytes of the
  * timed launches, then resets the counters. */

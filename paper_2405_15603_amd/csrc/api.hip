@@ -187,7 +187,7 @@ hipError_t alloc_slabs(kfac_pinn_ctx* c, Slabs& s) {
 inline char* wptr(const void* base, long elems, size_t esz) { return (char*)base + elems * esz; }
 
 // kernel classes for timing
-enum { KC_LAYER_GEMM = 0, KC_FACTOR_GEMM = 1, KC_INVERT = 2, KC_ACT = 3 };
+enum { KC_LAYER_GEMM = 0, KC_FACTOR_GEMM = 1, KC_INVERT = 2, KC_ACT = 3, KC_LS_LAYER = 4 };
 
 int tm_begin(kfac_pinn_ctx* c, int cls) {
   if (c->tm_cls != cls) return -1;
@@ -226,6 +226,7 @@ struct FwdTarget {
   std::function<void*(int)> pre;   // hidden pre-activations of layer l (or nullptr)
   std::function<void*(int)> sq;    // sum of squares table of layer l (or nullptr)
   void* u;                      // output rows
+  int kc_layer = KC_LAYER_GEMM;  // timing class of the layer products
 };
 
 // Forward through hidden layers [0, upto) and, when upto == L, the output layer.
@@ -260,7 +261,7 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
     a.tab_sq = s.has_lap ? wptr(c->tab, 2 * ts, c->esz_c) : nullptr;
     a.sq_out = T.sq(l);
     const int nch = fwdlap_chunks(T.mode, n, ld.h_out, s.nd, s.has_lap);
-    int ti = tm_begin(c, KC_LAYER_GEMM);
+    int ti = tm_begin(c, T.kc_layer);
     if ((e = fwdlap_main(T.mode, a, nch, c->st)) != hipSuccess) return e;
     tm_end(c, ti, 2.0 * R * ld.h_out * (ld.h_in + 1),
            (double)R * (ld.h_in + 1 + ld.h_out) * T.zesz + (double)ld.h_out * (ld.h_in + 1) * c->esz_w);
@@ -461,6 +462,7 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   T.pre = [](int) -> void* { return nullptr; };
   T.sq = [](int) -> void* { return nullptr; };
   T.u = c->ls_u;
+  T.kc_layer = KC_LS_LAYER;
   int acc = 0;
   if (ni > 0) {
     if ((e = forward_run(c, c->si, xi, ni, c->L, T)) != hipSuccess) return e;
@@ -988,7 +990,7 @@ kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* c, const void* in, int64_t step)
 
 kp_status kfac_pinn_timing_enable(kfac_pinn_ctx* c, int32_t kernel_class) {
   KP_ARG(c, "null context");
-  KP_ARG(kernel_class >= -1 && kernel_class <= 3, "unknown kernel class");
+  KP_ARG(kernel_class >= -1 && kernel_class <= 4, "unknown kernel class");
   c->tm_cls = kernel_class;
   c->tm_used = 0;
   c->tm_flops = c->tm_bytes = 0.0;
