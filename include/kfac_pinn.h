@@ -234,6 +234,11 @@ kp_status kfac_pinn_timing_read(kfac_pinn_ctx* ctx, double* out4);
    side B) in the last inversion; waits for the stream.  out: host, 2L ints. */
 kp_status kfac_pinn_get_sweeps(kfac_pinn_ctx* ctx, int32_t* out);
 
+/* Whether the interior (out[0]) and boundary (out[1]) terms recompute layer inputs
+   per layer instead of storing them (1) because their slabs exceed
+   workspace_limit_bytes.  out: host, 2 ints. */
+kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
+
 /* Waits for the context's stream; returns the device status word (and clears it). */
 kp_status kfac_pinn_sync(kfac_pinn_ctx* ctx);
 const char* kfac_pinn_status_string(kp_status status);

@@ -221,6 +221,12 @@ class KfacPinn:
         N.check(self.lib.kfac_pinn_get_sweeps(self.h, out), "kfac_pinn_get_sweeps")
         return list(out)
 
+    def recompute_mode(self) -> tuple:
+        """(interior, boundary): True where layer inputs are recomputed per layer."""
+        out = (C.c_int32 * 2)()
+        N.check(self.lib.kfac_pinn_get_workspace(self.h, out), "kfac_pinn_get_workspace")
+        return bool(out[0]), bool(out[1])
+
     def sync(self) -> int:
         """Waits for the stream; returns (and clears) the device status word."""
         return int(self.lib.kfac_pinn_sync(self.h))

@@ -66,6 +66,7 @@ _SIGS = {
     "kfac_pinn_timing_enable": (C.c_int, [_V, C.c_int32]),
     "kfac_pinn_timing_read": (C.c_int, [_V, C.POINTER(C.c_double)]),
     "kfac_pinn_get_sweeps": (C.c_int, [_V, C.POINTER(C.c_int32)]),
+    "kfac_pinn_get_workspace": (C.c_int, [_V, C.POINTER(C.c_int32)]),
     "kfac_pinn_sync": (C.c_int, [_V]),
     "kfac_pinn_status_string": (C.c_char_p, [C.c_int]),
     "kfac_pinn_last_error": (C.c_char_p, []),

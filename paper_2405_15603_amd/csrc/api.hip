@@ -1027,6 +1027,13 @@ kp_status kfac_pinn_get_sweeps(kfac_pinn_ctx* c, int32_t* out) {
   return KP_OK;
 }
 
+kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* c, int32_t* out) {
+  KP_ARG(c && out, "null argument");
+  out[0] = c->si.store ? 0 : 1;
+  out[1] = c->sb.store ? 0 : 1;
+  return KP_OK;
+}
+
 kp_status kfac_pinn_sync(kfac_pinn_ctx* c) {
   KP_ARG(c, "null context");
   KP_TRY(hipStreamSynchronize(c->st));
