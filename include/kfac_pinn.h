@@ -239,6 +239,33 @@ kp_status kfac_pinn_get_sweeps(kfac_pinn_ctx* ctx, int32_t* out);
    workspace_limit_bytes.  out: host, 2 ints. */
 kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
 
+/* ---- batches of independent instances --------------------------------------
+ * Not in the paper (which trains one network at a time): many small problems
+ * stepped together.  kfac_pinn_batch_create creates `count` contexts from
+ * problems[0..count) (host array) on internal streams of default priority;
+ * instance k runs on lane k % 8, so the instances' launches overlap.
+ * kfac_pinn_batch_step performs one kfac_pinn_step per instance with the same
+ * hyper-parameters: thetas, x_int, y_int, x_bnd, y_bnd are host arrays of
+ * `count` device pointers, n_int and n_bnd host arrays of sizes, infos a device
+ * array of `count` summaries (or NULL).  The work is ordered after the work
+ * already on `stream` and before anything enqueued there later.  The first
+ * call captures the whole batch step into a HIP graph, later calls with the
+ * same arguments replay it (different arguments recapture); with the graph
+ * disabled (kfac_pinn_batch_set_graph) every call enqueues the launches
+ * directly.  Errors as for kfac_pinn_step; per-instance device status is read
+ * with kfac_pinn_sync on kfac_pinn_batch_context(batch, k). */
+typedef struct kfac_pinn_batch kfac_pinn_batch;
+kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void* stream,
+                                 kfac_pinn_batch** out);
+kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* batch);
+kp_status kfac_pinn_batch_context(kfac_pinn_batch* batch, int32_t k, kfac_pinn_ctx** out);
+kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* batch, int32_t enabled);
+kp_status kfac_pinn_batch_step(kfac_pinn_batch* batch, void* const* thetas,
+                               const void* const* x_int, const void* const* y_int,
+                               const int32_t* n_int, const void* const* x_bnd,
+                               const void* const* y_bnd, const int32_t* n_bnd,
+                               const kp_hparams* hp, kp_step_info* infos);
+
 /* Waits for the context's stream; returns the device status word (and clears it). */
 kp_status kfac_pinn_sync(kfac_pinn_ctx* ctx);
 const char* kfac_pinn_status_string(kp_status status);

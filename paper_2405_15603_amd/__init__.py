@@ -83,7 +83,29 @@ class KfacPinn:
         return cls(problem.widths, precision, problem.time_coord, problem.coef_time,
                    problem.coef_lap, list(problem.lap_mask), **kw)
 
+    @classmethod
+    def _borrow(cls, handle: C.c_void_p, widths, precision: str, max_interior: int,
+                max_boundary: int, stream) -> "KfacPinn":
+        """A view of a context owned elsewhere (an instance of a batch)."""
+        self = cls.__new__(cls)
+        self.lib = N.lib()
+        self.widths = [int(w) for w in widths]
+        self.L = len(self.widths) - 1
+        self.d = self.widths[0]
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream
+        self._w = (C.c_int32 * len(self.widths))(*self.widths)
+        self.h = handle
+        self._owned = False
+        self.D = int(self.lib.kfac_pinn_num_params(self._w, self.L))
+        self.max_interior, self.max_boundary = max_interior, max_boundary
+        return self
+
     def __del__(self):
+        if not getattr(self, "_owned", True):
+            return
         h = getattr(self, "h", None)
         if h is not None and h.value:
             try:
@@ -252,6 +274,76 @@ class ForwardLaplacian(torch.autograd.Function):
                                           cast(u_bar), cast(grad_bar), cast(lap_bar),
                                           want_x_bar=ctx.needs_input_grad[1])
         return tb.to(theta.dtype), (xb if ctx.needs_input_grad[1] else None), None
+
+
+class KfacPinnBatch:
+    """Many independent problems stepped together (kfac_pinn_batch_*): one
+    context per problem on internal lanes, the batch step captured into a HIP
+    graph on the first call and replayed afterwards."""
+
+    def __init__(self, problems, precision: str = "bf16", use_graph: bool = True,
+                 stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("KfacPinnBatch needs a GPU (HIP device); there is no CPU path")
+        self.lib = N.lib()
+        self.problems = list(problems)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        n = len(self.problems)
+        self._keep = []
+        arr = (N.kp_problem * n)()
+        for k, p in enumerate(self.problems):
+            w = (C.c_int32 * len(p.widths))(*p.widths)
+            m = (C.c_uint8 * p.d)(*[1 if v else 0 for v in p.lap_mask])
+            self._keep += [w, m]
+            arr[k] = N.kp_problem(len(p.widths) - 1, w, p.time_coord, p.coef_time, p.coef_lap, m,
+                                  PRECISIONS[precision], p.n_interior, p.n_cond, 0)
+        h = C.c_void_p()
+        N.check(self.lib.kfac_pinn_batch_create(arr, n, C.c_void_p(self.stream.cuda_stream),
+                                                C.byref(h)), "kfac_pinn_batch_create")
+        self.h = h
+        self.set_graph(use_graph)
+        self.contexts = []
+        for k, p in enumerate(self.problems):
+            ch = C.c_void_p()
+            N.check(self.lib.kfac_pinn_batch_context(self.h, k, C.byref(ch)),
+                    "kfac_pinn_batch_context")
+            self.contexts.append(KfacPinn._borrow(ch, p.widths, precision, p.n_interior, p.n_cond,
+                                                  self.stream))
+
+    def __len__(self):
+        return len(self.problems)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize()
+                self.lib.kfac_pinn_batch_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def set_graph(self, enabled: bool) -> None:
+        N.check(self.lib.kfac_pinn_batch_set_graph(self.h, 1 if enabled else 0),
+                "kfac_pinn_batch_set_graph")
+
+    def step(self, thetas, xi, yi, xb, yb, hp: HParams, infos: Optional[torch.Tensor] = None):
+        """One step of every instance; lists of tensors per instance.  `infos`
+        (device bytes, len * sizeof(kp_step_info)) receives the summaries."""
+        n = len(self.problems)
+        V = C.c_void_p * n
+        I = C.c_int32 * n
+        hpc = hp.c()
+        N.check(self.lib.kfac_pinn_batch_step(
+            self.h, V(*[t.data_ptr() for t in thetas]), V(*[t.data_ptr() for t in xi]),
+            V(*[t.data_ptr() for t in yi]), I(*[t.shape[0] for t in xi]),
+            V(*[t.data_ptr() for t in xb]), V(*[t.data_ptr() for t in yb]),
+            I(*[t.shape[0] for t in xb]), C.byref(hpc), _ptr(infos)), "kfac_pinn_batch_step")
+
+    def sync(self) -> list:
+        return [c.sync() for c in self.contexts]
 
 
 def forward_laplacian(kp: KfacPinn, theta: torch.Tensor, x: torch.Tensor):

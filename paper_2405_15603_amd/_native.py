@@ -67,6 +67,13 @@ _SIGS = {
     "kfac_pinn_timing_read": (C.c_int, [_V, C.POINTER(C.c_double)]),
     "kfac_pinn_get_sweeps": (C.c_int, [_V, C.POINTER(C.c_int32)]),
     "kfac_pinn_get_workspace": (C.c_int, [_V, C.POINTER(C.c_int32)]),
+    "kfac_pinn_batch_create": (C.c_int, [C.POINTER(kp_problem), C.c_int32, _V, C.POINTER(_V)]),
+    "kfac_pinn_batch_destroy": (C.c_int, [_V]),
+    "kfac_pinn_batch_context": (C.c_int, [_V, C.c_int32, C.POINTER(_V)]),
+    "kfac_pinn_batch_set_graph": (C.c_int, [_V, C.c_int32]),
+    "kfac_pinn_batch_step": (C.c_int, [_V, C.POINTER(_V), C.POINTER(_V), C.POINTER(_V),
+                                       C.POINTER(C.c_int32), C.POINTER(_V), C.POINTER(_V),
+                                       C.POINTER(C.c_int32), C.POINTER(kp_hparams), _V]),
     "kfac_pinn_sync": (C.c_int, [_V]),
     "kfac_pinn_status_string": (C.c_char_p, [C.c_int]),
     "kfac_pinn_last_error": (C.c_char_p, []),

@@ -49,7 +49,7 @@ constexpr int kJacobiSweeps = 20;
 // Jacobi starts from the previous call's eigenvectors except on every
 // kEigRefresh-th call (and the first), which starts from the identity so that
 // rounding in the carried rotations cannot accumulate without bound.
-constexpr long kEigRefresh = 1000;
+constexpr int kEigRefresh = 1000;
 
 struct Slabs {            // one term (interior or boundary); rows are s-major (s*N + p)
   int S = 1, nd = 0, has_lap = 0, cap = 0;   // rows per point, derivative rows, capacity (points)
@@ -88,7 +88,6 @@ struct kfac_pinn_ctx {
   size_t ws_limit = 0;
   hipStream_t st = nullptr;
   long D = 0;
-  long eig_calls = 0;       // calls of the Kronecker-sum eigensolver since reset
   NetDesc nd{};
   std::vector<long> off, ldz, ldp, ldg;
   long ldz_max = 0, ldp_max = 0;
@@ -734,9 +733,8 @@ kp_status kfac_pinn_reset_state(kfac_pinn_ctx* c, int32_t init_identity) {
         const long n = sd == 0 ? c->w[l] + 1 : c->w[l + 1];
         KP_TRY(ema_fill(c->F[t][sd][l], n * n, (int)n, init_identity ? 1 : 0, c->st));
       }
-  KP_TRY(hipMemsetAsync(c->delta, 0, c->esz_p * c->D, c->st));
-  KP_TRY(hipMemsetAsync(c->ctl, 0, sizeof(int) * 8, c->st));
-  c->eig_calls = 0;
+  KP_TRY(zero_fill(c->delta, c->esz_p * c->D, c->st));
+  KP_TRY(zero_fill(c->ctl, sizeof(int) * 8, c->st));
   return KP_OK;
 }
 
@@ -785,7 +783,7 @@ kp_status kfac_pinn_forward_laplacian_vjp(kfac_pinn_ctx* c, const void* theta, c
   KP_ARG(c && theta && x && theta_bar, "null argument");
   KP_ARG(n >= 0 && n <= c->max_i, "n exceeds max_interior");
   if (n == 0) {
-    KP_TRY(hipMemsetAsync(theta_bar, 0, sizeof(double) * c->D, c->st));
+    KP_TRY(zero_fill(theta_bar, sizeof(double) * c->D, c->st));
     return KP_OK;
   }
   Slabs& s = c->si;
@@ -831,8 +829,8 @@ static hipError_t decay_term(kfac_pinn_ctx* c, int term, double beta) {
 static kp_status factors_impl(kfac_pinn_ctx* c, const void* theta, const void* xi, const void* yi,
                               int ni, const void* xb, const void* yb, int nb, double beta) {
   KP_TRY(prep(c, theta));
-  KP_TRY(hipMemsetAsync(c->grad, 0, sizeof(double) * c->D, c->st));
-  KP_TRY(hipMemsetAsync(c->loss, 0, sizeof(double) * 2, c->st));
+  KP_TRY(zero_fill(c->grad, sizeof(double) * c->D, c->st));
+  KP_TRY(zero_fill(c->loss, sizeof(double) * 2, c->st));
   // interior term first: it overwrites the gradient, the boundary term adds to it
   if (ni > 0) KP_TRY(curvature_term(c, 0, theta, xi, yi, ni, beta));
   else KP_TRY(decay_term(c, 0, beta));
@@ -859,10 +857,8 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* c, const void* theta, const void* xi,
 }
 
 static hipError_t eig_all(kfac_pinn_ctx* c, double lambda) {
-  const int warm = (c->eig_calls % kEigRefresh) != 0;
-  c->eig_calls++;
   return kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
-                          warm, kJacobiSweeps, c->st);
+                          kEigRefresh, kJacobiSweeps, c->st);
 }
 
 kp_status kfac_pinn_invert(kfac_pinn_ctx* c, double lambda) {
@@ -1044,6 +1040,191 @@ kp_status kfac_pinn_sync(kfac_pinn_ctx* c) {
     KP_TRY(hipMemcpy(c->ctl, &zero, sizeof(int), hipMemcpyHostToDevice));
   }
   return (kp_status)st;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent instances (one step of each per call).  Instance k
+// runs on internal lane k % lanes, so the instances' small launches overlap.
+// The whole step of all instances is captured into one HIP graph on the first
+// call and replayed on later calls with the same arguments; different
+// arguments recapture.
+// ---------------------------------------------------------------------------
+struct kfac_pinn_batch {
+  std::vector<kfac_pinn_ctx*> ctx;
+  hipStream_t st = nullptr;       // the caller's stream (may be the null stream)
+  hipStream_t origin = nullptr;   // internal stream the graph is captured on and launched to
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;   // caller -> origin -> caller
+  std::vector<hipStream_t> lanes;
+  std::vector<hipEvent_t> ev;   // fork, then one join per lane
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uintptr_t> key;
+  int use_graph = 1;
+};
+
+namespace {
+constexpr int kBatchLanes = 8;
+constexpr int kMaxBatch = 1024;
+
+void batch_drop_graph(kfac_pinn_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->key.clear();
+}
+
+kp_status batch_enqueue(kfac_pinn_batch* b, void* const* thetas, const void* const* xi,
+                        const void* const* yi, const int32_t* ni, const void* const* xb,
+                        const void* const* yb, const int32_t* nb, const kp_hparams* hp,
+                        kp_step_info* infos) {
+  for (size_t k = 0; k < b->ctx.size(); k++) {
+    kp_status s = kfac_pinn_step(b->ctx[k], thetas[k], xi[k], yi[k], ni[k], xb[k], yb[k], nb[k],
+                                 hp, infos ? infos + k : nullptr);
+    if (s != KP_OK) return s;
+  }
+  return KP_OK;
+}
+}  // namespace
+
+kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void* stream,
+                                 kfac_pinn_batch** out) {
+  KP_ARG(problems && out, "null argument");
+  *out = nullptr;
+  KP_ARG(count >= 1 && count <= kMaxBatch, "count must be in [1, 1024]");
+  kfac_pinn_batch* b = new kfac_pinn_batch();
+  b->st = (hipStream_t)stream;
+  const int nl = count < kBatchLanes ? count : kBatchLanes;
+  for (int l = 0; l < nl; l++) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      kfac_pinn_batch_destroy(b);
+      return KP_ERR_HIP;
+    }
+    b->lanes.push_back(s);
+  }
+  for (int l = 0; l <= nl; l++) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      kfac_pinn_batch_destroy(b);
+      return KP_ERR_HIP;
+    }
+    b->ev.push_back(e);
+  }
+  if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+    kfac_pinn_batch_destroy(b);
+    return KP_ERR_HIP;
+  }
+  for (int k = 0; k < count; k++) {
+    kfac_pinn_ctx* c = nullptr;
+    kp_status s = kfac_pinn_create(&problems[k], b->lanes[k % nl], &c);
+    if (s != KP_OK) {
+      kfac_pinn_batch_destroy(b);
+      return s;
+    }
+    b->ctx.push_back(c);
+  }
+  *out = b;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
+  if (!b) return KP_ERR_ARG;
+  for (hipStream_t s : b->lanes) (void)hipStreamSynchronize(s);
+  if (b->origin) (void)hipStreamSynchronize(b->origin);
+  batch_drop_graph(b);
+  for (kfac_pinn_ctx* c : b->ctx) kfac_pinn_destroy(c);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  delete b;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_batch_context(kfac_pinn_batch* b, int32_t k, kfac_pinn_ctx** out) {
+  KP_ARG(b && out, "null argument");
+  KP_ARG(k >= 0 && k < (int)b->ctx.size(), "instance index out of range");
+  *out = b->ctx[k];
+  return KP_OK;
+}
+
+kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* b, int32_t enabled) {
+  KP_ARG(b, "null batch");
+  b->use_graph = enabled ? 1 : 0;
+  if (!enabled) batch_drop_graph(b);
+  return KP_OK;
+}
+
+kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const void* const* x_int,
+                               const void* const* y_int, const int32_t* n_int,
+                               const void* const* x_bnd, const void* const* y_bnd,
+                               const int32_t* n_bnd, const kp_hparams* hp, kp_step_info* infos) {
+  KP_ARG(b && thetas && x_int && y_int && n_int && x_bnd && y_bnd && n_bnd && hp,
+         "null argument");
+  const int n = (int)b->ctx.size();
+  const int nl = (int)b->lanes.size();
+  if (!b->use_graph) {
+    // fork: every lane waits for the caller's stream
+    KP_TRY(hipEventRecord(b->ev[0], b->st));
+    for (int l = 0; l < nl; l++) KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev[0], 0));
+    kp_status s = batch_enqueue(b, thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp, infos);
+    for (int l = 0; l < nl; l++) {
+      KP_TRY(hipEventRecord(b->ev[1 + l], b->lanes[l]));
+      KP_TRY(hipStreamWaitEvent(b->st, b->ev[1 + l], 0));
+    }
+    return s;
+  }
+  std::vector<uintptr_t> key;
+  key.reserve(8 * n + 16);
+  for (int k = 0; k < n; k++) {
+    key.push_back((uintptr_t)thetas[k]);
+    key.push_back((uintptr_t)x_int[k]);
+    key.push_back((uintptr_t)y_int[k]);
+    key.push_back((uintptr_t)x_bnd[k]);
+    key.push_back((uintptr_t)y_bnd[k]);
+    key.push_back((uintptr_t)n_int[k]);
+    key.push_back((uintptr_t)n_bnd[k]);
+  }
+  key.push_back((uintptr_t)infos);
+  {
+    const unsigned char* hb = (const unsigned char*)hp;
+    for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);
+  }
+  if (!b->exec || key != b->key) {
+    batch_drop_graph(b);
+    // capture on the internal origin stream (the caller's may be the null stream)
+    KP_TRY(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipEventRecord(b->ev[0], b->origin);   // fork inside the capture
+    for (int l = 0; l < nl && e == hipSuccess; l++) e = hipStreamWaitEvent(b->lanes[l], b->ev[0], 0);
+    kp_status s = e == hipSuccess ? batch_enqueue(b, thetas, x_int, y_int, n_int, x_bnd, y_bnd,
+                                                  n_bnd, hp, infos)
+                                  : KP_ERR_HIP;
+    for (int l = 0; l < nl; l++) {
+      if (hipEventRecord(b->ev[1 + l], b->lanes[l]) != hipSuccess) s = KP_ERR_HIP;
+      if (hipStreamWaitEvent(b->origin, b->ev[1 + l], 0) != hipSuccess) s = KP_ERR_HIP;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->origin, &g);
+    if (s != KP_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess) kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+      return s != KP_OK ? s : KP_ERR_HIP;
+    }
+    b->graph = g;
+    KP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->key = key;
+  }
+  // ordered after the caller's earlier work and before its later work
+  KP_TRY(hipEventRecord(b->ev_in, b->st));
+  KP_TRY(hipStreamWaitEvent(b->origin, b->ev_in, 0));
+  KP_TRY(hipGraphLaunch(b->exec, b->origin));
+  KP_TRY(hipEventRecord(b->ev_out, b->origin));
+  KP_TRY(hipStreamWaitEvent(b->st, b->ev_out, 0));
+  return KP_OK;
 }
 
 }  // extern "C"

@@ -325,6 +325,23 @@ __global__ void k_ema_fill(double* a, long n, int dim, int identity) {
   a[e] = (identity && (e / dim) == (e % dim)) ? 1.0 : 0.0;
 }
 
+// Zero `words` 32-bit words (a kernel, not a memset node, so that captured
+// graphs replay it reliably).
+__global__ void k_zero_words(uint32_t* __restrict__ p, long words) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t st) {
+  const long words = (long)(bytes / 4);
+  if (words <= 0) return hipSuccess;
+  int nb = (int)((words + 255) / 256);
+  if (nb > 4096) nb = 4096;
+  k_zero_words<<<nb, 256, 0, st>>>((uint32_t*)p, words);
+  return hipGetLastError();
+}
+
 hipError_t ema_fill(double* a, long n, int dim, int identity, hipStream_t st) {
   k_ema_fill<<<(int)((n + 255) / 256), 256, 0, st>>>(a, n, dim, identity);
   return hipGetLastError();

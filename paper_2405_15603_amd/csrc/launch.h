@@ -77,6 +77,8 @@ hipError_t input_vjp(Prec p, const void* theta, int h_out, int d, const void* g1
 hipError_t axpy_theta(Prec p, const void* theta, const void* dir, double alpha, void* out, long D,
                       hipStream_t st);
 hipError_t ema_fill(double* a, long n, int dim, int identity, hipStream_t st);
+// zero a buffer of whole 32-bit words with a kernel (graph-capture safe)
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t st);
 // dhat = mu*delta + Delta  (real dhat, real delta, double Delta); use_mom = 0 -> dhat = Delta
 hipError_t momentum(Prec p, const double* Delta, const void* delta, double mu, const int* step,
                     void* dhat, long D, hipStream_t st);
@@ -114,9 +116,11 @@ struct EigProblem {
   double* Pout;       // n x n result P (row-major)
   double* eout;       // n eigenvalues
 };
-// warm != 0: start Jacobi from the V left in P[0] by the previous call
+// status: the context's control words (status[2..3] hold the call counter and
+// the warm-start flag).  Jacobi starts from the V left in P[0] by the previous
+// call, except on every refresh-th call (and the first after a reset).
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
-                            EigProblem* probs_dev, int* status, int warm, int max_sweeps,
+                            EigProblem* probs_dev, int* status, int refresh, int max_sweeps,
                             hipStream_t st);
 // Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T for every layer, V = gradient
 // (column-major h_out x (h_in+1) inside the theta layout).  Four strided FP64

@@ -236,7 +236,9 @@ __global__ __launch_bounds__(256) void k_trtri_row(const EigProblem* __restrict_
 //   mode 3: C0 <- V^T C1
 //   mode 4: P1 <- Li^T V         (Li^T upper: k >= bi)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ pr, int mode) {
+__global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ pr, int mode,
+                                                const int* __restrict__ warm) {
+  if (mode >= 2 && mode <= 3 && !*warm) return;   // the warm-start products only
   const EigProblem p = pr[blockIdx.z];
   const int nb = p.n_pad / BB;
   const int bi = blockIdx.y, bj = blockIdx.x;
@@ -286,8 +288,17 @@ __global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ p
       out[(long)(bi * BB + ty * 4 + a) * np + bj * BB + tx * 4 + b] = acc[a][b];
 }
 
+// Call counter and warm-start flag, decided on the device so that a captured
+// graph keeps the refresh schedule: calls[0] counts calls, calls[1] = warm.
+__global__ void k_eig_begin(int* calls, int refresh) {
+  const int n = calls[0];
+  calls[1] = (n % refresh) != 0;
+  calls[0] = n + 1;
+}
+
 // C <- (C + C^T)/2, V <- I on a cold start (kept on a warm start), flags reset
-__global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done, int warm) {
+__global__ void k_jac_init(const EigProblem* __restrict__ pr, int* done, const int* warmp) {
+  const int warm = *warmp;
   const EigProblem p = pr[blockIdx.y];
   const long np = p.n_pad;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < np * np;
@@ -552,13 +563,15 @@ __global__ void k_jac_extract(const EigProblem* __restrict__ pr) {
 }
 
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
-                            EigProblem* probs_dev, int* status, int warm, int max_sweeps,
+                            EigProblem* probs_dev, int* status, int refresh, int max_sweeps,
                             hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   int npmax = 0;
   for (int q = 0; q < nprob; q++) npmax = probs_host[q].n_pad > npmax ? probs_host[q].n_pad : npmax;
   const int nbmax = npmax / BB;
   int* done = status + 8;   // 2 ints per problem after the status block
+  int* calls = status + 2;  // call counter, warm flag
+  k_eig_begin<<<1, 1, 0, st>>>(calls, refresh);
   k_damp_pad<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, lambda);
   for (int j = 0; j < nbmax; j++) {
     k_chol_diag<<<dim3(1, nprob), 256, 0, st>>>(probs_dev, j, status);
@@ -570,13 +583,11 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
   }
   for (int i = 1; i < nbmax; i++) k_trtri_row<<<dim3(i, nprob), 256, 0, st>>>(probs_dev, i);
   const dim3 gmm(nbmax, nbmax, nprob);
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 0);
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 1);
-  if (warm) {
-    k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 2);
-    k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 3);
-  }
-  k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done, warm);
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 0, calls + 1);
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 1, calls + 1);
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 2, calls + 1);
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 3, calls + 1);
+  k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done, calls + 1);
   k_jac_dmax<<<nprob, 256, 0, st>>>(probs_dev);
   const int nblk = npmax / JB;
   const int npair = nblk / 2;
@@ -588,7 +599,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
     }
     k_jac_check<<<1, 64, 0, st>>>(probs_dev, done, nprob);
   }
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 4);
+  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 4, calls + 1);
   k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev);
   return hipGetLastError();
 }
