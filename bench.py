@@ -85,6 +85,37 @@ def run_gpu(problem, precision, steps, warmup, kernel_class=None, lr_mode="grid"
     return ms, tm, status, last
 
 
+def run_batch(count, steps, warmup, use_graph):
+    """One step of `count` heterogeneous instances per call (the 64-instance
+    recipe), as a captured graph or as direct launches on the internal lanes."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2405_15603_amd import KfacPinnBatch
+    dev = torch.device("cuda", 0)
+    probs = synth.batch_instances(count)
+    T = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float32, device=dev).contiguous()
+    thetas = [T(p.theta0()) for p in probs]
+    cols = list(zip(*[[T(a) for a in p.batch(0)] for p in probs]))
+    b = KfacPinnBatch(probs, "bf16", use_graph=use_graph)
+    hp = hparams()
+    for _ in range(warmup):
+        b.step(thetas, *cols, hp)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        b.step(thetas, *cols, hp)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    status = b.sync()
+    del b
+    return {"ms_per_step": ms, "instance_steps_per_s": count * 1000.0 / ms,
+            "status_nonzero": sum(1 for v in status if v != 0)}
+
+
 def copy_calibration(mib):
     """A plain elementwise copy of `mib` MiB (read once, written once), launched
     so that a rocprofv3 counter run can scale FETCH_SIZE / WRITE_SIZE."""
@@ -154,6 +185,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--no-core", action="store_true", help="skip the fixed-step (core) leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch leg")
     ap.add_argument("--kernel", default="ls_layer", choices=list(KERNEL_CLASSES))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain copy of this many MiB (counter calibration)")
@@ -214,6 +246,11 @@ def main():
         ms32, _, st32, _ = run_gpu(problem, "f32", max(2, args.steps // 2), 1, None)
         out["fp32"] = {"value": 1000.0 / ms32, "ms_per_step": ms32, "status": st32,
                        "mixed_over_fp32": ms32 / ms}
+    if not args.no_batch:
+        out["batch64"] = {"instances": 64, "note": "heterogeneous 64-instance recipe, mixed "
+                          "precision, grid line search; one step of every instance per call",
+                          "graph": run_batch(64, 3, 1, True),
+                          "direct": run_batch(64, 3, 1, False)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(out), flush=True)

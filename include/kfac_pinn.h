@@ -249,8 +249,9 @@ kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
  * `count` device pointers, n_int and n_bnd host arrays of sizes, infos a device
  * array of `count` summaries (or NULL).  The work is ordered after the work
  * already on `stream` and before anything enqueued there later.  The first
- * call captures the whole batch step into a HIP graph, later calls with the
- * same arguments replay it (different arguments recapture); with the graph
+ * call captures each lane's part of the batch step into a HIP graph, later
+ * calls with the same arguments replay them (different arguments recapture);
+ * with the graphs
  * disabled (kfac_pinn_batch_set_graph) every call enqueues the launches
  * directly.  Errors as for kfac_pinn_step; per-instance device status is read
  * with kfac_pinn_sync on kfac_pinn_batch_context(batch, k). */

@@ -1045,19 +1045,18 @@ kp_status kfac_pinn_sync(kfac_pinn_ctx* c) {
 // ---------------------------------------------------------------------------
 // Batches of independent instances (one step of each per call).  Instance k
 // runs on internal lane k % lanes, so the instances' small launches overlap.
-// The whole step of all instances is captured into one HIP graph on the first
-// call and replayed on later calls with the same arguments; different
-// arguments recapture.
+// Each lane's part of the batch step is captured into its own HIP graph on the
+// first call and replayed on later calls with the same arguments (different
+// arguments recapture); one graph per lane keeps the lanes concurrent.
 // ---------------------------------------------------------------------------
 struct kfac_pinn_batch {
   std::vector<kfac_pinn_ctx*> ctx;
   hipStream_t st = nullptr;       // the caller's stream (may be the null stream)
-  hipStream_t origin = nullptr;   // internal stream the graph is captured on and launched to
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;   // caller -> origin -> caller
+  hipEvent_t ev_in = nullptr;     // fork: lanes wait for the caller's earlier work
   std::vector<hipStream_t> lanes;
-  std::vector<hipEvent_t> ev;   // fork, then one join per lane
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  std::vector<hipEvent_t> ev;     // join: one per lane
+  std::vector<hipGraph_t> graph;  // one per lane
+  std::vector<hipGraphExec_t> exec;
   std::vector<uintptr_t> key;
   int use_graph = 1;
 };
@@ -1067,18 +1066,22 @@ constexpr int kBatchLanes = 8;
 constexpr int kMaxBatch = 1024;
 
 void batch_drop_graph(kfac_pinn_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+  for (hipGraphExec_t e : b->exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  for (hipGraph_t g : b->graph)
+    if (g) (void)hipGraphDestroy(g);
+  b->exec.clear();
+  b->graph.clear();
   b->key.clear();
 }
 
-kp_status batch_enqueue(kfac_pinn_batch* b, void* const* thetas, const void* const* xi,
-                        const void* const* yi, const int32_t* ni, const void* const* xb,
-                        const void* const* yb, const int32_t* nb, const kp_hparams* hp,
-                        kp_step_info* infos) {
-  for (size_t k = 0; k < b->ctx.size(); k++) {
+// the steps of the instances on lane l
+kp_status lane_enqueue(kfac_pinn_batch* b, int l, void* const* thetas, const void* const* xi,
+                       const void* const* yi, const int32_t* ni, const void* const* xb,
+                       const void* const* yb, const int32_t* nb, const kp_hparams* hp,
+                       kp_step_info* infos) {
+  const int nl = (int)b->lanes.size();
+  for (size_t k = l; k < b->ctx.size(); k += nl) {
     kp_status s = kfac_pinn_step(b->ctx[k], thetas[k], xi[k], yi[k], ni[k], xb[k], yb[k], nb[k],
                                  hp, infos ? infos + k : nullptr);
     if (s != KP_OK) return s;
@@ -1097,23 +1100,19 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
   const int nl = count < kBatchLanes ? count : kBatchLanes;
   for (int l = 0; l < nl; l++) {
     hipStream_t s;
+    hipEvent_t e;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       kfac_pinn_batch_destroy(b);
       return KP_ERR_HIP;
     }
     b->lanes.push_back(s);
-  }
-  for (int l = 0; l <= nl; l++) {
-    hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       kfac_pinn_batch_destroy(b);
       return KP_ERR_HIP;
     }
     b->ev.push_back(e);
   }
-  if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess) {
     kfac_pinn_batch_destroy(b);
     return KP_ERR_HIP;
   }
@@ -1133,14 +1132,11 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
 kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   if (!b) return KP_ERR_ARG;
   for (hipStream_t s : b->lanes) (void)hipStreamSynchronize(s);
-  if (b->origin) (void)hipStreamSynchronize(b->origin);
   batch_drop_graph(b);
   for (kfac_pinn_ctx* c : b->ctx) kfac_pinn_destroy(c);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
-  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
-  if (b->origin) (void)hipStreamDestroy(b->origin);
   delete b;
   return KP_OK;
 }
@@ -1167,63 +1163,64 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
          "null argument");
   const int n = (int)b->ctx.size();
   const int nl = (int)b->lanes.size();
-  if (!b->use_graph) {
-    // fork: every lane waits for the caller's stream
-    KP_TRY(hipEventRecord(b->ev[0], b->st));
-    for (int l = 0; l < nl; l++) KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev[0], 0));
-    kp_status s = batch_enqueue(b, thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp, infos);
-    for (int l = 0; l < nl; l++) {
-      KP_TRY(hipEventRecord(b->ev[1 + l], b->lanes[l]));
-      KP_TRY(hipStreamWaitEvent(b->st, b->ev[1 + l], 0));
+  if (b->use_graph) {
+    std::vector<uintptr_t> key;
+    key.reserve(7 * n + 16);
+    for (int k = 0; k < n; k++) {
+      key.push_back((uintptr_t)thetas[k]);
+      key.push_back((uintptr_t)x_int[k]);
+      key.push_back((uintptr_t)y_int[k]);
+      key.push_back((uintptr_t)x_bnd[k]);
+      key.push_back((uintptr_t)y_bnd[k]);
+      key.push_back((uintptr_t)n_int[k]);
+      key.push_back((uintptr_t)n_bnd[k]);
     }
-    return s;
-  }
-  std::vector<uintptr_t> key;
-  key.reserve(8 * n + 16);
-  for (int k = 0; k < n; k++) {
-    key.push_back((uintptr_t)thetas[k]);
-    key.push_back((uintptr_t)x_int[k]);
-    key.push_back((uintptr_t)y_int[k]);
-    key.push_back((uintptr_t)x_bnd[k]);
-    key.push_back((uintptr_t)y_bnd[k]);
-    key.push_back((uintptr_t)n_int[k]);
-    key.push_back((uintptr_t)n_bnd[k]);
-  }
-  key.push_back((uintptr_t)infos);
-  {
-    const unsigned char* hb = (const unsigned char*)hp;
-    for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);
-  }
-  if (!b->exec || key != b->key) {
-    batch_drop_graph(b);
-    // capture on the internal origin stream (the caller's may be the null stream)
-    KP_TRY(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipEventRecord(b->ev[0], b->origin);   // fork inside the capture
-    for (int l = 0; l < nl && e == hipSuccess; l++) e = hipStreamWaitEvent(b->lanes[l], b->ev[0], 0);
-    kp_status s = e == hipSuccess ? batch_enqueue(b, thetas, x_int, y_int, n_int, x_bnd, y_bnd,
-                                                  n_bnd, hp, infos)
-                                  : KP_ERR_HIP;
-    for (int l = 0; l < nl; l++) {
-      if (hipEventRecord(b->ev[1 + l], b->lanes[l]) != hipSuccess) s = KP_ERR_HIP;
-      if (hipStreamWaitEvent(b->origin, b->ev[1 + l], 0) != hipSuccess) s = KP_ERR_HIP;
+    key.push_back((uintptr_t)infos);
+    {
+      const unsigned char* hb = (const unsigned char*)hp;
+      for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);
     }
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->origin, &g);
-    if (s != KP_OK || e != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      if (e != hipSuccess) kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
-      return s != KP_OK ? s : KP_ERR_HIP;
+    if (b->exec.empty() || key != b->key) {
+      batch_drop_graph(b);
+      for (int l = 0; l < nl; l++) {
+        KP_TRY(hipStreamBeginCapture(b->lanes[l], hipStreamCaptureModeThreadLocal));
+        kp_status s = lane_enqueue(b, l, thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp,
+                                   infos);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->lanes[l], &g);
+        if (s != KP_OK || e != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          batch_drop_graph(b);
+          if (e != hipSuccess) kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+          return s != KP_OK ? s : KP_ERR_HIP;
+        }
+        b->graph.push_back(g);
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          batch_drop_graph(b);
+          kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+          return KP_ERR_HIP;
+        }
+        b->exec.push_back(x);
+      }
+      b->key = key;
     }
-    b->graph = g;
-    KP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    b->key = key;
   }
   // ordered after the caller's earlier work and before its later work
   KP_TRY(hipEventRecord(b->ev_in, b->st));
-  KP_TRY(hipStreamWaitEvent(b->origin, b->ev_in, 0));
-  KP_TRY(hipGraphLaunch(b->exec, b->origin));
-  KP_TRY(hipEventRecord(b->ev_out, b->origin));
-  KP_TRY(hipStreamWaitEvent(b->st, b->ev_out, 0));
+  for (int l = 0; l < nl; l++) {
+    KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev_in, 0));
+    if (b->use_graph) {
+      KP_TRY(hipGraphLaunch(b->exec[l], b->lanes[l]));
+    } else {
+      kp_status s = lane_enqueue(b, l, thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp,
+                                 infos);
+      if (s != KP_OK) return s;
+    }
+    KP_TRY(hipEventRecord(b->ev[l], b->lanes[l]));
+    KP_TRY(hipStreamWaitEvent(b->st, b->ev[l], 0));
+  }
   return KP_OK;
 }
 
