@@ -82,6 +82,7 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 // narrower wave tile (NARROW) to stay within registers.
 constexpr int kThreads = 512;
 template <int MODE, bool NARROW = false> struct Geo {
+  static constexpr int NWP = 4, NWN = 2, NW = 8, NT = kThreads;
   static constexpr int WP = 32, WN = (MODE == M_F64 || NARROW) ? 32 : 64;
   static constexpr int BP = 4 * WP, BN = 2 * WN;
   static constexpr int TI = WP / 16, TJ = WN / 16;
@@ -257,23 +258,34 @@ __device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
 // and MFMA columns are points.  epi(step, s, acc[q]) runs for the steps of a
 // pass in order once its products are complete.
 // ---------------------------------------------------------------------------
-constexpr int kStages = 3;
 __device__ __align__(16) u32x4 kZeroChunk = {0u, 0u, 0u, 0u};
 
-template <int MODE, bool NARROW, int NS>
+// Geometry of the direct-to-LDS forward kernel: NWP x NWN waves, each owning a
+// WP (points) x WN (neurons) tile; NS shared columns per pass; ST ring stages.
+// A wide neuron tile (256) reads each point tile's slab rows fewer times, and
+// four columns per pass amortise the epilogue and its store drain; with two
+// stages the ring is 128 KB.  Measured against 128 x 128 tiles with two or
+// three columns per pass and three or four stages, this is the fastest.
+template <int MODE> struct DGeo;
+template <> struct DGeo<M_BF16> {
+  static constexpr int NWP = 2, NWN = 4, WP = 32, WN = 64, NS = 4, ST = 2;
+  static constexpr int NW = NWP * NWN, NT = 64 * NW;
+  static constexpr int BP = NWP * WP, BN = NWN * WN;
+  static constexpr int TI = WP / 16, TJ = WN / 16;
+};
+
+template <class G, typename T>
 struct DmaCfg {
-  typedef Geo<MODE, NARROW> G;
-  typedef typename Op<MODE>::TL T;
   static constexpr int E = 16 / sizeof(T);            // elements per chunk
   static constexpr int BK = 128 / sizeof(T);          // k per tile (8 chunks)
   static constexpr int ACH = G::BP / 8, BCH = G::BN / 8;   // 1 KB chunks per tile
-  static constexpr int NCH = NS * ACH + BCH;
-  static constexpr int PER_WAVE = NCH / 8;
+  static constexpr int NCH = G::NS * ACH + BCH;
+  static constexpr int PER_WAVE = NCH / G::NW;
   static constexpr int STAGE = NCH * 1024;             // bytes
-  static_assert(NCH % 8 == 0, "every wave issues the same number of chunk loads");
+  static_assert(ACH % G::NW == 0 && BCH % G::NW == 0,
+                "every wave issues the same number of chunk loads of one operand");
 };
 template <int MODE> constexpr bool kDma = MODE == M_BF16;
-constexpr int kDmaNS = 2;
 
 __device__ __forceinline__ int swz(int r) { return (r >> 1) & 7; }
 
@@ -296,20 +308,20 @@ __device__ __forceinline__ double frag_dma<double>(const char* tile, int lane, i
   return *(const double*)(tile + r * 128 + (((k >> 1) ^ swz(r)) << 4) + ((k & 1) << 3));
 }
 
-template <int MODE, bool NARROW, int NS, class SOf, class Epi>
+template <int MODE, class G, class SOf, class Epi>
 __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL* __restrict__ A,
                                           long lda, int N, int p0,
                                           const typename Op<MODE>::TL* __restrict__ B, long ldb,
                                           int c0, int ncols, int K, int nsteps, SOf s_of,
                                           Epi epi) {
-  typedef DmaCfg<MODE, NARROW, NS> D;
-  typedef Geo<MODE, NARROW> G;
   typedef typename Op<MODE>::TL TL;
+  typedef DmaCfg<G, TL> D;
   typedef Mfma<TL> MF;
+  constexpr int NS = G::NS, kStages = G::ST, NW = G::NW;
   constexpr int E = D::E, BK = D::BK;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wp = wave >> 1, wn = wave & 1;
+  const int wp = wave / G::NWN, wn = wave % G::NWN;
   const int nk = (K + BK - 1) / BK;
   const int npass = (nsteps + NS - 1) / NS;
   const int total = npass * nk;
@@ -318,12 +330,11 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
 
   // Per-thread chunk coordinates are fixed for the whole loop: chunk slot j
   // (q = wave + 8 j) belongs to A tile j / (ACH / 8) or, past NS A tiles, to B.
-  static_assert(D::ACH % 8 == 0 && D::BCH % 8 == 0, "chunk slots map to one operand");
-  constexpr int JA = NS * D::ACH / 8;   // slots 0..JA-1 load A tiles, the rest B
+  constexpr int JA = NS * D::ACH / NW;   // slots 0..JA-1 load A tiles, the rest B
   int off[D::PER_WAVE], kin[D::PER_WAVE];   // element offset (without k0), chunk k offset
 #pragma unroll
   for (int j = 0; j < D::PER_WAVE; j++) {
-    const int q = wave + 8 * j;
+    const int q = wave + NW * j;
     if (j < JA) {
       const int r = (q % D::ACH) * 8 + rin;
       kin[j] = (pos ^ swz(r)) * E;
@@ -350,11 +361,11 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
     char* stage = lds + ist * D::STAGE;
 #pragma unroll
     for (int j = 0; j < D::PER_WAVE; j++) {
-      const TL* src = j < JA ? A + sbase[j / (D::ACH / 8)] + off[j] + k0 : B + off[j] + k0;
+      const TL* src = j < JA ? A + sbase[j / (D::ACH / NW)] + off[j] + k0 : B + off[j] + k0;
       if (last_k) src = k0 + kin[j] < K ? src : zchunk;
       __builtin_amdgcn_global_load_lds((const KP_GLOBAL void*)src,
                                        (__attribute__((address_space(3))) void*)(stage +
-                                                                                 (wave + 8 * j) * 1024),
+                                                                                 (wave + NW * j) * 1024),
                                        16, 0, 0);
     }
     if (++ikt == nk) { ikt = 0; ips++; }
@@ -377,11 +388,13 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
   for (int g = 0; g < total; g++) {
     // tile g must have landed: at most (tiles after g in flight) * PER_WAVE loads pending
     const int after = min(kStages - 2, total - 1 - g);
+    static_assert(kStages >= 2 && kStages <= 4, "up to two tiles in flight behind this one");
     if (drained || after <= 0) {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    } else {
-      static_assert(kStages == 3, "one tile in flight behind the current one");
+    } else if (after == 1) {
       asm volatile("s_waitcnt vmcnt(%0)" ::"n"(D::PER_WAVE) : "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(D::PER_WAVE * (kStages > 3 ? 2 : 1)) : "memory");
     }
     drained = false;
     // The waits above cover this wave's loads and the barrier the other waves'
@@ -470,10 +483,20 @@ __device__ __forceinline__ void put4(T* row, int cb, int lim, bool aligned, cons
 // Laplacian row's pre-activation.  Outputs: z rows (value, derivatives) of the
 // next slab, optional pre-activations, and the tables for the finishing pass.
 // ---------------------------------------------------------------------------
+template <int MODE>
+using FwdGeo = typename std::conditional<kDma<MODE>, DGeo<M_BF16>, Geo<MODE>>::type;
+
+template <int MODE> constexpr int fwd_smem() {
+  if constexpr (kDma<MODE>)
+    return DGeo<M_BF16>::ST * DmaCfg<DGeo<M_BF16>, bf16>::STAGE;
+  else
+    return (int)sizeof(typename Mainloop<MODE>::Smem);
+}
+
 template <int MODE, typename TZ>
-__global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
+__global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
   typedef Op<MODE> O;
-  typedef Geo<MODE> G;
+  typedef FwdGeo<MODE> G;
   typedef typename O::TC TC;
   typedef typename O::TL TL;
   typedef Mfma<TL> MF;
@@ -482,11 +505,10 @@ __global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
   // (except FP64, whose MFMA rows are not consecutive within a lane).
   constexpr bool TR = kDma<MODE>;
   constexpr bool VEC = TR && !std::is_same<TL, double>::value;
-  constexpr int SMEM = TR ? kStages * DmaCfg<MODE, false, kDmaNS>::STAGE
-                          : (int)sizeof(typename Mainloop<MODE>::Smem);
+  constexpr int SMEM = fwd_smem<MODE>();
   __shared__ __align__(16) char smem[SMEM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wp = wave >> 1, wn = wave & 1;
+  const int wp = wave / G::NWN, wn = wave % G::NWN;
   const int ntc = (a.h_out + G::BN - 1) / G::BN;
   const int ntp = (a.N + G::BP - 1) / G::BP;
   const int t = xcd_tile(blockIdx.x, ntp * ntc);
@@ -564,8 +586,8 @@ __global__ __launch_bounds__(kThreads) void k_fwdlap(FwdLayerArgs a) {
       }
   };
   if constexpr (TR)
-    sloop_dma<MODE, false, kDmaNS>(smem, (const TL*)a.zin, a.ldz, a.N, p0, (const TL*)a.w, a.ldw,
-                                   c0, a.h_out, a.K, nsteps, s_of, epi);
+    sloop_dma<MODE, G>(smem, (const TL*)a.zin, a.ldz, a.N, p0, (const TL*)a.w, a.ldw, c0,
+                       a.h_out, a.K, nsteps, s_of, epi);
   else
     sloop<MODE, false>(*(typename Mainloop<MODE>::Smem*)smem, (const typename O::TA*)a.zin, a.ldz,
                        a.N, p0, (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0,
@@ -823,7 +845,8 @@ static int choose_chunks(int tiles, int nd, int has_lap) {
 }
 
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
-  const int BP = 128, BN = mode == M_F64 ? 64 : 128;
+  const int BP = mode == M_BF16 ? DGeo<M_BF16>::BP : 128;
+  const int BN = mode == M_BF16 ? DGeo<M_BF16>::BN : (mode == M_F64 ? 64 : 128);
   const int tiles = ((N + BP - 1) / BP) * ((h_out + BN - 1) / BN);
   return choose_chunks(tiles, nd, has_lap);
 }
@@ -851,9 +874,12 @@ hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st)
     case M_F32:
       k_fwdlap<M_F32, float><<<tile_grid<M_F32>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
       break;
-    case M_BF16:
-      k_fwdlap<M_BF16, bf16><<<tile_grid<M_BF16>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
+    case M_BF16: {
+      typedef DGeo<M_BF16> G;
+      const dim3 g(((a.N + G::BP - 1) / G::BP) * ((a.h_out + G::BN - 1) / G::BN), nch);
+      k_fwdlap<M_BF16, bf16><<<g, G::NT, 0, st>>>(a);
       break;
+    }
     case M_BF16X3:
       k_fwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
       break;

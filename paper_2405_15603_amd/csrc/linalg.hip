@@ -350,6 +350,9 @@ constexpr int JS = 2 * JB;      // subproblem size
 constexpr int LDJ = JS + 1;
 constexpr double kJacTol = 1e-14;      // relative to the pivots
 constexpr double kJacAbs = 1e-13;      // relative to the largest diagonal entry
+#ifndef KP_JAC_INNER
+#define KP_JAC_INNER 1                   // inner sweeps per block-pair subproblem
+#endif
 
 __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict__ pr,
                                                    const int* __restrict__ done, int r,
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
   __shared__ double S[JS * LDJ];
   __shared__ double V[JS * LDJ];
   __shared__ double cs[JB], sn[JB];
-  __shared__ int pp[JB], qq[JB];
+  __shared__ int pp[JB], qq[JB], act[JB];
   __shared__ int any;
   const long np = p.n_pad;
   const double* C = p.C[0];
@@ -390,8 +393,13 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
     if (threadIdx.x == 0) p.pflag[i] = 1;
     return;
   }
+  // Inner cyclic sweeps over the 64 x 64 subproblem; a round whose rotations are
+  // all below threshold changes nothing and is skipped, and a sweep without any
+  // rotation ends the inner iteration.
   for (int sw = 0; sw < inner; sw++) {
+    int swept = 0;
     for (int rr = 0; rr < JS - 1; rr++) {
+      int active = 0;
       if (threadIdx.x < JB) {
         const int k = threadIdx.x;
         int a = rr_pos(k, rr, JS), b = rr_pos(JS - 1 - k, rr, JS);
@@ -403,13 +411,16 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
           const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           s = t * c;
+          active = 1;
         }
-        cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
+        cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b; act[k] = active;
       }
-      __syncthreads();
+      if (!__syncthreads_or(active)) continue;   // nothing to rotate in this round
+      swept = 1;
       // S <- J^T S J on 2x2 groups (rows of pair kx, columns of pair ky), V <- V J
       for (int e = threadIdx.x; e < JB * JB; e += blockDim.x) {
         const int kx = e / JB, ky = e % JB;
+        if (!(act[kx] | act[ky])) continue;
         const int a = pp[kx], b = qq[kx], f = pp[ky], g = qq[ky];
         const double c1 = cs[kx], s1 = sn[kx], c2 = cs[ky], s2 = sn[ky];
         const double saf = S[a * LDJ + f], sag = S[a * LDJ + g];
@@ -423,6 +434,7 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
       }
       for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
         const int k = e / JS, row = e % JS;
+        if (!act[k]) continue;
         const int a = pp[k], b = qq[k];
         const double c = cs[k], s = sn[k];
         const double xa = V[row * LDJ + a], xb = V[row * LDJ + b];
@@ -431,6 +443,7 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
       }
       __syncthreads();
     }
+    if (!swept) break;
   }
   double* Vo = p.V + (long)i * JS * JS;
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) Vo[e] = V[(e / JS) * LDJ + (e % JS)];
@@ -594,7 +607,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
   const int nwg = npair * (npair + 1) / 2 + npair * npair;
   for (int sw = 0; sw < max_sweeps; sw++) {
     for (int r = 0; r < nblk - 1; r++) {
-      k_jac_solve<<<dim3(npair, nprob), 256, 0, st>>>(probs_dev, done, r, 1);
+      k_jac_solve<<<dim3(npair, nprob), 256, 0, st>>>(probs_dev, done, r, KP_JAC_INNER);
       k_jac_apply<<<dim3(nwg, nprob), 256, 0, st>>>(probs_dev, done, r);
     }
     k_jac_check<<<1, 64, 0, st>>>(probs_dev, done, nprob);
