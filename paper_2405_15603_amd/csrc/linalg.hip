@@ -354,6 +354,46 @@ constexpr double kJacAbs = 1e-13;      // relative to the largest diagonal entry
 #define KP_JAC_INNER 1                   // inner sweeps per block-pair subproblem
 #endif
 
+// Jacobi rotation (c, s) that annihilates apq in [[app, apq], [apq, aqq]]
+// (Golub & Van Loan, Alg. 8.4.1): theta = (aqq - app) / (2 apq),
+// t = sign(theta) / (|theta| + sqrt(theta^2 + 1)), c = 1 / sqrt(1 + t^2), s = t c.
+// The reciprocals and inverse square roots start from the hardware estimates
+// and take Newton steps (each doubles the correct bits) to full precision; this
+// shortens the dependent chain that every round of the sweep waits for.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int i = 0; i < 3; i++) y = fma(y, fma(-x, y, 1.0), y);   // y (2 - x y)
+  return y;
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 3; i++) y = y * fma(-0.5 * x * y, y, 1.5);   // y (3 - x y^2) / 2
+  return y;
+}
+__device__ __forceinline__ void rotation(double app, double aqq, double apq, double& c,
+                                         double& s) {
+  if (!(fabs(apq) > 1e-150)) {   // outside the estimates' range: plain divisions
+    const double th = (aqq - app) / (2.0 * apq);
+    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+    c = 1.0 / sqrt(t * t + 1.0);
+    s = t * c;
+    return;
+  }
+  const double th = (aqq - app) * rcp_nr(2.0 * apq);
+  if (!(fabs(th) < 1e150)) {   // theta^2 would overflow: t = 1 / (2 theta)
+    c = 1.0;
+    s = 0.5 * rcp_nr(th);
+    return;
+  }
+  const double u = fma(th, th, 1.0);
+  const double su = u * rsqrt_nr(u);   // sqrt(theta^2 + 1)
+  const double t = copysign(rcp_nr(fabs(th) + su), th);
+  c = rsqrt_nr(fma(t, t, 1.0));
+  s = t * c;
+}
+
 __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict__ pr,
                                                    const int* __restrict__ done, int r,
                                                    int inner) {
@@ -368,7 +408,7 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
   __shared__ double S[JS * LDJ];
   __shared__ double V[JS * LDJ];
   __shared__ double cs[JB], sn[JB];
-  __shared__ int pp[JB], qq[JB], act[JB];
+  __shared__ int pp[JB], qq[JB];
   __shared__ int any;
   const long np = p.n_pad;
   const double* C = p.C[0];
@@ -393,34 +433,21 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
     if (threadIdx.x == 0) p.pflag[i] = 1;
     return;
   }
-  // Inner cyclic sweeps over the 64 x 64 subproblem; a round whose rotations are
-  // all below threshold changes nothing and is skipped, and a sweep without any
-  // rotation ends the inner iteration.
   for (int sw = 0; sw < inner; sw++) {
-    int swept = 0;
     for (int rr = 0; rr < JS - 1; rr++) {
-      int active = 0;
       if (threadIdx.x < JB) {
         const int k = threadIdx.x;
         int a = rr_pos(k, rr, JS), b = rr_pos(JS - 1 - k, rr, JS);
         if (a > b) { int t = a; a = b; b = t; }
         const double apq = S[a * LDJ + b], app = S[a * LDJ + a], aqq = S[b * LDJ + b];
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) {
-          const double th = (aqq - app) / (2.0 * apq);
-          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
-          active = 1;
-        }
-        cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b; act[k] = active;
+        if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) rotation(app, aqq, apq, c, s);
+        cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
       }
-      if (!__syncthreads_or(active)) continue;   // nothing to rotate in this round
-      swept = 1;
+      __syncthreads();
       // S <- J^T S J on 2x2 groups (rows of pair kx, columns of pair ky), V <- V J
       for (int e = threadIdx.x; e < JB * JB; e += blockDim.x) {
         const int kx = e / JB, ky = e % JB;
-        if (!(act[kx] | act[ky])) continue;
         const int a = pp[kx], b = qq[kx], f = pp[ky], g = qq[ky];
         const double c1 = cs[kx], s1 = sn[kx], c2 = cs[ky], s2 = sn[ky];
         const double saf = S[a * LDJ + f], sag = S[a * LDJ + g];
@@ -434,7 +461,6 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
       }
       for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
         const int k = e / JS, row = e % JS;
-        if (!act[k]) continue;
         const int a = pp[k], b = qq[k];
         const double c = cs[k], s = sn[k];
         const double xa = V[row * LDJ + a], xb = V[row * LDJ + b];
@@ -443,7 +469,6 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
       }
       __syncthreads();
     }
-    if (!swept) break;
   }
   double* Vo = p.V + (long)i * JS * JS;
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) Vo[e] = V[(e / JS) * LDJ + (e % JS)];
