@@ -394,7 +394,9 @@ __device__ __forceinline__ void rotation(double app, double aqq, double apq, dou
   s = t * c;
 }
 
-__global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict__ pr,
+constexpr int kSolveThreads = 512;
+
+__global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* __restrict__ pr,
                                                    const int* __restrict__ done, int r,
                                                    int inner) {
   const int q = blockIdx.y;
@@ -445,27 +447,53 @@ __global__ __launch_bounds__(256) void k_jac_solve(const EigProblem* __restrict_
         cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
       }
       __syncthreads();
-      // S <- J^T S J on 2x2 groups (rows of pair kx, columns of pair ky), V <- V J
-      for (int e = threadIdx.x; e < JB * JB; e += blockDim.x) {
-        const int kx = e / JB, ky = e % JB;
-        const int a = pp[kx], b = qq[kx], f = pp[ky], g = qq[ky];
-        const double c1 = cs[kx], s1 = sn[kx], c2 = cs[ky], s2 = sn[ky];
-        const double saf = S[a * LDJ + f], sag = S[a * LDJ + g];
-        const double sbf = S[b * LDJ + f], sbg = S[b * LDJ + g];
-        const double raf = c1 * saf - s1 * sbf, rag = c1 * sag - s1 * sbg;
-        const double rbf = s1 * saf + c1 * sbf, rbg = s1 * sag + c1 * sbg;
-        S[a * LDJ + f] = c2 * raf - s2 * rag;
-        S[a * LDJ + g] = s2 * raf + c2 * rag;
-        S[b * LDJ + f] = c2 * rbf - s2 * rbg;
-        S[b * LDJ + g] = s2 * rbf + c2 * rbg;
-      }
-      for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
-        const int k = e / JS, row = e % JS;
-        const int a = pp[k], b = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double xa = V[row * LDJ + a], xb = V[row * LDJ + b];
-        V[row * LDJ + a] = c * xa - s * xb;
-        V[row * LDJ + b] = s * xa + c * xb;
+      // S <- J^T S J on 2x2 groups (rows of pair kx, columns of pair ky), V <- V J.
+      // The groups (and the V element pairs) are disjoint, so each thread loads
+      // all of its operands before computing and storing: the LDS latency is paid
+      // once per phase instead of once per element.
+      constexpr int SG = JB * JB / kSolveThreads, VG = JB * JS / kSolveThreads;
+      {
+        double x[SG][4];
+        int ia[SG], ib[SG], jf[SG], jg[SG];
+        double c1[SG], s1[SG], c2[SG], s2[SG];
+#pragma unroll
+        for (int it = 0; it < SG; it++) {
+          const int e = threadIdx.x + it * kSolveThreads;
+          const int kx = e / JB, ky = e % JB;
+          ia[it] = pp[kx]; ib[it] = qq[kx]; jf[it] = pp[ky]; jg[it] = qq[ky];
+          c1[it] = cs[kx]; s1[it] = sn[kx]; c2[it] = cs[ky]; s2[it] = sn[ky];
+          x[it][0] = S[ia[it] * LDJ + jf[it]];
+          x[it][1] = S[ia[it] * LDJ + jg[it]];
+          x[it][2] = S[ib[it] * LDJ + jf[it]];
+          x[it][3] = S[ib[it] * LDJ + jg[it]];
+        }
+        double y[VG][2];
+        int va[VG], vb[VG], vr[VG];
+        double vc[VG], vs[VG];
+#pragma unroll
+        for (int it = 0; it < VG; it++) {
+          const int e = threadIdx.x + it * kSolveThreads;
+          const int k = e / JS;
+          vr[it] = e % JS; va[it] = pp[k]; vb[it] = qq[k]; vc[it] = cs[k]; vs[it] = sn[k];
+          y[it][0] = V[vr[it] * LDJ + va[it]];
+          y[it][1] = V[vr[it] * LDJ + vb[it]];
+        }
+#pragma unroll
+        for (int it = 0; it < SG; it++) {
+          const double raf = c1[it] * x[it][0] - s1[it] * x[it][2];
+          const double rag = c1[it] * x[it][1] - s1[it] * x[it][3];
+          const double rbf = s1[it] * x[it][0] + c1[it] * x[it][2];
+          const double rbg = s1[it] * x[it][1] + c1[it] * x[it][3];
+          S[ia[it] * LDJ + jf[it]] = c2[it] * raf - s2[it] * rag;
+          S[ia[it] * LDJ + jg[it]] = s2[it] * raf + c2[it] * rag;
+          S[ib[it] * LDJ + jf[it]] = c2[it] * rbf - s2[it] * rbg;
+          S[ib[it] * LDJ + jg[it]] = s2[it] * rbf + c2[it] * rbg;
+        }
+#pragma unroll
+        for (int it = 0; it < VG; it++) {
+          V[vr[it] * LDJ + va[it]] = vc[it] * y[it][0] - vs[it] * y[it][1];
+          V[vr[it] * LDJ + vb[it]] = vs[it] * y[it][0] + vc[it] * y[it][1];
+        }
       }
       __syncthreads();
     }
@@ -632,7 +660,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
   const int nwg = npair * (npair + 1) / 2 + npair * npair;
   for (int sw = 0; sw < max_sweeps; sw++) {
     for (int r = 0; r < nblk - 1; r++) {
-      k_jac_solve<<<dim3(npair, nprob), 256, 0, st>>>(probs_dev, done, r, KP_JAC_INNER);
+      k_jac_solve<<<dim3(npair, nprob), kSolveThreads, 0, st>>>(probs_dev, done, r, KP_JAC_INNER);
       k_jac_apply<<<dim3(nwg, nprob), 256, 0, st>>>(probs_dev, done, r);
     }
     k_jac_check<<<1, 64, 0, st>>>(probs_dev, done, nprob);
