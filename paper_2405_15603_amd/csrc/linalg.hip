@@ -533,9 +533,9 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
   int w = blockIdx.x;
   if (w >= ncg + npair * npair) return;
   const long np = p.n_pad;
+  // two LDS tiles (two workgroups fit a CU): the C block and one rotation block
   __shared__ double G[BB * LDB];
-  __shared__ double VX[BB * LDB];
-  __shared__ double VY[BB * LDB];
+  __shared__ double W[BB * LDB];
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   double acc[4][4];
   if (w < ncg) {
@@ -551,24 +551,26 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
     for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
       const int a = e / BB, b = e % BB;
       G[a * LDB + b] = C[grow(a, x0, x1) * np + grow(b, y0, y1)];
-      if (!ix) VX[a * LDB + b] = p.V[(long)pX * BB * BB + e];
-      if (!iy) VY[a * LDB + b] = p.V[(long)pY * BB * BB + e];
+      if (!iy) W[a * LDB + b] = p.V[(long)pY * BB * BB + e];
     }
     __syncthreads();
     if (!iy) {
       zero4(acc);
-      blk_mm<false, false>(acc, G, VY);
+      blk_mm<false, false>(acc, G, W);
       __syncthreads();
 #pragma unroll
       for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int b = 0; b < 4; b++) G[(ty * 4 + a) * LDB + tx * 4 + b] = acc[a][b];
-      __syncthreads();
     }
     if (!ix) {
+      for (int e = threadIdx.x; e < BB * BB; e += blockDim.x)
+        W[(e / BB) * LDB + (e % BB)] = p.V[(long)pX * BB * BB + e];
+      __syncthreads();
       zero4(acc);
-      blk_mm<true, false>(acc, VX, G);
+      blk_mm<true, false>(acc, W, G);
     } else {
+      __syncthreads();
 #pragma unroll
       for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -592,11 +594,11 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
     for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
       const int a = e / BB, b = e % BB;
       G[a * LDB + b] = P[((long)R * BB + a) * np + grow(b, y0, y1)];
-      VY[a * LDB + b] = p.V[(long)pY * BB * BB + e];
+      W[a * LDB + b] = p.V[(long)pY * BB * BB + e];
     }
     __syncthreads();
     zero4(acc);
-    blk_mm<false, false>(acc, G, VY);
+    blk_mm<false, false>(acc, G, W);
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
