@@ -88,6 +88,7 @@ struct kfac_pinn_ctx {
   size_t ws_limit = 0;
   hipStream_t st = nullptr;
   long D = 0;
+  void* qbuf = nullptr;     // input layer: sums of squared weights and transposed weights
   NetDesc nd{};
   std::vector<long> off, ldz, ldp, ldg;
   long ldz_max = 0, ldp_max = 0;
@@ -226,6 +227,7 @@ struct FwdTarget {
   std::function<void*(int)> sq;    // sum of squares table of layer l (or nullptr)
   void* u;                      // output rows
   int kc_layer = KC_LAYER_GEMM;  // timing class of the layer products
+  bool full_input = true;        // write every row of the input slab (false: value rows)
 };
 
 // Forward through hidden layers [0, upto) and, when upto == L, the output layer.
@@ -233,7 +235,11 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
                        const FwdTarget& T) {
   hipError_t e;
   const long R = (long)n * s.S;
-  if ((e = input_slab(T.zp, x, n, c->d, s.S, T.z(0), c->ldz[0], c->st)) != hipSuccess) return e;
+  // Only the layer products read the input slab's derivative and Laplacian rows
+  // (unit vectors and zeros); the input layer handles those rows without them,
+  // so a pass that needs no input-layer factors writes the value rows only.
+  const int s_in = (T.full_input || !s.has_lap) ? s.S : 1;
+  if ((e = input_slab(T.zp, x, n, c->d, s_in, T.z(0), c->ldz[0], c->st)) != hipSuccess) return e;
   const int nh = upto < c->L ? upto : c->L - 1;
   for (int l = 0; l < nh; l++) {
     const LayerDesc& ld = c->nd.l[l];
@@ -259,13 +265,23 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
     a.tab_lap = s.has_lap ? wptr(c->tab, ts, c->esz_c) : nullptr;
     a.tab_sq = s.has_lap ? wptr(c->tab, 2 * ts, c->esz_c) : nullptr;
     a.sq_out = T.sq(l);
-    const int nch = fwdlap_chunks(T.mode, n, ld.h_out, s.nd, s.has_lap);
+    // input layer: only the value row needs products (its other input rows are
+    // unit vectors and zeros)
+    const bool input_rows = l == 0 && s.has_lap;
+    a.value_only = input_rows ? 1 : 0;
+    const int nch = input_rows ? 1 : fwdlap_chunks(T.mode, n, ld.h_out, s.nd, s.has_lap);
+    const double Rp = input_rows ? (double)n : (double)R;   // rows with products
     int ti = tm_begin(c, T.kc_layer);
     if ((e = fwdlap_main(T.mode, a, nch, c->st)) != hipSuccess) return e;
-    tm_end(c, ti, 2.0 * R * ld.h_out * (ld.h_in + 1),
-           (double)R * (ld.h_in + 1 + ld.h_out) * T.zesz + (double)ld.h_out * (ld.h_in + 1) * c->esz_w);
+    tm_end(c, ti, 2.0 * Rp * ld.h_out * (ld.h_in + 1),
+           Rp * (ld.h_in + 1) * T.zesz + (double)R * ld.h_out * T.zesz +
+               (double)ld.h_out * (ld.h_in + 1) * c->esz_w);
     ti = tm_begin(c, KC_ACT);
-    if ((e = fwdlap_finish(T.mode, a, nch, c->st)) != hipSuccess) return e;
+    if (input_rows)
+      e = input_layer_rows(T.mode, a, c->qbuf, c->st);
+    else
+      e = fwdlap_finish(T.mode, a, nch, c->st);
+    if (e != hipSuccess) return e;
     tm_end(c, ti, 0.0, 0.0);
   }
   if (upto >= c->L) {
@@ -462,6 +478,7 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   T.sq = [](int) -> void* { return nullptr; };
   T.u = c->ls_u;
   T.kc_layer = KC_LS_LAYER;
+  T.full_input = false;
   int acc = 0;
   if (ni > 0) {
     if ((e = forward_run(c, c->si, xi, ni, c->L, T)) != hipSuccess) return e;
@@ -649,6 +666,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   ALLOC(c->dhat, c->esz_p * c->D);
   ALLOC(c->delta, c->esz_p * c->D);
   ALLOC(c->ctl, sizeof(int) * 128);
+  ALLOC(c->qbuf, sizeof(double) * (size_t)(c->d + 1) * c->w[1]);
 
   // eigenproblems: layer l side A (h_in+1) and side B (h_out)
   for (int l = 0; l < c->L; l++)

@@ -25,6 +25,7 @@ struct FwdLayerArgs {
   void* tab_sq;      // nch*N*h_out: chunk partial sums of squared derivative rows
   void* tab_lap;     // N*h_out: Laplacian-row pre-activation
   void* sq_out;      // optional N*h_out: total sum of squares (kept for the backward)
+  int value_only;    // products for the value row only (the input layer, see input_layer_rows)
 };
 
 struct BwdLayerArgs {
@@ -49,6 +50,13 @@ struct BwdLayerArgs {
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap);
 hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
 hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
+// The input layer's derivative and Laplacian rows without products: its input
+// rows are unit vectors and zero, so a_i = W[:, i] for every point and a_Lap = 0.
+// Writes z for rows s >= 1 (z_i = s1 W[:, i], z_Lap = s2 sum_{i in mask} W[:, i]^2),
+// the bias column and padding of every row, pre and sq_out when given.  Reads t
+// from tab_t (written by the value-only product).  q: scratch of (nd + 1) * h_out
+// values of the compute type.
+hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_t st);
 int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap);
 hipError_t bwdlap_main(int mode, const BwdLayerArgs& a, int nch, hipStream_t st);
 hipError_t bwdlap_finish(int mode, const BwdLayerArgs& a, int nch, hipStream_t st);

@@ -517,8 +517,8 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
   const int nd = a.nd;
   const int len = (nd + nch - 1) / nch;
   const int dbeg = 1 + chunk * len, dend = min(1 + nd, dbeg + len);
-  const int nder = max(0, dend - dbeg);
-  const bool lap_here = a.has_lap && chunk == nch - 1;
+  const int nder = a.value_only ? 0 : max(0, dend - dbeg);
+  const bool lap_here = a.has_lap && !a.value_only && chunk == nch - 1;
   const int nsteps = 1 + nder + (lap_here ? 1 : 0);
   const int S = a.S;
   const bool tab_vec = (a.h_out & 3) == 0;
@@ -829,6 +829,123 @@ __global__ void k_bwd_last(BwdLayerArgs a, const TSd* __restrict__ sigma, long l
 }
 
 // ---------------------------------------------------------------------------
+// Input layer without products for its unit-vector rows (Section 3.1: the
+// input's derivative rows are e_i and its Laplacian row is zero).
+// ---------------------------------------------------------------------------
+// Per neuron c: the input layer's weights of the derivative rows, stored
+// transposed (wt[i * h_out + c] = W[c, i] in the product precision, W = hi [+ lo])
+// so that row writers read them coalesced, and q[c] = sum_{i in mask} W[c, i]^2.
+template <typename TW, typename TC>
+__global__ void k_input_q(FwdLayerArgs a, TC* __restrict__ q, TC* __restrict__ wt) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.h_out) return;
+  const TW* w = (const TW*)a.w + (long)c * a.ldw;
+  const TW* w2 = a.w2 ? (const TW*)a.w2 + (long)c * a.ldw : nullptr;
+  TC sum = 0;
+  for (int i = 0; i < a.nd; i++) {
+    const TC v = (TC)to_d(w[i]) + (w2 ? (TC)to_d(w2[i]) : (TC)0);
+    wt[(long)i * a.h_out + c] = v;
+    if (mask_at(a.mask, i)) sum += v * v;
+  }
+  q[c] = sum;
+}
+
+// Eight consecutive values to z (one 16-byte store for BF16, two for FP32).
+template <typename TZ, typename TC>
+__device__ __forceinline__ void store8(TZ* dst, const TC (&v)[8]) {
+  if constexpr (std::is_same<TZ, bf16>::value) {
+    bf16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; e++) o[e] = (bf16)(float)v[e];
+    *gmem((bf16x8*)dst) = o;
+  } else if constexpr (std::is_same<TZ, float>::value) {
+    const f32x4 lo = {(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    const f32x4 hi = {(float)v[4], (float)v[5], (float)v[6], (float)v[7]};
+    *gmem((f32x4*)dst) = lo;
+    *gmem((f32x4*)(dst + 4)) = hi;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; e++) dst[e] = cvt<TZ>((double)v[e]);
+  }
+}
+
+// Eight consecutive compute-type values (two 16-byte loads for FP32).
+template <typename TC>
+__device__ __forceinline__ void load8(const TC* src, TC (&v)[8]) {
+  if constexpr (std::is_same<TC, float>::value) {
+    const f32x4 lo = *gmem((const f32x4*)src), hi = *gmem((const f32x4*)(src + 4));
+#pragma unroll
+    for (int e = 0; e < 4; e++) { v[e] = lo[e]; v[e + 4] = hi[e]; }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; e++) v[e] = src[e];
+  }
+}
+
+// One wave per row (rows s >= 1, and the padding of the value rows), a lane per
+// 8 consecutive columns; grid-stride over rows.  ldzo is a multiple of 8; the
+// vector path needs h_out to be one too (else every block takes the scalar path).
+template <typename TC, typename TZ>
+__global__ __launch_bounds__(256) void k_input_rows(FwdLayerArgs a, const TC* __restrict__ q,
+                                                    const TC* __restrict__ wt) {
+  const int lane = threadIdx.x & 63;
+  const long nrows = (long)a.S * a.N;
+  const long wave0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+  const bool vec = (a.h_out & 7) == 0;
+  TZ* z = (TZ*)a.z;
+  for (long r = wave0; r < nrows; r += nwaves) {
+    const int s = (int)(r / a.N), p = (int)(r - (long)s * a.N);
+    const bool lap = s == a.S - 1;
+    const TC* trow = (const TC*)a.tab_t + (long)p * a.h_out;
+    for (int c0 = lane * 8; c0 < a.ldzo; c0 += 512) {
+      TC zo[8], po[8];
+      if (s > 0 && vec && c0 + 8 <= a.h_out) {   // full block of real columns
+        TC t[8], w[8];
+        load8(trow + c0, t);
+        if (!lap) load8(wt + (long)(s - 1) * a.h_out + c0, w);
+        else load8(q + c0, w);
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+          const TC s1 = (TC)1 - t[e] * t[e];
+          zo[e] = lap ? (TC)-2 * t[e] * s1 * w[e] : s1 * w[e];
+          po[e] = lap ? (TC)0 : w[e];
+        }
+        store8(z + r * a.ldzo + c0, zo);
+        if (a.pre)
+#pragma unroll
+          for (int e = 0; e < 8; e++) ((TC*)a.pre)[r * a.ldp + c0 + e] = po[e];
+        if (lap && a.sq_out)
+#pragma unroll
+          for (int e = 0; e < 8; e++) ((TC*)a.sq_out)[(long)p * a.h_out + c0 + e] = w[e];
+        continue;
+      }
+      // padding, a block straddling h_out, or the value row's padding
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        const int c = c0 + e;
+        if (s == 0 && c < a.h_out) continue;   // value row: from the products
+        TC zv = (c == a.h_out && s == 0) ? (TC)1 : (TC)0;
+        if (c < a.h_out) {
+          const TC t = trow[c];
+          const TC s1 = (TC)1 - t * t;
+          TC pv = 0;
+          if (!lap) {
+            pv = wt[(long)(s - 1) * a.h_out + c];
+            zv = s1 * pv;
+          } else {
+            zv = (TC)-2 * t * s1 * q[c];
+            if (a.sq_out) ((TC*)a.sq_out)[(long)p * a.h_out + c] = q[c];
+          }
+          if (a.pre) ((TC*)a.pre)[r * a.ldp + c] = pv;
+        }
+        z[r * a.ldzo + c] = cvt<TZ>((double)zv);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static dim3 pc_grid(long cols, int npts, int bs) {
@@ -898,6 +1015,44 @@ hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t s
     case M_BF16: k_fwdlap_finish<float, bf16><<<g, 64, 0, st>>>(a, nch); break;
     case M_BF16X3: k_fwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
     default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  if (!a.has_lap || a.S != a.nd + 2) return hipErrorInvalidValue;
+  if (a.ldzo % 8) return hipErrorInvalidValue;
+  const int nq = (a.h_out + 63) / 64;
+  const long rows = (long)a.S * a.N;
+  const int g = (int)std::min<long>(4096, (rows + 3) / 4);   // 4 rows (waves) per block
+  switch (mode) {
+    case M_F64: {
+      double* qq = (double*)q;
+      k_input_q<double, double><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_rows<double, double><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
+      break;
+    }
+    case M_F32: {
+      float* qq = (float*)q;
+      k_input_q<float, float><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
+      break;
+    }
+    case M_BF16: {
+      float* qq = (float*)q;
+      k_input_q<bf16, float><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_rows<float, bf16><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
+      break;
+    }
+    case M_BF16X3: {
+      float* qq = (float*)q;
+      k_input_q<bf16, float><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
