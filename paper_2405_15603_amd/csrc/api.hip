@@ -228,6 +228,7 @@ struct FwdTarget {
   void* u;                      // output rows
   int kc_layer = KC_LAYER_GEMM;  // timing class of the layer products
   bool full_input = true;        // write every row of the input slab (false: value rows)
+  bool residual_rows = false;    // interior: only the output rows the residual reads
 };
 
 // Forward through hidden layers [0, upto) and, when upto == L, the output layer.
@@ -238,7 +239,7 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
   // Only the layer products read the input slab's derivative and Laplacian rows
   // (unit vectors and zeros); the input layer handles those rows without them,
   // so a pass that needs no input-layer factors writes the value rows only.
-  const int s_in = (T.full_input || !s.has_lap) ? s.S : 1;
+  const int s_in = (T.full_input || !s.has_lap || c->L < 2) ? s.S : 1;
   if ((e = input_slab(T.zp, x, n, c->d, s_in, T.z(0), c->ldz[0], c->st)) != hipSuccess) return e;
   const int nh = upto < c->L ? upto : c->L - 1;
   for (int l = 0; l < nh; l++) {
@@ -265,6 +266,14 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
     a.tab_lap = s.has_lap ? wptr(c->tab, ts, c->esz_c) : nullptr;
     a.tab_sq = s.has_lap ? wptr(c->tab, 2 * ts, c->esz_c) : nullptr;
     a.sq_out = T.sq(l);
+    if (T.residual_rows && s.has_lap && l == c->L - 2 && upto >= c->L) {
+      // the output layer reads only the time and Laplacian rows of this layer's z
+      a.sparse_store = 1;
+      a.keep_value = 0;
+      const int tr = time_row_of(c, s);
+      a.keep_lo = tr >= 0 ? tr : 1;
+      a.keep_hi = tr >= 0 ? tr : 0;
+    }
     // input layer: only the value row needs products (its other input rows are
     // unit vectors and zeros)
     const bool input_rows = l == 0 && s.has_lap;
@@ -286,9 +295,22 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
   }
   if (upto >= c->L) {
     const LayerDesc& ld = c->nd.l[c->L - 1];
-    if ((e = last_fwd(T.mode, T.z(c->L - 1), c->ldz[c->L - 1],
-                      wptr(T.theta, ld.off, c->esz_p), ld.h_in + 1, R, T.u, c->st)) != hipSuccess)
+    const long lz = c->ldz[c->L - 1];
+    const void* wl = wptr(T.theta, ld.off, c->esz_p);
+    if (T.residual_rows && s.has_lap && c->L >= 2) {
+      // only the rows the interior residual reads: the time row and the Laplacian row
+      const int rows[2] = {time_row_of(c, s), lap_row_of(s)};
+      for (int k = 0; k < 2; k++) {
+        if (rows[k] < 0) continue;
+        const long off = (long)rows[k] * n;
+        if ((e = last_fwd(T.mode, wptr(T.z(c->L - 1), off * lz, T.zesz), lz, wl, ld.h_in + 1, n,
+                          wptr(T.u, off, c->esz_c), c->st)) != hipSuccess)
+          return e;
+      }
+    } else if ((e = last_fwd(T.mode, T.z(c->L - 1), lz, wl, ld.h_in + 1, R, T.u, c->st)) !=
+               hipSuccess) {
       return e;
+    }
   }
   return hipSuccess;
 }
@@ -479,6 +501,7 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   T.u = c->ls_u;
   T.kc_layer = KC_LS_LAYER;
   T.full_input = false;
+  T.residual_rows = true;
   int acc = 0;
   if (ni > 0) {
     if ((e = forward_run(c, c->si, xi, ni, c->L, T)) != hipSuccess) return e;

@@ -26,6 +26,9 @@ struct FwdLayerArgs {
   void* tab_lap;     // N*h_out: Laplacian-row pre-activation
   void* sq_out;      // optional N*h_out: total sum of squares (kept for the backward)
   int value_only;    // products for the value row only (the input layer, see input_layer_rows)
+  int sparse_store;  // 1: z rows are stored only where needed: the value row if
+  int keep_value;    //    keep_value, derivative rows s in [keep_lo, keep_hi]
+  int keep_lo, keep_hi;   //    (the Laplacian row is always finished)
 };
 
 struct BwdLayerArgs {

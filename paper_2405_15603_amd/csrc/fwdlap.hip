@@ -544,6 +544,9 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
     const bool is_d = s >= 1 && s <= nd;
     const TC m = (is_d && mask_at(a.mask, s - 1)) ? (TC)1 : (TC)0;
     const int kind = s == 0 ? 0 : (is_d ? 1 : 2);
+    // whether this z row is stored (the Laplacian row is finished separately)
+    const bool keep = !a.sparse_store || (kind == 0 ? a.keep_value != 0
+                                                    : (s >= a.keep_lo && s <= a.keep_hi));
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
 #pragma unroll
@@ -566,7 +569,7 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
           if (p >= a.N) continue;
           const long row = (long)s * a.N + p;
           if (kind == 0 && chunk != 0) continue;
-          if (kind <= 1) put4((TZ*)a.z + row * a.ldzo, cb, a.h_out, true, out);
+          if (kind <= 1 && keep) put4((TZ*)a.z + row * a.ldzo, cb, a.h_out, true, out);
           if (a.pre) put4((TC*)a.pre + row * a.ldp, cb, a.h_out, true, v);
           if (kind == 0 && a.tab_t) put4((TC*)a.tab_t + (long)p * a.h_out, cb, a.h_out, tab_vec, out);
           if (kind == 2) put4((TC*)a.tab_lap + (long)p * a.h_out, cb, a.h_out, tab_vec, v);
@@ -577,7 +580,7 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
             if (p >= a.N || c >= a.h_out) continue;
             const long row = (long)s * a.N + p;
             if (kind == 0 && chunk != 0) continue;
-            if (kind <= 1) ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)out[e]);
+            if (kind <= 1 && keep) ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)out[e]);
             if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v[e];
             if (kind == 0 && a.tab_t) ((TC*)a.tab_t)[(long)p * a.h_out + c] = out[e];
             if (kind == 2) ((TC*)a.tab_lap)[(long)p * a.h_out + c] = v[e];
