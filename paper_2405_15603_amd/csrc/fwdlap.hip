@@ -264,11 +264,13 @@ __device__ __align__(16) u32x4 kZeroChunk = {0u, 0u, 0u, 0u};
 // WP (points) x WN (neurons) tile; NS shared columns per pass; ST ring stages.
 // A wide neuron tile (256) reads each point tile's slab rows fewer times, and
 // four columns per pass amortise the epilogue and its store drain; with two
-// stages the ring is 128 KB.  Measured against 128 x 128 tiles with two or
-// three columns per pass and three or four stages, this is the fastest.
+// stages the ring is 128 KB.  Measured against 128 x 128 tiles, two or three
+// columns per pass, three or four stages and 64-byte k-tiles, this is the
+// fastest.
 template <int MODE> struct DGeo;
 template <> struct DGeo<M_BF16> {
   static constexpr int NWP = 2, NWN = 4, WP = 32, WN = 64, NS = 4, ST = 2;
+  static constexpr int RB = 128;   // bytes of a k-tile row (64-byte rows with more stages were slower)
   static constexpr int NW = NWP * NWN, NT = 64 * NW;
   static constexpr int BP = NWP * WP, BN = NWN * WN;
   static constexpr int TI = WP / 16, TJ = WN / 16;
@@ -276,9 +278,12 @@ template <> struct DGeo<M_BF16> {
 
 template <class G, typename T>
 struct DmaCfg {
+  static constexpr int RB = G::RB;                    // row bytes: 128 or 64
+  static constexpr int CPR = RB / 16;                 // 16-byte chunks per row
+  static constexpr int RPI = 1024 / RB;               // rows per 1 KB load instruction
   static constexpr int E = 16 / sizeof(T);            // elements per chunk
-  static constexpr int BK = 128 / sizeof(T);          // k per tile (8 chunks)
-  static constexpr int ACH = G::BP / 8, BCH = G::BN / 8;   // 1 KB chunks per tile
+  static constexpr int BK = RB / sizeof(T);           // k per tile
+  static constexpr int ACH = G::BP / RPI, BCH = G::BN / RPI;   // 1 KB chunks per tile
   static constexpr int NCH = G::NS * ACH + BCH;
   static constexpr int PER_WAVE = NCH / G::NW;
   static constexpr int STAGE = NCH * 1024;             // bytes
@@ -287,25 +292,25 @@ struct DmaCfg {
 };
 template <int MODE> constexpr bool kDma = MODE == M_BF16;
 
-__device__ __forceinline__ int swz(int r) { return (r >> 1) & 7; }
+// Chunk position of chunk q in row r: q ^ swz(r).  Rows of 128 B (8 chunks)
+// repeat the bank pattern every 2 rows, rows of 64 B (4 chunks) every 4 rows; the
+// XOR spreads a 16-row fragment over distinct banks.
+template <int RB> __device__ __forceinline__ int swz(int r) {
+  return RB == 128 ? ((r >> 1) & 7) : ((r >> 2) & 3);
+}
 
-template <typename TL>
+template <typename TL, int RB>
 __device__ __forceinline__ typename Mfma<TL>::frag frag_dma(const char* tile, int lane, int kk);
 // bf16: 8 consecutive k of row lane%16 starting at kk + 8*(lane/16)
 template <>
-__device__ __forceinline__ bf16x8 frag_dma<bf16>(const char* tile, int lane, int kk) {
+__device__ __forceinline__ bf16x8 frag_dma<bf16, 128>(const char* tile, int lane, int kk) {
   const int r = lane & 15, c = (kk >> 3) + (lane >> 4);
-  return *(const bf16x8*)(tile + r * 128 + ((c ^ swz(r)) << 4));
+  return *(const bf16x8*)(tile + r * 128 + ((c ^ swz<128>(r)) << 4));
 }
 template <>
-__device__ __forceinline__ float frag_dma<float>(const char* tile, int lane, int kk) {
-  const int r = lane & 15, k = kk + (lane >> 4);
-  return *(const float*)(tile + r * 128 + (((k >> 2) ^ swz(r)) << 4) + ((k & 3) << 2));
-}
-template <>
-__device__ __forceinline__ double frag_dma<double>(const char* tile, int lane, int kk) {
-  const int r = lane & 15, k = kk + (lane >> 4);
-  return *(const double*)(tile + r * 128 + (((k >> 1) ^ swz(r)) << 4) + ((k & 1) << 3));
+__device__ __forceinline__ bf16x8 frag_dma<bf16, 64>(const char* tile, int lane, int kk) {
+  const int r = lane & 15, c = (kk >> 3) + (lane >> 4);
+  return *(const bf16x8*)(tile + r * 64 + ((c ^ swz<64>(r)) << 4));
 }
 
 template <int MODE, class G, class SOf, class Epi>
@@ -326,22 +331,23 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
   const int npass = (nsteps + NS - 1) / NS;
   const int total = npass * nk;
   if (total <= 0) return;
-  const int rin = lane >> 3, pos = lane & 7;
+  constexpr int RB = D::RB;
+  const int rin = lane / D::CPR, pos = lane % D::CPR;
 
   // Per-thread chunk coordinates are fixed for the whole loop: chunk slot j
-  // (q = wave + 8 j) belongs to A tile j / (ACH / 8) or, past NS A tiles, to B.
+  // (q = wave + NW j) belongs to A tile j / (ACH / NW) or, past NS A tiles, to B.
   constexpr int JA = NS * D::ACH / NW;   // slots 0..JA-1 load A tiles, the rest B
   int off[D::PER_WAVE], kin[D::PER_WAVE];   // element offset (without k0), chunk k offset
 #pragma unroll
   for (int j = 0; j < D::PER_WAVE; j++) {
     const int q = wave + NW * j;
     if (j < JA) {
-      const int r = (q % D::ACH) * 8 + rin;
-      kin[j] = (pos ^ swz(r)) * E;
+      const int r = (q % D::ACH) * D::RPI + rin;
+      kin[j] = (pos ^ swz<RB>(r)) * E;
       off[j] = min(p0 + r, N - 1) * (int)lda + kin[j];
     } else {
-      const int r = (q - NS * D::ACH) * 8 + rin;
-      kin[j] = (pos ^ swz(r)) * E;
+      const int r = (q - NS * D::ACH) * D::RPI + rin;
+      kin[j] = (pos ^ swz<RB>(r)) * E;
       off[j] = min(c0 + r, ncols - 1) * (int)ldb + kin[j];
     }
   }
@@ -405,20 +411,20 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
     if (g + kStages - 1 < total) issue();
     const char* stage = lds + cst * D::STAGE;
     if (++cst == kStages) cst = 0;
-    const char* Bt = stage + NS * D::ACH * 1024 + (wn * G::WN) * 128;
+    const char* Bt = stage + NS * D::ACH * 1024 + (wn * G::WN) * RB;
     const bool two = NS == 1 || ps * NS + 1 < nsteps;   // second column of the pass is real
 #pragma unroll
     for (int kk = 0; kk < BK; kk += MF::K) {
       typename MF::frag b[G::TJ];
 #pragma unroll
-      for (int j = 0; j < G::TJ; j++) b[j] = frag_dma<TL>(Bt + j * 16 * 128, lane, kk);
+      for (int j = 0; j < G::TJ; j++) b[j] = frag_dma<TL, RB>(Bt + j * 16 * RB, lane, kk);
 #pragma unroll
       for (int q = 0; q < NS; q++) {
         if (q > 0 && !two) break;
-        const char* At = stage + q * D::ACH * 1024 + (wp * G::WP) * 128;
+        const char* At = stage + q * D::ACH * 1024 + (wp * G::WP) * RB;
         typename MF::frag a[G::TI];
 #pragma unroll
-        for (int i = 0; i < G::TI; i++) a[i] = frag_dma<TL>(At + i * 16 * 128, lane, kk);
+        for (int i = 0; i < G::TI; i++) a[i] = frag_dma<TL, RB>(At + i * 16 * RB, lane, kk);
 #pragma unroll
         for (int i = 0; i < G::TI; i++)
 #pragma unroll
