@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <functional>
 #include <string>
 #include <vector>
@@ -112,7 +114,7 @@ struct kfac_pinn_ctx {
   double* Delta = nullptr;
   void* dhat = nullptr;
   void* delta = nullptr;
-  std::vector<EigProblem> probs;
+  std::vector<EigProblem> probs;        // layer l: 2l side A, 2l + 1 side B
   EigProblem* probs_dev = nullptr;
   G64* kdesc = nullptr;
   int k_mmax = 0, k_nmax = 0;
@@ -899,7 +901,7 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* c, const void* theta, const void* xi,
 
 static hipError_t eig_all(kfac_pinn_ctx* c, double lambda) {
   return kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
-                          kEigRefresh, kJacobiSweeps, c->st);
+                          c->ctl + 8, c->ctl + 2, kEigRefresh, kJacobiSweeps, c->st);
 }
 
 kp_status kfac_pinn_invert(kfac_pinn_ctx* c, double lambda) {

@@ -116,12 +116,13 @@ struct EigProblem {
   double* Pout;       // n x n result P (row-major)
   double* eout;       // n eigenvalues
 };
-// status: the context's control words (status[2..3] hold the call counter and
-// the warm-start flag).  Jacobi starts from the V left in P[0] by the previous
-// call, except on every refresh-th call (and the first after a reset).
+// status: the context's status word; done: 2 ints per problem (converged flag,
+// sweeps used); calls: call counter and warm-start flag.  Jacobi starts from the
+// V left in P[0] by the previous call, except on every refresh-th call (and the
+// first after the counter is reset).
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
-                            EigProblem* probs_dev, int* status, int refresh, int max_sweeps,
-                            hipStream_t st);
+                            EigProblem* probs_dev, int* status, int* done, int* calls,
+                            int refresh, int max_sweeps, hipStream_t st);
 // Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T for every layer, V = gradient
 // (column-major h_out x (h_in+1) inside the theta layout).  Four strided FP64
 // products per layer, described once (descriptors in device memory).

@@ -631,14 +631,12 @@ __global__ void k_jac_extract(const EigProblem* __restrict__ pr) {
 }
 
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
-                            EigProblem* probs_dev, int* status, int refresh, int max_sweeps,
-                            hipStream_t st) {
+                            EigProblem* probs_dev, int* status, int* done, int* calls,
+                            int refresh, int max_sweeps, hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   int npmax = 0;
   for (int q = 0; q < nprob; q++) npmax = probs_host[q].n_pad > npmax ? probs_host[q].n_pad : npmax;
   const int nbmax = npmax / BB;
-  int* done = status + 8;   // 2 ints per problem after the status block
-  int* calls = status + 2;  // call counter, warm flag
   k_eig_begin<<<1, 1, 0, st>>>(calls, refresh);
   k_damp_pad<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, lambda);
   for (int j = 0; j < nbmax; j++) {
