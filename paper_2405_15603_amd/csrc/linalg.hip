@@ -520,8 +520,61 @@ __device__ __forceinline__ long grow(int a, int b0, int b1) {
   return a < JB ? (long)b0 * JB + a : (long)b1 * JB + a - JB;
 }
 
+// 64 x 64 x 64 FP64 products on the MFMA unit (v_mfma_f64_16x16x4): four waves,
+// each owning a 32 x 32 quadrant as 2 x 2 tiles of 16 x 16.  Tiles sit in LDS
+// with row stride LDM = 70 doubles, which keeps the fragment reads at two
+// (16 rows x 4 k) or three (4 k x 16 columns) accesses per bank.
+constexpr int LDM = 70;
+
+// acc[ti][tj] += op(A) op(B) over k in [0, 64); op(A)[i][k] = TA ? A[k][i] : A[i][k],
+// op(B)[k][j] = TB ? B[j][k] : B[k][j].  Element (r) of acc[ti][tj] is output
+// (32 wi + 16 ti + (lane >> 4) + 4 r, 32 wj + 16 tj + (lane & 15)).
+template <bool TA, bool TB>
+__device__ __forceinline__ void mm64(f64x4 (&acc)[2][2], const double* A, const double* B) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1, r16 = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < 64; k0 += 4) {
+    const int k = k0 + kq;
+    double a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+      const int i = 32 * wi + 16 * t + r16, j = 32 * wj + 16 * t + r16;
+      a[t] = TA ? A[k * LDM + i] : A[i * LDM + k];
+      b[t] = TB ? B[j * LDM + k] : B[k * LDM + j];
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+      for (int tj = 0; tj < 2; tj++) acc[ti][tj] = Mfma<double>::mma(a[ti], b[tj], acc[ti][tj]);
+  }
+}
+
+__device__ __forceinline__ void mm64_zero(f64x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++) acc[ti][tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Visit the outputs of this thread: f(i, j, value) in tile coordinates.
+template <class F>
+__device__ __forceinline__ void mm64_each(const f64x4 (&acc)[2][2], F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+        f(32 * wi + 16 * ti + Mfma<double>::row(lane, r), 32 * wj + 16 * tj + (lane & 15),
+          acc[ti][tj][r]);
+}
+
 // In place: C region (pair X rows, pair Y cols) <- V_X^T C V_Y for pX <= pY
 // (mirrored), then P[R rows, pair Y cols] <- P V_Y.  Identity pairs are skipped.
+// Two LDS tiles, so two workgroups share a CU.
 __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict__ pr,
                                                    const int* __restrict__ done, int r) {
   const int q = blockIdx.y;
@@ -533,11 +586,9 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
   int w = blockIdx.x;
   if (w >= ncg + npair * npair) return;
   const long np = p.n_pad;
-  // two LDS tiles (two workgroups fit a CU): the C block and one rotation block
-  __shared__ double G[BB * LDB];
-  __shared__ double W[BB * LDB];
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double acc[4][4];
+  __shared__ double G[BB * LDM];
+  __shared__ double W[BB * LDM];
+  f64x4 acc[2][2];
   if (w < ncg) {
     int pX = 0, rowlen = npair;
     while (w >= rowlen) { w -= rowlen; pX++; rowlen--; }
@@ -550,40 +601,32 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
     double* C = p.C[0];
     for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
       const int a = e / BB, b = e % BB;
-      G[a * LDB + b] = C[grow(a, x0, x1) * np + grow(b, y0, y1)];
-      if (!iy) W[a * LDB + b] = p.V[(long)pY * BB * BB + e];
+      G[a * LDM + b] = C[grow(a, x0, x1) * np + grow(b, y0, y1)];
+      W[a * LDM + b] = iy ? p.V[(long)pX * BB * BB + e] : p.V[(long)pY * BB * BB + e];
     }
     __syncthreads();
-    if (!iy) {
-      zero4(acc);
-      blk_mm<false, false>(acc, G, W);
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) G[(ty * 4 + a) * LDB + tx * 4 + b] = acc[a][b];
-    }
-    if (!ix) {
-      for (int e = threadIdx.x; e < BB * BB; e += blockDim.x)
-        W[(e / BB) * LDB + (e % BB)] = p.V[(long)pX * BB * BB + e];
-      __syncthreads();
-      zero4(acc);
-      blk_mm<true, false>(acc, W, G);
-    } else {
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = G[(ty * 4 + a) * LDB + tx * 4 + b];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int b = 0; b < 4; b++) {
-        const long gr = grow(ty * 4 + a, x0, x1), gc = grow(tx * 4 + b, y0, y1);
-        C[gr * np + gc] = acc[a][b];
-        if (pX != pY) C[gc * np + gr] = acc[a][b];
+    auto store_c = [&](int i, int j, double v) {
+      const long gr = grow(i, x0, x1), gc = grow(j, y0, y1);
+      C[gr * np + gc] = v;
+      if (pX != pY) C[gc * np + gr] = v;
+    };
+    if (!iy) {   // C V_Y
+      mm64_zero(acc);
+      mm64<false, false>(acc, G, W);
+      if (ix) {   // V_X is the identity: done
+        mm64_each(acc, store_c);
+        return;
       }
+      __syncthreads();
+      mm64_each(acc, [&](int i, int j, double v) { G[i * LDM + j] = v; });
+      for (int e = threadIdx.x; e < BB * BB; e += blockDim.x)
+        W[(e / BB) * LDM + (e % BB)] = p.V[(long)pX * BB * BB + e];
+      __syncthreads();
+    }
+    // V_X^T G (W holds V_X)
+    mm64_zero(acc);
+    mm64<true, false>(acc, W, G);
+    mm64_each(acc, store_c);
   } else {
     w -= ncg;
     const int R = w / npair, pY = w % npair;
@@ -593,17 +636,13 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
     double* P = p.P[0];
     for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
       const int a = e / BB, b = e % BB;
-      G[a * LDB + b] = P[((long)R * BB + a) * np + grow(b, y0, y1)];
-      W[a * LDB + b] = p.V[(long)pY * BB * BB + e];
+      G[a * LDM + b] = P[((long)R * BB + a) * np + grow(b, y0, y1)];
+      W[a * LDM + b] = p.V[(long)pY * BB * BB + e];
     }
     __syncthreads();
-    zero4(acc);
-    blk_mm<false, false>(acc, G, W);
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int b = 0; b < 4; b++)
-        P[((long)R * BB + ty * 4 + a) * np + grow(tx * 4 + b, y0, y1)] = acc[a][b];
+    mm64_zero(acc);
+    mm64<false, false>(acc, G, W);
+    mm64_each(acc, [&](int i, int j, double v) { P[((long)R * BB + i) * np + grow(j, y0, y1)] = v; });
   }
 }
 
