@@ -83,3 +83,36 @@ def test_mixed_line_search_losses(case):
     assert np.all(err < 5e-2), err
     chosen = ref[ks.index(int(round(np.log2(alpha))))]
     assert chosen <= ref.min() * (1 + 5e-2)
+
+
+def test_mixed_factor_gate_along_trajectory():
+    """The mixed-precision gate on the 100-d workload: 100 mixed steps on the full
+    batch (3000 + 1000 points, 100-768-768-512-512-1), and at steps 0, 50 and 100
+    the factors of the GPU's current parameters (EMA off) against the oracle's on
+    the same parameters, on a subset of the points (the oracle's cost), every
+    factor within 1e-3."""
+    from paper_2405_15603_amd import HParams
+    p = synth.poisson100d()
+    th, xi, yi, xb, yb = problem_inputs(p, "bf16")
+    kp = kp_for(p, "bf16")
+    gate = kp_for(p, "bf16", max_interior=120, max_boundary=40)
+    theta = to_dev(th, "bf16")
+    full = [to_dev(a, "bf16") for a in (xi, yi, xb, yb)]
+    sub = (xi[:120], yi[:120], xb[:40], yb[:40])
+    hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
+    worst = {}
+    for it in range(101):
+        if it in (0, 50, 100):
+            th_t = theta.cpu().double().numpy()
+            gate.factors(theta, *(to_dev(a, "bf16") for a in sub), beta=0.0)
+            assert gate.sync() == 0
+            ref = oracle_curvature(p, th_t, *sub)
+            errs = [rel(gate.get_factor(l, t, s), ref[f"{sn}_{tn}"][l])
+                    for l in range(len(p.widths) - 1)
+                    for t, tn in ((0, "int"), (1, "bnd")) for s, sn in ((0, "A"), (1, "B"))]
+            worst[it] = max(errs)
+        if it < 100:
+            kp.step(theta, *full, hp)
+    assert kp.sync() == 0
+    print(f"worst factor error at steps 0, 50, 100: {worst}")
+    assert all(v < 1e-3 for v in worst.values()), worst
