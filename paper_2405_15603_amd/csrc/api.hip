@@ -664,7 +664,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   {
     int hmax = 1;
     for (int l = 1; l < c->L; l++) hmax = std::max(hmax, c->w[l]);
-    c->tab_stride = (long)std::max(c->max_i, 1) * hmax;
+    c->tab_stride = ((long)std::max(c->max_i, 1) * hmax + 3) & ~3L;   // 16-byte planes
     ALLOC(c->tab, (size_t)c->tab_stride * (2 + kMaxChunks) * c->esz_c);
   }
   c->partial_n = residual_blocks(std::max(c->max_i, c->max_b));

@@ -461,28 +461,6 @@ __device__ __forceinline__ bool mask_at(const uint8_t* mask, int i) {
   return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu;
 }
 
-// Store x[0..3] to row[cb .. cb+3] (columns below lim); one vector store when
-// all four are in range and the row is 4-aligned.
-template <typename T, typename TC>
-__device__ __forceinline__ void put4(T* row, int cb, int lim, bool aligned, const TC (&x)[4]) {
-  if (aligned && cb + 3 < lim) {
-    if constexpr (std::is_same<T, bf16>::value) {
-      const f32x4 f = {(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
-      *gmem((bf16x4*)(row + cb)) = __builtin_convertvector(f, bf16x4);
-    } else if constexpr (std::is_same<T, float>::value) {
-      const f32x4 f = {(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
-      *gmem((f32x4*)(row + cb)) = f;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; e++) row[cb + e] = cvt<T>((double)x[e]);
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; e++)
-      if (cb + e < lim) row[cb + e] = cvt<T>((double)x[e]);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Forward layer.  Chunk c of C handles derivative rows [1 + c*len, ...), always
 // recomputes the value row (s = 0) first for t, and the last chunk also forms the
@@ -499,7 +477,7 @@ template <int MODE> constexpr int fwd_smem() {
     return (int)sizeof(typename Mainloop<MODE>::Smem);
 }
 
-template <int MODE, typename TZ>
+template <int MODE, typename TZ, bool A4 = false>
 __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
   typedef Op<MODE> O;
   typedef FwdGeo<MODE> G;
@@ -507,10 +485,10 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
   typedef typename O::TL TL;
   typedef Mfma<TL> MF;
   // The direct-to-LDS loop computes the transposed tile (neurons x points), so a
-  // lane holds consecutive neurons of one point and stores them as one vector
-  // (except FP64, whose MFMA rows are not consecutive within a lane).
+  // lane holds four consecutive neurons of one point and, when every output row
+  // is 4-aligned (A4), stores them as one vector.
   constexpr bool TR = kDma<MODE>;
-  constexpr bool VEC = TR && !std::is_same<TL, double>::value;
+  constexpr bool VEC = TR && A4;
   constexpr int SMEM = fwd_smem<MODE>();
   __shared__ __align__(16) char smem[SMEM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -527,7 +505,6 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
   const bool lap_here = a.has_lap && !a.value_only && chunk == nch - 1;
   const int nsteps = 1 + nder + (lap_here ? 1 : 0);
   const int S = a.S;
-  const bool tab_vec = (a.h_out & 3) == 0;
   // output coordinates of accumulator element (i, j, e)
   auto P = [&](int i, int e) {
     return p0 + wp * G::WP + i * 16 + (TR ? (lane & 15) : MF::row(lane, e));
@@ -546,7 +523,89 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
 
   // step 0: value row, steps 1..nder: derivative rows of this chunk, then the Laplacian row
   auto s_of = [=](int st) { return st == 0 ? 0 : (st <= nder ? dbeg + st - 1 : S - 1); };
+  // Vector path: per-lane row and per-group neuron predicates; the column kind is
+  // uniform, so each kind has its own loop over the tile, and tv holds
+  // s1 = 1 - t^2 once the value row is done.
+  bool p_ok[G::TI], c_ok[G::TJ];
+#pragma unroll
+  for (int i = 0; i < G::TI; i++) p_ok[i] = P(i, 0) < a.N;
+#pragma unroll
+  for (int j = 0; j < G::TJ; j++) c_ok[j] = Cn(j, 0) < a.h_out;
+  auto epi_vec = [&](int s, typename MF::acc (&acc)[G::TI][G::TJ]) {
+    if constexpr (VEC) {
+      const bool is_d = s >= 1 && s <= nd;
+      const int kind = s == 0 ? 0 : (is_d ? 1 : 2);
+      const bool keep = !a.sparse_store || (kind == 0 ? a.keep_value != 0
+                                                      : (s >= a.keep_lo && s <= a.keep_hi));
+      const long rbase = (long)s * a.N + P(0, 0);
+      const int cb0 = Cn(0, 0);
+      auto zrow = [&](int i) { return (TZ*)a.z + (rbase + i * 16) * a.ldzo + cb0; };
+      auto prow = [&](int i) { return (TC*)a.pre + (rbase + i * 16) * a.ldp + cb0; };
+      auto tabrow = [&](void* tab, int i) {
+        return (TC*)tab + (long)(P(0, 0) + i * 16) * a.h_out + cb0;
+      };
+      if (kind == 1) {
+        if (mask_at(a.mask, s - 1)) {
+#pragma unroll
+          for (int i = 0; i < G::TI; i++)
+#pragma unroll
+            for (int j = 0; j < G::TJ; j++)
+#pragma unroll
+              for (int e = 0; e < 4; e++) sq[i][j][e] += acc[i][j][e] * acc[i][j][e];
+        }
+        if (keep) {
+#pragma unroll
+          for (int i = 0; i < G::TI; i++)
+#pragma unroll
+            for (int j = 0; j < G::TJ; j++) {
+              const f32x4 o = {tv[i][j][0] * acc[i][j][0], tv[i][j][1] * acc[i][j][1],
+                               tv[i][j][2] * acc[i][j][2], tv[i][j][3] * acc[i][j][3]};
+              if (p_ok[i] && c_ok[j])
+                *gmem((bf16x4*)(zrow(i) + j * 16)) = __builtin_convertvector(o, bf16x4);
+            }
+        }
+        if (a.pre) {
+#pragma unroll
+          for (int i = 0; i < G::TI; i++)
+#pragma unroll
+            for (int j = 0; j < G::TJ; j++)
+              if (p_ok[i] && c_ok[j]) *gmem((f32x4*)(prow(i) + j * 16)) = acc[i][j];
+        }
+      } else if (kind == 0) {
+        const bool first = chunk == 0;
+#pragma unroll
+        for (int i = 0; i < G::TI; i++)
+#pragma unroll
+          for (int j = 0; j < G::TJ; j++) {
+            f32x4 t;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+              t[e] = act_tanh(acc[i][j][e]);
+              tv[i][j][e] = __builtin_fmaf(-t[e], t[e], 1.0f);
+            }
+            if (first && p_ok[i] && c_ok[j]) {
+              if (keep) *gmem((bf16x4*)(zrow(i) + j * 16)) = __builtin_convertvector(t, bf16x4);
+              if (a.pre) *gmem((f32x4*)(prow(i) + j * 16)) = acc[i][j];
+              if (a.tab_t) *gmem((f32x4*)(tabrow(a.tab_t, i) + j * 16)) = t;
+            }
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < G::TI; i++)
+#pragma unroll
+          for (int j = 0; j < G::TJ; j++)
+            if (p_ok[i] && c_ok[j]) {
+              if (a.pre) *gmem((f32x4*)(prow(i) + j * 16)) = acc[i][j];
+              *gmem((f32x4*)(tabrow(a.tab_lap, i) + j * 16)) = acc[i][j];
+            }
+      }
+    }
+  };
   auto epi = [&](int st, int s, typename MF::acc (&acc)[G::TI][G::TJ]) {
+    if constexpr (VEC) {
+      epi_vec(s, acc);
+      return;
+    }
     const bool is_d = s >= 1 && s <= nd;
     const TC m = (is_d && mask_at(a.mask, s - 1)) ? (TC)1 : (TC)0;
     const int kind = s == 0 ? 0 : (is_d ? 1 : 2);
@@ -570,27 +629,16 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
             out[e] = ((TC)1 - th * th) * v[e];
           }
         }
-        if constexpr (VEC) {
-          const int p = P(i, 0), cb = Cn(j, 0);
-          if (p >= a.N) continue;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int p = P(i, e), c = Cn(j, e);
+          if (p >= a.N || c >= a.h_out) continue;
           const long row = (long)s * a.N + p;
           if (kind == 0 && chunk != 0) continue;
-          if (kind <= 1 && keep) put4((TZ*)a.z + row * a.ldzo, cb, a.h_out, true, out);
-          if (a.pre) put4((TC*)a.pre + row * a.ldp, cb, a.h_out, true, v);
-          if (kind == 0 && a.tab_t) put4((TC*)a.tab_t + (long)p * a.h_out, cb, a.h_out, tab_vec, out);
-          if (kind == 2) put4((TC*)a.tab_lap + (long)p * a.h_out, cb, a.h_out, tab_vec, v);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; e++) {
-            const int p = P(i, e), c = Cn(j, e);
-            if (p >= a.N || c >= a.h_out) continue;
-            const long row = (long)s * a.N + p;
-            if (kind == 0 && chunk != 0) continue;
-            if (kind <= 1 && keep) ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)out[e]);
-            if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v[e];
-            if (kind == 0 && a.tab_t) ((TC*)a.tab_t)[(long)p * a.h_out + c] = out[e];
-            if (kind == 2) ((TC*)a.tab_lap)[(long)p * a.h_out + c] = v[e];
-          }
+          if (kind <= 1 && keep) ((TZ*)a.z)[row * a.ldzo + c] = cvt<TZ>((double)out[e]);
+          if (a.pre) ((TC*)a.pre)[row * a.ldp + c] = v[e];
+          if (kind == 0 && a.tab_t) ((TC*)a.tab_t)[(long)p * a.h_out + c] = out[e];
+          if (kind == 2) ((TC*)a.tab_lap)[(long)p * a.h_out + c] = v[e];
         }
       }
   };
@@ -607,10 +655,9 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
 #pragma unroll
       for (int j = 0; j < G::TJ; j++) {
         if constexpr (VEC) {
-          const int p = P(i, 0);
-          if (p < a.N)
-            put4((TC*)a.tab_sq + ((long)chunk * a.N + p) * a.h_out, Cn(j, 0), a.h_out, tab_vec,
-                 sq[i][j]);
+          if (p_ok[i] && c_ok[j])
+            *gmem((f32x4*)((TC*)a.tab_sq + ((long)chunk * a.N + P(i, 0)) * a.h_out + Cn(j, 0))) =
+                f32x4{(float)sq[i][j][0], (float)sq[i][j][1], (float)sq[i][j][2], (float)sq[i][j][3]};
         } else {
 #pragma unroll
           for (int e = 0; e < 4; e++) {
@@ -1003,7 +1050,11 @@ hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st)
     case M_BF16: {
       typedef DGeo<M_BF16> G;
       const dim3 g(((a.N + G::BP - 1) / G::BP) * ((a.h_out + G::BN - 1) / G::BN), nch);
-      k_fwdlap<M_BF16, bf16><<<g, G::NT, 0, st>>>(a);
+      // 4-aligned rows take the vector epilogue (table planes are 4-aligned)
+      if ((a.h_out & 3) == 0 && (a.ldzo & 3) == 0 && (!a.pre || (a.ldp & 3) == 0))
+        k_fwdlap<M_BF16, bf16, true><<<g, G::NT, 0, st>>>(a);
+      else
+        k_fwdlap<M_BF16, bf16, false><<<g, G::NT, 0, st>>>(a);
       break;
     }
     case M_BF16X3:
