@@ -46,7 +46,6 @@ namespace {
 constexpr int kMaxLayers = 8;
 constexpr int kMaxCand = 64;
 constexpr int kMaxSplits = 64;
-constexpr int kMaxChunks = 16;
 constexpr int kJacobiSweeps = 20;
 // Jacobi starts from the previous call's eigenvectors except on every
 // kEigRefresh-th call (and the first), which starts from the identity so that

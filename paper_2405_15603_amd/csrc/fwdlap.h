@@ -5,6 +5,9 @@
 
 namespace kp {
 
+// chunks of derivative rows per layer launch (the finishing tables hold this many)
+constexpr int kMaxChunks = 16;
+
 // compute modes of the layer products
 enum { M_F64 = 0, M_F32 = 1, M_BF16 = 2, M_BF16X3 = 3 };
 

@@ -1017,11 +1017,47 @@ static int choose_chunks(int tiles, int nd, int has_lap) {
   return ch;
 }
 
+// The direct-to-LDS kernel holds one workgroup per compute unit and runs the
+// columns of a chunk (its value row, derivative rows and, in the last chunk, the
+// Laplacian row) NS at a time, so a launch takes about
+// ceil(blocks / CUs) * ceil(columns per chunk / NS) pass times: pick the chunk
+// count that minimises that.
+static int compute_units() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+static int choose_chunks_dma(int tiles, int nd, int has_lap) {
+  if (!has_lap || nd <= 1) return 1;
+  typedef DGeo<M_BF16> G;
+  const int cus = compute_units();
+  int best = 1;
+  long best_cost = -1;
+  for (int ch = 1; ch <= kMaxChunks && ch <= nd; ch++) {
+    const int len = (nd + ch - 1) / ch;
+    const long rounds = ((long)tiles * ch + cus - 1) / cus;
+    const long passes = (2 + len + G::NS - 1) / G::NS;
+    if (best_cost < 0 || rounds * passes < best_cost) {
+      best_cost = rounds * passes;
+      best = ch;
+    }
+  }
+  return best;
+}
+
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
   const int BP = mode == M_BF16 ? DGeo<M_BF16>::BP : 128;
   const int BN = mode == M_BF16 ? DGeo<M_BF16>::BN : (mode == M_F64 ? 64 : 128);
   const int tiles = ((N + BP - 1) / BP) * ((h_out + BN - 1) / BN);
-  return choose_chunks(tiles, nd, has_lap);
+  return mode == M_BF16 ? choose_chunks_dma(tiles, nd, has_lap) : choose_chunks(tiles, nd, has_lap);
 }
 int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap) {
   const int BP = 128, BN = 64;
