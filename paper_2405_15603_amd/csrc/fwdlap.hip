@@ -524,8 +524,11 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
   // step 0: value row, steps 1..nder: derivative rows of this chunk, then the Laplacian row
   auto s_of = [=](int st) { return st == 0 ? 0 : (st <= nder ? dbeg + st - 1 : S - 1); };
   // Vector path: per-lane row and per-group neuron predicates; the column kind is
-  // uniform, so each kind has its own loop over the tile, and tv holds
-  // s1 = 1 - t^2 once the value row is done.
+  // uniform, so each kind has its own loop over the tile.  s1 = 1 - t^2 of the
+  // value row is kept in half precision (relative rounding 2^-11, below the 2^-9
+  // of the BF16 rows it scales), which leaves the main loop the registers it
+  // needs.
+  f16x4 s1h[G::TI][G::TJ];
   bool p_ok[G::TI], c_ok[G::TJ];
 #pragma unroll
   for (int i = 0; i < G::TI; i++) p_ok[i] = P(i, 0) < a.N;
@@ -558,8 +561,7 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
           for (int i = 0; i < G::TI; i++)
 #pragma unroll
             for (int j = 0; j < G::TJ; j++) {
-              const f32x4 o = {tv[i][j][0] * acc[i][j][0], tv[i][j][1] * acc[i][j][1],
-                               tv[i][j][2] * acc[i][j][2], tv[i][j][3] * acc[i][j][3]};
+              const f32x4 o = __builtin_convertvector(s1h[i][j], f32x4) * acc[i][j];
               if (p_ok[i] && c_ok[j])
                 *gmem((bf16x4*)(zrow(i) + j * 16)) = __builtin_convertvector(o, bf16x4);
             }
@@ -577,12 +579,13 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
         for (int i = 0; i < G::TI; i++)
 #pragma unroll
           for (int j = 0; j < G::TJ; j++) {
-            f32x4 t;
+            f32x4 t, s1;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
               t[e] = act_tanh(acc[i][j][e]);
-              tv[i][j][e] = __builtin_fmaf(-t[e], t[e], 1.0f);
+              s1[e] = __builtin_fmaf(-t[e], t[e], 1.0f);
             }
+            s1h[i][j] = __builtin_convertvector(s1, f16x4);
             if (first && p_ok[i] && c_ok[j]) {
               if (keep) *gmem((bf16x4*)(zrow(i) + j * 16)) = __builtin_convertvector(t, bf16x4);
               if (a.pre) *gmem((f32x4*)(prow(i) + j * 16)) = acc[i][j];
