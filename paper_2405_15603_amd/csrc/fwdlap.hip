@@ -357,25 +357,35 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
   // ikt, stage ist); counters advance instead of dividing by nk.
   int ips = 0, ikt = 0, ist = 0;
   long sbase[NS];
-  auto issue = [&]() {
+  int i_k0 = 0;
+  bool i_last = false;   // only the last k-tile has chunks past K
+  char* i_stage = lds;
+  auto issue_begin = [&]() {
     if (ikt == 0) {
 #pragma unroll
       for (int q = 0; q < NS; q++) sbase[q] = (long)s_of(min(ips * NS + q, nsteps - 1)) * N * lda;
     }
-    const int k0 = ikt * BK;
-    const bool last_k = k0 + BK > K;   // only the last k-tile has chunks past K
-    char* stage = lds + ist * D::STAGE;
-#pragma unroll
-    for (int j = 0; j < D::PER_WAVE; j++) {
-      const TL* src = j < JA ? A + sbase[j / (D::ACH / NW)] + off[j] + k0 : B + off[j] + k0;
-      if (last_k) src = k0 + kin[j] < K ? src : zchunk;
-      __builtin_amdgcn_global_load_lds((const KP_GLOBAL void*)src,
-                                       (__attribute__((address_space(3))) void*)(stage +
-                                                                                 (wave + NW * j) * 1024),
-                                       16, 0, 0);
-    }
+    i_k0 = ikt * BK;
+    i_last = i_k0 + BK > K;
+    i_stage = lds + ist * D::STAGE;
+  };
+  auto issue_slot = [&](int j) {
+    const TL* src = j < JA ? A + sbase[j / (D::ACH / NW)] + off[j] + i_k0 : B + off[j] + i_k0;
+    if (i_last) src = i_k0 + kin[j] < K ? src : zchunk;
+    __builtin_amdgcn_global_load_lds((const KP_GLOBAL void*)src,
+                                     (__attribute__((address_space(3))) void*)(i_stage +
+                                                                               (wave + NW * j) * 1024),
+                                     16, 0, 0);
+  };
+  auto issue_end = [&]() {
     if (++ikt == nk) { ikt = 0; ips++; }
     if (++ist == kStages) ist = 0;
+  };
+  auto issue = [&]() {
+    issue_begin();
+#pragma unroll
+    for (int j = 0; j < D::PER_WAVE; j++) issue_slot(j);
+    issue_end();
   };
 
   typename MF::acc acc[NS][G::TI][G::TJ];
@@ -408,7 +418,12 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
     // workgroup fence would drain every load in flight.  The memory clobber
     // keeps the compiler from moving LDS accesses across it.
     asm volatile("s_barrier" ::: "memory");
-    if (g + kStages - 1 < total) issue();
+    // The next tile's loads are spread over the product groups below (one slot
+    // after each group) rather than issued together, so that no wave waits at
+    // the barrier's exit for the address unit to accept a burst of loads
+    // (measured: issuing them all in the first half of the groups is slower).
+    const bool nxt = g + kStages - 1 < total;
+    if (nxt) issue_begin();
     const char* stage = lds + cst * D::STAGE;
     if (++cst == kStages) cst = 0;
     const char* Bt = stage + NS * D::ACH * 1024 + (wn * G::WN) * RB;
@@ -420,17 +435,25 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
       for (int j = 0; j < G::TJ; j++) b[j] = frag_dma<TL, RB>(Bt + j * 16 * RB, lane, kk);
 #pragma unroll
       for (int q = 0; q < NS; q++) {
-        if (q > 0 && !two) break;
-        const char* At = stage + q * D::ACH * 1024 + (wp * G::WP) * RB;
-        typename MF::frag a[G::TI];
+        if (q == 0 || two) {
+          const char* At = stage + q * D::ACH * 1024 + (wp * G::WP) * RB;
+          typename MF::frag a[G::TI];
 #pragma unroll
-        for (int i = 0; i < G::TI; i++) a[i] = frag_dma<TL, RB>(At + i * 16 * RB, lane, kk);
+          for (int i = 0; i < G::TI; i++) a[i] = frag_dma<TL, RB>(At + i * 16 * RB, lane, kk);
 #pragma unroll
-        for (int i = 0; i < G::TI; i++)
+          for (int i = 0; i < G::TI; i++)
 #pragma unroll
-          for (int j = 0; j < G::TJ; j++) acc[q][i][j] = MF::mma(b[j], a[i], acc[q][i][j]);
+            for (int j = 0; j < G::TJ; j++) acc[q][i][j] = MF::mma(b[j], a[i], acc[q][i][j]);
+        }
+        if (nxt) {
+          constexpr int NG = (BK / MF::K) * NS;
+          const int grp = (kk / MF::K) * NS + q;
+#pragma unroll
+          for (int j = grp; j < D::PER_WAVE; j += NG) issue_slot(j);
+        }
       }
     }
+    if (nxt) issue_end();
     if (kt + 1 == nk) {
 #pragma unroll
       for (int q = 0; q < NS; q++) {
