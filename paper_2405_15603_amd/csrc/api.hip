@@ -283,9 +283,17 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
     const double Rp = input_rows ? (double)n : (double)R;   // rows with products
     int ti = tm_begin(c, T.kc_layer);
     if ((e = fwdlap_main(T.mode, a, nch, c->st)) != hipSuccess) return e;
+    // bytes: the input rows with products, the z rows this launch stores (the
+    // Laplacian row is the finishing pass's), the weights and the finishing tables
+    const double zrows =
+        a.value_only ? (double)n
+        : a.sparse_store ? (double)n * (a.keep_value + std::max(0, a.keep_hi - a.keep_lo + 1))
+        : (s.has_lap ? (double)n * (s.S - 1) : (double)R);
+    const double tabs =
+        s.has_lap ? (double)n * ld.h_out * c->esz_c * (a.value_only ? 1 : 2 + nch) : 0.0;
     tm_end(c, ti, 2.0 * Rp * ld.h_out * (ld.h_in + 1),
-           Rp * (ld.h_in + 1) * T.zesz + (double)R * ld.h_out * T.zesz +
-               (double)ld.h_out * (ld.h_in + 1) * c->esz_w);
+           Rp * (ld.h_in + 1) * T.zesz + zrows * ld.h_out * T.zesz +
+               (double)ld.h_out * (ld.h_in + 1) * c->esz_w + tabs);
     ti = tm_begin(c, KC_ACT);
     if (input_rows)
       e = input_layer_rows(T.mode, a, c->qbuf, c->st);
