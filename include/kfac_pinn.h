@@ -247,20 +247,32 @@ kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
  * kfac_pinn_batch_step performs one kfac_pinn_step per instance with the same
  * hyper-parameters: thetas, x_int, y_int, x_bnd, y_bnd are host arrays of
  * `count` device pointers, n_int and n_bnd host arrays of sizes, infos a device
- * array of `count` summaries (or NULL).  The work is ordered after the work
- * already on `stream` and before anything enqueued there later.  The first
- * call captures each lane's part of the batch step into a HIP graph, later
- * calls with the same arguments replay them (different arguments recapture);
- * with the graphs
- * disabled (kfac_pinn_batch_set_graph) every call enqueues the launches
- * directly.  Errors as for kfac_pinn_step; per-instance device status is read
- * with kfac_pinn_sync on kfac_pinn_batch_context(batch, k). */
+ * array of `count` summaries (or NULL).  It runs in three phases: the factors
+ * and gradients of every instance (on the lanes), then ONE inversion launch
+ * sequence over the damped factors of all instances together (on lane 0, so
+ * each eigensolver launch covers every instance's problems), then the
+ * directions, line searches and updates (on the lanes).  The results equal
+ * those of kfac_pinn_step on each instance.  The Jacobi warm start and its
+ * periodic cold start are counted per batch step, and the sweeps used are read
+ * with kfac_pinn_batch_get_sweeps (kfac_pinn_get_sweeps on an instance's
+ * context reports only its own kfac_pinn_step/invert calls).  The work is
+ * ordered after the work already on `stream` and before anything enqueued
+ * there later.  The first call captures each phase into HIP graphs (per lane,
+ * and one for the inversion); later calls with the same arguments replay them
+ * (different arguments recapture); with the graphs disabled
+ * (kfac_pinn_batch_set_graph) every call enqueues the launches directly.
+ * Errors as for kfac_pinn_step; per-instance device status is read with
+ * kfac_pinn_sync on kfac_pinn_batch_context(batch, k). */
 typedef struct kfac_pinn_batch kfac_pinn_batch;
 kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void* stream,
                                  kfac_pinn_batch** out);
 kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* batch);
 kp_status kfac_pinn_batch_context(kfac_pinn_batch* batch, int32_t k, kfac_pinn_ctx** out);
 kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* batch, int32_t enabled);
+/* Jacobi sweeps of instance k's eigenproblems in the last batch step (waits for
+ * it): sweeps[2*layer + side] for side 0 (input factors) and 1 (output factors);
+ * `sweeps` is a host array of 2 * n_layers ints. */
+kp_status kfac_pinn_batch_get_sweeps(kfac_pinn_batch* batch, int32_t k, int32_t* sweeps);
 kp_status kfac_pinn_batch_step(kfac_pinn_batch* batch, void* const* thetas,
                                const void* const* x_int, const void* const* y_int,
                                const int32_t* n_int, const void* const* x_bnd,

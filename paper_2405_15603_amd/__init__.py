@@ -345,6 +345,13 @@ class KfacPinnBatch:
     def sync(self) -> list:
         return [c.sync() for c in self.contexts]
 
+    def get_sweeps(self, k: int) -> list:
+        """Jacobi sweeps of instance k's eigenproblems in the last batch step."""
+        n = 2 * (len(self.problems[k].widths) - 1)
+        out = (C.c_int32 * n)()
+        N.check(self.lib.kfac_pinn_batch_get_sweeps(self.h, k, out), "kfac_pinn_batch_get_sweeps")
+        return list(out)
+
 
 def forward_laplacian(kp: KfacPinn, theta: torch.Tensor, x: torch.Tensor):
     return ForwardLaplacian.apply(theta, x, kp)

@@ -71,6 +71,7 @@ _SIGS = {
     "kfac_pinn_batch_destroy": (C.c_int, [_V]),
     "kfac_pinn_batch_context": (C.c_int, [_V, C.c_int32, C.POINTER(_V)]),
     "kfac_pinn_batch_set_graph": (C.c_int, [_V, C.c_int32]),
+    "kfac_pinn_batch_get_sweeps": (C.c_int, [_V, C.c_int32, C.POINTER(C.c_int32)]),
     "kfac_pinn_batch_step": (C.c_int, [_V, C.POINTER(_V), C.POINTER(_V), C.POINTER(_V),
                                        C.POINTER(C.c_int32), C.POINTER(_V), C.POINTER(_V),
                                        C.POINTER(C.c_int32), C.POINTER(kp_hparams), _V]),

@@ -722,6 +722,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
       ALLOC(p.dmax, sizeof(double));
       ALLOC(p.Pout, (size_t)p.n * p.n * sizeof(double));
       ALLOC(p.eout, (size_t)p.n * sizeof(double));
+      p.status = c->ctl;
       c->probs.push_back(p);
     }
   ALLOC(c->probs_dev, sizeof(EigProblem) * c->probs.size());
@@ -928,19 +929,21 @@ kp_status kfac_pinn_precondition(kfac_pinn_ctx* c, const double* grad_in, double
   return KP_OK;
 }
 
-kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const void* yi, int32_t ni,
-                         const void* xb, const void* yb, int32_t nb, const kp_hparams* hp,
-                         kp_step_info* info) {
+// A step in three parts: the factors and gradient (head), the inversion, and the
+// direction, line search and update (tail).  A batch runs the heads of all its
+// instances, one inversion over all of their factors, then the tails.
+static kp_status step_head(kfac_pinn_ctx* c, void* theta, const void* xi, const void* yi,
+                           int32_t ni, const void* xb, const void* yb, int32_t nb,
+                           const kp_hparams* hp) {
   KP_ARG(c && theta && hp, "null argument");
   KP_ARG(hp->beta >= 0.0 && hp->beta < 1.0, "beta must be in [0, 1)");
   KP_ARG(hp->lambda >= 0.0 && isfinite(hp->lambda), "lambda must be finite and >= 0");
   KP_ARG(isfinite(hp->momentum), "momentum must be finite");
   KP_ARG(hp->lr_mode == 0 || hp->lr_mode == 1, "lr_mode must be 0 or 1");
-  int ncand = 0;
   if (hp->lr_mode == 1) {
     KP_ARG(hp->grid_max_exp >= hp->grid_min_exp, "empty line-search grid");
-    ncand = hp->grid_max_exp - hp->grid_min_exp + 1;
-    KP_ARG(ncand <= kMaxCand, "at most 64 line-search candidates");
+    KP_ARG(hp->grid_max_exp - hp->grid_min_exp + 1 <= kMaxCand,
+           "at most 64 line-search candidates");
     KP_ARG(hp->grid_max_exp <= 60 && hp->grid_min_exp >= -1000, "grid exponents out of range");
   } else {
     KP_ARG(hp->lr >= 0.0 && isfinite(hp->lr), "lr must be finite and >= 0");
@@ -948,14 +951,13 @@ kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const vo
   kp_status s = check_batch(c, xi, yi, ni, xb, yb, nb);
   if (s != KP_OK) return s;
   // 1-2) factors, EMA, losses and gradient at theta_t
-  s = factors_impl(c, theta, xi, yi, ni, xb, yb, nb, hp->beta);
-  if (s != KP_OK) return s;
-  // 3) preconditioner
-  {
-    int ti = tm_begin(c, KC_INVERT);
-    KP_TRY(eig_all(c, hp->lambda));
-    tm_end(c, ti, 0.0, 0.0);
-  }
+  return factors_impl(c, theta, xi, yi, ni, xb, yb, nb, hp->beta);
+}
+
+static kp_status step_tail(kfac_pinn_ctx* c, void* theta, const void* xi, const void* yi,
+                           int32_t ni, const void* xb, const void* yb, int32_t nb,
+                           const kp_hparams* hp, kp_step_info* info) {
+  const int ncand = hp->lr_mode == 1 ? hp->grid_max_exp - hp->grid_min_exp + 1 : 0;
   // 4) Delta = -C g, momentum
   KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
   KP_TRY(momentum(c->pp, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
@@ -974,6 +976,20 @@ kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const vo
                      hp->lr_mode == 1 ? -1.0 : hp->lr, c->loss, theta, c->dhat, c->delta, c->D,
                      c->ctl, c->ctl + 1, info, c->st));
   return KP_OK;
+}
+
+kp_status kfac_pinn_step(kfac_pinn_ctx* c, void* theta, const void* xi, const void* yi, int32_t ni,
+                         const void* xb, const void* yb, int32_t nb, const kp_hparams* hp,
+                         kp_step_info* info) {
+  kp_status s = step_head(c, theta, xi, yi, ni, xb, yb, nb, hp);
+  if (s != KP_OK) return s;
+  // 3) preconditioner
+  {
+    int ti = tm_begin(c, KC_INVERT);
+    KP_TRY(eig_all(c, hp->lambda));
+    tm_end(c, ti, 0.0, 0.0);
+  }
+  return step_tail(c, theta, xi, yi, ni, xb, yb, nb, hp, info);
 }
 
 kp_status kfac_pinn_get_factor(kfac_pinn_ctx* c, int32_t layer, int32_t term, int32_t side,
@@ -1104,11 +1120,19 @@ struct kfac_pinn_batch {
   hipStream_t st = nullptr;       // the caller's stream (may be the null stream)
   hipEvent_t ev_in = nullptr;     // fork: lanes wait for the caller's earlier work
   std::vector<hipStream_t> lanes;
-  std::vector<hipEvent_t> ev;     // join: one per lane
-  std::vector<hipGraph_t> graph;  // one per lane
-  std::vector<hipGraphExec_t> exec;
+  std::vector<hipEvent_t> ev_head;  // per lane: factors of its instances done
+  hipEvent_t ev_eig = nullptr;      // the inversion of every instance done (lane 0)
+  std::vector<hipEvent_t> ev;       // join: one per lane
+  // graphs: per lane the heads and the tails of its instances, one inversion
+  std::vector<hipGraph_t> graph;
+  std::vector<hipGraphExec_t> exec_head, exec_tail;
+  hipGraphExec_t exec_eig = nullptr;
   std::vector<uintptr_t> key;
   int use_graph = 1;
+  // one inversion over the factors of every instance
+  std::vector<EigProblem> probs;
+  EigProblem* probs_dev = nullptr;
+  int* eig_ctl = nullptr;   // [0..1] call counter and warm-start flag, [2..] 2 per problem
 };
 
 namespace {
@@ -1116,26 +1140,80 @@ constexpr int kBatchLanes = 8;
 constexpr int kMaxBatch = 1024;
 
 void batch_drop_graph(kfac_pinn_batch* b) {
-  for (hipGraphExec_t e : b->exec)
+  for (hipGraphExec_t e : b->exec_head)
     if (e) (void)hipGraphExecDestroy(e);
+  for (hipGraphExec_t e : b->exec_tail)
+    if (e) (void)hipGraphExecDestroy(e);
+  if (b->exec_eig) (void)hipGraphExecDestroy(b->exec_eig);
   for (hipGraph_t g : b->graph)
     if (g) (void)hipGraphDestroy(g);
-  b->exec.clear();
+  b->exec_head.clear();
+  b->exec_tail.clear();
+  b->exec_eig = nullptr;
   b->graph.clear();
   b->key.clear();
 }
 
-// the steps of the instances on lane l
-kp_status lane_enqueue(kfac_pinn_batch* b, int l, void* const* thetas, const void* const* xi,
-                       const void* const* yi, const int32_t* ni, const void* const* xb,
-                       const void* const* yb, const int32_t* nb, const kp_hparams* hp,
-                       kp_step_info* infos) {
+struct BatchArgs {
+  void* const* thetas;
+  const void* const* xi;
+  const void* const* yi;
+  const int32_t* ni;
+  const void* const* xb;
+  const void* const* yb;
+  const int32_t* nb;
+  const kp_hparams* hp;
+  kp_step_info* infos;
+};
+
+// phase 0: the heads of the instances on lane l; 1: one inversion over every
+// instance's problems on lane 0; 2: the tails of the instances on lane l
+kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a) {
   const int nl = (int)b->lanes.size();
+  if (phase == 1) {
+    KP_TRY(kron_eig_batched(b->probs.data(), (int)b->probs.size(), a.hp->lambda, b->probs_dev,
+                            b->ctx[0]->ctl, b->eig_ctl + 2, b->eig_ctl, kEigRefresh,
+                            kJacobiSweeps, b->lanes[0]));
+    return KP_OK;
+  }
   for (size_t k = l; k < b->ctx.size(); k += nl) {
-    kp_status s = kfac_pinn_step(b->ctx[k], thetas[k], xi[k], yi[k], ni[k], xb[k], yb[k], nb[k],
-                                 hp, infos ? infos + k : nullptr);
+    kp_status s =
+        phase == 0
+            ? step_head(b->ctx[k], a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k],
+                        a.nb[k], a.hp)
+            : step_tail(b->ctx[k], a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k],
+                        a.nb[k], a.hp, a.infos ? a.infos + k : nullptr);
     if (s != KP_OK) return s;
   }
+  return KP_OK;
+}
+
+kp_status batch_capture(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a,
+                        hipGraphExec_t* out) {
+  hipStream_t s = b->lanes[phase == 1 ? 0 : l];
+  KP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  kp_status st = batch_enqueue(b, phase, l, a);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != KP_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+    return st != KP_OK ? st : KP_ERR_HIP;
+  }
+  b->graph.push_back(g);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+    return KP_ERR_HIP;
+  }
+  return KP_OK;
+}
+
+kp_status batch_launch(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a) {
+  if (!b->use_graph) return batch_enqueue(b, phase, l, a);
+  hipGraphExec_t x = phase == 0 ? b->exec_head[l] : phase == 1 ? b->exec_eig : b->exec_tail[l];
+  KP_TRY(hipGraphLaunch(x, b->lanes[phase == 1 ? 0 : l]));
   return KP_OK;
 }
 }  // namespace
@@ -1148,33 +1226,39 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
   kfac_pinn_batch* b = new kfac_pinn_batch();
   b->st = (hipStream_t)stream;
   const int nl = count < kBatchLanes ? count : kBatchLanes;
+  auto fail = [&](kp_status s) {
+    kfac_pinn_batch_destroy(b);
+    return s;
+  };
   for (int l = 0; l < nl; l++) {
     hipStream_t s;
-    hipEvent_t e;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-      kfac_pinn_batch_destroy(b);
-      return KP_ERR_HIP;
-    }
+    hipEvent_t e, eh;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(KP_ERR_HIP);
     b->lanes.push_back(s);
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      kfac_pinn_batch_destroy(b);
-      return KP_ERR_HIP;
-    }
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(KP_ERR_HIP);
     b->ev.push_back(e);
+    if (hipEventCreateWithFlags(&eh, hipEventDisableTiming) != hipSuccess) return fail(KP_ERR_HIP);
+    b->ev_head.push_back(eh);
   }
-  if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess) {
-    kfac_pinn_batch_destroy(b);
-    return KP_ERR_HIP;
-  }
+  if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_eig, hipEventDisableTiming) != hipSuccess)
+    return fail(KP_ERR_HIP);
   for (int k = 0; k < count; k++) {
     kfac_pinn_ctx* c = nullptr;
     kp_status s = kfac_pinn_create(&problems[k], b->lanes[k % nl], &c);
-    if (s != KP_OK) {
-      kfac_pinn_batch_destroy(b);
-      return s;
-    }
+    if (s != KP_OK) return fail(s);
     b->ctx.push_back(c);
+    b->probs.insert(b->probs.end(), c->probs.begin(), c->probs.end());
   }
+  const size_t np = b->probs.size();
+  if (hipMalloc((void**)&b->probs_dev, sizeof(EigProblem) * np) != hipSuccess ||
+      hipMalloc((void**)&b->eig_ctl, sizeof(int) * (2 + 2 * np)) != hipSuccess)
+    return fail(KP_ERR_OOM);
+  if (hipMemcpy(b->probs_dev, b->probs.data(), sizeof(EigProblem) * np, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemset(b->eig_ctl, 0, sizeof(int) * (2 + 2 * np)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return fail(KP_ERR_HIP);
   *out = b;
   return KP_OK;
 }
@@ -1184,8 +1268,12 @@ kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   for (hipStream_t s : b->lanes) (void)hipStreamSynchronize(s);
   batch_drop_graph(b);
   for (kfac_pinn_ctx* c : b->ctx) kfac_pinn_destroy(c);
+  if (b->probs_dev) (void)hipFree(b->probs_dev);
+  if (b->eig_ctl) (void)hipFree(b->eig_ctl);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->ev_head) (void)hipEventDestroy(e);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_eig) (void)hipEventDestroy(b->ev_eig);
   for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
   delete b;
   return KP_OK;
@@ -1205,6 +1293,20 @@ kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* b, int32_t enabled) {
   return KP_OK;
 }
 
+kp_status kfac_pinn_batch_get_sweeps(kfac_pinn_batch* b, int32_t k, int32_t* sweeps) {
+  KP_ARG(b && sweeps, "null argument");
+  KP_ARG(k >= 0 && k < (int)b->ctx.size(), "instance index out of range");
+  int first = 0;
+  for (int i = 0; i < k; i++) first += (int)b->ctx[i]->probs.size();
+  const int np = (int)b->ctx[k]->probs.size();
+  std::vector<int> d(2 * np);
+  KP_TRY(hipStreamSynchronize(b->lanes[0]));
+  KP_TRY(hipMemcpy(d.data(), b->eig_ctl + 2 + 2 * first, sizeof(int) * 2 * np,
+                   hipMemcpyDeviceToHost));
+  for (int q = 0; q < np; q++) sweeps[q] = d[2 * q + 1];
+  return KP_OK;
+}
+
 kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const void* const* x_int,
                                const void* const* y_int, const int32_t* n_int,
                                const void* const* x_bnd, const void* const* y_bnd,
@@ -1213,6 +1315,7 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
          "null argument");
   const int n = (int)b->ctx.size();
   const int nl = (int)b->lanes.size();
+  const BatchArgs a{thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp, infos};
   if (b->use_graph) {
     std::vector<uintptr_t> key;
     key.reserve(7 * n + 16);
@@ -1230,44 +1333,40 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
       const unsigned char* hb = (const unsigned char*)hp;
       for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);
     }
-    if (b->exec.empty() || key != b->key) {
+    if (b->exec_eig == nullptr || key != b->key) {
       batch_drop_graph(b);
-      for (int l = 0; l < nl; l++) {
-        KP_TRY(hipStreamBeginCapture(b->lanes[l], hipStreamCaptureModeThreadLocal));
-        kp_status s = lane_enqueue(b, l, thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp,
-                                   infos);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(b->lanes[l], &g);
-        if (s != KP_OK || e != hipSuccess) {
-          if (g) (void)hipGraphDestroy(g);
-          batch_drop_graph(b);
-          if (e != hipSuccess) kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
-          return s != KP_OK ? s : KP_ERR_HIP;
-        }
-        b->graph.push_back(g);
-        hipGraphExec_t x = nullptr;
-        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-          batch_drop_graph(b);
-          kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
-          return KP_ERR_HIP;
-        }
-        b->exec.push_back(x);
+      b->exec_head.assign(nl, nullptr);
+      b->exec_tail.assign(nl, nullptr);
+      kp_status s = KP_OK;
+      for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 0, l, a, &b->exec_head[l]);
+      if (s == KP_OK) s = batch_capture(b, 1, 0, a, &b->exec_eig);
+      for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 2, l, a, &b->exec_tail[l]);
+      if (s != KP_OK) {
+        batch_drop_graph(b);
+        return s;
       }
       b->key = key;
     }
   }
-  // ordered after the caller's earlier work and before its later work
+  // ordered after the caller's earlier work and before its later work: heads on
+  // every lane, the inversion on lane 0 after all heads, tails after it
   KP_TRY(hipEventRecord(b->ev_in, b->st));
   for (int l = 0; l < nl; l++) {
     KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev_in, 0));
-    if (b->use_graph) {
-      KP_TRY(hipGraphLaunch(b->exec[l], b->lanes[l]));
-    } else {
-      kp_status s = lane_enqueue(b, l, thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp,
-                                 infos);
-      if (s != KP_OK) return s;
-    }
+    kp_status s = batch_launch(b, 0, l, a);
+    if (s != KP_OK) return s;
+    KP_TRY(hipEventRecord(b->ev_head[l], b->lanes[l]));
+  }
+  for (int l = 1; l < nl; l++) KP_TRY(hipStreamWaitEvent(b->lanes[0], b->ev_head[l], 0));
+  {
+    kp_status s = batch_launch(b, 1, 0, a);
+    if (s != KP_OK) return s;
+  }
+  KP_TRY(hipEventRecord(b->ev_eig, b->lanes[0]));
+  for (int l = 0; l < nl; l++) {
+    if (l > 0) KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev_eig, 0));
+    kp_status s = batch_launch(b, 2, l, a);
+    if (s != KP_OK) return s;
     KP_TRY(hipEventRecord(b->ev[l], b->lanes[l]));
     KP_TRY(hipStreamWaitEvent(b->st, b->ev[l], 0));
   }

@@ -115,9 +115,12 @@ struct EigProblem {
   double* dmax;       // largest diagonal entry of C (absolute rotation threshold)
   double* Pout;       // n x n result P (row-major)
   double* eout;       // n eigenvalues
+  int* status;        // the owning context's status word (nullptr: the call's)
 };
-// status: the context's status word; done: 2 ints per problem (converged flag,
-// sweeps used); calls: call counter and warm-start flag.  Jacobi starts from the
+// status: the status word of problems without their own; done: 2 ints per
+// problem (converged flag, sweeps used); calls: call counter and warm-start flag.
+// The problems may belong to several contexts (a batch inverts all of its
+// instances' factors in one call).  Jacobi starts from the
 // V left in P[0] by the previous call, except on every refresh-th call (and the
 // first after the counter is reset).
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,

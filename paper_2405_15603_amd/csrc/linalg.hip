@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(const EigProblem* __restrict_
     lb[(long)i * np + c] = c <= i ? L[i * LDB + c] : 0.0;
     li[(long)i * np + c] = c <= i ? X[i * LDB + c] : 0.0;
   }
-  if (threadIdx.x == 0 && bad) atomicMax(status, 4);
+  if (threadIdx.x == 0 && bad) atomicMax(p.status ? p.status : status, 4);
 }
 
 // Panel and trailing update of step j: workgroup (i, k), j <= k <= i, i > j.
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
 
 // After a sweep: converged when no rotation exceeded the threshold.
 __global__ void k_jac_check(const EigProblem* __restrict__ pr, int* done, int nprob) {
-  const int q = threadIdx.x;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nprob) return;
   const EigProblem p = pr[q];
   if (done[2 * q]) return;
@@ -702,7 +702,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
       k_jac_solve<<<dim3(npair, nprob), kSolveThreads, 0, st>>>(probs_dev, done, r, KP_JAC_INNER);
       k_jac_apply<<<dim3(nwg, nprob), 256, 0, st>>>(probs_dev, done, r);
     }
-    k_jac_check<<<1, 64, 0, st>>>(probs_dev, done, nprob);
+    k_jac_check<<<(nprob + 63) / 64, 64, 0, st>>>(probs_dev, done, nprob);
   }
   k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 4, calls + 1);
   k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev);

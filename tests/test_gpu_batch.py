@@ -1,8 +1,10 @@
 """Batches of heterogeneous instances (64-instance recipe: d in {2,5,10,20},
-N ~ U{500..4000}, widths 64/128/256) stepped together through one captured HIP
-graph, against the same instances stepped one context at a time.  The kernels
-and their inputs are the same, so the results must be identical; every graph
-replay is checked, with unrelated eager work and synchronisation in between."""
+N ~ U{500..4000}, widths 64/128/256) stepped together (one inversion launch
+sequence over every instance's factors, captured HIP graphs), against the same
+instances stepped one context at a time.  The kernels and their inputs are the
+same, so the results must be identical, the Jacobi sweep counts included; every
+graph replay is checked, with unrelated eager work and synchronisation in
+between."""
 import ctypes as C
 
 import numpy as np
@@ -28,7 +30,7 @@ def test_batch_matches_single_contexts(use_graph):
     hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
     steps = 3
     # reference: one context per instance, eager
-    ref = []
+    ref, ref_sweeps = [], []
     for p in probs:
         th, (xi, yi, xb, yb) = inputs(p, dev)
         kp = KfacPinn.for_problem(p, "bf16")
@@ -38,6 +40,7 @@ def test_batch_matches_single_contexts(use_graph):
             traj.append(th.clone())
         assert kp.sync() == 0
         ref.append(traj)
+        ref_sweeps.append(kp.get_sweeps())
         del kp
     # the batch
     b = KfacPinnBatch(probs, "bf16", use_graph=use_graph)
@@ -54,6 +57,8 @@ def test_batch_matches_single_contexts(use_graph):
         for k in range(len(probs)):
             assert torch.equal(thetas[k], ref[k][it]), (it, k)
     assert b.sync() == [0] * len(probs)
+    for k in range(len(probs)):
+        assert b.get_sweeps(k) == list(ref_sweeps[k]), k
     raw = infos.cpu().numpy().tobytes()
     sz = C.sizeof(N.kp_step_info)
     for k in range(len(probs)):
