@@ -178,8 +178,8 @@ def cpu_baseline(problem, frac=0.1):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
     ap.add_argument("--workload", default="poisson100d")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
@@ -237,13 +237,13 @@ def main():
                            "algorithmic_hbm_GBs": tm["bytes"] / sec / 1e9,
                            "hbm_frac": tm["bytes"] / sec / 1e9 / HBM_GBS,
                            "share_of_step": tm["ms"] / (ms * args.steps)}
+    side_steps = max(2, min(20, args.steps // 2))   # the comparison legs
     if not args.no_core:
-        msc, _, stc, _ = run_gpu(problem, args.precision, max(2, args.steps // 2), 1, None,
-                                 lr_mode="fixed")
+        msc, _, stc, _ = run_gpu(problem, args.precision, side_steps, 1, None, lr_mode="fixed")
         out["core_step"] = {"value": 1000.0 / msc, "ms_per_step": msc, "status": stc,
                             "note": "fixed step size 2^-5, no line search"}
     if not args.no_fp32 and args.precision != "f32":
-        ms32, _, st32, _ = run_gpu(problem, "f32", max(2, args.steps // 2), 1, None)
+        ms32, _, st32, _ = run_gpu(problem, "f32", side_steps, 1, None)
         out["fp32"] = {"value": 1000.0 / ms32, "ms_per_step": ms32, "status": st32,
                        "mixed_over_fp32": ms32 / ms}
     if not args.no_batch:
