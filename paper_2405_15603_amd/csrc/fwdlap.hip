@@ -1036,18 +1036,6 @@ static dim3 pc_grid(long cols, int npts, int bs) {
   return dim3((unsigned)((cols + bs - 1) / bs), gy, gz);
 }
 
-static int choose_chunks(int tiles, int nd, int has_lap) {
-  if (!has_lap || nd <= 1) return 1;
-  int ch = 1;
-  while (tiles * ch < 512 && ch * 2 <= nd && ch < 16) ch *= 2;
-  return ch;
-}
-
-// The direct-to-LDS kernel holds one workgroup per compute unit and runs the
-// columns of a chunk (its value row, derivative rows and, in the last chunk, the
-// Laplacian row) NS at a time, so a launch takes about
-// ceil(blocks / CUs) * ceil(columns per chunk / NS) pass times: pick the chunk
-// count that minimises that.
 static int compute_units() {
   static int cached[64] = {0};
   int dev = 0;
@@ -1061,16 +1049,32 @@ static int compute_units() {
   return cached[dev];
 }
 
-static int choose_chunks_dma(int tiles, int nd, int has_lap) {
+// Workgroups of `kernel` resident on one compute unit (registers and LDS permitting).
+template <class F>
+static int resident(F* kernel, int threads, int& cache) {
+  if (cache == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1)
+      n = 1;
+    cache = n;
+  }
+  return cache;
+}
+
+// Chunks of derivative rows per layer launch.  A launch of tiles * ch workgroups
+// runs in about ceil(tiles * ch / slots) rounds, each as long as its longest
+// chunk: ceil((len + extra) / ns) column passes, with len = ceil(nd / ch)
+// derivative rows and `extra` rows that a chunk adds (the recomputed value or
+// Laplacian-cotangent row, and the row only the first or last chunk carries).
+// Pick the chunk count that minimises that.
+static int choose_chunks(int tiles, int nd, int has_lap, int slots, int ns, int extra) {
   if (!has_lap || nd <= 1) return 1;
-  typedef DGeo<M_BF16> G;
-  const int cus = compute_units();
   int best = 1;
   long best_cost = -1;
   for (int ch = 1; ch <= kMaxChunks && ch <= nd; ch++) {
     const int len = (nd + ch - 1) / ch;
-    const long rounds = ((long)tiles * ch + cus - 1) / cus;
-    const long passes = (2 + len + G::NS - 1) / G::NS;
+    const long rounds = ((long)tiles * ch + slots - 1) / slots;
+    const long passes = (len + extra + ns - 1) / ns;
     if (best_cost < 0 || rounds * passes < best_cost) {
       best_cost = rounds * passes;
       best = ch;
@@ -1080,15 +1084,38 @@ static int choose_chunks_dma(int tiles, int nd, int has_lap) {
 }
 
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
-  const int BP = mode == M_BF16 ? DGeo<M_BF16>::BP : 128;
-  const int BN = mode == M_BF16 ? DGeo<M_BF16>::BN : (mode == M_F64 ? 64 : 128);
+  static int occ[4] = {0, 0, 0, 0};
+  int per_cu = 1, ns = 1, BP = 128, BN = 128;
+  switch (mode) {
+    case M_BF16:
+      per_cu = resident(k_fwdlap<M_BF16, bf16, true>, DGeo<M_BF16>::NT, occ[M_BF16]);
+      ns = DGeo<M_BF16>::NS;
+      BP = DGeo<M_BF16>::BP;
+      BN = DGeo<M_BF16>::BN;
+      break;
+    case M_F64:
+      per_cu = resident(k_fwdlap<M_F64, double>, kThreads, occ[M_F64]);
+      BN = 64;
+      break;
+    case M_F32: per_cu = resident(k_fwdlap<M_F32, float>, kThreads, occ[M_F32]); break;
+    case M_BF16X3: per_cu = resident(k_fwdlap<M_BF16X3, float>, kThreads, occ[M_BF16X3]); break;
+    default: break;
+  }
   const int tiles = ((N + BP - 1) / BP) * ((h_out + BN - 1) / BN);
-  return mode == M_BF16 ? choose_chunks_dma(tiles, nd, has_lap) : choose_chunks(tiles, nd, has_lap);
+  return choose_chunks(tiles, nd, has_lap, compute_units() * per_cu, ns, 2);
 }
 int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap) {
+  static int occ[4] = {0, 0, 0, 0};
+  int per_cu = 1;
+  switch (mode) {
+    case M_F64: per_cu = resident(k_bwdlap<M_F64, double>, kThreads, occ[M_F64]); break;
+    case M_F32: per_cu = resident(k_bwdlap<M_F32, float>, kThreads, occ[M_F32]); break;
+    case M_BF16X3: per_cu = resident(k_bwdlap<M_BF16X3, float>, kThreads, occ[M_BF16X3]); break;
+    default: break;
+  }
   const int BP = 128, BN = 64;
   const int tiles = ((N + BP - 1) / BP) * ((h + BN - 1) / BN);
-  return choose_chunks(tiles, nd, has_lap);
+  return choose_chunks(tiles, nd, has_lap, compute_units() * per_cu, 1, 2);
 }
 
 template <int MODE, bool NARROW = false>
