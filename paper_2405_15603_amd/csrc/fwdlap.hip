@@ -15,6 +15,11 @@
 // the line search); BF16x3 (FP32 slabs split into BF16 hi + lo on the way into
 // LDS, weights as BF16 hi + lo; acc += hi*hi + lo*hi + hi*lo), used by the
 // mixed-precision curvature pass for FP32-level accuracy at BF16 MFMA rates.
+#include <map>
+#include <mutex>
+#include <queue>
+#include <tuple>
+
 #include "common.h"
 #include "fwdlap.h"
 #include "launch.h"
@@ -1061,25 +1066,61 @@ static int resident(F* kernel, int threads, int& cache) {
   return cache;
 }
 
-// Chunks of derivative rows per layer launch.  A launch of tiles * ch workgroups
-// runs in about ceil(tiles * ch / slots) rounds, each as long as its longest
-// chunk: ceil((len + extra) / ns) column passes, with len = ceil(nd / ch)
-// derivative rows and `extra` rows that a chunk adds (the recomputed value or
-// Laplacian-cotangent row, and the row only the first or last chunk carries).
-// Pick the chunk count that minimises that.
-static int choose_chunks(int tiles, int nd, int has_lap, int slots, int ns, int extra) {
+// Chunks of derivative rows per layer launch.  The launch's time is simulated in
+// column passes: workgroups, dispatched chunk by chunk, go to the earliest free
+// of `slots` places; a chunk takes ceil(cols / ns) passes plus a start-up cost
+// `ov`, where cols counts its derivative rows, the row every chunk recomputes
+// (value, or the Laplacian row's cotangent) and the row that only the last
+// (forward) or first (backward) chunk carries.  The chunk count with the
+// shortest simulated time wins (ties: fewer chunks, less table traffic); results
+// are cached per shape.
+static double launch_time(int tiles, int nd, int ch, int slots, int ns, double ov,
+                          bool extra_first) {
+  const int len = (nd + ch - 1) / ch;
+  std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+  for (int i = 0; i < slots; i++) q.push(0.0);
+  double end = 0.0;
+  for (int c = 0; c < ch; c++) {
+    const int nder = std::max(0, std::min(1 + nd, 1 + (c + 1) * len) - (1 + c * len));
+    const bool extra = extra_first ? c == 0 : c == ch - 1;
+    const double d = (double)((1 + nder + (extra ? 1 : 0) + ns - 1) / ns) + ov;
+    for (int t = 0; t < tiles; t++) {
+      const double f = q.top() + d;
+      q.pop();
+      q.push(f);
+      end = std::max(end, f);
+    }
+  }
+  return end;
+}
+
+static int choose_chunks(int tiles, int nd, int has_lap, int slots, int ns, double ov,
+                         bool extra_first) {
   if (!has_lap || nd <= 1) return 1;
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int, int, bool>, int> cache;
+  const auto key = std::make_tuple(tiles, nd, slots, ns, (int)(ov * 100), extra_first);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
   int best = 1;
-  long best_cost = -1;
+  double best_t = -1.0;
   for (int ch = 1; ch <= kMaxChunks && ch <= nd; ch++) {
+    // very large launches: rounds times the longest chunk instead of the simulation
     const int len = (nd + ch - 1) / ch;
-    const long rounds = ((long)tiles * ch + slots - 1) / slots;
-    const long passes = (len + extra + ns - 1) / ns;
-    if (best_cost < 0 || rounds * passes < best_cost) {
-      best_cost = rounds * passes;
+    const double t =
+        (long)tiles * ch > 65536
+            ? (double)(((long)tiles * ch + slots - 1) / slots) * ((len + 2 + ns - 1) / ns + ov)
+            : launch_time(tiles, nd, ch, slots, ns, ov, extra_first);
+    if (best_t < 0.0 || t < best_t - 1e-9) {
+      best_t = t;
       best = ch;
     }
   }
+  std::lock_guard<std::mutex> g(mu);
+  cache[key] = best;
   return best;
 }
 
@@ -1102,7 +1143,8 @@ int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
     default: break;
   }
   const int tiles = ((N + BP - 1) / BP) * ((h_out + BN - 1) / BN);
-  return choose_chunks(tiles, nd, has_lap, compute_units() * per_cu, ns, 2);
+  return choose_chunks(tiles, nd, has_lap, compute_units() * per_cu, ns, ns > 1 ? 0.3 : 1.0,
+                       false);
 }
 int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap) {
   static int occ[4] = {0, 0, 0, 0};
@@ -1115,7 +1157,7 @@ int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap) {
   }
   const int BP = 128, BN = 64;
   const int tiles = ((N + BP - 1) / BP) * ((h + BN - 1) / BN);
-  return choose_chunks(tiles, nd, has_lap, compute_units() * per_cu, 1, 2);
+  return choose_chunks(tiles, nd, has_lap, compute_units() * per_cu, 1, 1.0, true);
 }
 
 template <int MODE, bool NARROW = false>
