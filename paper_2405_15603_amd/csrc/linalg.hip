@@ -409,8 +409,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
   pair_blocks(i, r, nblk, bx, by);
   __shared__ double S[JS * LDJ];
   __shared__ double V[JS * LDJ];
-  __shared__ double cs[JB], sn[JB];
-  __shared__ int pp[JB], qq[JB];
+  // rotation k of the round: (c, s) and its index pair (p, q), each read as one
+  // 16- or 8-byte access
+  __shared__ double2 rot[JB];
+  __shared__ int2 pq[JB];
   __shared__ int any;
   const long np = p.n_pad;
   const double* C = p.C[0];
@@ -444,7 +446,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
         const double apq = S[a * LDJ + b], app = S[a * LDJ + a], aqq = S[b * LDJ + b];
         double c = 1.0, s = 0.0;
         if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) rotation(app, aqq, apq, c, s);
-        cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
+        rot[k] = make_double2(c, s);
+        pq[k] = make_int2(a, b);
       }
       __syncthreads();
       // S <- J^T S J on 2x2 groups (rows of pair kx, columns of pair ky), V <- V J.
@@ -460,8 +463,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
         for (int it = 0; it < SG; it++) {
           const int e = threadIdx.x + it * kSolveThreads;
           const int kx = e / JB, ky = e % JB;
-          ia[it] = pp[kx]; ib[it] = qq[kx]; jf[it] = pp[ky]; jg[it] = qq[ky];
-          c1[it] = cs[kx]; s1[it] = sn[kx]; c2[it] = cs[ky]; s2[it] = sn[ky];
+          const int2 px = pq[kx], py = pq[ky];
+          const double2 rx = rot[kx], ry = rot[ky];
+          ia[it] = px.x; ib[it] = px.y; jf[it] = py.x; jg[it] = py.y;
+          c1[it] = rx.x; s1[it] = rx.y; c2[it] = ry.x; s2[it] = ry.y;
           x[it][0] = S[ia[it] * LDJ + jf[it]];
           x[it][1] = S[ia[it] * LDJ + jg[it]];
           x[it][2] = S[ib[it] * LDJ + jf[it]];
@@ -474,7 +479,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
         for (int it = 0; it < VG; it++) {
           const int e = threadIdx.x + it * kSolveThreads;
           const int k = e / JS;
-          vr[it] = e % JS; va[it] = pp[k]; vb[it] = qq[k]; vc[it] = cs[k]; vs[it] = sn[k];
+          const int2 pk = pq[k];
+          const double2 rk = rot[k];
+          vr[it] = e % JS; va[it] = pk.x; vb[it] = pk.y; vc[it] = rk.x; vs[it] = rk.y;
           y[it][0] = V[vr[it] * LDJ + va[it]];
           y[it][1] = V[vr[it] * LDJ + vb[it]];
         }
