@@ -966,8 +966,9 @@ static kp_status step_tail(kfac_pinn_ctx* c, void* theta, const void* xi, const 
     for (int k = 0; k < ncand; k++) {
       const double alpha = ldexp(1.0, hp->grid_max_exp - k);
       KP_TRY(axpy_theta(c->pp, theta, c->dhat, alpha, c->theta_trial, c->D, c->st));
+      // the candidate's forward copy only: no backward copy, no BF16x3 low plane
       KP_TRY(prep_weights(c->lp == P_BF16 ? P_BF16 : c->wp, c->theta_trial, nullptr, 0.0, c->nd,
-                          c->w_hi, c->w_lo, nullptr, 0, c->st));
+                          c->w_hi, nullptr, nullptr, 0, c->st, 1));
       KP_TRY(eval_loss(c, xi, yi, ni, xb, yb, nb, 2 + k));
     }
     c->last_ncand = ncand;

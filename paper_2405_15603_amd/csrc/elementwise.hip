@@ -18,13 +18,13 @@ template <typename TP, typename TS>
 __global__ void k_prep_weights(const TP* __restrict__ theta, const TP* __restrict__ dir,
                                double alpha, NetDesc nd, TS* __restrict__ whi,
                                TS* __restrict__ wlo, typename Acc<TS>::type* __restrict__ bias,
-                               long bias_stride) {
+                               long bias_stride, int fwd_only) {
   typedef typename Acc<TS>::type TC;
   const int l = blockIdx.y;
   if (l >= nd.L) return;
   const LayerDesc ld = nd.l[l];
   const long nf = (long)ld.h_out * ld.ldk_in;    // forward copy elements
-  const long nb = (long)ld.h_in * ld.ldk_out;    // backward copy elements
+  const long nb = fwd_only ? 0 : (long)ld.h_in * ld.ldk_out;   // backward copy elements
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nf + nb + ld.h_out;
        e += (long)gridDim.x * blockDim.x) {
     long src = -1, dst;
@@ -57,23 +57,24 @@ __global__ void k_prep_weights(const TP* __restrict__ theta, const TP* __restric
 }
 
 hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha, NetDesc nd,
-                        void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st) {
+                        void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st,
+                        int fwd_only) {
   dim3 g(256, nd.L);
   switch (p) {
     case P_F64:
       k_prep_weights<double, double><<<g, 256, 0, st>>>((const double*)theta, (const double*)dir,
                                                         alpha, nd, (double*)w_hi, nullptr,
-                                                        (double*)bias, bias_stride);
+                                                        (double*)bias, bias_stride, fwd_only);
       break;
     case P_F32:
       k_prep_weights<float, float><<<g, 256, 0, st>>>((const float*)theta, (const float*)dir,
                                                       alpha, nd, (float*)w_hi, nullptr,
-                                                      (float*)bias, bias_stride);
+                                                      (float*)bias, bias_stride, fwd_only);
       break;
     case P_BF16:
       k_prep_weights<float, bf16><<<g, 256, 0, st>>>((const float*)theta, (const float*)dir,
                                                      alpha, nd, (bf16*)w_hi, (bf16*)w_lo,
-                                                     (float*)bias, bias_stride);
+                                                     (float*)bias, bias_stride, fwd_only);
       break;
   }
   return hipGetLastError();

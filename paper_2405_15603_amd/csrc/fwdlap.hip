@@ -922,19 +922,46 @@ __global__ void k_bwd_last(BwdLayerArgs a, const TSd* __restrict__ sigma, long l
 // Per neuron c: the input layer's weights of the derivative rows, stored
 // transposed (wt[i * h_out + c] = W[c, i] in the product precision, W = hi [+ lo])
 // so that row writers read them coalesced, and q[c] = sum_{i in mask} W[c, i]^2.
+// A block of 256 threads takes 64 neurons and walks the inputs 64 at a time
+// through an LDS tile, so that both the weight reads (along i) and the wt
+// writes (along c) are coalesced; q is summed in four interleaved partial sums
+// (i mod 4) added in a fixed order.
 template <typename TW, typename TC>
-__global__ void k_input_q(FwdLayerArgs a, TC* __restrict__ q, TC* __restrict__ wt) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.h_out) return;
-  const TW* w = (const TW*)a.w + (long)c * a.ldw;
-  const TW* w2 = a.w2 ? (const TW*)a.w2 + (long)c * a.ldw : nullptr;
+__global__ __launch_bounds__(256) void k_input_q(FwdLayerArgs a, TC* __restrict__ q,
+                                                 TC* __restrict__ wt) {
+  __shared__ TC tile[64][65];
+  __shared__ TC part[4][64];
+  const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
+  const int c0 = blockIdx.x * 64;
   TC sum = 0;
-  for (int i = 0; i < a.nd; i++) {
-    const TC v = (TC)to_d(w[i]) + (w2 ? (TC)to_d(w2[i]) : (TC)0);
-    wt[(long)i * a.h_out + c] = v;
-    if (mask_at(a.mask, i)) sum += v * v;
+  for (int i0 = 0; i0 < a.nd; i0 += 64) {
+#pragma unroll 4
+    for (int k = 0; k < 16; k++) {
+      const int cr = hi + 4 * k, c = c0 + cr, i = i0 + lo;
+      TC v = 0;
+      if (c < a.h_out && i < a.nd) {
+        const long e = (long)c * a.ldw + i;
+        v = (TC)to_d(((const TW*)a.w)[e]) + (a.w2 ? (TC)to_d(((const TW*)a.w2)[e]) : (TC)0);
+      }
+      tile[cr][lo] = v;
+    }
+    __syncthreads();
+    const int c = c0 + lo;
+#pragma unroll 4
+    for (int k = 0; k < 16; k++) {
+      const int ir = hi + 4 * k, i = i0 + ir;
+      if (c < a.h_out && i < a.nd) {
+        const TC v = tile[lo][ir];
+        wt[(long)i * a.h_out + c] = v;
+        if (mask_at(a.mask, i)) sum += v * v;
+      }
+    }
+    __syncthreads();
   }
-  q[c] = sum;
+  part[hi][lo] = sum;
+  __syncthreads();
+  if (hi == 0 && c0 + lo < a.h_out)
+    q[c0 + lo] = ((part[0][lo] + part[1][lo]) + part[2][lo]) + part[3][lo];
 }
 
 // Eight consecutive values to z (one 16-byte store for BF16, two for FP32).
@@ -1220,25 +1247,25 @@ hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_
   switch (mode) {
     case M_F64: {
       double* qq = (double*)q;
-      k_input_q<double, double><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_q<double, double><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<double, double><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }
     case M_F32: {
       float* qq = (float*)q;
-      k_input_q<float, float><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_q<float, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }
     case M_BF16: {
       float* qq = (float*)q;
-      k_input_q<bf16, float><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_q<bf16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<float, bf16><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }
     case M_BF16X3: {
       float* qq = (float*)q;
-      k_input_q<bf16, float><<<nq, 64, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_q<bf16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }

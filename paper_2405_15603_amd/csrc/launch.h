@@ -40,9 +40,10 @@ struct NetDesc {
 // Builds the product-layout copies of W~ = theta (+ alpha*dir) for all layers:
 // forward copy (h_out x ldk_in, bias in column h_in) and backward copy
 // (h_in x ldk_out, W transposed, no bias), plus biases (compute type) and, for
-// BF16, the residual low parts.
+// BF16, the residual low parts.  fwd_only: the forward copy (and biases) only.
 hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha, NetDesc nd,
-                        void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st);
+                        void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st,
+                        int fwd_only = 0);
 
 // Input slab Z~^(0): S rows per point (value x, unit rows e_i, zero Laplacian row)
 // plus the bias column; n points, d inputs, row length ldz.
