@@ -103,6 +103,8 @@ struct kfac_pinn_ctx {
   long tab_stride = 0;                 // elements per table plane (max N * h)
   void* ls_z[2] = {nullptr, nullptr};
   void* ls_u = nullptr;
+  void* ls_zb[2] = {nullptr, nullptr};   // boundary line-search slabs (paired launches)
+  void* ls_ub = nullptr;
   double* partial = nullptr;
   int partial_n = 0;
   double* loss = nullptr;              // [0] L_int [1] L_bnd [2..] candidates
@@ -232,96 +234,149 @@ struct FwdTarget {
   bool residual_rows = false;    // interior: only the output rows the residual reads
 };
 
+// One hidden layer's product: its arguments, chunk count and accounting.
+struct LayerLaunch {
+  FwdLayerArgs a{};
+  int nch = 1;
+  bool input_rows = false;   // the input layer's rows without products follow
+  double flops = 0.0, bytes = 0.0;
+};
+
+LayerLaunch layer_launch(kfac_pinn_ctx* c, const Slabs& s, int n, int l, int upto,
+                         const FwdTarget& T) {
+  const LayerDesc& ld = c->nd.l[l];
+  const long R = (long)n * s.S;
+  LayerLaunch L;
+  FwdLayerArgs& a = L.a;
+  a.zin = T.z(l);
+  a.ldz = c->ldz[l];
+  a.w = wptr(c->w_hi, ld.wrm, c->esz_w);
+  a.w2 = (T.mode == M_BF16X3) ? wptr(c->w_lo, ld.wrm, c->esz_w) : nullptr;
+  a.ldw = ld.ldk_in;
+  a.K = (int)ld.ldk_in;
+  a.N = n;
+  a.S = s.S;
+  a.nd = s.nd;
+  a.has_lap = s.has_lap;
+  a.h_out = ld.h_out;
+  a.mask = c->mask;
+  a.z = T.z(l + 1);
+  a.ldzo = c->ldz[l + 1];
+  a.pre = T.pre(l);
+  a.ldp = c->ldp[l];
+  const long ts = c->tab_stride;
+  a.tab_t = s.has_lap ? c->tab : nullptr;
+  a.tab_lap = s.has_lap ? wptr(c->tab, ts, c->esz_c) : nullptr;
+  a.tab_sq = s.has_lap ? wptr(c->tab, 2 * ts, c->esz_c) : nullptr;
+  a.sq_out = T.sq(l);
+  if (T.residual_rows && s.has_lap && l == c->L - 2 && upto >= c->L) {
+    // the output layer reads only the time and Laplacian rows of this layer's z
+    a.sparse_store = 1;
+    a.keep_value = 0;
+    const int tr = time_row_of(c, s);
+    a.keep_lo = tr >= 0 ? tr : 1;
+    a.keep_hi = tr >= 0 ? tr : 0;
+  }
+  // input layer: only the value row needs products (its other input rows are
+  // unit vectors and zeros)
+  L.input_rows = l == 0 && s.has_lap;
+  a.value_only = L.input_rows ? 1 : 0;
+  L.nch = L.input_rows ? 1 : fwdlap_chunks(T.mode, n, ld.h_out, s.nd, s.has_lap);
+  const double Rp = L.input_rows ? (double)n : (double)R;   // rows with products
+  // bytes: the input rows with products, the z rows this launch stores (the
+  // Laplacian row is the finishing pass's), the weights and the finishing tables
+  const double zrows =
+      a.value_only ? (double)n
+      : a.sparse_store ? (double)n * (a.keep_value + std::max(0, a.keep_hi - a.keep_lo + 1))
+      : (s.has_lap ? (double)n * (s.S - 1) : (double)R);
+  const double tabs =
+      s.has_lap ? (double)n * ld.h_out * c->esz_c * (a.value_only ? 1 : 2 + L.nch) : 0.0;
+  L.flops = 2.0 * Rp * ld.h_out * (ld.h_in + 1);
+  L.bytes = Rp * (ld.h_in + 1) * T.zesz + zrows * ld.h_out * T.zesz +
+            (double)ld.h_out * (ld.h_in + 1) * c->esz_w + tabs;
+  return L;
+}
+
+// the pass after a layer product: the input layer's remaining rows, or the
+// Laplacian row, bias feature and padding
+hipError_t layer_finish(kfac_pinn_ctx* c, const LayerLaunch& L, const FwdTarget& T) {
+  int ti = tm_begin(c, KC_ACT);
+  hipError_t e = L.input_rows ? input_layer_rows(T.mode, L.a, c->qbuf, c->st)
+                              : fwdlap_finish(T.mode, L.a, L.nch, c->st);
+  tm_end(c, ti, 0.0, 0.0);
+  return e;
+}
+
+hipError_t output_layer(kfac_pinn_ctx* c, const Slabs& s, int n, const FwdTarget& T) {
+  const LayerDesc& ld = c->nd.l[c->L - 1];
+  const long lz = c->ldz[c->L - 1];
+  const void* wl = wptr(T.theta, ld.off, c->esz_p);
+  hipError_t e;
+  if (T.residual_rows && s.has_lap && c->L >= 2) {
+    // only the rows the interior residual reads: the time row and the Laplacian row
+    const int rows[2] = {time_row_of(c, s), lap_row_of(s)};
+    for (int k = 0; k < 2; k++) {
+      if (rows[k] < 0) continue;
+      const long off = (long)rows[k] * n;
+      if ((e = last_fwd(T.mode, wptr(T.z(c->L - 1), off * lz, T.zesz), lz, wl, ld.h_in + 1, n,
+                        wptr(T.u, off, c->esz_c), c->st)) != hipSuccess)
+        return e;
+    }
+    return hipSuccess;
+  }
+  return last_fwd(T.mode, T.z(c->L - 1), lz, wl, ld.h_in + 1, (long)n * s.S, T.u, c->st);
+}
+
+int input_rows_of(kfac_pinn_ctx* c, const Slabs& s, const FwdTarget& T) {
+  // Only the layer products read the input slab's derivative and Laplacian rows
+  // (unit vectors and zeros); the input layer handles those rows without them,
+  // so a pass that needs no input-layer factors writes the value rows only.
+  return (T.full_input || !s.has_lap || c->L < 2) ? s.S : 1;
+}
+
 // Forward through hidden layers [0, upto) and, when upto == L, the output layer.
 hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, int upto,
                        const FwdTarget& T) {
   hipError_t e;
-  const long R = (long)n * s.S;
-  // Only the layer products read the input slab's derivative and Laplacian rows
-  // (unit vectors and zeros); the input layer handles those rows without them,
-  // so a pass that needs no input-layer factors writes the value rows only.
-  const int s_in = (T.full_input || !s.has_lap || c->L < 2) ? s.S : 1;
-  if ((e = input_slab(T.zp, x, n, c->d, s_in, T.z(0), c->ldz[0], c->st)) != hipSuccess) return e;
+  if ((e = input_slab(T.zp, x, n, c->d, input_rows_of(c, s, T), T.z(0), c->ldz[0], c->st)) !=
+      hipSuccess)
+    return e;
   const int nh = upto < c->L ? upto : c->L - 1;
   for (int l = 0; l < nh; l++) {
-    const LayerDesc& ld = c->nd.l[l];
-    FwdLayerArgs a{};
-    a.zin = T.z(l);
-    a.ldz = c->ldz[l];
-    a.w = wptr(c->w_hi, ld.wrm, c->esz_w);
-    a.w2 = (T.mode == M_BF16X3) ? wptr(c->w_lo, ld.wrm, c->esz_w) : nullptr;
-    a.ldw = ld.ldk_in;
-    a.K = (int)ld.ldk_in;
-    a.N = n;
-    a.S = s.S;
-    a.nd = s.nd;
-    a.has_lap = s.has_lap;
-    a.h_out = ld.h_out;
-    a.mask = c->mask;
-    a.z = T.z(l + 1);
-    a.ldzo = c->ldz[l + 1];
-    a.pre = T.pre(l);
-    a.ldp = c->ldp[l];
-    const long ts = c->tab_stride;
-    a.tab_t = s.has_lap ? c->tab : nullptr;
-    a.tab_lap = s.has_lap ? wptr(c->tab, ts, c->esz_c) : nullptr;
-    a.tab_sq = s.has_lap ? wptr(c->tab, 2 * ts, c->esz_c) : nullptr;
-    a.sq_out = T.sq(l);
-    if (T.residual_rows && s.has_lap && l == c->L - 2 && upto >= c->L) {
-      // the output layer reads only the time and Laplacian rows of this layer's z
-      a.sparse_store = 1;
-      a.keep_value = 0;
-      const int tr = time_row_of(c, s);
-      a.keep_lo = tr >= 0 ? tr : 1;
-      a.keep_hi = tr >= 0 ? tr : 0;
-    }
-    // input layer: only the value row needs products (its other input rows are
-    // unit vectors and zeros)
-    const bool input_rows = l == 0 && s.has_lap;
-    a.value_only = input_rows ? 1 : 0;
-    const int nch = input_rows ? 1 : fwdlap_chunks(T.mode, n, ld.h_out, s.nd, s.has_lap);
-    const double Rp = input_rows ? (double)n : (double)R;   // rows with products
+    const LayerLaunch L = layer_launch(c, s, n, l, upto, T);
     int ti = tm_begin(c, T.kc_layer);
-    if ((e = fwdlap_main(T.mode, a, nch, c->st)) != hipSuccess) return e;
-    // bytes: the input rows with products, the z rows this launch stores (the
-    // Laplacian row is the finishing pass's), the weights and the finishing tables
-    const double zrows =
-        a.value_only ? (double)n
-        : a.sparse_store ? (double)n * (a.keep_value + std::max(0, a.keep_hi - a.keep_lo + 1))
-        : (s.has_lap ? (double)n * (s.S - 1) : (double)R);
-    const double tabs =
-        s.has_lap ? (double)n * ld.h_out * c->esz_c * (a.value_only ? 1 : 2 + nch) : 0.0;
-    tm_end(c, ti, 2.0 * Rp * ld.h_out * (ld.h_in + 1),
-           Rp * (ld.h_in + 1) * T.zesz + zrows * ld.h_out * T.zesz +
-               (double)ld.h_out * (ld.h_in + 1) * c->esz_w + tabs);
-    ti = tm_begin(c, KC_ACT);
-    if (input_rows)
-      e = input_layer_rows(T.mode, a, c->qbuf, c->st);
-    else
-      e = fwdlap_finish(T.mode, a, nch, c->st);
-    if (e != hipSuccess) return e;
-    tm_end(c, ti, 0.0, 0.0);
+    if ((e = fwdlap_main(T.mode, L.a, L.nch, c->st)) != hipSuccess) return e;
+    tm_end(c, ti, L.flops, L.bytes);
+    if ((e = layer_finish(c, L, T)) != hipSuccess) return e;
   }
-  if (upto >= c->L) {
-    const LayerDesc& ld = c->nd.l[c->L - 1];
-    const long lz = c->ldz[c->L - 1];
-    const void* wl = wptr(T.theta, ld.off, c->esz_p);
-    if (T.residual_rows && s.has_lap && c->L >= 2) {
-      // only the rows the interior residual reads: the time row and the Laplacian row
-      const int rows[2] = {time_row_of(c, s), lap_row_of(s)};
-      for (int k = 0; k < 2; k++) {
-        if (rows[k] < 0) continue;
-        const long off = (long)rows[k] * n;
-        if ((e = last_fwd(T.mode, wptr(T.z(c->L - 1), off * lz, T.zesz), lz, wl, ld.h_in + 1, n,
-                          wptr(T.u, off, c->esz_c), c->st)) != hipSuccess)
-          return e;
-      }
-    } else if ((e = last_fwd(T.mode, T.z(c->L - 1), lz, wl, ld.h_in + 1, R, T.u, c->st)) !=
-               hipSuccess) {
-      return e;
-    }
-  }
+  if (upto >= c->L) return output_layer(c, s, n, T);
   return hipSuccess;
+}
+
+// The interior and boundary forwards of one line-search candidate, each hidden
+// layer's two products in one launch (the boundary tiles fill the interior
+// launch's last round).
+hipError_t forward_pair(kfac_pinn_ctx* c, const void* xi, int ni, const FwdTarget& Ti,
+                        const void* xb, int nb, const FwdTarget& Tb) {
+  hipError_t e;
+  const Slabs& si = c->si;
+  const Slabs& sb = c->sb;
+  if ((e = input_slab(Ti.zp, xi, ni, c->d, input_rows_of(c, si, Ti), Ti.z(0), c->ldz[0],
+                      c->st)) != hipSuccess ||
+      (e = input_slab(Tb.zp, xb, nb, c->d, input_rows_of(c, sb, Tb), Tb.z(0), c->ldz[0],
+                      c->st)) != hipSuccess)
+    return e;
+  for (int l = 0; l < c->L - 1; l++) {
+    const LayerLaunch Li = layer_launch(c, si, ni, l, c->L, Ti);
+    const LayerLaunch Lb = layer_launch(c, sb, nb, l, c->L, Tb);
+    int ti = tm_begin(c, Ti.kc_layer);
+    if ((e = fwdlap_pair(Ti.mode, Li.a, Li.nch, &Lb.a, c->st)) != hipSuccess) return e;
+    tm_end(c, ti, Li.flops + Lb.flops, Li.bytes + Lb.bytes);
+    if ((e = layer_finish(c, Li, Ti)) != hipSuccess || (e = layer_finish(c, Lb, Tb)) != hipSuccess)
+      return e;
+  }
+  if ((e = output_layer(c, si, ni, Ti)) != hipSuccess) return e;
+  return output_layer(c, sb, nb, Tb);
 }
 
 FwdTarget curvature_target(kfac_pinn_ctx* c, Slabs& s, const void* theta) {
@@ -511,6 +566,14 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   T.kc_layer = KC_LS_LAYER;
   T.full_input = false;
   T.residual_rows = true;
+  if (ni > 0 && nb > 0 && T.mode == M_BF16 && !c->sb.has_lap && c->L >= 2) {
+    FwdTarget Tb = T;
+    Tb.z = [c](int l) { return c->ls_zb[l & 1]; };
+    Tb.u = c->ls_ub;
+    if ((e = forward_pair(c, xi, ni, T, xb, nb, Tb)) != hipSuccess) return e;
+    if ((e = residual_loss_only(c, c->si, c->ls_u, yi, ni, slot, 0)) != hipSuccess) return e;
+    return residual_loss_only(c, c->sb, c->ls_ub, yb, nb, slot, 1);
+  }
   int acc = 0;
   if (ni > 0) {
     if ((e = forward_run(c, c->si, xi, ni, c->L, T)) != hipSuccess) return e;
@@ -668,6 +731,12 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   ALLOC(c->ls_z[0], Rmax * c->ldz_max * c->esz_l);
   ALLOC(c->ls_z[1], Rmax * c->ldz_max * c->esz_l);
   ALLOC(c->ls_u, Rmax * c->esz_c);
+  if (c->lmode == M_BF16 && c->max_b > 0) {
+    const size_t Rb = (size_t)c->max_b * c->sb.S;
+    ALLOC(c->ls_zb[0], Rb * c->ldz_max * c->esz_l);
+    ALLOC(c->ls_zb[1], Rb * c->ldz_max * c->esz_l);
+    ALLOC(c->ls_ub, Rb * c->esz_c);
+  }
   {
     int hmax = 1;
     for (int l = 1; l < c->L; l++) hmax = std::max(hmax, c->w[l]);

@@ -55,6 +55,11 @@ struct BwdLayerArgs {
 
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap);
 hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
+// One launch for two point sets of the same layer: a in nch chunks and b (or
+// nullptr), plain rows without derivative or Laplacian rows (the boundary
+// points), sharing a's weights and output row layout.
+hipError_t fwdlap_pair(int mode, const FwdLayerArgs& a, int nch, const FwdLayerArgs* b,
+                       hipStream_t st);
 hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
 // The input layer's derivative and Laplacian rows without products: its input
 // rows are unit vectors and zero, so a_i = W[:, i] for every point and a_Lap = 0.

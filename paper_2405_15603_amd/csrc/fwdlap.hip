@@ -505,8 +505,11 @@ template <int MODE> constexpr int fwd_smem() {
     return (int)sizeof(typename Mainloop<MODE>::Smem);
 }
 
-template <int MODE, typename TZ, bool A4 = false>
-__global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
+// One workgroup of a layer product: tile t, chunk `chunk` of nch.  PLAIN: rows
+// without derivative or Laplacian rows (one column per point, no tables).
+template <int MODE, typename TZ, bool A4, bool PLAIN = false>
+__device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chunk, int nch,
+                                          char* smem) {
   typedef Op<MODE> O;
   typedef FwdGeo<MODE> G;
   typedef typename O::TC TC;
@@ -517,20 +520,16 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
   // is 4-aligned (A4), stores them as one vector.
   constexpr bool TR = kDma<MODE>;
   constexpr bool VEC = TR && A4;
-  constexpr int SMEM = fwd_smem<MODE>();
-  __shared__ __align__(16) char smem[SMEM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wp = wave / G::NWN, wn = wave % G::NWN;
   const int ntc = (a.h_out + G::BN - 1) / G::BN;
   const int ntp = (a.N + G::BP - 1) / G::BP;
-  const int t = xcd_tile(blockIdx.x, ntp * ntc);
   const int p0 = (t / ntc) * G::BP, c0 = (t % ntc) * G::BN;
-  const int chunk = blockIdx.y, nch = gridDim.y;
   const int nd = a.nd;
   const int len = (nd + nch - 1) / nch;
   const int dbeg = 1 + chunk * len, dend = min(1 + nd, dbeg + len);
-  const int nder = a.value_only ? 0 : max(0, dend - dbeg);
-  const bool lap_here = a.has_lap && !a.value_only && chunk == nch - 1;
+  const int nder = (PLAIN || a.value_only) ? 0 : max(0, dend - dbeg);
+  const bool lap_here = !PLAIN && a.has_lap && !a.value_only && chunk == nch - 1;
   const int nsteps = 1 + nder + (lap_here ? 1 : 0);
   const int S = a.S;
   // output coordinates of accumulator element (i, j, e)
@@ -699,6 +698,23 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a) {
         }
       }
   }
+}
+
+// Grid (tiles0 + tiles1) x nch: blocks x < tiles0 take the tiles of layer
+// product a0 in chunk y; blocks x >= tiles0 of chunk 0 take the tiles of a1, a
+// second point set of the same layer without derivative rows (the boundary
+// points), in one chunk; the other blocks return at once.  The two sets take
+// separate inlined copies of the block, so neither pays registers for choosing
+// between them.
+template <int MODE, typename TZ, bool A4 = false>
+__global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a0, FwdLayerArgs a1,
+                                                             int tiles0) {
+  __shared__ __align__(16) char smem[fwd_smem<MODE>()];
+  if ((int)blockIdx.x < tiles0)
+    fwd_block<MODE, TZ, A4>(a0, xcd_tile(blockIdx.x, tiles0), blockIdx.y, gridDim.y, smem);
+  else if (blockIdx.y == 0)
+    fwd_block<MODE, TZ, A4, true>(a1, xcd_tile(blockIdx.x - tiles0, gridDim.x - tiles0), 0, 1,
+                                  smem);
 }
 
 // Laplacian rows  Lz = s1 La + s2 sum_chunks sq, the bias feature and padding.
@@ -1193,33 +1209,48 @@ static dim3 tile_grid(int N, int cols, int nch) {
   return dim3(((N + G::BP - 1) / G::BP) * ((cols + G::BN - 1) / G::BN), nch);
 }
 
-hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
-  if (a.N <= 0) return hipSuccess;
+template <int MODE>
+static int fwd_tiles(const FwdLayerArgs& a) {
+  typedef FwdGeo<MODE> G;
+  return a.N > 0 ? ((a.N + G::BP - 1) / G::BP) * ((a.h_out + G::BN - 1) / G::BN) : 0;
+}
+
+template <int MODE, typename TZ, bool A4>
+static void launch_fwd(const FwdLayerArgs& a0, int nch, const FwdLayerArgs* a1, hipStream_t st) {
+  const int t0 = fwd_tiles<MODE>(a0);
+  const int t1 = a1 ? fwd_tiles<MODE>(*a1) : 0;
+  const FwdLayerArgs none{};
+  k_fwdlap<MODE, TZ, A4><<<dim3(t0 + t1, nch), FwdGeo<MODE>::NT, 0, st>>>(a0, a1 ? *a1 : none, t0);
+}
+
+static bool fwd_args_ok(const FwdLayerArgs& a) {
   // the direct-to-LDS loop keeps per-point offsets in 32 bits
-  if ((long)a.N * a.ldz >= 0x7fffffffL || (long)a.h_out * a.ldw >= 0x7fffffffL)
-    return hipErrorInvalidValue;
+  return (long)a.N * a.ldz < 0x7fffffffL && (long)a.h_out * a.ldw < 0x7fffffffL;
+}
+
+hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
+  return fwdlap_pair(mode, a, nch, nullptr, st);
+}
+
+hipError_t fwdlap_pair(int mode, const FwdLayerArgs& a, int nch, const FwdLayerArgs* b,
+                       hipStream_t st) {
+  if (b && (b->N <= 0 || b->has_lap || b->value_only || b->sparse_store || b->h_out != a.h_out ||
+            b->ldzo != a.ldzo || b->pre || b->w != a.w))
+    return hipErrorInvalidValue;   // the second set: plain rows of the same layer
+  if (a.N <= 0) return b ? fwdlap_pair(mode, *b, 1, nullptr, st) : hipSuccess;
+  if (!fwd_args_ok(a) || (b && !fwd_args_ok(*b))) return hipErrorInvalidValue;
   switch (mode) {
-    case M_F64:
-      k_fwdlap<M_F64, double><<<tile_grid<M_F64>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
-      break;
-    case M_F32:
-      k_fwdlap<M_F32, float><<<tile_grid<M_F32>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
-      break;
-    case M_BF16: {
-      typedef DGeo<M_BF16> G;
-      const dim3 g(((a.N + G::BP - 1) / G::BP) * ((a.h_out + G::BN - 1) / G::BN), nch);
+    case M_F64: launch_fwd<M_F64, double, false>(a, nch, b, st); break;
+    case M_F32: launch_fwd<M_F32, float, false>(a, nch, b, st); break;
+    case M_BF16:
       // 4-aligned rows take the vector epilogue (table planes are 4-aligned)
       if ((a.h_out & 3) == 0 && (a.ldzo & 3) == 0 && (!a.pre || (a.ldp & 3) == 0))
-        k_fwdlap<M_BF16, bf16, true><<<g, G::NT, 0, st>>>(a);
+        launch_fwd<M_BF16, bf16, true>(a, nch, b, st);
       else
-        k_fwdlap<M_BF16, bf16, false><<<g, G::NT, 0, st>>>(a);
+        launch_fwd<M_BF16, bf16, false>(a, nch, b, st);
       break;
-    }
-    case M_BF16X3:
-      k_fwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3>(a.N, a.h_out, nch), kThreads, 0, st>>>(a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case M_BF16X3: launch_fwd<M_BF16X3, float, false>(a, nch, b, st); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
