@@ -103,7 +103,10 @@ struct kfac_pinn_ctx {
   long tab_stride = 0;                 // elements per table plane (max N * h)
   void* ls_z[2] = {nullptr, nullptr};
   void* ls_u = nullptr;
-  void* ls_zb[2] = {nullptr, nullptr};   // boundary line-search slabs (paired launches)
+  // boundary line-search slabs, one per layer input: their bias and padding
+  // columns are written once at creation (one row per point, so they do not depend
+  // on the point count), and the paired launches store only the product columns
+  void* ls_zb[kMaxLayers] = {};
   void* ls_ub = nullptr;
   double* partial = nullptr;
   int partial_n = 0;
@@ -372,8 +375,8 @@ hipError_t forward_pair(kfac_pinn_ctx* c, const void* xi, int ni, const FwdTarge
     int ti = tm_begin(c, Ti.kc_layer);
     if ((e = fwdlap_pair(Ti.mode, Li.a, Li.nch, &Lb.a, c->st)) != hipSuccess) return e;
     tm_end(c, ti, Li.flops + Lb.flops, Li.bytes + Lb.bytes);
-    if ((e = layer_finish(c, Li, Ti)) != hipSuccess || (e = layer_finish(c, Lb, Tb)) != hipSuccess)
-      return e;
+    // the boundary slabs' bias and padding columns are constant (written at creation)
+    if ((e = layer_finish(c, Li, Ti)) != hipSuccess) return e;
   }
   if ((e = output_layer(c, si, ni, Ti)) != hipSuccess) return e;
   return output_layer(c, sb, nb, Tb);
@@ -568,7 +571,7 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   T.residual_rows = true;
   if (ni > 0 && nb > 0 && T.mode == M_BF16 && !c->sb.has_lap && c->L >= 2) {
     FwdTarget Tb = T;
-    Tb.z = [c](int l) { return c->ls_zb[l & 1]; };
+    Tb.z = [c](int l) { return c->ls_zb[l]; };
     Tb.u = c->ls_ub;
     if ((e = forward_pair(c, xi, ni, T, xb, nb, Tb)) != hipSuccess) return e;
     if ((e = residual_loss_only(c, c->si, c->ls_u, yi, ni, slot, 0)) != hipSuccess) return e;
@@ -733,8 +736,22 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   ALLOC(c->ls_u, Rmax * c->esz_c);
   if (c->lmode == M_BF16 && c->max_b > 0) {
     const size_t Rb = (size_t)c->max_b * c->sb.S;
-    ALLOC(c->ls_zb[0], Rb * c->ldz_max * c->esz_l);
-    ALLOC(c->ls_zb[1], Rb * c->ldz_max * c->esz_l);
+    for (int l = 0; l < c->L; l++) {
+      ALLOC(c->ls_zb[l], Rb * c->ldz[l] * c->esz_l);
+      if (l == 0) continue;
+      FwdLayerArgs a{};
+      a.N = c->max_b;
+      a.S = 1;
+      a.h_out = c->w[l];
+      a.z = c->ls_zb[l];
+      a.ldzo = c->ldz[l];
+      if ((e = fwdlap_finish(c->lmode, a, 1, c->st)) != hipSuccess ||
+          (e = hipStreamSynchronize(c->st)) != hipSuccess) {
+        kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+        kfac_pinn_destroy(c);
+        return KP_ERR_HIP;
+      }
+    }
     ALLOC(c->ls_ub, Rb * c->esz_c);
   }
   {
