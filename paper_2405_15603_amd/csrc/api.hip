@@ -356,9 +356,9 @@ hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, i
   return hipSuccess;
 }
 
-// The interior and boundary forwards of one line-search candidate, each hidden
-// layer's two products in one launch (the boundary tiles fill the interior
-// launch's last round).
+// The interior and boundary forwards of one line-search candidate through the
+// hidden layers, each layer's two products in one launch (the boundary tiles
+// fill the interior launch's last round); the output layer is the loss kernel's.
 hipError_t forward_pair(kfac_pinn_ctx* c, const void* xi, int ni, const FwdTarget& Ti,
                         const void* xb, int nb, const FwdTarget& Tb) {
   hipError_t e;
@@ -378,8 +378,7 @@ hipError_t forward_pair(kfac_pinn_ctx* c, const void* xi, int ni, const FwdTarge
     // the boundary slabs' bias and padding columns are constant (written at creation)
     if ((e = layer_finish(c, Li, Ti)) != hipSuccess) return e;
   }
-  if ((e = output_layer(c, si, ni, Ti)) != hipSuccess) return e;
-  return output_layer(c, sb, nb, Tb);
+  return hipSuccess;
 }
 
 FwdTarget curvature_target(kfac_pinn_ctx* c, Slabs& s, const void* theta) {
@@ -574,8 +573,11 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
     Tb.z = [c](int l) { return c->ls_zb[l]; };
     Tb.u = c->ls_ub;
     if ((e = forward_pair(c, xi, ni, T, xb, nb, Tb)) != hipSuccess) return e;
-    if ((e = residual_loss_only(c, c->si, c->ls_u, yi, ni, slot, 0)) != hipSuccess) return e;
-    return residual_loss_only(c, c->sb, c->ls_ub, yb, nb, slot, 1);
+    const LayerDesc& ld = c->nd.l[c->L - 1];
+    return ls_loss(T.mode, T.z(c->L - 1), c->ldz[c->L - 1], ni, time_row_of(c, c->si),
+                   lap_row_of(c->si), c->c_t, c->c_lap, yi, Tb.z(c->L - 1), c->ldz[c->L - 1], nb,
+                   yb, wptr(T.theta, ld.off, c->esz_p), ld.h_in + 1, c->partial, c->loss + slot,
+                   c->st);
   }
   int acc = 0;
   if (ni > 0) {
@@ -760,7 +762,8 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     c->tab_stride = ((long)std::max(c->max_i, 1) * hmax + 3) & ~3L;   // 16-byte planes
     ALLOC(c->tab, (size_t)c->tab_stride * (2 + kMaxChunks) * c->esz_c);
   }
-  c->partial_n = residual_blocks(std::max(c->max_i, c->max_b));
+  c->partial_n = std::max(residual_blocks(std::max(c->max_i, c->max_b)),
+                          ls_loss_blocks(c->max_i, c->max_b));
   ALLOC(c->partial, sizeof(double) * c->partial_n);
   ALLOC(c->loss, sizeof(double) * (2 + kMaxCand + 2));
   for (int t = 0; t < 2; t++)

@@ -74,6 +74,15 @@ hipError_t bwdlap_finish(int mode, const BwdLayerArgs& a, int nch, hipStream_t s
 // output layer: u[row] = z[row] . w over K entries (bias column included)
 hipError_t last_fwd(int mode, const void* z, long ldz, const void* w, int K, long R, void* u,
                     hipStream_t st);
+// The loss L(theta) of one line-search candidate (BF16 slabs) from the last hidden
+// layer's rows of both point sets: interior rows time_row / lap_row (< 0: absent)
+// of an s-major slab of ni points, boundary rows of nb points, output weights w
+// (K = h_in + 1 values, bias last); partial holds ls_loss_blocks(ni, nb) doubles.
+int ls_loss_blocks(int ni, int nb);
+hipError_t ls_loss(int mode, const void* zi, long ldzi, int ni, int time_row, int lap_row,
+                   double c_t, double c_lap, const void* yi, const void* zb, long ldzb, int nb,
+                   const void* yb, const void* w, int K, double* partial, double* loss,
+                   hipStream_t st);
 // gradients of the last hidden layer from output seeds sigma (row stride lds)
 hipError_t bwd_last(int mode, const BwdLayerArgs& a, const void* sigma, long lds, const void* wl,
                     hipStream_t st);

@@ -891,6 +891,62 @@ __global__ __launch_bounds__(256) void k_last_fwd(const TZ* __restrict__ z, long
   if (lane == 0) u[row] = s;
 }
 
+// One line-search candidate's loss terms in one launch: each wave takes a point
+// (blocks [0, nbi) the interior points, 4 per block, the rest the boundary points),
+// forms its output rows as the dot products k_last_fwd forms (same order), its
+// residual (interior c_t u_t + c_lap u_lap - y, boundary u - y) and the block's
+// sum of squared residuals; k_ls_finalize adds the block sums of each term with
+// its 1 / (2 count).
+template <typename TZ, typename TW, typename TY>
+__global__ __launch_bounds__(256) void k_ls_loss(const TZ* __restrict__ zi, long ldzi, int ni,
+                                                 int time_row, int lap_row, double c_t,
+                                                 double c_lap, const TY* __restrict__ yi,
+                                                 const TZ* __restrict__ zb, long ldzb, int nb,
+                                                 const TY* __restrict__ yb,
+                                                 const TW* __restrict__ w, int K, int nbi,
+                                                 double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  auto dot = [&](const TZ* z) {
+    float s = 0.f;
+    for (int k = lane; k < K; k += 64) s += (float)to_d(z[k]) * (float)to_d(w[k]);
+    return warp_sum(s);
+  };
+  const bool bnd = (int)blockIdx.x >= nbi;
+  const int p = ((int)blockIdx.x - (bnd ? nbi : 0)) * 4 + wave;
+  double sq = 0.0;
+  if (!bnd && p < ni) {
+    double v = -(double)yi[p];
+    if (lap_row >= 0) v += c_lap * (double)dot(zi + ((long)lap_row * ni + p) * ldzi);
+    if (time_row >= 0) v += c_t * (double)dot(zi + ((long)time_row * ni + p) * ldzi);
+    sq = v * v;
+  } else if (bnd && p < nb) {
+    const double v = (double)dot(zb + (long)p * ldzb) - (double)yb[p];
+    sq = v * v;
+  }
+  if (lane == 0) red[wave] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_ls_finalize(const double* __restrict__ partial, int nbi,
+                                                     int nbt, double si, double sb,
+                                                     double* __restrict__ loss) {
+  __shared__ double red[2][4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nbt; i += 256) (i < nbi ? a : b) += partial[i];
+  a = warp_sum(a);
+  b = warp_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    *loss = si * (red[0][0] + red[0][1] + red[0][2] + red[0][3]) +
+            sb * (red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+}
+
 // g of the last hidden layer from the output seeds sigma (zbar_s = sigma_s w):
 // the same adjoint as k_bwdlap with an outer-product zbar.
 template <typename TC, typename TSd, typename TG, typename TW>
@@ -1358,6 +1414,21 @@ hipError_t last_fwd(int mode, const void* z, long ldz, const void* w, int K, lon
                                                           K, R, (float*)u);
       break;
   }
+  return hipGetLastError();
+}
+
+int ls_loss_blocks(int ni, int nb) { return (ni + 3) / 4 + (nb + 3) / 4; }
+
+hipError_t ls_loss(int mode, const void* zi, long ldzi, int ni, int time_row, int lap_row,
+                   double c_t, double c_lap, const void* yi, const void* zb, long ldzb, int nb,
+                   const void* yb, const void* w, int K, double* partial, double* loss,
+                   hipStream_t st) {
+  if (mode != M_BF16 || ni <= 0 || nb <= 0) return hipErrorInvalidValue;
+  const int nbi = (ni + 3) / 4, nbt = ls_loss_blocks(ni, nb);
+  k_ls_loss<bf16, float, float><<<nbt, 256, 0, st>>>(
+      (const bf16*)zi, ldzi, ni, time_row, lap_row, c_t, c_lap, (const float*)yi, (const bf16*)zb,
+      ldzb, nb, (const float*)yb, (const float*)w, K, nbi, partial);
+  k_ls_finalize<<<1, 256, 0, st>>>(partial, nbi, nbt, 0.5 / ni, 0.5 / nb, loss);
   return hipGetLastError();
 }
 
