@@ -115,7 +115,9 @@ struct Mainloop {
 // epilogue epi(step, s) runs when a column's product is complete.  The global
 // loads of the next k-tile (also across columns) are in flight while the
 // current one is multiplied; one barrier per k-tile.
-template <int MODE, bool NARROW, class SOf, class Epi>
+// TRANS: the accumulators hold the transposed tile (MFMA rows are columns of B,
+// MFMA columns are rows of A).
+template <int MODE, bool NARROW, class SOf, class Epi, bool TRANS = false>
 __device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
                                       const typename Op<MODE>::TA* __restrict__ A, long lda,
                                       int N, int p0, const typename Op<MODE>::TB* __restrict__ B,
@@ -221,10 +223,18 @@ __device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
       for (int i = 0; i < G::TI; i++)
 #pragma unroll
         for (int j = 0; j < G::TJ; j++) {
-          acc[i][j] = MF::mma(a[0][i], b[0][j], acc[i][j]);
-          if constexpr (MODE == M_BF16X3) {
-            acc[i][j] = MF::mma(a[O::NA - 1][i], b[0][j], acc[i][j]);
-            acc[i][j] = MF::mma(a[0][i], b[NB - 1][j], acc[i][j]);
+          if constexpr (TRANS) {
+            acc[i][j] = MF::mma(b[0][j], a[0][i], acc[i][j]);
+            if constexpr (MODE == M_BF16X3) {
+              acc[i][j] = MF::mma(b[0][j], a[O::NA - 1][i], acc[i][j]);
+              acc[i][j] = MF::mma(b[NB - 1][j], a[0][i], acc[i][j]);
+            }
+          } else {
+            acc[i][j] = MF::mma(a[0][i], b[0][j], acc[i][j]);
+            if constexpr (MODE == M_BF16X3) {
+              acc[i][j] = MF::mma(a[O::NA - 1][i], b[0][j], acc[i][j]);
+              acc[i][j] = MF::mma(a[0][i], b[NB - 1][j], acc[i][j]);
+            }
           }
         }
     }
@@ -747,6 +757,120 @@ __global__ void k_fwdlap_finish(FwdLayerArgs a, int nch) {
 //   g_0 = s1 zbar_0 + s2 sum_i d_i a zbar_i + (s2 La + s3 sq) Lbar   (finishing pass)
 // Every chunk first recomputes the Laplacian row's cotangent Lbar.
 // ---------------------------------------------------------------------------
+// The same backward layer with the transposed product: a lane holds four
+// consecutive neurons of one point, so every slab, table and pre-activation
+// access is one 16-byte vector (all row lengths 4-aligned, FP32 rows), and each
+// column kind has its own loop.  The tanh derivatives s1, s2 of each output are
+// formed once.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_bwdlap_vec(BwdLayerArgs a) {
+  typedef Op<MODE> O;
+  typedef Geo<MODE, true> G;
+  typedef Mfma<typename O::TL> MF;
+  static_assert(std::is_same<typename O::TC, float>::value, "FP32 compute rows");
+  __shared__ typename Mainloop<MODE, true>::Smem sm;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wp = wave >> 1, wn = wave & 1;
+  const int ntc = (a.h + G::BN - 1) / G::BN;
+  const int ntp = (a.N + G::BP - 1) / G::BP;
+  const int t = xcd_tile(blockIdx.x, ntp * ntc);
+  const int p0 = (t / ntc) * G::BP, c0 = (t % ntc) * G::BN;
+  const int chunk = blockIdx.y, nch = gridDim.y;
+  const int nd = a.nd;
+  const int len = (nd + nch - 1) / nch;
+  const int dbeg = 1 + chunk * len, dend = min(1 + nd, dbeg + len);
+  const int nder = max(0, dend - dbeg);
+  const int hl = a.has_lap ? 1 : 0;
+  const int nsteps = hl + nder + (chunk == 0 ? 1 : 0);
+  const float* pre = (const float*)a.pre;
+  // output coordinates: point P(i) (lane & 15), neurons Cn(j) .. Cn(j) + 3
+  int pp[G::TI], cc[G::TJ];
+  bool pok[G::TI], cok[G::TJ];
+#pragma unroll
+  for (int i = 0; i < G::TI; i++) {
+    pp[i] = p0 + wp * G::WP + i * 16 + (lane & 15);
+    pok[i] = pp[i] < a.N;
+  }
+#pragma unroll
+  for (int j = 0; j < G::TJ; j++) {
+    cc[j] = c0 + wn * G::WN + j * 16 + 4 * (lane >> 4);
+    cok[j] = cc[j] < a.h;
+  }
+  f32x4 s1[G::TI][G::TJ], s2[G::TI][G::TJ], lb[G::TI][G::TJ], sum1[G::TI][G::TJ];
+#pragma unroll
+  for (int i = 0; i < G::TI; i++)
+#pragma unroll
+    for (int j = 0; j < G::TJ; j++) {
+      f32x4 tt = {0.f, 0.f, 0.f, 0.f};
+      if (pok[i] && cok[j]) tt = *gmem((const f32x4*)(pre + (long)pp[i] * a.ldp + cc[j]));
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const float th = act_tanh(tt[e]);
+        s1[i][j][e] = 1.f - th * th;
+        s2[i][j][e] = -2.f * th * s1[i][j][e];
+        lb[i][j][e] = 0.f;
+        sum1[i][j][e] = 0.f;
+      }
+    }
+  auto s_of = [=](int st) {
+    if (hl && st == 0) return a.S - 1;
+    const int k = st - hl;
+    return k < nder ? dbeg + k : 0;
+  };
+  auto epi = [&](int st, int s, typename MF::acc (&acc)[G::TI][G::TJ]) __attribute__((always_inline)) {
+    auto grow = [&](int i) { return (float*)a.g + ((long)s * a.N + pp[i]) * a.ldgo; };
+    if (hl && st == 0) {   // Laplacian row: its cotangent, kept for the derivative rows
+      const bool last = chunk == nch - 1;
+#pragma unroll
+      for (int i = 0; i < G::TI; i++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++) {
+          lb[i][j] = acc[i][j];
+          if (last && pok[i] && cok[j]) {
+            *gmem((f32x4*)(grow(i) + cc[j])) = s1[i][j] * acc[i][j];
+            *gmem((f32x4*)((float*)a.tab_lb + (long)pp[i] * a.h + cc[j])) = acc[i][j];
+          }
+        }
+    } else if (s >= 1 && s <= nd) {   // derivative row
+      const bool m = mask_at(a.mask, s - 1);
+#pragma unroll
+      for (int i = 0; i < G::TI; i++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++) {
+          if (!(pok[i] && cok[j])) continue;
+          const f32x4 da = *gmem((const f32x4*)(pre + ((long)s * a.N + pp[i]) * a.ldp + cc[j]));
+          sum1[i][j] += da * acc[i][j];
+          f32x4 o = s1[i][j] * acc[i][j];
+          if (m) o += 2.f * s2[i][j] * da * lb[i][j];
+          *gmem((f32x4*)(grow(i) + cc[j])) = o;
+        }
+    } else {   // value row (chunk 0)
+#pragma unroll
+      for (int i = 0; i < G::TI; i++)
+#pragma unroll
+        for (int j = 0; j < G::TJ; j++) {
+          if (!(pok[i] && cok[j])) continue;
+          if (hl)
+            *gmem((f32x4*)((float*)a.tab_zv + (long)pp[i] * a.h + cc[j])) = acc[i][j];
+          else
+            *gmem((f32x4*)(grow(i) + cc[j])) = s1[i][j] * acc[i][j];
+        }
+    }
+  };
+  sloop<MODE, true, decltype(s_of), decltype(epi), true>(
+      sm, (const typename O::TA*)a.gin, a.ldgi, a.N, p0, (const typename O::TB*)a.w,
+      (const typename O::TB*)a.w2, a.ldw, c0, a.h, a.K, nsteps, s_of, epi);
+  if (hl) {
+#pragma unroll
+    for (int i = 0; i < G::TI; i++)
+#pragma unroll
+      for (int j = 0; j < G::TJ; j++)
+        if (pok[i] && cok[j])
+          *gmem((f32x4*)((float*)a.tab_s1 + ((long)chunk * a.N + pp[i]) * a.h + cc[j])) =
+              sum1[i][j];
+  }
+}
+
 template <int MODE, typename TG>
 __global__ __launch_bounds__(kThreads) void k_bwdlap(BwdLayerArgs a) {
   typedef Op<MODE> O;
@@ -1364,15 +1488,23 @@ hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_
 
 hipError_t bwdlap_main(int mode, const BwdLayerArgs& a, int nch, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
+  // FP32 rows, all row lengths 4-aligned: the vector epilogue (table planes are 4-aligned)
+  const bool vec = (a.h & 3) == 0 && (a.ldp & 3) == 0 && (a.ldgo & 3) == 0;
   switch (mode) {
     case M_F64:
       k_bwdlap<M_F64, double><<<tile_grid<M_F64, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
       break;
     case M_F32:
-      k_bwdlap<M_F32, float><<<tile_grid<M_F32, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
+      if (vec)
+        k_bwdlap_vec<M_F32><<<tile_grid<M_F32, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
+      else
+        k_bwdlap<M_F32, float><<<tile_grid<M_F32, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
       break;
     case M_BF16X3:
-      k_bwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
+      if (vec)
+        k_bwdlap_vec<M_BF16X3><<<tile_grid<M_BF16X3, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
+      else
+        k_bwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
       break;
     default:
       return hipErrorInvalidValue;
