@@ -528,7 +528,7 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
   // The direct-to-LDS loop computes the transposed tile (neurons x points), so a
   // lane holds four consecutive neurons of one point and, when every output row
   // is 4-aligned (A4), stores them as one vector.
-  constexpr bool TR = kDma<MODE>;
+  constexpr bool TR = kDma<MODE> || MODE != M_F64;   // FP64 MFMA rows are not consecutive
   constexpr bool VEC = TR && A4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wp = wave / G::NWN, wn = wave % G::NWN;
@@ -561,11 +561,19 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
   // step 0: value row, steps 1..nder: derivative rows of this chunk, then the Laplacian row
   auto s_of = [=](int st) { return st == 0 ? 0 : (st <= nder ? dbeg + st - 1 : S - 1); };
   // Vector path: per-lane row and per-group neuron predicates; the column kind is
-  // uniform, so each kind has its own loop over the tile.  s1 = 1 - t^2 of the
-  // value row is kept in half precision (relative rounding 2^-11, below the 2^-9
-  // of the BF16 rows it scales), which leaves the main loop the registers it
-  // needs.
-  f16x4 s1h[G::TI][G::TJ];
+  // uniform, so each kind has its own loop over the tile.  With BF16 rows, s1 =
+  // 1 - t^2 of the value row is kept in half precision (relative rounding 2^-11,
+  // below the 2^-9 of the BF16 rows it scales), which leaves the main loop the
+  // registers it needs; FP32 rows keep it in FP32.
+  constexpr bool kBf = std::is_same<TZ, bf16>::value;
+  typedef typename std::conditional<kBf, f16x4, f32x4>::type S1V;
+  auto store4z = [](TZ* dst, const f32x4& v) {
+    if constexpr (kBf)
+      *gmem((bf16x4*)dst) = __builtin_convertvector(v, bf16x4);
+    else
+      *gmem((f32x4*)dst) = v;
+  };
+  S1V s1h[G::TI][G::TJ];
   bool p_ok[G::TI], c_ok[G::TJ];
 #pragma unroll
   for (int i = 0; i < G::TI; i++) p_ok[i] = P(i, 0) < a.N;
@@ -598,9 +606,9 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
           for (int i = 0; i < G::TI; i++)
 #pragma unroll
             for (int j = 0; j < G::TJ; j++) {
-              const f32x4 o = __builtin_convertvector(s1h[i][j], f32x4) * acc[i][j];
+              const f32x4 o = __builtin_convertvector(s1h[i][j], f32x4) * (f32x4)acc[i][j];
               if (p_ok[i] && c_ok[j])
-                *gmem((bf16x4*)(zrow(i) + j * 16)) = __builtin_convertvector(o, bf16x4);
+                store4z(zrow(i) + j * 16, o);
             }
         }
         if (a.pre) {
@@ -622,9 +630,9 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
               t[e] = act_tanh(acc[i][j][e]);
               s1[e] = __builtin_fmaf(-t[e], t[e], 1.0f);
             }
-            s1h[i][j] = __builtin_convertvector(s1, f16x4);
+            s1h[i][j] = __builtin_convertvector(s1, S1V);
             if (first && p_ok[i] && c_ok[j]) {
-              if (keep) *gmem((bf16x4*)(zrow(i) + j * 16)) = __builtin_convertvector(t, bf16x4);
+              if (keep) store4z(zrow(i) + j * 16, t);
               if (a.pre) *gmem((f32x4*)(prow(i) + j * 16)) = acc[i][j];
               if (a.tab_t) *gmem((f32x4*)(tabrow(a.tab_t, i) + j * 16)) = t;
             }
@@ -682,13 +690,14 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
         }
       }
   };
-  if constexpr (TR)
+  if constexpr (kDma<MODE>)
     sloop_dma<MODE, G>(smem, (const TL*)a.zin, a.ldz, a.N, p0, (const TL*)a.w, a.ldw, c0,
                        a.h_out, a.K, nsteps, s_of, epi);
   else
-    sloop<MODE, false>(*(typename Mainloop<MODE>::Smem*)smem, (const typename O::TA*)a.zin, a.ldz,
-                       a.N, p0, (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0,
-                       a.h_out, a.K, nsteps, s_of, epi);
+    sloop<MODE, false, decltype(s_of), decltype(epi), TR>(
+        *(typename Mainloop<MODE>::Smem*)smem, (const typename O::TA*)a.zin, a.ldz, a.N, p0,
+        (const typename O::TB*)a.w, (const typename O::TB*)a.w2, a.ldw, c0, a.h_out, a.K, nsteps,
+        s_of, epi);
   if (a.has_lap) {
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
@@ -1419,17 +1428,24 @@ hipError_t fwdlap_pair(int mode, const FwdLayerArgs& a, int nch, const FwdLayerA
     return hipErrorInvalidValue;   // the second set: plain rows of the same layer
   if (a.N <= 0) return b ? fwdlap_pair(mode, *b, 1, nullptr, st) : hipSuccess;
   if (!fwd_args_ok(a) || (b && !fwd_args_ok(*b))) return hipErrorInvalidValue;
+  // 4-aligned rows take the vector epilogue (table planes are 4-aligned)
+  const bool a4 = (a.h_out & 3) == 0 && (a.ldzo & 3) == 0 && (!a.pre || (a.ldp & 3) == 0);
   switch (mode) {
     case M_F64: launch_fwd<M_F64, double, false>(a, nch, b, st); break;
-    case M_F32: launch_fwd<M_F32, float, false>(a, nch, b, st); break;
+    case M_F32:
+      if (a4) launch_fwd<M_F32, float, true>(a, nch, b, st);
+      else launch_fwd<M_F32, float, false>(a, nch, b, st);
+      break;
     case M_BF16:
-      // 4-aligned rows take the vector epilogue (table planes are 4-aligned)
-      if ((a.h_out & 3) == 0 && (a.ldzo & 3) == 0 && (!a.pre || (a.ldp & 3) == 0))
+      if (a4)
         launch_fwd<M_BF16, bf16, true>(a, nch, b, st);
       else
         launch_fwd<M_BF16, bf16, false>(a, nch, b, st);
       break;
-    case M_BF16X3: launch_fwd<M_BF16X3, float, false>(a, nch, b, st); break;
+    case M_BF16X3:
+      if (a4) launch_fwd<M_BF16X3, float, true>(a, nch, b, st);
+      else launch_fwd<M_BF16X3, float, false>(a, nch, b, st);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
