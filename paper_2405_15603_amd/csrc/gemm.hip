@@ -49,6 +49,19 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
 // ---------------------------------------------------------------------------
 // part[s] = sum_{k in split s} w(k) A[k]^T B[k]   (A: K x M, B: K x N, rows)
 // ---------------------------------------------------------------------------
+// Block -> (tile t, split): every split's tiles run on one XCD, so the slab rows
+// of a split are fetched into that XCD's L2 once and read there by all of its
+// tiles, which advance through the rows together.  Workgroups go to the XCDs
+// round-robin by linear id: block b runs on XCD b % 8 as that XCD's (b / 8)-th
+// block, and XCD x takes splits x, x + 8, ... in turn, all tiles of each.
+// False for blocks past the last split (no rows).
+__device__ __forceinline__ bool tn_block(int ntiles, int kchunk, int K, int& t, int& split) {
+  const int b = blockIdx.x, x = b & 7, i = b >> 3;
+  split = x + 8 * (i / ntiles);
+  t = i % ntiles;
+  return (long)split * kchunk < K;
+}
+
 template <int MODE> struct TnOp;
 template <> struct TnOp<M_F64> { typedef double TA; typedef double TL; static constexpr int NP = 1; };
 template <> struct TnOp<M_F32> { typedef float TA; typedef float TL; static constexpr int NP = 1; };
@@ -78,9 +91,10 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const typename TnOp<MODE>::TA* 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  int ti, tj;
+  int ti, tj, split;
   {
-    int t = blockIdx.x;
+    int t;
+    if (!tn_block(sym ? ntm * (ntm + 1) / 2 : ntm * ntn, kchunk, K, t, split)) return;
     if (sym) {
       ti = 0;
       int rowlen = ntm;
@@ -92,7 +106,6 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const typename TnOp<MODE>::TA* 
     }
   }
   const int m0 = ti * BM, n0 = tj * BN;
-  const int split = blockIdx.y;
   const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
   const int Mv = (int)kp_roundup(M, VN), Nv = (int)kp_roundup(N, VN);
   TC* out = part + (long)split * M * N;
@@ -236,9 +249,10 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
   __shared__ __align__(16) bf16 sm[2][2][2][BM * BK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  int ti, tj;
+  int ti, tj, split;
   {
-    int t = blockIdx.x;
+    int t;
+    if (!tn_block(sym ? ntm * (ntm + 1) / 2 : ntm * ntn, kchunk, K, t, split)) return;
     if (sym) {
       ti = 0;
       int rowlen = ntm;
@@ -250,7 +264,6 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
     }
   }
   const int m0 = ti * BM, n0 = tj * BM;
-  const int split = blockIdx.y;
   const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
   float* out = part + (long)split * M * N;
 
@@ -392,11 +405,13 @@ hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long
   if (splits > max_by_k) splits = max_by_k;
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
+  if (splits > 8) splits = std::min(max_splits, (int)kp_roundup(splits, 8));
   int kchunk = (int)kp_roundup(kp_cdiv(K, splits), BK);
   splits = kp_cdiv(K, kchunk);
   if (splits < 1) splits = 1;
   *splits_out = splits;
-  dim3 g(ntiles, splits);
+  // a linear grid in XCD-major order (see tn_block): 8 blocks per (tile, split group)
+  dim3 g(8 * ntiles * kp_cdiv(splits, 8));
   switch (mode) {
     case M_F64: launch_tn<M_F64>(g, A, lda, B, ldb, M, N, K, rw, rmod, sym, ntm, ntn, kchunk, part, st); break;
     case M_F32: launch_tn<M_F32>(g, A, lda, B, ldb, M, N, K, rw, rmod, sym, ntm, ntn, kchunk, part, st); break;
