@@ -36,16 +36,6 @@ __device__ __forceinline__ double load_frag<double>(const double* base, int lane
   return base[(lane & 15) * ldk + k0 + (lane >> 4)];
 }
 
-// XCD-aware tile order: the hardware deals consecutive workgroups round-robin
-// to the 8 XCDs; remap so that each XCD receives a contiguous run of logical
-// tiles (tiles that share slab rows then share one L2).
-__device__ __forceinline__ int xcd_remap(int b, int total) {
-  const int per = total / 8, rem = total % 8;
-  const int x = b % 8, i = b / 8;
-  // XCD x owns logical tiles [x*per + min(x, rem), ...) of length per + (x < rem)
-  return x * per + (x < rem ? x : rem) + i;
-}
-
 // ---------------------------------------------------------------------------
 // part[s] = sum_{k in split s} w(k) A[k]^T B[k]   (A: K x M, B: K x N, rows)
 // ---------------------------------------------------------------------------
