@@ -216,15 +216,21 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const typename TnOp<MODE>::TA* 
 // consecutive slab rows x 4 consecutive columns (eight 16-byte loads, 512 bytes
 // contiguous per row across a half-wave), so for each of its 4 columns it holds
 // 8 consecutive k; it splits them into BF16 hi and lo and writes each as one
-// 16-byte LDS store into a k-contiguous [column][k] tile.  The 4 chunks of 8 k
-// in a 64-byte tile row are XOR-swizzled by (column >> 2) & 3, which makes the
-// 16-row fragment reads conflict-free.  Waves 0-1 load A, waves 2-3 load B.
-// Tile 128 x 128 x 32, four waves of 64 x 64, two LDS stages.
+// 16-byte LDS store into a k-contiguous [column][k] tile of 64-byte rows.
+// A 16-byte access serves 16 lanes per LDS cycle over 256 bytes of banks, so
+// both access patterns need 16 distinct (row mod 4, chunk) slots per group of
+// 16 lanes: the fragment reads touch 16 consecutive columns at one chunk, the
+// stores 16 columns 4 apart (one per column group) at one chunk.  Column c is
+// kept in row c ^ ((c >> 2) & 3) and its chunk j at j ^ ((c >> 2) & 3) ^
+// ((c >> 4) & 3), a bijection per row that separates both groups.
+// Waves 0-1 load A, waves 2-3 load B.  Tile 128 x 128 x 32, four waves of
+// 64 x 64, two LDS stages.
 // ---------------------------------------------------------------------------
 constexpr int X3_BM = 128, X3_BK = 32;
 
 __device__ __forceinline__ int x3_pos(int col, int chunk) {
-  return col * X3_BK + ((chunk ^ ((col >> 2) & 3)) << 3);
+  const int q = (col >> 2) & 3;
+  return (col ^ q) * X3_BK + ((chunk ^ q ^ ((col >> 4) & 3)) << 3);
 }
 
 template <bool WEIGHTED>
