@@ -120,6 +120,8 @@ struct kfac_pinn_ctx {
   void* delta = nullptr;
   std::vector<EigProblem> probs;        // layer l: 2l side A, 2l + 1 side B
   EigProblem* probs_dev = nullptr;
+  EigGroups eg;                         // Jacobi groups; side streams made on first use
+  bool eg_streams = false;
   G64* kdesc = nullptr;
   int k_mmax = 0, k_nmax = 0;
   int* ctl = nullptr;                  // [0] status [1] step [4..5] alpha [8..] Jacobi flags
@@ -623,6 +625,16 @@ int64_t kfac_pinn_num_params(const int32_t* widths, int32_t n_layers) {
 
 kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx) {
   if (!ctx) return KP_ERR_ARG;
+  if (ctx->eg_streams) {
+    for (int k = 1; k < ctx->eg.n; k++) {
+      if (ctx->eg.st[k]) {
+        (void)hipStreamSynchronize(ctx->eg.st[k]);
+        (void)hipStreamDestroy(ctx->eg.st[k]);
+      }
+      if (ctx->eg.join[k]) (void)hipEventDestroy(ctx->eg.join[k]);
+    }
+    if (ctx->eg.fork) (void)hipEventDestroy(ctx->eg.fork);
+  }
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->tm_ev) (void)hipEventDestroy(e);
   delete ctx;
@@ -821,6 +833,18 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     return KP_ERR_HIP;
   }
   {
+    std::vector<int> ids(c->probs.size());
+    eig_groups_plan(c->probs.data(), (int)c->probs.size(), kEigGroups, ids.data(), c->eg);
+    int* ids_dev = nullptr;
+    ALLOC(ids_dev, sizeof(int) * ids.size());
+    if ((e = hipMemcpy(ids_dev, ids.data(), sizeof(int) * ids.size(), hipMemcpyHostToDevice)) !=
+        hipSuccess) {
+      kfac_pinn_destroy(c);
+      return KP_ERR_HIP;
+    }
+    c->eg.ids = ids_dev;
+  }
+  {
     std::vector<KronApply> ka(c->L);
     long tstride = 0;
     for (int l = 0; l < c->L; l++) {
@@ -997,8 +1021,17 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* c, const void* theta, const void* xi,
 }
 
 static hipError_t eig_all(kfac_pinn_ctx* c, double lambda) {
+  if (!c->eg_streams && c->eg.n > 1) {
+    // side streams of default priority for the concurrent Jacobi groups
+    c->eg_streams = true;
+    for (int k = 1; k < c->eg.n; k++) {
+      if (hipError_t e = hipStreamCreateWithFlags(&c->eg.st[k], hipStreamNonBlocking)) return e;
+      if (hipError_t e = hipEventCreateWithFlags(&c->eg.join[k], hipEventDisableTiming)) return e;
+    }
+    if (hipError_t e = hipEventCreateWithFlags(&c->eg.fork, hipEventDisableTiming)) return e;
+  }
   return kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
-                          c->ctl + 8, c->ctl + 2, kEigRefresh, kJacobiSweeps, c->st);
+                          c->ctl + 8, c->ctl + 2, kEigRefresh, kJacobiSweeps, c->eg, c->st);
 }
 
 kp_status kfac_pinn_invert(kfac_pinn_ctx* c, double lambda) {
@@ -1222,6 +1255,8 @@ struct kfac_pinn_batch {
   // one inversion over the factors of every instance
   std::vector<EigProblem> probs;
   EigProblem* probs_dev = nullptr;
+  EigGroups eg;             // one group: the inversion's launches already span every instance
+  int* eig_ids = nullptr;
   int* eig_ctl = nullptr;   // [0..1] call counter and warm-start flag, [2..] 2 per problem
 };
 
@@ -1263,7 +1298,7 @@ kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
   if (phase == 1) {
     KP_TRY(kron_eig_batched(b->probs.data(), (int)b->probs.size(), a.hp->lambda, b->probs_dev,
                             b->ctx[0]->ctl, b->eig_ctl + 2, b->eig_ctl, kEigRefresh,
-                            kJacobiSweeps, b->lanes[0]));
+                            kJacobiSweeps, b->eg, b->lanes[0]));
     return KP_OK;
   }
   for (size_t k = l; k < b->ctx.size(); k += nl) {
@@ -1342,10 +1377,15 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
   }
   const size_t np = b->probs.size();
   if (hipMalloc((void**)&b->probs_dev, sizeof(EigProblem) * np) != hipSuccess ||
+      hipMalloc((void**)&b->eig_ids, sizeof(int) * np) != hipSuccess ||
       hipMalloc((void**)&b->eig_ctl, sizeof(int) * (2 + 2 * np)) != hipSuccess)
     return fail(KP_ERR_OOM);
+  std::vector<int> ids(np);
+  eig_groups_plan(b->probs.data(), (int)np, 1, ids.data(), b->eg);
+  b->eg.ids = b->eig_ids;
   if (hipMemcpy(b->probs_dev, b->probs.data(), sizeof(EigProblem) * np, hipMemcpyHostToDevice) !=
           hipSuccess ||
+      hipMemcpy(b->eig_ids, ids.data(), sizeof(int) * np, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(b->eig_ctl, 0, sizeof(int) * (2 + 2 * np)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
     return fail(KP_ERR_HIP);
@@ -1359,6 +1399,7 @@ kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   batch_drop_graph(b);
   for (kfac_pinn_ctx* c : b->ctx) kfac_pinn_destroy(c);
   if (b->probs_dev) (void)hipFree(b->probs_dev);
+  if (b->eig_ids) (void)hipFree(b->eig_ids);
   if (b->eig_ctl) (void)hipFree(b->eig_ctl);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->ev_head) (void)hipEventDestroy(e);

@@ -124,9 +124,28 @@ struct EigProblem {
 // instances' factors in one call).  Jacobi starts from the
 // V left in P[0] by the previous call, except on every refresh-th call (and the
 // first after the counter is reset).
+// The Jacobi sweeps run in up to kEigGroups groups of problems, group k on
+// stream st[k] (k = 0: the call's stream, st[0] unused); the other streams fork
+// from the call's stream at `fork` and it waits for each at join[k].  Group k
+// holds the problems ids[off[k] .. off[k+1]) (ids: device, grouped problem
+// indices) and sweeps rounds sized for its largest problem, npmax[k].
+constexpr int kEigGroups = 4;
+struct EigGroups {
+  int n = 1;
+  int off[kEigGroups + 1] = {};
+  int npmax[kEigGroups] = {};
+  const int* ids = nullptr;
+  hipStream_t st[kEigGroups] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kEigGroups] = {};
+};
+// Splits nprob problems into min(ngroups, nprob, kEigGroups) groups of balanced
+// work (largest first to the lightest group); fills g.n, g.off, g.npmax and the
+// host array ids (nprob ints, to be copied to the device for g.ids).
+void eig_groups_plan(const EigProblem* probs, int nprob, int ngroups, int* ids, EigGroups& g);
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
                             EigProblem* probs_dev, int* status, int* done, int* calls,
-                            int refresh, int max_sweeps, hipStream_t st);
+                            int refresh, int max_sweeps, const EigGroups& g, hipStream_t st);
 // Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T for every layer, V = gradient
 // (column-major h_out x (h_in+1) inside the theta layout).  Four strided FP64
 // products per layer, described once (descriptors in device memory).

@@ -6,10 +6,12 @@
 //   2. blocked triangular inverse L^-1,
 //   3. M = L^-1 F2 L^-T (two products),
 //   4. two-sided block Jacobi on C = V0^T M V0 (32-wide blocks, round-robin
-//      pairing of block pairs; each pair's 64 x 64 subproblem gets one cyclic
-//      Jacobi sweep in LDS, then the rotations are applied to C and
-//      accumulated into V), until a sweep performs no rotation above the
-//      threshold.  V0 is the identity on a cold start; on a warm start it is
+//      pairing of block pairs; each pair's 64 x 64 subproblem gets one sweep
+//      of parallel Jacobi rotations in LDS (all index pairs in the first round
+//      of an outer sweep, the pairs across the two blocks in the others), then
+//      the rotations are applied to C and accumulated into V), until a sweep
+//      performs no rotation above the threshold.  The problems are split into
+//      groups whose rounds run on separate streams.  V0 is the identity on a cold start; on a warm start it is
 //      the previous call's V, the eigenvectors of the previous whitened
 //      matrix: the factors move slowly under the moving average, so C starts
 //      nearly diagonal and few sweeps remain,
@@ -19,6 +21,10 @@
 // block in F1 and a zero block in F2, which stays exactly decoupled (V keeps
 // the block structure).  All problems of a call run in the same launches
 // (grid.y = problem).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "common.h"
 #include "launch.h"
 
@@ -397,9 +403,10 @@ __device__ __forceinline__ void rotation(double app, double aqq, double apq, dou
 constexpr int kSolveThreads = 512;
 
 __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* __restrict__ pr,
+                                                   const int* __restrict__ ids,
                                                    const int* __restrict__ done, int r,
                                                    int inner) {
-  const int q = blockIdx.y;
+  const int q = ids[blockIdx.y];
   const EigProblem p = pr[q];
   const int nblk = p.n_pad / JB;
   if (done[2 * q] || r >= nblk - 1) return;
@@ -437,12 +444,25 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
     if (threadIdx.x == 0) p.pflag[i] = 1;
     return;
   }
+  // The first round of an outer sweep pairs every block once: its subproblems
+  // take every index pair of the two blocks (2 JB - 1 rounds), so each pair
+  // inside a block is met once per outer sweep.  The other rounds take only the
+  // JB x JB pairs across the two blocks (JB rounds of JB disjoint pairs).
+  const bool full = r == 0;
+  const int nrr = full ? JS - 1 : JB;
   for (int sw = 0; sw < inner; sw++) {
-    for (int rr = 0; rr < JS - 1; rr++) {
+    for (int rr = 0; rr < nrr; rr++) {
       if (threadIdx.x < JB) {
         const int k = threadIdx.x;
-        int a = rr_pos(k, rr, JS), b = rr_pos(JS - 1 - k, rr, JS);
-        if (a > b) { int t = a; a = b; b = t; }
+        int a, b;
+        if (full) {
+          a = rr_pos(k, rr, JS);
+          b = rr_pos(JS - 1 - k, rr, JS);
+          if (a > b) { int t = a; a = b; b = t; }
+        } else {
+          a = k;
+          b = JB + ((k + rr) & (JB - 1));
+        }
         const double apq = S[a * LDJ + b], app = S[a * LDJ + a], aqq = S[b * LDJ + b];
         double c = 1.0, s = 0.0;
         if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) rotation(app, aqq, apq, c, s);
@@ -583,8 +603,9 @@ __device__ __forceinline__ void mm64_each(const f64x4 (&acc)[2][2], F f) {
 // (mirrored), then P[R rows, pair Y cols] <- P V_Y.  Identity pairs are skipped.
 // Two LDS tiles, so two workgroups share a CU.
 __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict__ pr,
+                                                   const int* __restrict__ ids,
                                                    const int* __restrict__ done, int r) {
-  const int q = blockIdx.y;
+  const int q = ids[blockIdx.y];
   const EigProblem p = pr[q];
   const int nblk = p.n_pad / JB;
   if (done[2 * q] || r >= nblk - 1) return;
@@ -654,9 +675,11 @@ __global__ __launch_bounds__(256) void k_jac_apply(const EigProblem* __restrict_
 }
 
 // After a sweep: converged when no rotation exceeded the threshold.
-__global__ void k_jac_check(const EigProblem* __restrict__ pr, int* done, int nprob) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nprob) return;
+__global__ void k_jac_check(const EigProblem* __restrict__ pr, const int* __restrict__ ids,
+                            int* done, int nprob) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nprob) return;
+  const int q = ids[i];
   const EigProblem p = pr[q];
   if (done[2 * q]) return;
   int* rot = &p.pflag[p.n_pad / 64];
@@ -676,10 +699,42 @@ __global__ void k_jac_extract(const EigProblem* __restrict__ pr) {
   }
 }
 
+void eig_groups_plan(const EigProblem* probs, int nprob, int ngroups, int* ids, EigGroups& g) {
+  ngroups = std::max(1, std::min(ngroups, std::min(nprob, kEigGroups)));
+  // largest first, each to the group with the least work so far (work ~ n_pad^3)
+  std::vector<int> order(nprob);
+  for (int q = 0; q < nprob; q++) order[q] = q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return probs[a].n_pad > probs[b].n_pad; });
+  std::vector<std::vector<int>> mem(ngroups);
+  std::vector<double> load(ngroups, 0.0);
+  for (int q : order) {
+    int k = 0;
+    for (int j = 1; j < ngroups; j++)
+      if (load[j] < load[k]) k = j;
+    mem[k].push_back(q);
+    load[k] += std::pow((double)probs[q].n_pad, 3.0);
+  }
+  g.n = ngroups;
+  int o = 0;
+  for (int k = 0; k < ngroups; k++) {
+    g.off[k] = o;
+    g.npmax[k] = 0;
+    std::sort(mem[k].begin(), mem[k].end());
+    for (int q : mem[k]) {
+      ids[o++] = q;
+      g.npmax[k] = std::max(g.npmax[k], probs[q].n_pad);
+    }
+  }
+  g.off[ngroups] = o;
+}
+
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
                             EigProblem* probs_dev, int* status, int* done, int* calls,
-                            int refresh, int max_sweeps, hipStream_t st) {
+                            int refresh, int max_sweeps, const EigGroups& g, hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
+  if (g.n < 1 || g.n > kEigGroups || g.off[0] != 0 || g.off[g.n] != nprob || !g.ids)
+    return hipErrorInvalidValue;
   int npmax = 0;
   for (int q = 0; q < nprob; q++) npmax = probs_host[q].n_pad > npmax ? probs_host[q].n_pad : npmax;
   const int nbmax = npmax / BB;
@@ -701,15 +756,38 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
   k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 3, calls + 1);
   k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done, calls + 1);
   k_jac_dmax<<<nprob, 256, 0, st>>>(probs_dev);
-  const int nblk = npmax / JB;
-  const int npair = nblk / 2;
-  const int nwg = npair * (npair + 1) / 2 + npair * npair;
-  for (int sw = 0; sw < max_sweeps; sw++) {
-    for (int r = 0; r < nblk - 1; r++) {
-      k_jac_solve<<<dim3(npair, nprob), kSolveThreads, 0, st>>>(probs_dev, done, r, KP_JAC_INNER);
-      k_jac_apply<<<dim3(nwg, nprob), 256, 0, st>>>(probs_dev, done, r);
+  // Sweeps of the groups, interleaved round by round on their streams: the
+  // rounds of one group form a dependent chain of short launches, so chains of
+  // other groups fill the machine meanwhile.
+  const int ng = g.n;
+  if (ng > 1) {
+    if (hipError_t e = hipEventRecord(g.fork, st)) return e;
+    for (int k = 1; k < ng; k++)
+      if (hipError_t e = hipStreamWaitEvent(g.st[k], g.fork, 0)) return e;
+  }
+  int rounds[kEigGroups], ticks = 0;
+  for (int k = 0; k < ng; k++) {
+    rounds[k] = g.npmax[k] / JB - 1;
+    ticks = std::max(ticks, max_sweeps * rounds[k]);
+  }
+  for (int t = 0; t < ticks; t++)
+    for (int k = 0; k < ng; k++) {
+      if (rounds[k] < 1 || t >= max_sweeps * rounds[k]) continue;
+      const hipStream_t sk = k == 0 ? st : g.st[k];
+      const int* ids = g.ids + g.off[k];
+      const int nq = g.off[k + 1] - g.off[k];
+      const int npair = g.npmax[k] / JB / 2;
+      const int nwg = npair * (npair + 1) / 2 + npair * npair;
+      const int r = t % rounds[k];
+      k_jac_solve<<<dim3(npair, nq), kSolveThreads, 0, sk>>>(probs_dev, ids, done, r, KP_JAC_INNER);
+      k_jac_apply<<<dim3(nwg, nq), 256, 0, sk>>>(probs_dev, ids, done, r);
+      if (r == rounds[k] - 1) k_jac_check<<<(nq + 63) / 64, 64, 0, sk>>>(probs_dev, ids, done, nq);
     }
-    k_jac_check<<<(nprob + 63) / 64, 64, 0, st>>>(probs_dev, done, nprob);
+  if (ng > 1) {
+    for (int k = 1; k < ng; k++) {
+      if (hipError_t e = hipEventRecord(g.join[k], g.st[k])) return e;
+      if (hipError_t e = hipStreamWaitEvent(st, g.join[k], 0)) return e;
+    }
   }
   k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 4, calls + 1);
   k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev);
