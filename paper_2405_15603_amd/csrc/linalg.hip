@@ -65,6 +65,58 @@ __device__ __forceinline__ void zero4(double acc[4][4]) {
     for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
 }
 
+// 64 x 64 x 64 FP64 products on the MFMA unit (v_mfma_f64_16x16x4): four waves,
+// each owning a 32 x 32 quadrant as 2 x 2 tiles of 16 x 16.  Tiles sit in LDS
+// with row stride LDM = 70 doubles, which keeps the fragment reads at two
+// (16 rows x 4 k) or three (4 k x 16 columns) accesses per bank.
+constexpr int LDM = 70;
+
+// acc[ti][tj] += op(A) op(B) over k in [0, 64); op(A)[i][k] = TA ? A[k][i] : A[i][k],
+// op(B)[k][j] = TB ? B[j][k] : B[k][j].  Element (r) of acc[ti][tj] is output
+// (32 wi + 16 ti + (lane >> 4) + 4 r, 32 wj + 16 tj + (lane & 15)).
+template <bool TA, bool TB>
+__device__ __forceinline__ void mm64(f64x4 (&acc)[2][2], const double* A, const double* B) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1, r16 = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < 64; k0 += 4) {
+    const int k = k0 + kq;
+    double a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+      const int i = 32 * wi + 16 * t + r16, j = 32 * wj + 16 * t + r16;
+      a[t] = TA ? A[k * LDM + i] : A[i * LDM + k];
+      b[t] = TB ? B[j * LDM + k] : B[k * LDM + j];
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+      for (int tj = 0; tj < 2; tj++) acc[ti][tj] = Mfma<double>::mma(a[ti], b[tj], acc[ti][tj]);
+  }
+}
+
+__device__ __forceinline__ void mm64_zero(f64x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++) acc[ti][tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Visit the outputs of this thread: f(i, j, value) in tile coordinates.
+template <class F>
+__device__ __forceinline__ void mm64_each(const f64x4 (&acc)[2][2], F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+        f(32 * wi + 16 * ti + Mfma<double>::row(lane, r), 32 * wj + 16 * tj + (lane & 15),
+          acc[ti][tj][r]);
+}
+
 // ---------------------------------------------------------------------------
 // 0. damping and padding
 // ---------------------------------------------------------------------------
@@ -91,54 +143,92 @@ __global__ void k_damp_pad(const EigProblem* __restrict__ pr, double lambda) {
 
 // ---------------------------------------------------------------------------
 // 1. Cholesky: diagonal block (factor + inverse of the factor)
+//
+// Right-looking elimination with the inverse carried along: thread (ty, tx)
+// keeps the 16 elements (ty + 16 a, tx + 16 b) of the tile in registers.  At
+// step k the pivot column k of the Schur complement W and row k of R (the
+// rows of the identity reduced by the finished columns, L X = I solved
+// forward) are published in LDS; then
+//   L[i][k] = W[i][k] / d_k (d_k = sqrt W[k][k]),  X[k][c] = R[k][c] / d_k,
+//   W[i][c] -= W[i][k] W[c][k] / W[k][k]           (k < c <= i),
+//   R[i][c] -= W[i][k] R[k][c] / W[k][k]           (c <= k < i),
+// and an element leaves W for R when its column is finished.  The column and
+// row of step k + 1 are published into the other LDS buffer, so a step takes
+// one barrier; the results stay in registers until the end (a global store
+// before a barrier would make every step wait for it).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_diag(const EigProblem* __restrict__ pr, int j,
                                                    int* status) {
   const EigProblem p = pr[blockIdx.y];
   const int nb = p.n_pad / BB;
   if (j >= nb) return;
-  __shared__ double L[BB * LDB];
-  __shared__ double X[BB * LDB];
-  __shared__ int bad;
+  __shared__ double colk[2][BB];
+  __shared__ double rowk[2][BB];
   const long np = p.n_pad;
   const double* src = p.M1 + (long)j * BB * np + (long)j * BB;
-  tile_load(L, src, np);
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int k = 0; k < BB; k++) {
-    if (threadIdx.x == 0) {
-      double piv = L[k * LDB + k];
-      if (!(piv > 0.0)) { bad = 1; piv = 1.0; }
-      L[k * LDB + k] = sqrt(piv);
-    }
-    __syncthreads();
-    const double dk = L[k * LDB + k];
-    for (int i = k + 1 + threadIdx.x; i < BB; i += blockDim.x) L[i * LDB + k] /= dk;
-    __syncthreads();
-    const int rem = BB - k - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-      const int i = k + 1 + e / rem, c = k + 1 + e % rem;
-      if (c <= i) L[i * LDB + c] -= L[i * LDB + k] * L[c * LDB + k];
-    }
-    __syncthreads();
-  }
-  // inverse of the lower-triangular factor, one column per thread
-  if (threadIdx.x < BB) {
-    const int c = threadIdx.x;
-    for (int i = 0; i < BB; i++) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; k++) s -= L[i * LDB + k] * X[k * LDB + c];
-      X[i * LDB + c] = (i < c) ? 0.0 : s / L[i * LDB + i];
-    }
-  }
-  __syncthreads();
   double* lb = p.Lb + (long)j * BB * np + (long)j * BB;
   double* li = p.Li + (long)j * BB * np + (long)j * BB;
-  for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
-    const int i = e / BB, c = e % BB;
-    lb[(long)i * np + c] = c <= i ? L[i * LDB + c] : 0.0;
-    li[(long)i * np + c] = c <= i ? X[i * LDB + c] : 0.0;
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double v[4][4], ol[4][4], ox[4][4];   // working element, outputs L and L^-1
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int i = ty + 16 * a, c = tx + 16 * b;
+      v[a][b] = c <= i ? src[(long)i * np + c] : 0.0;
+      ol[a][b] = ox[a][b] = 0.0;
+    }
+  // publish column 0 of W and row 0 of R (e_0)
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int i = ty + 16 * a, c = tx + 16 * b;
+      if (c == 0) colk[0][i] = v[a][b];
+      if (i == 0) rowk[0][c] = c == 0 ? 1.0 : 0.0;
+    }
+  bool bad = false;
+  for (int k = 0; k < BB; k++) {
+    const int par = k & 1;
+    __syncthreads();
+    double piv = colk[par][k];
+    if (!(piv > 0.0)) { bad = true; piv = 1.0; }
+    const double dk = sqrt(piv), idk = 1.0 / dk, ip = idk * idk;
+    double wi[4], wc[4], rk[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) wi[a] = colk[par][ty + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      wc[b] = colk[par][tx + 16 * b];
+      rk[b] = rowk[par][tx + 16 * b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int i = ty + 16 * a, c = tx + 16 * b;
+        if (c == k && i >= k) {
+          ol[a][b] = i == k ? dk : wi[a] * idk;
+          v[a][b] = i == k ? 1.0 : -wi[a] * ip;   // R[i][k] after step k
+        } else if (i > k && c > k && c <= i) {
+          v[a][b] -= wi[a] * wc[b] * ip;
+        } else if (i > k && c < k) {
+          v[a][b] -= wi[a] * rk[b] * ip;
+        }
+        if (i == k && c <= k) ox[a][b] = c == k ? idk : v[a][b] * idk;
+        // publish the pivot column and R row of step k + 1
+        if (c == k + 1) colk[par ^ 1][i] = v[a][b];
+        if (i == k + 1) rowk[par ^ 1][c] = c == k + 1 ? 1.0 : v[a][b];
+      }
   }
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const long e = (long)(ty + 16 * a) * np + tx + 16 * b;
+      lb[e] = ol[a][b];
+      li[e] = ox[a][b];
+    }
   if (threadIdx.x == 0 && bad) atomicMax(p.status ? p.status : status, 4);
 }
 
@@ -204,34 +294,32 @@ __global__ __launch_bounds__(256) void k_trtri_row(const EigProblem* __restrict_
   const int nb = p.n_pad / BB;
   const int j = blockIdx.x;
   if (i >= nb || j >= i) return;
-  __shared__ double A[BB * LDB];
-  __shared__ double B[BB * LDB];
+  __shared__ __align__(16) double A[BB * LDM];
+  __shared__ __align__(16) double B[BB * LDM];
   const long np = p.n_pad;
-  double acc[4][4];
-  zero4(acc);
+  auto load = [&](double* dst, const double* src) {
+    for (int e = threadIdx.x; e < BB * BB / 2; e += blockDim.x) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      *(double2*)&dst[r * LDM + c] = *(const double2*)(src + (long)r * np + c);
+    }
+  };
+  f64x4 acc[2][2];
+  mm64_zero(acc);
   for (int k = j; k < i; k++) {
     __syncthreads();
-    tile_load(A, p.Lb + (long)i * BB * np + (long)k * BB, np);
-    tile_load(B, p.Li + (long)k * BB * np + (long)j * BB, np);
+    load(A, p.Lb + (long)i * BB * np + (long)k * BB);
+    load(B, p.Li + (long)k * BB * np + (long)j * BB);
     __syncthreads();
-    blk_mm<false, false>(acc, A, B);
+    mm64<false, false>(acc, A, B);
   }
   __syncthreads();
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) B[(ty * 4 + a) * LDB + tx * 4 + b] = acc[a][b];
-  tile_load(A, p.Li + (long)i * BB * np + (long)i * BB, np);
+  mm64_each(acc, [&](int a, int b, double v) { B[a * LDM + b] = v; });
+  load(A, p.Li + (long)i * BB * np + (long)i * BB);
   __syncthreads();
-  double r[4][4];
-  zero4(r);
-  blk_mm<false, false>(r, A, B);
+  mm64_zero(acc);
+  mm64<false, false>(acc, A, B);
   double* dst = p.Li + (long)i * BB * np + (long)j * BB;
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) dst[(long)(ty * 4 + a) * np + tx * 4 + b] = -r[a][b];
+  mm64_each(acc, [&](int a, int b, double v) { dst[(long)a * np + b] = -v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -250,48 +338,61 @@ __global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ p
   const int bi = blockIdx.y, bj = blockIdx.x;
   if (bi >= nb || bj >= nb) return;
   const long np = p.n_pad;
-  __shared__ double As[BB * LDB];
-  __shared__ double Bs[BB * LDB];
-  double acc[4][4];
-  zero4(acc);
+  __shared__ __align__(16) double As[BB * LDM];
+  __shared__ __align__(16) double Bs[BB * LDM];
+  // 64 x 64 operand tiles of block k
+  auto tile_a = [&](int k) -> const double* {
+    switch (mode) {
+      case 0: return p.Li + (long)bi * BB * np + (long)k * BB;
+      case 1: return p.C[1] + (long)bi * BB * np + (long)k * BB;
+      case 2: return p.C[0] + (long)bi * BB * np + (long)k * BB;
+      case 3: return p.P[0] + (long)k * BB * np + (long)bi * BB;
+      default: return p.Li + (long)k * BB * np + (long)bi * BB;
+    }
+  };
+  auto tile_b = [&](int k) -> const double* {
+    switch (mode) {
+      case 0: return p.M2 + (long)bj * BB * np + (long)k * BB;
+      case 1: return p.Li + (long)bj * BB * np + (long)k * BB;
+      case 2: return p.P[0] + (long)k * BB * np + (long)bj * BB;
+      case 3: return p.C[1] + (long)k * BB * np + (long)bj * BB;
+      default: return p.P[0] + (long)k * BB * np + (long)bj * BB;
+    }
+  };
+  // thread t moves elements 2t + 512 m (m < 8) of a tile: rows 8m + t / 32,
+  // columns 2 (t % 32) and the next
+  const int lr = threadIdx.x >> 5, lc = 2 * (threadIdx.x & 31);
+  double2 ra[8], rb[8];
+  auto fetch = [&](int k) {
+    const double* a = tile_a(k);
+    const double* b = tile_b(k);
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+      ra[m] = *(const double2*)(a + (long)(8 * m + lr) * np + lc);
+      rb[m] = *(const double2*)(b + (long)(8 * m + lr) * np + lc);
+    }
+  };
+  f64x4 acc[2][2];
+  mm64_zero(acc);
   const int kbeg = mode == 4 ? bi : 0;
   const int kend = mode == 0 ? bi : (mode == 1 ? bj : nb - 1);
+  fetch(kbeg);
   for (int k = kbeg; k <= kend; k++) {
     __syncthreads();
-    switch (mode) {
-      case 0:
-        tile_load(As, p.Li + (long)bi * BB * np + (long)k * BB, np);
-        tile_load(Bs, p.M2 + (long)bj * BB * np + (long)k * BB, np);
-        break;
-      case 1:
-        tile_load(As, p.C[1] + (long)bi * BB * np + (long)k * BB, np);
-        tile_load(Bs, p.Li + (long)bj * BB * np + (long)k * BB, np);
-        break;
-      case 2:
-        tile_load(As, p.C[0] + (long)bi * BB * np + (long)k * BB, np);
-        tile_load(Bs, p.P[0] + (long)k * BB * np + (long)bj * BB, np);
-        break;
-      case 3:
-        tile_load(As, p.P[0] + (long)k * BB * np + (long)bi * BB, np);
-        tile_load(Bs, p.C[1] + (long)k * BB * np + (long)bj * BB, np);
-        break;
-      default:
-        tile_load(As, p.Li + (long)k * BB * np + (long)bi * BB, np);
-        tile_load(Bs, p.P[0] + (long)k * BB * np + (long)bj * BB, np);
-        break;
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+      *(double2*)&As[(8 * m + lr) * LDM + lc] = ra[m];
+      *(double2*)&Bs[(8 * m + lr) * LDM + lc] = rb[m];
     }
     __syncthreads();
-    if (mode <= 1) blk_mm<false, true>(acc, As, Bs);
-    else if (mode == 2) blk_mm<false, false>(acc, As, Bs);
-    else blk_mm<true, false>(acc, As, Bs);
+    if (k < kend) fetch(k + 1);   // in flight during the products
+    if (mode <= 1) mm64<false, true>(acc, As, Bs);
+    else if (mode == 2) mm64<false, false>(acc, As, Bs);
+    else mm64<true, false>(acc, As, Bs);
   }
   double* out = (mode == 0 || mode == 2) ? p.C[1] : (mode == 4 ? p.P[1] : p.C[0]);
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++)
-      out[(long)(bi * BB + ty * 4 + a) * np + bj * BB + tx * 4 + b] = acc[a][b];
+  out += (long)bi * BB * np + (long)bj * BB;
+  mm64_each(acc, [&](int i, int j, double v) { out[(long)i * np + j] = v; });
 }
 
 // Call counter and warm-start flag, decided on the device so that a captured
@@ -547,58 +648,6 @@ __device__ __forceinline__ long grow(int a, int b0, int b1) {
   return a < JB ? (long)b0 * JB + a : (long)b1 * JB + a - JB;
 }
 
-// 64 x 64 x 64 FP64 products on the MFMA unit (v_mfma_f64_16x16x4): four waves,
-// each owning a 32 x 32 quadrant as 2 x 2 tiles of 16 x 16.  Tiles sit in LDS
-// with row stride LDM = 70 doubles, which keeps the fragment reads at two
-// (16 rows x 4 k) or three (4 k x 16 columns) accesses per bank.
-constexpr int LDM = 70;
-
-// acc[ti][tj] += op(A) op(B) over k in [0, 64); op(A)[i][k] = TA ? A[k][i] : A[i][k],
-// op(B)[k][j] = TB ? B[j][k] : B[k][j].  Element (r) of acc[ti][tj] is output
-// (32 wi + 16 ti + (lane >> 4) + 4 r, 32 wj + 16 tj + (lane & 15)).
-template <bool TA, bool TB>
-__device__ __forceinline__ void mm64(f64x4 (&acc)[2][2], const double* A, const double* B) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wi = wave >> 1, wj = wave & 1, r16 = lane & 15, kq = lane >> 4;
-#pragma unroll 4
-  for (int k0 = 0; k0 < 64; k0 += 4) {
-    const int k = k0 + kq;
-    double a[2], b[2];
-#pragma unroll
-    for (int t = 0; t < 2; t++) {
-      const int i = 32 * wi + 16 * t + r16, j = 32 * wj + 16 * t + r16;
-      a[t] = TA ? A[k * LDM + i] : A[i * LDM + k];
-      b[t] = TB ? B[j * LDM + k] : B[k * LDM + j];
-    }
-#pragma unroll
-    for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-      for (int tj = 0; tj < 2; tj++) acc[ti][tj] = Mfma<double>::mma(a[ti], b[tj], acc[ti][tj]);
-  }
-}
-
-__device__ __forceinline__ void mm64_zero(f64x4 (&acc)[2][2]) {
-#pragma unroll
-  for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-    for (int tj = 0; tj < 2; tj++) acc[ti][tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-}
-
-// Visit the outputs of this thread: f(i, j, value) in tile coordinates.
-template <class F>
-__device__ __forceinline__ void mm64_each(const f64x4 (&acc)[2][2], F f) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wi = wave >> 1, wj = wave & 1;
-#pragma unroll
-  for (int ti = 0; ti < 2; ti++)
-#pragma unroll
-    for (int tj = 0; tj < 2; tj++)
-#pragma unroll
-      for (int r = 0; r < 4; r++)
-        f(32 * wi + 16 * ti + Mfma<double>::row(lane, r), 32 * wj + 16 * tj + (lane & 15),
-          acc[ti][tj][r]);
-}
-
 // In place: C region (pair X rows, pair Y cols) <- V_X^T C V_Y for pX <= pY
 // (mirrored), then P[R rows, pair Y cols] <- P V_Y.  Identity pairs are skipped.
 // Two LDS tiles, so two workgroups share a CU.
@@ -802,32 +851,28 @@ __global__ __launch_bounds__(256) void k_gemm64(const G64* __restrict__ gs) {
   const G64 g = gs[blockIdx.z];
   const int i0 = blockIdx.y * BB, j0 = blockIdx.x * BB;
   if (i0 >= g.M || j0 >= g.N) return;
-  __shared__ double As[BB * LDB];
-  __shared__ double Bs[BB * LDB];
-  double acc[4][4];
-  zero4(acc);
+  __shared__ __align__(16) double As[BB * LDM];
+  __shared__ __align__(16) double Bs[BB * LDM];
+  f64x4 acc[2][2];
+  mm64_zero(acc);
   for (int k0 = 0; k0 < g.K; k0 += BB) {
     __syncthreads();
     for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
       const int a = e / BB, b = e % BB;
-      As[a * LDB + b] = (i0 + a < g.M && k0 + b < g.K) ? g.A[(i0 + a) * g.sai + (k0 + b) * g.sak] : 0.0;
-      Bs[a * LDB + b] = (k0 + a < g.K && j0 + b < g.N) ? g.B[(k0 + a) * g.sbk + (j0 + b) * g.sbj] : 0.0;
+      As[a * LDM + b] = (i0 + a < g.M && k0 + b < g.K) ? g.A[(i0 + a) * g.sai + (k0 + b) * g.sak] : 0.0;
+      Bs[a * LDM + b] = (k0 + a < g.K && j0 + b < g.N) ? g.B[(k0 + a) * g.sbk + (j0 + b) * g.sbj] : 0.0;
     }
     __syncthreads();
-    blk_mm<false, false>(acc, As, Bs);
+    mm64<false, false>(acc, As, Bs);
   }
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
-      if (i < g.M && j < g.N) {
-        double v = g.alpha * acc[a][b];
-        if (g.ea) v /= (1.0 + g.eb[i] * g.ea[j]);
-        g.C[i * g.sci + j * g.scj] = v;
-      }
+  mm64_each(acc, [&](int a, int b, double v) {
+    const int i = i0 + a, j = j0 + b;
+    if (i < g.M && j < g.N) {
+      v *= g.alpha;
+      if (g.ea) v /= (1.0 + g.eb[i] * g.ea[j]);
+      g.C[i * g.sci + j * g.scj] = v;
     }
+  });
 }
 
 void kron_apply_descs(const KronApply* layers, int L, const double* grad, double* delta,
