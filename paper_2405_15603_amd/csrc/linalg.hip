@@ -164,26 +164,21 @@ __global__ __launch_bounds__(256) void k_chol_diag(const EigProblem* __restrict_
   if (j >= nb) return;
   __shared__ double colk[2][BB];
   __shared__ double rowk[2][BB];
+  __shared__ double LO[BB * LDB];   // L, filled a column per step
+  __shared__ double XO[BB * LDB];   // L^-1, filled a row per step
   const long np = p.n_pad;
   const double* src = p.M1 + (long)j * BB * np + (long)j * BB;
-  double* lb = p.Lb + (long)j * BB * np + (long)j * BB;
-  double* li = p.Li + (long)j * BB * np + (long)j * BB;
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double v[4][4], ol[4][4], ox[4][4];   // working element, outputs L and L^-1
+  // Elements above the diagonal are loaded as zero and later take values that
+  // nothing reads: the published entries above row k + 1 of the column and
+  // right of column k + 1 of the row are never used.
+  double v[4][4];
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) {
       const int i = ty + 16 * a, c = tx + 16 * b;
       v[a][b] = c <= i ? src[(long)i * np + c] : 0.0;
-      ol[a][b] = ox[a][b] = 0.0;
-    }
-  // publish column 0 of W and row 0 of R (e_0)
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int i = ty + 16 * a, c = tx + 16 * b;
       if (c == 0) colk[0][i] = v[a][b];
       if (i == 0) rowk[0][c] = c == 0 ? 1.0 : 0.0;
     }
@@ -194,41 +189,52 @@ __global__ __launch_bounds__(256) void k_chol_diag(const EigProblem* __restrict_
     double piv = colk[par][k];
     if (!(piv > 0.0)) { bad = true; piv = 1.0; }
     const double dk = sqrt(piv), idk = 1.0 / dk, ip = idk * idk;
-    double wi[4], wc[4], rk[4];
-#pragma unroll
-    for (int a = 0; a < 4; a++) wi[a] = colk[par][ty + 16 * a];
+    if (threadIdx.x < BB) {   // column k of L
+      const int i = threadIdx.x;
+      LO[i * LDB + k] = i < k ? 0.0 : (i == k ? dk : colk[par][i] * idk);
+    } else if (threadIdx.x < 2 * BB) {   // row k of L^-1 (R[k][k] = 1)
+      const int c = threadIdx.x - BB;
+      XO[k * LDB + c] = c > k ? 0.0 : rowk[par][c] * idk;
+    }
+    double oc[4];
 #pragma unroll
     for (int b = 0; b < 4; b++) {
-      wc[b] = colk[par][tx + 16 * b];
-      rk[b] = rowk[par][tx + 16 * b];
+      const int c = tx + 16 * b;
+      oc[b] = c > k ? colk[par][c] : rowk[par][c];
     }
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < 4; a++) {
+      const int i = ty + 16 * a;
+      const double f = i > k ? colk[par][i] * ip : 0.0;
+      const double eik = i == k ? 1.0 : 0.0;
 #pragma unroll
       for (int b = 0; b < 4; b++) {
-        const int i = ty + 16 * a, c = tx + 16 * b;
-        if (c == k && i >= k) {
-          ol[a][b] = i == k ? dk : wi[a] * idk;
-          v[a][b] = i == k ? 1.0 : -wi[a] * ip;   // R[i][k] after step k
-        } else if (i > k && c > k && c <= i) {
-          v[a][b] -= wi[a] * wc[b] * ip;
-        } else if (i > k && c < k) {
-          v[a][b] -= wi[a] * rk[b] * ip;
-        }
-        if (i == k && c <= k) ox[a][b] = c == k ? idk : v[a][b] * idk;
-        // publish the pivot column and R row of step k + 1
-        if (c == k + 1) colk[par ^ 1][i] = v[a][b];
-        if (i == k + 1) rowk[par ^ 1][c] = c == k + 1 ? 1.0 : v[a][b];
+        const double x = tx + 16 * b == k ? eik : v[a][b];
+        v[a][b] = x - f * oc[b];
       }
-  }
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const long e = (long)(ty + 16 * a) * np + tx + 16 * b;
-      lb[e] = ol[a][b];
-      li[e] = ox[a][b];
     }
+    // publish the pivot column and R row of step k + 1 (static register
+    // indices: a dynamic one would put v in scratch memory)
+    const int k1 = k + 1;
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+      if (tx + 16 * b == k1)
+#pragma unroll
+        for (int a = 0; a < 4; a++) colk[par ^ 1][ty + 16 * a] = v[a][b];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+      if (ty + 16 * a == k1)
+#pragma unroll
+        for (int b = 0; b < 4; b++) rowk[par ^ 1][tx + 16 * b] = tx + 16 * b == k1 ? 1.0 : v[a][b];
+  }
+  __syncthreads();
+  double* lb = p.Lb + (long)j * BB * np + (long)j * BB;
+  double* li = p.Li + (long)j * BB * np + (long)j * BB;
+  for (int e = threadIdx.x; e < BB * BB; e += blockDim.x) {
+    const int i = e / BB, c = e % BB;
+    lb[(long)i * np + c] = LO[i * LDB + c];
+    li[(long)i * np + c] = XO[i * LDB + c];
+  }
   if (threadIdx.x == 0 && bad) atomicMax(p.status ? p.status : status, 4);
 }
 
