@@ -557,8 +557,15 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
   // JB x JB pairs across the two blocks (JB rounds of JB disjoint pairs).
   const bool full = r == 0;
   const int nrr = full ? JS - 1 : JB;
+  int rr = 0;
+  // index pair of rotation k in round rr: from the table in the first round, by
+  // formula in the others
+  auto pair_of = [&](int k) -> int2 {
+    if (full) return pq[k];
+    return make_int2(k, JB + ((k + rr) & (JB - 1)));
+  };
   for (int sw = 0; sw < inner; sw++) {
-    for (int rr = 0; rr < nrr; rr++) {
+    for (rr = 0; rr < nrr; rr++) {
       if (threadIdx.x < JB) {
         const int k = threadIdx.x;
         int a, b;
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
         for (int it = 0; it < SG; it++) {
           const int e = threadIdx.x + it * kSolveThreads;
           const int kx = e / JB, ky = e % JB;
-          const int2 px = pq[kx], py = pq[ky];
+          const int2 px = pair_of(kx), py = pair_of(ky);
           const double2 rx = rot[kx], ry = rot[ky];
           ia[it] = px.x; ib[it] = px.y; jf[it] = py.x; jg[it] = py.y;
           c1[it] = rx.x; s1[it] = rx.y; c2[it] = ry.x; s2[it] = ry.y;
@@ -606,7 +613,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
         for (int it = 0; it < VG; it++) {
           const int e = threadIdx.x + it * kSolveThreads;
           const int k = e / JS;
-          const int2 pk = pq[k];
+          const int2 pk = pair_of(k);
           const double2 rk = rot[k];
           vr[it] = e % JS; va[it] = pk.x; vb[it] = pk.y; vc[it] = rk.x; vs[it] = rk.y;
           y[it][0] = V[vr[it] * LDJ + va[it]];
