@@ -509,6 +509,125 @@ __device__ __forceinline__ void rotation(double app, double aqq, double apq, dou
 
 constexpr int kSolveThreads = 512;
 
+// S <- J^T S J on one 2x2 group: rows (ia, ib) rotated by (c1, s1), columns
+// (jf, jg) by (c2, s2); x = S[ia][jf], S[ia][jg], S[ib][jf], S[ib][jg].
+__device__ __forceinline__ void rot2x2(const double (&x)[4], double c1, double s1, double c2,
+                                       double s2, double (&o)[4]) {
+  const double raf = c1 * x[0] - s1 * x[2];
+  const double rag = c1 * x[1] - s1 * x[3];
+  const double rbf = s1 * x[0] + c1 * x[2];
+  const double rbg = s1 * x[1] + c1 * x[3];
+  o[0] = c2 * raf - s2 * rag;
+  o[1] = s2 * raf + c2 * rag;
+  o[2] = c2 * rbf - s2 * rbg;
+  o[3] = s2 * rbf + c2 * rbg;
+}
+
+__device__ __forceinline__ void jac_rotation(double app, double aqq, double apq, double floor_abs,
+                                             double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) rotation(app, aqq, apq, c, s);
+}
+
+// The JB rounds across the two blocks of a subproblem: rotation k of round rr
+// pairs k with JB + (k + rr) mod JB.  One barrier per round: thread k < JB owns
+// the 2x2 groups (k, k) and (k, k + 1) and also recomputes (k + 1, k + 1), which
+// hold the three entries that rotation k of the next round needs (pair k of
+// round rr + 1 is (a_k, b_{k+1}) of round rr), so it computes that rotation
+// right after its update.  The other threads take the groups (kx, kx + d),
+// d = 2 .. JB - 1; V <- V J as in the first round.
+__device__ void jac_cross_rounds(double* S, double* V, double2 (*rotx)[JB], int inner,
+                                 double floor_abs) {
+  const int t = threadIdx.x;
+  auto pr_of = [](int k, int rr) { return make_int2(k, JB + ((k + rr) & (JB - 1))); };
+  constexpr int VG = JB * JS / kSolveThreads;
+  for (int sw = 0; sw < inner; sw++) {
+    if (t < JB) {
+      double c, s;
+      jac_rotation(S[t * LDJ + t], S[(JB + t) * LDJ + JB + t], S[t * LDJ + JB + t], floor_abs, c, s);
+      rotx[0][t] = make_double2(c, s);
+    }
+    __syncthreads();
+    for (int rr = 0; rr < JB; rr++) {
+      const int par = rr & 1;
+      // V element pairs (loads first, as below)
+      double y[VG][2], vc[VG], vs[VG];
+      int va[VG], vb[VG], vr[VG];
+#pragma unroll
+      for (int it = 0; it < VG; it++) {
+        const int e = t + it * kSolveThreads;
+        const int k = e / JS;
+        const int2 pk = pr_of(k, rr);
+        const double2 rk = rotx[par][k];
+        vr[it] = e % JS; va[it] = pk.x; vb[it] = pk.y; vc[it] = rk.x; vs[it] = rk.y;
+        y[it][0] = V[vr[it] * LDJ + va[it]];
+        y[it][1] = V[vr[it] * LDJ + vb[it]];
+      }
+      if (t < JB) {
+        const int k = t, k1 = (t + 1) & (JB - 1);
+        const int2 p0 = pr_of(k, rr), p1 = pr_of(k1, rr);
+        const double2 r0 = rotx[par][k], r1 = rotx[par][k1];
+        double g1[4], g2[4], g3[4];
+        g1[0] = S[p0.x * LDJ + p0.x]; g1[1] = S[p0.x * LDJ + p0.y];
+        g1[2] = S[p0.y * LDJ + p0.x]; g1[3] = S[p0.y * LDJ + p0.y];
+        g2[0] = S[p0.x * LDJ + p1.x]; g2[1] = S[p0.x * LDJ + p1.y];
+        g2[2] = S[p0.y * LDJ + p1.x]; g2[3] = S[p0.y * LDJ + p1.y];
+        g3[0] = S[p1.x * LDJ + p1.x]; g3[1] = S[p1.x * LDJ + p1.y];
+        g3[2] = S[p1.y * LDJ + p1.x]; g3[3] = S[p1.y * LDJ + p1.y];
+        double n1[4], n2[4], n3[4];
+        rot2x2(g1, r0.x, r0.y, r0.x, r0.y, n1);
+        rot2x2(g2, r0.x, r0.y, r1.x, r1.y, n2);
+        rot2x2(g3, r1.x, r1.y, r1.x, r1.y, n3);
+        // (k1, k1) is written by thread k1 of this wave after this thread's reads
+        S[p0.x * LDJ + p0.x] = n1[0]; S[p0.x * LDJ + p0.y] = n1[1];
+        S[p0.y * LDJ + p0.x] = n1[2]; S[p0.y * LDJ + p0.y] = n1[3];
+        S[p0.x * LDJ + p1.x] = n2[0]; S[p0.x * LDJ + p1.y] = n2[1];
+        S[p0.y * LDJ + p1.x] = n2[2]; S[p0.y * LDJ + p1.y] = n2[3];
+        if (rr + 1 < JB) {
+          // next pair k = (a_k, b_{k1}): S'[a_k][a_k], S'[b_k1][b_k1], S'[a_k][b_k1]
+          double c, s;
+          jac_rotation(n1[0], n3[3], n2[1], floor_abs, c, s);
+          rotx[par ^ 1][k] = make_double2(c, s);
+        }
+      } else {
+        constexpr int NO = JB - 2;   // off-diagonal distances per row of groups
+        double x[2][4];
+        int ia[2], ib[2], jf[2], jg[2];
+        double c1[2], s1[2], c2[2], s2[2];
+#pragma unroll
+        for (int it = 0; it < 2; it++) {
+          const int g = (t - JB) + it * (kSolveThreads - JB);
+          const int kx = g / NO, ky = (kx + 2 + g % NO) & (JB - 1);
+          const int2 px = pr_of(kx, rr), py = pr_of(ky, rr);
+          const double2 rx = rotx[par][kx], ry = rotx[par][ky];
+          ia[it] = px.x; ib[it] = px.y; jf[it] = py.x; jg[it] = py.y;
+          c1[it] = rx.x; s1[it] = rx.y; c2[it] = ry.x; s2[it] = ry.y;
+          x[it][0] = S[ia[it] * LDJ + jf[it]];
+          x[it][1] = S[ia[it] * LDJ + jg[it]];
+          x[it][2] = S[ib[it] * LDJ + jf[it]];
+          x[it][3] = S[ib[it] * LDJ + jg[it]];
+        }
+#pragma unroll
+        for (int it = 0; it < 2; it++) {
+          double o[4];
+          rot2x2(x[it], c1[it], s1[it], c2[it], s2[it], o);
+          S[ia[it] * LDJ + jf[it]] = o[0];
+          S[ia[it] * LDJ + jg[it]] = o[1];
+          S[ib[it] * LDJ + jf[it]] = o[2];
+          S[ib[it] * LDJ + jg[it]] = o[3];
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < VG; it++) {
+        V[vr[it] * LDJ + va[it]] = vc[it] * y[it][0] - vs[it] * y[it][1];
+        V[vr[it] * LDJ + vb[it]] = vs[it] * y[it][0] + vc[it] * y[it][1];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* __restrict__ pr,
                                                    const int* __restrict__ ids,
                                                    const int* __restrict__ done, int r,
@@ -527,6 +646,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
   // 16- or 8-byte access
   __shared__ double2 rot[JB];
   __shared__ int2 pq[JB];
+  __shared__ double2 rotx[2][JB];   // cross rounds: rotations by round parity
   __shared__ int any;
   const long np = p.n_pad;
   const double* C = p.C[0];
@@ -564,6 +684,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const EigProblem* _
     if (full) return pq[k];
     return make_int2(k, JB + ((k + rr) & (JB - 1)));
   };
+  if (!full) {
+    jac_cross_rounds(S, V, rotx, inner, floor_abs);
+  } else
   for (int sw = 0; sw < inner; sw++) {
     for (rr = 0; rr < nrr; rr++) {
       if (threadIdx.x < JB) {
