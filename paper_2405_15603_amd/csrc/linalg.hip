@@ -34,37 +34,6 @@ constexpr int BB = 64;        // Cholesky / inverse block
 constexpr int LDB = BB + 1;   // LDS row stride (doubles)
 constexpr int JB = 32;        // Jacobi block
 
-// acc[4][4] += op(A) op(B) over k in [0, 64) for the 4x4 output patch of this
-// thread (rows 4*ty.., cols 4*tx.., ty = tid/16, tx = tid%16); tiles in LDS.
-template <bool TA, bool TB>
-__device__ __forceinline__ void blk_mm(double acc[4][4], const double* A, const double* B,
-                                       int kdim = BB) {
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  for (int k = 0; k < kdim; k++) {
-    double a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) a[i] = TA ? A[k * LDB + ty * 4 + i] : A[(ty * 4 + i) * LDB + k];
-#pragma unroll
-    for (int j = 0; j < 4; j++) b[j] = TB ? B[(tx * 4 + j) * LDB + k] : B[k * LDB + tx * 4 + j];
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-      for (int j = 0; j < 4; j++) acc[i][j] += a[i] * b[j];
-  }
-}
-
-__device__ __forceinline__ void tile_load(double* dst, const double* src, long ld) {
-  for (int e = threadIdx.x; e < BB * BB; e += blockDim.x)
-    dst[(e / BB) * LDB + (e % BB)] = src[(long)(e / BB) * ld + (e % BB)];
-}
-
-__device__ __forceinline__ void zero4(double acc[4][4]) {
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
-}
-
 // 64 x 64 x 64 FP64 products on the MFMA unit (v_mfma_f64_16x16x4): four waves,
 // each owning a 32 x 32 quadrant as 2 x 2 tiles of 16 x 16.  Tiles sit in LDS
 // with row stride LDM = 70 doubles, which keeps the fragment reads at two
@@ -251,45 +220,43 @@ __global__ __launch_bounds__(256) void k_chol_update(const EigProblem* __restric
     if (i >= nb) return;
     k = j + w;
   }
-  __shared__ double T[BB * LDB];   // L_jj^-1
-  __shared__ double Ai[BB * LDB];
-  __shared__ double Ak[BB * LDB];
+  __shared__ __align__(16) double T[BB * LDM];   // L_jj^-1
+  __shared__ __align__(16) double Ai[BB * LDM];
+  __shared__ __align__(16) double Ak[BB * LDM];
   const long np = p.n_pad;
-  tile_load(T, p.Li + (long)j * BB * np + (long)j * BB, np);
-  tile_load(Ai, p.M1 + (long)i * BB * np + (long)j * BB, np);
-  if (k > j && k != i) tile_load(Ak, p.M1 + (long)k * BB * np + (long)j * BB, np);
+  auto load = [&](double* dst, const double* src) {
+    for (int e = threadIdx.x; e < BB * BB / 2; e += blockDim.x) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      *(double2*)&dst[r * LDM + c] = *(const double2*)(src + (long)r * np + c);
+    }
+  };
+  const bool two = k > j && k != i;
+  load(T, p.Li + (long)j * BB * np + (long)j * BB);
+  load(Ai, p.M1 + (long)i * BB * np + (long)j * BB);
+  if (two) load(Ak, p.M1 + (long)k * BB * np + (long)j * BB);
   __syncthreads();
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double li[4][4], lk[4][4];
-  zero4(li);
-  blk_mm<false, true>(li, Ai, T);
-  if (k > j && k != i) {
-    zero4(lk);
-    blk_mm<false, true>(lk, Ak, T);
+  f64x4 li[2][2], lk[2][2];
+  mm64_zero(li);
+  mm64<false, true>(li, Ai, T);
+  if (two) {
+    mm64_zero(lk);
+    mm64<false, true>(lk, Ak, T);
   }
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      Ai[(ty * 4 + a) * LDB + tx * 4 + b] = li[a][b];
-      if (k > j && k != i) Ak[(ty * 4 + a) * LDB + tx * 4 + b] = lk[a][b];
-    }
+  mm64_each(li, [&](int a, int b, double v) { Ai[a * LDM + b] = v; });
+  if (two) mm64_each(lk, [&](int a, int b, double v) { Ak[a * LDM + b] = v; });
   __syncthreads();
   if (k == j) {
     double* dst = p.Lb + (long)i * BB * np + (long)j * BB;
     for (int e = threadIdx.x; e < BB * BB; e += blockDim.x)
-      dst[(long)(e / BB) * np + (e % BB)] = Ai[(e / BB) * LDB + (e % BB)];
+      dst[(long)(e / BB) * np + (e % BB)] = Ai[(e / BB) * LDM + (e % BB)];
     return;
   }
-  double acc[4][4];
-  zero4(acc);
-  blk_mm<false, true>(acc, Ai, (k == i) ? Ai : Ak);
+  f64x4 acc[2][2];
+  mm64_zero(acc);
+  mm64<false, true>(acc, Ai, (k == i) ? Ai : Ak);
   double* dst = p.M1 + (long)i * BB * np + (long)k * BB;
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) dst[(long)(ty * 4 + a) * np + tx * 4 + b] -= acc[a][b];
+  mm64_each(acc, [&](int a, int b, double v) { dst[(long)a * np + b] -= v; });
 }
 
 // ---------------------------------------------------------------------------
