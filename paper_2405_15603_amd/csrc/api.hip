@@ -693,7 +693,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     ld.h_in = hi;
     ld.h_out = ho;
     ld.off = toff;
-    ld.ldk_in = kp_roundup(hi + 1, 32);
+    ld.ldk_in = kp_roundup(hi + 1, 64);
     ld.ldk_out = kp_roundup(ho, 8);
     ld.wrm = woff;
     woff += (long)ho * ld.ldk_in;
