@@ -230,6 +230,15 @@ kp_status kfac_pinn_set_momentum(kfac_pinn_ctx* ctx, const void* dev_in, int64_t
 kp_status kfac_pinn_timing_enable(kfac_pinn_ctx* ctx, int32_t kernel_class);
 kp_status kfac_pinn_timing_read(kfac_pinn_ctx* ctx, double* out4);
 
+/* Line-search lanes (1 or 2; default 2).  The candidates of the grid line search
+ * (Section 3.4) are independent: with 2 lanes the odd candidates are enqueued on an
+ * internal stream of default priority with their own slab, weight and table
+ * buffers (allocated on the first step that uses them outside a stream capture,
+ * about the size of the line-search slabs), forked from and joined back to the
+ * context's stream, so that two candidates' launches overlap.  The results do not
+ * depend on the lane count.  Instances of a batch use 1 lane. */
+kp_status kfac_pinn_set_line_search_lanes(kfac_pinn_ctx* ctx, int32_t lanes);
+
 /* Jacobi sweeps used by each of the 2L eigenproblems (layer l: 2l side A, 2l+1
    side B) in the last inversion; waits for the stream.  out: host, 2L ints. */
 kp_status kfac_pinn_get_sweeps(kfac_pinn_ctx* ctx, int32_t* out);

@@ -238,6 +238,11 @@ class KfacPinn:
         N.check(self.lib.kfac_pinn_timing_read(self.h, out), "kfac_pinn_timing_read")
         return {"launches": int(out[0]), "ms": out[1], "flops": out[2], "bytes": out[3]}
 
+    def set_line_search_lanes(self, lanes: int) -> None:
+        """1 or 2 streams for the grid line search's candidates (results unchanged)."""
+        N.check(self.lib.kfac_pinn_set_line_search_lanes(self.h, int(lanes)),
+                "kfac_pinn_set_line_search_lanes")
+
     def get_sweeps(self) -> list:
         out = (C.c_int32 * (2 * self.L))()
         N.check(self.lib.kfac_pinn_get_sweeps(self.h, out), "kfac_pinn_get_sweeps")

@@ -66,6 +66,7 @@ _SIGS = {
     "kfac_pinn_timing_enable": (C.c_int, [_V, C.c_int32]),
     "kfac_pinn_timing_read": (C.c_int, [_V, C.POINTER(C.c_double)]),
     "kfac_pinn_get_sweeps": (C.c_int, [_V, C.POINTER(C.c_int32)]),
+    "kfac_pinn_set_line_search_lanes": (C.c_int, [_V, C.c_int32]),
     "kfac_pinn_get_workspace": (C.c_int, [_V, C.POINTER(C.c_int32)]),
     "kfac_pinn_batch_create": (C.c_int, [C.POINTER(kp_problem), C.c_int32, _V, C.POINTER(_V)]),
     "kfac_pinn_batch_destroy": (C.c_int, [_V]),

@@ -122,6 +122,24 @@ struct kfac_pinn_ctx {
   EigProblem* probs_dev = nullptr;
   EigGroups eg;                         // Jacobi groups; side streams made on first use
   bool eg_streams = false;
+  // Line-search lanes: odd candidates run on the first side stream with their own
+  // buffers (lane 1), made on the first step that uses them outside a capture.
+  int ls_lanes = 2;
+  struct LsLane {
+    bool ready = false;
+    hipStream_t st = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    void* theta_trial = nullptr;
+    void* w_hi = nullptr;
+    void* ls_z[2] = {nullptr, nullptr};
+    void* ls_u = nullptr;
+    void* ls_zb[kMaxLayers] = {};
+    void* ls_ub = nullptr;
+    void* tab = nullptr;
+    double* partial = nullptr;
+    void* qbuf = nullptr;
+  } ls1;
+  size_t w_bytes = 0;                   // product-layout weight copy
   G64* kdesc = nullptr;
   int k_mmax = 0, k_nmax = 0;
   int* ctl = nullptr;                  // [0] status [1] step [4..5] alpha [8..] Jacobi flags
@@ -625,6 +643,8 @@ int64_t kfac_pinn_num_params(const int32_t* widths, int32_t n_layers) {
 
 kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx) {
   if (!ctx) return KP_ERR_ARG;
+  if (ctx->ls1.fork) (void)hipEventDestroy(ctx->ls1.fork);
+  if (ctx->ls1.join) (void)hipEventDestroy(ctx->ls1.join);
   if (ctx->eg_streams) {
     for (int k = 1; k < ctx->eg.n; k++) {
       if (ctx->eg.st[k]) {
@@ -736,7 +756,8 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
       return KP_ERR_HIP;
     }
   }
-  ALLOC(c->w_hi, (size_t)woff * c->esz_w);
+  c->w_bytes = (size_t)woff * c->esz_w;
+  ALLOC(c->w_hi, c->w_bytes);
   if (c->wp == P_BF16) ALLOC(c->w_lo, (size_t)woff * c->esz_w);
   ALLOC(c->theta_trial, (size_t)c->D * c->esz_p);
   if ((e = alloc_slabs(c, c->si)) != hipSuccess || (e = alloc_slabs(c, c->sb)) != hipSuccess) {
@@ -750,9 +771,15 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   ALLOC(c->ls_u, Rmax * c->esz_c);
   if (c->lmode == M_BF16 && c->max_b > 0) {
     const size_t Rb = (size_t)c->max_b * c->sb.S;
-    for (int l = 0; l < c->L; l++) {
-      ALLOC(c->ls_zb[l], Rb * c->ldz[l] * c->esz_l);
-      if (l == 0) continue;
+    for (int l = 0; l < c->L; l++) ALLOC(c->ls_zb[l], Rb * c->ldz[l] * c->esz_l);
+    // the zero fills run on the null stream: finish them before the padding
+    // kernels on the context's stream, which may be a non-blocking one
+    if ((e = hipDeviceSynchronize()) != hipSuccess) {
+      kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
+      kfac_pinn_destroy(c);
+      return KP_ERR_HIP;
+    }
+    for (int l = 1; l < c->L; l++) {
       FwdLayerArgs a{};
       a.N = c->max_b;
       a.S = 1;
@@ -1020,16 +1047,83 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* c, const void* theta, const void* xi,
   return KP_OK;
 }
 
-static hipError_t eig_all(kfac_pinn_ctx* c, double lambda) {
-  if (!c->eg_streams && c->eg.n > 1) {
-    // side streams of default priority for the concurrent Jacobi groups
-    c->eg_streams = true;
-    for (int k = 1; k < c->eg.n; k++) {
-      if (hipError_t e = hipStreamCreateWithFlags(&c->eg.st[k], hipStreamNonBlocking)) return e;
-      if (hipError_t e = hipEventCreateWithFlags(&c->eg.join[k], hipEventDisableTiming)) return e;
-    }
-    if (hipError_t e = hipEventCreateWithFlags(&c->eg.fork, hipEventDisableTiming)) return e;
+// side streams of default priority for the concurrent Jacobi groups (the first
+// one also carries line-search lane 1)
+static hipError_t side_streams(kfac_pinn_ctx* c) {
+  if (c->eg_streams || c->eg.n < 2) return hipSuccess;
+  c->eg_streams = true;
+  for (int k = 1; k < c->eg.n; k++) {
+    if (hipError_t e = hipStreamCreateWithFlags(&c->eg.st[k], hipStreamNonBlocking)) return e;
+    if (hipError_t e = hipEventCreateWithFlags(&c->eg.join[k], hipEventDisableTiming)) return e;
   }
+  return hipEventCreateWithFlags(&c->eg.fork, hipEventDisableTiming);
+}
+
+// Buffers of line-search lane 1, sized as lane 0's (the context's own).
+static hipError_t ls_lane_alloc(kfac_pinn_ctx* c) {
+  kfac_pinn_ctx::LsLane& x = c->ls1;
+  if (x.ready) return hipSuccess;
+  hipError_t e;
+  if ((e = side_streams(c)) != hipSuccess) return e;
+  if (c->eg.n < 2) return hipErrorNotReady;
+  x.st = c->eg.st[1];
+  if ((e = hipEventCreateWithFlags(&x.fork, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&x.join, hipEventDisableTiming)) != hipSuccess)
+    return e;
+  const size_t Rmax = std::max((size_t)c->max_i * c->si.S, (size_t)c->max_b);
+  if ((e = dmalloc(c, &x.theta_trial, (size_t)c->D * c->esz_p)) != hipSuccess ||
+      (e = dmalloc(c, &x.w_hi, c->w_bytes)) != hipSuccess ||
+      (e = dmalloc(c, &x.ls_z[0], Rmax * c->ldz_max * c->esz_l)) != hipSuccess ||
+      (e = dmalloc(c, &x.ls_z[1], Rmax * c->ldz_max * c->esz_l)) != hipSuccess ||
+      (e = dmalloc(c, &x.ls_u, Rmax * c->esz_c)) != hipSuccess ||
+      (e = dmalloc(c, &x.tab, (size_t)c->tab_stride * (2 + kMaxChunks) * c->esz_c)) != hipSuccess ||
+      (e = dmalloc(c, (void**)&x.partial, sizeof(double) * c->partial_n)) != hipSuccess ||
+      (e = dmalloc(c, &x.qbuf, sizeof(double) * (size_t)(c->d + 1) * c->w[1])) != hipSuccess)
+    return e;
+  const size_t Rb = (size_t)c->max_b * c->sb.S;
+  if (c->ls_zb[0]) {
+    for (int l = 0; l < c->L; l++)
+      if ((e = dmalloc(c, &x.ls_zb[l], Rb * c->ldz[l] * c->esz_l)) != hipSuccess) return e;
+    if ((e = dmalloc(c, &x.ls_ub, Rb * c->esz_c)) != hipSuccess) return e;
+  }
+  // the zero fills of dmalloc run on the null stream, which a non-blocking stream
+  // does not wait for: finish them before lane 1 writes its buffers
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+  if (c->ls_zb[0]) {   // boundary slabs with their constant bias and padding columns
+    for (int l = 1; l < c->L; l++) {
+      FwdLayerArgs a{};
+      a.N = c->max_b;
+      a.S = 1;
+      a.h_out = c->w[l];
+      a.z = x.ls_zb[l];
+      a.ldzo = c->ldz[l];
+      if ((e = fwdlap_finish(c->lmode, a, 1, x.st)) != hipSuccess) return e;
+    }
+    if ((e = hipStreamSynchronize(x.st)) != hipSuccess) return e;
+  }
+  x.ready = true;
+  return hipSuccess;
+}
+
+// Exchanges the context's stream and line-search buffers with lane 1's: the
+// line-search helpers then enqueue a candidate on lane 1.
+static void ls_lane_swap(kfac_pinn_ctx* c) {
+  kfac_pinn_ctx::LsLane& x = c->ls1;
+  std::swap(c->st, x.st);
+  std::swap(c->theta_trial, x.theta_trial);
+  std::swap(c->w_hi, x.w_hi);
+  std::swap(c->ls_z[0], x.ls_z[0]);
+  std::swap(c->ls_z[1], x.ls_z[1]);
+  std::swap(c->ls_u, x.ls_u);
+  for (int l = 0; l < kMaxLayers; l++) std::swap(c->ls_zb[l], x.ls_zb[l]);
+  std::swap(c->ls_ub, x.ls_ub);
+  std::swap(c->tab, x.tab);
+  std::swap(c->partial, x.partial);
+  std::swap(c->qbuf, x.qbuf);
+}
+
+static hipError_t eig_all(kfac_pinn_ctx* c, double lambda) {
+  if (hipError_t e = side_streams(c)) return e;
   return kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
                           c->ctl + 8, c->ctl + 2, kEigRefresh, kJacobiSweeps, c->eg, c->st);
 }
@@ -1085,13 +1179,37 @@ static kp_status step_tail(kfac_pinn_ctx* c, void* theta, const void* xi, const 
   KP_TRY(momentum(c->pp, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
   // 5) learning rate and update
   if (hp->lr_mode == 1) {
+    // The candidates are independent: with two lanes the odd ones run on lane 1
+    // (its own buffers, forked from and joined to the context's stream), so one
+    // candidate's launches fill the chip while the other's drain.  Lane 1 is
+    // made on the first such step outside a stream capture.
+    bool two = c->ls_lanes == 2 && ncand > 1;
+    if (two && !c->ls1.ready) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      KP_TRY(hipStreamIsCapturing(c->st, &cs));
+      if (cs == hipStreamCaptureStatusNone) KP_TRY(ls_lane_alloc(c));
+      two = c->ls1.ready;
+    }
+    if (two) {
+      KP_TRY(hipEventRecord(c->ls1.fork, c->st));
+      KP_TRY(hipStreamWaitEvent(c->ls1.st, c->ls1.fork, 0));
+    }
     for (int k = 0; k < ncand; k++) {
+      const bool lane1 = two && (k & 1);
+      if (lane1) ls_lane_swap(c);
       const double alpha = ldexp(1.0, hp->grid_max_exp - k);
-      KP_TRY(axpy_theta(c->pp, theta, c->dhat, alpha, c->theta_trial, c->D, c->st));
+      hipError_t e = axpy_theta(c->pp, theta, c->dhat, alpha, c->theta_trial, c->D, c->st);
       // the candidate's forward copy only: no backward copy, no BF16x3 low plane
-      KP_TRY(prep_weights(c->lp == P_BF16 ? P_BF16 : c->wp, c->theta_trial, nullptr, 0.0, c->nd,
-                          c->w_hi, nullptr, nullptr, 0, c->st, 1));
-      KP_TRY(eval_loss(c, xi, yi, ni, xb, yb, nb, 2 + k));
+      if (e == hipSuccess)
+        e = prep_weights(c->lp == P_BF16 ? P_BF16 : c->wp, c->theta_trial, nullptr, 0.0, c->nd,
+                         c->w_hi, nullptr, nullptr, 0, c->st, 1);
+      if (e == hipSuccess) e = eval_loss(c, xi, yi, ni, xb, yb, nb, 2 + k);
+      if (lane1) ls_lane_swap(c);
+      KP_TRY(e);
+    }
+    if (two) {
+      KP_TRY(hipEventRecord(c->ls1.join, c->ls1.st));
+      KP_TRY(hipStreamWaitEvent(c->st, c->ls1.join, 0));
     }
     c->last_ncand = ncand;
   }
@@ -1199,6 +1317,13 @@ kp_status kfac_pinn_timing_read(kfac_pinn_ctx* c, double* out) {
   c->tm_used = 0;
   c->tm_flops = c->tm_bytes = 0.0;
   c->tm_launches = 0;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_set_line_search_lanes(kfac_pinn_ctx* c, int32_t lanes) {
+  KP_ARG(c, "null context");
+  KP_ARG(lanes == 1 || lanes == 2, "lanes must be 1 or 2");
+  c->ls_lanes = lanes;
   return KP_OK;
 }
 
@@ -1372,6 +1497,7 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
     kfac_pinn_ctx* c = nullptr;
     kp_status s = kfac_pinn_create(&problems[k], b->lanes[k % nl], &c);
     if (s != KP_OK) return fail(s);
+    c->ls_lanes = 1;   // the batch's own lanes already overlap the instances
     b->ctx.push_back(c);
     b->probs.insert(b->probs.end(), c->probs.begin(), c->probs.end());
   }

@@ -220,3 +220,33 @@ def test_vjp_matches_autograd_of_oracle(precision, tol):
     rt, rx = torch.autograd.grad(obj, (tht, x))
     assert rel(tb, rt) < tol
     assert rel(xbar, rx) < tol
+
+
+@pytest.mark.parametrize("case,precision", [("tiny_heat", "f64"), ("poisson2d", "bf16"),
+                                            ("ragged", "bf16")])
+def test_line_search_lanes_bitwise(case, precision):
+    """Two line-search lanes (odd candidates on a second stream with their own
+    buffers) give bit-identical candidate losses, step sizes and parameters to one
+    lane, over three consecutive steps."""
+    from paper_2405_15603_amd import HParams, KfacPinn
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, precision)
+    dev = [to_dev(a, precision) for a in (xi, yi, xb, yb)]
+    hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588)
+    runs = []
+    for lanes in (1, 2):
+        kp = kp_for(p, precision)
+        kp.set_line_search_lanes(lanes)
+        tht = to_dev(th, precision)
+        out = []
+        for _ in range(3):
+            info = KfacPinn.decode_info(kp.step(tht, *dev, hp))
+            out.append((info["lr"], kp.get_line_search(31).cpu().numpy().copy(),
+                        tht.detach().cpu().numpy().copy()))
+        assert kp.sync() == 0
+        runs.append(out)
+        del kp
+    for (lr1, ls1, t1), (lr2, ls2, t2) in zip(*runs):
+        assert lr1 == lr2
+        assert np.array_equal(ls1, ls2, equal_nan=True)
+        assert np.array_equal(t1, t2)
