@@ -26,7 +26,10 @@
  * Pointers: every array argument is DEVICE memory owned by the caller unless
  *   the comment says "host".  It must stay valid until the work enqueued on the
  *   context's stream has finished.  The context owns all workspaces (allocated
- *   once in kfac_pinn_create); no other entry point allocates.
+ *   in kfac_pinn_create); no other entry point allocates device memory except
+ *   kfac_pinn_set_line_search_lanes (which frees or re-makes the second
+ *   line-search lane's buffers).  The context's internal streams (default
+ *   priority) are created by its first inversion.
  * Errors: invalid arguments return KP_ERR_ARG synchronously and enqueue
  *   nothing.  HIP launch failures return KP_ERR_HIP.  Failures found on the
  *   device (a factor that is not positive definite, non-finite losses) set the
@@ -233,10 +236,13 @@ kp_status kfac_pinn_timing_read(kfac_pinn_ctx* ctx, double* out4);
 /* Line-search lanes (1 or 2; default 2).  The candidates of the grid line search
  * (Section 3.4) are independent: with 2 lanes the odd candidates are enqueued on an
  * internal stream of default priority with their own slab, weight and table
- * buffers (allocated on the first step that uses them outside a stream capture,
- * about the size of the line-search slabs), forked from and joined back to the
- * context's stream, so that two candidates' launches overlap.  The results do not
- * depend on the lane count.  Instances of a batch use 1 lane. */
+ * buffers (about the size of the line-search slabs, made by kfac_pinn_create),
+ * forked from and joined back to the context's stream, so that two candidates'
+ * launches overlap.  Setting 1 frees those buffers (after a device-wide wait);
+ * setting 2 again re-makes them (and waits for the device).  A step uses the
+ * second lane once the context's internal streams exist (from its first
+ * inversion on).  The results do not depend on the lane count.  Instances of a
+ * batch use 1 lane.  Errors: KP_ERR_ARG for other counts, KP_ERR_HIP. */
 kp_status kfac_pinn_set_line_search_lanes(kfac_pinn_ctx* ctx, int32_t lanes);
 
 /* Jacobi sweeps used by each of the 2L eigenproblems (layer l: 2l side A, 2l+1

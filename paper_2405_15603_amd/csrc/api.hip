@@ -661,6 +661,8 @@ kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx) {
   return KP_OK;
 }
 
+static hipError_t ls_lane_alloc(kfac_pinn_ctx* c);
+
 kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** out) {
   KP_ARG(pb && out, "null argument");
   *out = nullptr;
@@ -907,10 +909,13 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
           return KP_ERR_HIP;
         }
       }
-  if ((e = hipDeviceSynchronize()) != hipSuccess) {
+  if ((e = hipDeviceSynchronize()) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&c->ls1.fork, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&c->ls1.join, hipEventDisableTiming)) != hipSuccess ||
+      (e = ls_lane_alloc(c)) != hipSuccess) {
     kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);
     kfac_pinn_destroy(c);
-    return KP_ERR_HIP;
+    return e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_HIP;
   }
   *out = c;
   return KP_OK;
@@ -1059,17 +1064,12 @@ static hipError_t side_streams(kfac_pinn_ctx* c) {
   return hipEventCreateWithFlags(&c->eg.fork, hipEventDisableTiming);
 }
 
-// Buffers of line-search lane 1, sized as lane 0's (the context's own).
+// Buffers of line-search lane 1, sized as lane 0's (the context's own); its
+// stream is the first side stream, attached when a step uses the lane.
 static hipError_t ls_lane_alloc(kfac_pinn_ctx* c) {
   kfac_pinn_ctx::LsLane& x = c->ls1;
   if (x.ready) return hipSuccess;
   hipError_t e;
-  if ((e = side_streams(c)) != hipSuccess) return e;
-  if (c->eg.n < 2) return hipErrorNotReady;
-  x.st = c->eg.st[1];
-  if ((e = hipEventCreateWithFlags(&x.fork, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&x.join, hipEventDisableTiming)) != hipSuccess)
-    return e;
   const size_t Rmax = std::max((size_t)c->max_i * c->si.S, (size_t)c->max_b);
   if ((e = dmalloc(c, &x.theta_trial, (size_t)c->D * c->esz_p)) != hipSuccess ||
       (e = dmalloc(c, &x.w_hi, c->w_bytes)) != hipSuccess ||
@@ -1087,7 +1087,7 @@ static hipError_t ls_lane_alloc(kfac_pinn_ctx* c) {
     if ((e = dmalloc(c, &x.ls_ub, Rb * c->esz_c)) != hipSuccess) return e;
   }
   // the zero fills of dmalloc run on the null stream, which a non-blocking stream
-  // does not wait for: finish them before lane 1 writes its buffers
+  // does not wait for: finish them before the padding kernels
   if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
   if (c->ls_zb[0]) {   // boundary slabs with their constant bias and padding columns
     for (int l = 1; l < c->L; l++) {
@@ -1097,11 +1097,32 @@ static hipError_t ls_lane_alloc(kfac_pinn_ctx* c) {
       a.h_out = c->w[l];
       a.z = x.ls_zb[l];
       a.ldzo = c->ldz[l];
-      if ((e = fwdlap_finish(c->lmode, a, 1, x.st)) != hipSuccess) return e;
+      if ((e = fwdlap_finish(c->lmode, a, 1, c->st)) != hipSuccess) return e;
     }
-    if ((e = hipStreamSynchronize(x.st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return e;
   }
   x.ready = true;
+  return hipSuccess;
+}
+
+static hipError_t ls_lane_free(kfac_pinn_ctx* c) {
+  kfac_pinn_ctx::LsLane& x = c->ls1;
+  if (!x.ready) return hipSuccess;
+  if (hipError_t e = hipDeviceSynchronize()) return e;
+  std::vector<void*> bufs = {x.theta_trial, x.w_hi, x.ls_z[0], x.ls_z[1], x.ls_u, x.ls_ub,
+                             x.tab, x.partial, x.qbuf};
+  for (int l = 0; l < kMaxLayers; l++) bufs.push_back(x.ls_zb[l]);
+  for (void* b : bufs) {
+    if (!b) continue;
+    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), b), c->allocs.end());
+    (void)hipFree(b);
+  }
+  hipStream_t st = x.st;
+  hipEvent_t f = x.fork, j = x.join;
+  x = kfac_pinn_ctx::LsLane{};
+  x.st = st;
+  x.fork = f;
+  x.join = j;
   return hipSuccess;
 }
 
@@ -1181,16 +1202,11 @@ static kp_status step_tail(kfac_pinn_ctx* c, void* theta, const void* xi, const 
   if (hp->lr_mode == 1) {
     // The candidates are independent: with two lanes the odd ones run on lane 1
     // (its own buffers, forked from and joined to the context's stream), so one
-    // candidate's launches fill the chip while the other's drain.  Lane 1 is
-    // made on the first such step outside a stream capture.
-    bool two = c->ls_lanes == 2 && ncand > 1;
-    if (two && !c->ls1.ready) {
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      KP_TRY(hipStreamIsCapturing(c->st, &cs));
-      if (cs == hipStreamCaptureStatusNone) KP_TRY(ls_lane_alloc(c));
-      two = c->ls1.ready;
-    }
+    // candidate's launches fill the chip while the other's drain.
+    const bool two = c->ls_lanes == 2 && ncand > 1 && c->ls1.ready && c->eg_streams &&
+                     c->eg.n > 1;
     if (two) {
+      c->ls1.st = c->eg.st[1];
       KP_TRY(hipEventRecord(c->ls1.fork, c->st));
       KP_TRY(hipStreamWaitEvent(c->ls1.st, c->ls1.fork, 0));
     }
@@ -1323,6 +1339,7 @@ kp_status kfac_pinn_timing_read(kfac_pinn_ctx* c, double* out) {
 kp_status kfac_pinn_set_line_search_lanes(kfac_pinn_ctx* c, int32_t lanes) {
   KP_ARG(c, "null context");
   KP_ARG(lanes == 1 || lanes == 2, "lanes must be 1 or 2");
+  KP_TRY(lanes == 2 ? ls_lane_alloc(c) : ls_lane_free(c));
   c->ls_lanes = lanes;
   return KP_OK;
 }
@@ -1497,7 +1514,11 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
     kfac_pinn_ctx* c = nullptr;
     kp_status s = kfac_pinn_create(&problems[k], b->lanes[k % nl], &c);
     if (s != KP_OK) return fail(s);
-    c->ls_lanes = 1;   // the batch's own lanes already overlap the instances
+    // the batch's own lanes already overlap the instances: one line-search lane
+    if ((s = kfac_pinn_set_line_search_lanes(c, 1)) != KP_OK) {
+      kfac_pinn_destroy(c);
+      return fail(s);
+    }
     b->ctx.push_back(c);
     b->probs.insert(b->probs.end(), c->probs.begin(), c->probs.end());
   }
