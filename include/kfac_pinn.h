@@ -29,7 +29,10 @@
  *   in kfac_pinn_create); no other entry point allocates device memory except
  *   kfac_pinn_set_line_search_lanes (which frees or re-makes the second
  *   line-search lane's buffers).  The context's internal streams (default
- *   priority) are created by its first inversion.
+ *   priority) are created by its first inversion; work an entry point forks
+ *   onto them (the inversion's Jacobi groups, the second line-search lane) is
+ *   joined back into the context's stream before the entry point returns, so
+ *   the order that the caller sees on that stream is unchanged.
  * Errors: invalid arguments return KP_ERR_ARG synchronously and enqueue
  *   nothing.  HIP launch failures return KP_ERR_HIP.  Failures found on the
  *   device (a factor that is not positive definite, non-finite losses) set the
