@@ -35,9 +35,15 @@
  *   the order that the caller sees on that stream is unchanged.
  * Errors: invalid arguments return KP_ERR_ARG synchronously and enqueue
  *   nothing.  HIP launch failures return KP_ERR_HIP.  Failures found on the
- *   device (a factor that is not positive definite, non-finite losses) set the
- *   context's device status word; the parameter update is then skipped (theta
- *   and the momentum stay untouched) and kfac_pinn_sync returns the code.
+ *   device set the context's device status word: a damped interior factor that
+ *   is not positive definite (KP_ERR_NOT_PD), a non-finite loss at theta_t or at
+ *   every line-search candidate (KP_ERR_NONFINITE; it takes precedence, being the
+ *   cause of the others), an eigensolver that reached its sweep cap unconverged
+ *   (KP_ERR_NOT_CONVERGED, only when nothing failed before it).  The parameter
+ *   update is then skipped (theta, the momentum and the step counter stay
+ *   untouched) and kfac_pinn_sync returns the code.  The Kronecker factors
+ *   already hold the failed step's EMA; kfac_pinn_reset_state or
+ *   kfac_pinn_set_factor restores them.
  * Threads: a context is not thread-safe; distinct contexts are independent.
  */
 #ifndef KFAC_PINN_H
@@ -59,15 +65,20 @@ typedef enum {
   KP_ERR_HIP = 3,
   KP_ERR_NOT_PD = 4,
   KP_ERR_NONFINITE = 5,
-  KP_ERR_STATE = 6
+  KP_ERR_STATE = 6,
+  KP_ERR_NOT_CONVERGED = 7  /* the Jacobi eigensolver of the Kronecker-sum inverse
+                               reached its sweep cap with rotations left        */
 } kp_status;
 
 typedef enum {
   KP_F64 = 0,        /* everything in FP64 (the paper's precision)                 */
   KP_F32 = 1,        /* FP32 slabs and matrix products, FP64 factors and inversion */
-  KP_MIXED_BF16 = 2  /* BF16 slabs, BF16 MFMA with FP32 accumulation (parameters
-                        enter the products as a BF16 hi + lo pair), FP32 elementwise
-                        work, FP64 factors and inversion                            */
+  KP_MIXED_BF16 = 2  /* BF16 MFMA with FP32 accumulation.  Curvature pass (forward
+                        Laplacian, adjoint, factors, gradient): FP32 slabs whose
+                        products run as BF16x3 (hi*hi + lo*hi + hi*lo of the BF16
+                        split of each operand).  Line-search forwards: BF16 slabs
+                        and BF16 weights, one MFMA per product.  FP32 elementwise
+                        work, FP32 master parameters, FP64 factors and inversion */
 } kp_precision;
 
 typedef struct {
@@ -89,8 +100,10 @@ typedef struct {
 typedef struct {
   double lambda;        /* damping added to all four factors (Section 3.4)          */
   double beta;          /* EMA factor in [0, 1)                                     */
-  double momentum;      /* mu                                                       */
-  int32_t lr_mode;      /* 0: fixed alpha = lr; 1: grid line search                 */
+  double momentum;      /* mu (modes 0 and 1)                                       */
+  int32_t lr_mode;      /* 0: fixed alpha = lr; 1: grid line search; 2: KFAC*, alpha
+                           and mu from the quadratic model with the exact damped
+                           Gramian (Section 3.4)                                     */
   double lr;            /* fixed step (lr_mode 0)                                   */
   int32_t grid_min_exp; /* grid alpha = 2^k, k = grid_max_exp .. grid_min_exp       */
   int32_t grid_max_exp; /* (the paper: -30 .. 0)                                    */
@@ -104,6 +117,9 @@ typedef struct {
   double loss_after;     /* L(theta_t + delta_t) (grid mode; NaN in fixed mode)     */
   int32_t status;        /* kp_status of this step                                  */
   int32_t step;          /* step counter after this step                            */
+  double momentum_chosen;  /* coefficient of delta_{t-1} in the applied update:
+                              alpha * mu in modes 0 and 1 (0 at the first step),
+                              mu* in mode 2                                        */
 } kp_step_info;
 
 /* Seeded sampler (kfac_pinn_sample).  Values come from SplitMix64 (Steele, Lea &
@@ -187,10 +203,17 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* ctx, const void* theta,
  * sum is then (P_A (x) P_B) (I + e_A (x) e_B)^-1 (P_A (x) P_B)^T.  The Jacobi
  * iteration starts from the eigenvectors found by the previous call on this
  * context (the identity after create/reset_state and on every 1000th call) and
- * runs until no rotation exceeds its threshold, so the result does not depend
- * on the start beyond rounding.  Sets KP_ERR_NOT_PD in the device status when
- * a damped interior factor is not positive definite. */
+ * runs until a sweep performs no rotation above its threshold, at most
+ * max_sweeps sweeps (default 20), so the result does not depend on the start
+ * beyond rounding.  Sets KP_ERR_NOT_PD in the device status when a damped
+ * interior factor is not positive definite, and KP_ERR_NOT_CONVERGED when a
+ * problem still rotated in its last allowed sweep. */
 kp_status kfac_pinn_invert(kfac_pinn_ctx* ctx, double lambda);
+
+/* Sweep cap of the Jacobi eigensolver (1 .. 64; default 20).  Every call enqueues
+ * the launches of max_sweeps sweeps; a converged problem's launches return at
+ * once.  Errors: KP_ERR_ARG outside the range. */
+kp_status kfac_pinn_set_max_sweeps(kfac_pinn_ctx* ctx, int32_t max_sweeps);
 
 /* Delta = -(A_i (x) B_i + A_b (x) B_b)^-1 g per layer with the preconditioner of
  * the last kfac_pinn_invert (grad_in, delta_out: D doubles each). */
@@ -201,8 +224,15 @@ kp_status kfac_pinn_precondition(kfac_pinn_ctx* ctx, const double* grad_in, doub
  * (lambda), Delta = -C g, momentum delta^ = mu delta_{t-1} + Delta (delta_{-1} =
  * 0), the learning rate (fixed, or argmin of L(theta + 2^k delta^) over the grid
  * with ties to the larger step and non-finite losses skipped), then
- * theta_inout += alpha delta^ and delta_t = alpha delta^.  Nothing is read back
- * to the host; `info` (device, may be NULL) receives the step's summary. */
+ * theta_inout += alpha delta^ and delta_t = alpha delta^.
+ * KFAC* (lr_mode 2, Section 3.4): delta_t = alpha* Delta + mu* delta_{t-1} with
+ * (alpha*, mu*) = -Q^-1 (Delta^T g, delta_{t-1}^T g), Q_ij = d_i^T (G + lambda I) d_j
+ * for d = (Delta, delta_{t-1}) and G the exact Gramian of the loss; G enters
+ * through one Jacobian-vector product per direction, contracted from the slabs of
+ * this step's curvature pass (so a workspace limit that drops them is an
+ * argument error).  At the first step mu* = 0 and alpha* = -Delta^T g / Q_11.
+ * Nothing is read back to the host; `info` (device, may be NULL) receives the
+ * step's summary. */
 kp_status kfac_pinn_step(kfac_pinn_ctx* ctx, void* theta_inout,
                          const void* x_int, const void* y_int, int32_t n_int,
                          const void* x_bnd, const void* y_bnd, int32_t n_bnd,
@@ -296,6 +326,15 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* batch, void* const* thetas,
                                const int32_t* n_int, const void* const* x_bnd,
                                const void* const* y_bnd, const int32_t* n_bnd,
                                const kp_hparams* hp, kp_step_info* infos);
+
+/* Guard check (diagnostics).  When the environment variable KFAC_PINN_GUARD_KB is
+ * a positive number at kfac_pinn_create, every device buffer of the context is
+ * allocated with that many KiB of guard bytes before and after it, filled with a
+ * fixed pattern.  kfac_pinn_check_guards waits for the device and writes (host)
+ * the number of guard bytes that no longer hold the pattern (0: no kernel wrote
+ * outside a buffer by up to the guard size) and the number of guarded buffers.
+ * Without guards both counts are 0. */
+kp_status kfac_pinn_check_guards(kfac_pinn_ctx* ctx, int64_t* bad_bytes, int64_t* buffers);
 
 /* Waits for the context's stream; returns the device status word (and clears it). */
 kp_status kfac_pinn_sync(kfac_pinn_ctx* ctx);

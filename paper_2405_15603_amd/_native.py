@@ -10,7 +10,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkfac_pinn.so")
 
-KP_OK, KP_ERR_ARG, KP_ERR_OOM, KP_ERR_HIP, KP_ERR_NOT_PD, KP_ERR_NONFINITE, KP_ERR_STATE = range(7)
+(KP_OK, KP_ERR_ARG, KP_ERR_OOM, KP_ERR_HIP, KP_ERR_NOT_PD, KP_ERR_NONFINITE, KP_ERR_STATE,
+ KP_ERR_NOT_CONVERGED) = range(8)
 KP_F64, KP_F32, KP_MIXED_BF16 = 0, 1, 2
 
 
@@ -31,7 +32,7 @@ class kp_hparams(C.Structure):
 class kp_step_info(C.Structure):
     _fields_ = [("loss_interior", C.c_double), ("loss_boundary", C.c_double),
                 ("lr_chosen", C.c_double), ("loss_after", C.c_double), ("status", C.c_int32),
-                ("step", C.c_int32)]
+                ("step", C.c_int32), ("momentum_chosen", C.c_double)]
 
 
 class kp_sampler(C.Structure):
@@ -55,6 +56,8 @@ _SIGS = {
                                     _V, _V]),
     "kfac_pinn_invert": (C.c_int, [_V, C.c_double]),
     "kfac_pinn_precondition": (C.c_int, [_V, _V, _V]),
+    "kfac_pinn_set_max_sweeps": (C.c_int, [_V, C.c_int32]),
+    "kfac_pinn_check_guards": (C.c_int, [_V, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kfac_pinn_step": (C.c_int, [_V, _V, _V, _V, C.c_int32, _V, _V, C.c_int32,
                                  C.POINTER(kp_hparams), _V]),
     "kfac_pinn_get_factor": (C.c_int, [_V, C.c_int32, C.c_int32, C.c_int32, _V]),

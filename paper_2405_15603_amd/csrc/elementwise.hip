@@ -392,16 +392,20 @@ hipError_t axpy_theta(Prec p, const void* theta, const void* dir, double alpha, 
 struct StepInfoDev {
   double loss_interior, loss_boundary, lr_chosen, loss_after;
   int status, step;
+  double momentum_chosen;   // coefficient of delta_{t-1} in the applied update
 };
 
 // alpha* = first strict minimum over candidates ordered from the largest step
 // (ties go to the larger alpha); non-finite losses are skipped.
 __global__ void k_select(const double* __restrict__ losses, int ncand, int kmax, double fixed_lr,
-                         const double* __restrict__ base, int* status, int* step, double* alpha,
-                         StepInfoDev* info) {
+                         double mu, const double* __restrict__ base, int* status, int* step,
+                         double* alpha, StepInfoDev* info) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double a = 0.0, after = __builtin_nan("");
   int st = *status;
+  // a non-finite loss at theta_t (non-finite points, targets or parameters) is the
+  // cause of whatever else failed downstream of it
+  if (!isfinite(base[0]) || !isfinite(base[1])) st = 5;
   if (st == 0) {
     if (fixed_lr >= 0.0) {
       a = fixed_lr;
@@ -417,6 +421,9 @@ __global__ void k_select(const double* __restrict__ losses, int ncand, int kmax,
     }
   }
   if (st != 0) a = 0.0;
+  // delta_t = alpha (mu delta_{t-1} + Delta) carries alpha mu of delta_{t-1}
+  // (none at the first step, where delta_{-1} = 0)
+  const double mom = (st == 0 && *step > 0) ? a * mu : 0.0;
   *status = st;
   *alpha = a;
   if (st == 0) *step += 1;
@@ -427,6 +434,7 @@ __global__ void k_select(const double* __restrict__ losses, int ncand, int kmax,
     info->loss_after = after;
     info->status = st;
     info->step = *step;
+    info->momentum_chosen = mom;
   }
 }
 
@@ -442,10 +450,10 @@ __global__ void k_apply_update(const int* __restrict__ status, const double* __r
 }
 
 hipError_t finish_step(Prec p, const double* losses, int ncand, int kmax, double fixed_lr,
-                       const double* base_loss, void* theta, void* dhat, void* delta, long D,
-                       int* status, int* step, void* info, hipStream_t st) {
+                       double mu, const double* base_loss, void* theta, void* dhat, void* delta,
+                       long D, int* status, int* step, void* info, hipStream_t st) {
   double* alpha = (double*)(status + 4);   // scalar slot next to the status word
-  k_select<<<1, 64, 0, st>>>(losses, ncand, kmax, fixed_lr, base_loss, status, step, alpha,
+  k_select<<<1, 64, 0, st>>>(losses, ncand, kmax, fixed_lr, mu, base_loss, status, step, alpha,
                              (StepInfoDev*)info);
   int nb = (int)((D + 255) / 256);
   if (p == P_F64)

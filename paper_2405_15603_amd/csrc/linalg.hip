@@ -840,6 +840,17 @@ __global__ void k_jac_check(const EigProblem* __restrict__ pr, const int* __rest
   *rot = 0;
 }
 
+// After the last scheduled sweep: a problem that still rotated in its last sweep
+// has not converged; its e = diag(C) would not diagonalise the whitened factor, so
+// the owning context's status becomes 7 (unless an earlier failure is recorded).
+__global__ void k_jac_final(const EigProblem* __restrict__ pr, const int* __restrict__ done,
+                            int nprob, int* status) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nprob || done[2 * q]) return;
+  int* s = pr[q].status ? pr[q].status : status;
+  atomicCAS(s, 0, 7);
+}
+
 __global__ void k_jac_extract(const EigProblem* __restrict__ pr) {
   const EigProblem p = pr[blockIdx.y];
   const long np = p.n_pad;
@@ -941,6 +952,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
       if (hipError_t e = hipStreamWaitEvent(st, g.join[k], 0)) return e;
     }
   }
+  k_jac_final<<<(nprob + 63) / 64, 64, 0, st>>>(probs_dev, done, nprob, status);
   k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 4, calls + 1);
   k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev);
   return hipGetLastError();
