@@ -27,7 +27,8 @@ def _ptr(t: Optional[torch.Tensor]):
 class HParams:
     """Hyper-parameters of one step (Section 3.4): damping lambda, EMA beta,
     momentum mu, and the learning rate: a grid line search over 2^k,
-    k = grid_max_exp .. grid_min_exp, or a fixed step."""
+    k = grid_max_exp .. grid_min_exp ("grid"), a fixed step ("fixed"), or KFAC*'s
+    automatic learning rate and momentum ("kfac_star"; mu is then unused)."""
     lam: float = 1e-3
     beta: float = 0.0
     momentum: float = 0.0
@@ -37,8 +38,9 @@ class HParams:
     grid_max_exp: int = 0
 
     def c(self) -> N.kp_hparams:
-        return N.kp_hparams(self.lam, self.beta, self.momentum, 1 if self.lr_mode == "grid" else 0,
-                            self.lr, self.grid_min_exp, self.grid_max_exp)
+        mode = {"fixed": 0, "grid": 1, "kfac_star": 2}[self.lr_mode]
+        return N.kp_hparams(self.lam, self.beta, self.momentum, mode, self.lr, self.grid_min_exp,
+                            self.grid_max_exp)
 
 
 class KfacPinn:
@@ -170,6 +172,18 @@ class KfacPinn:
     def invert(self, lam: float) -> None:
         N.check(self.lib.kfac_pinn_invert(self.h, lam), "kfac_pinn_invert")
 
+    def set_max_sweeps(self, max_sweeps: int) -> None:
+        """Sweep cap of the Jacobi eigensolver (1..64)."""
+        N.check(self.lib.kfac_pinn_set_max_sweeps(self.h, int(max_sweeps)),
+                "kfac_pinn_set_max_sweeps")
+
+    def check_guards(self) -> tuple:
+        """(guard bytes overwritten, guarded buffers); (0, 0) without guards."""
+        bad, n = C.c_int64(), C.c_int64()
+        N.check(self.lib.kfac_pinn_check_guards(self.h, C.byref(bad), C.byref(n)),
+                "kfac_pinn_check_guards")
+        return int(bad.value), int(n.value)
+
     def precondition(self, grad: torch.Tensor) -> torch.Tensor:
         out = self.empty(self.D, dtype=torch.float64)
         N.check(self.lib.kfac_pinn_precondition(self.h, _ptr(grad), _ptr(out)),
@@ -194,7 +208,7 @@ class KfacPinn:
         s = N.kp_step_info.from_buffer_copy(raw)
         return {"loss_interior": s.loss_interior, "loss_boundary": s.loss_boundary,
                 "lr": s.lr_chosen, "loss_after": s.loss_after, "status": s.status,
-                "step": s.step}
+                "step": s.step, "mu": s.momentum_chosen}
 
     def get_factor(self, layer: int, term: int, side: int) -> torch.Tensor:
         n = self.widths[layer] + 1 if side == 0 else self.widths[layer + 1]

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-SOURCES = ["fwdlap.hip", "gemm.hip", "elementwise.hip", "linalg.hip", "api.hip"]
+SOURCES = ["fwdlap.hip", "gemm.hip", "elementwise.hip", "linalg.hip", "kstar.hip", "api.hip"]
 
 
 def _compile(src: str) -> str:

@@ -4,6 +4,7 @@
 // except kfac_pinn_sync.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -94,7 +95,13 @@ struct kfac_pinn_ctx {
   std::vector<long> off, ldz, ldp, ldg;
   long ldz_max = 0, ldp_max = 0;
 
-  std::vector<void*> allocs;
+  // device buffers: the pointer handed out, the allocation it lives in and its size;
+  // with guards (KFAC_PINN_GUARD_KB) the allocation has `guard` pattern bytes on
+  // either side of the buffer
+  struct Alloc { void* user; void* base; size_t bytes; };
+  std::vector<Alloc> allocs;
+  size_t guard = 0;
+  int max_sweeps = kJacobiSweeps;
   uint8_t* mask = nullptr;
   void *w_hi = nullptr, *w_lo = nullptr;
   void* theta_trial = nullptr;
@@ -142,7 +149,12 @@ struct kfac_pinn_ctx {
   size_t w_bytes = 0;                   // product-layout weight copy
   G64* kdesc = nullptr;
   int k_mmax = 0, k_nmax = 0;
-  int* ctl = nullptr;                  // [0] status [1] step [4..5] alpha [8..] Jacobi flags
+  int* ctl = nullptr;                  // [0] status [1] step [4..7] alpha, mu [8..] Jacobi flags
+  // KFAC*: per-point Jacobian-vector products (term, direction, point) and the
+  // per-tile partial sums they are gathered from
+  double* jv = nullptr;
+  long jv_ld = 0;
+  void* jvp_part = nullptr;
   // measurement: launches of one kernel class bracketed by events
   int tm_cls = -1;
   std::vector<hipEvent_t> tm_ev;
@@ -153,14 +165,29 @@ struct kfac_pinn_ctx {
 
 namespace {
 
+constexpr unsigned char kGuardByte = 0xA5;
+
 hipError_t dmalloc(kfac_pinn_ctx* c, void** p, size_t bytes) {
   if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e == hipSuccess) {
-    c->allocs.push_back(*p);
-    e = hipMemset(*p, 0, bytes);
-  }
-  return e;
+  const size_t g = c->guard;
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, bytes + 2 * g);
+  if (e != hipSuccess) return e;
+  *p = (char*)base + g;
+  c->allocs.push_back({*p, base, bytes});
+  if (g > 0 && ((e = hipMemset(base, kGuardByte, g)) != hipSuccess ||
+                (e = hipMemset((char*)*p + bytes, kGuardByte, g)) != hipSuccess))
+    return e;
+  return hipMemset(*p, 0, bytes);
+}
+
+void dfree(kfac_pinn_ctx* c, void* user) {
+  for (size_t i = 0; i < c->allocs.size(); i++)
+    if (c->allocs[i].user == user) {
+      (void)hipFree(c->allocs[i].base);
+      c->allocs.erase(c->allocs.begin() + (long)i);
+      return;
+    }
 }
 
 size_t slab_bytes(const kfac_pinn_ctx* c, const Slabs& s, bool store) {
@@ -630,6 +657,7 @@ const char* kfac_pinn_status_string(kp_status s) {
     case KP_ERR_NOT_PD: return "damped factor not positive definite";
     case KP_ERR_NONFINITE: return "non-finite loss for every step size";
     case KP_ERR_STATE: return "invalid state";
+    case KP_ERR_NOT_CONVERGED: return "eigensolver reached its sweep cap unconverged";
   }
   return "unknown status";
 }
@@ -655,7 +683,7 @@ kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx) {
     }
     if (ctx->eg.fork) (void)hipEventDestroy(ctx->eg.fork);
   }
-  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (const auto& a : ctx->allocs) (void)hipFree(a.base);
   for (hipEvent_t e : ctx->tm_ev) (void)hipEventDestroy(e);
   delete ctx;
   return KP_OK;
@@ -677,6 +705,10 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   KP_ARG(pb->time_coord >= -1 && pb->time_coord < pb->widths[0], "time_coord out of range");
 
   kfac_pinn_ctx* c = new kfac_pinn_ctx();
+  if (const char* gk = getenv("KFAC_PINN_GUARD_KB")) {
+    const long kb = atol(gk);
+    if (kb > 0) c->guard = (size_t)std::min(kb, 1L << 20) * 1024;
+  }
   c->L = pb->n_layers;
   c->w.assign(pb->widths, pb->widths + pb->n_layers + 1);
   c->d = c->w[0];
@@ -828,6 +860,14 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   ALLOC(c->dhat, c->esz_p * c->D);
   ALLOC(c->delta, c->esz_p * c->D);
   ALLOC(c->ctl, sizeof(int) * 128);
+  {
+    c->jv_ld = std::max(1, std::max(c->max_i, c->max_b));
+    ALLOC(c->jv, sizeof(double) * 4 * c->jv_ld);
+    int ntj = 1;
+    for (int l = 0; l < c->L; l++) ntj = std::max(ntj, jvp_tiles(c->w[l + 1]));
+    const size_t Rmax = std::max((size_t)c->max_i * c->si.S, (size_t)c->max_b);
+    ALLOC(c->jvp_part, 2 * (size_t)ntj * std::max(Rmax, (size_t)1) * c->esz_s);
+  }
   ALLOC(c->qbuf, sizeof(double) * (size_t)(c->d + 1) * c->w[1]);
 
   // eigenproblems: layer l side A (h_in+1) and side B (h_out)
@@ -1114,8 +1154,7 @@ static hipError_t ls_lane_free(kfac_pinn_ctx* c) {
   for (int l = 0; l < kMaxLayers; l++) bufs.push_back(x.ls_zb[l]);
   for (void* b : bufs) {
     if (!b) continue;
-    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), b), c->allocs.end());
-    (void)hipFree(b);
+    dfree(c, b);
   }
   hipStream_t st = x.st;
   hipEvent_t f = x.fork, j = x.join;
@@ -1146,13 +1185,38 @@ static void ls_lane_swap(kfac_pinn_ctx* c) {
 static hipError_t eig_all(kfac_pinn_ctx* c, double lambda) {
   if (hipError_t e = side_streams(c)) return e;
   return kron_eig_batched(c->probs.data(), (int)c->probs.size(), lambda, c->probs_dev, c->ctl,
-                          c->ctl + 8, c->ctl + 2, kEigRefresh, kJacobiSweeps, c->eg, c->st);
+                          c->ctl + 8, c->ctl + 2, kEigRefresh, c->max_sweeps, c->eg, c->st);
 }
 
 kp_status kfac_pinn_invert(kfac_pinn_ctx* c, double lambda) {
   KP_ARG(c, "null context");
   KP_ARG(lambda >= 0.0 && isfinite(lambda), "lambda must be finite and >= 0");
   KP_TRY(eig_all(c, lambda));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_set_max_sweeps(kfac_pinn_ctx* c, int32_t max_sweeps) {
+  KP_ARG(c, "null context");
+  KP_ARG(max_sweeps >= 1 && max_sweeps <= 64, "max_sweeps must be in [1, 64]");
+  c->max_sweeps = max_sweeps;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_check_guards(kfac_pinn_ctx* c, int64_t* bad_bytes, int64_t* buffers) {
+  KP_ARG(c && bad_bytes && buffers, "null argument");
+  *bad_bytes = 0;
+  *buffers = 0;
+  if (c->guard == 0) return KP_OK;
+  KP_TRY(hipDeviceSynchronize());
+  std::vector<unsigned char> h(c->guard);
+  for (const auto& a : c->allocs) {
+    const char* regions[2] = {(const char*)a.base, (const char*)a.user + a.bytes};
+    for (const char* r : regions) {
+      KP_TRY(hipMemcpy(h.data(), r, c->guard, hipMemcpyDeviceToHost));
+      for (unsigned char v : h) *bad_bytes += v != kGuardByte;
+    }
+    *buffers += 1;
+  }
   return KP_OK;
 }
 
@@ -1176,7 +1240,9 @@ static kp_status step_head(kfac_pinn_ctx* c, void* theta, const void* xi, const 
   KP_ARG(hp->beta >= 0.0 && hp->beta < 1.0, "beta must be in [0, 1)");
   KP_ARG(hp->lambda >= 0.0 && isfinite(hp->lambda), "lambda must be finite and >= 0");
   KP_ARG(isfinite(hp->momentum), "momentum must be finite");
-  KP_ARG(hp->lr_mode == 0 || hp->lr_mode == 1, "lr_mode must be 0 or 1");
+  KP_ARG(hp->lr_mode >= 0 && hp->lr_mode <= 2, "lr_mode must be 0, 1 or 2");
+  KP_ARG(hp->lr_mode != 2 || c->si.store,
+         "KFAC* (lr_mode 2) needs the stored interior slabs (no workspace limit)");
   if (hp->lr_mode == 1) {
     KP_ARG(hp->grid_max_exp >= hp->grid_min_exp, "empty line-search grid");
     KP_ARG(hp->grid_max_exp - hp->grid_min_exp + 1 <= kMaxCand,
@@ -1191,12 +1257,37 @@ static kp_status step_head(kfac_pinn_ctx* c, void* theta, const void* xi, const 
   return factors_impl(c, theta, xi, yi, ni, xb, yb, nb, hp->beta);
 }
 
+// KFAC* (Section 3.4): the residuals' Jacobian-vector products along Delta and
+// delta_{t-1} from the slabs the curvature pass stored (layer by layer, interior
+// and boundary), then the 2 x 2 quadratic model and the update.
+static kp_status kstar_tail(kfac_pinn_ctx* c, void* theta, int32_t ni, int32_t nb,
+                            const kp_hparams* hp, kp_step_info* info) {
+  const Prec sp = c->sp == P_F64 ? P_F64 : P_F32;   // slab type of the curvature pass
+  for (int term = 0; term < 2; term++) {
+    const Slabs& s = term == 0 ? c->si : c->sb;
+    const int n = term == 0 ? ni : nb;
+    double* jv = c->jv + (long)term * 2 * c->jv_ld;
+    if (n <= 0) continue;
+    for (int l = 0; l < c->L; l++) {
+      const LayerDesc& ld = c->nd.l[l];
+      KP_TRY(jvp_layer(sp, s.zin_at(l), c->ldz[l], s.g_at(l), c->ldg[l], n, s.S, ld.h_in + 1,
+                       ld.h_out, c->Delta + ld.off, wptr(c->delta, ld.off, c->esz_p),
+                       c->jvp_part, jv, c->jv_ld, l > 0 ? 1 : 0, c->st));
+    }
+  }
+  KP_TRY(kstar_finish(c->pp, c->jv, c->jv_ld, ni, c->jv + 2 * c->jv_ld, c->jv_ld, nb, c->Delta,
+                      c->delta, c->grad, c->D, hp->lambda, c->loss, c->ctl, c->ctl + 1, theta,
+                      info, c->st));
+  return KP_OK;
+}
+
 static kp_status step_tail(kfac_pinn_ctx* c, void* theta, const void* xi, const void* yi,
                            int32_t ni, const void* xb, const void* yb, int32_t nb,
                            const kp_hparams* hp, kp_step_info* info) {
   const int ncand = hp->lr_mode == 1 ? hp->grid_max_exp - hp->grid_min_exp + 1 : 0;
   // 4) Delta = -C g, momentum
   KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
+  if (hp->lr_mode == 2) return kstar_tail(c, theta, ni, nb, hp, info);
   KP_TRY(momentum(c->pp, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
   // 5) learning rate and update
   if (hp->lr_mode == 1) {
@@ -1230,7 +1321,7 @@ static kp_status step_tail(kfac_pinn_ctx* c, void* theta, const void* xi, const 
     c->last_ncand = ncand;
   }
   KP_TRY(finish_step(c->pp, c->loss + 2, ncand, hp->grid_max_exp,
-                     hp->lr_mode == 1 ? -1.0 : hp->lr, c->loss, theta, c->dhat, c->delta, c->D,
+                     hp->lr_mode == 1 ? -1.0 : hp->lr, hp->momentum, c->loss, theta, c->dhat, c->delta, c->D,
                      c->ctl, c->ctl + 1, info, c->st));
   return KP_OK;
 }
@@ -1438,9 +1529,11 @@ struct BatchArgs {
 kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a) {
   const int nl = (int)b->lanes.size();
   if (phase == 1) {
+    int cap = 1;
+    for (const kfac_pinn_ctx* c : b->ctx) cap = std::max(cap, c->max_sweeps);
     KP_TRY(kron_eig_batched(b->probs.data(), (int)b->probs.size(), a.hp->lambda, b->probs_dev,
-                            b->ctx[0]->ctl, b->eig_ctl + 2, b->eig_ctl, kEigRefresh,
-                            kJacobiSweeps, b->eg, b->lanes[0]));
+                            b->ctx[0]->ctl, b->eig_ctl + 2, b->eig_ctl, kEigRefresh, cap, b->eg,
+                            b->lanes[0]));
     return KP_OK;
   }
   for (size_t k = l; k < b->ctx.size(); k += nl) {

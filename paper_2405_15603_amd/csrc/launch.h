@@ -86,8 +86,29 @@ hipError_t momentum(Prec p, const double* Delta, const void* delta, double mu, c
 // alpha* from candidate losses; then theta += alpha*dhat, delta = alpha*dhat;
 // writes info and status.  fixed_lr >= 0 -> fixed mode.
 hipError_t finish_step(Prec p, const double* losses, int ncand, int kmax, double fixed_lr,
-                       const double* base_loss, void* theta, void* dhat, void* delta, long D,
-                       int* status, int* step, void* info, hipStream_t st);
+                       double mu, const double* base_loss, void* theta, void* dhat, void* delta,
+                       long D, int* status, int* step, void* info, hipStream_t st);
+
+// ---- KFAC* (automatic learning rate and momentum) ---------------------------
+// Per-point Jacobian-vector products of the residuals along two directions from
+// one layer's stored slabs: jv[dir * ldjv + n] (+)= sum_s g_{n,s}^T D_dir z~_{n,s}
+// (dir 0: d0, double; dir 1: d1, the parameter type; both at the layer's offset
+// in the theta layout, column-major H x K).  zin: n*S rows of ldz, g: n*S rows of
+// ldg (slab type: double for P_F64, float for P_F32).  part: 2 * jvp_tiles(H) *
+// n * S slab-type elements of scratch.
+int jvp_tiles(int h_out);
+hipError_t jvp_layer(Prec p, const void* zin, long ldz, const void* g, long ldg, int n, int S,
+                     int K, int H, const double* d0, const void* d1, void* part, double* jv,
+                     long ldjv, int accumulate, hipStream_t st);
+// The 2 x 2 quadratic model from the products (interior jvi, boundary jvb, two
+// rows each of ldi / ldb), Delta, delta_{t-1} (parameter type), the gradient and
+// lambda; then delta = alpha Delta + mu delta_{t-1}, theta += delta (skipped when
+// the status is set).  Writes alpha and mu into the two doubles after the status
+// word and the step summary into info (may be null).
+hipError_t kstar_finish(Prec p, const double* jvi, long ldi, int N, const double* jvb, long ldb,
+                        int M, const double* Delta, void* delta, const double* grad, long D,
+                        double lambda, const double* base_loss, int* status, int* step,
+                        void* theta, void* info, hipStream_t st);
 
 // ---- sampler ----------------------------------------------------------------
 struct SamplerDesc {
