@@ -8,8 +8,11 @@ backward pass, Kronecker factors with EMA, damped Kronecker-sum inverse,
 preconditioned direction with momentum, grid line search over 31 step sizes and
 the update.  The headline runs the mixed-precision path (BF16 MFMA, FP32
 accumulation, FP64 factors and inversion); the plain FP32 path and the core
-step (fixed step size, no line search) are timed beside it.  Inputs are resident
-in HBM before the timed region.
+step (fixed step size, no line search) and KFAC* (learning rate and momentum
+from the quadratic model, Section 3.4) are timed beside it.  Inputs are resident
+in HBM before the timed region.  The headline times --repeats regions of exactly
+--steps steps each (after --warmup untimed steps) and reports their median; all
+of them are listed under last_step.
 
 The roofline object describes the dominant kernel, the line-search layer
 product (k_fwdlap in BF16): algorithmic FLOPs of its launches over their
@@ -50,7 +53,8 @@ def hparams(lr_mode="grid", lr=1.0):
     return HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode=lr_mode, lr=lr)
 
 
-def run_gpu(problem, precision, steps, warmup, kernel_class=None, lr_mode="grid", ls_lanes=2):
+def run_gpu(problem, precision, steps, warmup, kernel_class=None, lr_mode="grid", ls_lanes=2,
+            repeats=1):
     import numpy as np
     import torch
     from paper_2405_15603_amd import KfacPinn
@@ -68,20 +72,25 @@ def run_gpu(problem, precision, steps, warmup, kernel_class=None, lr_mode="grid"
     torch.cuda.synchronize()
     if kernel_class is not None:
         kp.timing_enable(kernel_class)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(steps):
-        kp.step(th, xi, yi, xb, yb, hp, info)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
+    # `repeats` timed regions of exactly `steps` steps each, back to back
+    runs = []
+    for _ in range(repeats):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            kp.step(th, xi, yi, xb, yb, hp, info)
+        t1.record()
+        torch.cuda.synchronize()
+        runs.append(t0.elapsed_time(t1) / steps)
+    ms = sorted(runs)[len(runs) // 2]
     tm = kp.timing_read() if kernel_class is not None else None
     sweeps = kp.get_sweeps()
     status = kp.sync()
     last = KfacPinn.decode_info(info)
     last["jacobi_sweeps"] = sweeps
+    last["repeats_ms_per_step"] = runs
     del kp
     return ms, tm, status, last
 
@@ -143,37 +152,74 @@ def measured_traffic():
     return float(t.group(1)) if cur == m.group(1) else None
 
 
-def cpu_baseline(problem, frac=0.1):
-    """The FP64 oracle's step on a bounded sample of the same workload (same
-    network, a fraction of the points), extrapolated to the full point count:
-    the per-point work scales with the number of points, the Kronecker-sum
-    inverse does not and is timed on its own."""
+def blas_info():
+    import torch
+    cfg = torch.__config__.show()
+    blas = [l.strip() for l in cfg.splitlines() if "BLAS" in l or "LAPACK" in l]
+    return "; ".join(blas) or "unknown"
+
+
+def cpu_baseline(problem):
+    """The FP64 oracle (plain PyTorch on the host cores) for one step of the same
+    workload, timed in three parts whose cost is known to scale: the curvature part
+    (forward Laplacian, autodiff backward, factors, gradient) on a 10 % sample of
+    the points, scaled by 10 (every point's work is the same); the Kronecker-sum
+    inverse of the resulting factors at full size (it does not depend on the point
+    count); and one full-size line-search candidate loss, times the 31 candidates.
+    The sum is the step time, extrapolated from those measurements.  Timed with all
+    the host cores this process may use, and with one thread on smaller samples."""
     import torch
     import oracle
-    ns = max(1, int(problem.n_interior * frac))
-    ms = max(1, int(problem.n_cond * frac))
-    xi, yi, xb, yb = problem.batch(0)
-    data = (xi[:ns], yi[:ns], xb[:ms], yb[:ms])
     op = oracle.operator_of(problem)
     h = hparams()
-    hp = oracle.HParams(lam=h.lam, beta=h.beta, momentum=h.momentum, lr_mode="grid")
-    st = oracle.init_state(problem.widths, True)
+    hp = oracle.HParams(lam=h.lam, beta=h.beta, momentum=h.momentum, lr_mode="fixed", lr=0.0)
     th = problem.theta0()
-    t0 = time.perf_counter()
-    _, st1, _ = oracle.kfac_step(th, problem.widths, data, op, hp, st)
-    t_sample = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for l in range(len(problem.widths) - 1):
-        oracle.kron_sum_inverse(*(oracle.damp(m[l], hp.lam)
-                                  for m in (st1.A_int, st1.B_int, st1.A_bnd, st1.B_bnd)))
-    t_inv = time.perf_counter() - t0
-    t_full = t_inv + max(t_sample - t_inv, 0.0) / frac
-    return {"value": 1.0 / t_full, "unit": "steps/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": (f"oracle step on {ns} of {problem.n_interior} interior and {ms} of "
-                       f"{problem.n_cond} boundary points with the full network "
-                       f"({t_sample:.1f} s, of which Kronecker-sum inverse {t_inv:.2f} s); "
-                       f"per-point work scaled by {1 / frac:.0f}")}
+    xi, yi, xb, yb = problem.batch(0)
+    widths = problem.widths
+
+    def leg(frac_curv, frac_loss):
+        ns, ms = max(1, int(problem.n_interior * frac_curv)), max(1, int(problem.n_cond * frac_curv))
+        st = oracle.init_state(widths, True)
+        t0 = time.perf_counter()
+        _, st1, info = oracle.kfac_step(th, widths, (xi[:ns], yi[:ns], xb[:ms], yb[:ms]), op, hp, st)
+        t_step = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for l in range(len(widths) - 1):
+            oracle.kron_sum_inverse(*(oracle.damp(m[l], hp.lam)
+                                      for m in (st1.A_int, st1.B_int, st1.A_bnd, st1.B_bnd)))
+        t_inv = time.perf_counter() - t0
+        # kfac_step with a fixed step evaluates the loss once at the end: the part that
+        # scales with the points is the step minus that loss and minus the inverse
+        nl, ml = max(1, int(problem.n_interior * frac_loss)), max(1, int(problem.n_cond * frac_loss))
+        t0 = time.perf_counter()
+        oracle.loss(th, widths, xi[:nl], yi[:nl], xb[:ml], yb[:ml], op)
+        t_loss = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.loss(th, widths, xi[:ns], yi[:ns], xb[:ms], yb[:ms], op)
+        t_loss_sample = time.perf_counter() - t0
+        t_curv = max(t_step - t_inv - t_loss_sample, 0.0)
+        total = t_curv / frac_curv + t_inv + 31 * t_loss / frac_loss
+        return total, {"curvature_sample_s": t_curv, "curvature_points": [ns, ms],
+                       "inverse_s": t_inv, "loss_s": t_loss, "loss_points": [nl, ml]}
+
+    cores = len(os.sched_getaffinity(0))
+    prev = torch.get_num_threads()
+    torch.set_num_threads(cores)
+    t_all, parts_all = leg(0.1, 1.0)
+    torch.set_num_threads(1)
+    t_one, parts_one = leg(0.01, 0.1)
+    torch.set_num_threads(prev)
+    return {"value": 1.0 / t_all, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle, {cores} threads: curvature part on {parts_all['curvature_points']} "
+                       f"interior/boundary points ({parts_all['curvature_sample_s']:.1f} s, x10), "
+                       f"full-size Kronecker-sum inverse ({parts_all['inverse_s']:.2f} s), one "
+                       f"full-size candidate loss ({parts_all['loss_s']:.1f} s, x31): "
+                       f"{t_all:.0f} s per step, extrapolated from these measurements"),
+            "one_thread": {"value": 1.0 / t_one, "seconds_per_step": t_one, "parts": parts_one,
+                           "note": "1 thread; curvature on 1 % of the points (x100), candidate "
+                                   "loss on 10 % (x10, x31)"},
+            "seconds_per_step": t_all, "parts": parts_all, "blas": blas_info(),
+            "threads": cores}
 
 
 def main():
@@ -190,6 +236,9 @@ def main():
     ap.add_argument("--kernel", default="ls_layer", choices=list(KERNEL_CLASSES))
     ap.add_argument("--ls-lanes", type=int, default=2, choices=[1, 2],
                     help="streams for the line-search candidates in the timed run")
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed regions of --steps steps each; the headline is their median")
+    ap.add_argument("--no-kfac-star", action="store_true", help="skip the KFAC* leg")
     ap.add_argument("--roofline-steps", type=int, default=20,
                     help="steps of the one-lane run that times the dominant kernel's launches")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -210,7 +259,7 @@ def main():
     # launch has the chip to itself (with two lanes a launch's events also span the
     # other lane's work).
     ms, _, status, last = run_gpu(problem, args.precision, args.steps, args.warmup, None,
-                                  ls_lanes=args.ls_lanes)
+                                  ls_lanes=args.ls_lanes, repeats=args.repeats)
     if status != 0:
         print(f"device status {status} after the timed steps", file=sys.stderr)
         sys.exit(1)
@@ -260,6 +309,14 @@ def main():
         msc, _, stc, _ = run_gpu(problem, args.precision, side_steps, 1, None, lr_mode="fixed")
         out["core_step"] = {"value": 1000.0 / msc, "ms_per_step": msc, "status": stc,
                             "note": "fixed step size 2^-5, no line search"}
+    if not args.no_kfac_star:
+        msk, _, stk, lastk = run_gpu(problem, args.precision, side_steps, 2, None,
+                                     lr_mode="kfac_star")
+        out["kfac_star"] = {"value": 1000.0 / msk, "ms_per_step": msk, "status": stk,
+                            "last_step": {k: lastk[k] for k in ("lr", "mu", "step", "status")},
+                            "note": "KFAC*: learning rate and momentum from the 2 x 2 quadratic "
+                                    "model with the exact damped Gramian (Section 3.4), no line "
+                                    "search"}
     if not args.no_fp32 and args.precision != "f32":
         ms32, _, st32, _ = run_gpu(problem, "f32", side_steps, 1, None)
         out["fp32"] = {"value": 1000.0 / ms32, "ms_per_step": ms32, "status": st32,

@@ -79,27 +79,40 @@ TANH = Activation("tanh")
 
 @dataclass(frozen=True)
 class Operator:
-    """Interior operator  c_t d/dx_t + c_lap sum_{i in mask} d^2/dx_i^2.
+    """Interior operator  c_t d/dx_t + c_lap sum_{i,j} C_ij d^2/dx_i dx_j.
 
-    Poisson (Section 2.1 writes -Lap u = f): c_t = 0, c_lap = -1.
+    C = diag(mask) unless a coefficient matrix is given (Section 3.1, closing
+    paragraph; Appendix C.3: a weighted sum of second derivatives).
+    Poisson (Section 2.1 writes -Lap u = f): c_t = 0, c_lap = -1, C = I.
     Heat (Appendix A, x_1 = t): c_t = 1, c_lap = -kappa, mask excludes t."""
     time_coord: int = -1
     coef_time: float = 0.0
     coef_lap: float = -1.0
     mask: Optional[Sequence[int]] = None
+    coef: Optional[Sequence[Sequence[float]]] = None   # C, d x d symmetric
 
     def mask_vec(self, d: int) -> torch.Tensor:
         if self.mask is None:
             return torch.ones(d, dtype=DT)
         return torch.as_tensor(np.asarray(self.mask, dtype=np.float64))
 
+    def second_order(self, d: int) -> torch.Tensor:
+        """What the forward pass sums over: the mask vector (a diagonal C) or the
+        coefficient matrix C."""
+        if self.coef is None:
+            return self.mask_vec(d)
+        return torch.as_tensor(np.asarray(self.coef, dtype=np.float64))
+
 
 POISSON_OP = Operator()
 
 
 def operator_of(problem) -> Operator:
+    coef = getattr(problem, "op_coef", None)
+    if coef is not None:
+        coef = tuple(tuple(float(v) for v in row) for row in np.asarray(coef))
     return Operator(problem.time_coord, problem.coef_time, problem.coef_lap,
-                    tuple(int(v) for v in problem.lap_mask))
+                    tuple(int(v) for v in problem.lap_mask), coef)
 
 
 # ----------------------------------------------------------------------------
@@ -157,12 +170,18 @@ def augment(Z: torch.Tensor) -> torch.Tensor:
 def activation_rows(a: torch.Tensor, mask: torch.Tensor, act: Activation) -> torch.Tensor:
     """Elementwise layer on the stacked rows (Eq. forward-laplacian-main, second line,
     restricted to the coordinates in `mask` for a partial Laplacian):
-        v = s(a0),  d_i v = s'(a0) d_i a,  Lv = s'(a0) La + s''(a0) sum_{i in M} (d_i a)^2."""
+        v = s(a0),  d_i v = s'(a0) d_i a,  Lv = s'(a0) La + s''(a0) sum_{i in M} (d_i a)^2.
+    With a coefficient matrix C in place of the mask (Appendix C.3), the collapsed
+    second-order row is  s'(a0) La + s''(a0) sum_{i,j} C_ij d_i a d_j a."""
     a0, da, la = a[:, 0, :], a[:, 1:-1, :], a[:, -1, :]
     v = act.f(a0)
     s1, s2 = act.d1(a0), act.d2(a0)
     dv = s1[:, None, :] * da
-    lv = s1 * la + s2 * (mask[None, :, None] * da * da).sum(1)
+    if mask.dim() == 2:
+        quad = torch.einsum("ij,nik,njk->nk", mask, da, da)
+    else:
+        quad = (mask[None, :, None] * da * da).sum(1)
+    lv = s1 * la + s2 * quad
     return torch.cat([v[:, None, :], dv, lv[:, None, :]], 1)
 
 
@@ -235,7 +254,7 @@ def loss(theta, widths, Xi, yi, Xb, yb, op: Operator = POISSON_OP, act: Activati
     with torch.no_grad():
         Ws = unpack(_t(theta), widths)
         Xi, yi, Xb, yb = map(_t, (Xi, yi, Xb, yb))
-        fi = forward_laplacian(Ws, Xi, op.mask_vec(Xi.shape[1]), act)
+        fi = forward_laplacian(Ws, Xi, op.second_order(Xi.shape[1]), act)
         fb = forward_plain(Ws, Xb, act)
         li, lb = loss_terms(interior_residual(fi.out, yi, op), boundary_residual(fb.out, yb))
     return float(li + lb), float(li), float(lb)
@@ -266,7 +285,7 @@ def interior_curvature_inputs(Ws, Xi, yi, op: Operator, act: Activation = TANH) 
         zin.append(Zt.detach())
         pre.append(a)
         if l < len(Ws) - 1:
-            Z = activation_rows(a, op.mask_vec(Xi.shape[1]), act)
+            Z = activation_rows(a, op.second_order(Xi.shape[1]), act)
     r = interior_residual(pre[-1][:, :, 0], yi, op)
     g = torch.autograd.grad(r.sum(), pre, allow_unused=True)
     g = [gi if gi is not None else torch.zeros_like(p) for gi, p in zip(g, pre)]
@@ -320,7 +339,7 @@ def loss_gradient(theta, widths, Xi, yi, Xb, yb, op: Operator = POISSON_OP,
     th = _t(theta).detach().clone().requires_grad_(True)
     Ws = unpack(th, widths)
     Xi, yi, Xb, yb = map(_t, (Xi, yi, Xb, yb))
-    fi = forward_laplacian(Ws, Xi, op.mask_vec(Xi.shape[1]), act)
+    fi = forward_laplacian(Ws, Xi, op.second_order(Xi.shape[1]), act)
     fb = forward_plain(Ws, Xb, act)
     li, lb = loss_terms(interior_residual(fi.out, yi, op), boundary_residual(fb.out, yb))
     (gr,) = torch.autograd.grad(li + lb, th)

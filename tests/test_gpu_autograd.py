@@ -60,7 +60,8 @@ def test_autograd_function_matches_oracle_autodiff(precision, tol):
 def test_autograd_function_against_finite_differences():
     """FP64: the adjoint's directional derivatives along 16 random unit directions
     (seed 4004) against central differences with h = 1e-4 of the GPU forward.  The
-    FD truncation error is O(h^2 |f'''|) ~ 1e-8 relative; the bound is 1e-6."""
+    FD truncation error is O(h^2 |f'''|) ~ 1e-8 relative (measured 3e-9); the bound
+    is 1e-7."""
     from paper_2405_15603_amd import forward_laplacian
     p = synth.heat4d()
     th, xi, _, _, _ = problem_inputs(p, "f64", 400, 10)
@@ -90,7 +91,7 @@ def test_autograd_function_against_finite_differences():
         err = abs(fd - ad) / max(abs(ad), 1e-12 * float(grad.norm()))
         worst = max(worst, err)
     print(f"worst directional-derivative relative error {worst:.2e}")
-    assert worst < 1e-6
+    assert worst < 1e-7
 
 
 def test_workspace_limit_recompute_matches_store():

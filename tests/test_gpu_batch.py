@@ -95,3 +95,61 @@ def test_batch_graph_recaptures_on_new_arguments():
         assert torch.equal(th_b[k], th), k
         assert ref.sync() == 0
         del ref
+
+
+def test_batch_instances_against_oracle():
+    """Four instances of the 64-instance recipe (d = 20 at widths 256, 64 and 128,
+    and a d = 2 one) stepped as a batch in mixed precision, one step from identity
+    factors with beta = 0, so the factors after the step are the step's own.  Each
+    instance's factors must be within the 1e-3 gate of the oracle's at the same
+    parameters and points, and its candidate losses and chosen step must pass the
+    BF16 line-search check (helpers.check_bf16_candidates)."""
+    from paper_2405_15603_amd import HParams, KfacPinnBatch
+    import oracle
+    from helpers import check_bf16_candidates, oracle_curvature, rel
+    dev = torch.device("cuda", 0)
+    allp = synth.batch_instances(64)
+    pick = [0, 28, 36, 15]
+    probs = [allp[k] for k in pick]
+    assert {p.d for p in probs} >= {20, 2} and 256 in {p.widths[1] for p in probs}
+    hp = HParams(lam=1e-3, beta=0.0, momentum=0.0, lr_mode="grid")
+    b = KfacPinnBatch(probs, "bf16")
+    data = [inputs(p, dev) for p in probs]
+    thetas = [d[0] for d in data]
+    th0 = [t.cpu().double().numpy().copy() for t in thetas]
+    cols = list(zip(*[d[1] for d in data]))
+    infos = torch.zeros(len(probs) * C.sizeof(N_info()), dtype=torch.uint8, device=dev)
+    b.step(thetas, *cols, hp, infos)
+    torch.cuda.synchronize()
+    assert b.sync() == [0] * len(probs)
+    raw = infos.cpu().numpy().tobytes()
+    sz = C.sizeof(N_info())
+    for k, p in enumerate(probs):
+        kp = b.contexts[k]
+        xi, yi, xb, yb = (np.asarray(a.cpu().double()) for a in data[k][1])
+        ref = oracle_curvature(p, th0[k], xi, yi, xb, yb)
+        # an instance's context runs on its lane: wait for it after each copy
+        def fetch(t):
+            assert kp.sync() == 0
+            return t.cpu().double().numpy()
+        worst = 0.0
+        for l in range(len(p.widths) - 1):
+            for t, tn in ((0, "int"), (1, "bnd")):
+                for s, sn in ((0, "A"), (1, "B")):
+                    worst = max(worst, rel(fetch(kp.get_factor(l, t, s)), ref[f"{sn}_{tn}"][l]))
+        s = N_info().from_buffer_copy(raw[k * sz:(k + 1) * sz])
+        alpha = s.lr_chosen
+        dhat = fetch(kp.get_momentum()) / alpha
+        ls = fetch(kp.get_line_search(31))
+        op = oracle.operator_of(p)
+        cand = np.array([oracle.loss(th0[k] + 2.0 ** -j * dhat, p.widths, xi, yi, xb, yb, op)[0]
+                         for j in range(31)])
+        res = check_bf16_candidates(ls, cand, alpha)
+        print(f"instance {pick[k]} {p.widths} N={p.n_interior}: worst factor {worst:.2e}, "
+              f"alpha* {alpha:g}, candidates {res}")
+        assert worst < 1e-3
+
+
+def N_info():
+    from paper_2405_15603_amd import _native as N
+    return N.kp_step_info

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import synth
-from helpers import oracle_curvature, problem_inputs, rel, rounded, to_dev
+from helpers import blockwise, oracle_curvature, problem_inputs, rel, rounded, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,10 @@ def test_forward_laplacian(case, precision, tol):
     op = oracle.operator_of(p)
     U = oracle.forward_laplacian(oracle.unpack(torch.as_tensor(th), p.widths), torch.as_tensor(xi),
                                  op.mask_vec(p.d)).out
-    assert rel(u, U[:, 0]) < tol
-    assert rel(g, U[:, 1:p.d + 1]) < tol
-    assert rel(lap, U[:, -1]) < tol
+    for got, want in ((u, U[:, 0]), (g, U[:, 1:p.d + 1]), (lap, U[:, -1])):
+        assert rel(got, want) < tol
+        # elementwise companion: worst block of 64 points, 10x the norm-wise bound
+        assert blockwise(got, want) < 10 * tol
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -55,8 +56,9 @@ def test_factors_gradient_loss(case, precision, tol, gtol):
     for l in range(len(p.widths) - 1):
         for t, tn in ((0, "int"), (1, "bnd")):
             for s, sn in ((0, "A"), (1, "B")):
-                e = rel(kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l])
-                assert e < tol, (l, tn, sn, e)
+                got, want = kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l]
+                e, eb = rel(got, want), blockwise(got, want)
+                assert e < tol and eb < 10 * tol, (l, tn, sn, e, eb)
     assert rel(grad, ref["grad"]) < gtol
     assert rel(loss, np.array(ref["loss"])) < gtol
 
@@ -177,12 +179,29 @@ def test_full_step_f64(case):
         assert rel(tht, ref) < 1e-10
         assert abs(d["loss_interior"] - rinfo.loss_interior) <= 1e-10 * abs(rinfo.loss_interior)
         if hp_o.lr_mode == "grid":
-            # candidate k evaluates L(theta + 2^-k dhat): the 1e-10 error of dhat is
-            # amplified by 2^-k |grad L| there (losses reach 1e13 at k = 0), so each
-            # candidate is compared at 1e-8 relative; theta_1 and alpha* above are binding
-            ls = kp.get_line_search(31).cpu().numpy()
-            ref_ls = np.array(rinfo.candidate_losses)
-            assert np.all(np.abs(ls - ref_ls) <= 1e-8 * np.abs(ref_ls))
+            check_candidates(kp, p, th, (xi, yi, xb, yb), d["lr"], rinfo)
+
+
+def check_candidates(kp, p, th, data, alpha, rinfo):
+    """Candidate k is L(theta + 2^-k dhat).  dhat is a result of the step and must
+    match the oracle's to 1e-10, and so must every candidate within 10x of the
+    best loss (the ones the argmin decides between).  Steps far too large push the
+    weights into saturating tanh units, where s1 = 1 - t^2 cancels and the loss is
+    ill-conditioned in FP64 itself (errors of ~1e-10 there come from the
+    evaluation, not from dhat: they exceed dhat's error times the loss's
+    sensitivity to it by orders of magnitude); those candidates are held to 1e-8."""
+    dhat = kp.get_momentum().cpu().numpy() / alpha
+    dref = rinfo.update.numpy() / rinfo.lr
+    e = rel(dhat, dref)
+    assert e < 1e-10, e
+    ls = kp.get_line_search(31).cpu().numpy()
+    ref_ls = np.array(rinfo.candidate_losses)
+    err = np.abs(ls - ref_ls) / np.abs(ref_ls)
+    near = ref_ls <= 10 * ref_ls.min()
+    print(f"dhat rel err {e:.2e}; {int(near.sum())} near candidates, worst {err[near].max():.2e}; "
+          f"others worst {err[~near].max() if (~near).any() else 0.0:.2e}")
+    assert np.all(err[near] < 1e-10), err
+    assert np.all(err < 1e-8), err
 
 
 def test_sampler_matches_seeded_generator():

@@ -174,3 +174,22 @@ def test_parameter_counts_printed_in_paper(widths, D):
     assert oracle.num_params(widths) == D == synth.num_params(widths)
     th = torch.arange(D, dtype=DT)
     torch.testing.assert_close(oracle.pack(oracle.unpack(th, widths)), th)
+
+
+def test_chunked_factor_assembly_equals_direct():
+    """The test helper that assembles the oracle's factors over chunks of points
+    (used at full workload sizes) reproduces the direct computation."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import oracle_curvature, oracle_factors_chunked, oracle_forward_chunked
+    p = synth.small_problem("heat", (3, 9, 7, 1), 53, 17, n_init=5, problem_id=91)
+    th = p.theta0()
+    xi, yi, xb, yb = p.batch()
+    direct = oracle_curvature(p, th, xi, yi, xb, yb)
+    chunked = oracle_factors_chunked(p, th, xi, yi, xb, yb, chunk=10)
+    for k in ("A_int", "B_int", "A_bnd", "B_bnd"):
+        for a, b in zip(chunked[k], direct[k]):
+            torch.testing.assert_close(a, b, rtol=1e-13, atol=1e-15)
+    U = oracle.forward_laplacian(oracle.unpack(torch.as_tensor(th), p.widths), torch.as_tensor(xi),
+                                 oracle.operator_of(p).mask_vec(p.d)).out
+    torch.testing.assert_close(oracle_forward_chunked(p, th, xi, chunk=8), U, rtol=1e-14, atol=0)

@@ -107,3 +107,51 @@ def test_kfac_descends_on_poisson2d_subset():
     for _ in range(5):
         th, st, info = oracle.kfac_step(th, widths, data, op, hp, st)
     assert info.loss_after < 0.5 * l0
+
+
+@pytest.mark.parametrize("lam", [1e-3, 0.5, 7.0])
+def test_damping_closed_forms(lam):
+    """Damping adds lambda to each of the four factors (Section 3.4), not to their
+    Kronecker sum.  With all four factors zero the damped sum is 2 lambda^2 I, so the
+    direction is -g / (2 lambda^2); with scaled identities a_k I, b_k I it is
+    (a1+lam)(b1+lam) + (a2+lam)(b2+lam) times I.  Adding lambda to the sum instead
+    would give -g / lambda, and damping one term only -g / lambda^2."""
+    g = torch.Generator().manual_seed(11)
+    V = torch.randn(4, 6, generator=g, dtype=DT)
+    Z6, Z4 = torch.zeros(6, 6, dtype=DT), torch.zeros(4, 4, dtype=DT)
+    inv = oracle.kron_sum_inverse(oracle.damp(Z6, lam), oracle.damp(Z4, lam),
+                                  oracle.damp(Z6, lam), oracle.damp(Z4, lam))
+    torch.testing.assert_close(inv.apply(V), V / (2 * lam * lam), rtol=1e-13, atol=0)
+    a1, b1, a2, b2 = 0.3, 2.0, 1.5, 0.25
+    I6, I4 = torch.eye(6, dtype=DT), torch.eye(4, dtype=DT)
+    inv = oracle.kron_sum_inverse(oracle.damp(a1 * I6, lam), oracle.damp(b1 * I4, lam),
+                                  oracle.damp(a2 * I6, lam), oracle.damp(b2 * I4, lam))
+    c = (a1 + lam) * (b1 + lam) + (a2 + lam) * (b2 + lam)
+    torch.testing.assert_close(inv.apply(V), V / c, rtol=1e-13, atol=0)
+
+
+def zero_output_problem(kind="poisson"):
+    """A net whose output layer is zero, with zero targets: u = 0 everywhere, every
+    residual and the whole gradient vanish exactly, so Delta = 0 and every
+    line-search candidate has the same loss (0)."""
+    p = synth.small_problem(kind, (3, 7, 5, 1), 13, 6, n_init=3 if kind == "heat" else 0,
+                            problem_id=79)
+    th = p.theta0().copy()
+    off = synth.layer_offsets(p.widths)
+    th[off[-2]:off[-1]] = 0.0
+    xi, yi, xb, yb = p.batch()
+    return p, th, (xi, 0.0 * yi, xb, 0.0 * yb)
+
+
+@pytest.mark.parametrize("kind", ["poisson", "heat"])
+def test_line_search_ties_go_to_the_largest_step(kind):
+    """Reading G7: scanning from the largest step, the first strict minimum wins.
+    With Delta = 0 all 31 candidate losses are equal, so alpha* must be 2^0 (a scan
+    that kept the last minimum would return 2^-30)."""
+    p, th, data = zero_output_problem(kind)
+    op = oracle.operator_of(p)
+    hp = oracle.HParams(lam=1e-3, beta=0.0, lr_mode="grid")
+    th1, st1, info = oracle.kfac_step(th, p.widths, data, op, hp, oracle.init_state(p.widths, True))
+    assert float(info.gradient.abs().max()) == 0.0
+    assert len(set(info.candidate_losses)) == 1 and info.candidate_losses[0] == 0.0
+    assert info.lr == 1.0 and info.status == 0
