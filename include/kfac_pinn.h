@@ -210,6 +210,26 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* ctx, const void* theta,
  * problem still rotated in its last allowed sweep. */
 kp_status kfac_pinn_invert(kfac_pinn_ctx* ctx, double lambda);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the apply of
+ * kfac_pinn_precondition for ONE layer, Delta = -(A_i (x) B_i + A_b (x) B_b)^-1 g,
+ * with that layer's factorisation passed in (as kfac_pinn_get_preconditioner
+ * returns it) and no context.  nA = h_in + 1, nB = h_out; PA (nA x nA, row-major),
+ * a (nA), PB (nB x nB), b (nB); grad and delta_out: the layer's block of the theta
+ * layout (column-major nB x nA); all device doubles owned by the caller; `stream`
+ * a hipStream_t (NULL = default stream).  Nothing is allocated: the two
+ * intermediate nB x nA products live in a static device array of the library,
+ * 2 x 1048576 doubles (16 MiB) per GPU, held until the process ends, and the
+ * product descriptors are kernel arguments.  Every call on a GPU shares that
+ * array, so calls that overlap on one GPU (other streams, other threads) race;
+ * nothing in it needs to start at zero.  Results equal kfac_pinn_precondition's
+ * for that layer (same kernels).  Errors: KP_ERR_ARG for null pointers,
+ * non-positive sizes or nA * nB > 1048576; KP_ERR_HIP. */
+kp_status kfac_pinn_precondition_layer_noalloc(int32_t nA, int32_t nB, const double* PA,
+                                               const double* a, const double* PB,
+                                               const double* b, const double* grad,
+                                               double* delta_out, void* stream);
+
 /* Sweep cap of the Jacobi eigensolver (1 .. 64; default 20).  Every call enqueues
  * the launches of max_sweeps sweeps; a converged problem's launches return at
  * once.  Errors: KP_ERR_ARG outside the range. */

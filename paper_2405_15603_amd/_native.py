@@ -56,6 +56,8 @@ _SIGS = {
                                     _V, _V]),
     "kfac_pinn_invert": (C.c_int, [_V, C.c_double]),
     "kfac_pinn_precondition": (C.c_int, [_V, _V, _V]),
+    "kfac_pinn_precondition_layer_noalloc": (C.c_int, [C.c_int32, C.c_int32, _V, _V, _V, _V, _V,
+                                                       _V, _V]),
     "kfac_pinn_set_max_sweeps": (C.c_int, [_V, C.c_int32]),
     "kfac_pinn_check_guards": (C.c_int, [_V, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kfac_pinn_step": (C.c_int, [_V, _V, _V, _V, C.c_int32, _V, _V, C.c_int32,

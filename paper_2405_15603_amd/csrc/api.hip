@@ -1195,6 +1195,24 @@ kp_status kfac_pinn_invert(kfac_pinn_ctx* c, double lambda) {
   return KP_OK;
 }
 
+kp_status kfac_pinn_precondition_layer_noalloc(int32_t nA, int32_t nB, const double* PA,
+                                               const double* a, const double* PB, const double* b,
+                                               const double* grad, double* delta, void* stream) {
+  KP_ARG(PA && a && PB && b && grad && delta, "null argument");
+  KP_ARG(nA >= 1 && nB >= 1, "nA and nB must be positive");
+  KP_ARG((long)nA * nB <= kKronScratchElems,
+         "nA * nB exceeds the static scratch (1048576 elements per product)");
+  KronApply k{};
+  k.nA = nA;
+  k.nB = nB;
+  k.PA = PA;
+  k.a = a;
+  k.PB = PB;
+  k.b = b;
+  KP_TRY(kron_apply_noalloc(k, grad, delta, (hipStream_t)stream));
+  return KP_OK;
+}
+
 kp_status kfac_pinn_set_max_sweeps(kfac_pinn_ctx* c, int32_t max_sweeps) {
   KP_ARG(c, "null context");
   KP_ARG(max_sweeps >= 1 && max_sweeps <= 64, "max_sweeps must be in [1, 64]");

@@ -192,5 +192,12 @@ struct G64 {                // C[i*sci + j*scj] = alpha sum_k A(i,k) B(k,j) [/(1
 void kron_apply_descs(const KronApply* layers, int L, const double* grad, double* delta,
                       double* tmp, long tmp_stride, G64* h, int* mmax, int* nmax);
 hipError_t kron_apply_batched(const G64* descs_dev, int L, int mmax, int nmax, hipStream_t st);
+// The same for one layer (layer.off ignored: grad and delta point at the layer's
+// block) with its two intermediate products in a static device array of
+// 2 * kKronScratchElems doubles and the descriptors as kernel arguments: nothing
+// is allocated.  hipErrorInvalidValue when nA * nB > kKronScratchElems.
+constexpr long kKronScratchElems = 1L << 20;
+hipError_t kron_apply_noalloc(const KronApply& layer, const double* grad, double* delta,
+                              hipStream_t st);
 
 }  // namespace kp

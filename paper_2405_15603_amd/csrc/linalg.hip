@@ -23,6 +23,7 @@
 // (grid.y = problem).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -962,8 +963,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
 // Kronecker-sum apply (per layer, FP64):
 //   Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gemm64(const G64* __restrict__ gs) {
-  const G64 g = gs[blockIdx.z];
+__device__ __forceinline__ void gemm64_tile(const G64& g) {
   const int i0 = blockIdx.y * BB, j0 = blockIdx.x * BB;
   if (i0 >= g.M || j0 >= g.N) return;
   __shared__ __align__(16) double As[BB * LDM];
@@ -989,6 +989,14 @@ __global__ __launch_bounds__(256) void k_gemm64(const G64* __restrict__ gs) {
     }
   });
 }
+
+// descriptors in device memory, one product per grid.z
+__global__ __launch_bounds__(256) void k_gemm64(const G64* __restrict__ gs) {
+  gemm64_tile(gs[blockIdx.z]);
+}
+
+// one product whose descriptor travels as the kernel argument
+__global__ __launch_bounds__(256) void k_gemm64_arg(const G64 g) { gemm64_tile(g); }
 
 void kron_apply_descs(const KronApply* layers, int L, const double* grad, double* delta,
                       double* tmp, long tmp_stride, G64* h, int* mmax, int* nmax) {
@@ -1016,6 +1024,52 @@ void kron_apply_descs(const KronApply* layers, int L, const double* grad, double
 hipError_t kron_apply_batched(const G64* descs_dev, int L, int mmax, int nmax, hipStream_t st) {
   dim3 g(kp_cdiv(nmax, BB), kp_cdiv(mmax, BB), L);
   for (int s = 0; s < 4; s++) k_gemm64<<<g, 256, 0, st>>>(descs_dev + s * L);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The same apply for one layer without any allocation: the two nB x nA
+// intermediate products live in `scratch`, a file-scope device array (one copy
+// per GPU, held until the process ends), and the four product descriptors are
+// kernel arguments.  Host code never passes `scratch` itself to a kernel: its
+// device address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[2 * kKronScratchElems];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static hipError_t scratch_address(double** out) {
+  int dev = -1;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+hipError_t kron_apply_noalloc(const KronApply& layer, const double* grad, double* delta,
+                              hipStream_t st) {
+  if ((long)layer.nA * layer.nB > kKronScratchElems) return hipErrorInvalidValue;
+  double* tmp = nullptr;
+  if (hipError_t e = scratch_address(&tmp)) return e;
+  KronApply k = layer;
+  k.off = 0;
+  G64 h[4];
+  int mmax = 0, nmax = 0;
+  kron_apply_descs(&k, 1, grad, delta, tmp, 2L * k.nA * k.nB, h, &mmax, &nmax);
+  const dim3 g(kp_cdiv(nmax, BB), kp_cdiv(mmax, BB), 1);
+  for (int s = 0; s < 4; s++) k_gemm64_arg<<<g, 256, 0, st>>>(h[s]);
   return hipGetLastError();
 }
 
