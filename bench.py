@@ -46,6 +46,11 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fwdlap_bf16_poisson100d_traf
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_15603_amd", "csrc", "fwdlap.hip")
 
 
+def log(msg):
+    """Progress of the legs on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def hparams(lr_mode="grid", lr=1.0):
     from paper_2405_15603_amd import HParams
     # the paper's only printed KFAC hyper-parameters (2d Poisson run): beta, mu;
@@ -153,10 +158,11 @@ def measured_traffic():
 
 
 def blas_info():
+    """The BLAS and LAPACK the oracle's PyTorch build links (from its build string)."""
     import torch
     cfg = torch.__config__.show()
-    blas = [l.strip() for l in cfg.splitlines() if "BLAS" in l or "LAPACK" in l]
-    return "; ".join(blas) or "unknown"
+    found = re.findall(r"(BLAS_INFO|LAPACK_INFO)=([^,\s]+)", cfg)
+    return ", ".join(f"{k}={v}" for k, v in found) or "unknown"
 
 
 def cpu_baseline(problem):
@@ -258,12 +264,15 @@ def main():
     # dominant kernel's launch durations come from a run with one lane, where each
     # launch has the chip to itself (with two lanes a launch's events also span the
     # other lane's work).
+    log(f"headline: {args.repeats} x {args.steps} steps after {args.warmup} warm-up")
     ms, _, status, last = run_gpu(problem, args.precision, args.steps, args.warmup, None,
                                   ls_lanes=args.ls_lanes, repeats=args.repeats)
+    log(f"headline done: {ms:.2f} ms per step (repeats {last['repeats_ms_per_step']})")
     if status != 0:
         print(f"device status {status} after the timed steps", file=sys.stderr)
         sys.exit(1)
     rsteps = max(1, min(args.steps, args.roofline_steps))
+    log("one-lane run for the dominant kernel's launch durations")
     ms1, tm, st1, _ = run_gpu(problem, args.precision, rsteps, args.warmup, kc, ls_lanes=1)
     if st1 != 0:
         print(f"device status {st1} after the one-lane steps", file=sys.stderr)
@@ -306,10 +315,12 @@ def main():
     out["line_search_lanes"] = args.ls_lanes
     side_steps = max(2, min(20, args.steps // 2))   # the comparison legs
     if not args.no_core:
+        log("core step (fixed step size)")
         msc, _, stc, _ = run_gpu(problem, args.precision, side_steps, 1, None, lr_mode="fixed")
         out["core_step"] = {"value": 1000.0 / msc, "ms_per_step": msc, "status": stc,
                             "note": "fixed step size 2^-5, no line search"}
     if not args.no_kfac_star:
+        log("KFAC* step")
         msk, _, stk, lastk = run_gpu(problem, args.precision, side_steps, 2, None,
                                      lr_mode="kfac_star")
         out["kfac_star"] = {"value": 1000.0 / msk, "ms_per_step": msk, "status": stk,
@@ -318,15 +329,18 @@ def main():
                                     "model with the exact damped Gramian (Section 3.4), no line "
                                     "search"}
     if not args.no_fp32 and args.precision != "f32":
+        log("FP32 path")
         ms32, _, st32, _ = run_gpu(problem, "f32", side_steps, 1, None)
         out["fp32"] = {"value": 1000.0 / ms32, "ms_per_step": ms32, "status": st32,
                        "mixed_over_fp32": ms32 / ms}
     if not args.no_batch:
+        log("64-instance batch")
         out["batch64"] = {"instances": 64, "note": "heterogeneous 64-instance recipe, mixed "
                           "precision, grid line search; one step of every instance per call",
                           "graph": run_batch(64, 3, 1, True),
                           "direct": run_batch(64, 3, 1, False)}
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(out), flush=True)
 
