@@ -20,6 +20,12 @@
  *   (FP32 master parameters).  Points are row-major n x d reals, targets are n
  *   reals.  Factors, gradients and preconditioners are always double.
  * Residuals: interior r = c_t du/dx_t + c_lap sum_{i in mask} d2u/dx_i^2 - y
+ *   (or c_lap sum_ij C_ij d2u/dx_i dx_j with a coefficient matrix, kp_problem),
+ *   plus sum_{i in mask} (c_x x_i du/dx_i + c_g (du/dx_i)^2) + c_0 for PDEs whose
+ *   residual depends on the first derivatives non-linearly (Section 3.3; the
+ *   logarithmic Fokker-Planck equation of Section 4: c_t = 1, c_lap = -1,
+ *   c_x = -1/2, c_g = -1, c_0 = -d_x/2, t outside the mask).  The output gradients
+ *   g then use the point-dependent seed dr/dU.
  *   (Poisson -Lap u = f: c_t = 0, c_lap = -1, y = f; heat u_t = kappa Lap_x u:
  *   c_t = 1, c_lap = -kappa, t excluded from the mask); boundary r = u - y.
  *   Loss L = sum r^2/(2N) + sum r_b^2/(2M).
@@ -95,6 +101,15 @@ typedef struct {
                                    kfac_pinn_forward_laplacian would exceed it, the
                                    forward keeps no intermediates and the VJP
                                    recomputes each layer's input from x.            */
+  const double* op_coef;        /* host, d x d row-major symmetric C, or NULL.  When
+                                   given (lap_mask must be NULL) the second-order
+                                   part is sum_ij C_ij d2u/dx_i dx_j (Section 3.1,
+                                   closing paragraph; Appendix C.3), propagated
+                                   along the eigenvectors of C; with a time term,
+                                   C's row and column time_coord must be zero.   */
+  double coef_xgrad;            /* c_x  } first-order terms of the interior residual */
+  double coef_gradsq;           /* c_g  } (Section 3.3), see Residuals above; 0 for  */
+  double coef_const;            /* c_0  } a linear PDE.  c_x, c_g need lap_mask form */
 } kp_problem;
 
 typedef struct {
@@ -194,6 +209,20 @@ kp_status kfac_pinn_factors(kfac_pinn_ctx* ctx, const void* theta,
                             const void* x_int, const void* y_int, int32_t n_int,
                             const void* x_bnd, const void* y_bnd, int32_t n_bnd,
                             double beta, double* grad_out, double* loss_out);
+
+/* ---- exact per-layer Gramian (Section 3.2, Eq. laplace_gramian_block_exact) ----
+ * The block of Eq. (gramian) that KFAC approximates, for layer `layer` and one
+ * term (0 interior, 1 boundary with S = 1), from the slabs of the last
+ * kfac_pinn_factors / kfac_pinn_step call on this context:
+ *   G = (1/n) sum_p J_p J_p^T,   J_p = sum_s z~_{p,s} (x) g_{p,s},
+ * with p the parameter count h_out (h_in + 1) of the layer in the theta layout
+ * (column-stacked [W | b]) and n that call's point count of the term.
+ * out: p x p doubles (row-major, symmetric); work: n x p doubles of scratch;
+ * both device memory owned by the caller.  For small layers: p <= 16384.
+ * Errors: KP_ERR_ARG for indices, a layer above the limit, a context without
+ * stored slabs (workspace limit) or without a curvature pass of that term. */
+kp_status kfac_pinn_layer_gramian(kfac_pinn_ctx* ctx, int32_t layer, int32_t term, double* out,
+                                  double* work);
 
 /* ---- damped Kronecker-sum factorisation (Section 3.4) ------------------------
  * For every layer and side, damps the EMA factors (+ lambda I) and computes,

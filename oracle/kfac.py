@@ -90,6 +90,10 @@ class Operator:
     coef_lap: float = -1.0
     mask: Optional[Sequence[int]] = None
     coef: Optional[Sequence[Sequence[float]]] = None   # C, d x d symmetric
+    # first-order terms (Section 3.3): sum_{i in mask} (c_x x_i d_i u + c_g (d_i u)^2) + c_0
+    coef_xgrad: float = 0.0
+    coef_gradsq: float = 0.0
+    coef_const: float = 0.0
 
     def mask_vec(self, d: int) -> torch.Tensor:
         if self.mask is None:
@@ -112,7 +116,9 @@ def operator_of(problem) -> Operator:
     if coef is not None:
         coef = tuple(tuple(float(v) for v in row) for row in np.asarray(coef))
     return Operator(problem.time_coord, problem.coef_time, problem.coef_lap,
-                    tuple(int(v) for v in problem.lap_mask), coef)
+                    tuple(int(v) for v in problem.lap_mask), coef,
+                    getattr(problem, "coef_xgrad", 0.0), getattr(problem, "coef_gradsq", 0.0),
+                    getattr(problem, "coef_const", 0.0))
 
 
 # ----------------------------------------------------------------------------
@@ -227,12 +233,21 @@ def forward_plain(Ws: Sequence[torch.Tensor], X: torch.Tensor, act: Activation =
 # Residuals and loss (Section 2.1, Eq. pinn-loss)
 # ----------------------------------------------------------------------------
 
-def interior_residual(U: torch.Tensor, y: torch.Tensor, op: Operator) -> torch.Tensor:
+def interior_residual(U: torch.Tensor, y: torch.Tensor, op: Operator,
+                      X: Optional[torch.Tensor] = None) -> torch.Tensor:
     """r_n = L u(x_n) - y_n with L u = c_t d_t u + c_lap (masked) Lap u.  The output
-    rows are value (0), derivatives (1..d), Laplacian (d+1)."""
+    rows are value (0), derivatives (1..d), Laplacian (d+1).  A residual with
+    first-order terms (Section 3.3; e.g. the logarithmic Fokker-Planck equation of
+    Section 4) adds sum_{i in mask} (c_x x_i d_i u + c_g (d_i u)^2) + c_0, which
+    needs the points X."""
     r = op.coef_lap * U[:, -1] - y
     if op.time_coord >= 0 and op.coef_time != 0.0:
         r = r + op.coef_time * U[:, 1 + op.time_coord]
+    if op.coef_xgrad != 0.0 or op.coef_gradsq != 0.0 or op.coef_const != 0.0:
+        d = U.shape[1] - 2
+        m = op.mask_vec(d)
+        du = U[:, 1:d + 1]
+        r = r + ((op.coef_xgrad * X + op.coef_gradsq * du) * du * m).sum(1) + op.coef_const
     return r
 
 
@@ -256,7 +271,7 @@ def loss(theta, widths, Xi, yi, Xb, yb, op: Operator = POISSON_OP, act: Activati
         Xi, yi, Xb, yb = map(_t, (Xi, yi, Xb, yb))
         fi = forward_laplacian(Ws, Xi, op.second_order(Xi.shape[1]), act)
         fb = forward_plain(Ws, Xb, act)
-        li, lb = loss_terms(interior_residual(fi.out, yi, op), boundary_residual(fb.out, yb))
+        li, lb = loss_terms(interior_residual(fi.out, yi, op, Xi), boundary_residual(fb.out, yb))
     return float(li + lb), float(li), float(lb)
 
 
@@ -286,7 +301,7 @@ def interior_curvature_inputs(Ws, Xi, yi, op: Operator, act: Activation = TANH) 
         pre.append(a)
         if l < len(Ws) - 1:
             Z = activation_rows(a, op.second_order(Xi.shape[1]), act)
-    r = interior_residual(pre[-1][:, :, 0], yi, op)
+    r = interior_residual(pre[-1][:, :, 0], yi, op, Xi)
     g = torch.autograd.grad(r.sum(), pre, allow_unused=True)
     g = [gi if gi is not None else torch.zeros_like(p) for gi, p in zip(g, pre)]
     return Curvature(zin, [x.detach() for x in g], r.detach(), pre[-1][:, :, 0].detach())
@@ -341,7 +356,7 @@ def loss_gradient(theta, widths, Xi, yi, Xb, yb, op: Operator = POISSON_OP,
     Xi, yi, Xb, yb = map(_t, (Xi, yi, Xb, yb))
     fi = forward_laplacian(Ws, Xi, op.second_order(Xi.shape[1]), act)
     fb = forward_plain(Ws, Xb, act)
-    li, lb = loss_terms(interior_residual(fi.out, yi, op), boundary_residual(fb.out, yb))
+    li, lb = loss_terms(interior_residual(fi.out, yi, op, Xi), boundary_residual(fb.out, yb))
     (gr,) = torch.autograd.grad(li + lb, th)
     return gr.detach(), float(li.detach()), float(lb.detach())
 

@@ -40,7 +40,7 @@ def residual_vectors(theta, widths, Xi, yi, Xb, yb, op, act=TANH):
     Ws = unpack(theta, widths)
     fi = forward_laplacian(Ws, Xi, op.second_order(Xi.shape[1]), act)
     fb = forward_plain(Ws, Xb, act)
-    return interior_residual(fi.out, yi, op), boundary_residual(fb.out, yb)
+    return interior_residual(fi.out, yi, op, Xi), boundary_residual(fb.out, yb)
 
 
 def jacobian_vector_products(theta, widths, data, op, d, act=TANH):

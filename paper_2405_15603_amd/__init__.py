@@ -45,12 +45,15 @@ class HParams:
 
 class KfacPinn:
     """One KFAC-PINN context: a tanh MLP with the given widths, an interior
-    operator c_t d/dx_t + c_lap sum_{i in mask} d2/dx_i^2 and capacities."""
+    operator c_t d/dx_t + c_lap sum_{i in mask} d2/dx_i^2 (or, with op_coef = C,
+    c_lap sum_ij C_ij d2/dx_i dx_j) and capacities."""
 
     def __init__(self, widths: Sequence[int], precision: str = "f32", time_coord: int = -1,
                  coef_time: float = 0.0, coef_lap: float = -1.0, lap_mask=None,
                  max_interior: int = 4096, max_boundary: int = 4096,
-                 workspace_limit_bytes: int = 0, stream: Optional[torch.cuda.Stream] = None):
+                 workspace_limit_bytes: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                 op_coef=None, coef_xgrad: float = 0.0, coef_gradsq: float = 0.0,
+                 coef_const: float = 0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("KfacPinn needs a GPU (HIP device); there is no CPU path")
         self.lib = N.lib()
@@ -65,10 +68,18 @@ class KfacPinn:
         self._mask = None
         if lap_mask is not None:
             self._mask = (C.c_uint8 * self.d)(*[1 if m else 0 for m in lap_mask])
+        self._coef = None
+        if op_coef is not None:
+            flat = [float(v) for row in op_coef for v in row]
+            if len(flat) != self.d * self.d:
+                raise ValueError("op_coef must be d x d")
+            self._coef = (C.c_double * len(flat))(*flat)
+            self._mask = None
         prob = N.kp_problem(self.L, self._w, time_coord, coef_time, coef_lap,
                             self._mask if self._mask is not None else None,
                             PRECISIONS[precision], max_interior, max_boundary,
-                            workspace_limit_bytes)
+                            workspace_limit_bytes, self._coef, coef_xgrad, coef_gradsq,
+                            coef_const)
         h = C.c_void_p()
         N.check(self.lib.kfac_pinn_create(C.byref(prob), C.c_void_p(self.stream.cuda_stream),
                                           C.byref(h)), "kfac_pinn_create")
@@ -82,8 +93,13 @@ class KfacPinn:
         operator coefficients and point counts)."""
         kw.setdefault("max_interior", problem.n_interior)
         kw.setdefault("max_boundary", problem.n_cond)
+        coef = getattr(problem, "op_coef", None)
+        if coef is not None:
+            kw.setdefault("op_coef", [list(r) for r in coef])
+        for k in ("coef_xgrad", "coef_gradsq", "coef_const"):
+            kw.setdefault(k, getattr(problem, k, 0.0))
         return cls(problem.widths, precision, problem.time_coord, problem.coef_time,
-                   problem.coef_lap, list(problem.lap_mask), **kw)
+                   problem.coef_lap, None if coef is not None else list(problem.lap_mask), **kw)
 
     @classmethod
     def _borrow(cls, handle: C.c_void_p, widths, precision: str, max_interior: int,
@@ -176,6 +192,16 @@ class KfacPinn:
         """Sweep cap of the Jacobi eigensolver (1..64)."""
         N.check(self.lib.kfac_pinn_set_max_sweeps(self.h, int(max_sweeps)),
                 "kfac_pinn_set_max_sweeps")
+
+    def layer_gramian(self, layer: int, term: int, n: int) -> torch.Tensor:
+        """Exact Gramian block of `layer` for one term (0 interior, 1 boundary) from
+        the last curvature pass, which had n points of that term."""
+        p = self.widths[layer + 1] * (self.widths[layer] + 1)
+        out = self.empty(p, p, dtype=torch.float64)
+        work = self.empty(max(n, 1), p, dtype=torch.float64)
+        N.check(self.lib.kfac_pinn_layer_gramian(self.h, layer, term, _ptr(out), _ptr(work)),
+                "kfac_pinn_layer_gramian")
+        return out
 
     def check_guards(self) -> tuple:
         """(guard bytes overwritten, guarded buffers); (0, 0) without guards."""
@@ -316,8 +342,16 @@ class KfacPinnBatch:
             w = (C.c_int32 * len(p.widths))(*p.widths)
             m = (C.c_uint8 * p.d)(*[1 if v else 0 for v in p.lap_mask])
             self._keep += [w, m]
+            coef = getattr(p, "op_coef", None)
+            cf = None
+            if coef is not None:
+                cf = (C.c_double * (p.d * p.d))(*[float(v) for r in coef for v in r])
+                self._keep.append(cf)
+                m = None
             arr[k] = N.kp_problem(len(p.widths) - 1, w, p.time_coord, p.coef_time, p.coef_lap, m,
-                                  PRECISIONS[precision], p.n_interior, p.n_cond, 0)
+                                  PRECISIONS[precision], p.n_interior, p.n_cond, 0, cf,
+                                  getattr(p, "coef_xgrad", 0.0), getattr(p, "coef_gradsq", 0.0),
+                                  getattr(p, "coef_const", 0.0))
         h = C.c_void_p()
         N.check(self.lib.kfac_pinn_batch_create(arr, n, C.c_void_p(self.stream.cuda_stream),
                                                 C.byref(h)), "kfac_pinn_batch_create")

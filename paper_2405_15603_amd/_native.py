@@ -20,7 +20,9 @@ class kp_problem(C.Structure):
                 ("time_coord", C.c_int32), ("coef_time", C.c_double), ("coef_lap", C.c_double),
                 ("lap_mask", C.POINTER(C.c_uint8)), ("precision", C.c_int32),
                 ("max_interior", C.c_int32), ("max_boundary", C.c_int32),
-                ("workspace_limit_bytes", C.c_size_t)]
+                ("workspace_limit_bytes", C.c_size_t), ("op_coef", C.POINTER(C.c_double)),
+                ("coef_xgrad", C.c_double), ("coef_gradsq", C.c_double),
+                ("coef_const", C.c_double)]
 
 
 class kp_hparams(C.Structure):
@@ -55,6 +57,7 @@ _SIGS = {
     "kfac_pinn_factors": (C.c_int, [_V, _V, _V, _V, C.c_int32, _V, _V, C.c_int32, C.c_double,
                                     _V, _V]),
     "kfac_pinn_invert": (C.c_int, [_V, C.c_double]),
+    "kfac_pinn_layer_gramian": (C.c_int, [_V, C.c_int32, C.c_int32, _V, _V]),
     "kfac_pinn_precondition": (C.c_int, [_V, _V, _V]),
     "kfac_pinn_precondition_layer_noalloc": (C.c_int, [C.c_int32, C.c_int32, _V, _V, _V, _V, _V,
                                                        _V, _V]),

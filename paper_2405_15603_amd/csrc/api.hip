@@ -48,6 +48,7 @@ constexpr int kMaxLayers = 8;
 constexpr int kMaxCand = 64;
 constexpr int kMaxSplits = 64;
 constexpr int kJacobiSweeps = 20;
+constexpr long kMaxGramianParams = 16384;
 // Jacobi starts from the previous call's eigenvectors except on every
 // kEigRefresh-th call (and the first), which starts from the identity so that
 // rounding in the carried rotations cannot accumulate without bound.
@@ -78,6 +79,10 @@ struct kfac_pinn_ctx {
   std::vector<int> w;
   int time_coord = -1;
   double c_t = 0.0, c_lap = -1.0;
+  // first-order terms of the interior residual (Section 3.3; zero for linear PDEs):
+  // sum_{i in mask} (c_x x_i d_i u + c_g (d_i u)^2) + c_0
+  double c_x = 0.0, c_g = 0.0, c_0 = 0.0;
+  bool nonlinear = false;
   int precision = KP_F32;
   Prec pp = P_F32;          // parameters and points
   Prec sp = P_F32;          // curvature slabs
@@ -102,7 +107,9 @@ struct kfac_pinn_ctx {
   std::vector<Alloc> allocs;
   size_t guard = 0;
   int max_sweeps = kJacobiSweeps;
-  uint8_t* mask = nullptr;
+  float* wts = nullptr;     // weights of the derivative rows' squares (mask or eigenvalues of C)
+  double* wts64 = nullptr;  // the same in FP64
+  double* dirs = nullptr;   // input directions (rows: eigenvectors of C), nullptr = unit vectors
   void *w_hi = nullptr, *w_lo = nullptr;
   void* theta_trial = nullptr;
   Slabs si, sb;
@@ -155,6 +162,7 @@ struct kfac_pinn_ctx {
   double* jv = nullptr;
   long jv_ld = 0;
   void* jvp_part = nullptr;
+  int last_n[2] = {0, 0};   // point counts of the last curvature pass (interior, boundary)
   // measurement: launches of one kernel class bracketed by events
   int tm_cls = -1;
   std::vector<hipEvent_t> tm_ev;
@@ -179,6 +187,54 @@ hipError_t dmalloc(kfac_pinn_ctx* c, void** p, size_t bytes) {
                 (e = hipMemset((char*)*p + bytes, kGuardByte, g)) != hipSuccess))
     return e;
   return hipMemset(*p, 0, bytes);
+}
+
+// A = V diag(w) V^T for a small symmetric matrix (row-major n x n, host), by
+// cyclic Jacobi rotations (tan of the rotation from the textbook quadratic
+// t^2 + 2 theta t - 1 = 0) until the off-diagonal part is below 1e-32 of the
+// squared Frobenius norm.  A row and column that are zero are never rotated, so
+// e_k stays an eigenvector exactly.  The matrix is symmetrised first.
+void eig_sym_host(int n, const double* A0, std::vector<double>& V, std::vector<double>& w) {
+  std::vector<double> A((size_t)n * n);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) A[(size_t)i * n + j] = 0.5 * (A0[(size_t)i * n + j] + A0[(size_t)j * n + i]);
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; i++) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; sweep++) {
+    double off = 0.0, fro = 0.0;
+    for (int i = 0; i < n; i++)
+      for (int j = 0; j < n; j++) {
+        fro += a(i, j) * a(i, j);
+        if (i != j) off += a(i, j) * a(i, j);
+      }
+    if (off <= 1e-32 * fro) break;
+    for (int p = 0; p < n - 1; p++)
+      for (int q = p + 1; q < n; q++) {
+        const double apq = a(p, q);
+        if (apq == 0.0) continue;
+        const double th = (a(q, q) - a(p, p)) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; k++) {   // columns p, q
+          const double akp = a(k, p), akq = a(k, q);
+          a(k, p) = cs * akp - sn * akq;
+          a(k, q) = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; k++) {   // rows p, q
+          const double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = cs * apk - sn * aqk;
+          a(q, k) = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; k++) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; i++) w[i] = a(i, i);
 }
 
 void dfree(kfac_pinn_ctx* c, void* user) {
@@ -309,7 +365,10 @@ LayerLaunch layer_launch(kfac_pinn_ctx* c, const Slabs& s, int n, int l, int upt
   a.nd = s.nd;
   a.has_lap = s.has_lap;
   a.h_out = ld.h_out;
-  a.mask = c->mask;
+  a.wts = c->wts;
+  a.wts64 = c->wts64;
+  a.dirs = c->dirs;
+  a.d = c->d;
   a.z = T.z(l + 1);
   a.ldzo = c->ldz[l + 1];
   a.pre = T.pre(l);
@@ -388,7 +447,8 @@ int input_rows_of(kfac_pinn_ctx* c, const Slabs& s, const FwdTarget& T) {
 hipError_t forward_run(kfac_pinn_ctx* c, const Slabs& s, const void* x, int n, int upto,
                        const FwdTarget& T) {
   hipError_t e;
-  if ((e = input_slab(T.zp, x, n, c->d, input_rows_of(c, s, T), T.z(0), c->ldz[0], c->st)) !=
+  if ((e = input_slab(T.zp, x, n, c->d, input_rows_of(c, s, T), c->dirs, T.z(0), c->ldz[0],
+                      c->st)) !=
       hipSuccess)
     return e;
   const int nh = upto < c->L ? upto : c->L - 1;
@@ -411,9 +471,9 @@ hipError_t forward_pair(kfac_pinn_ctx* c, const void* xi, int ni, const FwdTarge
   hipError_t e;
   const Slabs& si = c->si;
   const Slabs& sb = c->sb;
-  if ((e = input_slab(Ti.zp, xi, ni, c->d, input_rows_of(c, si, Ti), Ti.z(0), c->ldz[0],
+  if ((e = input_slab(Ti.zp, xi, ni, c->d, input_rows_of(c, si, Ti), c->dirs, Ti.z(0), c->ldz[0],
                       c->st)) != hipSuccess ||
-      (e = input_slab(Tb.zp, xb, nb, c->d, input_rows_of(c, sb, Tb), Tb.z(0), c->ldz[0],
+      (e = input_slab(Tb.zp, xb, nb, c->d, input_rows_of(c, sb, Tb), c->dirs, Tb.z(0), c->ldz[0],
                       c->st)) != hipSuccess)
     return e;
   for (int l = 0; l < c->L - 1; l++) {
@@ -442,24 +502,38 @@ FwdTarget curvature_target(kfac_pinn_ctx* c, Slabs& s, const void* theta) {
   return T;
 }
 
+ResidualTerms residual_terms(const kfac_pinn_ctx* c, const Slabs& s, const void* x) {
+  ResidualTerms t;
+  if (c->nonlinear && s.has_lap) {
+    t.x = x;
+    t.mask = c->wts;
+    t.d = c->d;
+    t.c_x = c->c_x;
+    t.c_g = c->c_g;
+    t.c_0 = c->c_0;
+  }
+  return t;
+}
+
 // residual, loss[slot] and the seed rows of the output layer
-hipError_t residual_and_seed(kfac_pinn_ctx* c, Slabs& s, const void* u, const void* y, int n,
-                             void* g_last, int slot, int accumulate) {
+hipError_t residual_and_seed(kfac_pinn_ctx* c, Slabs& s, const void* u, const void* x,
+                             const void* y, int n, void* g_last, int slot, int accumulate) {
   hipError_t e;
   const int nb = residual_blocks(n);
   if ((e = residual(c->sp, u, 1, y, n, s.S, time_row_of(c, s), c->c_t, c->c_lap, lap_row_of(s),
-                    s.r, s.rf, g_last, c->ldg[c->L - 1], c->partial, c->st)) != hipSuccess)
+                    residual_terms(c, s, x), s.r, s.rf, g_last, c->ldg[c->L - 1], c->partial,
+                    c->st)) != hipSuccess)
     return e;
   return finalize_loss(c->partial, nb, 0.5 / (double)n, c->loss, slot, accumulate, c->st);
 }
 
-hipError_t residual_loss_only(kfac_pinn_ctx* c, Slabs& s, const void* u, const void* y, int n,
-                              int slot, int accumulate) {
+hipError_t residual_loss_only(kfac_pinn_ctx* c, Slabs& s, const void* u, const void* x,
+                              const void* y, int n, int slot, int accumulate) {
   hipError_t e;
   const int nb = residual_blocks(n);
   if ((e = residual(c->sp == P_F64 ? P_F64 : P_F32, u, 1, y, n, s.S, time_row_of(c, s), c->c_t,
-                    c->c_lap, lap_row_of(s), nullptr, nullptr, nullptr, 1, c->partial, c->st)) !=
-      hipSuccess)
+                    c->c_lap, lap_row_of(s), residual_terms(c, s, x), nullptr, nullptr, nullptr, 1,
+                    c->partial, c->st)) != hipSuccess)
     return e;
   return finalize_loss(c->partial, nb, 0.5 / (double)n, c->loss, slot, accumulate, c->st);
 }
@@ -492,7 +566,8 @@ hipError_t backward_sweep(kfac_pinn_ctx* c, Slabs& s, const void* theta, const v
     a.nd = s.nd;
     a.has_lap = s.has_lap;
     a.h = ld.h_in;
-    a.mask = c->mask;
+    a.wts = c->wts;
+    a.wts64 = c->wts64;
     a.pre = s.pre_at(l - 1);
     a.ldp = c->ldp[l - 1];
     a.sq = s.sq[l - 1];
@@ -593,7 +668,8 @@ hipError_t curvature_term(kfac_pinn_ctx* c, int term, const void* theta, const v
   hipError_t e;
   if (n <= 0) return hipSuccess;
   if ((e = forward_run(c, s, x, n, c->L, curvature_target(c, s, theta))) != hipSuccess) return e;
-  if ((e = residual_and_seed(c, s, s.u, y, n, s.g_at(c->L - 1), term, 0)) != hipSuccess) return e;
+  if ((e = residual_and_seed(c, s, s.u, x, y, n, s.g_at(c->L - 1), term, 0)) != hipSuccess)
+    return e;
   FactorGrad fg;
   fg.c = c; fg.term = term; fg.n = n; fg.S = s.S; fg.beta = beta;
   return backward_sweep(c, s, theta, x, n, fg);
@@ -614,8 +690,9 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   T.u = c->ls_u;
   T.kc_layer = KC_LS_LAYER;
   T.full_input = false;
-  T.residual_rows = true;
-  if (ni > 0 && nb > 0 && T.mode == M_BF16 && !c->sb.has_lap && c->L >= 2) {
+  // a residual with first-order terms reads every derivative row of the output
+  T.residual_rows = !c->nonlinear;
+  if (ni > 0 && nb > 0 && T.mode == M_BF16 && !c->sb.has_lap && c->L >= 2 && !c->nonlinear) {
     FwdTarget Tb = T;
     Tb.z = [c](int l) { return c->ls_zb[l]; };
     Tb.u = c->ls_ub;
@@ -629,12 +706,12 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   int acc = 0;
   if (ni > 0) {
     if ((e = forward_run(c, c->si, xi, ni, c->L, T)) != hipSuccess) return e;
-    if ((e = residual_loss_only(c, c->si, c->ls_u, yi, ni, slot, 0)) != hipSuccess) return e;
+    if ((e = residual_loss_only(c, c->si, c->ls_u, xi, yi, ni, slot, 0)) != hipSuccess) return e;
     acc = 1;
   }
   if (nb > 0) {
     if ((e = forward_run(c, c->sb, xb, nb, c->L, T)) != hipSuccess) return e;
-    if ((e = residual_loss_only(c, c->sb, c->ls_u, yb, nb, slot, acc)) != hipSuccess) return e;
+    if ((e = residual_loss_only(c, c->sb, c->ls_u, xb, yb, nb, slot, acc)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -703,6 +780,28 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   KP_ARG(pb->precision >= KP_F64 && pb->precision <= KP_MIXED_BF16, "unknown precision");
   KP_ARG(pb->max_interior >= 0 && pb->max_boundary >= 0, "negative capacity");
   KP_ARG(pb->time_coord >= -1 && pb->time_coord < pb->widths[0], "time_coord out of range");
+  KP_ARG(std::isfinite(pb->coef_xgrad) && std::isfinite(pb->coef_gradsq) &&
+             std::isfinite(pb->coef_const),
+         "first-order residual coefficients must be finite");
+  KP_ARG(!(pb->op_coef && (pb->coef_xgrad != 0.0 || pb->coef_gradsq != 0.0)),
+         "first-order residual terms need the mask form of the operator (no op_coef)");
+  if (pb->op_coef) {
+    const int d = pb->widths[0];
+    KP_ARG(!pb->lap_mask, "give either lap_mask or op_coef");
+    double mx = 0.0;
+    for (long e = 0; e < (long)d * d; e++) {
+      KP_ARG(std::isfinite(pb->op_coef[e]), "op_coef must be finite");
+      mx = std::max(mx, std::fabs(pb->op_coef[e]));
+    }
+    for (int i = 0; i < d; i++)
+      for (int j = 0; j < i; j++)
+        KP_ARG(std::fabs(pb->op_coef[(long)i * d + j] - pb->op_coef[(long)j * d + i]) <= 1e-12 * mx,
+               "op_coef must be symmetric");
+    if (pb->time_coord >= 0 && pb->coef_time != 0.0)
+      for (int i = 0; i < d; i++)
+        KP_ARG(pb->op_coef[(long)pb->time_coord * d + i] == 0.0,
+               "op_coef: the time coordinate's row and column must be zero");
+  }
 
   kfac_pinn_ctx* c = new kfac_pinn_ctx();
   if (const char* gk = getenv("KFAC_PINN_GUARD_KB")) {
@@ -715,6 +814,10 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   c->time_coord = pb->time_coord;
   c->c_t = pb->coef_time;
   c->c_lap = pb->coef_lap;
+  c->c_x = pb->coef_xgrad;
+  c->c_g = pb->coef_gradsq;
+  c->c_0 = pb->coef_const;
+  c->nonlinear = c->c_x != 0.0 || c->c_g != 0.0 || c->c_0 != 0.0;
   c->precision = pb->precision;
   if (pb->precision == KP_F64) {
     c->pp = c->sp = c->lp = c->wp = P_F64;
@@ -779,13 +882,45 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     kfac_pinn_destroy(c);                                          \
     return e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_HIP;    \
   }
-  // Laplacian mask (per input coordinate), padded to whole 32-bit words
-  const size_t mask_bytes = (size_t)kp_roundup(c->d, 4);
-  ALLOC(c->mask, mask_bytes);
+  // Second-order part of the operator: sum_k w_k d^2/dv_k^2 along orthonormal
+  // directions v_k.  A mask gives v_k = e_k and w_k in {0, 1}; a coefficient
+  // matrix C gives its eigenvectors and eigenvalues (Appendix C.3's operator
+  // sum_ij C_ij d_i d_j, diagonal in that basis).
   {
-    std::vector<uint8_t> m(mask_bytes, 0);
-    for (int i = 0; i < c->d; i++) m[i] = (!pb->lap_mask || pb->lap_mask[i]) ? 1 : 0;
-    if ((e = hipMemcpy(c->mask, m.data(), mask_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+    std::vector<double> V, w;
+    if (pb->op_coef) {
+      eig_sym_host(c->d, pb->op_coef, V, w);
+      bool ident = true;
+      for (int i = 0; i < c->d && ident; i++)
+        for (int k = 0; k < c->d; k++)
+          if (V[(long)i * c->d + k] != (i == k ? 1.0 : 0.0)) { ident = false; break; }
+      if (!ident) {
+        std::vector<double> rows((size_t)c->d * c->d);   // row k = v_k
+        for (int i = 0; i < c->d; i++)
+          for (int k = 0; k < c->d; k++) rows[(size_t)k * c->d + i] = V[(size_t)i * c->d + k];
+        ALLOC(c->dirs, sizeof(double) * rows.size());
+        if ((e = hipMemcpy(c->dirs, rows.data(), sizeof(double) * rows.size(),
+                           hipMemcpyHostToDevice)) != hipSuccess) {
+          kfac_pinn_destroy(c);
+          return KP_ERR_HIP;
+        }
+      }
+    } else {
+      w.resize(c->d);
+      for (int i = 0; i < c->d; i++) w[i] = (!pb->lap_mask || pb->lap_mask[i]) ? 1.0 : 0.0;
+    }
+    std::vector<float> wf(kp_roundup(c->d, 4), 0.0f);
+    std::vector<double> wd(kp_roundup(c->d, 4), 0.0);
+    for (int i = 0; i < c->d; i++) {
+      wf[i] = (float)w[i];
+      wd[i] = w[i];
+    }
+    ALLOC(c->wts, sizeof(float) * wf.size());
+    ALLOC(c->wts64, sizeof(double) * wd.size());
+    if ((e = hipMemcpy(c->wts, wf.data(), sizeof(float) * wf.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(c->wts64, wd.data(), sizeof(double) * wd.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess) {
       kfac_pinn_destroy(c);
       return KP_ERR_HIP;
     }
@@ -1008,7 +1143,8 @@ kp_status kfac_pinn_forward_laplacian(kfac_pinn_ctx* c, const void* theta, const
   if (n == 0) return KP_OK;
   KP_TRY(prep(c, theta));
   KP_TRY(forward_run(c, c->si, x, n, c->L, curvature_target(c, c->si, theta)));
-  KP_TRY(extract_outputs(c->pp, c->si.u, 1, n, c->si.S, c->d, c->si.S - 1, u_out, grad_out,
+  KP_TRY(extract_outputs(c->pp, c->si.u, 1, n, c->si.S, c->d, c->si.S - 1, c->dirs, u_out,
+                         grad_out,
                          lap_out, c->st));
   return KP_OK;
 }
@@ -1027,7 +1163,8 @@ kp_status kfac_pinn_forward_laplacian_vjp(kfac_pinn_ctx* c, const void* theta, c
   // stored mode: slabs of this (theta, x); recompute mode: the last hidden layer's
   // inputs and pre-activations for the first backward step
   KP_TRY(forward_run(c, s, x, n, c->L, curvature_target(c, s, theta)));
-  KP_TRY(seed_rows(c->sp, u_bar, grad_bar, lap_bar, n, s.S, c->d, s.S - 1, s.g_at(c->L - 1),
+  KP_TRY(seed_rows(c->sp, u_bar, grad_bar, lap_bar, n, s.S, c->d, s.S - 1, c->dirs,
+                   s.g_at(c->L - 1),
                    c->ldg[c->L - 1], c->st));
   ThetaBar tb;
   tb.c = c;
@@ -1067,6 +1204,8 @@ static kp_status factors_impl(kfac_pinn_ctx* c, const void* theta, const void* x
   KP_TRY(prep(c, theta));
   KP_TRY(zero_fill(c->grad, sizeof(double) * c->D, c->st));
   KP_TRY(zero_fill(c->loss, sizeof(double) * 2, c->st));
+  c->last_n[0] = ni;
+  c->last_n[1] = nb;
   // interior term first: it overwrites the gradient, the boundary term adds to it
   if (ni > 0) KP_TRY(curvature_term(c, 0, theta, xi, yi, ni, beta));
   else KP_TRY(decay_term(c, 0, beta));
@@ -1210,6 +1349,23 @@ kp_status kfac_pinn_precondition_layer_noalloc(int32_t nA, int32_t nB, const dou
   k.PB = PB;
   k.b = b;
   KP_TRY(kron_apply_noalloc(k, grad, delta, (hipStream_t)stream));
+  return KP_OK;
+}
+
+kp_status kfac_pinn_layer_gramian(kfac_pinn_ctx* c, int32_t layer, int32_t term, double* out,
+                                  double* work) {
+  KP_ARG(c && out && work, "null argument");
+  KP_ARG(layer >= 0 && layer < c->L && (term == 0 || term == 1), "index out of range");
+  const Slabs& s = term == 0 ? c->si : c->sb;
+  KP_ARG(s.store, "the exact Gramian needs the stored slabs (no workspace limit)");
+  const int n = c->last_n[term];
+  KP_ARG(n > 0, "no curvature pass with points of this term yet");
+  const LayerDesc& ld = c->nd.l[layer];
+  const long p = (long)ld.h_out * (ld.h_in + 1);
+  KP_ARG(p <= kMaxGramianParams, "layer too large for the exact Gramian (more than 16384 parameters)");
+  KP_TRY(layer_gramian(c->sp == P_F64 ? P_F64 : P_F32, s.zin_at(layer), c->ldz[layer],
+                       s.g_at(layer), c->ldg[layer], n, s.S, ld.h_in + 1, ld.h_out, work, out,
+                       c->st));
   return KP_OK;
 }
 

@@ -81,11 +81,12 @@ hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha
 }
 
 // ---------------------------------------------------------------------------
-// Input slab Z~^(0) (Section 3.1: z = x, d_i z = e_i, Lap z = 0)
+// Input slab Z~^(0) (Section 3.1: z = x, d_i z = e_i, Lap z = 0; with input
+// directions v_k the derivative rows are v_k instead of the unit vectors)
 // ---------------------------------------------------------------------------
 template <typename TP, typename TS>
-__global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S, TS* __restrict__ z,
-                             long ldz) {
+__global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S,
+                             const double* __restrict__ dirs, TS* __restrict__ z, long ldz) {
   const long R = (long)n * S;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < R * ldz;
        e += (long)gridDim.x * blockDim.x) {
@@ -94,26 +95,27 @@ __global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S, TS* 
     int s = (int)(r / n), pt = (int)(r % n);
     double v = 0.0;
     if (s == 0) v = j < d ? (double)x[(long)pt * d + j] : (j == d ? 1.0 : 0.0);
-    else if (S > 1 && s < S - 1) v = (j == s - 1) ? 1.0 : 0.0;
+    else if (S > 1 && s < S - 1)
+      v = dirs ? (j < d ? dirs[(long)(s - 1) * d + j] : 0.0) : ((j == s - 1) ? 1.0 : 0.0);
     z[e] = cvt<TS>(v);
   }
 }
 
-hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long ldz,
-                      hipStream_t st) {
+hipError_t input_slab(Prec p, const void* x, int n, int d, int S, const double* dirs, void* z,
+                      long ldz, hipStream_t st) {
   long tot = (long)n * S * ldz;
   int nb = (int)((tot + 255) / 256);
   if (nb > 65536) nb = 65536;
   if (nb < 1) nb = 1;
   switch (p) {
     case P_F64:
-      k_input_slab<double, double><<<nb, 256, 0, st>>>((const double*)x, n, d, S, (double*)z, ldz);
+      k_input_slab<double, double><<<nb, 256, 0, st>>>((const double*)x, n, d, S, dirs, (double*)z, ldz);
       break;
     case P_F32:
-      k_input_slab<float, float><<<nb, 256, 0, st>>>((const float*)x, n, d, S, (float*)z, ldz);
+      k_input_slab<float, float><<<nb, 256, 0, st>>>((const float*)x, n, d, S, dirs, (float*)z, ldz);
       break;
     case P_BF16:
-      k_input_slab<float, bf16><<<nb, 256, 0, st>>>((const float*)x, n, d, S, (bf16*)z, ldz);
+      k_input_slab<float, bf16><<<nb, 256, 0, st>>>((const float*)x, n, d, S, dirs, (bf16*)z, ldz);
       break;
   }
   return hipGetLastError();
@@ -124,16 +126,23 @@ hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long 
 // ---------------------------------------------------------------------------
 int residual_blocks(int npts) { return npts > 0 ? (npts + 255) / 256 : 1; }
 
+// Interior residuals with first-order terms (Section 3.3: a residual that depends
+// on the derivatives non-linearly, e.g. the logarithmic Fokker-Planck equation of
+// Section 4):  r += sum_{i in mask} (c_x x_i d_i u + c_g (d_i u)^2) + c_0, whose
+// seed on derivative row i is c_x x_i + 2 c_g d_i u (point-dependent).
 template <typename TC, typename TP, typename TS>
 __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, long ldp,
                                                   const TP* __restrict__ y, int npts, int S,
                                                   int time_row, double c_t, double c_lap,
-                                                  int lap_row, double* __restrict__ r,
+                                                  int lap_row, ResidualTerms nl,
+                                                  double* __restrict__ r,
                                                   float* __restrict__ rf, TS* __restrict__ g,
                                                   long ldg,
                                                   double* __restrict__ partial) {
   __shared__ double red[4];
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool extra = lap_row >= 0 && nl.mask != nullptr;
+  const TP* xp = (const TP*)nl.x;
   double sq = 0.0;
   if (n < npts) {
     double v;
@@ -141,6 +150,14 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
       v = -(double)y[n];
       if (lap_row >= 0) v += c_lap * (double)pre[((long)lap_row * npts + n) * ldp];
       if (time_row >= 0) v += c_t * (double)pre[((long)time_row * npts + n) * ldp];
+      if (extra) {
+        v += nl.c_0;
+        for (int i = 0; i < nl.d; i++) {
+          if (nl.mask[i] == 0.0f) continue;
+          const double du = (double)pre[((long)(1 + i) * npts + n) * ldp];
+          v += (nl.c_x * (double)xp[(long)n * nl.d + i] + nl.c_g * du) * du;
+        }
+      }
     } else {
       v = (double)pre[(long)n * ldp] - (double)y[n];   // boundary: r = u - g
     }
@@ -154,6 +171,10 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
         else {
           if (s == lap_row) sv += c_lap;
           if (s == time_row) sv += c_t;
+          if (extra && s >= 1 && s <= nl.d && nl.mask[s - 1] != 0.0f) {
+            const double du = (double)pre[((long)s * npts + n) * ldp];
+            sv += nl.c_x * (double)xp[(long)n * nl.d + s - 1] + 2.0 * nl.c_g * du;
+          }
         }
         const long row = (long)s * npts + n;
         g[row * ldg] = cvt<TS>(sv);
@@ -168,25 +189,25 @@ __global__ __launch_bounds__(256) void k_residual(const TC* __restrict__ pre, lo
 }
 
 hipError_t residual(Prec p, const void* pre, long ldp, const void* y, int npts, int S,
-                    int time_row, double c_t, double c_lap, int lap_row, double* r, float* rf, void* g,
-                    long ldg, double* partial, hipStream_t st) {
+                    int time_row, double c_t, double c_lap, int lap_row, const ResidualTerms& nl,
+                    double* r, float* rf, void* g, long ldg, double* partial, hipStream_t st) {
   int nb = residual_blocks(npts);
   switch (p) {
     case P_F64:
       k_residual<double, double, double><<<nb, 256, 0, st>>>(
-          (const double*)pre, ldp, (const double*)y, npts, S, time_row, c_t, c_lap, lap_row, r, rf,
+          (const double*)pre, ldp, (const double*)y, npts, S, time_row, c_t, c_lap, lap_row, nl, r, rf,
           (double*)g, ldg, partial);
       break;
     case P_F32:
       k_residual<float, float, float><<<nb, 256, 0, st>>>((const float*)pre, ldp,
                                                           (const float*)y, npts, S, time_row, c_t,
-                                                          c_lap, lap_row, r, rf, (float*)g, ldg,
+                                                          c_lap, lap_row, nl, r, rf, (float*)g, ldg,
                                                           partial);
       break;
     case P_BF16:
       k_residual<float, float, bf16><<<nb, 256, 0, st>>>((const float*)pre, ldp, (const float*)y,
                                                          npts, S, time_row, c_t, c_lap, lap_row,
-                                                         r, rf, (bf16*)g, ldg, partial);
+                                                         nl, r, rf, (bf16*)g, ldg, partial);
       break;
   }
   return hipGetLastError();
@@ -216,41 +237,56 @@ hipError_t finalize_loss(const double* partial, int nb, double scale, double* lo
 // ---------------------------------------------------------------------------
 // Forward-Laplacian outputs and general seeds (autograd entry points)
 // ---------------------------------------------------------------------------
+// With input directions v_k (rows 1..d hold the derivatives along v_k, V
+// orthogonal) the gradient is grad_i = sum_k V[i][k] d_k u, dirs[k*d + i] = V[i][k].
 template <typename TC, typename TP>
 __global__ void k_extract(const TC* __restrict__ pre, long ldp, int npts, int S, int d,
-                          int lap_row, TP* u, TP* grad, TP* lap) {
+                          int lap_row, const double* __restrict__ dirs, TP* u, TP* grad, TP* lap) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= npts) return;
   if (u) u[n] = (TP)pre[(long)n * ldp];
-  if (grad)
+  if (grad && dirs)
+    for (int i = 0; i < d; i++) {
+      double g = 0.0;
+      for (int k = 0; k < d; k++)
+        g += dirs[(long)k * d + i] * (double)pre[((long)(1 + k) * npts + n) * ldp];
+      grad[(long)n * d + i] = (TP)g;
+    }
+  else if (grad)
     for (int i = 0; i < d; i++) grad[(long)n * d + i] = (TP)pre[((long)(1 + i) * npts + n) * ldp];
   if (lap) lap[n] = lap_row >= 0 ? (TP)pre[((long)lap_row * npts + n) * ldp] : (TP)0;
 }
 
 hipError_t extract_outputs(Prec p, const void* pre, long ldp, int npts, int S, int d, int lap_row,
-                           void* u, void* grad, void* lap, hipStream_t st) {
+                           const double* dirs, void* u, void* grad, void* lap, hipStream_t st) {
   int nb = (npts + 255) / 256;
   if (nb < 1) return hipSuccess;
   if (p == P_F64)
     k_extract<double, double><<<nb, 256, 0, st>>>((const double*)pre, ldp, npts, S, d, lap_row,
-                                                  (double*)u, (double*)grad, (double*)lap);
+                                                  dirs, (double*)u, (double*)grad, (double*)lap);
   else
     k_extract<float, float><<<nb, 256, 0, st>>>((const float*)pre, ldp, npts, S, d, lap_row,
-                                                (float*)u, (float*)grad, (float*)lap);
+                                                dirs, (float*)u, (float*)grad, (float*)lap);
   return hipGetLastError();
 }
 
+// The cotangent of grad u enters row k as sum_i V[i][k] grad_bar_i with input
+// directions (the transpose of k_extract's map).
 template <typename TP, typename TS>
 __global__ void k_seed(const TP* __restrict__ ub, const TP* __restrict__ gb,
-                       const TP* __restrict__ lb, int npts, int S, int d, int lap_row, TS* g,
-                       long ldg) {
+                       const TP* __restrict__ lb, int npts, int S, int d, int lap_row,
+                       const double* __restrict__ dirs, TS* g, long ldg) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= npts) return;
   for (int s = 0; s < S; s++) {
     double v = 0.0;
     if (s == 0) v = ub ? (double)ub[n] : 0.0;
     else if (s == lap_row) v = lb ? (double)lb[n] : 0.0;
-    else if (s <= d) v = gb ? (double)gb[(long)n * d + s - 1] : 0.0;
+    else if (s <= d && gb && dirs) {
+      for (int i = 0; i < d; i++) v += dirs[(long)(s - 1) * d + i] * (double)gb[(long)n * d + i];
+    } else if (s <= d) {
+      v = gb ? (double)gb[(long)n * d + s - 1] : 0.0;
+    }
     const long row = (long)s * npts + n;
     g[row * ldg] = cvt<TS>(v);
     for (int c = 1; c < ldg; c++) g[row * ldg + c] = cvt<TS>(0.0);
@@ -258,24 +294,25 @@ __global__ void k_seed(const TP* __restrict__ ub, const TP* __restrict__ gb,
 }
 
 hipError_t seed_rows(Prec p, const void* u_bar, const void* grad_bar, const void* lap_bar,
-                     int npts, int S, int d, int lap_row, void* g, long ldg, hipStream_t st) {
+                     int npts, int S, int d, int lap_row, const double* dirs, void* g, long ldg,
+                     hipStream_t st) {
   int nb = (npts + 255) / 256;
   if (nb < 1) return hipSuccess;
   switch (p) {
     case P_F64:
       k_seed<double, double><<<nb, 256, 0, st>>>((const double*)u_bar, (const double*)grad_bar,
                                                  (const double*)lap_bar, npts, S, d, lap_row,
-                                                 (double*)g, ldg);
+                                                 dirs, (double*)g, ldg);
       break;
     case P_F32:
       k_seed<float, float><<<nb, 256, 0, st>>>((const float*)u_bar, (const float*)grad_bar,
                                                (const float*)lap_bar, npts, S, d, lap_row,
-                                               (float*)g, ldg);
+                                               dirs, (float*)g, ldg);
       break;
     case P_BF16:
       k_seed<float, bf16><<<nb, 256, 0, st>>>((const float*)u_bar, (const float*)grad_bar,
                                               (const float*)lap_bar, npts, S, d, lap_row,
-                                              (bf16*)g, ldg);
+                                              dirs, (bf16*)g, ldg);
       break;
   }
   return hipGetLastError();

@@ -19,7 +19,10 @@ struct FwdLayerArgs {
   long ldw;
   int K;             // h_in + 1 rounded up to 8
   int N, S, nd, has_lap, h_out;
-  const uint8_t* mask;   // nd entries
+  const float* wts;  // nd weights of the derivative rows' squares in the second-order row
+  const double* wts64;  // the same weights in FP64 (read by FP64 work)
+  const double* dirs;   // input-layer directions, nd rows of d (nullptr: unit vectors)
+  int d;             // input dimension (directions)
   void* z;           // output slab (row length ldzo): tanh rows, bias column, zeros
   long ldzo;
   void* pre;         // optional pre-activations (row length ldp)
@@ -42,7 +45,8 @@ struct BwdLayerArgs {
   long ldw;
   int K;             // next layer's width rounded up to 8
   int N, S, nd, has_lap, h;
-  const uint8_t* mask;
+  const float* wts;  // nd weights (see FwdLayerArgs)
+  const double* wts64;
   const void* pre;   // this layer's pre-activations (row length ldp)
   long ldp;
   const void* sq;    // N*h: sum over masked derivative rows of pre^2
@@ -62,8 +66,9 @@ hipError_t fwdlap_pair(int mode, const FwdLayerArgs& a, int nch, const FwdLayerA
                        hipStream_t st);
 hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
 // The input layer's derivative and Laplacian rows without products: its input
-// rows are unit vectors and zero, so a_i = W[:, i] for every point and a_Lap = 0.
-// Writes z for rows s >= 1 (z_i = s1 W[:, i], z_Lap = s2 sum_{i in mask} W[:, i]^2),
+// rows are the directions v_k (unit vectors e_k by default) and zero, so
+// a_k = W v_k for every point and a_Lap = 0.  Writes z for rows s >= 1
+// (z_k = s1 W v_k, z_Lap = s2 sum_k w_k (W v_k)^2),
 // the bias column and padding of every row, pre and sq_out when given.  Reads t
 // from tab_t (written by the value-only product).  q: scratch of (nd + 1) * h_out
 // values of the compute type.

@@ -491,12 +491,20 @@ __device__ __forceinline__ void sloop_dma(char* lds, const typename Op<MODE>::TL
   __syncthreads();
 }
 
-// Entry i of the derivative mask, read through the scalar cache (the mask is
-// read-only during a launch and its allocation is padded to whole words).
-__device__ __forceinline__ bool mask_at(const uint8_t* mask, int i) {
-  const __attribute__((address_space(4))) uint32_t* w =
-      (const __attribute__((address_space(4))) uint32_t*)mask;
-  return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu;
+// Weight of derivative row i in the second-order row (1 or 0 for a Laplacian
+// over a subset of the coordinates), read through the scalar cache (the weights
+// are read-only during a launch).
+__device__ __forceinline__ float wt_at(const float* wts, int i) {
+  return ((const __attribute__((address_space(4))) float*)wts)[i];
+}
+// The weight in the compute type: FP64 work reads the FP64 copy (eigenvalues of
+// a coefficient matrix are not exact in FP32).
+template <typename TC, typename Args>
+__device__ __forceinline__ TC wt_of(const Args& a, int i) {
+  if constexpr (std::is_same<TC, double>::value)
+    return ((const __attribute__((address_space(4))) double*)a.wts64)[i];
+  else
+    return (TC)wt_at(a.wts, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -593,13 +601,14 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
         return (TC*)tab + (long)(P(0, 0) + i * 16) * a.h_out + cb0;
       };
       if (kind == 1) {
-        if (mask_at(a.mask, s - 1)) {
+        const float wk = wt_at(a.wts, s - 1);
+        if (wk != 0.0f) {
 #pragma unroll
           for (int i = 0; i < G::TI; i++)
 #pragma unroll
             for (int j = 0; j < G::TJ; j++)
 #pragma unroll
-              for (int e = 0; e < 4; e++) sq[i][j][e] += acc[i][j][e] * acc[i][j][e];
+              for (int e = 0; e < 4; e++) sq[i][j][e] += (wk * acc[i][j][e]) * acc[i][j][e];
         }
         if (keep) {
 #pragma unroll
@@ -655,7 +664,7 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
       return;
     }
     const bool is_d = s >= 1 && s <= nd;
-    const TC m = (is_d && mask_at(a.mask, s - 1)) ? (TC)1 : (TC)0;
+    const TC m = is_d ? wt_of<TC>(a, s - 1) : (TC)0;
     const int kind = s == 0 ? 0 : (is_d ? 1 : 2);
     // whether this z row is stored (the Laplacian row is finished separately)
     const bool keep = !a.sparse_store || (kind == 0 ? a.keep_value != 0
@@ -841,7 +850,7 @@ __global__ __launch_bounds__(kThreads) void k_bwdlap_vec(BwdLayerArgs a) {
           }
         }
     } else if (s >= 1 && s <= nd) {   // derivative row
-      const bool m = mask_at(a.mask, s - 1);
+      const float m2 = 2.f * wt_at(a.wts, s - 1);
 #pragma unroll
       for (int i = 0; i < G::TI; i++)
 #pragma unroll
@@ -850,7 +859,7 @@ __global__ __launch_bounds__(kThreads) void k_bwdlap_vec(BwdLayerArgs a) {
           const f32x4 da = *gmem((const f32x4*)(pre + ((long)s * a.N + pp[i]) * a.ldp + cc[j]));
           sum1[i][j] += da * acc[i][j];
           f32x4 o = s1[i][j] * acc[i][j];
-          if (m) o += 2.f * s2[i][j] * da * lb[i][j];
+          if (m2 != 0.f) o += m2 * s2[i][j] * da * lb[i][j];
           *gmem((f32x4*)(grow(i) + cc[j])) = o;
         }
     } else {   // value row (chunk 0)
@@ -929,7 +938,7 @@ __global__ __launch_bounds__(kThreads) void k_bwdlap(BwdLayerArgs a) {
   auto epi = [&](int st, int s, typename MF::acc (&acc)[G::TI][G::TJ]) {
     const bool is_lap = hl && st == 0;
     const bool is_d = !is_lap && s >= 1 && s <= nd;
-    const TC m = (is_d && a.mask[s - 1]) ? (TC)1 : (TC)0;
+    const TC m = is_d ? wt_of<TC>(a, s - 1) : (TC)0;
 #pragma unroll
     for (int i = 0; i < G::TI; i++)
 #pragma unroll
@@ -1110,7 +1119,7 @@ __global__ void k_bwd_last(BwdLayerArgs a, const TSd* __restrict__ sigma, long l
     const long row = (long)s * a.N + p;
     const TC da = pre[row * a.ldp + c];
     const TC zb = sig(s) * w;
-    const TC m = a.mask[i] ? (TC)1 : (TC)0;
+    const TC m = wt_of<TC>(a, i);
     sum1 += da * zb;
     sq += m * da * da;
     g[row * a.ldgo + c] = cvt<TG>((double)(s1 * zb + (TC)2 * m * s2 * da * lb));
@@ -1126,7 +1135,7 @@ __global__ void k_bwd_last(BwdLayerArgs a, const TSd* __restrict__ sigma, long l
 // ---------------------------------------------------------------------------
 // Per neuron c: the input layer's weights of the derivative rows, stored
 // transposed (wt[i * h_out + c] = W[c, i] in the product precision, W = hi [+ lo])
-// so that row writers read them coalesced, and q[c] = sum_{i in mask} W[c, i]^2.
+// so that row writers read them coalesced, and q[c] = sum_i w_i W[c, i]^2.
 // A block of 256 threads takes 64 neurons and walks the inputs 64 at a time
 // through an LDS tile, so that both the weight reads (along i) and the wt
 // writes (along c) are coalesced; q is summed in four interleaved partial sums
@@ -1158,7 +1167,7 @@ __global__ __launch_bounds__(256) void k_input_q(FwdLayerArgs a, TC* __restrict_
       if (c < a.h_out && i < a.nd) {
         const TC v = tile[lo][ir];
         wt[(long)i * a.h_out + c] = v;
-        if (mask_at(a.mask, i)) sum += v * v;
+        sum += wt_of<TC>(a, i) * v * v;
       }
     }
     __syncthreads();
@@ -1167,6 +1176,31 @@ __global__ __launch_bounds__(256) void k_input_q(FwdLayerArgs a, TC* __restrict_
   __syncthreads();
   if (hi == 0 && c0 + lo < a.h_out)
     q[c0 + lo] = ((part[0][lo] + part[1][lo]) + part[2][lo]) + part[3][lo];
+}
+
+// The same tables when the input layer's derivative rows are general directions
+// v_k (a weighted second-order operator propagated along the eigenvectors of its
+// coefficient matrix): wt[k * h_out + c] = (W v_k)[c] and q[c] = sum_k w_k
+// (W v_k)[c]^2, one thread per neuron, accumulated in FP64 over the d inputs.
+template <typename TW, typename TC>
+__global__ __launch_bounds__(256) void k_input_q_dirs(FwdLayerArgs a, TC* __restrict__ q,
+                                                      TC* __restrict__ wt) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.h_out) return;
+  const TW* w = (const TW*)a.w + (long)c * a.ldw;
+  const TW* w2 = a.w2 ? (const TW*)a.w2 + (long)c * a.ldw : nullptr;
+  double sum = 0.0;
+  for (int k = 0; k < a.nd; k++) {
+    const double* v = a.dirs + (long)k * a.d;
+    double acc = 0.0;
+    for (int i = 0; i < a.d; i++) {
+      const double wi = to_d(w[i]) + (w2 ? to_d(w2[i]) : 0.0);
+      acc += wi * v[i];
+    }
+    wt[(long)k * a.h_out + c] = (TC)acc;
+    sum += a.wts64[k] * acc * acc;
+  }
+  q[c] = (TC)sum;
 }
 
 // Eight consecutive values to z (one 16-byte store for BF16, two for FP32).
@@ -1469,30 +1503,44 @@ hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_
   if (!a.has_lap || a.S != a.nd + 2) return hipErrorInvalidValue;
   if (a.ldzo % 8) return hipErrorInvalidValue;
   const int nq = (a.h_out + 63) / 64;
+  const int nd256 = (a.h_out + 255) / 256;
+  if (a.dirs && a.d <= 0) return hipErrorInvalidValue;
   const long rows = (long)a.S * a.N;
   const int g = (int)std::min<long>(4096, (rows + 3) / 4);   // 4 rows (waves) per block
   switch (mode) {
     case M_F64: {
       double* qq = (double*)q;
-      k_input_q<double, double><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
+      if (a.dirs)
+        k_input_q_dirs<double, double><<<nd256, 256, 0, st>>>(a, qq, qq + a.h_out);
+      else
+        k_input_q<double, double><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<double, double><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }
     case M_F32: {
       float* qq = (float*)q;
-      k_input_q<float, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
+      if (a.dirs)
+        k_input_q_dirs<float, float><<<nd256, 256, 0, st>>>(a, qq, qq + a.h_out);
+      else
+        k_input_q<float, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }
     case M_BF16: {
       float* qq = (float*)q;
-      k_input_q<bf16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
+      if (a.dirs)
+        k_input_q_dirs<bf16, float><<<nd256, 256, 0, st>>>(a, qq, qq + a.h_out);
+      else
+        k_input_q<bf16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<float, bf16><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }
     case M_BF16X3: {
       float* qq = (float*)q;
-      k_input_q<bf16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
+      if (a.dirs)
+        k_input_q_dirs<bf16, float><<<nd256, 256, 0, st>>>(a, qq, qq + a.h_out);
+      else
+        k_input_q<bf16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
       k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }

@@ -9,6 +9,12 @@
 // stored: J_n d = sum_l sum_s g^(l)_{n,s}^T D^(l) z~^(l-1)_{n,s}, with g the
 // output gradients of the backward pass and D^(l) the direction's layer block.
 // No extra forward pass is needed.
+//
+// The same slabs give the exact Gramian block of a layer (Section 3.2,
+// Eq. laplace_gramian_block_exact): J_n = sum_s z~_{n,s} (x) g_{n,s} per point,
+// then G = J^T J / N.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -148,6 +154,46 @@ hipError_t jvp_layer(Prec p, const void* zin, long ldz, const void* g, long ldg,
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// work[n * p + k * H + j] = sum_s Z[s N + n][k] G[s N + n][j]  (p = K H): the
+// per-point Jacobian of the residual with respect to the layer's parameters in
+// the theta layout (column-stacked [W | b], so entry (j, k) sits at k H + j).
+template <typename T>
+__global__ void k_layer_jac(const T* __restrict__ Z, long ldz, const T* __restrict__ G, long ldg,
+                            int N, int S, int K, int H, double* __restrict__ work) {
+  const long p = (long)K * H;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (long)N * p;
+       e += (long)gridDim.x * blockDim.x) {
+    const int n = (int)(e / p);
+    const long q = e - (long)n * p;
+    const int k = (int)(q / H), j = (int)(q - (long)k * H);
+    double v = 0.0;
+    for (int s = 0; s < S; s++) {
+      const long row = (long)s * N + n;
+      v += to_d(Z[row * ldz + k]) * to_d(G[row * ldg + j]);
+    }
+    work[e] = v;
+  }
+}
+
+hipError_t layer_gramian(Prec p, const void* zin, long ldz, const void* g, long ldg, int n, int S,
+                         int K, int H, double* work, double* out, hipStream_t st) {
+  const long np = (long)K * H;
+  const long tot = (long)n * np;
+  const int nb = (int)std::min<long>(16384, (tot + 255) / 256);
+  if (p == P_F64)
+    k_layer_jac<double><<<nb, 256, 0, st>>>((const double*)zin, ldz, (const double*)g, ldg, n, S, K,
+                                           H, work);
+  else if (p == P_F32)
+    k_layer_jac<float><<<nb, 256, 0, st>>>((const float*)zin, ldz, (const float*)g, ldg, n, S, K,
+                                          H, work);
+  else
+    return hipErrorInvalidValue;
+  if (hipError_t e = hipGetLastError()) return e;
+  // out = J^T J / n on the FP64 matrix unit: A(i, k) = J[k][i], B(k, j) = J[k][j]
+  G64 d{work, 1, np, work, np, 1, out, np, 1, (int)np, (int)np, n, 1.0 / n, nullptr, nullptr};
+  return gemm64_one(d, st);
 }
 
 // ---------------------------------------------------------------------------

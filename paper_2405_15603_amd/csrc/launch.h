@@ -45,10 +45,11 @@ hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha
                         void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st,
                         int fwd_only = 0);
 
-// Input slab Z~^(0): S rows per point (value x, unit rows e_i, zero Laplacian row)
-// plus the bias column; n points, d inputs, row length ldz.
-hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long ldz,
-                      hipStream_t st);
+// Input slab Z~^(0): S rows per point (value x, unit rows e_i or the directions
+// dirs[k*d .. k*d + d) when dirs is given, zero Laplacian row) plus the bias
+// column; n points, d inputs, row length ldz.
+hipError_t input_slab(Prec p, const void* x, int n, int d, int S, const double* dirs, void* z,
+                      long ldz, hipStream_t st);
 
 // Residual, loss partials and the output seed.  pre: last layer output rows
 // (compute type, ldp); y: targets (real); r: residual per point (double) and
@@ -56,19 +57,31 @@ hipError_t input_slab(Prec p, const void* x, int n, int d, int S, void* z, long 
 // g: seed rows (storage type, ldg; nullptr = not written); partial: per-block
 // sums of r^2 (double, grid size returned by residual_blocks).
 int residual_blocks(int npts);
+// Terms of an interior residual beyond c_t d_t u + c_lap Lu - y (inactive when
+// mask is null): sum_{i: mask[i] != 0} (c_x x_i d_i u + c_g (d_i u)^2) + c_0, with
+// x the points (real, row-major npts x d) and d_i u output row 1 + i.
+struct ResidualTerms {
+  const void* x = nullptr;
+  const float* mask = nullptr;
+  int d = 0;
+  double c_x = 0.0, c_g = 0.0, c_0 = 0.0;
+};
 hipError_t residual(Prec p, const void* pre, long ldp, const void* y, int npts, int S,
-                    int time_row, double c_t, double c_lap, int lap_row, double* r, float* rf,
-                    void* g, long ldg, double* partial, hipStream_t st);
+                    int time_row, double c_t, double c_lap, int lap_row, const ResidualTerms& nl,
+                    double* r, float* rf, void* g, long ldg, double* partial, hipStream_t st);
 // loss[slot] = scale * sum(partial[0..nb)) (+ loss[slot] if accumulate)
 hipError_t finalize_loss(const double* partial, int nb, double scale, double* loss, int slot,
                          int accumulate, hipStream_t st);
 
-// Network outputs for the forward-Laplacian entry point: u, grad, lap (real).
+// Network outputs for the forward-Laplacian entry point: u, grad, lap (real);
+// with input directions (dirs, nullable) the gradient is mapped back to the
+// coordinate axes.
 hipError_t extract_outputs(Prec p, const void* pre, long ldp, int npts, int S, int d, int lap_row,
-                           void* u, void* grad, void* lap, hipStream_t st);
+                           const double* dirs, void* u, void* grad, void* lap, hipStream_t st);
 // Output seed rows of a general cotangent (u_bar, grad_bar, lap_bar; real, nullable).
 hipError_t seed_rows(Prec p, const void* u_bar, const void* grad_bar, const void* lap_bar,
-                     int npts, int S, int d, int lap_row, void* g, long ldg, hipStream_t st);
+                     int npts, int S, int d, int lap_row, const double* dirs, void* g, long ldg,
+                     hipStream_t st);
 // x_bar[n][k] = sum_j W1[j][k] g1[n*S][j]  (value row of the first layer)
 hipError_t input_vjp(Prec p, const void* theta, int h_out, int d, const void* g1, long ldg,
                      int npts, int S, void* x_bar, hipStream_t st);
@@ -192,6 +205,14 @@ struct G64 {                // C[i*sci + j*scj] = alpha sum_k A(i,k) B(k,j) [/(1
 void kron_apply_descs(const KronApply* layers, int L, const double* grad, double* delta,
                       double* tmp, long tmp_stride, G64* h, int* mmax, int* nmax);
 hipError_t kron_apply_batched(const G64* descs_dev, int L, int mmax, int nmax, hipStream_t st);
+// One FP64 product C = alpha A B (+ the optional scaling) with its descriptor as
+// the kernel argument.
+hipError_t gemm64_one(const G64& g, hipStream_t st);
+// Exact Gramian block of one layer and term from its stored slabs (slab type
+// P_F64 / P_F32): work (n x p doubles, p = K H) receives the per-point Jacobians
+// sum_s z~_{n,s} (x) g_{n,s}, out (p x p doubles) J^T J / n.
+hipError_t layer_gramian(Prec p, const void* zin, long ldz, const void* g, long ldg, int n, int S,
+                         int K, int H, double* work, double* out, hipStream_t st);
 // The same for one layer (layer.off ignored: grad and delta point at the layer's
 // block) with its two intermediate products in a static device array of
 // 2 * kKronScratchElems doubles and the descriptors as kernel arguments: nothing

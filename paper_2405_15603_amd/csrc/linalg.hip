@@ -998,6 +998,11 @@ __global__ __launch_bounds__(256) void k_gemm64(const G64* __restrict__ gs) {
 // one product whose descriptor travels as the kernel argument
 __global__ __launch_bounds__(256) void k_gemm64_arg(const G64 g) { gemm64_tile(g); }
 
+hipError_t gemm64_one(const G64& g, hipStream_t st) {
+  k_gemm64_arg<<<dim3(kp_cdiv(g.N, BB), kp_cdiv(g.M, BB), 1), 256, 0, st>>>(g);
+  return hipGetLastError();
+}
+
 void kron_apply_descs(const KronApply* layers, int L, const double* grad, double* delta,
                       double* tmp, long tmp_stride, G64* h, int* mmax, int* nmax) {
   *mmax = 0;

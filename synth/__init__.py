@@ -118,6 +118,7 @@ def sample_initial(seed: int, step: int, n: int, d: int) -> np.ndarray:
 
 POISSON = "poisson"
 HEAT = "heat"
+LOGFP = "logfp"   # logarithmic Fokker-Planck equation (Section 4, Appendix A)
 
 
 @dataclass
@@ -138,6 +139,7 @@ class Problem:
     problem_id: int = 0
     resample: bool = False
     lam: float = 1e-3
+    op_coef: Optional[np.ndarray] = None   # C of sum_ij C_ij d2/dx_i dx_j (None: the mask)
 
     @property
     def d(self) -> int:
@@ -145,20 +147,34 @@ class Problem:
 
     @property
     def time_coord(self) -> int:
-        return 0 if self.kind == HEAT else -1
+        return 0 if self.kind in (HEAT, LOGFP) else -1
 
     @property
     def coef_time(self) -> float:
-        return 1.0 if self.kind == HEAT else 0.0
+        return 1.0 if self.kind in (HEAT, LOGFP) else 0.0
 
     @property
     def coef_lap(self) -> float:
         return -self.kappa if self.kind == HEAT else -1.0
 
+    # first-order terms of the residual: the logarithmic Fokker-Planck equation
+    # d_t q - d_x/2 - (1/2) x . grad q - |grad q|^2 - Lap q = 0 (d_x spatial dims)
+    @property
+    def coef_xgrad(self) -> float:
+        return -0.5 if self.kind == LOGFP else 0.0
+
+    @property
+    def coef_gradsq(self) -> float:
+        return -1.0 if self.kind == LOGFP else 0.0
+
+    @property
+    def coef_const(self) -> float:
+        return -0.5 * (self.d - 1) if self.kind == LOGFP else 0.0
+
     @property
     def lap_mask(self) -> np.ndarray:
         m = np.ones(self.d, dtype=np.uint8)
-        if self.kind == HEAT:
+        if self.kind in (HEAT, LOGFP):
             m[0] = 0
         return m
 
@@ -171,6 +187,11 @@ class Problem:
 
     # manufactured solutions -------------------------------------------------
     def u_star(self, x: np.ndarray) -> np.ndarray:
+        if self.kind == LOGFP:
+            # q* = log p*, p*(t) = N(0, s2(t) I) with s2(t) = e^-t + 2 (1 - e^-t)
+            s2 = 2.0 - np.exp(-x[:, 0])
+            k = self.d - 1
+            return -0.5 * k * np.log(2 * math.pi * s2) - (x[:, 1:] ** 2).sum(1) / (2 * s2)
         if self.kind == HEAT:
             t = x[:, 0]
             return np.exp(-self.kappa * math.pi ** 2 * t) * np.sin(math.pi * x[:, 1:]).sum(1)
@@ -179,9 +200,13 @@ class Problem:
         return self.scale * np.sin(math.pi * x).sum(1)
 
     def f_rhs(self, x: np.ndarray) -> np.ndarray:
-        """Interior target y: f = -Lap u* for Poisson, 0 for heat."""
-        if self.kind == HEAT:
+        """Interior target y: f = -Lap u* for Poisson, 0 for heat; with a coefficient
+        matrix C, f = -sum_ij C_ij d2u*/dx_i dx_j, which for u* = c sum sin(pi x_i)
+        (no mixed derivatives) is c pi^2 sum_i C_ii sin(pi x_i)."""
+        if self.kind in (HEAT, LOGFP):
             return np.zeros(x.shape[0])
+        if self.op_coef is not None:
+            return self.scale * math.pi ** 2 * (np.sin(math.pi * x) * np.diag(self.op_coef)).sum(1)
         if self.name == "poisson2d":
             return 2 * math.pi ** 2 * np.sin(math.pi * x[:, 0]) * np.sin(math.pi * x[:, 1])
         return self.scale * math.pi ** 2 * np.sin(math.pi * x).sum(1)
@@ -198,6 +223,13 @@ class Problem:
         d = self.d
         st = step if self.resample else 0
         xi = sample_interior(self.seed(PURPOSE_INTERIOR), st, self.n_interior, d)
+        if self.kind == LOGFP:
+            # t in [0, 1), x in [-5, 5)^(d-1); the loss has the residual and the
+            # initial condition q(0, .) = log p*(0, .) only (no spatial boundary)
+            xi[:, 1:] = 10.0 * xi[:, 1:] - 5.0
+            x0 = sample_initial(self.seed(PURPOSE_INITIAL), st, self.n_initial, d)
+            x0[:, 1:] = 10.0 * x0[:, 1:] - 5.0
+            return xi, self.f_rhs(xi), x0, self.u_star(x0)
         face_lo = 1 if self.kind == HEAT else 0
         xb = sample_boundary(self.seed(PURPOSE_BOUNDARY), st, self.n_boundary, d, face_lo)
         if self.n_initial:
@@ -233,11 +265,35 @@ def heat4d() -> Problem:
                    problem_id=4)
 
 
+def log_fokker_planck(widths=(10, 256, 256, 128, 128, 1), n_int: int = 3000,
+                      n_init: int = 1000, problem_id: int = 7) -> Problem:
+    """(9+1)-d logarithmic Fokker-Planck equation of Section 4 / Appendix A:
+    drift -x/2, diffusion sqrt(2) I, on [0, 1] x [-5, 5]^9; solution
+    q* = log N(0, (2 - e^-t) I); 10->256->256->128->128->1 (D = 118 145)."""
+    return Problem("logfp10d", LOGFP, list(widths), n_int, 0, n_initial=n_init,
+                   problem_id=problem_id)
+
+
+def anisotropic(d: int = 8, widths=None, n_int: int = 600, n_bnd: int = 160,
+                problem_id: int = 6, scale: float = 1.0) -> Problem:
+    """Poisson-type problem -sum_ij C_ij d2u/dx_i dx_j = f with a dense symmetric
+    positive-definite C = B B^T / d + I/2 (B uniform in [-1, 1), seeded) and
+    u* = c sum sin(pi x_i): the general second-order operator of the paper's
+    Section 3.1 / Appendix C.3 on the unit cube."""
+    u = uniform(1000 * problem_id + PURPOSE_INSTANCES, 0, d * d).reshape(d, d)
+    B = 2.0 * u - 1.0
+    C = B @ B.T / d + 0.5 * np.eye(d)
+    widths = list(widths) if widths is not None else [d, 64, 64, 48, 48, 1]
+    return Problem(f"aniso{d}d", POISSON, widths, n_int, n_bnd, problem_id=problem_id,
+                   scale=scale, op_coef=C)
+
+
 def small_problem(kind: str = POISSON, widths=(3, 8, 8, 1), n_int: int = 7, n_bnd: int = 5,
-                  n_init: int = 0, problem_id: int = 90, scale: float = 1.0) -> Problem:
+                  n_init: int = 0, problem_id: int = 90, scale: float = 1.0,
+                  op_coef=None) -> Problem:
     """A tiny problem for pins and fast parity cases."""
     return Problem(f"small_{kind}", kind, list(widths), n_int, n_bnd, n_initial=n_init,
-                   problem_id=problem_id, scale=scale)
+                   problem_id=problem_id, scale=scale, op_coef=op_coef)
 
 
 def batch_instances(count: int = 64, seed: int = 5005) -> List[Problem]:
@@ -259,4 +315,4 @@ def batch_instances(count: int = 64, seed: int = 5005) -> List[Problem]:
 
 
 PROBLEMS = {"poisson2d": poisson2d, "poisson5d": poisson5d, "poisson100d": poisson100d,
-            "heat4d": heat4d}
+            "heat4d": heat4d, "logfp10d": log_fokker_planck, "aniso8d": lambda: anisotropic()}

@@ -1,0 +1,126 @@
+"""The weighted second-order operator sum_ij C_ij d2/dx_i dx_j (Section 3.1, closing
+paragraph; Appendix C.3) through the C ABI against the oracle, which propagates the
+paper's coordinate directions with the collapsed quadratic form while the GPU
+propagates along C's eigenvectors (the factors are invariant under that orthogonal
+change of directions, a CPU pin).  Dense positive-definite C (anisotropic Poisson),
+an indefinite C, and a parabolic operator whose time coordinate is left out of C."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import blockwise, oracle_curvature, problem_inputs, rel, rounded, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def indefinite(d, seed):
+    u = synth.uniform(seed, 0, d * d).reshape(d, d)
+    A = 2 * u - 1
+    return (A + A.T) / 2
+
+
+CASES = {
+    "aniso_small": lambda: synth.small_problem("poisson", (4, 24, 17, 1), 53, 19, problem_id=84,
+                                               op_coef=synth.anisotropic(4).op_coef),
+    "aniso8d": synth.anisotropic,
+    "indefinite": lambda: synth.small_problem("poisson", (5, 33, 20, 9, 1), 77, 21, problem_id=85,
+                                              op_coef=indefinite(5, 8585)),
+    "parabolic": lambda: synth.small_problem(
+        "heat", (4, 20, 12, 1), 41, 13, n_init=7, problem_id=86,
+        op_coef=np.pad(synth.anisotropic(3).op_coef, ((1, 0), (1, 0)))),
+}
+
+
+def kp_for(p, precision, **kw):
+    from paper_2405_15603_amd import KfacPinn
+    return KfacPinn.for_problem(p, precision, **kw)
+
+
+def oracle_rows(p, th, xi):
+    op = oracle.operator_of(p)
+    return oracle.forward_laplacian(oracle.unpack(torch.as_tensor(th), p.widths),
+                                    torch.as_tensor(xi), op.second_order(p.d)).out
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_forward_operator(case, precision, tol):
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, precision)
+    kp = kp_for(p, precision)
+    u, g, lap = kp.forward_laplacian(to_dev(th, precision), to_dev(xi, precision))
+    assert kp.sync() == 0
+    U = oracle_rows(p, th, xi)
+    for got, want in ((u, U[:, 0]), (g, U[:, 1:p.d + 1]), (lap, U[:, -1])):
+        assert rel(got, want) < tol and blockwise(got, want) < 10 * tol
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision,tol,gtol", [("f64", 1e-10, 1e-10), ("f32", 1e-5, 1e-4),
+                                                ("bf16", 1e-3, 2e-2)])
+def test_factors_gradient_loss(case, precision, tol, gtol):
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, precision)
+    kp = kp_for(p, precision)
+    grad, loss = kp.factors(*(to_dev(a, precision) for a in (th, xi, yi, xb, yb)), beta=0.0)
+    assert kp.sync() == 0
+    ref = oracle_curvature(p, th, xi, yi, xb, yb)
+    for l in range(len(p.widths) - 1):
+        for t, tn in ((0, "int"), (1, "bnd")):
+            for s, sn in ((0, "A"), (1, "B")):
+                got, want = kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l]
+                e = rel(got, want)
+                assert e < tol, (l, tn, sn, e)
+    assert rel(grad, ref["grad"]) < gtol
+    assert rel(loss, np.array(ref["loss"])) < gtol
+
+
+@pytest.mark.parametrize("case", ["aniso_small", "indefinite", "parabolic"])
+def test_full_step_f64(case):
+    """One full FP64 step (grid line search) and one fixed-step step with EMA and
+    momentum state, against the oracle: alpha* equal, theta within 1e-10."""
+    from paper_2405_15603_amd import HParams, KfacPinn
+    p = CASES[case]()
+    th, xi, yi, xb, yb = problem_inputs(p, "f64")
+    kp = kp_for(p, "f64")
+    dev = [to_dev(a, "f64") for a in (xi, yi, xb, yb)]
+    st = oracle.init_state(p.widths, True)
+    th_ref = torch.as_tensor(th)
+    tht = to_dev(th, "f64")
+    for hp_o, hp_g in [
+        (oracle.HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid"),
+         HParams(lam=1e-3, beta=0.886041, momentum=0.707588)),
+        (oracle.HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="fixed", lr=0.5),
+         HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="fixed", lr=0.5)),
+    ]:
+        info = KfacPinn.decode_info(kp.step(tht, *dev, hp_g))
+        assert kp.sync() == 0
+        th_ref, st, rinfo = oracle.kfac_step(th_ref, p.widths, (xi, yi, xb, yb),
+                                             oracle.operator_of(p), hp_o, st)
+        assert info["lr"] == rinfo.lr
+        assert rel(tht, th_ref) < 1e-10
+
+
+def test_vjp_f64():
+    """The adjoint with directions: theta_bar and x_bar of a random cotangent of
+    (u, grad u, C-operator row) against autodiff of the oracle."""
+    p = CASES["indefinite"]()
+    th, xi, _, _, _ = problem_inputs(p, "f64")
+    kp = kp_for(p, "f64")
+    g = torch.Generator().manual_seed(9)
+    n, d = xi.shape
+    ub, gb, lb = (torch.randn(n, generator=g, dtype=torch.float64),
+                  torch.randn(n, d, generator=g, dtype=torch.float64),
+                  torch.randn(n, generator=g, dtype=torch.float64))
+    tb, xbar = kp.forward_laplacian_vjp(to_dev(th, "f64"), to_dev(xi, "f64"), to_dev(ub, "f64"),
+                                        to_dev(gb, "f64"), to_dev(lb, "f64"))
+    assert kp.sync() == 0
+    tht = torch.as_tensor(th).clone().requires_grad_(True)
+    x = torch.as_tensor(xi).clone().requires_grad_(True)
+    U = oracle.forward_laplacian(oracle.unpack(tht, p.widths), x,
+                                 oracle.operator_of(p).second_order(d)).out
+    obj = (U[:, 0] * ub).sum() + (U[:, 1:d + 1] * gb).sum() + (U[:, -1] * lb).sum()
+    rt, rx = torch.autograd.grad(obj, (tht, x))
+    assert rel(tb, rt) < 1e-11 and rel(xbar, rx) < 1e-11

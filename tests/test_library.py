@@ -52,3 +52,25 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     w = (ctypes.c_int32 * 3)(2, 8, 1)
     prob = N.kp_problem(2, w, -1, 0.0, -1.0, None, 7, 10, 10, 0)
     assert L.kfac_pinn_create(ctypes.byref(prob), None, ctypes.byref(h)) == N.KP_ERR_ARG
+
+
+def test_create_rejects_bad_operator_coefficients():
+    """A coefficient matrix must be symmetric and finite, comes instead of a mask,
+    and with a time term leaves the time coordinate out of the second-order part."""
+    from paper_2405_15603_amd import _native as N
+    L = N.lib()
+    w = (ctypes.c_int32 * 3)(3, 8, 1)
+    h = ctypes.c_void_p()
+
+    def create(coef, time_coord=-1, c_t=0.0, mask=None):
+        cf = (ctypes.c_double * 9)(*coef)
+        prob = N.kp_problem(2, w, time_coord, c_t, -1.0, mask, N.KP_F64, 10, 10, 0, cf)
+        return L.kfac_pinn_create(ctypes.byref(prob), None, ctypes.byref(h))
+
+    assert create([1, 2, 0, 0, 1, 0, 0, 0, 1]) == N.KP_ERR_ARG
+    assert "symmetric" in L.kfac_pinn_last_error().decode()
+    assert create([1, 0, 0, 0, float("nan"), 0, 0, 0, 1]) == N.KP_ERR_ARG
+    assert create([1, 0, 0, 0, 1, 0.5, 0, 0.5, 1], time_coord=0, c_t=1.0) == N.KP_ERR_ARG
+    assert "time coordinate" in L.kfac_pinn_last_error().decode()
+    m = (ctypes.c_uint8 * 3)(1, 1, 1)
+    assert create([1, 0, 0, 0, 1, 0, 0, 0, 1], mask=m) == N.KP_ERR_ARG

@@ -15,7 +15,9 @@ import oracle
 import synth
 from oracle.kfac import DT
 
-OPS = {"poisson": oracle.POISSON_OP, "heat": oracle.Operator(0, 1.0, -0.25, (0, 1, 1))}
+OPS = {"poisson": oracle.POISSON_OP, "heat": oracle.Operator(0, 1.0, -0.25, (0, 1, 1)),
+       # a residual with first-order terms (Section 3.3): the log-Fokker-Planck form
+       "logfp": oracle.Operator(0, 1.0, -1.0, (0, 1, 1), None, -0.5, -1.0, -1.0)}
 
 
 def setup(widths=(3, 4, 3, 1), n=5, m=4, seed=0):
@@ -32,7 +34,7 @@ def residuals(th, widths, Xi, yi, Xb, yb, op):
     Ws = oracle.unpack(th, widths)
     fi = oracle.forward_laplacian(Ws, Xi, op.mask_vec(Xi.shape[1]))
     fb = oracle.forward_plain(Ws, Xb)
-    return oracle.interior_residual(fi.out, yi, op), oracle.boundary_residual(fb.out, yb)
+    return oracle.interior_residual(fi.out, yi, op, Xi), oracle.boundary_residual(fb.out, yb)
 
 
 def fd_jacobian(fun, th, sl, h=1e-5):
@@ -44,7 +46,7 @@ def fd_jacobian(fun, th, sl, h=1e-5):
     return torch.stack(cols, 1)
 
 
-@pytest.mark.parametrize("kind", ["poisson", "heat"])
+@pytest.mark.parametrize("kind", ["poisson", "heat", "logfp"])
 def test_per_point_jacobian_identity(kind):
     """J_{W^(l)} r_n = sum_s Z~_{n,s}^T (x) g_{n,s} (Section 3.2): with column
     stacking its entry (j, i) is sum_s Z~_{n,s,j} g_{n,s,i}.  Checked against FD."""
@@ -68,7 +70,7 @@ def test_per_point_jacobian_identity(kind):
         torch.testing.assert_close(G_exact, Ji.T @ Ji / Xi.shape[0], rtol=1e-6, atol=1e-8)
 
 
-@pytest.mark.parametrize("kind", ["poisson", "heat"])
+@pytest.mark.parametrize("kind", ["poisson", "heat", "logfp"])
 def test_gradient_matches_fd(kind):
     op = OPS[kind]
     widths, th, Xi, yi, Xb, yb = setup(seed=3)
