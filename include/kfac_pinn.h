@@ -234,7 +234,12 @@ kp_status kfac_pinn_layer_gramian(kfac_pinn_ctx* ctx, int32_t layer, int32_t ter
  * context (the identity after create/reset_state and on every 1000th call) and
  * runs until a sweep performs no rotation above its threshold, at most
  * max_sweeps sweeps (default 20), so the result does not depend on the start
- * beyond rounding.  Sets KP_ERR_NOT_PD in the device status when a damped
+ * beyond rounding.  When the context's stream is not being captured into a graph,
+ * the call reads each sweep's convergence flags back to the host one sweep later
+ * (so it waits on the host for all but its last sweep) and enqueues no further
+ * sweeps for problems that have all converged; under capture it enqueues all
+ * max_sweeps sweeps.  Both give the same result: a converged problem's launches
+ * return at once.  Sets KP_ERR_NOT_PD in the device status when a damped
  * interior factor is not positive definite, and KP_ERR_NOT_CONVERGED when a
  * problem still rotated in its last allowed sweep. */
 kp_status kfac_pinn_invert(kfac_pinn_ctx* ctx, double lambda);
@@ -259,10 +264,17 @@ kp_status kfac_pinn_precondition_layer_noalloc(int32_t nA, int32_t nB, const dou
                                                const double* b, const double* grad,
                                                double* delta_out, void* stream);
 
-/* Sweep cap of the Jacobi eigensolver (1 .. 64; default 20).  Every call enqueues
- * the launches of max_sweeps sweeps; a converged problem's launches return at
- * once.  Errors: KP_ERR_ARG outside the range. */
+/* Sweep cap of the Jacobi eigensolver (1 .. 64; default 20): the most sweeps a
+ * call runs (and, under graph capture, the sweeps it enqueues).  Errors:
+ * KP_ERR_ARG outside the range. */
 kp_status kfac_pinn_set_max_sweeps(kfac_pinn_ctx* ctx, int32_t max_sweeps);
+
+/* Early stop of the Jacobi sweeps (kfac_pinn_invert): 1 (default) lets the call
+ * wait on the host for each sweep's convergence flags and stop enqueueing sweeps
+ * once every problem has converged; 0 makes every call enqueue max_sweeps sweeps
+ * without any host wait (as under graph capture).  The results are the same.
+ * Errors: KP_ERR_ARG unless enabled is 0 or 1. */
+kp_status kfac_pinn_set_sweep_wait(kfac_pinn_ctx* ctx, int32_t enabled);
 
 /* Delta = -(A_i (x) B_i + A_b (x) B_b)^-1 g per layer with the preconditioner of
  * the last kfac_pinn_invert (grad_in, delta_out: D doubles each). */

@@ -193,6 +193,12 @@ class KfacPinn:
         N.check(self.lib.kfac_pinn_set_max_sweeps(self.h, int(max_sweeps)),
                 "kfac_pinn_set_max_sweeps")
 
+    def set_sweep_wait(self, enabled: bool) -> None:
+        """Early stop of the Jacobi sweeps with host waits (default on); off: every
+        inversion enqueues the full sweep cap without waiting.  Same results."""
+        N.check(self.lib.kfac_pinn_set_sweep_wait(self.h, int(bool(enabled))),
+                "kfac_pinn_set_sweep_wait")
+
     def layer_gramian(self, layer: int, term: int, n: int) -> torch.Tensor:
         """Exact Gramian block of `layer` for one term (0 interior, 1 boundary) from
         the last curvature pass, which had n points of that term."""

@@ -62,6 +62,7 @@ _SIGS = {
     "kfac_pinn_precondition_layer_noalloc": (C.c_int, [C.c_int32, C.c_int32, _V, _V, _V, _V, _V,
                                                        _V, _V]),
     "kfac_pinn_set_max_sweeps": (C.c_int, [_V, C.c_int32]),
+    "kfac_pinn_set_sweep_wait": (C.c_int, [_V, C.c_int32]),
     "kfac_pinn_check_guards": (C.c_int, [_V, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kfac_pinn_step": (C.c_int, [_V, _V, _V, _V, C.c_int32, _V, _V, C.c_int32,
                                  C.POINTER(kp_hparams), _V]),

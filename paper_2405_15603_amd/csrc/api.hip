@@ -750,6 +750,7 @@ kp_status kfac_pinn_destroy(kfac_pinn_ctx* ctx) {
   if (!ctx) return KP_ERR_ARG;
   if (ctx->ls1.fork) (void)hipEventDestroy(ctx->ls1.fork);
   if (ctx->ls1.join) (void)hipEventDestroy(ctx->ls1.join);
+  eig_host_free(ctx->eg);
   if (ctx->eg_streams) {
     for (int k = 1; k < ctx->eg.n; k++) {
       if (ctx->eg.st[k]) {
@@ -1047,6 +1048,10 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
       return KP_ERR_HIP;
     }
     c->eg.ids = ids_dev;
+    if ((e = eig_host_sync(c->eg, ids.data(), (int)ids.size())) != hipSuccess) {
+      kfac_pinn_destroy(c);
+      return KP_ERR_HIP;
+    }
   }
   {
     std::vector<KronApply> ka(c->L);
@@ -1373,6 +1378,13 @@ kp_status kfac_pinn_set_max_sweeps(kfac_pinn_ctx* c, int32_t max_sweeps) {
   KP_ARG(c, "null context");
   KP_ARG(max_sweeps >= 1 && max_sweeps <= 64, "max_sweeps must be in [1, 64]");
   c->max_sweeps = max_sweeps;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_set_sweep_wait(kfac_pinn_ctx* c, int32_t enabled) {
+  KP_ARG(c, "null context");
+  KP_ARG(enabled == 0 || enabled == 1, "enabled must be 0 or 1");
+  c->eg.host_wait = enabled == 1;
   return KP_OK;
 }
 
@@ -1797,6 +1809,7 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
   std::vector<int> ids(np);
   eig_groups_plan(b->probs.data(), (int)np, 1, ids.data(), b->eg);
   b->eg.ids = b->eig_ids;
+  if (eig_host_sync(b->eg, ids.data(), (int)np) != hipSuccess) return fail(KP_ERR_HIP);
   if (hipMemcpy(b->probs_dev, b->probs.data(), sizeof(EigProblem) * np, hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(b->eig_ids, ids.data(), sizeof(int) * np, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1812,6 +1825,7 @@ kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   for (hipStream_t s : b->lanes) (void)hipStreamSynchronize(s);
   batch_drop_graph(b);
   for (kfac_pinn_ctx* c : b->ctx) kfac_pinn_destroy(c);
+  eig_host_free(b->eg);
   if (b->probs_dev) (void)hipFree(b->probs_dev);
   if (b->eig_ids) (void)hipFree(b->eig_ids);
   if (b->eig_ctl) (void)hipFree(b->eig_ctl);

@@ -768,6 +768,44 @@ __global__ void k_fwdlap_finish(FwdLayerArgs a, int nch) {
   if (a.sq_out) ((TC*)a.sq_out)[pc] = sq;
 }
 
+// The same with FP32 tables and 4 columns per thread (h_out and ldzo multiples
+// of 4): threads [0, N h_out / 4) finish column quads of the Laplacian row, the
+// rest write the bias feature and padding, one row (s, p) each.
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_fwdlap_finish4(FwdLayerArgs a, int nch) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int hq = a.h_out >> 2;
+  const long nmain = a.has_lap ? (long)a.N * hq : 0;
+  TZ* z = (TZ*)a.z;
+  auto store4 = [](TZ* dst, const f32x4& v) {
+    if constexpr (std::is_same<TZ, bf16>::value)
+      *gmem((bf16x4*)dst) = __builtin_convertvector(v, bf16x4);
+    else
+      *gmem((f32x4*)dst) = v;
+  };
+  if (idx < nmain) {
+    const int p = (int)(idx / hq), c = (int)(idx - (long)p * hq) * 4;
+    const long pc = (long)p * a.h_out + c;
+    const long plane = (long)a.N * a.h_out;
+    const f32x4 t = *gmem((const f32x4*)((const float*)a.tab_t + pc));
+    f32x4 sq = *gmem((const f32x4*)((const float*)a.tab_sq + pc));
+    for (int k = 1; k < nch; k++) sq += *gmem((const f32x4*)((const float*)a.tab_sq + k * plane + pc));
+    const f32x4 la = *gmem((const f32x4*)((const float*)a.tab_lap + pc));
+    const f32x4 s1 = 1.0f - t * t, s2 = -2.0f * t * s1;
+    store4(z + ((long)(a.S - 1) * a.N + p) * a.ldzo + c, s1 * la + s2 * sq);
+    if (a.sq_out) *gmem((f32x4*)((float*)a.sq_out + pc)) = sq;
+    return;
+  }
+  const long row = idx - nmain;   // s * N + p
+  if (row >= (long)a.S * a.N) return;
+  TZ* zr = z + row * a.ldzo;
+  for (int c = a.h_out; c < a.ldzo; c += 4) {
+    f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (c == a.h_out && row < a.N) v[0] = 1.0f;
+    store4(zr + c, v);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Backward layer: zbar_s = G_s W (W: h_out_next x h_in_next as rows of W^T), then
 // the adjoint of the tanh rows at this layer's pre-activations:
@@ -1487,6 +1525,15 @@ hipError_t fwdlap_pair(int mode, const FwdLayerArgs& a, int nch, const FwdLayerA
 
 hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
+  if (mode != M_F64 && (a.h_out & 3) == 0 && (a.ldzo & 3) == 0) {
+    const long items = (a.has_lap ? (long)a.N * (a.h_out / 4) : 0) + (long)a.S * a.N;
+    const unsigned nb = (unsigned)((items + 255) / 256);
+    if (mode == M_BF16)
+      k_fwdlap_finish4<bf16><<<nb, 256, 0, st>>>(a, nch);
+    else
+      k_fwdlap_finish4<float><<<nb, 256, 0, st>>>(a, nch);
+    return hipGetLastError();
+  }
   dim3 g = pc_grid(a.ldzo, a.N, 64);
   switch (mode) {
     case M_F64: k_fwdlap_finish<double, double><<<g, 64, 0, st>>>(a, nch); break;

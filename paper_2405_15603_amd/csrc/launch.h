@@ -163,6 +163,12 @@ struct EigProblem {
 // from the call's stream at `fork` and it waits for each at join[k].  Group k
 // holds the problems ids[off[k] .. off[k+1]) (ids: device, grouped problem
 // indices) and sweeps rounds sized for its largest problem, npmax[k].
+// Early stop: with `host` set (eig_host_sync) and the call's stream not being
+// captured into a graph, each group's convergence flags are copied to pinned host
+// memory after every sweep and read one sweep later; a group whose problems have
+// all converged gets no further sweeps.  The launches left out would have returned
+// at once (every launch of a converged problem does), so the results equal the
+// full schedule's; the call then waits on the host for each sweep but the last.
 constexpr int kEigGroups = 4;
 struct EigGroups {
   int n = 1;
@@ -172,11 +178,19 @@ struct EigGroups {
   hipStream_t st[kEigGroups] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kEigGroups] = {};
+  int* host = nullptr;              // pinned: ids (nprob), then 2 x kEigGroups flag copies
+  int host_nprob = 0;
+  bool host_wait = true;           // early stop allowed (kfac_pinn_set_sweep_wait)
+  hipEvent_t swept[kEigGroups][2] = {};
 };
 // Splits nprob problems into min(ngroups, nprob, kEigGroups) groups of balanced
 // work (largest first to the lightest group); fills g.n, g.off, g.npmax and the
 // host array ids (nprob ints, to be copied to the device for g.ids).
 void eig_groups_plan(const EigProblem* probs, int nprob, int ngroups, int* ids, EigGroups& g);
+// Pinned host copies and events of the early stop (ids: the host array of
+// eig_groups_plan); eig_host_free releases them.
+hipError_t eig_host_sync(EigGroups& g, const int* ids, int nprob);
+void eig_host_free(EigGroups& g);
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
                             EigProblem* probs_dev, int* status, int* done, int* calls,
                             int refresh, int max_sweeps, const EigGroups& g, hipStream_t st);

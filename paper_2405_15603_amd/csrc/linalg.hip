@@ -23,6 +23,7 @@
 // (grid.y = problem).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -863,6 +864,37 @@ __global__ void k_jac_extract(const EigProblem* __restrict__ pr) {
   }
 }
 
+hipError_t eig_host_sync(EigGroups& g, const int* ids, int nprob) {
+  if (g.host) return hipSuccess;
+  const size_t bytes = sizeof(int) * ((size_t)nprob + 4 * kEigGroups * (size_t)nprob);
+  if (hipError_t e = hipHostMalloc((void**)&g.host, bytes, hipHostMallocDefault)) {
+    g.host = nullptr;
+    return e;
+  }
+  std::memcpy(g.host, ids, sizeof(int) * nprob);
+  for (int k = 0; k < g.n; k++)
+    for (int par = 0; par < 2; par++)
+      if (hipError_t e = hipEventCreateWithFlags(&g.swept[k][par], hipEventDisableTiming)) {
+        eig_host_free(g);
+        return e;
+      }
+  g.host_nprob = nprob;
+  return hipSuccess;
+}
+
+void eig_host_free(EigGroups& g) {
+  for (int k = 0; k < kEigGroups; k++)
+    for (int par = 0; par < 2; par++)
+      if (g.swept[k][par]) {
+        (void)hipEventSynchronize(g.swept[k][par]);
+        (void)hipEventDestroy(g.swept[k][par]);
+        g.swept[k][par] = nullptr;
+      }
+  if (g.host) (void)hipHostFree(g.host);
+  g.host = nullptr;
+  g.host_nprob = 0;
+}
+
 void eig_groups_plan(const EigProblem* probs, int nprob, int ngroups, int* ids, EigGroups& g) {
   ngroups = std::max(1, std::min(ngroups, std::min(nprob, kEigGroups)));
   // largest first, each to the group with the least work so far (work ~ n_pad^3)
@@ -929,24 +961,52 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
     for (int k = 1; k < ng; k++)
       if (hipError_t e = hipStreamWaitEvent(g.st[k], g.fork, 0)) return e;
   }
-  int rounds[kEigGroups], ticks = 0;
+  // Sweep by sweep; within a sweep the groups' rounds interleave launch by launch.
+  int rounds[kEigGroups], rmax = 0;
+  bool active[kEigGroups];
   for (int k = 0; k < ng; k++) {
     rounds[k] = g.npmax[k] / JB - 1;
-    ticks = std::max(ticks, max_sweeps * rounds[k]);
+    rmax = std::max(rmax, rounds[k]);
+    active[k] = rounds[k] >= 1;
   }
-  for (int t = 0; t < ticks; t++)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusActive;
+  const bool early = g.host && g.host_wait && g.host_nprob == nprob && hipStreamIsCapturing(st, &cap) == hipSuccess &&
+                     cap == hipStreamCaptureStatusNone;
+  const long nflag = 2L * nprob;
+  auto flags = [&](int k, int par) { return g.host + nprob + (2 * k + par) * nflag; };
+  for (int sw = 0; sw < max_sweeps; sw++) {
+    bool any = false;
+    for (int k = 0; k < ng; k++) any = any || active[k];
+    if (!any) break;
+    for (int r = 0; r < rmax; r++)
+      for (int k = 0; k < ng; k++) {
+        if (!active[k] || r >= rounds[k]) continue;
+        const hipStream_t sk = k == 0 ? st : g.st[k];
+        const int* ids = g.ids + g.off[k];
+        const int nq = g.off[k + 1] - g.off[k];
+        const int npair = g.npmax[k] / JB / 2;
+        const int nwg = npair * (npair + 1) / 2 + npair * npair;
+        k_jac_solve<<<dim3(npair, nq), kSolveThreads, 0, sk>>>(probs_dev, ids, done, r, KP_JAC_INNER);
+        k_jac_apply<<<dim3(nwg, nq), 256, 0, sk>>>(probs_dev, ids, done, r);
+        if (r < rounds[k] - 1) continue;
+        k_jac_check<<<(nq + 63) / 64, 64, 0, sk>>>(probs_dev, ids, done, nq);
+        if (!early) continue;
+        if (hipError_t e = hipMemcpyAsync(flags(k, sw & 1), done, sizeof(int) * nflag,
+                                          hipMemcpyDeviceToHost, sk))
+          return e;
+        if (hipError_t e = hipEventRecord(g.swept[k][sw & 1], sk)) return e;
+      }
+    if (!early || sw == 0) continue;
+    // the previous sweep's flags (this sweep is already queued behind it)
     for (int k = 0; k < ng; k++) {
-      if (rounds[k] < 1 || t >= max_sweeps * rounds[k]) continue;
-      const hipStream_t sk = k == 0 ? st : g.st[k];
-      const int* ids = g.ids + g.off[k];
-      const int nq = g.off[k + 1] - g.off[k];
-      const int npair = g.npmax[k] / JB / 2;
-      const int nwg = npair * (npair + 1) / 2 + npair * npair;
-      const int r = t % rounds[k];
-      k_jac_solve<<<dim3(npair, nq), kSolveThreads, 0, sk>>>(probs_dev, ids, done, r, KP_JAC_INNER);
-      k_jac_apply<<<dim3(nwg, nq), 256, 0, sk>>>(probs_dev, ids, done, r);
-      if (r == rounds[k] - 1) k_jac_check<<<(nq + 63) / 64, 64, 0, sk>>>(probs_dev, ids, done, nq);
+      if (!active[k]) continue;
+      if (hipError_t e = hipEventSynchronize(g.swept[k][(sw - 1) & 1])) return e;
+      const int* f = flags(k, (sw - 1) & 1);
+      bool all = true;
+      for (int i = g.off[k]; i < g.off[k + 1] && all; i++) all = f[2 * g.host[i]] != 0;
+      if (all) active[k] = false;
     }
+  }
   if (ng > 1) {
     for (int k = 1; k < ng; k++) {
       if (hipError_t e = hipEventRecord(g.join[k], g.st[k])) return e;
