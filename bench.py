@@ -6,8 +6,9 @@ points, on one MI355X.
 One step = one full KFAC iteration (Algorithm 1): forward Laplacian, residuals,
 backward pass, Kronecker factors with EMA, damped Kronecker-sum inverse,
 preconditioned direction with momentum, grid line search over 31 step sizes and
-the update.  The headline runs the mixed-precision path (BF16 MFMA, FP32
-accumulation, FP64 factors and inversion); the plain FP32 path and the core
+the update.  The headline runs a mixed-precision path (FP32 accumulation, FP64
+factors and inversion, BF16 line search; curvature products in BF16x3 or FP16,
+--precision), the other mixed path is timed beside it; the plain FP32 path and the core
 step (fixed step size, no line search) and KFAC* (learning rate and momentum
 from the quadratic model, Section 3.4) are timed beside it.  Inputs are resident
 in HBM before the timed region.  The headline times --repeats regions of exactly
@@ -34,7 +35,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
+# dense MFMA peaks of the dominant kernel's arithmetic (the line search is BF16 in
+# both mixed paths)
+PEAK_TFLOPS = {"bf16": 2500.0, "f16": 2500.0, "f32": 157.3, "f64": 78.6}
 HBM_GBS = 8000.0
 KERNEL_CLASSES = {"layer_gemm": 0, "factor_gemm": 1, "invert": 2, "act": 3, "ls_layer": 4}
 KERNEL_NAMES = {"ls_layer": "k_fwdlap (line-search forward layer product)",
@@ -100,7 +103,7 @@ def run_gpu(problem, precision, steps, warmup, kernel_class=None, lr_mode="grid"
     return ms, tm, status, last
 
 
-def run_batch(count, steps, warmup, use_graph):
+def run_batch(count, steps, warmup, use_graph, precision="bf16"):
     """One step of `count` heterogeneous instances per call (the 64-instance
     recipe), as a captured graph or as direct launches on the internal lanes."""
     import numpy as np
@@ -112,7 +115,7 @@ def run_batch(count, steps, warmup, use_graph):
     T = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float32, device=dev).contiguous()
     thetas = [T(p.theta0()) for p in probs]
     cols = list(zip(*[[T(a) for a in p.batch(0)] for p in probs]))
-    b = KfacPinnBatch(probs, "bf16", use_graph=use_graph)
+    b = KfacPinnBatch(probs, precision, use_graph=use_graph)
     hp = hparams()
     for _ in range(warmup):
         b.step(thetas, *cols, hp)
@@ -233,7 +236,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "f16", "f32", "f64"],
+                    help="bf16: BF16x3 curvature products; f16: FP16 curvature products "
+                         "(both with a BF16 line search)")
     ap.add_argument("--workload", default="poisson100d")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--no-core", action="store_true", help="skip the fixed-step (core) leg")
@@ -245,6 +250,8 @@ def main():
     ap.add_argument("--repeats", type=int, default=3,
                     help="timed regions of --steps steps each; the headline is their median")
     ap.add_argument("--no-kfac-star", action="store_true", help="skip the KFAC* leg")
+    ap.add_argument("--no-other-mixed", action="store_true",
+                    help="skip the leg that times the other mixed-precision curvature path")
     ap.add_argument("--roofline-steps", type=int, default=20,
                     help="steps of the one-lane run that times the dominant kernel's launches")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -288,7 +295,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16": "bf16", "f32": "f32", "f64": "f64"}[args.precision],
+        "dtype": {"bf16": "bf16", "f16": "f16", "f32": "f32", "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{problem.name}: -Lap u = f on [0,1]^{problem.d}, "
                                f"tanh MLP {'-'.join(map(str, problem.widths))}, "
@@ -301,7 +308,8 @@ def main():
         sec = tm["ms"] * 1e-3
         ach = tm["flops"] / sec / 1e12
         peak = PEAK_TFLOPS[args.precision]
-        traffic = measured_traffic() if (args.kernel == "ls_layer" and args.precision == "bf16") else None
+        traffic = (measured_traffic() if (args.kernel == "ls_layer" and args.precision in ("bf16", "f16"))
+                   else None)
         out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                            "frac": ach / peak, "traffic": traffic,
                            "kernel": f"{KERNEL_NAMES[args.kernel]}: {tm['launches']} launches, "
@@ -328,6 +336,15 @@ def main():
                             "note": "KFAC*: learning rate and momentum from the 2 x 2 quadratic "
                                     "model with the exact damped Gramian (Section 3.4), no line "
                                     "search"}
+    if args.precision in ("bf16", "f16") and not args.no_other_mixed:
+        other = "f16" if args.precision == "bf16" else "bf16"
+        log(f"other mixed path ({other})")
+        mso, _, sto, _ = run_gpu(problem, other, side_steps, args.warmup, None)
+        out["other_mixed"] = {"precision": other, "value": 1000.0 / mso, "ms_per_step": mso,
+                              "status": sto,
+                              "note": {"bf16": "BF16x3 curvature products (hi*hi + lo*hi + hi*lo)",
+                                       "f16": "FP16 curvature products (slab rounded once, "
+                                              "weights as FP16 hi + lo)"}[other]}
     if not args.no_fp32 and args.precision != "f32":
         log("FP32 path")
         ms32, _, st32, _ = run_gpu(problem, "f32", side_steps, 1, None)
@@ -335,10 +352,11 @@ def main():
                        "mixed_over_fp32": ms32 / ms}
     if not args.no_batch:
         log("64-instance batch")
+        bp = args.precision if args.precision in ("bf16", "f16") else "bf16"
         out["batch64"] = {"instances": 64, "note": "heterogeneous 64-instance recipe, mixed "
                           "precision, grid line search; one step of every instance per call",
-                          "graph": run_batch(64, 3, 1, True),
-                          "direct": run_batch(64, 3, 1, False)}
+                          "graph": run_batch(64, 3, 1, True, bp),
+                          "direct": run_batch(64, 3, 1, False, bp)}
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(problem)

@@ -79,12 +79,17 @@ typedef enum {
 typedef enum {
   KP_F64 = 0,        /* everything in FP64 (the paper's precision)                 */
   KP_F32 = 1,        /* FP32 slabs and matrix products, FP64 factors and inversion */
-  KP_MIXED_BF16 = 2  /* BF16 MFMA with FP32 accumulation.  Curvature pass (forward
+  KP_MIXED_BF16 = 2, /* BF16 MFMA with FP32 accumulation.  Curvature pass (forward
                         Laplacian, adjoint, factors, gradient): FP32 slabs whose
                         products run as BF16x3 (hi*hi + lo*hi + hi*lo of the BF16
                         split of each operand).  Line-search forwards: BF16 slabs
                         and BF16 weights, one MFMA per product.  FP32 elementwise
                         work, FP32 master parameters, FP64 factors and inversion */
+  KP_MIXED_F16 = 3   /* as KP_MIXED_BF16, but the curvature pass runs FP16 MFMAs with
+                        FP32 accumulation: FP32 slab entries are rounded once to
+                        FP16 on their way into the products; the weights are split
+                        into FP16 hi + lo (layer products: two MFMAs, the factor
+                        and gradient products: one)                              */
 } kp_precision;
 
 typedef struct {

@@ -14,9 +14,9 @@ from typing import Optional, Sequence
 import torch
 
 from . import _native as N
-from ._native import KP_F32, KP_F64, KP_MIXED_BF16, KfacPinnError
+from ._native import KP_F32, KP_F64, KP_MIXED_BF16, KP_MIXED_F16, KfacPinnError
 
-PRECISIONS = {"f64": KP_F64, "f32": KP_F32, "bf16": KP_MIXED_BF16}
+PRECISIONS = {"f64": KP_F64, "f32": KP_F32, "bf16": KP_MIXED_BF16, "f16": KP_MIXED_F16}
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libkfac_pinn.so")
 
 (KP_OK, KP_ERR_ARG, KP_ERR_OOM, KP_ERR_HIP, KP_ERR_NOT_PD, KP_ERR_NONFINITE, KP_ERR_STATE,
  KP_ERR_NOT_CONVERGED) = range(8)
-KP_F64, KP_F32, KP_MIXED_BF16 = 0, 1, 2
+KP_F64, KP_F32, KP_MIXED_BF16, KP_MIXED_F16 = 0, 1, 2, 3
 
 
 class kp_problem(C.Structure):

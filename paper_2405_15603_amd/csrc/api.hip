@@ -357,7 +357,7 @@ LayerLaunch layer_launch(kfac_pinn_ctx* c, const Slabs& s, int n, int l, int upt
   a.zin = T.z(l);
   a.ldz = c->ldz[l];
   a.w = wptr(c->w_hi, ld.wrm, c->esz_w);
-  a.w2 = (T.mode == M_BF16X3) ? wptr(c->w_lo, ld.wrm, c->esz_w) : nullptr;
+  a.w2 = (T.mode == M_BF16X3 || T.mode == M_F16) ? wptr(c->w_lo, ld.wrm, c->esz_w) : nullptr;
   a.ldw = ld.ldk_in;
   a.K = (int)ld.ldk_in;
   a.N = n;
@@ -582,7 +582,7 @@ hipError_t backward_sweep(kfac_pinn_ctx* c, Slabs& s, const void* theta, const v
     a.gin = s.g_at(l);
     a.ldgi = c->ldg[l];
     a.w = wptr(c->w_hi, ld.wcm, c->esz_w);
-    a.w2 = c->cmode == M_BF16X3 ? wptr(c->w_lo, ld.wcm, c->esz_w) : nullptr;
+    a.w2 = (c->cmode == M_BF16X3 || c->cmode == M_F16) ? wptr(c->w_lo, ld.wcm, c->esz_w) : nullptr;
     a.ldw = ld.ldk_out;
     a.K = (int)ld.ldk_out;
     const long ts = c->tab_stride;
@@ -778,7 +778,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     KP_ARG(pb->widths[l] >= 1 && pb->widths[l] <= 4096, "widths must be in [1, 4096]");
   KP_ARG(pb->widths[pb->n_layers] == 1, "the network output must be scalar (widths[L] == 1)");
   KP_ARG(pb->widths[0] <= 1024, "at most 1024 inputs");
-  KP_ARG(pb->precision >= KP_F64 && pb->precision <= KP_MIXED_BF16, "unknown precision");
+  KP_ARG(pb->precision >= KP_F64 && pb->precision <= KP_MIXED_F16, "unknown precision");
   KP_ARG(pb->max_interior >= 0 && pb->max_boundary >= 0, "negative capacity");
   KP_ARG(pb->time_coord >= -1 && pb->time_coord < pb->widths[0], "time_coord out of range");
   KP_ARG(std::isfinite(pb->coef_xgrad) && std::isfinite(pb->coef_gradsq) &&
@@ -828,10 +828,11 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
     c->pp = c->sp = c->lp = c->wp = P_F32;
     c->cmode = c->lmode = M_F32;
     c->esz_p = c->esz_s = c->esz_l = c->esz_c = c->esz_w = 4;
-  } else {   // mixed: FP32 slabs with BF16x3 products for the curvature pass, BF16 line search
+  } else {   // mixed: FP32 slabs with BF16x3 or FP16 products for the curvature pass, BF16 line search
     c->pp = c->sp = P_F32;
-    c->lp = c->wp = P_BF16;
-    c->cmode = M_BF16X3;
+    c->lp = P_BF16;
+    c->wp = pb->precision == KP_MIXED_F16 ? P_F16 : P_BF16;
+    c->cmode = pb->precision == KP_MIXED_F16 ? M_F16 : M_BF16X3;
     c->lmode = M_BF16;
     c->esz_p = c->esz_s = c->esz_c = 4;
     c->esz_l = c->esz_w = 2;
@@ -928,7 +929,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
   }
   c->w_bytes = (size_t)woff * c->esz_w;
   ALLOC(c->w_hi, c->w_bytes);
-  if (c->wp == P_BF16) ALLOC(c->w_lo, (size_t)woff * c->esz_w);
+  if (c->wp == P_BF16 || c->wp == P_F16) ALLOC(c->w_lo, (size_t)woff * c->esz_w);
   ALLOC(c->theta_trial, (size_t)c->D * c->esz_p);
   if ((e = alloc_slabs(c, c->si)) != hipSuccess || (e = alloc_slabs(c, c->sb)) != hipSuccess) {
     kp_set_last_error(hipGetErrorString(e), __FILE__, __LINE__);

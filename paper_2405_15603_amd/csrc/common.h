@@ -7,6 +7,8 @@
 namespace kp {
 
 typedef __bf16 bf16;
+typedef _Float16 f16;
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -19,22 +21,26 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float to_f(float x) { return x; }
 __device__ __forceinline__ float to_f(double x) { return (float)x; }
 __device__ __forceinline__ float to_f(bf16 x) { return (float)x; }
+__device__ __forceinline__ float to_f(f16 x) { return (float)x; }
 
 template <typename T> __device__ __forceinline__ T from_f(float x);
 template <> __device__ __forceinline__ float from_f<float>(float x) { return x; }
 template <> __device__ __forceinline__ double from_f<double>(float x) { return (double)x; }
 template <> __device__ __forceinline__ bf16 from_f<bf16>(float x) { return (bf16)x; }
+template <> __device__ __forceinline__ f16 from_f<f16>(float x) { return (f16)x; }
 
 template <typename T> __device__ __forceinline__ T cvt(double x);
 template <> __device__ __forceinline__ double cvt<double>(double x) { return x; }
 template <> __device__ __forceinline__ float cvt<float>(double x) { return (float)x; }
 template <> __device__ __forceinline__ bf16 cvt<bf16>(double x) { return (bf16)(float)x; }
+template <> __device__ __forceinline__ f16 cvt<f16>(double x) { return (f16)(float)x; }
 template <typename T> __device__ __forceinline__ T cvtf(float x) { return from_f<T>(x); }
 template <> __device__ __forceinline__ double cvtf<double>(float x) { return (double)x; }
 
 __device__ __forceinline__ double to_d(double x) { return x; }
 __device__ __forceinline__ double to_d(float x) { return (double)x; }
 __device__ __forceinline__ double to_d(bf16 x) { return (double)(float)x; }
+__device__ __forceinline__ double to_d(f16 x) { return (double)(float)x; }
 
 // Accumulation / compute type of a storage type: FP64 stays FP64, the rest FP32.
 template <typename T> struct Acc { typedef float type; };
@@ -57,6 +63,17 @@ template <> struct Mfma<bf16> {
   __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
   __device__ __forceinline__ static acc mma(const frag& a, const frag& b, const acc& c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+// FP16: the same operand and output layout as BF16 (k = 32)
+template <> struct Mfma<f16> {
+  static constexpr int K = 32;
+  static constexpr int KV = 8;
+  typedef f16x8 frag;
+  typedef f32x4 acc;
+  __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+  __device__ __forceinline__ static acc mma(const frag& a, const frag& b, const acc& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
 };
 template <> struct Mfma<float> {

@@ -76,6 +76,11 @@ hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha
                                                      alpha, nd, (bf16*)w_hi, (bf16*)w_lo,
                                                      (float*)bias, bias_stride, fwd_only);
       break;
+    case P_F16:
+      k_prep_weights<float, f16><<<g, 256, 0, st>>>((const float*)theta, (const float*)dir,
+                                                    alpha, nd, (f16*)w_hi, (f16*)w_lo, (float*)bias,
+                                                    bias_stride, fwd_only);
+      break;
   }
   return hipGetLastError();
 }

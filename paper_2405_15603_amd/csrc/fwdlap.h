@@ -9,7 +9,9 @@ namespace kp {
 constexpr int kMaxChunks = 16;
 
 // compute modes of the layer products
-enum { M_F64 = 0, M_F32 = 1, M_BF16 = 2, M_BF16X3 = 3 };
+// M_F16: FP32 slabs rounded to FP16 on the way into LDS, weights as FP16 hi + lo,
+// FP16 MFMAs with FP32 accumulation (one slab rounding per product)
+enum { M_F64 = 0, M_F32 = 1, M_BF16 = 2, M_BF16X3 = 3, M_F16 = 4 };
 
 struct FwdLayerArgs {
   const void* zin;   // input slab (s-major rows s*N + p), row length ldz, zero beyond K

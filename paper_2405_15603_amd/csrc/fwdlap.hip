@@ -59,6 +59,17 @@ template <> struct Op<M_BF16X3> {
   static constexpr int NA = 2, NB = 2, BK = 32, PAD = 8, VA = 4;
 };
 
+// FP16: the slab operand is rounded once; the weights are split into FP16 hi + lo
+// (two MFMAs per product), because their rounding error would be the same for
+// every point and would not average out in the factor sums.
+template <> struct Op<M_F16> {
+  typedef float TA;
+  typedef f16 TB;
+  typedef f16 TL;
+  typedef float TC;
+  static constexpr int NA = 1, NB = 2, BK = 32, PAD = 8, VA = 4;
+};
+
 typedef uint4 v16;
 
 template <typename TL>
@@ -66,6 +77,10 @@ __device__ __forceinline__ typename Mfma<TL>::frag frag_ld(const TL* base, int l
 template <>
 __device__ __forceinline__ bf16x8 frag_ld<bf16>(const bf16* base, int lane, int ldk, int k0) {
   return *(const bf16x8*)(base + (lane & 15) * ldk + k0 + (lane >> 4) * 8);
+}
+template <>
+__device__ __forceinline__ f16x8 frag_ld<f16>(const f16* base, int lane, int ldk, int k0) {
+  return *(const f16x8*)(base + (lane & 15) * ldk + k0 + (lane >> 4) * 8);
 }
 template <>
 __device__ __forceinline__ float frag_ld<float>(const float* base, int lane, int ldk, int k0) {
@@ -173,6 +188,9 @@ __device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
             __builtin_convertvector(fv - __builtin_convertvector(hv, f32x4), bf16x4); \
         *(bf16x4*)(&sm.a[BUF][0][ar[i] * LDK + ak[i]]) = hv;                          \
         *(bf16x4*)(&sm.a[BUF][O::NA - 1][ar[i] * LDK + ak[i]]) = lv;                  \
+      } else if constexpr (MODE == M_F16) {                                           \
+        const f32x4 fv = __builtin_bit_cast(f32x4, ra[i]);                            \
+        *(f16x4*)(&sm.a[BUF][0][ar[i] * LDK + ak[i]]) = __builtin_convertvector(fv, f16x4); \
       } else {                                                                        \
         *(u32x4*)(&sm.a[BUF][0][ar[i] * LDK + ak[i]]) = ra[i];                        \
       }                                                                               \
@@ -228,11 +246,15 @@ __device__ __forceinline__ void sloop(typename Mainloop<MODE, NARROW>::Smem& sm,
             if constexpr (MODE == M_BF16X3) {
               acc[i][j] = MF::mma(b[0][j], a[O::NA - 1][i], acc[i][j]);
               acc[i][j] = MF::mma(b[NB - 1][j], a[0][i], acc[i][j]);
+            } else if constexpr (MODE == M_F16) {
+              acc[i][j] = MF::mma(b[NB - 1][j], a[0][i], acc[i][j]);
             }
           } else {
             acc[i][j] = MF::mma(a[0][i], b[0][j], acc[i][j]);
             if constexpr (MODE == M_BF16X3) {
               acc[i][j] = MF::mma(a[O::NA - 1][i], b[0][j], acc[i][j]);
+              acc[i][j] = MF::mma(a[0][i], b[NB - 1][j], acc[i][j]);
+            } else if constexpr (MODE == M_F16) {
               acc[i][j] = MF::mma(a[0][i], b[NB - 1][j], acc[i][j]);
             }
           }
@@ -1429,7 +1451,7 @@ static int choose_chunks(int tiles, int nd, int has_lap, int slots, int ns, doub
 }
 
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
-  static int occ[4] = {0, 0, 0, 0};
+  static int occ[5] = {0, 0, 0, 0, 0};
   int per_cu = 1, ns = 1, BP = 128, BN = 128;
   switch (mode) {
     case M_BF16:
@@ -1444,6 +1466,7 @@ int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
       break;
     case M_F32: per_cu = resident(k_fwdlap<M_F32, float>, kThreads, occ[M_F32]); break;
     case M_BF16X3: per_cu = resident(k_fwdlap<M_BF16X3, float>, kThreads, occ[M_BF16X3]); break;
+    case M_F16: per_cu = resident(k_fwdlap<M_F16, float>, kThreads, occ[M_F16]); break;
     default: break;
   }
   const int tiles = ((N + BP - 1) / BP) * ((h_out + BN - 1) / BN);
@@ -1451,12 +1474,13 @@ int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap) {
                        false);
 }
 int bwdlap_chunks(int mode, int N, int h, int nd, int has_lap) {
-  static int occ[4] = {0, 0, 0, 0};
+  static int occ[5] = {0, 0, 0, 0, 0};
   int per_cu = 1;
   switch (mode) {
     case M_F64: per_cu = resident(k_bwdlap<M_F64, double>, kThreads, occ[M_F64]); break;
     case M_F32: per_cu = resident(k_bwdlap<M_F32, float>, kThreads, occ[M_F32]); break;
     case M_BF16X3: per_cu = resident(k_bwdlap<M_BF16X3, float>, kThreads, occ[M_BF16X3]); break;
+    case M_F16: per_cu = resident(k_bwdlap<M_F16, float>, kThreads, occ[M_F16]); break;
     default: break;
   }
   const int BP = 128, BN = 64;
@@ -1518,6 +1542,10 @@ hipError_t fwdlap_pair(int mode, const FwdLayerArgs& a, int nch, const FwdLayerA
       if (a4) launch_fwd<M_BF16X3, float, true>(a, nch, b, st);
       else launch_fwd<M_BF16X3, float, false>(a, nch, b, st);
       break;
+    case M_F16:
+      if (a4) launch_fwd<M_F16, float, true>(a, nch, b, st);
+      else launch_fwd<M_F16, float, false>(a, nch, b, st);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1539,7 +1567,8 @@ hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t s
     case M_F64: k_fwdlap_finish<double, double><<<g, 64, 0, st>>>(a, nch); break;
     case M_F32: k_fwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
     case M_BF16: k_fwdlap_finish<float, bf16><<<g, 64, 0, st>>>(a, nch); break;
-    case M_BF16X3: k_fwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
+    case M_BF16X3:
+    case M_F16: k_fwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1591,6 +1620,15 @@ hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_
       k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
       break;
     }
+    case M_F16: {
+      float* qq = (float*)q;
+      if (a.dirs)
+        k_input_q_dirs<f16, float><<<nd256, 256, 0, st>>>(a, qq, qq + a.h_out);
+      else
+        k_input_q<f16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
+      k_input_rows<float, float><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }
@@ -1617,6 +1655,12 @@ hipError_t bwdlap_main(int mode, const BwdLayerArgs& a, int nch, hipStream_t st)
       else
         k_bwdlap<M_BF16X3, float><<<tile_grid<M_BF16X3, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
       break;
+    case M_F16:
+      if (vec)
+        k_bwdlap_vec<M_F16><<<tile_grid<M_F16, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
+      else
+        k_bwdlap<M_F16, float><<<tile_grid<M_F16, true>(a.N, a.h, nch), kThreads, 0, st>>>(a);
+      break;
     default:
       return hipErrorInvalidValue;
   }
@@ -1629,7 +1673,8 @@ hipError_t bwdlap_finish(int mode, const BwdLayerArgs& a, int nch, hipStream_t s
   switch (mode) {
     case M_F64: k_bwdlap_finish<double, double><<<g, 64, 0, st>>>(a, nch); break;
     case M_F32: k_bwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
-    case M_BF16X3: k_bwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
+    case M_BF16X3:
+    case M_F16: k_bwdlap_finish<float, float><<<g, 64, 0, st>>>(a, nch); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1653,6 +1698,7 @@ hipError_t last_fwd(int mode, const void* z, long ldz, const void* w, int K, lon
                                                          R, (float*)u);
       break;
     case M_BF16X3:
+    case M_F16:
       k_last_fwd<float, float, float><<<nb, 256, 0, st>>>((const float*)z, ldz, (const float*)w,
                                                           K, R, (float*)u);
       break;
@@ -1689,6 +1735,7 @@ hipError_t bwd_last(int mode, const BwdLayerArgs& a, const void* sigma, long lds
                                                                (const float*)wl);
       break;
     case M_BF16X3:
+    case M_F16:
       k_bwd_last<float, float, float, float><<<g, 64, 0, st>>>(a, (const float*)sigma, lds,
                                                                (const float*)wl);
       break;

@@ -233,16 +233,21 @@ __device__ __forceinline__ int x3_pos(int col, int chunk) {
   return (col ^ q) * X3_BK + ((chunk ^ q ^ ((col >> 4) & 3)) << 3);
 }
 
-template <bool WEIGHTED>
+// X3 = false: the single-pass FP16 variant (one FP16 plane, one MFMA per
+// product) with the same tiles, loads and LDS layout.
+template <bool WEIGHTED, bool X3 = true>
 __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long lda,
                                                const float* __restrict__ B, long ldb, int M,
                                                int N, int K, const float* __restrict__ rw,
                                                int rmod, int sym, int ntm, int ntn, int kchunk,
                                                float* __restrict__ part) {
-  typedef Mfma<bf16> MF;
-  constexpr int BM = X3_BM, BK = X3_BK, TI = 4, TJ = 4;
+  typedef typename std::conditional<X3, bf16, f16>::type TL;
+  typedef typename std::conditional<X3, bf16x4, f16x4>::type TL4;
+  typedef typename std::conditional<X3, bf16x8, f16x8>::type TL8;
+  typedef Mfma<TL> MF;
+  constexpr int BM = X3_BM, BK = X3_BK, TI = 4, TJ = 4, NPL = X3 ? 2 : 1;
   // [stage][operand][plane][BM * BK]
-  __shared__ __align__(16) bf16 sm[2][2][2][BM * BK];
+  __shared__ __align__(16) TL sm[2][2][NPL][BM * BK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int ti, tj, split;
@@ -301,19 +306,21 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
         f0[j] = fr[j][e];                                                        \
         f1[j] = fr[j + 4][e];                                                    \
       }                                                                          \
-      const bf16x4 h0 = __builtin_convertvector(f0, bf16x4);                     \
-      const bf16x4 h1 = __builtin_convertvector(f1, bf16x4);                     \
-      const bf16x4 l0 = __builtin_convertvector(f0 - __builtin_convertvector(h0, f32x4), bf16x4); \
-      const bf16x4 l1 = __builtin_convertvector(f1 - __builtin_convertvector(h1, f32x4), bf16x4); \
+      const TL4 h0 = __builtin_convertvector(f0, TL4);                           \
+      const TL4 h1 = __builtin_convertvector(f1, TL4);                           \
       const int pos = x3_pos(4 * cg + e, rg);                                    \
-      bf16x8 hv = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);       \
-      bf16x8 lv = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);       \
-      *(bf16x8*)&sm[BUF][opd][0][pos] = hv;                                      \
-      *(bf16x8*)&sm[BUF][opd][1][pos] = lv;                                      \
+      TL8 hv = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);          \
+      *(TL8*)&sm[BUF][opd][0][pos] = hv;                                         \
+      if constexpr (X3) {                                                        \
+        const TL4 l0 = __builtin_convertvector(f0 - __builtin_convertvector(h0, f32x4), TL4); \
+        const TL4 l1 = __builtin_convertvector(f1 - __builtin_convertvector(h1, f32x4), TL4); \
+        TL8 lv = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);        \
+        *(TL8*)&sm[BUF][opd][NPL - 1][pos] = lv;                                 \
+      }                                                                          \
     }                                                                            \
   }
 
-  MF::acc acc[TI][TJ];
+  typename MF::acc acc[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; i++)
 #pragma unroll
@@ -336,23 +343,25 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
     KP_X3_LOAD(knext);
     // keep the loads ahead of the products (the scheduler would sink them)
     __builtin_amdgcn_sched_barrier(0);
-    MF::frag a[2][TI], b[2][TJ];
+    typename MF::frag a[NPL][TI], b[NPL][TJ];
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
+    for (int h = 0; h < NPL; h++) {
 #pragma unroll
       for (int i = 0; i < TI; i++)
-        a[h][i] = *(const bf16x8*)&sm[cur][0][h][x3_pos(wm * 64 + i * 16 + fr, fc)];
+        a[h][i] = *(const TL8*)&sm[cur][0][h][x3_pos(wm * 64 + i * 16 + fr, fc)];
 #pragma unroll
       for (int j = 0; j < TJ; j++)
-        b[h][j] = *(const bf16x8*)&sm[cur][1][h][x3_pos(wn * 64 + j * 16 + fr, fc)];
+        b[h][j] = *(const TL8*)&sm[cur][1][h][x3_pos(wn * 64 + j * 16 + fr, fc)];
     }
 #pragma unroll
     for (int i = 0; i < TI; i++)
 #pragma unroll
       for (int j = 0; j < TJ; j++) {
         acc[i][j] = MF::mma(a[0][i], b[0][j], acc[i][j]);
-        acc[i][j] = MF::mma(a[1][i], b[0][j], acc[i][j]);
-        acc[i][j] = MF::mma(a[0][i], b[1][j], acc[i][j]);
+        if constexpr (X3) {
+          acc[i][j] = MF::mma(a[NPL - 1][i], b[0][j], acc[i][j]);
+          acc[i][j] = MF::mma(a[0][i], b[NPL - 1][j], acc[i][j]);
+        }
       }
     __builtin_amdgcn_sched_barrier(0);
     KP_X3_STORE(cur ^ 1, knext);
@@ -393,7 +402,7 @@ hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long
                           int K, const double* rw, const float* rwf, int rmod, bool sym,
                           void* part, int max_splits, int* splits_out, hipStream_t st) {
   const int BT = (mode == M_F64) ? 64 : 128;
-  const int BK = (mode == M_BF16 || mode == M_BF16X3) ? 32 : 16;
+  const int BK = (mode == M_BF16 || mode == M_BF16X3 || mode == M_F16) ? 32 : 16;
   const int ntm = kp_cdiv(M, BT), ntn = kp_cdiv(N, BT);
   const int ntiles = sym ? ntm * (ntm + 1) / 2 : ntm * ntn;
   int splits = kp_cdiv(1024, ntiles);
@@ -420,6 +429,17 @@ hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long
       else
         k_tn_x3<false><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M, N, K,
                                           nullptr, rmod, sym, ntm, ntn, kchunk, (float*)part);
+      break;
+    case M_F16:
+      if (rw && !rwf) return hipErrorInvalidValue;
+      if (rw)
+        k_tn_x3<true, false><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M, N,
+                                                K, rwf, rmod, sym, ntm, ntn, kchunk,
+                                                (float*)part);
+      else
+        k_tn_x3<false, false><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M,
+                                                 N, K, nullptr, rmod, sym, ntm, ntn, kchunk,
+                                                 (float*)part);
       break;
     default: return hipErrorInvalidValue;
   }

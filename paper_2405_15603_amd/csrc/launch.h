@@ -7,7 +7,7 @@
 
 namespace kp {
 
-enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
 
 // ---- factor / gradient products (modes of fwdlap.h) -------------------------
 // part[s][m*N + n] = sum_{k in split s} w(k) A[k][m] B[k][n] for the tiles the

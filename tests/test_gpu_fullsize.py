@@ -40,7 +40,8 @@ def factor_errors(kp, ref, L):
     return out
 
 
-def test_mixed_factor_gate_full_batch():
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
+def test_mixed_factor_gate_full_batch(precision):
     """The binding gate of the mixed path on its own workload: 100 mixed steps
     (grid line search, EMA) on the whole 3000 + 1000 batch; at steps 0, 50 and 100
     a second full-capacity context computes the factors of the current parameters
@@ -48,11 +49,11 @@ def test_mixed_factor_gate_full_batch():
     slab rows), and every factor must be within 1e-3 of the oracle's."""
     from paper_2405_15603_amd import HParams
     p = synth.poisson100d()
-    th, xi, yi, xb, yb = problem_inputs(p, "bf16")
-    kp = kp_for(p, "bf16")
-    gate = kp_for(p, "bf16")
-    theta = to_dev(th, "bf16")
-    full = [to_dev(a, "bf16") for a in (xi, yi, xb, yb)]
+    th, xi, yi, xb, yb = problem_inputs(p, precision)
+    kp = kp_for(p, precision)
+    gate = kp_for(p, precision)
+    theta = to_dev(th, precision)
+    full = [to_dev(a, precision) for a in (xi, yi, xb, yb)]
     hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
     worst = {}
     for it in range(101):
@@ -64,7 +65,7 @@ def test_mixed_factor_gate_full_batch():
             ref = oracle_factors_chunked(p, th_t, xi, yi, xb, yb)
             errs = factor_errors(gate, ref, len(p.widths) - 1)
             worst[it] = (max(e[0] for e in errs.values()), max(e[1] for e in errs.values()))
-            print(f"step {it}: worst factor rel {worst[it][0]:.2e}, blockwise {worst[it][1]:.2e}",
+            print(f"{precision} step {it}: worst factor rel {worst[it][0]:.2e}, blockwise {worst[it][1]:.2e}",
                   flush=True)
             bad = {k: v for k, v in errs.items() if not v[0] < 1e-3}
             assert not bad, (it, bad)

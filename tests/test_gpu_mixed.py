@@ -1,7 +1,8 @@
-"""Mixed-precision path (BF16 MFMA, FP32 accumulation, FP64 factors) against the
-FP64 oracle.  The binding tolerance is 1e-3 relative (Frobenius) per Kronecker
-factor; the Laplacian, gradient and direction are reported with looser bounds
-derived from BF16's unit roundoff 2^-9 ~ 2e-3 per rounded operand."""
+"""Mixed-precision paths (BF16x3 or single-pass FP16 curvature products, BF16
+line search, FP32 accumulation, FP64 factors) against the FP64 oracle.  The
+binding tolerance is 1e-3 relative (Frobenius) per Kronecker factor; the
+Laplacian, gradient and direction are reported with looser bounds derived from
+BF16's unit roundoff 2^-9 ~ 2e-3 per rounded operand (FP16's is 2^-11)."""
 import numpy as np
 import pytest
 import torch
@@ -18,18 +19,19 @@ def kp_for(p, precision, **kw):
     return KfacPinn.for_problem(p, precision, **kw)
 
 
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
 @pytest.mark.parametrize("case", ["poisson100d_subset", "heat_subset", "tiny"])
-def test_mixed_factors_within_1e_3(case):
+def test_mixed_factors_within_1e_3(case, precision):
     if case == "poisson100d_subset":
         p = synth.poisson100d(); ni, nb = 240, 80
     elif case == "heat_subset":
         p = synth.heat4d(); ni, nb = 800, 300
     else:
         p = synth.small_problem("poisson", (3, 16, 12, 1), 37, 11, problem_id=71); ni, nb = None, None
-    th, xi, yi, xb, yb = problem_inputs(p, "bf16", ni, nb)
-    kp = kp_for(p, "bf16", max_interior=xi.shape[0], max_boundary=xb.shape[0])
-    grad, loss = kp.factors(*(to_dev(a, "bf16") for a in (th, xi, yi, xb, yb)), beta=0.0)
-    u, g, lap = kp.forward_laplacian(to_dev(th, "bf16"), to_dev(xi, "bf16"))
+    th, xi, yi, xb, yb = problem_inputs(p, precision, ni, nb)
+    kp = kp_for(p, precision, max_interior=xi.shape[0], max_boundary=xb.shape[0])
+    grad, loss = kp.factors(*(to_dev(a, precision) for a in (th, xi, yi, xb, yb)), beta=0.0)
+    u, g, lap = kp.forward_laplacian(to_dev(th, precision), to_dev(xi, precision))
     assert kp.sync() == 0
     ref = oracle_curvature(p, th, xi, yi, xb, yb)
     errs = {}
@@ -41,7 +43,7 @@ def test_mixed_factors_within_1e_3(case):
     op = oracle.operator_of(p)
     U = oracle.forward_laplacian(oracle.unpack(torch.as_tensor(th), p.widths), torch.as_tensor(xi),
                                  op.mask_vec(p.d)).out
-    print(f"{case}: worst factor {worst:.2e}  lap {rel(lap, U[:, -1]):.2e}  "
+    print(f"{case} {precision}: worst factor {worst:.2e}  lap {rel(lap, U[:, -1]):.2e}  "
           f"grad {rel(grad, ref['grad']):.2e}")
     bad = {k: v for k, v in errs.items() if not v < 1e-3}
     assert not bad, bad
@@ -49,8 +51,9 @@ def test_mixed_factors_within_1e_3(case):
     assert rel(grad, ref["grad"]) < 2e-2
 
 
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
 @pytest.mark.parametrize("case", ["poisson100d_subset", "heat_subset"])
-def test_mixed_line_search_losses(case):
+def test_mixed_line_search_losses(case, precision):
     """The BF16 line-search forward: every candidate loss L(theta + 2^k dhat) of a
     mixed step against the FP64 oracle's loss at the same point (dhat recovered
     from the applied update, delta = alpha* dhat).  BF16 rounds every slab entry
@@ -63,11 +66,11 @@ def test_mixed_line_search_losses(case):
         p = synth.poisson100d(); ni, nb = 240, 80
     else:
         p = synth.heat4d(); ni, nb = 800, 300
-    th, xi, yi, xb, yb = problem_inputs(p, "bf16", ni, nb)
-    kp = kp_for(p, "bf16", max_interior=ni, max_boundary=nb)
-    theta = to_dev(th, "bf16")
+    th, xi, yi, xb, yb = problem_inputs(p, precision, ni, nb)
+    kp = kp_for(p, precision, max_interior=ni, max_boundary=nb)
+    theta = to_dev(th, precision)
     hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
-    info = KfacPinn.decode_info(kp.step(theta, *(to_dev(a, "bf16") for a in (xi, yi, xb, yb)), hp))
+    info = KfacPinn.decode_info(kp.step(theta, *(to_dev(a, precision) for a in (xi, yi, xb, yb)), hp))
     assert kp.sync() == 0 and info["status"] == 0
     alpha = info["lr"]
     dhat = kp.get_momentum().cpu().double().numpy() / alpha

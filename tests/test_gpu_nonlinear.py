@@ -30,7 +30,7 @@ def kp_for(p, precision, **kw):
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("precision,tol,gtol", [("f64", 1e-10, 1e-10), ("f32", 1e-5, 1e-4),
-                                                ("bf16", 1e-3, 2e-2)])
+                                                ("bf16", 1e-3, 2e-2), ("f16", 1e-3, 2e-2)])
 def test_factors_gradient_loss(case, precision, tol, gtol):
     p = CASES[case]()
     th, xi, yi, xb, yb = problem_inputs(p, precision)
