@@ -267,6 +267,25 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
   const int m0 = ti * BM, n0 = tj * BM;
   const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
   float* out = part + (long)split * M * N;
+  // FP16: the row weights (residuals, any magnitude) are scaled by a power of two
+  // to at most 1 in magnitude before the weighted rows are rounded to FP16, and the
+  // partial sums are scaled back; both scalings are exact.
+  float wscale = 1.0f, wunscale = 1.0f;
+  if constexpr (WEIGHTED && !X3) {
+    __shared__ float wmax[4];
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < rmod; i += blockDim.x) m = fmaxf(m, fabsf(rw[i]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    if (m > 0.0f && m <= 3.0e38f) {
+      int e;
+      (void)frexpf(m, &e);   // m < 2^e
+      wscale = ldexpf(1.0f, -e);
+      wunscale = ldexpf(1.0f, e);
+    }
+  }
 
   // loader role: operand (0 = A, 1 = B), column group, row group
   const int opd = tid >> 7, lt = tid & 127;
@@ -286,7 +305,7 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
       const int gk = (K0) + 8 * rg + j;                                          \
       const int gkc = min(gk, kend - 1);                                         \
       ra[j] = ld16(src + (long)gkc * ld + colc);                                 \
-      if (WEIGHTED && opd == 0) wr[j] = rw[gkc % rmod];                          \
+      if (WEIGHTED && opd == 0) wr[j] = rw[gkc % rmod] * wscale;                 \
     }                                                                            \
   }
 #define KP_X3_STORE(BUF, K0)                                                      \
@@ -379,7 +398,7 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         const int r = m0 + wm * 64 + i * 16 + MF::row(lane, e);
-        if (r < M) out[(long)r * N + c] = acc[i][j][e];
+        if (r < M) out[(long)r * N + c] = acc[i][j][e] * wunscale;
       }
     }
 }

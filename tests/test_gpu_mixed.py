@@ -86,3 +86,25 @@ def test_mixed_line_search_losses(case, precision):
     assert np.all(err < 5e-2), err
     chosen = ref[ks.index(int(round(np.log2(alpha))))]
     assert chosen <= ref.min() * (1 + 5e-2)
+
+
+def test_f16_gradient_with_residuals_beyond_fp16_range():
+    """Targets scaled by 300, so residuals reach ~1e5 and the residual-weighted rows
+    of the gradient product exceed FP16's largest value (65504): that product scales
+    its row weights by a power of two before rounding, so the FP16 path's gradient
+    stays finite and within the mixed bound of the oracle's, as do the factors."""
+    p = synth.Problem("large_residuals", synth.POISSON, [20, 64, 64, 48, 48, 1], 400, 70,
+                      scale=300.0, problem_id=10060)
+    th, xi, yi, xb, yb = problem_inputs(p, "f16")
+    assert np.abs(yi).max() > 65504.0 / 10
+    kp = kp_for(p, "f16", max_interior=xi.shape[0], max_boundary=xb.shape[0])
+    grad, loss = kp.factors(*(to_dev(a, "f16") for a in (th, xi, yi, xb, yb)), beta=0.0)
+    assert kp.sync() == 0
+    ref = oracle_curvature(p, th, xi, yi, xb, yb)
+    assert torch.isfinite(grad).all()
+    print(f"gradient rel {rel(grad, ref['grad']):.2e}")
+    assert rel(grad, ref["grad"]) < 2e-2
+    for l in range(len(p.widths) - 1):
+        for t, tn in ((0, "int"), (1, "bnd")):
+            for s, sn in ((0, "A"), (1, "B")):
+                assert rel(kp.get_factor(l, t, s), ref[f"{sn}_{tn}"][l]) < 1e-3
