@@ -236,7 +236,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "f16", "f32", "f64"],
+    ap.add_argument("--precision", default="f16", choices=["bf16", "f16", "f32", "f64"],
                     help="bf16: BF16x3 curvature products; f16: FP16 curvature products "
                          "(both with a BF16 line search)")
     ap.add_argument("--workload", default="poisson100d")

@@ -128,6 +128,7 @@ struct kfac_pinn_ctx {
   int last_ncand = 0;
   std::vector<double*> F[2][2];        // F[term][side][layer]
   void* part = nullptr;
+  float* wsc = nullptr;                 // FP16 row-weight scale (2 floats)
   double* grad = nullptr;
   double* Delta = nullptr;
   void* dhat = nullptr;
@@ -633,9 +634,13 @@ struct FactorGrad : LayerConsumer {
       return e;
     // gradient: sum_rows (r_n / n) g (x) z~, column-major into theta
     const Slabs& s = term == 0 ? c->si : c->sb;
+    ti = tm_begin(c, KC_FACTOR_GEMM);
     if ((e = gemm_tn_splitk(m, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1, K, s.r,
-                            s.rf, n, false, c->part, kMaxSplits, &sp, c->st)) != hipSuccess)
+                            s.rf, n, false, c->part, kMaxSplits, &sp, c->st, c->wsc)) !=
+        hipSuccess)
       return e;
+    tm_end(c, ti, 2.0 * K * ld.h_out * (ld.h_in + 1),
+           (double)K * (ld.h_out + ld.h_in + 1) * c->esz_s);
     return reduce_splitk(m, c->part, sp, ld.h_out, ld.h_in + 1, false, c->grad + ld.off, 1,
                          ld.h_out, 1.0 / n, term == 0 ? 0.0 : 1.0, c->st);
   }
@@ -991,6 +996,7 @@ kp_status kfac_pinn_create(const kp_problem* pb, void* stream, kfac_pinn_ctx** o
       mn = std::max(mn, std::max(a * a, std::max(b * b, a * b)));
     }
     ALLOC(c->part, (size_t)kMaxSplits * mn * c->esz_c);
+    ALLOC(c->wsc, 2 * sizeof(float));
   }
   ALLOC(c->grad, sizeof(double) * c->D);
   ALLOC(c->Delta, sizeof(double) * c->D);

@@ -233,6 +233,29 @@ __device__ __forceinline__ int x3_pos(int col, int chunk) {
   return (col ^ q) * X3_BK + ((chunk ^ q ^ ((col >> 4) & 3)) << 3);
 }
 
+// wsc[0] = 2^-e and wsc[1] = 2^e with max_i |rw[i]| < 2^e (1 and 1 when the weights
+// are all zero or not finite): the scaling that keeps FP16 row weights within 1.
+__global__ __launch_bounds__(256) void k_row_scale(const float* __restrict__ rw, int n,
+                                                   float* __restrict__ wsc) {
+  __shared__ float part[4];
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(rw[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  m = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+  float s = 1.0f, u = 1.0f;
+  if (m > 0.0f && m <= 3.0e38f) {
+    int e;
+    (void)frexpf(m, &e);   // m < 2^e
+    s = ldexpf(1.0f, -e);
+    u = ldexpf(1.0f, e);
+  }
+  wsc[0] = s;
+  wsc[1] = u;
+}
+
 // X3 = false: the single-pass FP16 variant (one FP16 plane, one MFMA per
 // product) with the same tiles, loads and LDS layout.
 template <bool WEIGHTED, bool X3 = true>
@@ -240,7 +263,8 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
                                                const float* __restrict__ B, long ldb, int M,
                                                int N, int K, const float* __restrict__ rw,
                                                int rmod, int sym, int ntm, int ntn, int kchunk,
-                                               float* __restrict__ part) {
+                                               float* __restrict__ part,
+                                               const float* __restrict__ wsc) {
   typedef typename std::conditional<X3, bf16, f16>::type TL;
   typedef typename std::conditional<X3, bf16x4, f16x4>::type TL4;
   typedef typename std::conditional<X3, bf16x8, f16x8>::type TL8;
@@ -267,24 +291,15 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
   const int m0 = ti * BM, n0 = tj * BM;
   const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
   float* out = part + (long)split * M * N;
-  // FP16: the row weights (residuals, any magnitude) are scaled by a power of two
-  // to at most 1 in magnitude before the weighted rows are rounded to FP16, and the
-  // partial sums are scaled back; both scalings are exact.
+  // FP16: the row weights (residuals, any magnitude) enter scaled by the power of
+  // two wsc[0] (k_row_scale: |w| <= 1) and the partial sums leave scaled by
+  // wsc[1] = 1 / wsc[0]; both scalings are exact.  (The scaling is applied where
+  // the weights are used, after the products: applied where they are loaded, it
+  // would wait for those loads and with them for the prefetched rows.)
   float wscale = 1.0f, wunscale = 1.0f;
   if constexpr (WEIGHTED && !X3) {
-    __shared__ float wmax[4];
-    float m = 0.0f;
-    for (int i = threadIdx.x; i < rmod; i += blockDim.x) m = fmaxf(m, fabsf(rw[i]));
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-    __syncthreads();
-    m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-    if (m > 0.0f && m <= 3.0e38f) {
-      int e;
-      (void)frexpf(m, &e);   // m < 2^e
-      wscale = ldexpf(1.0f, -e);
-      wunscale = ldexpf(1.0f, e);
-    }
+    wscale = wsc[0];
+    wunscale = wsc[1];
   }
 
   // loader role: operand (0 = A, 1 = B), column group, row group
@@ -305,7 +320,7 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
       const int gk = (K0) + 8 * rg + j;                                          \
       const int gkc = min(gk, kend - 1);                                         \
       ra[j] = ld16(src + (long)gkc * ld + colc);                                 \
-      if (WEIGHTED && opd == 0) wr[j] = rw[gkc % rmod] * wscale;                 \
+      if (WEIGHTED && opd == 0) wr[j] = rw[gkc % rmod];                          \
     }                                                                            \
   }
 #define KP_X3_STORE(BUF, K0)                                                      \
@@ -314,7 +329,7 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
     _Pragma("unroll") for (int j = 0; j < 8; j++) {                              \
       const int gk = (K0) + 8 * rg + j;                                          \
       wt[j] = (col_ok && gk < kend) ? 1.0f : 0.0f;                               \
-      if (WEIGHTED && opd == 0) wt[j] *= wr[j];                                  \
+      if (WEIGHTED && opd == 0) wt[j] *= wr[j] * wscale;                         \
     }                                                                            \
     f32x4 fr[8];                                                                 \
     _Pragma("unroll") for (int j = 0; j < 8; j++)                                \
@@ -419,7 +434,8 @@ static void launch_tn(dim3 g, const void* A, long lda, const void* B, long ldb, 
 
 hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long ldb, int M, int N,
                           int K, const double* rw, const float* rwf, int rmod, bool sym,
-                          void* part, int max_splits, int* splits_out, hipStream_t st) {
+                          void* part, int max_splits, int* splits_out, hipStream_t st,
+                          float* wsc) {
   const int BT = (mode == M_F64) ? 64 : 128;
   const int BK = (mode == M_BF16 || mode == M_BF16X3 || mode == M_F16) ? 32 : 16;
   const int ntm = kp_cdiv(M, BT), ntn = kp_cdiv(N, BT);
@@ -444,21 +460,24 @@ hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long
       if (rw && !rwf) return hipErrorInvalidValue;
       if (rw)
         k_tn_x3<true><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M, N, K, rwf,
-                                         rmod, sym, ntm, ntn, kchunk, (float*)part);
+                                         rmod, sym, ntm, ntn, kchunk, (float*)part, nullptr);
       else
         k_tn_x3<false><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M, N, K,
-                                          nullptr, rmod, sym, ntm, ntn, kchunk, (float*)part);
+                                          nullptr, rmod, sym, ntm, ntn, kchunk, (float*)part,
+                                          nullptr);
       break;
     case M_F16:
-      if (rw && !rwf) return hipErrorInvalidValue;
-      if (rw)
+      if (rw && (!rwf || !wsc)) return hipErrorInvalidValue;
+      if (rw) {
+        k_row_scale<<<1, 256, 0, st>>>(rwf, rmod, wsc);
         k_tn_x3<true, false><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M, N,
                                                 K, rwf, rmod, sym, ntm, ntn, kchunk,
-                                                (float*)part);
-      else
+                                                (float*)part, wsc);
+      } else {
         k_tn_x3<false, false><<<g, 256, 0, st>>>((const float*)A, lda, (const float*)B, ldb, M,
                                                  N, K, nullptr, rmod, sym, ntm, ntn, kchunk,
-                                                 (float*)part);
+                                                 (float*)part, nullptr);
+      }
       break;
     default: return hipErrorInvalidValue;
   }

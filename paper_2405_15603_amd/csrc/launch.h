@@ -16,9 +16,12 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
 // the BF16x3 mode reads the FP32 copy rwf of the weights instead.  A and B are
 // row-major K x (>= M / N, rounded up to 4) with lda/ldb.  part is double for
 // FP64, float otherwise.  The launcher picks the number of splits (<= max_splits).
+// wsc: 2 floats of device scratch for the FP16 path's row-weight scaling (needed
+// with rw in mode M_F16).
 hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long ldb, int M, int N,
                           int K, const double* rw, const float* rwf, int rmod, bool sym,
-                          void* part, int max_splits, int* splits_out, hipStream_t st);
+                          void* part, int max_splits, int* splits_out, hipStream_t st,
+                          float* wsc = nullptr);
 // out[m*so_m + n*so_n] = c_prev*out + alpha * sum_s part[s][m*N+n]  (double out);
 // with sym the lower triangle is mirrored from the upper.
 hipError_t reduce_splitk(int mode, const void* part, int splits, int M, int N, bool sym,
