@@ -305,9 +305,29 @@ __global__ __launch_bounds__(256) void k_trtri_row(const EigProblem* __restrict_
 //   mode 3: C0 <- V^T C1
 //   mode 4: P1 <- Li^T V         (Li^T upper: k >= bi)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ pr, int mode,
+// The operand tiles of block k for output tile (bi, bj), by mode (a template
+// parameter, so that the pointers need no run-time dispatch).
+template <int MODE>
+__device__ __forceinline__ const double* eig_mm_a(const EigProblem& p, long np, int bi, int k) {
+  if constexpr (MODE == 0) return p.Li + (long)bi * BB * np + (long)k * BB;
+  if constexpr (MODE == 1) return p.C[1] + (long)bi * BB * np + (long)k * BB;
+  if constexpr (MODE == 2) return p.C[0] + (long)bi * BB * np + (long)k * BB;
+  if constexpr (MODE == 3) return p.P[0] + (long)k * BB * np + (long)bi * BB;
+  return p.Li + (long)k * BB * np + (long)bi * BB;
+}
+template <int MODE>
+__device__ __forceinline__ const double* eig_mm_b(const EigProblem& p, long np, int bj, int k) {
+  if constexpr (MODE == 0) return p.M2 + (long)bj * BB * np + (long)k * BB;
+  if constexpr (MODE == 1) return p.Li + (long)bj * BB * np + (long)k * BB;
+  if constexpr (MODE == 2) return p.P[0] + (long)k * BB * np + (long)bj * BB;
+  if constexpr (MODE == 3) return p.C[1] + (long)k * BB * np + (long)bj * BB;
+  return p.P[0] + (long)k * BB * np + (long)bj * BB;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ pr,
                                                 const int* __restrict__ warm) {
-  if (mode >= 2 && mode <= 3 && !*warm) return;   // the warm-start products only
+  if (MODE >= 2 && MODE <= 3 && !*warm) return;   // the warm-start products only
   const EigProblem p = pr[blockIdx.z];
   const int nb = p.n_pad / BB;
   const int bi = blockIdx.y, bj = blockIdx.x;
@@ -315,57 +335,47 @@ __global__ __launch_bounds__(256) void k_eig_mm(const EigProblem* __restrict__ p
   const long np = p.n_pad;
   __shared__ __align__(16) double As[BB * LDM];
   __shared__ __align__(16) double Bs[BB * LDM];
-  // 64 x 64 operand tiles of block k
-  auto tile_a = [&](int k) -> const double* {
-    switch (mode) {
-      case 0: return p.Li + (long)bi * BB * np + (long)k * BB;
-      case 1: return p.C[1] + (long)bi * BB * np + (long)k * BB;
-      case 2: return p.C[0] + (long)bi * BB * np + (long)k * BB;
-      case 3: return p.P[0] + (long)k * BB * np + (long)bi * BB;
-      default: return p.Li + (long)k * BB * np + (long)bi * BB;
-    }
-  };
-  auto tile_b = [&](int k) -> const double* {
-    switch (mode) {
-      case 0: return p.M2 + (long)bj * BB * np + (long)k * BB;
-      case 1: return p.Li + (long)bj * BB * np + (long)k * BB;
-      case 2: return p.P[0] + (long)k * BB * np + (long)bj * BB;
-      case 3: return p.C[1] + (long)k * BB * np + (long)bj * BB;
-      default: return p.P[0] + (long)k * BB * np + (long)bj * BB;
-    }
-  };
   // thread t moves elements 2t + 512 m (m < 8) of a tile: rows 8m + t / 32,
   // columns 2 (t % 32) and the next
   const int lr = threadIdx.x >> 5, lc = 2 * (threadIdx.x & 31);
-  double2 ra[8], rb[8];
-  auto fetch = [&](int k) {
-    const double* a = tile_a(k);
-    const double* b = tile_b(k);
-#pragma unroll
-    for (int m = 0; m < 8; m++) {
-      ra[m] = *(const double2*)(a + (long)(8 * m + lr) * np + lc);
-      rb[m] = *(const double2*)(b + (long)(8 * m + lr) * np + lc);
-    }
-  };
+  // native 2-vectors (HIP's double2 struct arrays are not kept in registers)
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2 ra[8], rb[8];
   f64x4 acc[2][2];
   mm64_zero(acc);
-  const int kbeg = mode == 4 ? bi : 0;
-  const int kend = mode == 0 ? bi : (mode == 1 ? bj : nb - 1);
-  fetch(kbeg);
+  const int kbeg = MODE == 4 ? bi : 0;
+  const int kend = MODE == 0 ? bi : (MODE == 1 ? bj : nb - 1);
+  {
+    const double* a = eig_mm_a<MODE>(p, np, bi, kbeg);
+    const double* b = eig_mm_b<MODE>(p, np, bj, kbeg);
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+      ra[m] = *(const d2*)(a + (long)(8 * m + lr) * np + lc);
+      rb[m] = *(const d2*)(b + (long)(8 * m + lr) * np + lc);
+    }
+  }
   for (int k = kbeg; k <= kend; k++) {
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 8; m++) {
-      *(double2*)&As[(8 * m + lr) * LDM + lc] = ra[m];
-      *(double2*)&Bs[(8 * m + lr) * LDM + lc] = rb[m];
+      *(d2*)&As[(8 * m + lr) * LDM + lc] = ra[m];
+      *(d2*)&Bs[(8 * m + lr) * LDM + lc] = rb[m];
     }
     __syncthreads();
-    if (k < kend) fetch(k + 1);   // in flight during the products
-    if (mode <= 1) mm64<false, true>(acc, As, Bs);
-    else if (mode == 2) mm64<false, false>(acc, As, Bs);
-    else mm64<true, false>(acc, As, Bs);
+    if (k < kend) {   // the next tiles are in flight during the products
+      const double* a = eig_mm_a<MODE>(p, np, bi, k + 1);
+      const double* b = eig_mm_b<MODE>(p, np, bj, k + 1);
+#pragma unroll
+      for (int m = 0; m < 8; m++) {
+        ra[m] = *(const d2*)(a + (long)(8 * m + lr) * np + lc);
+        rb[m] = *(const d2*)(b + (long)(8 * m + lr) * np + lc);
+      }
+    }
+    if constexpr (MODE <= 1) mm64<false, true>(acc, As, Bs);
+    else if constexpr (MODE == 2) mm64<false, false>(acc, As, Bs);
+    else mm64<true, false>(acc, As, Bs);   // modes 3 and 4: the A tile transposed
   }
-  double* out = (mode == 0 || mode == 2) ? p.C[1] : (mode == 4 ? p.P[1] : p.C[0]);
+  double* out = (MODE == 0 || MODE == 2) ? p.C[1] : (MODE == 4 ? p.P[1] : p.C[0]);
   out += (long)bi * BB * np + (long)bj * BB;
   mm64_each(acc, [&](int i, int j, double v) { out[(long)i * np + j] = v; });
 }
@@ -946,10 +956,10 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
   }
   for (int i = 1; i < nbmax; i++) k_trtri_row<<<dim3(i, nprob), 256, 0, st>>>(probs_dev, i);
   const dim3 gmm(nbmax, nbmax, nprob);
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 0, calls + 1);
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 1, calls + 1);
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 2, calls + 1);
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 3, calls + 1);
+  k_eig_mm<0><<<gmm, 256, 0, st>>>(probs_dev, calls + 1);
+  k_eig_mm<1><<<gmm, 256, 0, st>>>(probs_dev, calls + 1);
+  k_eig_mm<2><<<gmm, 256, 0, st>>>(probs_dev, calls + 1);
+  k_eig_mm<3><<<gmm, 256, 0, st>>>(probs_dev, calls + 1);
   k_jac_init<<<dim3(256, nprob), 256, 0, st>>>(probs_dev, done, calls + 1);
   k_jac_dmax<<<nprob, 256, 0, st>>>(probs_dev);
   // Sweeps of the groups, interleaved round by round on their streams: the
@@ -1014,7 +1024,7 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
     }
   }
   k_jac_final<<<(nprob + 63) / 64, 64, 0, st>>>(probs_dev, done, nprob, status);
-  k_eig_mm<<<gmm, 256, 0, st>>>(probs_dev, 4, calls + 1);
+  k_eig_mm<4><<<gmm, 256, 0, st>>>(probs_dev, calls + 1);
   k_jac_extract<<<dim3(64, nprob), 256, 0, st>>>(probs_dev);
   return hipGetLastError();
 }
