@@ -103,9 +103,11 @@ def run_gpu(problem, precision, steps, warmup, kernel_class=None, lr_mode="grid"
     return ms, tm, status, last
 
 
-def run_batch(count, steps, warmup, use_graph, precision="bf16"):
+def run_batch(count, steps, warmup, use_graph, precision="bf16", grouped=True, tuned=False):
     """One step of `count` heterogeneous instances per call (the 64-instance
-    recipe), as a captured graph or as direct launches on the internal lanes."""
+    recipe), as a captured graph or as direct launches on the internal lanes,
+    with the grouped line search (one launch per kernel over every instance) or
+    the per-instance one."""
     import numpy as np
     import torch
     import synth
@@ -116,6 +118,8 @@ def run_batch(count, steps, warmup, use_graph, precision="bf16"):
     thetas = [T(p.theta0()) for p in probs]
     cols = list(zip(*[[T(a) for a in p.batch(0)] for p in probs]))
     b = KfacPinnBatch(probs, precision, use_graph=use_graph)
+    b.set_grouped(grouped)
+    timed_classes = b.tune(thetas, *cols) if tuned else 0
     hp = hparams()
     for _ in range(warmup):
         b.step(thetas, *cols, hp)
@@ -129,9 +133,11 @@ def run_batch(count, steps, warmup, use_graph, precision="bf16"):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     status = b.sync()
+    was_grouped = b.is_grouped()
     del b
     return {"ms_per_step": ms, "instance_steps_per_s": count * 1000.0 / ms,
-            "status_nonzero": sum(1 for v in status if v != 0)}
+            "status_nonzero": sum(1 for v in status if v != 0), "grouped_line_search": was_grouped,
+            "tuned_classes": timed_classes}
 
 
 def copy_calibration(mib):
@@ -356,7 +362,10 @@ def main():
         out["batch64"] = {"instances": 64, "note": "heterogeneous 64-instance recipe, mixed "
                           "precision, grid line search; one step of every instance per call",
                           "graph": run_batch(64, 3, 1, True, bp),
-                          "direct": run_batch(64, 3, 1, False, bp)}
+                          "graph_tuned": run_batch(64, 3, 1, True, bp, tuned=True),
+                          "direct": run_batch(64, 3, 1, False, bp),
+                          "graph_per_instance_line_search": run_batch(64, 3, 1, True, bp,
+                                                                      grouped=False)}
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(problem)

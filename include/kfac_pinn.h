@@ -365,8 +365,14 @@ kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
  * and gradients of every instance (on the lanes), then ONE inversion launch
  * sequence over the damped factors of all instances together (on lane 0, so
  * each eigensolver launch covers every instance's problems), then the
- * directions, line searches and updates (on the lanes).  The results equal
- * those of kfac_pinn_step on each instance.  The Jacobi warm start and its
+ * directions, line searches and updates (on the lanes).  With the grid line
+ * search (lr_mode 1), BF16 line-search slabs and every instance on the paired
+ * line-search launches (linear residuals, unit input directions, both point
+ * sets non-empty), the line search is grouped: each of a candidate's kernels
+ * runs ONCE over every instance (job tables in device memory, made at creation
+ * for the largest point counts and rewritten when the step's buffers or point
+ * counts change), on lane 0 between the directions and the updates on the
+ * lanes.  The results equal those of kfac_pinn_step on each instance.  The Jacobi warm start and its
  * periodic cold start are counted per batch step, and the sweeps used are read
  * with kfac_pinn_batch_get_sweeps (kfac_pinn_get_sweeps on an instance's
  * context reports only its own kfac_pinn_step/invert calls).  The work is
@@ -383,6 +389,32 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
 kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* batch);
 kp_status kfac_pinn_batch_context(kfac_pinn_batch* batch, int32_t k, kfac_pinn_ctx** out);
 kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* batch, int32_t enabled);
+/* The grouped line search (default 1) on or off (0: every instance's candidates
+ * launch per instance on its lane, as kfac_pinn_step does); KP_ERR_ARG for other
+ * values.  kfac_pinn_batch_is_grouped writes (host) whether the last batch step
+ * took the grouped line search. */
+kp_status kfac_pinn_batch_set_grouped(kfac_pinn_batch* batch, int32_t enabled);
+kp_status kfac_pinn_batch_is_grouped(kfac_pinn_batch* batch, int32_t* out);
+/* Autotuning of the grouped line search (not in the paper).  Chooses, per class
+ * (K = h_in + 1 rounded up to 8, h_out, rows per point S) of the grouped layer
+ * products past the input layer, the number of derivative-row chunks by timing
+ * the grouped layer launch of every instance with each candidate (the
+ * single-instance choice and 1, 2, 4, 8 chunks); a count replaces the
+ * single-instance choice only when at least 3 % faster.  The arguments are those
+ * of kfac_pinn_batch_step (both point sets non-empty); the instances' parameters
+ * are not changed, their line-search buffers are overwritten.  cache_path (or
+ * NULL): a JSON file of earlier choices per device and class, read first (cached
+ * classes are not timed) and rewritten with the merged choices; an unwritable
+ * path gives KP_ERR_ARG after the choices are applied.  timed (or NULL): the
+ * number of classes timed.  Waits for the device.  With tuned counts other than
+ * the single-instance choice the candidates' losses differ from kfac_pinn_step's
+ * in rounding (another grouping of the sums over derivative rows).  KP_ERR_STATE
+ * when the instances do not take the grouped line search. */
+kp_status kfac_pinn_batch_tune(kfac_pinn_batch* batch, void* const* thetas,
+                               const void* const* x_int, const void* const* y_int,
+                               const int32_t* n_int, const void* const* x_bnd,
+                               const void* const* y_bnd, const int32_t* n_bnd,
+                               const char* cache_path, int32_t* timed);
 /* Jacobi sweeps of instance k's eigenproblems in the last batch step (waits for
  * it): sweeps[2*layer + side] for side 0 (input factors) and 1 (output factors);
  * `sweeps` is a host array of 2 * n_layers ints. */

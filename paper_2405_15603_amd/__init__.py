@@ -388,6 +388,15 @@ class KfacPinnBatch:
         N.check(self.lib.kfac_pinn_batch_set_graph(self.h, 1 if enabled else 0),
                 "kfac_pinn_batch_set_graph")
 
+    def set_grouped(self, enabled: bool) -> None:
+        N.check(self.lib.kfac_pinn_batch_set_grouped(self.h, 1 if enabled else 0),
+                "kfac_pinn_batch_set_grouped")
+
+    def is_grouped(self) -> bool:
+        v = C.c_int32()
+        N.check(self.lib.kfac_pinn_batch_is_grouped(self.h, C.byref(v)), "kfac_pinn_batch_is_grouped")
+        return bool(v.value)
+
     def step(self, thetas, xi, yi, xb, yb, hp: HParams, infos: Optional[torch.Tensor] = None):
         """One step of every instance; lists of tensors per instance.  `infos`
         (device bytes, len * sizeof(kp_step_info)) receives the summaries."""
@@ -400,6 +409,21 @@ class KfacPinnBatch:
             V(*[t.data_ptr() for t in yi]), I(*[t.shape[0] for t in xi]),
             V(*[t.data_ptr() for t in xb]), V(*[t.data_ptr() for t in yb]),
             I(*[t.shape[0] for t in xb]), C.byref(hpc), _ptr(infos)), "kfac_pinn_batch_step")
+
+    def tune(self, thetas, xi, yi, xb, yb, cache_path: Optional[str] = None) -> int:
+        """Chunk counts of the grouped line search by timing (kfac_pinn_batch_tune);
+        returns the number of classes timed (the rest came from the cache)."""
+        n = len(self.problems)
+        V = C.c_void_p * n
+        I = C.c_int32 * n
+        timed = C.c_int32()
+        N.check(self.lib.kfac_pinn_batch_tune(
+            self.h, V(*[t.data_ptr() for t in thetas]), V(*[t.data_ptr() for t in xi]),
+            V(*[t.data_ptr() for t in yi]), I(*[t.shape[0] for t in xi]),
+            V(*[t.data_ptr() for t in xb]), V(*[t.data_ptr() for t in yb]),
+            I(*[t.shape[0] for t in xb]), cache_path.encode() if cache_path else None,
+            C.byref(timed)), "kfac_pinn_batch_tune")
+        return timed.value
 
     def sync(self) -> list:
         return [c.sync() for c in self.contexts]

@@ -81,6 +81,12 @@ _SIGS = {
     "kfac_pinn_batch_destroy": (C.c_int, [_V]),
     "kfac_pinn_batch_context": (C.c_int, [_V, C.c_int32, C.POINTER(_V)]),
     "kfac_pinn_batch_set_graph": (C.c_int, [_V, C.c_int32]),
+    "kfac_pinn_batch_set_grouped": (C.c_int, [_V, C.c_int32]),
+    "kfac_pinn_batch_is_grouped": (C.c_int, [_V, C.POINTER(C.c_int32)]),
+    "kfac_pinn_batch_tune": (C.c_int, [_V, C.POINTER(_V), C.POINTER(_V), C.POINTER(_V),
+                                       C.POINTER(C.c_int32), C.POINTER(_V), C.POINTER(_V),
+                                       C.POINTER(C.c_int32), C.c_char_p,
+                                       C.POINTER(C.c_int32)]),
     "kfac_pinn_batch_get_sweeps": (C.c_int, [_V, C.c_int32, C.POINTER(C.c_int32)]),
     "kfac_pinn_batch_step": (C.c_int, [_V, C.POINTER(_V), C.POINTER(_V), C.POINTER(_V),
                                        C.POINTER(C.c_int32), C.POINTER(_V), C.POINTER(_V),

@@ -8,8 +8,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <functional>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -681,10 +683,9 @@ hipError_t curvature_term(kfac_pinn_ctx* c, int term, const void* theta, const v
 }
 
 // total loss at the parameters in theta_trial (line-search precision) into loss[slot]
-hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, const void* xb,
-                     const void* yb, int nb, int slot) {
-  hipError_t e;
-  FwdTarget T;
+// The line-search forward targets: the interior (ping-pong slabs) and the
+// boundary (one slab per layer input).
+void ls_targets(kfac_pinn_ctx* c, FwdTarget& T, FwdTarget& Tb) {
   T.mode = c->lmode;
   T.zp = c->lp;
   T.zesz = c->esz_l;
@@ -697,10 +698,22 @@ hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, c
   T.full_input = false;
   // a residual with first-order terms reads every derivative row of the output
   T.residual_rows = !c->nonlinear;
-  if (ni > 0 && nb > 0 && T.mode == M_BF16 && !c->sb.has_lap && c->L >= 2 && !c->nonlinear) {
-    FwdTarget Tb = T;
-    Tb.z = [c](int l) { return c->ls_zb[l]; };
-    Tb.u = c->ls_ub;
+  Tb = T;
+  Tb.z = [c](int l) { return c->ls_zb[l]; };
+  Tb.u = c->ls_ub;
+}
+
+// whether a candidate's two point sets take the paired BF16 launches
+bool ls_paired(const kfac_pinn_ctx* c, int ni, int nb) {
+  return ni > 0 && nb > 0 && c->lmode == M_BF16 && !c->sb.has_lap && c->L >= 2 && !c->nonlinear;
+}
+
+hipError_t eval_loss(kfac_pinn_ctx* c, const void* xi, const void* yi, int ni, const void* xb,
+                     const void* yb, int nb, int slot) {
+  hipError_t e;
+  FwdTarget T, Tb;
+  ls_targets(c, T, Tb);
+  if (ls_paired(c, ni, nb)) {
     if ((e = forward_pair(c, xi, ni, T, xb, nb, Tb)) != hipSuccess) return e;
     const LayerDesc& ld = c->nd.l[c->L - 1];
     return ls_loss(T.mode, T.z(c->L - 1), c->ldz[c->L - 1], ni, time_row_of(c, c->si),
@@ -1474,16 +1487,23 @@ static kp_status kstar_tail(kfac_pinn_ctx* c, void* theta, int32_t ni, int32_t n
   return KP_OK;
 }
 
+// The step after the inversion.  part < 0: all of it; 0: the direction and the
+// momentum only; 2: the choice of the step size and the update only (the line
+// search's losses already in loss[2..], e.g. from a grouped batch launch).
 static kp_status step_tail(kfac_pinn_ctx* c, void* theta, const void* xi, const void* yi,
                            int32_t ni, const void* xb, const void* yb, int32_t nb,
-                           const kp_hparams* hp, kp_step_info* info) {
+                           const kp_hparams* hp, kp_step_info* info, int part = -1) {
   const int ncand = hp->lr_mode == 1 ? hp->grid_max_exp - hp->grid_min_exp + 1 : 0;
-  // 4) Delta = -C g, momentum
-  KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
-  if (hp->lr_mode == 2) return kstar_tail(c, theta, ni, nb, hp, info);
-  KP_TRY(momentum(c->pp, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
+  if (part <= 0) {
+    // 4) Delta = -C g, momentum
+    KP_TRY(kron_apply_batched(c->kdesc, c->L, c->k_mmax, c->k_nmax, c->st));
+    if (hp->lr_mode == 2) return kstar_tail(c, theta, ni, nb, hp, info);
+    KP_TRY(momentum(c->pp, c->Delta, c->delta, hp->momentum, c->ctl + 1, c->dhat, c->D, c->st));
+    if (part == 0) return KP_OK;
+  }
+  if (part == 2) c->last_ncand = ncand;
   // 5) learning rate and update
-  if (hp->lr_mode == 1) {
+  if (hp->lr_mode == 1 && part < 0) {
     // The candidates are independent: with two lanes the odd ones run on lane 1
     // (its own buffers, forked from and joined to the context's stream), so one
     // candidate's launches fill the chip while the other's drain.
@@ -1684,6 +1704,30 @@ struct kfac_pinn_batch {
   EigGroups eg;             // one group: the inversion's launches already span every instance
   int* eig_ids = nullptr;
   int* eig_ctl = nullptr;   // [0..1] call counter and warm-start flag, [2..] 2 per problem
+  // Grouped line search: each kernel of a candidate runs once over every instance
+  // (job tables in device memory, sized at creation for the largest point counts
+  // and rewritten when the step's buffers or point counts change).
+  struct GTab {
+    size_t jobs = 0, blk = 0;   // byte offsets in dev
+    int njobs = 0, nblk = 0;
+  };
+  struct Group {
+    GTab axpy, prep, slab, inq, inrows, loss;
+    std::vector<GTab> fwd, fin;   // per hidden layer (fin[0] unused: the input layer's rows)
+    char* dev = nullptr;
+    size_t cap = 0;
+    std::vector<uintptr_t> key;   // the step arguments the tables were built for
+  } grp;
+  // Chunk counts of the grouped layer products chosen by kfac_pinn_batch_tune, per
+  // class (K, h_out, S) of a hidden layer past the input layer; other classes take
+  // the single-instance choice (and then the same results as kfac_pinn_step).
+  std::map<std::array<int, 3>, int> nch_tuned;
+  int grouped = 1;          // use the grouped line search when every instance qualifies
+  bool grp_active = false;  // this step's choice
+  std::vector<hipEvent_t> ev_pre;   // per lane: directions and momenta done
+  hipEvent_t ev_ls = nullptr;       // grouped line search done (lane 0)
+  std::vector<hipGraphExec_t> exec_fin;
+  hipGraphExec_t exec_ls = nullptr;
 };
 
 namespace {
@@ -1695,12 +1739,17 @@ void batch_drop_graph(kfac_pinn_batch* b) {
     if (e) (void)hipGraphExecDestroy(e);
   for (hipGraphExec_t e : b->exec_tail)
     if (e) (void)hipGraphExecDestroy(e);
+  for (hipGraphExec_t e : b->exec_fin)
+    if (e) (void)hipGraphExecDestroy(e);
   if (b->exec_eig) (void)hipGraphExecDestroy(b->exec_eig);
+  if (b->exec_ls) (void)hipGraphExecDestroy(b->exec_ls);
   for (hipGraph_t g : b->graph)
     if (g) (void)hipGraphDestroy(g);
   b->exec_head.clear();
   b->exec_tail.clear();
+  b->exec_fin.clear();
   b->exec_eig = nullptr;
+  b->exec_ls = nullptr;
   b->graph.clear();
   b->key.clear();
 }
@@ -1717,8 +1766,354 @@ struct BatchArgs {
   kp_step_info* infos;
 };
 
+// Builds the grouped line search's job tables of every instance into `blob`
+// (offsets into it in g).  bound: sizes only, for the largest point counts (the
+// step's data pointers are not read).  False when an instance does not take the
+// paired BF16 line search these kernels cover.
+std::array<int, 3> nch_class(const FwdLayerArgs& a) { return {a.K, a.h_out, a.S}; }
+
+bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector<char>& blob,
+                 kfac_pinn_batch::Group& g,
+                 const std::map<std::array<int, 3>, int>* nch_over = nullptr) {
+  if (!nch_over) nch_over = &b->nch_tuned;
+  const int n = (int)b->ctx.size();
+  const int L = b->ctx[0]->L;
+  if (L < 2) return false;
+  std::vector<AxpyJob> ax(n);
+  std::vector<PrepJob> pw(n);
+  std::vector<SlabJob> sl(2 * n);
+  std::vector<std::vector<FwdJob>> fw(L - 1, std::vector<FwdJob>(n));
+  std::vector<std::vector<FinJob>> fi(L - 1, std::vector<FinJob>(n));
+  std::vector<InQJob> iq(n);
+  std::vector<InRowsJob> ir(n);
+  std::vector<LossJob> lo(n);
+  std::vector<int> nax(n), npw(n), nsl(2 * n), niq(n), nir(n), nlo(n);
+  std::vector<std::vector<int>> nfw(L - 1, std::vector<int>(n)), nfi(L - 1, std::vector<int>(n));
+  auto blocks = [](long work, int cap) { return (int)std::max(1L, std::min<long>(cap, (work + 255) / 256)); };
+  for (int k = 0; k < n; k++) {
+    kfac_pinn_ctx* c = b->ctx[k];
+    if (c->L != L || c->lp != P_BF16 || c->pp != P_F32 || c->nonlinear || c->dirs ||
+        c->ls_lanes != 1 || !c->si.has_lap || c->sb.has_lap)
+      return false;
+    const int ni = bound ? c->max_i : a->ni[k], nb = bound ? c->max_b : a->nb[k];
+    if (!ls_paired(c, ni, nb)) return false;
+    FwdTarget Ti, Tb;
+    ls_targets(c, Ti, Tb);
+    ax[k] = AxpyJob{bound ? nullptr : (const float*)a->thetas[k], (const float*)c->dhat,
+                    (float*)c->theta_trial, c->D, blocks(c->D, 128)};
+    nax[k] = ax[k].nblk;
+    long mx = 1;
+    for (int l = 0; l < c->nd.L; l++)
+      mx = std::max(mx, (long)c->nd.l[l].h_out * c->nd.l[l].ldk_in + c->nd.l[l].h_out);
+    pw[k] = PrepJob{(const float*)c->theta_trial, c->w_hi, c->nd, blocks(mx, 64)};
+    npw[k] = pw[k].nblk * c->nd.L;
+    const int Si = input_rows_of(c, c->si, Ti), Sb = input_rows_of(c, c->sb, Tb);
+    sl[2 * k] = SlabJob{bound ? nullptr : (const float*)a->xi[k], Ti.z(0), c->ldz[0], ni, c->d, Si,
+                        blocks((long)ni * Si * c->ldz[0], 256)};
+    sl[2 * k + 1] = SlabJob{bound ? nullptr : (const float*)a->xb[k], Tb.z(0), c->ldz[0], nb, c->d,
+                            Sb, blocks((long)nb * Sb * c->ldz[0], 256)};
+    nsl[2 * k] = sl[2 * k].nblk;
+    nsl[2 * k + 1] = sl[2 * k + 1].nblk;
+    for (int l = 0; l < L - 1; l++) {
+      const LayerLaunch Li = layer_launch(c, c->si, ni, l, L, Ti);
+      const LayerLaunch Lb = layer_launch(c, c->sb, nb, l, L, Tb);
+      int nch = Li.nch;
+      if (l > 0) {
+        auto it = nch_over->find(nch_class(Li.a));
+        if (it != nch_over->end()) nch = it->second;
+      }
+      if (!make_fwd_job(Li.a, nch, Lb.a, &fw[l][k])) return false;
+      // sizes at creation: the chunk count of a smaller step may be larger
+      nfw[l][k] = bound ? fw[l][k].t0 * kMaxChunks + fw[l][k].t1 : fwd_job_blocks(fw[l][k]);
+      if (l == 0) {
+        if (!Li.input_rows || !make_input_jobs(Li.a, c->qbuf, 512, &iq[k], &ir[k])) return false;
+        niq[k] = inq_job_blocks(iq[k]);
+        nir[k] = ir[k].nblk;
+      } else {
+        if (Li.input_rows || !make_fin_job(Li.a, nch, &fi[l][k])) return false;
+        nfi[l][k] = fin_job_blocks(fi[l][k]);
+      }
+    }
+    const LayerDesc& ld = c->nd.l[L - 1];
+    lo[k] = LossJob{Ti.z(L - 1), c->ldz[L - 1], ni, time_row_of(c, c->si), lap_row_of(c->si),
+                    c->c_t, c->c_lap, bound ? nullptr : (const float*)a->yi[k], Tb.z(L - 1),
+                    c->ldz[L - 1], nb, bound ? nullptr : (const float*)a->yb[k],
+                    (const float*)wptr(c->theta_trial, ld.off, c->esz_p), ld.h_in + 1,
+                    (ni + 3) / 4, ls_loss_blocks(ni, nb), c->partial, c->loss + 2};
+    if (lo[k].nbt > c->partial_n) return false;
+    nlo[k] = lo[k].nbt;
+  }
+  blob.clear();
+  auto align = [&]() { blob.resize((blob.size() + 255) & ~(size_t)255); };
+  // jobs, then the workgroup list with the largest jobs first (their tiles start
+  // in the first rounds, the small ones fill the tail)
+  auto add = [&](kfac_pinn_batch::GTab& t, const void* jobs, size_t bytes,
+                 const std::vector<int>& nblk) {
+    align();
+    t.jobs = blob.size();
+    t.njobs = (int)nblk.size();
+    blob.insert(blob.end(), (const char*)jobs, (const char*)jobs + bytes);
+    std::vector<int> order(nblk.size());
+    for (size_t j = 0; j < order.size(); j++) order[j] = (int)j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nblk[x] > nblk[y]; });
+    std::vector<GroupBlk> bl;
+    for (int j : order)
+      for (int i = 0; i < nblk[j]; i++) bl.push_back(GroupBlk{j, i});
+    align();
+    t.blk = blob.size();
+    t.nblk = (int)bl.size();
+    blob.insert(blob.end(), (const char*)bl.data(), (const char*)(bl.data() + bl.size()));
+  };
+  add(g.axpy, ax.data(), sizeof(AxpyJob) * n, nax);
+  add(g.prep, pw.data(), sizeof(PrepJob) * n, npw);
+  add(g.slab, sl.data(), sizeof(SlabJob) * 2 * n, nsl);
+  g.fwd.assign(L - 1, kfac_pinn_batch::GTab{});
+  g.fin.assign(L - 1, kfac_pinn_batch::GTab{});
+  for (int l = 0; l < L - 1; l++) {
+    add(g.fwd[l], fw[l].data(), sizeof(FwdJob) * n, nfw[l]);
+    if (l > 0) add(g.fin[l], fi[l].data(), sizeof(FinJob) * n, nfi[l]);
+  }
+  add(g.inq, iq.data(), sizeof(InQJob) * n, niq);
+  add(g.inrows, ir.data(), sizeof(InRowsJob) * n, nir);
+  add(g.loss, lo.data(), sizeof(LossJob) * n, nlo);
+  align();
+  return true;
+}
+
+// The grid line search of every instance, each kernel of a candidate one launch
+// over all instances (the instances' own buffers, as their single-instance
+// launches use them; the same kernels' bodies, so the losses are the same).
+kp_status group_ls(kfac_pinn_batch* b, const kp_hparams* hp, hipStream_t st) {
+  const kfac_pinn_batch::Group& g = b->grp;
+  char* d = g.dev;
+  auto blk = [&](const kfac_pinn_batch::GTab& t) { return (const GroupBlk*)(d + t.blk); };
+  const int ncand = hp->grid_max_exp - hp->grid_min_exp + 1;
+  const int L = (int)g.fwd.size() + 1;
+  for (int k = 0; k < ncand; k++) {
+    const double alpha = ldexp(1.0, hp->grid_max_exp - k);
+    KP_TRY(axpy_group((const AxpyJob*)(d + g.axpy.jobs), blk(g.axpy), g.axpy.nblk, alpha, st));
+    KP_TRY(prep_group((const PrepJob*)(d + g.prep.jobs), blk(g.prep), g.prep.nblk, st));
+    KP_TRY(slab_group((const SlabJob*)(d + g.slab.jobs), blk(g.slab), g.slab.nblk, st));
+    for (int l = 0; l < L - 1; l++) {
+      KP_TRY(fwd_group((const FwdJob*)(d + g.fwd[l].jobs), blk(g.fwd[l]), g.fwd[l].nblk, st));
+      if (l == 0) {
+        KP_TRY(inq_group((const InQJob*)(d + g.inq.jobs), blk(g.inq), g.inq.nblk, st));
+        KP_TRY(inrows_group((const InRowsJob*)(d + g.inrows.jobs), blk(g.inrows), g.inrows.nblk,
+                            st));
+      } else {
+        KP_TRY(fin_group((const FinJob*)(d + g.fin[l].jobs), blk(g.fin[l]), g.fin[l].nblk, st));
+      }
+    }
+    KP_TRY(loss_group((const LossJob*)(d + g.loss.jobs), blk(g.loss), g.loss.nblk, st));
+    KP_TRY(final_group((const LossJob*)(d + g.loss.jobs), g.loss.njobs, k, st));
+  }
+  return KP_OK;
+}
+
+// ---- autotuning of the grouped line search's chunk counts --------------------
+// A cache entry: device, class (K, h_out, S) and the chosen chunk count (0: the
+// single-instance choice).  The cache is a JSON file of these entries.
+struct TuneEntry {
+  std::string device;
+  int K = 0, h_out = 0, S = 0, nch = 0;
+};
+
+std::string device_tag() {
+  int dev = 0;
+  hipDeviceProp_t pr{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess)
+    return "unknown";
+  std::string t = std::string(pr.gcnArchName) + " " + pr.name + " cu" +
+                  std::to_string(pr.multiProcessorCount);
+  for (char& ch : t)
+    if (ch == '"' || ch == '\\' || (unsigned char)ch < 32) ch = ' ';
+  return t;
+}
+
+// Reads the flat objects of the cache's "entries" array (unknown keys skipped; a
+// missing or malformed file reads as empty).
+std::vector<TuneEntry> tune_cache_read(const char* path) {
+  std::vector<TuneEntry> out;
+  if (!path) return out;
+  FILE* f = fopen(path, "rb");
+  if (!f) return out;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  fclose(f);
+  size_t pos = txt.find("\"entries\"");
+  while (pos != std::string::npos) {
+    const size_t o = txt.find('{', pos), e = o == std::string::npos ? o : txt.find('}', o);
+    if (o == std::string::npos || e == std::string::npos) break;
+    const std::string obj = txt.substr(o + 1, e - o - 1);
+    TuneEntry t;
+    bool ok = true;
+    auto num = [&](const char* key, int& v) {
+      const size_t k = obj.find(std::string("\"") + key + "\"");
+      if (k == std::string::npos) { ok = false; return; }
+      const size_t c = obj.find(':', k);
+      if (c == std::string::npos) { ok = false; return; }
+      v = atoi(obj.c_str() + c + 1);
+    };
+    num("K", t.K);
+    num("h_out", t.h_out);
+    num("S", t.S);
+    num("nch", t.nch);
+    const size_t k = obj.find("\"device\"");
+    const size_t q0 = k == std::string::npos ? k : obj.find('"', obj.find(':', k));
+    const size_t q1 = q0 == std::string::npos ? q0 : obj.find('"', q0 + 1);
+    if (q1 == std::string::npos) ok = false;
+    else t.device = obj.substr(q0 + 1, q1 - q0 - 1);
+    if (ok && t.nch >= 0 && t.nch <= kMaxChunks) out.push_back(t);
+    pos = e + 1;
+  }
+  return out;
+}
+
+bool tune_cache_write(const char* path, const std::vector<TuneEntry>& es) {
+  if (!path) return true;
+  FILE* f = fopen(path, "wb");
+  if (!f) return false;
+  fprintf(f, "{\n  \"kfac_pinn_tune\": 1,\n  \"entries\": [\n");
+  for (size_t i = 0; i < es.size(); i++)
+    fprintf(f, "    {\"device\": \"%s\", \"K\": %d, \"h_out\": %d, \"S\": %d, \"nch\": %d}%s\n",
+            es[i].device.c_str(), es[i].K, es[i].h_out, es[i].S, es[i].nch,
+            i + 1 < es.size() ? "," : "");
+  fprintf(f, "  ]\n}\n");
+  return fclose(f) == 0;
+}
+
+// Chooses the chunk count of each class of grouped layer products (hidden layers
+// past the input layer) by timing: class by class, within the full grouped
+// launch of its layer (layer product and finishing pass over every instance), the
+// single-instance choice and 1, 2, 4, 8 chunks (at most one per derivative row);
+// another count replaces the single-instance choice only when at least 3 % faster
+// (minimum of 3 timed launches after one untimed).  Classes in the cache for this
+// device are taken from it.
+kp_status batch_tune(kfac_pinn_batch* b, const BatchArgs& a, const char* cache_path,
+                     int* timed_out) {
+  hipStream_t st = b->lanes[0];
+  std::map<std::array<int, 3>, int> cur = b->nch_tuned;
+  std::vector<char> blob;
+  kfac_pinn_batch::Group g = b->grp;
+  if (!b->grp.dev || !group_build(b, &a, false, blob, g, &cur) || blob.size() > b->grp.cap)
+    return KP_ERR_STATE;
+  const int L = (int)g.fwd.size() + 1;
+  // classes per layer, with their largest derivative-row count
+  std::vector<std::map<std::array<int, 3>, int>> cls(L - 1);
+  for (size_t k = 0; k < b->ctx.size(); k++) {
+    kfac_pinn_ctx* c = b->ctx[k];
+    FwdTarget Ti, Tb;
+    ls_targets(c, Ti, Tb);
+    for (int l = 1; l < L - 1; l++) {
+      const LayerLaunch Li = layer_launch(c, c->si, a.ni[k], l, L, Ti);
+      int& nd = cls[l][nch_class(Li.a)];
+      nd = std::max(nd, Li.a.nd);
+    }
+  }
+  const std::string dev = device_tag();
+  std::vector<TuneEntry> cache = tune_cache_read(cache_path);
+  auto cached = [&](const std::array<int, 3>& k) -> const TuneEntry* {
+    for (const TuneEntry& t : cache)
+      if (t.device == dev && t.K == k[0] && t.h_out == k[1] && t.S == k[2]) return &t;
+    return nullptr;
+  };
+  auto set = [&](const std::array<int, 3>& k, int n) {
+    if (n == 0) cur.erase(k);
+    else cur[k] = n;
+  };
+  // real slab contents for the timed launches: one line-search candidate (alpha = 1)
+  KP_TRY(hipStreamSynchronize(st));
+  KP_TRY(hipMemcpy(b->grp.dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  b->grp.key.clear();
+  {
+    kfac_pinn_batch::Group keep = b->grp;
+    b->grp = g;
+    b->grp.dev = keep.dev;
+    b->grp.cap = keep.cap;
+    kp_hparams one{};
+    one.lr_mode = 1;
+    one.grid_min_exp = 0;
+    one.grid_max_exp = 0;
+    kp_status s = group_ls(b, &one, st);
+    b->grp = keep;
+    if (s != KP_OK) return s;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  KP_TRY(hipEventCreate(&e0));
+  KP_TRY(hipEventCreate(&e1));
+  auto timed = [&](int l, float* ms) -> kp_status {
+    kfac_pinn_batch::Group t = b->grp;
+    if (!group_build(b, &a, false, blob, t, &cur) || blob.size() > b->grp.cap) return KP_ERR_STATE;
+    KP_TRY(hipStreamSynchronize(st));
+    KP_TRY(hipMemcpy(b->grp.dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    char* d = b->grp.dev;
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; rep++) {
+      KP_TRY(hipEventRecord(e0, st));
+      KP_TRY(fwd_group((const FwdJob*)(d + t.fwd[l].jobs), (const GroupBlk*)(d + t.fwd[l].blk),
+                       t.fwd[l].nblk, st));
+      KP_TRY(fin_group((const FinJob*)(d + t.fin[l].jobs), (const GroupBlk*)(d + t.fin[l].blk),
+                       t.fin[l].nblk, st));
+      KP_TRY(hipEventRecord(e1, st));
+      KP_TRY(hipEventSynchronize(e1));
+      float v = 0.0f;
+      KP_TRY(hipEventElapsedTime(&v, e0, e1));
+      if (rep > 0) best = std::min(best, v);
+    }
+    *ms = best;
+    return KP_OK;
+  };
+  int ntimed = 0;
+  kp_status s = KP_OK;
+  for (int l = 1; l < L - 1 && s == KP_OK; l++) {
+    for (const auto& kv : cls[l]) {
+      const std::array<int, 3>& key = kv.first;
+      if (const TuneEntry* t = cached(key)) {
+        set(key, t->nch);
+        continue;
+      }
+      set(key, 0);
+      float base = 0.0f;
+      if ((s = timed(l, &base)) != KP_OK) break;
+      int best_n = 0;
+      float best_ms = base;
+      for (int n : {1, 2, 4, 8}) {
+        if (n > std::max(1, kv.second)) continue;
+        set(key, n);
+        float v = 0.0f;
+        if ((s = timed(l, &v)) != KP_OK) break;
+        if (v < best_ms && v < 0.97f * base) {
+          best_ms = v;
+          best_n = n;
+        }
+      }
+      if (s != KP_OK) break;
+      set(key, best_n);
+      cache.push_back(TuneEntry{dev, key[0], key[1], key[2], best_n});
+      ntimed++;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // the step's tables are rebuilt (and its graphs recaptured) on the next call
+  b->grp.key.clear();
+  batch_drop_graph(b);
+  if (s != KP_OK) return s;
+  b->nch_tuned = cur;
+  if (timed_out) *timed_out = ntimed;
+  if (!tune_cache_write(cache_path, cache)) {
+    kp_set_last_error("cannot write the tuning cache", __FILE__, __LINE__);
+    return KP_ERR_ARG;
+  }
+  return KP_OK;
+}
+
 // phase 0: the heads of the instances on lane l; 1: one inversion over every
-// instance's problems on lane 0; 2: the tails of the instances on lane l
+// instance's problems on lane 0; 2: the tails of the instances on lane l (with the
+// grouped line search: their directions and momenta); 3: the grouped line search
+// of every instance on lane 0; 4: the step sizes and updates on lane l
 kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a) {
   const int nl = (int)b->lanes.size();
   if (phase == 1) {
@@ -1729,13 +2124,15 @@ kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
                             b->lanes[0]));
     return KP_OK;
   }
+  if (phase == 3) return group_ls(b, a.hp, b->lanes[0]);
+  const int part = phase == 2 ? (b->grp_active ? 0 : -1) : 2;
   for (size_t k = l; k < b->ctx.size(); k += nl) {
     kp_status s =
         phase == 0
             ? step_head(b->ctx[k], a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k],
                         a.nb[k], a.hp)
             : step_tail(b->ctx[k], a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k],
-                        a.nb[k], a.hp, a.infos ? a.infos + k : nullptr);
+                        a.nb[k], a.hp, a.infos ? a.infos + k : nullptr, part);
     if (s != KP_OK) return s;
   }
   return KP_OK;
@@ -1743,7 +2140,7 @@ kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
 
 kp_status batch_capture(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a,
                         hipGraphExec_t* out) {
-  hipStream_t s = b->lanes[phase == 1 ? 0 : l];
+  hipStream_t s = b->lanes[phase == 1 || phase == 3 ? 0 : l];
   KP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   kp_status st = batch_enqueue(b, phase, l, a);
   hipGraph_t g = nullptr;
@@ -1765,8 +2162,12 @@ kp_status batch_capture(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
 
 kp_status batch_launch(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a) {
   if (!b->use_graph) return batch_enqueue(b, phase, l, a);
-  hipGraphExec_t x = phase == 0 ? b->exec_head[l] : phase == 1 ? b->exec_eig : b->exec_tail[l];
-  KP_TRY(hipGraphLaunch(x, b->lanes[phase == 1 ? 0 : l]));
+  hipGraphExec_t x = phase == 0   ? b->exec_head[l]
+                     : phase == 1 ? b->exec_eig
+                     : phase == 2 ? b->exec_tail[l]
+                     : phase == 3 ? b->exec_ls
+                                  : b->exec_fin[l];
+  KP_TRY(hipGraphLaunch(x, b->lanes[phase == 1 || phase == 3 ? 0 : l]));
   return KP_OK;
 }
 }  // namespace
@@ -1792,9 +2193,12 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
     b->ev.push_back(e);
     if (hipEventCreateWithFlags(&eh, hipEventDisableTiming) != hipSuccess) return fail(KP_ERR_HIP);
     b->ev_head.push_back(eh);
+    if (hipEventCreateWithFlags(&eh, hipEventDisableTiming) != hipSuccess) return fail(KP_ERR_HIP);
+    b->ev_pre.push_back(eh);
   }
   if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_eig, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&b->ev_eig, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_ls, hipEventDisableTiming) != hipSuccess)
     return fail(KP_ERR_HIP);
   for (int k = 0; k < count; k++) {
     kfac_pinn_ctx* c = nullptr;
@@ -1823,6 +2227,14 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
       hipMemset(b->eig_ctl, 0, sizeof(int) * (2 + 2 * np)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
     return fail(KP_ERR_HIP);
+  {
+    // the grouped line search's tables, sized for the largest point counts
+    std::vector<char> blob;
+    if (group_build(b, nullptr, true, blob, b->grp)) {
+      if (hipMalloc((void**)&b->grp.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
+      b->grp.cap = blob.size();
+    }
+  }
   *out = b;
   return KP_OK;
 }
@@ -1836,10 +2248,13 @@ kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   if (b->probs_dev) (void)hipFree(b->probs_dev);
   if (b->eig_ids) (void)hipFree(b->eig_ids);
   if (b->eig_ctl) (void)hipFree(b->eig_ctl);
+  if (b->grp.dev) (void)hipFree(b->grp.dev);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->ev_head) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->ev_pre) (void)hipEventDestroy(e);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_eig) (void)hipEventDestroy(b->ev_eig);
+  if (b->ev_ls) (void)hipEventDestroy(b->ev_ls);
   for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
   delete b;
   return KP_OK;
@@ -1856,6 +2271,50 @@ kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* b, int32_t enabled) {
   KP_ARG(b, "null batch");
   b->use_graph = enabled ? 1 : 0;
   if (!enabled) batch_drop_graph(b);
+  return KP_OK;
+}
+
+kp_status kfac_pinn_batch_set_grouped(kfac_pinn_batch* b, int32_t enabled) {
+  KP_ARG(b, "null batch");
+  KP_ARG(enabled == 0 || enabled == 1, "enabled must be 0 or 1");
+  b->grouped = enabled;
+  return KP_OK;
+}
+
+kp_status kfac_pinn_batch_tune(kfac_pinn_batch* b, void* const* thetas, const void* const* x_int,
+                               const void* const* y_int, const int32_t* n_int,
+                               const void* const* x_bnd, const void* const* y_bnd,
+                               const int32_t* n_bnd, const char* cache_path, int32_t* timed) {
+  KP_ARG(b && thetas && x_int && y_int && n_int && x_bnd && y_bnd && n_bnd, "null argument");
+  const int n = (int)b->ctx.size();
+  for (int k = 0; k < n; k++) {
+    KP_ARG(n_int[k] > 0 && n_int[k] <= b->ctx[k]->max_i && n_bnd[k] > 0 &&
+               n_bnd[k] <= b->ctx[k]->max_b,
+           "point counts out of range (the grouped line search needs both point sets)");
+    KP_ARG(thetas[k] && x_int[k] && y_int[k] && x_bnd[k] && y_bnd[k], "null buffer");
+  }
+  if (!b->grp.dev) {
+    kp_set_last_error("the batch's instances do not take the grouped line search", __FILE__,
+                      __LINE__);
+    return KP_ERR_STATE;
+  }
+  // after the work already on the caller's stream
+  KP_TRY(hipEventRecord(b->ev_in, b->st));
+  KP_TRY(hipStreamWaitEvent(b->lanes[0], b->ev_in, 0));
+  for (int l = 1; l < (int)b->lanes.size(); l++) KP_TRY(hipStreamSynchronize(b->lanes[l]));
+  kp_hparams hp{};
+  hp.lr_mode = 1;
+  const BatchArgs a{thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, &hp, nullptr};
+  int t = 0;
+  kp_status s = batch_tune(b, a, cache_path, &t);
+  if (timed) *timed = t;
+  KP_TRY(hipStreamSynchronize(b->lanes[0]));
+  return s;
+}
+
+kp_status kfac_pinn_batch_is_grouped(kfac_pinn_batch* b, int32_t* out) {
+  KP_ARG(b && out, "null argument");
+  *out = b->grp_active ? 1 : 0;
   return KP_OK;
 }
 
@@ -1882,31 +2341,63 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
   const int n = (int)b->ctx.size();
   const int nl = (int)b->lanes.size();
   const BatchArgs a{thetas, x_int, y_int, n_int, x_bnd, y_bnd, n_bnd, hp, infos};
+  std::vector<uintptr_t> key;
+  key.reserve(7 * n + 16);
+  for (int k = 0; k < n; k++) {
+    key.push_back((uintptr_t)thetas[k]);
+    key.push_back((uintptr_t)x_int[k]);
+    key.push_back((uintptr_t)y_int[k]);
+    key.push_back((uintptr_t)x_bnd[k]);
+    key.push_back((uintptr_t)y_bnd[k]);
+    key.push_back((uintptr_t)n_int[k]);
+    key.push_back((uintptr_t)n_bnd[k]);
+  }
+  // The grouped line search needs the grid search, tables for these arguments and
+  // arguments every instance accepts (a failing instance reports from its head).
+  b->grp_active = false;
+  if (b->grouped && hp->lr_mode == 1 && b->grp.dev) {
+    bool valid = true;
+    for (int k = 0; k < n && valid; k++)
+      valid = n_int[k] > 0 && n_int[k] <= b->ctx[k]->max_i && n_bnd[k] > 0 &&
+              n_bnd[k] <= b->ctx[k]->max_b && x_int[k] && y_int[k] && x_bnd[k] && y_bnd[k] &&
+              thetas[k];
+    if (valid && key == b->grp.key) {
+      b->grp_active = true;
+    } else if (valid) {
+      std::vector<char> blob;
+      kfac_pinn_batch::Group g = b->grp;
+      if (group_build(b, &a, false, blob, g) && blob.size() <= b->grp.cap) {
+        // nothing in flight may read the old tables (the grouped launches run on lane 0)
+        KP_TRY(hipStreamSynchronize(b->lanes[0]));
+        KP_TRY(hipMemcpy(b->grp.dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        g.dev = b->grp.dev;
+        g.cap = b->grp.cap;
+        g.key = key;
+        b->grp = g;
+        b->grp_active = true;
+      }
+    }
+  }
+  key.push_back((uintptr_t)infos);
+  key.push_back((uintptr_t)b->grp_active);
+  {
+    const unsigned char* hb = (const unsigned char*)hp;
+    for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);
+  }
   if (b->use_graph) {
-    std::vector<uintptr_t> key;
-    key.reserve(7 * n + 16);
-    for (int k = 0; k < n; k++) {
-      key.push_back((uintptr_t)thetas[k]);
-      key.push_back((uintptr_t)x_int[k]);
-      key.push_back((uintptr_t)y_int[k]);
-      key.push_back((uintptr_t)x_bnd[k]);
-      key.push_back((uintptr_t)y_bnd[k]);
-      key.push_back((uintptr_t)n_int[k]);
-      key.push_back((uintptr_t)n_bnd[k]);
-    }
-    key.push_back((uintptr_t)infos);
-    {
-      const unsigned char* hb = (const unsigned char*)hp;
-      for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);
-    }
     if (b->exec_eig == nullptr || key != b->key) {
       batch_drop_graph(b);
       b->exec_head.assign(nl, nullptr);
       b->exec_tail.assign(nl, nullptr);
+      b->exec_fin.assign(nl, nullptr);
       kp_status s = KP_OK;
       for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 0, l, a, &b->exec_head[l]);
       if (s == KP_OK) s = batch_capture(b, 1, 0, a, &b->exec_eig);
       for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 2, l, a, &b->exec_tail[l]);
+      if (b->grp_active) {
+        if (s == KP_OK) s = batch_capture(b, 3, 0, a, &b->exec_ls);
+        for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 4, l, a, &b->exec_fin[l]);
+      }
       if (s != KP_OK) {
         batch_drop_graph(b);
         return s;
@@ -1932,6 +2423,26 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
   for (int l = 0; l < nl; l++) {
     if (l > 0) KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev_eig, 0));
     kp_status s = batch_launch(b, 2, l, a);
+    if (s != KP_OK) return s;
+    if (b->grp_active) {
+      KP_TRY(hipEventRecord(b->ev_pre[l], b->lanes[l]));
+      continue;
+    }
+    KP_TRY(hipEventRecord(b->ev[l], b->lanes[l]));
+    KP_TRY(hipStreamWaitEvent(b->st, b->ev[l], 0));
+  }
+  if (!b->grp_active) return KP_OK;
+  // the grouped line search on lane 0 after every lane's directions, then the
+  // step sizes and updates back on the lanes
+  for (int l = 1; l < nl; l++) KP_TRY(hipStreamWaitEvent(b->lanes[0], b->ev_pre[l], 0));
+  {
+    kp_status s = batch_launch(b, 3, 0, a);
+    if (s != KP_OK) return s;
+  }
+  KP_TRY(hipEventRecord(b->ev_ls, b->lanes[0]));
+  for (int l = 0; l < nl; l++) {
+    if (l > 0) KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev_ls, 0));
+    kp_status s = batch_launch(b, 4, l, a);
     if (s != KP_OK) return s;
     KP_TRY(hipEventRecord(b->ev[l], b->lanes[l]));
     KP_TRY(hipStreamWaitEvent(b->st, b->ev[l], 0));

@@ -15,18 +15,16 @@ namespace kp {
 // Product-layout copies of the augmented weights W~ = [W | b]
 // ---------------------------------------------------------------------------
 template <typename TP, typename TS>
-__global__ void k_prep_weights(const TP* __restrict__ theta, const TP* __restrict__ dir,
-                               double alpha, NetDesc nd, TS* __restrict__ whi,
-                               TS* __restrict__ wlo, typename Acc<TS>::type* __restrict__ bias,
-                               long bias_stride, int fwd_only) {
+__device__ __forceinline__ void prep_weights_at(const TP* __restrict__ theta,
+                                                const TP* __restrict__ dir, double alpha,
+                                                const LayerDesc& ld, int l, TS* __restrict__ whi,
+                                                TS* __restrict__ wlo,
+                                                typename Acc<TS>::type* __restrict__ bias,
+                                                long bias_stride, int fwd_only, long bx, long gx) {
   typedef typename Acc<TS>::type TC;
-  const int l = blockIdx.y;
-  if (l >= nd.L) return;
-  const LayerDesc ld = nd.l[l];
   const long nf = (long)ld.h_out * ld.ldk_in;    // forward copy elements
   const long nb = fwd_only ? 0 : (long)ld.h_in * ld.ldk_out;   // backward copy elements
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nf + nb + ld.h_out;
-       e += (long)gridDim.x * blockDim.x) {
+  for (long e = bx * blockDim.x + threadIdx.x; e < nf + nb + ld.h_out; e += gx * blockDim.x) {
     long src = -1, dst;
     if (e < nf) {                         // forward: row i (output), column j (input, bias at h_in)
       int i = (int)(e / ld.ldk_in), j = (int)(e % ld.ldk_in);
@@ -54,6 +52,16 @@ __global__ void k_prep_weights(const TP* __restrict__ theta, const TP* __restric
     whi[dst] = hi;
     if (wlo) wlo[dst] = cvt<TS>(w - to_d(hi));
   }
+}
+template <typename TP, typename TS>
+__global__ void k_prep_weights(const TP* __restrict__ theta, const TP* __restrict__ dir,
+                               double alpha, NetDesc nd, TS* __restrict__ whi,
+                               TS* __restrict__ wlo, typename Acc<TS>::type* __restrict__ bias,
+                               long bias_stride, int fwd_only) {
+  const int l = blockIdx.y;
+  if (l >= nd.L) return;
+  prep_weights_at<TP, TS>(theta, dir, alpha, nd.l[l], l, whi, wlo, bias, bias_stride, fwd_only,
+                          blockIdx.x, gridDim.x);
 }
 
 hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha, NetDesc nd,
@@ -90,11 +98,11 @@ hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha
 // directions v_k the derivative rows are v_k instead of the unit vectors)
 // ---------------------------------------------------------------------------
 template <typename TP, typename TS>
-__global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S,
-                             const double* __restrict__ dirs, TS* __restrict__ z, long ldz) {
+__device__ __forceinline__ void input_slab_at(const TP* __restrict__ x, int n, int d, int S,
+                                              const double* __restrict__ dirs, TS* __restrict__ z,
+                                              long ldz, long bx, long gx) {
   const long R = (long)n * S;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < R * ldz;
-       e += (long)gridDim.x * blockDim.x) {
+  for (long e = bx * blockDim.x + threadIdx.x; e < R * ldz; e += gx * blockDim.x) {
     long r = e / ldz;
     int j = (int)(e % ldz);
     int s = (int)(r / n), pt = (int)(r % n);
@@ -104,6 +112,11 @@ __global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S,
       v = dirs ? (j < d ? dirs[(long)(s - 1) * d + j] : 0.0) : ((j == s - 1) ? 1.0 : 0.0);
     z[e] = cvt<TS>(v);
   }
+}
+template <typename TP, typename TS>
+__global__ void k_input_slab(const TP* __restrict__ x, int n, int d, int S,
+                             const double* __restrict__ dirs, TS* __restrict__ z, long ldz) {
+  input_slab_at<TP, TS>(x, n, d, S, dirs, z, ldz, blockIdx.x, gridDim.x);
 }
 
 hipError_t input_slab(Prec p, const void* x, int n, int d, int S, const double* dirs, void* z,
@@ -428,6 +441,65 @@ hipError_t axpy_theta(Prec p, const void* theta, const void* dir, double alpha, 
   else
     k_axpy_theta<float><<<nb, 256, 0, st>>>((const float*)theta, (const float*)dir, alpha,
                                             (float*)out, D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Grouped line-search launches (see GroupBlk): the candidate parameters, their
+// BF16 forward copy and both input slabs of many instances, one launch each.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)p;
+#else
+  return *p;   // the host pass only parses device code
+#endif
+}
+
+__global__ __launch_bounds__(256) void k_axpy_group(const AxpyJob* __restrict__ jobs,
+                                                    const GroupBlk* __restrict__ blk,
+                                                    double alpha) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const AxpyJob j = ld_uniform(jobs + g.job);
+  for (long e = (long)g.local * blockDim.x + threadIdx.x; e < j.D; e += (long)j.nblk * blockDim.x)
+    j.out[e] = j.theta[e] + (float)(alpha * (double)j.dir[e]);
+}
+
+__global__ __launch_bounds__(256) void k_prep_group(const PrepJob* __restrict__ jobs,
+                                                    const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const PrepJob* jp = jobs + g.job;
+  const int nblk = ld_uniform(&jp->nblk);
+  const int l = g.local / nblk;   // nblk workgroups per layer
+  // only this layer's descriptor (a whole NetDesc indexed by l would live in scratch)
+  const LayerDesc ld = ld_uniform(&jp->nd.l[l]);
+  prep_weights_at<float, bf16>(ld_uniform(&jp->theta), nullptr, 0.0, ld, l,
+                               (bf16*)ld_uniform(&jp->w_hi), nullptr, nullptr, 0, 1,
+                               g.local - l * nblk, nblk);
+}
+
+__global__ __launch_bounds__(256) void k_slab_group(const SlabJob* __restrict__ jobs,
+                                                    const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const SlabJob j = ld_uniform(jobs + g.job);
+  input_slab_at<float, bf16>(j.x, j.n, j.d, j.S, nullptr, (bf16*)j.z, j.ldz, g.local, j.nblk);
+}
+
+hipError_t axpy_group(const AxpyJob* jobs, const GroupBlk* blk, int nblk, double alpha,
+                      hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_axpy_group<<<nblk, 256, 0, st>>>(jobs, blk, alpha);
+  return hipGetLastError();
+}
+hipError_t prep_group(const PrepJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_prep_group<<<nblk, 256, 0, st>>>(jobs, blk);
+  return hipGetLastError();
+}
+hipError_t slab_group(const SlabJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_slab_group<<<nblk, 256, 0, st>>>(jobs, blk);
   return hipGetLastError();
 }
 

@@ -59,6 +59,64 @@ struct BwdLayerArgs {
   void* tab_s1;      // nch*N*h: chunk partials of sum_i d_i a zbar_i
 };
 
+// ---- grouped line-search launches ------------------------------------------
+// One launch runs the same line-search kernel for many independent instances
+// (GroupBlk, launch.h).  The jobs take the BF16 line-search path (4-aligned rows,
+// unit input directions).
+struct GroupBlk;
+// a layer product of both point sets (fwdlap_pair): t0 tiles x nch chunks of a0,
+// then t1 tiles of a1
+struct FwdJob {
+  FwdLayerArgs a0, a1;
+  int t0, t1, nch;
+};
+struct FinJob {    // the finishing pass (fwdlap_finish)
+  FwdLayerArgs a;
+  int nch;
+};
+struct InQJob {    // the input layer's tables (input_layer_rows): q, then wt = q + h_out
+  FwdLayerArgs a;
+  float* q;
+};
+struct InRowsJob { // the input layer's rows without products, nblk workgroups
+  FwdLayerArgs a;
+  const float* q;
+  int nblk;
+};
+struct LossJob {   // one candidate's loss (ls_loss); the finalize adds `slot` to loss
+  const void* zi;
+  long ldzi;
+  int ni, time_row, lap_row;
+  double c_t, c_lap;
+  const float* yi;
+  const void* zb;
+  long ldzb;
+  int nb;
+  const float* yb;
+  const float* w;
+  int K, nbi, nbt;
+  double* partial;
+  double* loss;
+};
+// Job makers: false when the arguments do not take the grouped BF16 path (the
+// single-instance launchers' checks, plus 4-aligned rows and unit directions).
+bool make_fwd_job(const FwdLayerArgs& a0, int nch, const FwdLayerArgs& a1, FwdJob* j);
+bool make_fin_job(const FwdLayerArgs& a, int nch, FinJob* j);
+bool make_input_jobs(const FwdLayerArgs& a, void* q, int max_blocks, InQJob* jq, InRowsJob* jr);
+// the number of workgroups of each job
+int fwd_job_blocks(const FwdJob& j);
+int fin_job_blocks(const FinJob& j);
+int inq_job_blocks(const InQJob& j);
+int loss_job_blocks(const LossJob& j);
+// Grouped launches over `nblk` workgroups (blk holds nblk entries).  The
+// finalize runs one workgroup per job and writes loss[slot] of each.
+hipError_t fwd_group(const FwdJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+hipError_t fin_group(const FinJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+hipError_t inq_group(const InQJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+hipError_t inrows_group(const InRowsJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+hipError_t loss_group(const LossJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+hipError_t final_group(const LossJob* jobs, int njobs, int slot, hipStream_t st);
+
 int fwdlap_chunks(int mode, int N, int h_out, int nd, int has_lap);
 hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st);
 // One launch for two point sets of the same layer: a in nch chunks and b (or

@@ -771,7 +771,34 @@ __global__ __launch_bounds__(FwdGeo<MODE>::NT) void k_fwdlap(FwdLayerArgs a0, Fw
                                   smem);
 }
 
-// Laplacian rows  Lz = s1 La + s2 sum_chunks sq, the bias feature and padding.
+// ---------------------------------------------------------------------------
+// Grouped line-search launches: each workgroup reads its (job, local index) and
+// the job's arguments through the scalar cache (uniform per workgroup, read-only
+// during the launch), then runs the same body as the single-instance kernel.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)p;
+#else
+  return *p;   // the host pass only parses device code
+#endif
+}
+
+template <typename TZ, bool A4>
+__global__ __launch_bounds__(DGeo<M_BF16>::NT) void k_fwdlap_group(
+    const FwdJob* __restrict__ jobs, const GroupBlk* __restrict__ blk) {
+  __shared__ __align__(16) char smem[fwd_smem<M_BF16>()];
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const FwdJob j = ld_uniform(jobs + g.job);
+  const int n0 = j.t0 * j.nch;
+  if (g.local < n0)
+    fwd_block<M_BF16, TZ, A4>(j.a0, xcd_tile(g.local % j.t0, j.t0), g.local / j.t0, j.nch, smem);
+  else
+    fwd_block<M_BF16, TZ, A4, true>(j.a1, xcd_tile(g.local - n0, j.t1), 0, 1, smem);
+}
+
+
 template <typename TC, typename TZ>
 __global__ void k_fwdlap_finish(FwdLayerArgs a, int nch) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -798,8 +825,7 @@ __global__ void k_fwdlap_finish(FwdLayerArgs a, int nch) {
 // of 4): threads [0, N h_out / 4) finish column quads of the Laplacian row, the
 // rest write the bias feature and padding, one row (s, p) each.
 template <typename TZ>
-__global__ __launch_bounds__(256) void k_fwdlap_finish4(FwdLayerArgs a, int nch) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void finish4_at(const FwdLayerArgs& a, int nch, long idx) {
   const int hq = a.h_out >> 2;
   const long nmain = a.has_lap ? (long)a.N * hq : 0;
   TZ* z = (TZ*)a.z;
@@ -830,6 +856,10 @@ __global__ __launch_bounds__(256) void k_fwdlap_finish4(FwdLayerArgs a, int nch)
     if (c == a.h_out && row < a.N) v[0] = 1.0f;
     store4(zr + c, v);
   }
+}
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_fwdlap_finish4(FwdLayerArgs a, int nch) {
+  finish4_at<TZ>(a, nch, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1104,13 +1134,12 @@ __global__ __launch_bounds__(256) void k_last_fwd(const TZ* __restrict__ z, long
 // sum of squared residuals; k_ls_finalize adds the block sums of each term with
 // its 1 / (2 count).
 template <typename TZ, typename TW, typename TY>
-__global__ __launch_bounds__(256) void k_ls_loss(const TZ* __restrict__ zi, long ldzi, int ni,
-                                                 int time_row, int lap_row, double c_t,
-                                                 double c_lap, const TY* __restrict__ yi,
-                                                 const TZ* __restrict__ zb, long ldzb, int nb,
-                                                 const TY* __restrict__ yb,
-                                                 const TW* __restrict__ w, int K, int nbi,
-                                                 double* __restrict__ partial) {
+__device__ __forceinline__ void ls_loss_at(const TZ* __restrict__ zi, long ldzi, int ni,
+                                           int time_row, int lap_row, double c_t, double c_lap,
+                                           const TY* __restrict__ yi, const TZ* __restrict__ zb,
+                                           long ldzb, int nb, const TY* __restrict__ yb,
+                                           const TW* __restrict__ w, int K, int nbi,
+                                           double* __restrict__ partial, int bx) {
   __shared__ double red[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   auto dot = [&](const TZ* z) {
@@ -1118,8 +1147,8 @@ __global__ __launch_bounds__(256) void k_ls_loss(const TZ* __restrict__ zi, long
     for (int k = lane; k < K; k += 64) s += (float)to_d(z[k]) * (float)to_d(w[k]);
     return warp_sum(s);
   };
-  const bool bnd = (int)blockIdx.x >= nbi;
-  const int p = ((int)blockIdx.x - (bnd ? nbi : 0)) * 4 + wave;
+  const bool bnd = bx >= nbi;
+  const int p = (bx - (bnd ? nbi : 0)) * 4 + wave;
   double sq = 0.0;
   if (!bnd && p < ni) {
     double v = -(double)yi[p];
@@ -1132,12 +1161,23 @@ __global__ __launch_bounds__(256) void k_ls_loss(const TZ* __restrict__ zi, long
   }
   if (lane == 0) red[wave] = sq;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) partial[bx] = red[0] + red[1] + red[2] + red[3];
+}
+template <typename TZ, typename TW, typename TY>
+__global__ __launch_bounds__(256) void k_ls_loss(const TZ* __restrict__ zi, long ldzi, int ni,
+                                                 int time_row, int lap_row, double c_t,
+                                                 double c_lap, const TY* __restrict__ yi,
+                                                 const TZ* __restrict__ zb, long ldzb, int nb,
+                                                 const TY* __restrict__ yb,
+                                                 const TW* __restrict__ w, int K, int nbi,
+                                                 double* __restrict__ partial) {
+  ls_loss_at<TZ, TW, TY>(zi, ldzi, ni, time_row, lap_row, c_t, c_lap, yi, zb, ldzb, nb, yb, w, K,
+                         nbi, partial, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_ls_finalize(const double* __restrict__ partial, int nbi,
-                                                     int nbt, double si, double sb,
-                                                     double* __restrict__ loss) {
+__device__ __forceinline__ void ls_finalize_at(const double* __restrict__ partial, int nbi,
+                                               int nbt, double si, double sb,
+                                               double* __restrict__ loss) {
   __shared__ double red[2][4];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nbt; i += 256) (i < nbi ? a : b) += partial[i];
@@ -1151,6 +1191,26 @@ __global__ __launch_bounds__(256) void k_ls_finalize(const double* __restrict__ 
   if (threadIdx.x == 0)
     *loss = si * (red[0][0] + red[0][1] + red[0][2] + red[0][3]) +
             sb * (red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+}
+__global__ __launch_bounds__(256) void k_ls_finalize(const double* __restrict__ partial, int nbi,
+                                                     int nbt, double si, double sb,
+                                                     double* __restrict__ loss) {
+  ls_finalize_at(partial, nbi, nbt, si, sb, loss);
+}
+
+__global__ __launch_bounds__(256) void k_ls_loss_group(const LossJob* __restrict__ jobs,
+                                                       const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const LossJob j = ld_uniform(jobs + g.job);
+  ls_loss_at<bf16, float, float>((const bf16*)j.zi, j.ldzi, j.ni, j.time_row, j.lap_row, j.c_t,
+                                 j.c_lap, j.yi, (const bf16*)j.zb, j.ldzb, j.nb, j.yb, j.w, j.K,
+                                 j.nbi, j.partial, g.local);
+}
+
+__global__ __launch_bounds__(256) void k_ls_finalize_group(const LossJob* __restrict__ jobs,
+                                                           int slot) {
+  const LossJob j = ld_uniform(jobs + blockIdx.x);
+  ls_finalize_at(j.partial, j.nbi, j.nbt, 0.5 / j.ni, 0.5 / j.nb, j.loss + slot);
 }
 
 // g of the last hidden layer from the output seeds sigma (zbar_s = sigma_s w):
@@ -1205,12 +1265,12 @@ __global__ void k_bwd_last(BwdLayerArgs a, const TSd* __restrict__ sigma, long l
 // writes (along c) are coalesced; q is summed in four interleaved partial sums
 // (i mod 4) added in a fixed order.
 template <typename TW, typename TC>
-__global__ __launch_bounds__(256) void k_input_q(FwdLayerArgs a, TC* __restrict__ q,
-                                                 TC* __restrict__ wt) {
+__device__ __forceinline__ void input_q_at(const FwdLayerArgs& a, TC* __restrict__ q,
+                                           TC* __restrict__ wt, int bx) {
   __shared__ TC tile[64][65];
   __shared__ TC part[4][64];
   const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
-  const int c0 = blockIdx.x * 64;
+  const int c0 = bx * 64;
   TC sum = 0;
   for (int i0 = 0; i0 < a.nd; i0 += 64) {
 #pragma unroll 4
@@ -1240,6 +1300,11 @@ __global__ __launch_bounds__(256) void k_input_q(FwdLayerArgs a, TC* __restrict_
   __syncthreads();
   if (hi == 0 && c0 + lo < a.h_out)
     q[c0 + lo] = ((part[0][lo] + part[1][lo]) + part[2][lo]) + part[3][lo];
+}
+template <typename TW, typename TC>
+__global__ __launch_bounds__(256) void k_input_q(FwdLayerArgs a, TC* __restrict__ q,
+                                                 TC* __restrict__ wt) {
+  input_q_at<TW, TC>(a, q, wt, blockIdx.x);
 }
 
 // The same tables when the input layer's derivative rows are general directions
@@ -1299,23 +1364,31 @@ __device__ __forceinline__ void load8(const TC* src, TC (&v)[8]) {
   }
 }
 
-// One wave per row (rows s >= 1, and the padding of the value rows), a lane per
-// 8 consecutive columns; grid-stride over rows.  ldzo is a multiple of 8; the
+// A wave per row (rows s >= 1, and the padding of the value rows), or several
+// rows per wave when rows are narrow, a lane per 8 consecutive columns;
+// grid-stride over rows.  ldzo is a multiple of 8; the
 // vector path needs h_out to be one too (else every block takes the scalar path).
 template <typename TC, typename TZ>
-__global__ __launch_bounds__(256) void k_input_rows(FwdLayerArgs a, const TC* __restrict__ q,
-                                                    const TC* __restrict__ wt) {
+__device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* __restrict__ q,
+                                              const TC* __restrict__ wt, long bx, long gx) {
   const int lane = threadIdx.x & 63;
   const long nrows = (long)a.S * a.N;
-  const long wave0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+  const long wave0 = (bx * blockDim.x + threadIdx.x) >> 6;
+  const long nwaves = (gx * blockDim.x) >> 6;
   const bool vec = (a.h_out & 7) == 0;
   TZ* z = (TZ*)a.z;
-  for (long r = wave0; r < nrows; r += nwaves) {
+  // lpr lanes per row (8 columns each, a power of two covering the row); narrow
+  // rows give a wave several rows (rpw), so that its lanes are not idle
+  int lpr = 1;
+  while (lpr < 64 && lpr * 8 < a.ldzo) lpr *= 2;
+  const int rpw = 64 / lpr, sub = lane / lpr, cl = lane - sub * lpr;
+  for (long rb = wave0 * rpw; rb < nrows; rb += nwaves * rpw) {
+    const long r = rb + sub;
+    if (r >= nrows) continue;
     const int s = (int)(r / a.N), p = (int)(r - (long)s * a.N);
     const bool lap = s == a.S - 1;
     const TC* trow = (const TC*)a.tab_t + (long)p * a.h_out;
-    for (int c0 = lane * 8; c0 < a.ldzo; c0 += 512) {
+    for (int c0 = cl * 8; c0 < a.ldzo; c0 += 8 * lpr) {
       TC zo[8], po[8];
       if (s > 0 && vec && c0 + 8 <= a.h_out) {   // full block of real columns
         TC t[8], w[8];
@@ -1360,6 +1433,32 @@ __global__ __launch_bounds__(256) void k_input_rows(FwdLayerArgs a, const TC* __
       }
     }
   }
+}
+template <typename TC, typename TZ>
+__global__ __launch_bounds__(256) void k_input_rows(FwdLayerArgs a, const TC* __restrict__ q,
+                                                    const TC* __restrict__ wt) {
+  input_rows_at<TC, TZ>(a, q, wt, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_fwdlap_finish4_group(const FinJob* __restrict__ jobs,
+                                                              const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const FinJob j = ld_uniform(jobs + g.job);
+  finish4_at<bf16>(j.a, j.nch, (long)g.local * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_input_q_group(const InQJob* __restrict__ jobs,
+                                                       const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const InQJob j = ld_uniform(jobs + g.job);
+  input_q_at<bf16, float>(j.a, j.q, j.q + j.a.h_out, g.local);
+}
+
+__global__ __launch_bounds__(256) void k_input_rows_group(const InRowsJob* __restrict__ jobs,
+                                                          const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const InRowsJob j = ld_uniform(jobs + g.job);
+  input_rows_at<float, bf16>(j.a, j.q, j.q + j.a.h_out, g.local, j.nblk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1722,6 +1821,81 @@ hipError_t ls_loss(int mode, const void* zi, long ldzi, int ni, int time_row, in
       (const bf16*)zi, ldzi, ni, time_row, lap_row, c_t, c_lap, (const float*)yi, (const bf16*)zb,
       ldzb, nb, (const float*)yb, (const float*)w, K, nbi, partial);
   k_ls_finalize<<<1, 256, 0, st>>>(partial, nbi, nbt, 0.5 / ni, 0.5 / nb, loss);
+  return hipGetLastError();
+}
+
+static bool fwd_group_ok(const FwdLayerArgs& a) {
+  return fwd_args_ok(a) && (a.h_out & 3) == 0 && (a.ldzo & 3) == 0 && !a.pre && !a.dirs;
+}
+
+bool make_fwd_job(const FwdLayerArgs& a0, int nch, const FwdLayerArgs& a1, FwdJob* j) {
+  if (a0.N <= 0 || a1.N <= 0 || a1.has_lap || a1.value_only || a1.sparse_store ||
+      a1.h_out != a0.h_out || a1.ldzo != a0.ldzo || a1.w != a0.w || nch < 1 || nch > kMaxChunks ||
+      !fwd_group_ok(a0) || !fwd_group_ok(a1))
+    return false;
+  j->a0 = a0;
+  j->a1 = a1;
+  j->t0 = fwd_tiles<M_BF16>(a0);
+  j->t1 = fwd_tiles<M_BF16>(a1);
+  j->nch = nch;
+  return true;
+}
+
+bool make_fin_job(const FwdLayerArgs& a, int nch, FinJob* j) {
+  if (a.N <= 0 || (a.h_out & 3) != 0 || (a.ldzo & 3) != 0 || nch < 1 || nch > kMaxChunks)
+    return false;
+  j->a = a;
+  j->nch = nch;
+  return true;
+}
+
+bool make_input_jobs(const FwdLayerArgs& a, void* q, int max_blocks, InQJob* jq, InRowsJob* jr) {
+  if (a.N <= 0 || !a.has_lap || a.S != a.nd + 2 || a.ldzo % 8 || a.dirs || max_blocks < 1)
+    return false;
+  jq->a = a;
+  jq->q = (float*)q;
+  jr->a = a;
+  jr->q = (const float*)q;
+  jr->nblk = (int)std::min<long>(max_blocks, ((long)a.S * a.N + 3) / 4);   // 4 rows per block
+  return true;
+}
+
+int fwd_job_blocks(const FwdJob& j) { return j.t0 * j.nch + j.t1; }
+int fin_job_blocks(const FinJob& j) {
+  const long items = (j.a.has_lap ? (long)j.a.N * (j.a.h_out / 4) : 0) + (long)j.a.S * j.a.N;
+  return (int)((items + 255) / 256);
+}
+int inq_job_blocks(const InQJob& j) { return (j.a.h_out + 63) / 64; }
+int loss_job_blocks(const LossJob& j) { return j.nbt; }
+
+hipError_t fwd_group(const FwdJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_fwdlap_group<bf16, true><<<nblk, DGeo<M_BF16>::NT, 0, st>>>(jobs, blk);
+  return hipGetLastError();
+}
+hipError_t fin_group(const FinJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_fwdlap_finish4_group<<<nblk, 256, 0, st>>>(jobs, blk);
+  return hipGetLastError();
+}
+hipError_t inq_group(const InQJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_input_q_group<<<nblk, 256, 0, st>>>(jobs, blk);
+  return hipGetLastError();
+}
+hipError_t inrows_group(const InRowsJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_input_rows_group<<<nblk, 256, 0, st>>>(jobs, blk);
+  return hipGetLastError();
+}
+hipError_t loss_group(const LossJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_ls_loss_group<<<nblk, 256, 0, st>>>(jobs, blk);
+  return hipGetLastError();
+}
+hipError_t final_group(const LossJob* jobs, int njobs, int slot, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  k_ls_finalize_group<<<njobs, 256, 0, st>>>(jobs, slot);
   return hipGetLastError();
 }
 

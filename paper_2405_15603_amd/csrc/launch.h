@@ -48,6 +48,38 @@ hipError_t prep_weights(Prec p, const void* theta, const void* dir, double alpha
                         void* w_hi, void* w_lo, void* bias, long bias_stride, hipStream_t st,
                         int fwd_only = 0);
 
+// Grouped launches: one launch runs the same kernel for many independent
+// instances.  Workgroup b runs workgroup blk[b].local of job blk[b].job (tables
+// in device memory, built by the host; every job's workgroups are listed once).
+struct GroupBlk {
+  int job, local;
+};
+// Grouped line-search launches (FP32 parameters, BF16 slabs and weight copies);
+// each job lists nblk workgroups (prep: nblk per layer, L layers).
+struct AxpyJob {   // out = theta + alpha * dir over D entries
+  const float* theta;
+  const float* dir;
+  float* out;
+  long D;
+  int nblk;
+};
+struct PrepJob {   // the forward BF16 copy of theta (prep_weights with fwd_only)
+  const float* theta;
+  void* w_hi;
+  NetDesc nd;
+  int nblk;
+};
+struct SlabJob {   // the BF16 input slab of n points (unit directions)
+  const float* x;
+  void* z;
+  long ldz;
+  int n, d, S, nblk;
+};
+hipError_t axpy_group(const AxpyJob* jobs, const GroupBlk* blk, int nblk, double alpha,
+                      hipStream_t st);
+hipError_t prep_group(const PrepJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+hipError_t slab_group(const SlabJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+
 // Input slab Z~^(0): S rows per point (value x, unit rows e_i or the directions
 // dirs[k*d .. k*d + d) when dirs is given, zero Laplacian row) plus the bias
 // column; n points, d inputs, row length ldz.

@@ -1,7 +1,8 @@
 """Batches of heterogeneous instances (64-instance recipe: d in {2,5,10,20},
 N ~ U{500..4000}, widths 64/128/256) stepped together (one inversion launch
-sequence over every instance's factors, captured HIP graphs), against the same
-instances stepped one context at a time.  The kernels and their inputs are the
+sequence over every instance's factors, the grouped line search whose launches
+each cover every instance, captured HIP graphs), against the same instances
+stepped one context at a time.  The kernels' bodies and their inputs are the
 same, so the results must be identical, the Jacobi sweep counts included; every
 graph replay is checked, with unrelated eager work and synchronisation in
 between."""
@@ -21,8 +22,8 @@ def inputs(p, dev):
     return T(p.theta0()), [T(a) for a in p.batch(0)]
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_matches_single_contexts(use_graph):
+@pytest.mark.parametrize("use_graph,grouped", [(True, True), (False, True), (True, False)])
+def test_batch_matches_single_contexts(use_graph, grouped):
     from paper_2405_15603_amd import HParams, KfacPinn, KfacPinnBatch
     from paper_2405_15603_amd import _native as N
     dev = torch.device("cuda", 0)
@@ -44,6 +45,7 @@ def test_batch_matches_single_contexts(use_graph):
         del kp
     # the batch
     b = KfacPinnBatch(probs, "bf16", use_graph=use_graph)
+    b.set_grouped(grouped)
     data = [inputs(p, dev) for p in probs]
     thetas = [d[0] for d in data]
     cols = list(zip(*[d[1] for d in data]))
@@ -51,6 +53,7 @@ def test_batch_matches_single_contexts(use_graph):
     for it in range(steps):
         b.step(thetas, *cols, hp, infos)
         torch.cuda.synchronize()
+        assert b.is_grouped() == grouped
         # unrelated eager work between replays
         junk = torch.randn(1 << 20, device=dev)
         (junk * 2).sum().item()
@@ -97,13 +100,139 @@ def test_batch_graph_recaptures_on_new_arguments():
         del ref
 
 
-def test_batch_instances_against_oracle():
+def test_grouped_line_search_with_new_point_counts():
+    """Grouped line search over instances whose point counts change from one call
+    to the next (fewer interior and boundary points on the second call, the job
+    tables rewritten): each call equals the single-context step on the same
+    points, in direct launches and in captured graphs."""
+    from paper_2405_15603_amd import HParams, KfacPinn, KfacPinnBatch
+    dev = torch.device("cuda", 0)
+    probs = synth.batch_instances(64)[20:26]
+    hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
+    for use_graph in (False, True):
+        b = KfacPinnBatch(probs, "bf16", use_graph=use_graph)
+        data = [inputs(p, dev) for p in probs]
+        thetas = [d[0] for d in data]
+        refs = [KfacPinn.for_problem(p, "bf16") for p in probs]
+        ref_th = [d[0].clone() for d in data]
+        for frac in (1.0, 0.55, 0.55, 1.0):
+            cols = []
+            for (th, (xi, yi, xb, yb)) in data:
+                ni, nb = max(1, int(xi.shape[0] * frac)), max(1, int(xb.shape[0] * frac))
+                cols.append((xi[:ni], yi[:ni], xb[:nb], yb[:nb]))
+            b.step(thetas, *list(zip(*cols)), hp)
+            torch.cuda.synchronize()
+            assert b.is_grouped()
+            for k, kp in enumerate(refs):
+                kp.step(ref_th[k], *cols[k], hp)
+            torch.cuda.synchronize()
+            for k in range(len(probs)):
+                assert torch.equal(thetas[k], ref_th[k]), (use_graph, frac, k)
+        assert b.sync() == [0] * len(probs)
+        assert all(kp.sync() == 0 for kp in refs)
+        del b, refs
+
+
+def test_grouped_line_search_fallbacks():
+    """The grouped line search needs the grid search and BF16 line-search slabs:
+    a fixed step size, the FP32 path or grouping switched off take the
+    per-instance launches (and still equal the single contexts)."""
+    from paper_2405_15603_amd import HParams, KfacPinn, KfacPinnBatch
+    dev = torch.device("cuda", 0)
+    probs = synth.batch_instances(64)[30:33]
+    cases = [("bf16", HParams(lam=1e-3, beta=0.5, momentum=0.5, lr_mode="fixed", lr=2.0 ** -6)),
+             ("f32", HParams(lam=1e-3, beta=0.5, momentum=0.5, lr_mode="grid"))]
+    for precision, hp in cases:
+        b = KfacPinnBatch(probs, precision)
+        data = [inputs(p, dev) for p in probs]
+        thetas = [d[0] for d in data]
+        cols = list(zip(*[d[1] for d in data]))
+        b.step(thetas, *cols, hp)
+        torch.cuda.synchronize()
+        assert not b.is_grouped()
+        assert b.sync() == [0] * len(probs)
+        for k, p in enumerate(probs):
+            th, (xi, yi, xb, yb) = inputs(p, dev)
+            kp = KfacPinn.for_problem(p, precision)
+            kp.step(th, xi, yi, xb, yb, hp)
+            torch.cuda.synchronize()
+            assert torch.equal(thetas[k], th), (precision, k)
+            del kp
+        del b
+    from paper_2405_15603_amd import _native as N
+    b = KfacPinnBatch(probs, "bf16")
+    assert b.lib.kfac_pinn_batch_set_grouped(b.h, 2) == N.KP_ERR_ARG
+
+
+def forced_chunks_cache(b, data, path, nch):
+    """A tuning cache that sets every class of the batch to `nch` chunks (at most
+    one per derivative row): a first tune writes the timed choices for this
+    device, the rewritten file is read back by a second tune (nothing timed)."""
+    import json
+    thetas = [d[0].clone() for d in data]
+    cols = list(zip(*[d[1] for d in data]))
+    assert b.tune(thetas, *cols, cache_path=str(path)) > 0
+    doc = json.loads(path.read_text())
+    assert doc["kfac_pinn_tune"] == 1 and doc["entries"]
+    for e in doc["entries"]:
+        e["nch"] = min(nch, e["S"] - 2)
+    path.write_text(json.dumps(doc))
+    assert b.tune(thetas, *cols, cache_path=str(path)) == 0
+    return doc
+
+
+def test_batch_tune_cache_and_choices(tmp_path):
+    """The tuner times every class once and writes them to its JSON cache; a second
+    tune reads them back without timing.  A step after tuning takes the grouped
+    line search and succeeds on every instance; with the single-instance choice
+    forced for every class (nch 0 in the cache) it equals the single contexts."""
+    import json
+    from paper_2405_15603_amd import HParams, KfacPinn, KfacPinnBatch
+    dev = torch.device("cuda", 0)
+    probs = synth.batch_instances(64)[40:48]
+    hp = HParams(lam=1e-3, beta=0.886041, momentum=0.707588, lr_mode="grid")
+    b = KfacPinnBatch(probs, "bf16")
+    data = [inputs(p, dev) for p in probs]
+    thetas = [d[0].clone() for d in data]
+    cols = list(zip(*[d[1] for d in data]))
+    path = tmp_path / "tune.json"
+    timed = b.tune(thetas, *cols, cache_path=str(path))
+    doc = json.loads(path.read_text())
+    keys = {(e["K"], e["h_out"], e["S"]) for e in doc["entries"]}
+    assert timed == len(keys) > 0
+    assert all(0 <= e["nch"] <= 8 for e in doc["entries"])
+    assert b.tune(thetas, *cols, cache_path=str(path)) == 0
+    b.step(thetas, *cols, hp)
+    torch.cuda.synchronize()
+    assert b.is_grouped() and b.sync() == [0] * len(probs)
+    # every class at the single-instance choice: the results of kfac_pinn_step
+    for e in doc["entries"]:
+        e["nch"] = 0
+    path.write_text(json.dumps(doc))
+    b2 = KfacPinnBatch(probs, "bf16")
+    assert b2.tune(thetas, *cols, cache_path=str(path)) == 0
+    th2 = [d[0].clone() for d in data]
+    b2.step(th2, *cols, hp)
+    torch.cuda.synchronize()
+    assert b2.is_grouped() and b2.sync() == [0] * len(probs)
+    for k, p in enumerate(probs):
+        th, (xi, yi, xb, yb) = inputs(p, dev)
+        kp = KfacPinn.for_problem(p, "bf16")
+        kp.step(th, xi, yi, xb, yb, hp)
+        torch.cuda.synchronize()
+        assert torch.equal(th2[k], th), k
+        del kp
+
+
+@pytest.mark.parametrize("forced_nch", [None, 1])
+def test_batch_instances_against_oracle(forced_nch, tmp_path):
     """Four instances of the 64-instance recipe (d = 20 at widths 256, 64 and 128,
     and a d = 2 one) stepped as a batch in mixed precision, one step from identity
     factors with beta = 0, so the factors after the step are the step's own.  Each
     instance's factors must be within the 1e-3 gate of the oracle's at the same
     parameters and points, and its candidate losses and chosen step must pass the
-    BF16 line-search check (helpers.check_bf16_candidates)."""
+    BF16 line-search check (helpers.check_bf16_candidates) -- also with the grouped
+    line search's layer products in one chunk per class (a tuned choice)."""
     from paper_2405_15603_amd import HParams, KfacPinnBatch
     import oracle
     from helpers import check_bf16_candidates, oracle_curvature, rel
@@ -115,6 +244,8 @@ def test_batch_instances_against_oracle():
     hp = HParams(lam=1e-3, beta=0.0, momentum=0.0, lr_mode="grid")
     b = KfacPinnBatch(probs, "bf16")
     data = [inputs(p, dev) for p in probs]
+    if forced_nch is not None:
+        forced_chunks_cache(b, data, tmp_path / "tune.json", forced_nch)
     thetas = [d[0] for d in data]
     th0 = [t.cpu().double().numpy().copy() for t in thetas]
     cols = list(zip(*[d[1] for d in data]))
@@ -122,6 +253,7 @@ def test_batch_instances_against_oracle():
     b.step(thetas, *cols, hp, infos)
     torch.cuda.synchronize()
     assert b.sync() == [0] * len(probs)
+    assert b.is_grouped()
     raw = infos.cpu().numpy().tobytes()
     sz = C.sizeof(N_info())
     for k, p in enumerate(probs):
