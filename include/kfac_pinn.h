@@ -396,20 +396,25 @@ kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* batch, int32_t enabled);
 kp_status kfac_pinn_batch_set_grouped(kfac_pinn_batch* batch, int32_t enabled);
 kp_status kfac_pinn_batch_is_grouped(kfac_pinn_batch* batch, int32_t* out);
 /* Autotuning of the grouped line search (not in the paper).  Chooses, per class
- * (K = h_in + 1 rounded up to 8, h_out, rows per point S) of the grouped layer
- * products past the input layer, the number of derivative-row chunks by timing
- * the grouped layer launch of every instance with each candidate (the
- * single-instance choice and 1, 2, 4, 8 chunks); a count replaces the
- * single-instance choice only when at least 3 % faster.  The arguments are those
- * of kfac_pinn_batch_step (both point sets non-empty); the instances' parameters
- * are not changed, their line-search buffers are overwritten.  cache_path (or
- * NULL): a JSON file of earlier choices per device and class, read first (cached
- * classes are not timed) and rewritten with the merged choices; an unwritable
- * path gives KP_ERR_ARG after the choices are applied.  timed (or NULL): the
- * number of classes timed.  Waits for the device.  With tuned counts other than
- * the single-instance choice the candidates' losses differ from kfac_pinn_step's
- * in rounding (another grouping of the sums over derivative rows).  KP_ERR_STATE
- * when the instances do not take the grouped line search. */
+ * (K = h_in + 1 rounded up to 8, h_out, rows per point S, value rows only) of the
+ * grouped layer products, the tile geometry (points x neurons per workgroup:
+ * 64 x 256, 128 x 128 or 256 x 64; untuned: the narrowest neuron tile covering
+ * the layer) and, past the input layer, the number of derivative-row chunks (the
+ * single-instance choice, 1, 2, 4 or 8), by timing the grouped launches over
+ * every instance: first one policy for all classes (geometry by width or
+ * 64 x 256; chunk counts as for a single instance or capped at 1, 2, 4 or 8),
+ * then each class's alternatives within the launches of its layers (kept when
+ * faster by more than 2 us and 0.5 %).  The arguments are those of
+ * kfac_pinn_batch_step (both point sets non-empty); the instances' parameters are
+ * not changed, their line-search buffers are overwritten.  cache_path (or NULL):
+ * a JSON file of earlier choices per device and class, read first (cached classes
+ * are not timed) and rewritten with the merged choices; an unwritable path gives
+ * KP_ERR_ARG after the choices are applied.  timed (or NULL): the number of
+ * classes timed.  Waits for the device.  The geometry does not change results;
+ * chunk counts other than the single-instance choice make the candidates' losses
+ * differ from kfac_pinn_step's in rounding (another grouping of the sums over
+ * derivative rows).  KP_ERR_STATE when the instances do not take the grouped
+ * line search. */
 kp_status kfac_pinn_batch_tune(kfac_pinn_batch* batch, void* const* thetas,
                                const void* const* x_int, const void* const* y_int,
                                const int32_t* n_int, const void* const* x_bnd,

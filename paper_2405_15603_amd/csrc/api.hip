@@ -1684,6 +1684,11 @@ kp_status kfac_pinn_sync(kfac_pinn_ctx* c) {
 // first call and replayed on later calls with the same arguments (different
 // arguments recapture); one graph per lane keeps the lanes concurrent.
 // ---------------------------------------------------------------------------
+struct GroupChoice {
+  int nch = 0;    // derivative-row chunks (0: the single-instance choice)
+  int geo = -1;   // tile geometry (-1: the narrowest neuron tile covering the layer)
+};
+
 struct kfac_pinn_batch {
   std::vector<kfac_pinn_ctx*> ctx;
   hipStream_t st = nullptr;       // the caller's stream (may be the null stream)
@@ -1713,15 +1718,16 @@ struct kfac_pinn_batch {
   };
   struct Group {
     GTab axpy, prep, slab, inq, inrows, loss;
-    std::vector<GTab> fwd, fin;   // per hidden layer (fin[0] unused: the input layer's rows)
+    std::vector<std::array<GTab, kFwdGeos>> fwd;   // per hidden layer and tile geometry
+    std::vector<GTab> fin;   // per hidden layer (fin[0] unused: the input layer's rows)
     char* dev = nullptr;
     size_t cap = 0;
     std::vector<uintptr_t> key;   // the step arguments the tables were built for
   } grp;
-  // Chunk counts of the grouped layer products chosen by kfac_pinn_batch_tune, per
-  // class (K, h_out, S) of a hidden layer past the input layer; other classes take
-  // the single-instance choice (and then the same results as kfac_pinn_step).
-  std::map<std::array<int, 3>, int> nch_tuned;
+  // Choices of the grouped layer products made by kfac_pinn_batch_tune, per class
+  // (K, h_out, S, value rows only): the chunk count (0: the single-instance choice,
+  // which gives the results of kfac_pinn_step) and the tile geometry (-1: by width).
+  std::map<std::array<int, 4>, GroupChoice> tuned;
   int grouped = 1;          // use the grouped line search when every instance qualifies
   bool grp_active = false;  // this step's choice
   std::vector<hipEvent_t> ev_pre;   // per lane: directions and momenta done
@@ -1770,12 +1776,20 @@ struct BatchArgs {
 // (offsets into it in g).  bound: sizes only, for the largest point counts (the
 // step's data pointers are not read).  False when an instance does not take the
 // paired BF16 line search these kernels cover.
-std::array<int, 3> nch_class(const FwdLayerArgs& a) { return {a.K, a.h_out, a.S}; }
+typedef std::map<std::array<int, 4>, GroupChoice> ChoiceMap;
+std::array<int, 4> group_class(const FwdLayerArgs& a) { return {a.K, a.h_out, a.S, a.value_only}; }
+
+// the narrowest neuron tile that covers a layer of h_out neurons
+int default_geo(int h_out) {
+  int best = 0;
+  for (int g = 0; g < kFwdGeos; g++)
+    if (fwd_geo_width(g) >= h_out && fwd_geo_width(g) < fwd_geo_width(best)) best = g;
+  return best;
+}
 
 bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector<char>& blob,
-                 kfac_pinn_batch::Group& g,
-                 const std::map<std::array<int, 3>, int>* nch_over = nullptr) {
-  if (!nch_over) nch_over = &b->nch_tuned;
+                 kfac_pinn_batch::Group& g, const ChoiceMap* over = nullptr) {
+  if (!over) over = &b->tuned;
   const int n = (int)b->ctx.size();
   const int L = b->ctx[0]->L;
   if (L < 2) return false;
@@ -1783,6 +1797,7 @@ bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector
   std::vector<PrepJob> pw(n);
   std::vector<SlabJob> sl(2 * n);
   std::vector<std::vector<FwdJob>> fw(L - 1, std::vector<FwdJob>(n));
+  std::vector<std::vector<int>> fgeo(L - 1, std::vector<int>(n));
   std::vector<std::vector<FinJob>> fi(L - 1, std::vector<FinJob>(n));
   std::vector<InQJob> iq(n);
   std::vector<InRowsJob> ir(n);
@@ -1817,12 +1832,14 @@ bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector
     for (int l = 0; l < L - 1; l++) {
       const LayerLaunch Li = layer_launch(c, c->si, ni, l, L, Ti);
       const LayerLaunch Lb = layer_launch(c, c->sb, nb, l, L, Tb);
-      int nch = Li.nch;
-      if (l > 0) {
-        auto it = nch_over->find(nch_class(Li.a));
-        if (it != nch_over->end()) nch = it->second;
+      int nch = Li.nch, geo = default_geo(Li.a.h_out);
+      auto it = over->find(group_class(Li.a));
+      if (it != over->end()) {
+        if (l > 0 && it->second.nch > 0) nch = it->second.nch;
+        if (it->second.geo >= 0) geo = it->second.geo;
       }
-      if (!make_fwd_job(Li.a, nch, Lb.a, &fw[l][k])) return false;
+      if (!make_fwd_job(Li.a, nch, Lb.a, geo, &fw[l][k])) return false;
+      fgeo[l][k] = geo;
       // sizes at creation: the chunk count of a smaller step may be larger
       nfw[l][k] = bound ? fw[l][k].t0 * kMaxChunks + fw[l][k].t1 : fwd_job_blocks(fw[l][k]);
       if (l == 0) {
@@ -1867,10 +1884,20 @@ bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector
   add(g.axpy, ax.data(), sizeof(AxpyJob) * n, nax);
   add(g.prep, pw.data(), sizeof(PrepJob) * n, npw);
   add(g.slab, sl.data(), sizeof(SlabJob) * 2 * n, nsl);
-  g.fwd.assign(L - 1, kfac_pinn_batch::GTab{});
+  g.fwd.assign(L - 1, std::array<kfac_pinn_batch::GTab, kFwdGeos>{});
   g.fin.assign(L - 1, kfac_pinn_batch::GTab{});
   for (int l = 0; l < L - 1; l++) {
-    add(g.fwd[l], fw[l].data(), sizeof(FwdJob) * n, nfw[l]);
+    // one table (one launch) per tile geometry in use
+    for (int geo = 0; geo < kFwdGeos; geo++) {
+      std::vector<FwdJob> jobs;
+      std::vector<int> nbl;
+      for (int k = 0; k < n; k++)
+        if (fgeo[l][k] == geo) {
+          jobs.push_back(fw[l][k]);
+          nbl.push_back(nfw[l][k]);
+        }
+      add(g.fwd[l][geo], jobs.data(), sizeof(FwdJob) * jobs.size(), nbl);
+    }
     if (l > 0) add(g.fin[l], fi[l].data(), sizeof(FinJob) * n, nfi[l]);
   }
   add(g.inq, iq.data(), sizeof(InQJob) * n, niq);
@@ -1895,7 +1922,9 @@ kp_status group_ls(kfac_pinn_batch* b, const kp_hparams* hp, hipStream_t st) {
     KP_TRY(prep_group((const PrepJob*)(d + g.prep.jobs), blk(g.prep), g.prep.nblk, st));
     KP_TRY(slab_group((const SlabJob*)(d + g.slab.jobs), blk(g.slab), g.slab.nblk, st));
     for (int l = 0; l < L - 1; l++) {
-      KP_TRY(fwd_group((const FwdJob*)(d + g.fwd[l].jobs), blk(g.fwd[l]), g.fwd[l].nblk, st));
+      for (int geo = 0; geo < kFwdGeos; geo++)
+        KP_TRY(fwd_group(geo, (const FwdJob*)(d + g.fwd[l][geo].jobs), blk(g.fwd[l][geo]),
+                         g.fwd[l][geo].nblk, st));
       if (l == 0) {
         KP_TRY(inq_group((const InQJob*)(d + g.inq.jobs), blk(g.inq), g.inq.nblk, st));
         KP_TRY(inrows_group((const InRowsJob*)(d + g.inrows.jobs), blk(g.inrows), g.inrows.nblk,
@@ -1910,12 +1939,13 @@ kp_status group_ls(kfac_pinn_batch* b, const kp_hparams* hp, hipStream_t st) {
   return KP_OK;
 }
 
-// ---- autotuning of the grouped line search's chunk counts --------------------
-// A cache entry: device, class (K, h_out, S) and the chosen chunk count (0: the
-// single-instance choice).  The cache is a JSON file of these entries.
+// ---- autotuning of the grouped line search's layer products ------------------
+// A cache entry: device, class (K, h_out, S, value rows only) and the choice
+// (chunk count, 0: the single-instance choice; tile geometry).  The cache is a
+// JSON file of these entries.
 struct TuneEntry {
   std::string device;
-  int K = 0, h_out = 0, S = 0, nch = 0;
+  int K = 0, h_out = 0, S = 0, value_only = 0, nch = 0, geo = 0;
 };
 
 std::string device_tag() {
@@ -1923,15 +1953,16 @@ std::string device_tag() {
   hipDeviceProp_t pr{};
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess)
     return "unknown";
-  std::string t = std::string(pr.gcnArchName) + " " + pr.name + " cu" +
-                  std::to_string(pr.multiProcessorCount);
+  // the architecture and compute-unit count (the marketing name is not always
+  // reported, e.g. under a profiler)
+  std::string t = std::string(pr.gcnArchName) + " cu" + std::to_string(pr.multiProcessorCount);
   for (char& ch : t)
     if (ch == '"' || ch == '\\' || (unsigned char)ch < 32) ch = ' ';
   return t;
 }
 
 // Reads the flat objects of the cache's "entries" array (unknown keys skipped; a
-// missing or malformed file reads as empty).
+// missing or malformed file, or an entry with a missing key, reads as absent).
 std::vector<TuneEntry> tune_cache_read(const char* path) {
   std::vector<TuneEntry> out;
   if (!path) return out;
@@ -1951,21 +1982,24 @@ std::vector<TuneEntry> tune_cache_read(const char* path) {
     bool ok = true;
     auto num = [&](const char* key, int& v) {
       const size_t k = obj.find(std::string("\"") + key + "\"");
-      if (k == std::string::npos) { ok = false; return; }
-      const size_t c = obj.find(':', k);
-      if (c == std::string::npos) { ok = false; return; }
-      v = atoi(obj.c_str() + c + 1);
+      const size_t c = k == std::string::npos ? k : obj.find(':', k);
+      if (c == std::string::npos) ok = false;
+      else v = atoi(obj.c_str() + c + 1);
     };
     num("K", t.K);
     num("h_out", t.h_out);
     num("S", t.S);
+    num("value_only", t.value_only);
     num("nch", t.nch);
+    num("geo", t.geo);
     const size_t k = obj.find("\"device\"");
-    const size_t q0 = k == std::string::npos ? k : obj.find('"', obj.find(':', k));
+    const size_t c = k == std::string::npos ? k : obj.find(':', k);
+    const size_t q0 = c == std::string::npos ? c : obj.find('"', c);
     const size_t q1 = q0 == std::string::npos ? q0 : obj.find('"', q0 + 1);
     if (q1 == std::string::npos) ok = false;
     else t.device = obj.substr(q0 + 1, q1 - q0 - 1);
-    if (ok && t.nch >= 0 && t.nch <= kMaxChunks) out.push_back(t);
+    if (ok && t.nch >= 0 && t.nch <= kMaxChunks && t.geo >= 0 && t.geo < kFwdGeos)
+      out.push_back(t);
     pos = e + 1;
   }
   return out;
@@ -1975,53 +2009,58 @@ bool tune_cache_write(const char* path, const std::vector<TuneEntry>& es) {
   if (!path) return true;
   FILE* f = fopen(path, "wb");
   if (!f) return false;
-  fprintf(f, "{\n  \"kfac_pinn_tune\": 1,\n  \"entries\": [\n");
+  fprintf(f, "{\n  \"kfac_pinn_tune\": 2,\n  \"entries\": [\n");
   for (size_t i = 0; i < es.size(); i++)
-    fprintf(f, "    {\"device\": \"%s\", \"K\": %d, \"h_out\": %d, \"S\": %d, \"nch\": %d}%s\n",
-            es[i].device.c_str(), es[i].K, es[i].h_out, es[i].S, es[i].nch,
-            i + 1 < es.size() ? "," : "");
+    fprintf(f,
+            "    {\"device\": \"%s\", \"K\": %d, \"h_out\": %d, \"S\": %d, "
+            "\"value_only\": %d, \"nch\": %d, \"geo\": %d}%s\n",
+            es[i].device.c_str(), es[i].K, es[i].h_out, es[i].S, es[i].value_only, es[i].nch,
+            es[i].geo, i + 1 < es.size() ? "," : "");
   fprintf(f, "  ]\n}\n");
   return fclose(f) == 0;
 }
 
-// Chooses the chunk count of each class of grouped layer products (hidden layers
-// past the input layer) by timing: class by class, within the full grouped
-// launch of its layer (layer product and finishing pass over every instance), the
-// single-instance choice and 1, 2, 4, 8 chunks (at most one per derivative row);
-// another count replaces the single-instance choice only when at least 3 % faster
-// (minimum of 3 timed launches after one untimed).  Classes in the cache for this
-// device are taken from it.
+// Chooses the tile geometry and chunk count of the grouped layer products by
+// timing the grouped launches of every instance's layers (layer products, and
+// the finishing passes past the input layer; minimum of 3 timed runs after one
+// untimed).  First a policy for every class at once: the geometry by width or
+// 64 x 256 everywhere, with the single-instance chunk counts or at most 1, 2, 4
+// or 8 chunks (kept when at least 1 % faster in total).  Then class by class,
+// within the launches of the layers the class occurs in, the other geometries
+// and chunk counts (at most one per derivative row; kept when faster by more
+// than 2 us and 0.5 %).  Classes in the cache for this device are taken from it.
 kp_status batch_tune(kfac_pinn_batch* b, const BatchArgs& a, const char* cache_path,
                      int* timed_out) {
   hipStream_t st = b->lanes[0];
-  std::map<std::array<int, 3>, int> cur = b->nch_tuned;
+  ChoiceMap cur = b->tuned;
   std::vector<char> blob;
   kfac_pinn_batch::Group g = b->grp;
   if (!b->grp.dev || !group_build(b, &a, false, blob, g, &cur) || blob.size() > b->grp.cap)
     return KP_ERR_STATE;
   const int L = (int)g.fwd.size() + 1;
-  // classes per layer, with their largest derivative-row count
-  std::vector<std::map<std::array<int, 3>, int>> cls(L - 1);
+  // classes per layer, with their largest derivative-row count and their width
+  struct ClassInfo {
+    int nd = 0, h_out = 0;
+  };
+  std::vector<std::map<std::array<int, 4>, ClassInfo>> cls(L - 1);
   for (size_t k = 0; k < b->ctx.size(); k++) {
     kfac_pinn_ctx* c = b->ctx[k];
     FwdTarget Ti, Tb;
     ls_targets(c, Ti, Tb);
-    for (int l = 1; l < L - 1; l++) {
+    for (int l = 0; l < L - 1; l++) {
       const LayerLaunch Li = layer_launch(c, c->si, a.ni[k], l, L, Ti);
-      int& nd = cls[l][nch_class(Li.a)];
-      nd = std::max(nd, Li.a.nd);
+      ClassInfo& ci = cls[l][group_class(Li.a)];
+      ci.nd = std::max(ci.nd, Li.a.nd);
+      ci.h_out = Li.a.h_out;
     }
   }
   const std::string dev = device_tag();
   std::vector<TuneEntry> cache = tune_cache_read(cache_path);
-  auto cached = [&](const std::array<int, 3>& k) -> const TuneEntry* {
+  auto cached = [&](const std::array<int, 4>& k) -> const TuneEntry* {
     for (const TuneEntry& t : cache)
-      if (t.device == dev && t.K == k[0] && t.h_out == k[1] && t.S == k[2]) return &t;
+      if (t.device == dev && t.K == k[0] && t.h_out == k[1] && t.S == k[2] && t.value_only == k[3])
+        return &t;
     return nullptr;
-  };
-  auto set = [&](const std::array<int, 3>& k, int n) {
-    if (n == 0) cur.erase(k);
-    else cur[k] = n;
   };
   // real slab contents for the timed launches: one line-search candidate (alpha = 1)
   KP_TRY(hipStreamSynchronize(st));
@@ -2052,10 +2091,12 @@ kp_status batch_tune(kfac_pinn_batch* b, const BatchArgs& a, const char* cache_p
     float best = 1e30f;
     for (int rep = 0; rep < 4; rep++) {
       KP_TRY(hipEventRecord(e0, st));
-      KP_TRY(fwd_group((const FwdJob*)(d + t.fwd[l].jobs), (const GroupBlk*)(d + t.fwd[l].blk),
-                       t.fwd[l].nblk, st));
-      KP_TRY(fin_group((const FinJob*)(d + t.fin[l].jobs), (const GroupBlk*)(d + t.fin[l].blk),
-                       t.fin[l].nblk, st));
+      for (int geo = 0; geo < kFwdGeos; geo++)
+        KP_TRY(fwd_group(geo, (const FwdJob*)(d + t.fwd[l][geo].jobs),
+                         (const GroupBlk*)(d + t.fwd[l][geo].blk), t.fwd[l][geo].nblk, st));
+      if (l > 0)
+        KP_TRY(fin_group((const FinJob*)(d + t.fin[l].jobs), (const GroupBlk*)(d + t.fin[l].blk),
+                         t.fin[l].nblk, st));
       KP_TRY(hipEventRecord(e1, st));
       KP_TRY(hipEventSynchronize(e1));
       float v = 0.0f;
@@ -2065,35 +2106,86 @@ kp_status batch_tune(kfac_pinn_batch* b, const BatchArgs& a, const char* cache_p
     *ms = best;
     return KP_OK;
   };
-  int ntimed = 0;
-  kp_status s = KP_OK;
-  for (int l = 1; l < L - 1 && s == KP_OK; l++) {
+  // the classes to time (not in the cache), the layers each occurs in
+  std::map<std::array<int, 4>, std::vector<int>> open_cls;
+  std::map<std::array<int, 4>, ClassInfo> info;
+  for (int l = 0; l < L - 1; l++)
     for (const auto& kv : cls[l]) {
-      const std::array<int, 3>& key = kv.first;
-      if (const TuneEntry* t = cached(key)) {
-        set(key, t->nch);
-        continue;
-      }
-      set(key, 0);
-      float base = 0.0f;
-      if ((s = timed(l, &base)) != KP_OK) break;
-      int best_n = 0;
-      float best_ms = base;
-      for (int n : {1, 2, 4, 8}) {
-        if (n > std::max(1, kv.second)) continue;
-        set(key, n);
+      info[kv.first] = kv.second;
+      if (const TuneEntry* t = cached(kv.first)) cur[kv.first] = GroupChoice{t->nch, t->geo};
+      else open_cls[kv.first].push_back(l);
+    }
+  auto layers_ms = [&](const std::vector<int>& ls, float* ms) -> kp_status {
+    float sum = 0.0f;
+    for (int l : ls) {
+      float v = 0.0f;
+      kp_status s = timed(l, &v);
+      if (s != KP_OK) return s;
+      sum += v;
+    }
+    *ms = sum;
+    return KP_OK;
+  };
+  std::vector<int> all_layers;
+  for (int l = 0; l < L - 1; l++) all_layers.push_back(l);
+  kp_status s = KP_OK;
+  // 1) one policy for every open class
+  auto policy = [&](bool by_width, int cap) {
+    for (const auto& kv : open_cls) {
+      const ClassInfo& ci = info[kv.first];
+      const bool value_only = kv.first[3] != 0;
+      cur[kv.first] = GroupChoice{value_only || cap == 0 ? 0 : std::min(cap, std::max(1, ci.nd)),
+                                  by_width ? default_geo(ci.h_out) : 0};
+    }
+  };
+  if (!open_cls.empty()) {
+    bool best_w = true;
+    int best_cap = 0;
+    policy(true, 0);
+    float best = 0.0f;
+    s = layers_ms(all_layers, &best);
+    for (int w = 1; w >= 0 && s == KP_OK; w--)
+      for (int cap : {0, 1, 2, 4, 8}) {
+        if (s != KP_OK || (w == 1 && cap == 0)) continue;
+        policy(w == 1, cap);
         float v = 0.0f;
-        if ((s = timed(l, &v)) != KP_OK) break;
-        if (v < best_ms && v < 0.97f * base) {
-          best_ms = v;
-          best_n = n;
+        if ((s = layers_ms(all_layers, &v)) == KP_OK && v < 0.99f * best) {
+          best = v;
+          best_w = w == 1;
+          best_cap = cap;
         }
       }
-      if (s != KP_OK) break;
-      set(key, best_n);
-      cache.push_back(TuneEntry{dev, key[0], key[1], key[2], best_n});
-      ntimed++;
+    policy(best_w, best_cap);
+  }
+  // 2) class by class
+  int ntimed = 0;
+  for (const auto& kv : open_cls) {
+    if (s != KP_OK) break;
+    const std::array<int, 4>& key = kv.first;
+    const ClassInfo& ci = info[key];
+    GroupChoice ch = cur[key];
+    float best = 0.0f;
+    if ((s = layers_ms(kv.second, &best)) != KP_OK) break;
+    std::vector<GroupChoice> alts;
+    for (int geo = 0; geo < kFwdGeos; geo++)
+      for (int nch : {0, 1, 2, 4, 8}) {
+        if (key[3] != 0 && nch != 0) continue;   // the input layer's value rows: one chunk
+        if (nch > std::max(1, ci.nd) || (geo == ch.geo && nch == ch.nch)) continue;
+        alts.push_back(GroupChoice{nch, geo});
+      }
+    for (const GroupChoice& alt : alts) {
+      cur[key] = alt;
+      float v = 0.0f;
+      if ((s = layers_ms(kv.second, &v)) != KP_OK) break;
+      if (best - v > std::max(0.002f, 0.005f * best)) {
+        best = v;
+        ch = alt;
+      }
     }
+    if (s != KP_OK) break;
+    cur[key] = ch;
+    cache.push_back(TuneEntry{dev, key[0], key[1], key[2], key[3], ch.nch, ch.geo});
+    ntimed++;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -2101,7 +2193,7 @@ kp_status batch_tune(kfac_pinn_batch* b, const BatchArgs& a, const char* cache_p
   b->grp.key.clear();
   batch_drop_graph(b);
   if (s != KP_OK) return s;
-  b->nch_tuned = cur;
+  b->tuned = cur;
   if (timed_out) *timed_out = ntimed;
   if (!tune_cache_write(cache_path, cache)) {
     kp_set_last_error("cannot write the tuning cache", __FILE__, __LINE__);

@@ -100,7 +100,12 @@ struct LossJob {   // one candidate's loss (ls_loss); the finalize adds `slot` t
 };
 // Job makers: false when the arguments do not take the grouped BF16 path (the
 // single-instance launchers' checks, plus 4-aligned rows and unit directions).
-bool make_fwd_job(const FwdLayerArgs& a0, int nch, const FwdLayerArgs& a1, FwdJob* j);
+// Tile geometries of the grouped layer product (points x neurons per workgroup):
+// 0: 64 x 256 (the single-instance line search's), 1: 128 x 128, 2: 256 x 64.  An
+// output element's arithmetic is the same in each.
+constexpr int kFwdGeos = 3;
+int fwd_geo_width(int geo);   // neurons per tile
+bool make_fwd_job(const FwdLayerArgs& a0, int nch, const FwdLayerArgs& a1, int geo, FwdJob* j);
 bool make_fin_job(const FwdLayerArgs& a, int nch, FinJob* j);
 bool make_input_jobs(const FwdLayerArgs& a, void* q, int max_blocks, InQJob* jq, InRowsJob* jr);
 // the number of workgroups of each job
@@ -110,7 +115,7 @@ int inq_job_blocks(const InQJob& j);
 int loss_job_blocks(const LossJob& j);
 // Grouped launches over `nblk` workgroups (blk holds nblk entries).  The
 // finalize runs one workgroup per job and writes loss[slot] of each.
-hipError_t fwd_group(const FwdJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+hipError_t fwd_group(int geo, const FwdJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
 hipError_t fin_group(const FinJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
 hipError_t inq_group(const InQJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
 hipError_t inrows_group(const InRowsJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);

@@ -308,14 +308,22 @@ __device__ __align__(16) u32x4 kZeroChunk = {0u, 0u, 0u, 0u};
 // stages the ring is 128 KB.  Measured against 128 x 128 tiles, two or three
 // columns per pass, three or four stages and 64-byte k-tiles, this is the
 // fastest.
-template <int MODE> struct DGeo;
-template <> struct DGeo<M_BF16> {
-  static constexpr int NWP = 2, NWN = 4, WP = 32, WN = 64, NS = 4, ST = 2;
+template <int NWP_, int NWN_, int NS_> struct DGeoT {
+  static constexpr int NWP = NWP_, NWN = NWN_, WP = 32, WN = 64, NS = NS_, ST = 2;
   static constexpr int RB = 128;   // bytes of a k-tile row (64-byte rows with more stages were slower)
   static constexpr int NW = NWP * NWN, NT = 64 * NW;
   static constexpr int BP = NWP * WP, BN = NWN * WN;
   static constexpr int TI = WP / 16, TJ = WN / 16;
 };
+template <int MODE> struct DGeo;
+template <> struct DGeo<M_BF16> : DGeoT<2, 4, 4> {};
+// Narrower neuron tiles for narrow layers (the grouped line search of many small
+// networks): the same wave tile, waves stacked along the points.  128 x 128 with
+// four rows per pass fills the 160 KB of LDS with its two-stage ring; 256 x 64
+// holds two rows per pass.  An output element's products and sums are the same
+// in every geometry.
+using DGeoW128 = DGeoT<4, 2, 4>;
+using DGeoW64 = DGeoT<8, 1, 2>;
 
 template <class G, typename T>
 struct DmaCfg {
@@ -542,20 +550,22 @@ __device__ __forceinline__ TC wt_of(const Args& a, int i) {
 template <int MODE>
 using FwdGeo = typename std::conditional<kDma<MODE>, DGeo<M_BF16>, Geo<MODE>>::type;
 
+template <class G> constexpr int dma_smem() { return G::ST * DmaCfg<G, bf16>::STAGE; }
+static_assert(dma_smem<DGeoW128>() <= 160 * 1024 && dma_smem<DGeoW64>() <= 160 * 1024,
+              "the ring fits the LDS of a compute unit");
 template <int MODE> constexpr int fwd_smem() {
   if constexpr (kDma<MODE>)
-    return DGeo<M_BF16>::ST * DmaCfg<DGeo<M_BF16>, bf16>::STAGE;
+    return dma_smem<DGeo<M_BF16>>();
   else
     return (int)sizeof(typename Mainloop<MODE>::Smem);
 }
 
 // One workgroup of a layer product: tile t, chunk `chunk` of nch.  PLAIN: rows
 // without derivative or Laplacian rows (one column per point, no tables).
-template <int MODE, typename TZ, bool A4, bool PLAIN = false>
+template <int MODE, typename TZ, bool A4, bool PLAIN = false, class G = FwdGeo<MODE>>
 __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chunk, int nch,
                                           char* smem) {
   typedef Op<MODE> O;
-  typedef FwdGeo<MODE> G;
   typedef typename O::TC TC;
   typedef typename O::TL TL;
   typedef Mfma<TL> MF;
@@ -785,17 +795,18 @@ __device__ __forceinline__ T ld_uniform(const T* p) {
 #endif
 }
 
-template <typename TZ, bool A4>
-__global__ __launch_bounds__(DGeo<M_BF16>::NT) void k_fwdlap_group(
-    const FwdJob* __restrict__ jobs, const GroupBlk* __restrict__ blk) {
-  __shared__ __align__(16) char smem[fwd_smem<M_BF16>()];
+template <typename TZ, bool A4, class G>
+__global__ __launch_bounds__(G::NT) void k_fwdlap_group(const FwdJob* __restrict__ jobs,
+                                                        const GroupBlk* __restrict__ blk) {
+  __shared__ __align__(16) char smem[dma_smem<G>()];
   const GroupBlk g = ld_uniform(blk + blockIdx.x);
   const FwdJob j = ld_uniform(jobs + g.job);
   const int n0 = j.t0 * j.nch;
   if (g.local < n0)
-    fwd_block<M_BF16, TZ, A4>(j.a0, xcd_tile(g.local % j.t0, j.t0), g.local / j.t0, j.nch, smem);
+    fwd_block<M_BF16, TZ, A4, false, G>(j.a0, xcd_tile(g.local % j.t0, j.t0), g.local / j.t0,
+                                        j.nch, smem);
   else
-    fwd_block<M_BF16, TZ, A4, true>(j.a1, xcd_tile(g.local - n0, j.t1), 0, 1, smem);
+    fwd_block<M_BF16, TZ, A4, true, G>(j.a1, xcd_tile(g.local - n0, j.t1), 0, 1, smem);
 }
 
 
@@ -1364,73 +1375,78 @@ __device__ __forceinline__ void load8(const TC* src, TC (&v)[8]) {
   }
 }
 
-// A wave per row (rows s >= 1, and the padding of the value rows), or several
-// rows per wave when rows are narrow, a lane per 8 consecutive columns;
-// grid-stride over rows.  ldzo is a multiple of 8; the
+// The rows s >= 1 and the padding of the value rows, a thread per 8 consecutive
+// columns of a row, grid-stride over the rows' chunks.  ldzo is a multiple of 8; the
 // vector path needs h_out to be one too (else every block takes the scalar path).
 template <typename TC, typename TZ>
 __device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* __restrict__ q,
                                               const TC* __restrict__ wt, long bx, long gx) {
-  const int lane = threadIdx.x & 63;
   const long nrows = (long)a.S * a.N;
-  const long wave0 = (bx * blockDim.x + threadIdx.x) >> 6;
-  const long nwaves = (gx * blockDim.x) >> 6;
   const bool vec = (a.h_out & 7) == 0;
   TZ* z = (TZ*)a.z;
-  // lpr lanes per row (8 columns each, a power of two covering the row); narrow
-  // rows give a wave several rows (rpw), so that its lanes are not idle
-  int lpr = 1;
-  while (lpr < 64 && lpr * 8 < a.ldzo) lpr *= 2;
-  const int rpw = 64 / lpr, sub = lane / lpr, cl = lane - sub * lpr;
-  for (long rb = wave0 * rpw; rb < nrows; rb += nwaves * rpw) {
-    const long r = rb + sub;
-    if (r >= nrows) continue;
+  // one 8-column chunk (row r, columns c0 .. c0+7) of the output
+  auto chunk = [&](long r, int c0) {
     const int s = (int)(r / a.N), p = (int)(r - (long)s * a.N);
     const bool lap = s == a.S - 1;
     const TC* trow = (const TC*)a.tab_t + (long)p * a.h_out;
-    for (int c0 = cl * 8; c0 < a.ldzo; c0 += 8 * lpr) {
-      TC zo[8], po[8];
-      if (s > 0 && vec && c0 + 8 <= a.h_out) {   // full block of real columns
-        TC t[8], w[8];
-        load8(trow + c0, t);
-        if (!lap) load8(wt + (long)(s - 1) * a.h_out + c0, w);
-        else load8(q + c0, w);
-#pragma unroll
-        for (int e = 0; e < 8; e++) {
-          const TC s1 = (TC)1 - t[e] * t[e];
-          zo[e] = lap ? (TC)-2 * t[e] * s1 * w[e] : s1 * w[e];
-          po[e] = lap ? (TC)0 : w[e];
-        }
-        store8(z + r * a.ldzo + c0, zo);
-        if (a.pre)
-#pragma unroll
-          for (int e = 0; e < 8; e++) ((TC*)a.pre)[r * a.ldp + c0 + e] = po[e];
-        if (lap && a.sq_out)
-#pragma unroll
-          for (int e = 0; e < 8; e++) ((TC*)a.sq_out)[(long)p * a.h_out + c0 + e] = w[e];
-        continue;
-      }
-      // padding, a block straddling h_out, or the value row's padding
+    TC zo[8], po[8];
+    if (s > 0 && vec && c0 + 8 <= a.h_out) {   // full block of real columns
+      TC t[8], w[8];
+      load8(trow + c0, t);
+      if (!lap) load8(wt + (long)(s - 1) * a.h_out + c0, w);
+      else load8(q + c0, w);
 #pragma unroll
       for (int e = 0; e < 8; e++) {
-        const int c = c0 + e;
-        if (s == 0 && c < a.h_out) continue;   // value row: from the products
-        TC zv = (c == a.h_out && s == 0) ? (TC)1 : (TC)0;
-        if (c < a.h_out) {
-          const TC t = trow[c];
-          const TC s1 = (TC)1 - t * t;
-          TC pv = 0;
-          if (!lap) {
-            pv = wt[(long)(s - 1) * a.h_out + c];
-            zv = s1 * pv;
-          } else {
-            zv = (TC)-2 * t * s1 * q[c];
-            if (a.sq_out) ((TC*)a.sq_out)[(long)p * a.h_out + c] = q[c];
-          }
-          if (a.pre) ((TC*)a.pre)[r * a.ldp + c] = pv;
-        }
-        z[r * a.ldzo + c] = cvt<TZ>((double)zv);
+        const TC s1 = (TC)1 - t[e] * t[e];
+        zo[e] = lap ? (TC)-2 * t[e] * s1 * w[e] : s1 * w[e];
+        po[e] = lap ? (TC)0 : w[e];
       }
+      store8(z + r * a.ldzo + c0, zo);
+      if (a.pre)
+#pragma unroll
+        for (int e = 0; e < 8; e++) ((TC*)a.pre)[r * a.ldp + c0 + e] = po[e];
+      if (lap && a.sq_out)
+#pragma unroll
+        for (int e = 0; e < 8; e++) ((TC*)a.sq_out)[(long)p * a.h_out + c0 + e] = w[e];
+      return;
+    }
+    // padding, a block straddling h_out, or the value row's padding
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int c = c0 + e;
+      if (s == 0 && c < a.h_out) continue;   // value row: from the products
+      TC zv = (c == a.h_out && s == 0) ? (TC)1 : (TC)0;
+      if (c < a.h_out) {
+        const TC t = trow[c];
+        const TC s1 = (TC)1 - t * t;
+        TC pv = 0;
+        if (!lap) {
+          pv = wt[(long)(s - 1) * a.h_out + c];
+          zv = s1 * pv;
+        } else {
+          zv = (TC)-2 * t * s1 * q[c];
+          if (a.sq_out) ((TC*)a.sq_out)[(long)p * a.h_out + c] = q[c];
+        }
+        if (a.pre) ((TC*)a.pre)[r * a.ldp + c] = pv;
+      }
+      z[r * a.ldzo + c] = cvt<TZ>((double)zv);
+    }
+  };
+  // The rows' 8-column chunks in one flat grid-stride sequence (consecutive lanes
+  // take consecutive chunks, across row ends), so that no lane idles on rows
+  // whose length is not a multiple of 512 columns.
+  const int cpr = (int)(a.ldzo / 8);
+  const long nq = nrows * cpr;
+  const long i0 = bx * blockDim.x + threadIdx.x, ni = gx * blockDim.x;
+  if (nq < 0x7fffffffL) {   // 32-bit index arithmetic
+    for (int i = (int)i0; i < (int)nq; i += (int)ni) {
+      const int r = i / cpr;
+      chunk(r, (i - r * cpr) * 8);
+    }
+  } else {
+    for (long i = i0; i < nq; i += ni) {
+      const long r = i / cpr;
+      chunk(r, (int)(i - r * cpr) * 8);
     }
   }
 }
@@ -1828,17 +1844,28 @@ static bool fwd_group_ok(const FwdLayerArgs& a) {
   return fwd_args_ok(a) && (a.h_out & 3) == 0 && (a.ldzo & 3) == 0 && !a.pre && !a.dirs;
 }
 
-bool make_fwd_job(const FwdLayerArgs& a0, int nch, const FwdLayerArgs& a1, FwdJob* j) {
+template <class G>
+static int geo_tiles(const FwdLayerArgs& a) {
+  return a.N > 0 ? ((a.N + G::BP - 1) / G::BP) * ((a.h_out + G::BN - 1) / G::BN) : 0;
+}
+
+bool make_fwd_job(const FwdLayerArgs& a0, int nch, const FwdLayerArgs& a1, int geo, FwdJob* j) {
   if (a0.N <= 0 || a1.N <= 0 || a1.has_lap || a1.value_only || a1.sparse_store ||
       a1.h_out != a0.h_out || a1.ldzo != a0.ldzo || a1.w != a0.w || nch < 1 || nch > kMaxChunks ||
-      !fwd_group_ok(a0) || !fwd_group_ok(a1))
+      geo < 0 || geo >= kFwdGeos || !fwd_group_ok(a0) || !fwd_group_ok(a1))
     return false;
   j->a0 = a0;
   j->a1 = a1;
-  j->t0 = fwd_tiles<M_BF16>(a0);
-  j->t1 = fwd_tiles<M_BF16>(a1);
+  j->t0 = geo == 0 ? geo_tiles<DGeo<M_BF16>>(a0) : geo == 1 ? geo_tiles<DGeoW128>(a0)
+                                                            : geo_tiles<DGeoW64>(a0);
+  j->t1 = geo == 0 ? geo_tiles<DGeo<M_BF16>>(a1) : geo == 1 ? geo_tiles<DGeoW128>(a1)
+                                                            : geo_tiles<DGeoW64>(a1);
   j->nch = nch;
   return true;
+}
+
+int fwd_geo_width(int geo) {
+  return geo == 0 ? DGeo<M_BF16>::BN : geo == 1 ? DGeoW128::BN : DGeoW64::BN;
 }
 
 bool make_fin_job(const FwdLayerArgs& a, int nch, FinJob* j) {
@@ -1868,9 +1895,15 @@ int fin_job_blocks(const FinJob& j) {
 int inq_job_blocks(const InQJob& j) { return (j.a.h_out + 63) / 64; }
 int loss_job_blocks(const LossJob& j) { return j.nbt; }
 
-hipError_t fwd_group(const FwdJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+hipError_t fwd_group(int geo, const FwdJob* jobs, const GroupBlk* blk, int nblk,
+                     hipStream_t st) {
   if (nblk <= 0) return hipSuccess;
-  k_fwdlap_group<bf16, true><<<nblk, DGeo<M_BF16>::NT, 0, st>>>(jobs, blk);
+  switch (geo) {
+    case 0: k_fwdlap_group<bf16, true, DGeo<M_BF16>><<<nblk, DGeo<M_BF16>::NT, 0, st>>>(jobs, blk); break;
+    case 1: k_fwdlap_group<bf16, true, DGeoW128><<<nblk, DGeoW128::NT, 0, st>>>(jobs, blk); break;
+    case 2: k_fwdlap_group<bf16, true, DGeoW64><<<nblk, DGeoW64::NT, 0, st>>>(jobs, blk); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 hipError_t fin_group(const FinJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {

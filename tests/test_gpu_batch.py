@@ -173,7 +173,7 @@ def forced_chunks_cache(b, data, path, nch):
     cols = list(zip(*[d[1] for d in data]))
     assert b.tune(thetas, *cols, cache_path=str(path)) > 0
     doc = json.loads(path.read_text())
-    assert doc["kfac_pinn_tune"] == 1 and doc["entries"]
+    assert doc["kfac_pinn_tune"] == 2 and doc["entries"]
     for e in doc["entries"]:
         e["nch"] = min(nch, e["S"] - 2)
     path.write_text(json.dumps(doc))
@@ -184,8 +184,9 @@ def forced_chunks_cache(b, data, path, nch):
 def test_batch_tune_cache_and_choices(tmp_path):
     """The tuner times every class once and writes them to its JSON cache; a second
     tune reads them back without timing.  A step after tuning takes the grouped
-    line search and succeeds on every instance; with the single-instance choice
-    forced for every class (nch 0 in the cache) it equals the single contexts."""
+    line search and succeeds on every instance; with the single-instance chunk
+    count forced for every class (nch 0 in the cache) and every class on one tile
+    geometry, each of the three, it equals the single contexts."""
     import json
     from paper_2405_15603_amd import HParams, KfacPinn, KfacPinnBatch
     dev = torch.device("cuda", 0)
@@ -198,30 +199,36 @@ def test_batch_tune_cache_and_choices(tmp_path):
     path = tmp_path / "tune.json"
     timed = b.tune(thetas, *cols, cache_path=str(path))
     doc = json.loads(path.read_text())
-    keys = {(e["K"], e["h_out"], e["S"]) for e in doc["entries"]}
+    keys = {(e["K"], e["h_out"], e["S"], e["value_only"]) for e in doc["entries"]}
     assert timed == len(keys) > 0
-    assert all(0 <= e["nch"] <= 8 for e in doc["entries"])
+    assert all(0 <= e["nch"] <= 8 and 0 <= e["geo"] <= 2 for e in doc["entries"])
+    assert any(e["value_only"] == 1 for e in doc["entries"])
     assert b.tune(thetas, *cols, cache_path=str(path)) == 0
     b.step(thetas, *cols, hp)
     torch.cuda.synchronize()
     assert b.is_grouped() and b.sync() == [0] * len(probs)
-    # every class at the single-instance choice: the results of kfac_pinn_step
-    for e in doc["entries"]:
-        e["nch"] = 0
-    path.write_text(json.dumps(doc))
-    b2 = KfacPinnBatch(probs, "bf16")
-    assert b2.tune(thetas, *cols, cache_path=str(path)) == 0
-    th2 = [d[0].clone() for d in data]
-    b2.step(th2, *cols, hp)
-    torch.cuda.synchronize()
-    assert b2.is_grouped() and b2.sync() == [0] * len(probs)
+    ref = []
     for k, p in enumerate(probs):
         th, (xi, yi, xb, yb) = inputs(p, dev)
         kp = KfacPinn.for_problem(p, "bf16")
         kp.step(th, xi, yi, xb, yb, hp)
         torch.cuda.synchronize()
-        assert torch.equal(th2[k], th), k
+        ref.append(th)
         del kp
+    # the single-instance chunk counts on each tile geometry: kfac_pinn_step's results
+    for geo in range(3):
+        for e in doc["entries"]:
+            e["nch"], e["geo"] = 0, geo
+        path.write_text(json.dumps(doc))
+        b2 = KfacPinnBatch(probs, "bf16")
+        assert b2.tune(thetas, *cols, cache_path=str(path)) == 0
+        th2 = [d[0].clone() for d in data]
+        b2.step(th2, *cols, hp)
+        torch.cuda.synchronize()
+        assert b2.is_grouped() and b2.sync() == [0] * len(probs)
+        for k in range(len(probs)):
+            assert torch.equal(th2[k], ref[k]), (geo, k)
+        del b2
 
 
 @pytest.mark.parametrize("forced_nch", [None, 1])
