@@ -372,7 +372,12 @@ kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
  * runs ONCE over every instance (job tables in device memory, made at creation
  * for the largest point counts and rewritten when the step's buffers or point
  * counts change), on lane 0 between the directions and the updates on the
- * lanes.  The results equal those of kfac_pinn_step on each instance.  The Jacobi warm start and its
+ * lanes.  With mixed curvature products (KP_MIXED_BF16, KP_MIXED_F16), stored
+ * slabs and both point sets non-empty, the factor and gradient products are
+ * grouped too: the curvature passes on the lanes leave them to one launch per
+ * (term, layer, product) over every instance plus one for its split-K
+ * reduction, on lane 0 before the inversion.  The results equal those of
+ * kfac_pinn_step on each instance.  The Jacobi warm start and its
  * periodic cold start are counted per batch step, and the sweeps used are read
  * with kfac_pinn_batch_get_sweeps (kfac_pinn_get_sweeps on an instance's
  * context reports only its own kfac_pinn_step/invert calls).  The work is
@@ -389,10 +394,11 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
 kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* batch);
 kp_status kfac_pinn_batch_context(kfac_pinn_batch* batch, int32_t k, kfac_pinn_ctx** out);
 kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* batch, int32_t enabled);
-/* The grouped line search (default 1) on or off (0: every instance's candidates
- * launch per instance on its lane, as kfac_pinn_step does); KP_ERR_ARG for other
- * values.  kfac_pinn_batch_is_grouped writes (host) whether the last batch step
- * took the grouped line search. */
+/* The grouped launches (default 1) on or off (0: every instance's factor
+ * products and line-search candidates launch per instance on its lane, as
+ * kfac_pinn_step does); KP_ERR_ARG for other values.  kfac_pinn_batch_is_grouped
+ * writes (host) which grouped launches the last batch step took: bit 0 the line
+ * search, bit 1 the factor and gradient products. */
 kp_status kfac_pinn_batch_set_grouped(kfac_pinn_batch* batch, int32_t enabled);
 kp_status kfac_pinn_batch_is_grouped(kfac_pinn_batch* batch, int32_t* out);
 /* Autotuning of the grouped line search (not in the paper).  Chooses, per class

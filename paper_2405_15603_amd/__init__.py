@@ -392,10 +392,18 @@ class KfacPinnBatch:
         N.check(self.lib.kfac_pinn_batch_set_grouped(self.h, 1 if enabled else 0),
                 "kfac_pinn_batch_set_grouped")
 
-    def is_grouped(self) -> bool:
+    def _grouped_bits(self) -> int:
         v = C.c_int32()
         N.check(self.lib.kfac_pinn_batch_is_grouped(self.h, C.byref(v)), "kfac_pinn_batch_is_grouped")
-        return bool(v.value)
+        return v.value
+
+    def is_grouped(self) -> bool:
+        """Whether the last step took the grouped line search."""
+        return bool(self._grouped_bits() & 1)
+
+    def grouped_products(self) -> bool:
+        """Whether the last step took the grouped factor and gradient products."""
+        return bool(self._grouped_bits() & 2)
 
     def step(self, thetas, xi, yi, xb, yb, hp: HParams, infos: Optional[torch.Tensor] = None):
         """One step of every instance; lists of tensors per instance.  `infos`

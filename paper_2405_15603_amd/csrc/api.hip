@@ -166,6 +166,9 @@ struct kfac_pinn_ctx {
   long jv_ld = 0;
   void* jvp_part = nullptr;
   int last_n[2] = {0, 0};   // point counts of the last curvature pass (interior, boundary)
+  // the batch's grouped factor products: the curvature pass leaves the products
+  // to a grouped launch over every instance
+  bool defer_products = false;
   // measurement: launches of one kernel class bracketed by events
   int tm_cls = -1;
   std::vector<hipEvent_t> tm_ev;
@@ -610,6 +613,7 @@ struct FactorGrad : LayerConsumer {
   int term, n, S;
   double beta;
   hipError_t operator()(int l, const void* zin, const void* g) override {
+    if (c->defer_products) return hipSuccess;
     hipError_t e;
     const LayerDesc& ld = c->nd.l[l];
     const int K = n * S;
@@ -1728,7 +1732,23 @@ struct kfac_pinn_batch {
   // (K, h_out, S, value rows only): the chunk count (0: the single-instance choice,
   // which gives the results of kfac_pinn_step) and the tile geometry (-1: by width).
   std::map<std::array<int, 4>, GroupChoice> tuned;
-  int grouped = 1;          // use the grouped line search when every instance qualifies
+  // Grouped factor and gradient products: per (term, layer, product) one launch
+  // of the split-K products over every instance and one of their reductions (in
+  // the order of the single-instance backward sweep), on lane 0 before the
+  // inversion; tables sized at creation, rewritten when point counts or beta change.
+  struct PTab {
+    GTab tn, red;
+    int weighted = 0;
+  };
+  struct Prod {
+    std::vector<PTab> pos;
+    char* dev = nullptr;
+    size_t cap = 0;
+    int mode = 0;
+    std::vector<uintptr_t> key;
+  } prod;
+  bool prod_active = false;
+  int grouped = 1;          // use the grouped launches when every instance qualifies
   bool grp_active = false;  // this step's choice
   std::vector<hipEvent_t> ev_pre;   // per lane: directions and momenta done
   hipEvent_t ev_ls = nullptr;       // grouped line search done (lane 0)
@@ -1776,6 +1796,101 @@ struct BatchArgs {
 // (offsets into it in g).  bound: sizes only, for the largest point counts (the
 // step's data pointers are not read).  False when an instance does not take the
 // paired BF16 line search these kernels cover.
+// Appends a job table and its workgroup list (largest jobs first: their tiles
+// start in the first rounds, the small ones fill the tail) to blob.
+void add_table(std::vector<char>& blob, kfac_pinn_batch::GTab& t, const void* jobs, size_t bytes,
+               const std::vector<int>& nblk) {
+  auto align = [&]() { blob.resize((blob.size() + 255) & ~(size_t)255); };
+  align();
+  t.jobs = blob.size();
+  t.njobs = (int)nblk.size();
+  blob.insert(blob.end(), (const char*)jobs, (const char*)jobs + bytes);
+  std::vector<int> order(nblk.size());
+  for (size_t j = 0; j < order.size(); j++) order[j] = (int)j;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nblk[x] > nblk[y]; });
+  std::vector<GroupBlk> bl;
+  for (int j : order)
+    for (int i = 0; i < nblk[j]; i++) bl.push_back(GroupBlk{j, i});
+  align();
+  t.blk = blob.size();
+  t.nblk = (int)bl.size();
+  blob.insert(blob.end(), (const char*)bl.data(), (const char*)(bl.data() + bl.size()));
+  align();
+}
+
+// The grouped factor and gradient products' tables (the arguments FactorGrad
+// passes for every instance, term and layer).  bound: sizes for the largest point
+// counts (every split count up to the cap).  False when an instance does not
+// qualify (mixed curvature products, stored slabs, both point sets).
+bool prod_build(kfac_pinn_batch* b, const int32_t* ni, const int32_t* nb, double beta, bool bound,
+                std::vector<char>& blob, kfac_pinn_batch::Prod& pr) {
+  const int n = (int)b->ctx.size();
+  const int L = b->ctx[0]->L, mode = b->ctx[0]->cmode;
+  if (mode != M_BF16X3 && mode != M_F16) return false;
+  for (kfac_pinn_ctx* c : b->ctx)
+    if (c->L != L || c->cmode != mode || !c->si.store || !c->sb.store) return false;
+  pr.mode = mode;
+  pr.pos.assign(2 * L * 3, kfac_pinn_batch::PTab{});
+  blob.clear();
+  std::vector<TnJob> tj(n);
+  std::vector<RedJob> rj(n);
+  std::vector<int> tnb(n), rnb(n);
+  for (int t = 0; t < 2; t++)
+    for (int l = L - 1; l >= 0; l--)
+      for (int kind = 0; kind < 3; kind++) {
+        for (int k = 0; k < n; k++) {
+          kfac_pinn_ctx* c = b->ctx[k];
+          const Slabs& s = t == 0 ? c->si : c->sb;
+          const int np = bound ? (t == 0 ? c->max_i : c->max_b) : (t == 0 ? ni[k] : nb[k]);
+          if (np <= 0) return false;
+          const LayerDesc& ld = c->nd.l[l];
+          const int K = np * s.S;
+          const float* zin = (const float*)s.zin_at(l);
+          const float* g = (const float*)s.g_at(l);
+          const double sa = t == 0 ? 1.0 / ((double)np * s.S) : 1.0 / np, sbf = 1.0 / np;
+          bool ok;
+          if (kind == 0) {
+            ok = make_tn_job(mode, zin, c->ldz[l], zin, c->ldz[l], ld.h_in + 1, ld.h_in + 1, K,
+                             nullptr, np, true, (float*)c->part, kMaxSplits, c->wsc, &tj[k], &tnb[k]);
+            rj[k] = make_red_job(tj[k], c->F[t][0][l], ld.h_in + 1, 1, (1.0 - beta) * sa, beta,
+                                 &rnb[k]);
+          } else if (kind == 1) {
+            ok = make_tn_job(mode, g, c->ldg[l], g, c->ldg[l], ld.h_out, ld.h_out, K, nullptr, np,
+                             true, (float*)c->part, kMaxSplits, c->wsc, &tj[k], &tnb[k]);
+            rj[k] = make_red_job(tj[k], c->F[t][1][l], ld.h_out, 1, (1.0 - beta) * sbf, beta,
+                                 &rnb[k]);
+          } else {
+            ok = make_tn_job(mode, g, c->ldg[l], zin, c->ldz[l], ld.h_out, ld.h_in + 1, K, s.rf, np,
+                             false, (float*)c->part, kMaxSplits, c->wsc, &tj[k], &tnb[k]);
+            rj[k] = make_red_job(tj[k], c->grad + ld.off, 1, ld.h_out, 1.0 / np,
+                                 t == 0 ? 0.0 : 1.0, &rnb[k]);
+          }
+          if (!ok) return false;
+          // sizes at creation: a smaller point count may take more splits
+          if (bound) tnb[k] = 8 * (tj[k].sym ? tj[k].ntm * (tj[k].ntm + 1) / 2 : tj[k].ntm * tj[k].ntn) *
+                              kp_cdiv(kMaxSplits, 8);
+        }
+        kfac_pinn_batch::PTab& p = pr.pos[(t * L + (L - 1 - l)) * 3 + kind];
+        p.weighted = kind == 2;
+        add_table(blob, p.tn, tj.data(), sizeof(TnJob) * n, tnb);
+        add_table(blob, p.red, rj.data(), sizeof(RedJob) * n, rnb);
+      }
+  return true;
+}
+
+kp_status prod_run(kfac_pinn_batch* b, hipStream_t st) {
+  const kfac_pinn_batch::Prod& pr = b->prod;
+  char* d = pr.dev;
+  for (const kfac_pinn_batch::PTab& p : pr.pos) {
+    const TnJob* tj = (const TnJob*)(d + p.tn.jobs);
+    if (p.weighted && pr.mode == M_F16) KP_TRY(row_scale_group(tj, p.tn.njobs, st));
+    KP_TRY(tn_group(pr.mode, p.weighted != 0, tj, (const GroupBlk*)(d + p.tn.blk), p.tn.nblk, st));
+    KP_TRY(reduce_group((const RedJob*)(d + p.red.jobs), (const GroupBlk*)(d + p.red.blk),
+                        p.red.nblk, st));
+  }
+  return KP_OK;
+}
+
 typedef std::map<std::array<int, 4>, GroupChoice> ChoiceMap;
 std::array<int, 4> group_class(const FwdLayerArgs& a) { return {a.K, a.h_out, a.S, a.value_only}; }
 
@@ -1861,26 +1976,8 @@ bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector
     nlo[k] = lo[k].nbt;
   }
   blob.clear();
-  auto align = [&]() { blob.resize((blob.size() + 255) & ~(size_t)255); };
-  // jobs, then the workgroup list with the largest jobs first (their tiles start
-  // in the first rounds, the small ones fill the tail)
   auto add = [&](kfac_pinn_batch::GTab& t, const void* jobs, size_t bytes,
-                 const std::vector<int>& nblk) {
-    align();
-    t.jobs = blob.size();
-    t.njobs = (int)nblk.size();
-    blob.insert(blob.end(), (const char*)jobs, (const char*)jobs + bytes);
-    std::vector<int> order(nblk.size());
-    for (size_t j = 0; j < order.size(); j++) order[j] = (int)j;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nblk[x] > nblk[y]; });
-    std::vector<GroupBlk> bl;
-    for (int j : order)
-      for (int i = 0; i < nblk[j]; i++) bl.push_back(GroupBlk{j, i});
-    align();
-    t.blk = blob.size();
-    t.nblk = (int)bl.size();
-    blob.insert(blob.end(), (const char*)bl.data(), (const char*)(bl.data() + bl.size()));
-  };
+                 const std::vector<int>& nblk) { add_table(blob, t, jobs, bytes, nblk); };
   add(g.axpy, ax.data(), sizeof(AxpyJob) * n, nax);
   add(g.prep, pw.data(), sizeof(PrepJob) * n, npw);
   add(g.slab, sl.data(), sizeof(SlabJob) * 2 * n, nsl);
@@ -1903,7 +2000,6 @@ bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector
   add(g.inq, iq.data(), sizeof(InQJob) * n, niq);
   add(g.inrows, ir.data(), sizeof(InRowsJob) * n, nir);
   add(g.loss, lo.data(), sizeof(LossJob) * n, nlo);
-  align();
   return true;
 }
 
@@ -2209,6 +2305,10 @@ kp_status batch_tune(kfac_pinn_batch* b, const BatchArgs& a, const char* cache_p
 kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a) {
   const int nl = (int)b->lanes.size();
   if (phase == 1) {
+    if (b->prod_active) {
+      kp_status s = prod_run(b, b->lanes[0]);
+      if (s != KP_OK) return s;
+    }
     int cap = 1;
     for (const kfac_pinn_ctx* c : b->ctx) cap = std::max(cap, c->max_sweeps);
     KP_TRY(kron_eig_batched(b->probs.data(), (int)b->probs.size(), a.hp->lambda, b->probs_dev,
@@ -2219,12 +2319,17 @@ kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
   if (phase == 3) return group_ls(b, a.hp, b->lanes[0]);
   const int part = phase == 2 ? (b->grp_active ? 0 : -1) : 2;
   for (size_t k = l; k < b->ctx.size(); k += nl) {
-    kp_status s =
-        phase == 0
-            ? step_head(b->ctx[k], a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k],
-                        a.nb[k], a.hp)
-            : step_tail(b->ctx[k], a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k],
-                        a.nb[k], a.hp, a.infos ? a.infos + k : nullptr, part);
+    kfac_pinn_ctx* c = b->ctx[k];
+    kp_status s;
+    if (phase == 0) {
+      // with the grouped products the curvature passes leave them to phase 1
+      c->defer_products = b->prod_active;
+      s = step_head(c, a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k], a.nb[k], a.hp);
+      c->defer_products = false;
+    } else {
+      s = step_tail(c, a.thetas[k], a.xi[k], a.yi[k], a.ni[k], a.xb[k], a.yb[k], a.nb[k], a.hp,
+                    a.infos ? a.infos + k : nullptr, part);
+    }
     if (s != KP_OK) return s;
   }
   return KP_OK;
@@ -2320,11 +2425,15 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
       hipDeviceSynchronize() != hipSuccess)
     return fail(KP_ERR_HIP);
   {
-    // the grouped line search's tables, sized for the largest point counts
+    // the grouped line search's and products' tables, sized for the largest point counts
     std::vector<char> blob;
     if (group_build(b, nullptr, true, blob, b->grp)) {
       if (hipMalloc((void**)&b->grp.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
       b->grp.cap = blob.size();
+    }
+    if (prod_build(b, nullptr, nullptr, 0.0, true, blob, b->prod)) {
+      if (hipMalloc((void**)&b->prod.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
+      b->prod.cap = blob.size();
     }
   }
   *out = b;
@@ -2341,6 +2450,7 @@ kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   if (b->eig_ids) (void)hipFree(b->eig_ids);
   if (b->eig_ctl) (void)hipFree(b->eig_ctl);
   if (b->grp.dev) (void)hipFree(b->grp.dev);
+  if (b->prod.dev) (void)hipFree(b->prod.dev);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->ev_head) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->ev_pre) (void)hipEventDestroy(e);
@@ -2406,7 +2516,7 @@ kp_status kfac_pinn_batch_tune(kfac_pinn_batch* b, void* const* thetas, const vo
 
 kp_status kfac_pinn_batch_is_grouped(kfac_pinn_batch* b, int32_t* out) {
   KP_ARG(b && out, "null argument");
-  *out = b->grp_active ? 1 : 0;
+  *out = (b->grp_active ? 1 : 0) | (b->prod_active ? 2 : 0);
   return KP_OK;
 }
 
@@ -2470,8 +2580,40 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
       }
     }
   }
+  // The grouped products need valid point counts and beta (their tables hold the
+  // EMA weights); an invalid argument is reported by the instance's head.
+  b->prod_active = false;
+  if (b->grouped && b->prod.dev && hp->beta >= 0.0 && hp->beta < 1.0) {
+    std::vector<uintptr_t> pkey;
+    bool valid = true;
+    for (int k = 0; k < n && valid; k++) {
+      valid = n_int[k] > 0 && n_int[k] <= b->ctx[k]->max_i && n_bnd[k] > 0 &&
+              n_bnd[k] <= b->ctx[k]->max_b;
+      pkey.push_back((uintptr_t)n_int[k]);
+      pkey.push_back((uintptr_t)n_bnd[k]);
+    }
+    uint64_t bb = 0;
+    memcpy(&bb, &hp->beta, sizeof bb);
+    pkey.push_back((uintptr_t)bb);
+    if (valid && pkey == b->prod.key) {
+      b->prod_active = true;
+    } else if (valid) {
+      std::vector<char> blob;
+      kfac_pinn_batch::Prod pr = b->prod;
+      if (prod_build(b, n_int, n_bnd, hp->beta, false, blob, pr) && blob.size() <= b->prod.cap) {
+        KP_TRY(hipStreamSynchronize(b->lanes[0]));
+        KP_TRY(hipMemcpy(b->prod.dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        pr.dev = b->prod.dev;
+        pr.cap = b->prod.cap;
+        pr.key = pkey;
+        b->prod = pr;
+        b->prod_active = true;
+      }
+    }
+  }
   key.push_back((uintptr_t)infos);
   key.push_back((uintptr_t)b->grp_active);
+  key.push_back((uintptr_t)b->prod_active);
   {
     const unsigned char* hb = (const unsigned char*)hp;
     for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);

@@ -45,8 +45,9 @@ __device__ __forceinline__ double load_frag<double>(const double* base, int lane
 // round-robin by linear id: block b runs on XCD b % 8 as that XCD's (b / 8)-th
 // block, and XCD x takes splits x, x + 8, ... in turn, all tiles of each.
 // False for blocks past the last split (no rows).
-__device__ __forceinline__ bool tn_block(int ntiles, int kchunk, int K, int& t, int& split) {
-  const int b = blockIdx.x, x = b & 7, i = b >> 3;
+__device__ __forceinline__ bool tn_block(int ntiles, int kchunk, int K, int& t, int& split,
+                                         int b = blockIdx.x) {
+  const int x = b & 7, i = b >> 3;
   split = x + 8 * (i / ntiles);
   t = i % ntiles;
   return (long)split * kchunk < K;
@@ -235,8 +236,8 @@ __device__ __forceinline__ int x3_pos(int col, int chunk) {
 
 // wsc[0] = 2^-e and wsc[1] = 2^e with max_i |rw[i]| < 2^e (1 and 1 when the weights
 // are all zero or not finite): the scaling that keeps FP16 row weights within 1.
-__global__ __launch_bounds__(256) void k_row_scale(const float* __restrict__ rw, int n,
-                                                   float* __restrict__ wsc) {
+__device__ __forceinline__ void row_scale_at(const float* __restrict__ rw, int n,
+                                             float* __restrict__ wsc) {
   __shared__ float part[4];
   float m = 0.0f;
   for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(rw[i]));
@@ -255,16 +256,19 @@ __global__ __launch_bounds__(256) void k_row_scale(const float* __restrict__ rw,
   wsc[0] = s;
   wsc[1] = u;
 }
+__global__ __launch_bounds__(256) void k_row_scale(const float* __restrict__ rw, int n,
+                                                   float* __restrict__ wsc) {
+  row_scale_at(rw, n, wsc);
+}
 
 // X3 = false: the single-pass FP16 variant (one FP16 plane, one MFMA per
 // product) with the same tiles, loads and LDS layout.
-template <bool WEIGHTED, bool X3 = true>
-__global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long lda,
-                                               const float* __restrict__ B, long ldb, int M,
-                                               int N, int K, const float* __restrict__ rw,
-                                               int rmod, int sym, int ntm, int ntn, int kchunk,
-                                               float* __restrict__ part,
-                                               const float* __restrict__ wsc) {
+template <bool WEIGHTED, bool X3>
+__device__ __forceinline__ void tn_x3_at(const float* __restrict__ A, long lda,
+                                         const float* __restrict__ B, long ldb, int M, int N,
+                                         int K, const float* __restrict__ rw, int rmod, int sym,
+                                         int ntm, int ntn, int kchunk, float* __restrict__ part,
+                                         const float* __restrict__ wsc, int blk) {
   typedef typename std::conditional<X3, bf16, f16>::type TL;
   typedef typename std::conditional<X3, bf16x4, f16x4>::type TL4;
   typedef typename std::conditional<X3, bf16x8, f16x8>::type TL8;
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
   int ti, tj, split;
   {
     int t;
-    if (!tn_block(sym ? ntm * (ntm + 1) / 2 : ntm * ntn, kchunk, K, t, split)) return;
+    if (!tn_block(sym ? ntm * (ntm + 1) / 2 : ntm * ntn, kchunk, K, t, split, blk)) return;
     if (sym) {
       ti = 0;
       int rowlen = ntm;
@@ -417,6 +421,16 @@ __global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long
       }
     }
 }
+template <bool WEIGHTED, bool X3 = true>
+__global__ __launch_bounds__(256) void k_tn_x3(const float* __restrict__ A, long lda,
+                                               const float* __restrict__ B, long ldb, int M,
+                                               int N, int K, const float* __restrict__ rw,
+                                               int rmod, int sym, int ntm, int ntn, int kchunk,
+                                               float* __restrict__ part,
+                                               const float* __restrict__ wsc) {
+  tn_x3_at<WEIGHTED, X3>(A, lda, B, ldb, M, N, K, rw, rmod, sym, ntm, ntn, kchunk, part, wsc,
+                         blockIdx.x);
+}
 
 template <int MODE>
 static void launch_tn(dim3 g, const void* A, long lda, const void* B, long ldb, int M, int N, int K,
@@ -485,10 +499,9 @@ hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long
 }
 
 template <typename TP>
-__global__ void k_reduce_splitk(const TP* __restrict__ part, int splits, int M, int N, int sym,
-                                double* __restrict__ out, long so_m, long so_n, double alpha,
-                                double c_prev) {
-  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void reduce_at(const TP* __restrict__ part, int splits, int M, int N,
+                                          int sym, double* __restrict__ out, long so_m, long so_n,
+                                          double alpha, double c_prev, long idx) {
   if (idx >= (long)M * N) return;
   int m = (int)(idx / N), n = (int)(idx % N);
   if (sym && n < m) return;
@@ -501,6 +514,107 @@ __global__ void k_reduce_splitk(const TP* __restrict__ part, int splits, int M, 
     double* o2 = out + n * so_m + m * so_n;
     *o2 = v;   // the lower triangle equals the upper triangle before and after the update
   }
+}
+template <typename TP>
+__global__ void k_reduce_splitk(const TP* __restrict__ part, int splits, int M, int N, int sym,
+                                double* __restrict__ out, long so_m, long so_n, double alpha,
+                                double c_prev) {
+  reduce_at<TP>(part, splits, M, N, sym, out, so_m, so_n, alpha, c_prev,
+                (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped factor and gradient products (see GroupBlk): the split-K products of
+// many instances in one launch, their reductions in another; the same bodies,
+// split counts and tile orders as the single-instance launches.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)p;
+#else
+  return *p;   // the host pass only parses device code
+#endif
+}
+
+template <bool WEIGHTED, bool X3>
+__global__ __launch_bounds__(256) void k_tn_x3_group(const TnJob* __restrict__ jobs,
+                                                     const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const TnJob j = ld_uniform(jobs + g.job);
+  tn_x3_at<WEIGHTED, X3>(j.A, j.lda, j.B, j.ldb, j.M, j.N, j.K, j.rw, j.rmod, j.sym, j.ntm, j.ntn,
+                         j.kchunk, j.part, j.wsc, g.local);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_group(const RedJob* __restrict__ jobs,
+                                                      const GroupBlk* __restrict__ blk) {
+  const GroupBlk g = ld_uniform(blk + blockIdx.x);
+  const RedJob j = ld_uniform(jobs + g.job);
+  reduce_at<float>(j.part, j.splits, j.M, j.N, j.sym, j.out, j.so_m, j.so_n, j.alpha, j.c_prev,
+                   (long)g.local * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_row_scale_group(const TnJob* __restrict__ jobs) {
+  const TnJob j = ld_uniform(jobs + blockIdx.x);
+  row_scale_at(j.rw, j.rmod, j.wsc);
+}
+
+bool make_tn_job(int mode, const float* A, long lda, const float* B, long ldb, int M, int N, int K,
+                 const float* rwf, int rmod, bool sym, float* part, int max_splits, float* wsc,
+                 TnJob* j, int* nblk) {
+  if ((mode != M_BF16X3 && mode != M_F16) || M <= 0 || N <= 0 || K <= 0 ||
+      (rwf && mode == M_F16 && !wsc))
+    return false;
+  // the split count and grid of gemm_tn_splitk
+  const int BT = 128, BK = 32;
+  const int ntm = kp_cdiv(M, BT), ntn = kp_cdiv(N, BT);
+  const int ntiles = sym ? ntm * (ntm + 1) / 2 : ntm * ntn;
+  int splits = kp_cdiv(1024, ntiles);
+  int max_by_k = kp_cdiv(K, 8 * BK);
+  if (splits > max_by_k) splits = max_by_k;
+  if (splits > max_splits) splits = max_splits;
+  if (splits < 1) splits = 1;
+  if (splits > 8) splits = std::min(max_splits, (int)kp_roundup(splits, 8));
+  const int kchunk = (int)kp_roundup(kp_cdiv(K, splits), BK);
+  splits = kp_cdiv(K, kchunk);
+  if (splits < 1) splits = 1;
+  *j = TnJob{A, lda, B, ldb, M, N, K, rwf, rmod, sym ? 1 : 0, ntm, ntn, kchunk, part,
+             mode == M_F16 ? wsc : nullptr, splits};
+  *nblk = 8 * ntiles * kp_cdiv(splits, 8);
+  return true;
+}
+
+RedJob make_red_job(const TnJob& t, double* out, long so_m, long so_n, double alpha,
+                    double c_prev, int* nblk) {
+  *nblk = kp_cdiv((long)t.M * t.N, 256);
+  return RedJob{t.part, t.splits, t.M, t.N, t.sym, out, so_m, so_n, alpha, c_prev};
+}
+
+hipError_t tn_group(int mode, bool weighted, const TnJob* jobs, const GroupBlk* blk, int nblk,
+                    hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  if (mode == M_BF16X3) {
+    if (weighted) k_tn_x3_group<true, true><<<nblk, 256, 0, st>>>(jobs, blk);
+    else k_tn_x3_group<false, true><<<nblk, 256, 0, st>>>(jobs, blk);
+  } else if (mode == M_F16) {
+    if (weighted) k_tn_x3_group<true, false><<<nblk, 256, 0, st>>>(jobs, blk);
+    else k_tn_x3_group<false, false><<<nblk, 256, 0, st>>>(jobs, blk);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t row_scale_group(const TnJob* jobs, int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  k_row_scale_group<<<njobs, 256, 0, st>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t reduce_group(const RedJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  k_reduce_group<<<nblk, 256, 0, st>>>(jobs, blk);
+  return hipGetLastError();
 }
 
 hipError_t reduce_splitk(int mode, const void* part, int splits, int M, int N, bool sym,

@@ -22,6 +22,41 @@ hipError_t gemm_tn_splitk(int mode, const void* A, long lda, const void* B, long
                           int K, const double* rw, const float* rwf, int rmod, bool sym,
                           void* part, int max_splits, int* splits_out, hipStream_t st,
                           float* wsc = nullptr);
+// Grouped factor and gradient products (GroupBlk below): a job holds the
+// arguments of one split-K product of the mixed modes (M_BF16X3, M_F16; FP32
+// operands, FP32 partial sums), with the split count and grid gemm_tn_splitk
+// chooses; the reduction job sums its partials as reduce_splitk does.  The
+// FP16 weighted product needs its row scale (row_scale_group) first.
+struct TnJob {
+  const float* A;
+  long lda;
+  const float* B;
+  long ldb;
+  int M, N, K;
+  const float* rw;   // FP32 row weights (nullptr: unweighted)
+  int rmod, sym, ntm, ntn, kchunk;
+  float* part;
+  float* wsc;        // FP16: the row-weight scale (2 floats)
+  int splits;
+};
+struct RedJob {
+  const float* part;
+  int splits, M, N, sym;
+  double* out;
+  long so_m, so_n;
+  double alpha, c_prev;
+};
+struct GroupBlk;
+bool make_tn_job(int mode, const float* A, long lda, const float* B, long ldb, int M, int N, int K,
+                 const float* rwf, int rmod, bool sym, float* part, int max_splits, float* wsc,
+                 TnJob* j, int* nblk);
+RedJob make_red_job(const TnJob& t, double* out, long so_m, long so_n, double alpha,
+                    double c_prev, int* nblk);
+hipError_t tn_group(int mode, bool weighted, const TnJob* jobs, const GroupBlk* blk, int nblk,
+                    hipStream_t st);
+hipError_t row_scale_group(const TnJob* jobs, int njobs, hipStream_t st);
+hipError_t reduce_group(const RedJob* jobs, const GroupBlk* blk, int nblk, hipStream_t st);
+
 // out[m*so_m + n*so_n] = c_prev*out + alpha * sum_s part[s][m*N+n]  (double out);
 // with sym the lower triangle is mirrored from the upper.
 hipError_t reduce_splitk(int mode, const void* part, int splits, int M, int N, bool sym,

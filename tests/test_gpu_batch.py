@@ -53,7 +53,7 @@ def test_batch_matches_single_contexts(use_graph, grouped):
     for it in range(steps):
         b.step(thetas, *cols, hp, infos)
         torch.cuda.synchronize()
-        assert b.is_grouped() == grouped
+        assert b.is_grouped() == grouped and b.grouped_products() == grouped
         # unrelated eager work between replays
         junk = torch.randn(1 << 20, device=dev)
         (junk * 2).sum().item()
@@ -122,7 +122,7 @@ def test_grouped_line_search_with_new_point_counts():
                 cols.append((xi[:ni], yi[:ni], xb[:nb], yb[:nb]))
             b.step(thetas, *list(zip(*cols)), hp)
             torch.cuda.synchronize()
-            assert b.is_grouped()
+            assert b.is_grouped() and b.grouped_products()
             for k, kp in enumerate(refs):
                 kp.step(ref_th[k], *cols[k], hp)
             torch.cuda.synchronize()
@@ -150,6 +150,8 @@ def test_grouped_line_search_fallbacks():
         b.step(thetas, *cols, hp)
         torch.cuda.synchronize()
         assert not b.is_grouped()
+        # the factor products stay grouped with a fixed step (mixed curvature products)
+        assert b.grouped_products() == (precision == "bf16")
         assert b.sync() == [0] * len(probs)
         for k, p in enumerate(probs):
             th, (xi, yi, xb, yb) = inputs(p, dev)
