@@ -1376,7 +1376,8 @@ __device__ __forceinline__ void load8(const TC* src, TC (&v)[8]) {
 }
 
 // The rows s >= 1 and the padding of the value rows, a thread per 8 consecutive
-// columns of a row, grid-stride over the rows' chunks.  ldzo is a multiple of 8; the
+// columns of a row, grid-stride over rows (wide rows) or over the rows' chunks
+// (narrow rows).  ldzo is a multiple of 8; the
 // vector path needs h_out to be one too (else every block takes the scalar path).
 template <typename TC, typename TZ>
 __device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* __restrict__ q,
@@ -1384,9 +1385,8 @@ __device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* _
   const long nrows = (long)a.S * a.N;
   const bool vec = (a.h_out & 7) == 0;
   TZ* z = (TZ*)a.z;
-  // one 8-column chunk (row r, columns c0 .. c0+7) of the output
-  auto chunk = [&](long r, int c0) {
-    const int s = (int)(r / a.N), p = (int)(r - (long)s * a.N);
+  // one 8-column chunk (row r = s N + p, columns c0 .. c0+7) of the output
+  auto chunk = [&](long r, int s, int p, int c0) {
     const bool lap = s == a.S - 1;
     const TC* trow = (const TC*)a.tab_t + (long)p * a.h_out;
     TC zo[8], po[8];
@@ -1432,21 +1432,32 @@ __device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* _
       z[r * a.ldzo + c] = cvt<TZ>((double)zv);
     }
   };
-  // The rows' 8-column chunks in one flat grid-stride sequence (consecutive lanes
-  // take consecutive chunks, across row ends), so that no lane idles on rows
-  // whose length is not a multiple of 512 columns.
+  // Wide rows: a wave per row, 512 columns per pass.  Narrow rows (at most 256
+  // columns, where a wave per row would leave lanes idle): the rows' 8-column
+  // chunks in one flat grid-stride sequence (consecutive lanes take consecutive
+  // chunks, across row ends).
+  if (a.ldzo > 256) {
+    const int lane = threadIdx.x & 63;
+    const long nwaves = (gx * blockDim.x) >> 6;
+    for (long r = (bx * blockDim.x + threadIdx.x) >> 6; r < nrows; r += nwaves) {
+      const int s = (int)(r / a.N), p = (int)(r - (long)s * a.N);
+      for (int c0 = lane * 8; c0 < a.ldzo; c0 += 512) chunk(r, s, p, c0);
+    }
+    return;
+  }
   const int cpr = (int)(a.ldzo / 8);
   const long nq = nrows * cpr;
   const long i0 = bx * blockDim.x + threadIdx.x, ni = gx * blockDim.x;
   if (nq < 0x7fffffffL) {   // 32-bit index arithmetic
     for (int i = (int)i0; i < (int)nq; i += (int)ni) {
-      const int r = i / cpr;
-      chunk(r, (i - r * cpr) * 8);
+      const int r = i / cpr, s = r / a.N;
+      chunk(r, s, r - s * a.N, (i - r * cpr) * 8);
     }
   } else {
     for (long i = i0; i < nq; i += ni) {
       const long r = i / cpr;
-      chunk(r, (int)(i - r * cpr) * 8);
+      const int s = (int)(r / a.N);
+      chunk(r, s, (int)(r - (long)s * a.N), (int)(i - r * cpr) * 8);
     }
   }
 }
