@@ -371,8 +371,8 @@ kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
  * sets non-empty), the line search is grouped: each of a candidate's kernels
  * runs ONCE over every instance (job tables in device memory, made at creation
  * for the largest point counts and rewritten when the step's buffers or point
- * counts change), on lane 0 between the directions and the updates on the
- * lanes.  With mixed curvature products (KP_MIXED_BF16, KP_MIXED_F16), stored
+ * counts change), on lanes 0 and 1 (even and odd candidates) between the
+ * directions and the updates on the lanes.  With mixed curvature products (KP_MIXED_BF16, KP_MIXED_F16), stored
  * slabs and both point sets non-empty, the factor and gradient products are
  * grouped too: the curvature passes on the lanes leave them to one launch per
  * (term, layer, product) over every instance plus one for its split-K
@@ -398,7 +398,9 @@ kp_status kfac_pinn_batch_set_graph(kfac_pinn_batch* batch, int32_t enabled);
  * products and line-search candidates launch per instance on its lane, as
  * kfac_pinn_step does); KP_ERR_ARG for other values.  kfac_pinn_batch_is_grouped
  * writes (host) which grouped launches the last batch step took: bit 0 the line
- * search, bit 1 the factor and gradient products. */
+ * search, bit 1 the factor and gradient products, bit 2 the line search on two
+ * lanes (odd candidates on lane 1 with each instance's second line-search
+ * buffers, made at creation). */
 kp_status kfac_pinn_batch_set_grouped(kfac_pinn_batch* batch, int32_t enabled);
 kp_status kfac_pinn_batch_is_grouped(kfac_pinn_batch* batch, int32_t* out);
 /* Autotuning of the grouped line search (not in the paper).  Chooses, per class

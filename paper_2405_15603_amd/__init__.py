@@ -401,6 +401,10 @@ class KfacPinnBatch:
         """Whether the last step took the grouped line search."""
         return bool(self._grouped_bits() & 1)
 
+    def grouped_two_lanes(self) -> bool:
+        """Whether the last step's grouped line search ran on two lanes."""
+        return bool(self._grouped_bits() & 4)
+
     def grouped_products(self) -> bool:
         """Whether the last step took the grouped factor and gradient products."""
         return bool(self._grouped_bits() & 2)

@@ -1727,7 +1727,7 @@ struct kfac_pinn_batch {
     char* dev = nullptr;
     size_t cap = 0;
     std::vector<uintptr_t> key;   // the step arguments the tables were built for
-  } grp;
+  } grp, grp1;   // grp1: the instances' second line-search buffers (odd candidates, lane 1)
   // Choices of the grouped layer products made by kfac_pinn_batch_tune, per class
   // (K, h_out, S, value rows only): the chunk count (0: the single-instance choice,
   // which gives the results of kfac_pinn_step) and the tile geometry (-1: by width).
@@ -1750,10 +1750,12 @@ struct kfac_pinn_batch {
   bool prod_active = false;
   int grouped = 1;          // use the grouped launches when every instance qualifies
   bool grp_active = false;  // this step's choice
+  bool grp_two = false;     // with the odd candidates on lane 1
   std::vector<hipEvent_t> ev_pre;   // per lane: directions and momenta done
   hipEvent_t ev_ls = nullptr;       // grouped line search done (lane 0)
+  hipEvent_t ev_ls1 = nullptr;      // its odd candidates done (lane 1)
   std::vector<hipGraphExec_t> exec_fin;
-  hipGraphExec_t exec_ls = nullptr;
+  hipGraphExec_t exec_ls = nullptr, exec_ls1 = nullptr;
 };
 
 namespace {
@@ -1769,6 +1771,7 @@ void batch_drop_graph(kfac_pinn_batch* b) {
     if (e) (void)hipGraphExecDestroy(e);
   if (b->exec_eig) (void)hipGraphExecDestroy(b->exec_eig);
   if (b->exec_ls) (void)hipGraphExecDestroy(b->exec_ls);
+  if (b->exec_ls1) (void)hipGraphExecDestroy(b->exec_ls1);
   for (hipGraph_t g : b->graph)
     if (g) (void)hipGraphDestroy(g);
   b->exec_head.clear();
@@ -1776,6 +1779,7 @@ void batch_drop_graph(kfac_pinn_batch* b) {
   b->exec_fin.clear();
   b->exec_eig = nullptr;
   b->exec_ls = nullptr;
+  b->exec_ls1 = nullptr;
   b->graph.clear();
   b->key.clear();
 }
@@ -1902,8 +1906,23 @@ int default_geo(int h_out) {
   return best;
 }
 
+bool group_build_set(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector<char>& blob,
+                     kfac_pinn_batch::Group& g, const ChoiceMap* over);
+
+// set 1: the tables over the instances' second line-search buffers
 bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector<char>& blob,
-                 kfac_pinn_batch::Group& g, const ChoiceMap* over = nullptr) {
+                 kfac_pinn_batch::Group& g, const ChoiceMap* over = nullptr, int set = 0) {
+  if (set == 0) return group_build_set(b, a, bound, blob, g, over);
+  for (kfac_pinn_ctx* c : b->ctx)
+    if (!c->ls1.ready) return false;
+  for (kfac_pinn_ctx* c : b->ctx) ls_lane_swap(c);
+  const bool ok = group_build_set(b, a, bound, blob, g, over);
+  for (kfac_pinn_ctx* c : b->ctx) ls_lane_swap(c);
+  return ok;
+}
+
+bool group_build_set(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector<char>& blob,
+                     kfac_pinn_batch::Group& g, const ChoiceMap* over) {
   if (!over) over = &b->tuned;
   const int n = (int)b->ctx.size();
   const int L = b->ctx[0]->L;
@@ -2006,13 +2025,15 @@ bool group_build(kfac_pinn_batch* b, const BatchArgs* a, bool bound, std::vector
 // The grid line search of every instance, each kernel of a candidate one launch
 // over all instances (the instances' own buffers, as their single-instance
 // launches use them; the same kernels' bodies, so the losses are the same).
-kp_status group_ls(kfac_pinn_batch* b, const kp_hparams* hp, hipStream_t st) {
-  const kfac_pinn_batch::Group& g = b->grp;
+// parity < 0: every candidate on the tables of set 0; 0 / 1: the even / odd
+// candidates on the tables of set 0 / 1.
+kp_status group_ls(kfac_pinn_batch* b, const kp_hparams* hp, hipStream_t st, int parity = -1) {
+  const kfac_pinn_batch::Group& g = parity == 1 ? b->grp1 : b->grp;
   char* d = g.dev;
   auto blk = [&](const kfac_pinn_batch::GTab& t) { return (const GroupBlk*)(d + t.blk); };
   const int ncand = hp->grid_max_exp - hp->grid_min_exp + 1;
   const int L = (int)g.fwd.size() + 1;
-  for (int k = 0; k < ncand; k++) {
+  for (int k = parity < 0 ? 0 : parity; k < ncand; k += parity < 0 ? 1 : 2) {
     const double alpha = ldexp(1.0, hp->grid_max_exp - k);
     KP_TRY(axpy_group((const AxpyJob*)(d + g.axpy.jobs), blk(g.axpy), g.axpy.nblk, alpha, st));
     KP_TRY(prep_group((const PrepJob*)(d + g.prep.jobs), blk(g.prep), g.prep.nblk, st));
@@ -2316,7 +2337,10 @@ kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
                             b->lanes[0]));
     return KP_OK;
   }
-  if (phase == 3) return group_ls(b, a.hp, b->lanes[0]);
+  // the grouped line search: all candidates on lane 0, or the even ones there and
+  // the odd ones on lane 1 (phase 5), each lane's launch tails overlapping the other's
+  if (phase == 3) return group_ls(b, a.hp, b->lanes[0], b->grp_two ? 0 : -1);
+  if (phase == 5) return group_ls(b, a.hp, b->lanes[1], 1);
   const int part = phase == 2 ? (b->grp_active ? 0 : -1) : 2;
   for (size_t k = l; k < b->ctx.size(); k += nl) {
     kfac_pinn_ctx* c = b->ctx[k];
@@ -2337,7 +2361,7 @@ kp_status batch_enqueue(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
 
 kp_status batch_capture(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a,
                         hipGraphExec_t* out) {
-  hipStream_t s = b->lanes[phase == 1 || phase == 3 ? 0 : l];
+  hipStream_t s = b->lanes[phase == 1 || phase == 3 ? 0 : phase == 5 ? 1 : l];
   KP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   kp_status st = batch_enqueue(b, phase, l, a);
   hipGraph_t g = nullptr;
@@ -2363,8 +2387,9 @@ kp_status batch_launch(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a)
                      : phase == 1 ? b->exec_eig
                      : phase == 2 ? b->exec_tail[l]
                      : phase == 3 ? b->exec_ls
+                     : phase == 5 ? b->exec_ls1
                                   : b->exec_fin[l];
-  KP_TRY(hipGraphLaunch(x, b->lanes[phase == 1 || phase == 3 ? 0 : l]));
+  KP_TRY(hipGraphLaunch(x, b->lanes[phase == 1 || phase == 3 ? 0 : phase == 5 ? 1 : l]));
   return KP_OK;
 }
 }  // namespace
@@ -2395,7 +2420,8 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
   }
   if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_eig, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_ls, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&b->ev_ls, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_ls1, hipEventDisableTiming) != hipSuccess)
     return fail(KP_ERR_HIP);
   for (int k = 0; k < count; k++) {
     kfac_pinn_ctx* c = nullptr;
@@ -2430,6 +2456,14 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
     if (group_build(b, nullptr, true, blob, b->grp)) {
       if (hipMalloc((void**)&b->grp.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
       b->grp.cap = blob.size();
+      // the second line-search buffers of every instance (odd candidates on lane 1)
+      bool ok = nl >= 2;
+      for (kfac_pinn_ctx* c : b->ctx)
+        if (ok && ls_lane_alloc(c) != hipSuccess) return fail(KP_ERR_OOM);
+      if (ok && group_build(b, nullptr, true, blob, b->grp1, nullptr, 1)) {
+        if (hipMalloc((void**)&b->grp1.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
+        b->grp1.cap = blob.size();
+      }
     }
     if (prod_build(b, nullptr, nullptr, 0.0, true, blob, b->prod)) {
       if (hipMalloc((void**)&b->prod.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
@@ -2450,6 +2484,7 @@ kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   if (b->eig_ids) (void)hipFree(b->eig_ids);
   if (b->eig_ctl) (void)hipFree(b->eig_ctl);
   if (b->grp.dev) (void)hipFree(b->grp.dev);
+  if (b->grp1.dev) (void)hipFree(b->grp1.dev);
   if (b->prod.dev) (void)hipFree(b->prod.dev);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->ev_head) (void)hipEventDestroy(e);
@@ -2457,6 +2492,7 @@ kp_status kfac_pinn_batch_destroy(kfac_pinn_batch* b) {
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_eig) (void)hipEventDestroy(b->ev_eig);
   if (b->ev_ls) (void)hipEventDestroy(b->ev_ls);
+  if (b->ev_ls1) (void)hipEventDestroy(b->ev_ls1);
   for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
   delete b;
   return KP_OK;
@@ -2516,7 +2552,7 @@ kp_status kfac_pinn_batch_tune(kfac_pinn_batch* b, void* const* thetas, const vo
 
 kp_status kfac_pinn_batch_is_grouped(kfac_pinn_batch* b, int32_t* out) {
   KP_ARG(b && out, "null argument");
-  *out = (b->grp_active ? 1 : 0) | (b->prod_active ? 2 : 0);
+  *out = (b->grp_active ? 1 : 0) | (b->prod_active ? 2 : 0) | (b->grp_two ? 4 : 0);
   return KP_OK;
 }
 
@@ -2566,20 +2602,34 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
     if (valid && key == b->grp.key) {
       b->grp_active = true;
     } else if (valid) {
+      // nothing in flight may read the old tables (the grouped launches run on
+      // lanes 0 and 1)
+      KP_TRY(hipStreamSynchronize(b->lanes[0]));
+      if (b->grp1.dev) KP_TRY(hipStreamSynchronize(b->lanes[1]));
       std::vector<char> blob;
       kfac_pinn_batch::Group g = b->grp;
       if (group_build(b, &a, false, blob, g) && blob.size() <= b->grp.cap) {
-        // nothing in flight may read the old tables (the grouped launches run on lane 0)
-        KP_TRY(hipStreamSynchronize(b->lanes[0]));
         KP_TRY(hipMemcpy(b->grp.dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
         g.dev = b->grp.dev;
         g.cap = b->grp.cap;
         g.key = key;
         b->grp = g;
         b->grp_active = true;
+        b->grp1.key.clear();
+        kfac_pinn_batch::Group g1 = b->grp1;
+        if (b->grp1.dev && group_build(b, &a, false, blob, g1, nullptr, 1) &&
+            blob.size() <= b->grp1.cap) {
+          KP_TRY(hipMemcpy(b->grp1.dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
+          g1.dev = b->grp1.dev;
+          g1.cap = b->grp1.cap;
+          g1.key = key;
+          b->grp1 = g1;
+        }
       }
     }
   }
+  b->grp_two = b->grp_active && b->grp1.dev && b->grp1.key == b->grp.key &&
+               hp->grid_max_exp > hp->grid_min_exp;
   // The grouped products need valid point counts and beta (their tables hold the
   // EMA weights); an invalid argument is reported by the instance's head.
   b->prod_active = false;
@@ -2613,6 +2663,7 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
   }
   key.push_back((uintptr_t)infos);
   key.push_back((uintptr_t)b->grp_active);
+  key.push_back((uintptr_t)b->grp_two);
   key.push_back((uintptr_t)b->prod_active);
   {
     const unsigned char* hb = (const unsigned char*)hp;
@@ -2630,6 +2681,7 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
       for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 2, l, a, &b->exec_tail[l]);
       if (b->grp_active) {
         if (s == KP_OK) s = batch_capture(b, 3, 0, a, &b->exec_ls);
+        if (s == KP_OK && b->grp_two) s = batch_capture(b, 5, 1, a, &b->exec_ls1);
         for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 4, l, a, &b->exec_fin[l]);
       }
       if (s != KP_OK) {
@@ -2669,13 +2721,19 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
   // the grouped line search on lane 0 after every lane's directions, then the
   // step sizes and updates back on the lanes
   for (int l = 1; l < nl; l++) KP_TRY(hipStreamWaitEvent(b->lanes[0], b->ev_pre[l], 0));
+  if (b->grp_two)
+    for (int l = 0; l < nl; l++)
+      if (l != 1) KP_TRY(hipStreamWaitEvent(b->lanes[1], b->ev_pre[l], 0));
   {
     kp_status s = batch_launch(b, 3, 0, a);
     if (s != KP_OK) return s;
+    if (b->grp_two && (s = batch_launch(b, 5, 1, a)) != KP_OK) return s;
   }
   KP_TRY(hipEventRecord(b->ev_ls, b->lanes[0]));
+  if (b->grp_two) KP_TRY(hipEventRecord(b->ev_ls1, b->lanes[1]));
   for (int l = 0; l < nl; l++) {
     if (l > 0) KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev_ls, 0));
+    if (b->grp_two && l != 1) KP_TRY(hipStreamWaitEvent(b->lanes[l], b->ev_ls1, 0));
     kp_status s = batch_launch(b, 4, l, a);
     if (s != KP_OK) return s;
     KP_TRY(hipEventRecord(b->ev[l], b->lanes[l]));

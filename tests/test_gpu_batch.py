@@ -54,6 +54,7 @@ def test_batch_matches_single_contexts(use_graph, grouped):
         b.step(thetas, *cols, hp, infos)
         torch.cuda.synchronize()
         assert b.is_grouped() == grouped and b.grouped_products() == grouped
+        assert b.grouped_two_lanes() == grouped
         # unrelated eager work between replays
         junk = torch.randn(1 << 20, device=dev)
         (junk * 2).sum().item()
