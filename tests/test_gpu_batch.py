@@ -234,6 +234,44 @@ def test_batch_tune_cache_and_choices(tmp_path):
         del b2
 
 
+def test_batch_tune_errors(tmp_path):
+    """The tuner's error paths: instances that do not take the grouped line search
+    (FP32) give KP_ERR_STATE, an empty boundary set KP_ERR_ARG, and a cache path
+    that cannot be written KP_ERR_ARG after the choices are applied (the next step
+    still takes the grouped line search and succeeds)."""
+    from paper_2405_15603_amd import HParams, KfacPinnBatch
+    from paper_2405_15603_amd import _native as N
+    dev = torch.device("cuda", 0)
+    probs = synth.batch_instances(64)[50:53]
+    n = len(probs)
+
+    def call(b, thetas, cols, path, nb_override=None):
+        V = C.c_void_p * n
+        I = C.c_int32 * n
+        xi, yi, xb, yb = cols
+        nbs = [t.shape[0] for t in xb] if nb_override is None else nb_override
+        return b.lib.kfac_pinn_batch_tune(
+            b.h, V(*[t.data_ptr() for t in thetas]), V(*[t.data_ptr() for t in xi]),
+            V(*[t.data_ptr() for t in yi]), I(*[t.shape[0] for t in xi]),
+            V(*[t.data_ptr() for t in xb]), V(*[t.data_ptr() for t in yb]), I(*nbs),
+            path.encode() if path else None, None)
+
+    data = [inputs(p, dev) for p in probs]
+    thetas = [d[0] for d in data]
+    cols = list(zip(*[d[1] for d in data]))
+    b32 = KfacPinnBatch(probs, "f32")
+    assert call(b32, thetas, cols, None) == N.KP_ERR_STATE
+    del b32
+    b = KfacPinnBatch(probs, "bf16")
+    assert call(b, thetas, cols, None, nb_override=[0] * n) == N.KP_ERR_ARG
+    bad = str(tmp_path / "no_such_dir" / "tune.json")
+    assert call(b, thetas, cols, bad) == N.KP_ERR_ARG
+    hp = HParams(lam=1e-3, beta=0.5, momentum=0.5, lr_mode="grid")
+    b.step(thetas, *cols, hp)
+    torch.cuda.synchronize()
+    assert b.is_grouped() and b.sync() == [0] * n
+
+
 @pytest.mark.parametrize("forced_nch", [None, 1])
 def test_batch_instances_against_oracle(forced_nch, tmp_path):
     """Four instances of the 64-instance recipe (d = 20 at widths 256, 64 and 128,

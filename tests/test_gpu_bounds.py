@@ -64,7 +64,9 @@ def test_guards_intact(case, monkeypatch):
 
 
 def test_guards_intact_batch(monkeypatch):
-    """Batch instances (captured graphs, one inversion over all instances)."""
+    """Batch instances (captured graphs, one inversion over all instances, the
+    grouped products and line search on two lanes), also after tuning (other tile
+    geometries and chunk counts) and with fewer points than the capacity."""
     from paper_2405_15603_amd import HParams, KfacPinnBatch
     monkeypatch.setenv("KFAC_PINN_GUARD_KB", GUARD_KB)
     probs = synth.batch_instances(64)[:10]
@@ -77,6 +79,13 @@ def test_guards_intact_batch(monkeypatch):
     for _ in range(2):
         b.step(thetas, *cols, hp)
     torch.cuda.synchronize()
+    assert b.is_grouped() and b.grouped_products() and b.grouped_two_lanes()
+    b.tune(thetas, *cols)
+    b.step(thetas, *cols, hp)
+    less = [tuple(a[:max(1, (2 * a.shape[0]) // 3)] for a in inst) for inst in zip(*cols)]
+    b.step(thetas, *list(zip(*less)), hp)
+    torch.cuda.synchronize()
+    assert b.is_grouped()
     assert b.sync() == [0] * len(probs)
     for k, c in enumerate(b.contexts):
         bad, nbuf = c.check_guards()
