@@ -2456,10 +2456,16 @@ kp_status kfac_pinn_batch_create(const kp_problem* problems, int32_t count, void
     if (group_build(b, nullptr, true, blob, b->grp)) {
       if (hipMalloc((void**)&b->grp.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
       b->grp.cap = blob.size();
-      // the second line-search buffers of every instance (odd candidates on lane 1)
+      // the second line-search buffers of every instance (odd candidates on lane
+      // 1); without the memory for them the grouped line search keeps one lane
       bool ok = nl >= 2;
       for (kfac_pinn_ctx* c : b->ctx)
-        if (ok && ls_lane_alloc(c) != hipSuccess) return fail(KP_ERR_OOM);
+        if (ok && ls_lane_alloc(c) != hipSuccess) ok = false;
+      if (!ok) {
+        (void)hipGetLastError();
+        for (kfac_pinn_ctx* c : b->ctx)
+          if (ls_lane_free(c) != hipSuccess) return fail(KP_ERR_HIP);
+      }
       if (ok && group_build(b, nullptr, true, blob, b->grp1, nullptr, 1)) {
         if (hipMalloc((void**)&b->grp1.dev, blob.size()) != hipSuccess) return fail(KP_ERR_OOM);
         b->grp1.cap = blob.size();
