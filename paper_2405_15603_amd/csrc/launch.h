@@ -252,6 +252,14 @@ struct EigGroups {
   int host_nprob = 0;
   bool host_wait = true;           // early stop allowed (kfac_pinn_set_sweep_wait)
   hipEvent_t swept[kEigGroups][2] = {};
+  // With the early stop, a group's sweep (its rounds, the convergence check and
+  // the flag copy for one parity) is one captured graph, launched once per sweep:
+  // a sweep is ~200 launches, more host time than its GPU time.  Captured on
+  // first use on a private stream, for the arguments in sweep_key.
+  hipGraphExec_t sweep[kEigGroups][2] = {};
+  hipGraph_t sweep_graph[kEigGroups][2] = {};
+  hipStream_t cap = nullptr;
+  const void* sweep_key[3] = {};
 };
 // Splits nprob problems into min(ngroups, nprob, kEigGroups) groups of balanced
 // work (largest first to the lightest group); fills g.n, g.off, g.npmax and the
@@ -263,7 +271,7 @@ hipError_t eig_host_sync(EigGroups& g, const int* ids, int nprob);
 void eig_host_free(EigGroups& g);
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
                             EigProblem* probs_dev, int* status, int* done, int* calls,
-                            int refresh, int max_sweeps, const EigGroups& g, hipStream_t st);
+                            int refresh, int max_sweeps, EigGroups& g, hipStream_t st);
 // Delta = -P_B [(P_B^T V P_A) / (1 + b a^T)] P_A^T for every layer, V = gradient
 // (column-major h_out x (h_in+1) inside the theta layout).  Four strided FP64
 // products per layer, described once (descriptors in device memory).

@@ -892,6 +892,17 @@ hipError_t eig_host_sync(EigGroups& g, const int* ids, int nprob) {
   return hipSuccess;
 }
 
+static void sweep_graphs_free(EigGroups& g) {
+  for (int k = 0; k < kEigGroups; k++)
+    for (int par = 0; par < 2; par++) {
+      if (g.sweep[k][par]) (void)hipGraphExecDestroy(g.sweep[k][par]);
+      if (g.sweep_graph[k][par]) (void)hipGraphDestroy(g.sweep_graph[k][par]);
+      g.sweep[k][par] = nullptr;
+      g.sweep_graph[k][par] = nullptr;
+    }
+  g.sweep_key[0] = g.sweep_key[1] = g.sweep_key[2] = nullptr;
+}
+
 void eig_host_free(EigGroups& g) {
   for (int k = 0; k < kEigGroups; k++)
     for (int par = 0; par < 2; par++)
@@ -900,6 +911,9 @@ void eig_host_free(EigGroups& g) {
         (void)hipEventDestroy(g.swept[k][par]);
         g.swept[k][par] = nullptr;
       }
+  sweep_graphs_free(g);
+  if (g.cap) (void)hipStreamDestroy(g.cap);
+  g.cap = nullptr;
   if (g.host) (void)hipHostFree(g.host);
   g.host = nullptr;
   g.host_nprob = 0;
@@ -937,7 +951,7 @@ void eig_groups_plan(const EigProblem* probs, int nprob, int ngroups, int* ids, 
 
 hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lambda,
                             EigProblem* probs_dev, int* status, int* done, int* calls,
-                            int refresh, int max_sweeps, const EigGroups& g, hipStream_t st) {
+                            int refresh, int max_sweeps, EigGroups& g, hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   if (g.n < 1 || g.n > kEigGroups || g.off[0] != 0 || g.off[g.n] != nprob || !g.ids)
     return hipErrorInvalidValue;
@@ -984,28 +998,82 @@ hipError_t kron_eig_batched(const EigProblem* probs_host, int nprob, double lamb
                      cap == hipStreamCaptureStatusNone;
   const long nflag = 2L * nprob;
   auto flags = [&](int k, int par) { return g.host + nprob + (2 * k + par) * nflag; };
+  // one group's sweep: its rounds, the convergence check and (early stop) the copy
+  // of the flags for the host
+  auto enqueue_sweep = [&](int k, int par, hipStream_t sk) -> hipError_t {
+    const int* ids = g.ids + g.off[k];
+    const int nq = g.off[k + 1] - g.off[k];
+    const int npair = g.npmax[k] / JB / 2;
+    const int nwg = npair * (npair + 1) / 2 + npair * npair;
+    for (int r = 0; r < rounds[k]; r++) {
+      k_jac_solve<<<dim3(npair, nq), kSolveThreads, 0, sk>>>(probs_dev, ids, done, r, KP_JAC_INNER);
+      k_jac_apply<<<dim3(nwg, nq), 256, 0, sk>>>(probs_dev, ids, done, r);
+    }
+    k_jac_check<<<(nq + 63) / 64, 64, 0, sk>>>(probs_dev, ids, done, nq);
+    if (hipError_t e = hipGetLastError()) return e;
+    if (!early) return hipSuccess;
+    return hipMemcpyAsync(flags(k, par), done, sizeof(int) * nflag, hipMemcpyDeviceToHost, sk);
+  };
+  if (early && (g.sweep_key[0] != probs_dev || g.sweep_key[1] != done || g.sweep_key[2] != g.ids))
+    sweep_graphs_free(g);
+  // the early stop's sweeps as graphs (captured once on a private stream)
+  auto sweep_graph = [&](int k, int par) -> hipGraphExec_t {
+    if (g.sweep[k][par]) return g.sweep[k][par];
+    if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess) {
+      g.cap = nullptr;
+      return nullptr;
+    }
+    if (hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    const hipError_t e = enqueue_sweep(k, par, g.cap);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(g.cap, &gr);
+    if (e != hipSuccess || e2 != hipSuccess || !gr) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return nullptr;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, gr, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(gr);
+      return nullptr;
+    }
+    g.sweep_graph[k][par] = gr;
+    g.sweep[k][par] = x;
+    g.sweep_key[0] = probs_dev;
+    g.sweep_key[1] = done;
+    g.sweep_key[2] = g.ids;
+    return x;
+  };
   for (int sw = 0; sw < max_sweeps; sw++) {
     bool any = false;
     for (int k = 0; k < ng; k++) any = any || active[k];
     if (!any) break;
-    for (int r = 0; r < rmax; r++)
+    if (early) {
       for (int k = 0; k < ng; k++) {
-        if (!active[k] || r >= rounds[k]) continue;
+        if (!active[k] || rounds[k] < 1) continue;
         const hipStream_t sk = k == 0 ? st : g.st[k];
-        const int* ids = g.ids + g.off[k];
-        const int nq = g.off[k + 1] - g.off[k];
-        const int npair = g.npmax[k] / JB / 2;
-        const int nwg = npair * (npair + 1) / 2 + npair * npair;
-        k_jac_solve<<<dim3(npair, nq), kSolveThreads, 0, sk>>>(probs_dev, ids, done, r, KP_JAC_INNER);
-        k_jac_apply<<<dim3(nwg, nq), 256, 0, sk>>>(probs_dev, ids, done, r);
-        if (r < rounds[k] - 1) continue;
-        k_jac_check<<<(nq + 63) / 64, 64, 0, sk>>>(probs_dev, ids, done, nq);
-        if (!early) continue;
-        if (hipError_t e = hipMemcpyAsync(flags(k, sw & 1), done, sizeof(int) * nflag,
-                                          hipMemcpyDeviceToHost, sk))
+        if (hipGraphExec_t x = sweep_graph(k, sw & 1)) {
+          if (hipError_t e = hipGraphLaunch(x, sk)) return e;
+        } else if (hipError_t e = enqueue_sweep(k, sw & 1, sk)) {
           return e;
+        }
         if (hipError_t e = hipEventRecord(g.swept[k][sw & 1], sk)) return e;
       }
+    } else {
+      // the groups' rounds interleaved launch by launch on their streams
+      for (int r = 0; r < rmax; r++)
+        for (int k = 0; k < ng; k++) {
+          if (!active[k] || r >= rounds[k]) continue;
+          const hipStream_t sk = k == 0 ? st : g.st[k];
+          const int* ids = g.ids + g.off[k];
+          const int nq = g.off[k + 1] - g.off[k];
+          const int npair = g.npmax[k] / JB / 2;
+          const int nwg = npair * (npair + 1) / 2 + npair * npair;
+          k_jac_solve<<<dim3(npair, nq), kSolveThreads, 0, sk>>>(probs_dev, ids, done, r, KP_JAC_INNER);
+          k_jac_apply<<<dim3(nwg, nq), 256, 0, sk>>>(probs_dev, ids, done, r);
+          if (r < rounds[k] - 1) continue;
+          k_jac_check<<<(nq + 63) / 64, 64, 0, sk>>>(probs_dev, ids, done, nq);
+        }
+    }
     if (!early || sw == 0) continue;
     // the previous sweep's flags (this sweep is already queued behind it)
     for (int k = 0; k < ng; k++) {
