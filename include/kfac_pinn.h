@@ -361,23 +361,27 @@ kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
  * kfac_pinn_batch_step performs one kfac_pinn_step per instance with the same
  * hyper-parameters: thetas, x_int, y_int, x_bnd, y_bnd are host arrays of
  * `count` device pointers, n_int and n_bnd host arrays of sizes, infos a device
- * array of `count` summaries (or NULL).  It runs in three phases: the factors
- * and gradients of every instance (on the lanes), then ONE inversion launch
- * sequence over the damped factors of all instances together (on lane 0, so
- * each eigensolver launch covers every instance's problems), then the
- * directions, line searches and updates (on the lanes).  With the grid line
- * search (lr_mode 1), BF16 line-search slabs and every instance on the paired
- * line-search launches (linear residuals, unit input directions, both point
- * sets non-empty), the line search is grouped: each of a candidate's kernels
- * runs ONCE over every instance (job tables in device memory, made at creation
- * for the largest point counts and rewritten when the step's buffers or point
- * counts change), on lanes 0 and 1 (even and odd candidates) between the
- * directions and the updates on the lanes.  With mixed curvature products (KP_MIXED_BF16, KP_MIXED_F16), stored
- * slabs and both point sets non-empty, the factor and gradient products are
- * grouped too: the curvature passes on the lanes leave them to one launch per
- * (term, layer, product) over every instance plus one for its split-K
- * reduction, on lane 0 before the inversion.  The results equal those of
- * kfac_pinn_step on each instance.  The Jacobi warm start and its
+ * array of `count` summaries (or NULL).  Its phases:
+ *   1. the curvature passes of every instance, on the lanes;
+ *   2. on lane 0: the factor and gradient products of every instance, then ONE
+ *      inversion launch sequence over the damped factors of all instances (each
+ *      eigensolver launch covers every instance's problems);
+ *   3. the directions and momenta, on the lanes;
+ *   4. the line searches;
+ *   5. the step sizes and updates, on the lanes.
+ * Grouped launches (see kfac_pinn_batch_set_grouped): with mixed curvature
+ * products (KP_MIXED_BF16, KP_MIXED_F16), stored slabs and both point sets
+ * non-empty, phase 2's products are one launch per (term, layer, product) over
+ * every instance plus one for its split-K reduction; with the grid line search
+ * (lr_mode 1), BF16 line-search slabs and every instance on the paired
+ * line-search launches (linear residuals, unit input directions), each of a
+ * candidate's kernels in phase 4 is ONE launch over every instance, even
+ * candidates on lane 0 and odd ones on lane 1 (each instance's second set of
+ * line-search buffers).  Otherwise those launches run per instance on its lane.
+ * The grouped launches read job tables in device memory, made at creation for
+ * the largest point counts and rewritten when the step's buffers, point counts
+ * or beta change.  The results equal those of kfac_pinn_step on each instance.
+ * The Jacobi warm start and its
  * periodic cold start are counted per batch step, and the sweeps used are read
  * with kfac_pinn_batch_get_sweeps (kfac_pinn_get_sweeps on an instance's
  * context reports only its own kfac_pinn_step/invert calls).  The work is
