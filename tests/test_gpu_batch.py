@@ -266,6 +266,12 @@ def test_batch_tune_errors(tmp_path):
     assert call(b, thetas, cols, None, nb_override=[0] * n) == N.KP_ERR_ARG
     bad = str(tmp_path / "no_such_dir" / "tune.json")
     assert call(b, thetas, cols, bad) == N.KP_ERR_ARG
+    # a malformed cache reads as empty: every class is timed and the file rewritten
+    junk = tmp_path / "junk.json"
+    junk.write_text('{"entries": [{"device": "x", "K": }, {nonsense')
+    assert b.tune(thetas, *cols, cache_path=str(junk)) > 0
+    import json
+    assert json.loads(junk.read_text())["entries"]
     hp = HParams(lam=1e-3, beta=0.5, momentum=0.5, lr_mode="grid")
     b.step(thetas, *cols, hp)
     torch.cuda.synchronize()
