@@ -387,8 +387,12 @@ kp_status kfac_pinn_get_workspace(kfac_pinn_ctx* ctx, int32_t* out);
  * context reports only its own kfac_pinn_step/invert calls).  The work is
  * ordered after the work already on `stream` and before anything enqueued
  * there later.  The first call captures each phase into HIP graphs (per lane,
- * and one for the inversion); later calls with the same arguments replay them
- * (different arguments recapture); with the graphs disabled
+ * and for the grouped line search); later calls with the same arguments replay
+ * them (different arguments recapture).  The inversion (with the grouped factor
+ * products) is enqueued directly, so that its sweeps stop once the host reads
+ * every problem as converged (each sweep replays a graph of its own); only when
+ * the convergence flags have no host buffer is it captured too, running every
+ * sweep up to the cap.  With the graphs disabled
  * (kfac_pinn_batch_set_graph) every call enqueues the launches directly.
  * Errors as for kfac_pinn_step; per-instance device status is read with
  * kfac_pinn_sync on kfac_pinn_batch_context(batch, k). */

@@ -2381,8 +2381,15 @@ kp_status batch_capture(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a
   return KP_OK;
 }
 
+// The inversion's sweeps stop early when the host can read the convergence flags,
+// which a captured graph cannot: then phase 1 is enqueued directly (each group's
+// sweep still replays a graph of its own) and the other phases replay theirs.
+bool batch_eig_direct(const kfac_pinn_batch* b) {
+  return b->eg.host && b->eg.host_wait && b->eg.host_nprob == (int)b->probs.size();
+}
+
 kp_status batch_launch(kfac_pinn_batch* b, int phase, int l, const BatchArgs& a) {
-  if (!b->use_graph) return batch_enqueue(b, phase, l, a);
+  if (!b->use_graph || (phase == 1 && !b->exec_eig)) return batch_enqueue(b, phase, l, a);
   hipGraphExec_t x = phase == 0   ? b->exec_head[l]
                      : phase == 1 ? b->exec_eig
                      : phase == 2 ? b->exec_tail[l]
@@ -2671,19 +2678,21 @@ kp_status kfac_pinn_batch_step(kfac_pinn_batch* b, void* const* thetas, const vo
   key.push_back((uintptr_t)b->grp_active);
   key.push_back((uintptr_t)b->grp_two);
   key.push_back((uintptr_t)b->prod_active);
+  const bool eig_direct = batch_eig_direct(b);
+  key.push_back((uintptr_t)eig_direct);
   {
     const unsigned char* hb = (const unsigned char*)hp;
     for (size_t i = 0; i < sizeof(kp_hparams); i++) key.push_back(hb[i]);
   }
   if (b->use_graph) {
-    if (b->exec_eig == nullptr || key != b->key) {
+    if (b->exec_head.empty() || key != b->key) {
       batch_drop_graph(b);
       b->exec_head.assign(nl, nullptr);
       b->exec_tail.assign(nl, nullptr);
       b->exec_fin.assign(nl, nullptr);
       kp_status s = KP_OK;
       for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 0, l, a, &b->exec_head[l]);
-      if (s == KP_OK) s = batch_capture(b, 1, 0, a, &b->exec_eig);
+      if (s == KP_OK && !eig_direct) s = batch_capture(b, 1, 0, a, &b->exec_eig);
       for (int l = 0; l < nl && s == KP_OK; l++) s = batch_capture(b, 2, l, a, &b->exec_tail[l]);
       if (b->grp_active) {
         if (s == KP_OK) s = batch_capture(b, 3, 0, a, &b->exec_ls);
