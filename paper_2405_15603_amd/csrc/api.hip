@@ -344,6 +344,7 @@ struct FwdTarget {
   int kc_layer = KC_LAYER_GEMM;  // timing class of the layer products
   bool full_input = true;        // write every row of the input slab (false: value rows)
   bool residual_rows = false;    // interior: only the output rows the residual reads
+  bool narrow_pad = false;       // rows read and padded only to h + 1 rounded up to 8
 };
 
 // One hidden layer's product: its arguments, chunk count and accounting.
@@ -384,6 +385,10 @@ LayerLaunch layer_launch(kfac_pinn_ctx* c, const Slabs& s, int n, int l, int upt
   a.tab_lap = s.has_lap ? wptr(c->tab, ts, c->esz_c) : nullptr;
   a.tab_sq = s.has_lap ? wptr(c->tab, 2 * ts, c->esz_c) : nullptr;
   a.sq_out = T.sq(l);
+  if (T.narrow_pad) {
+    a.kz = (int)kp_roundup(ld.h_in + 1, 8);
+    a.padz = (int)kp_roundup(ld.h_out + 1, 8);
+  }
   if (T.residual_rows && s.has_lap && l == c->L - 2 && upto >= c->L) {
     // the output layer reads only the time and Laplacian rows of this layer's z
     a.sparse_store = 1;
@@ -700,6 +705,11 @@ void ls_targets(kfac_pinn_ctx* c, FwdTarget& T, FwdTarget& Tb) {
   T.u = c->ls_u;
   T.kc_layer = KC_LS_LAYER;
   T.full_input = false;
+  // The direct-to-LDS products read a row only up to its bias column rounded up to
+  // 8 (the rest of the last k-tile reads zeros), so the finishing passes write the
+  // bias column and zeros only that far: the rest of each row of the two buffers
+  // the layers share is never read.
+  T.narrow_pad = c->lmode == M_BF16;
   // a residual with first-order terms reads every derivative row of the output
   T.residual_rows = !c->nonlinear;
   Tb = T;

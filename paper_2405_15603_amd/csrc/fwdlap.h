@@ -37,6 +37,10 @@ struct FwdLayerArgs {
   int sparse_store;  // 1: z rows are stored only where needed: the value row if
   int keep_value;    //    keep_value, derivative rows s in [keep_lo, keep_hi]
   int keep_lo, keep_hi;   //    (the Laplacian row is always finished)
+  int kz;            // direct-to-LDS products: input columns read (multiple of 8; the
+                     //   rest of the K loop reads zeros); 0: K
+  int padz;          // output columns the finishing and input-row passes write (the
+                     //   bias column and zeros up to here, multiple of 8); 0: ldzo
 };
 
 struct BwdLayerArgs {

@@ -737,7 +737,7 @@ __device__ __forceinline__ void fwd_block(const FwdLayerArgs& a, int t, int chun
   };
   if constexpr (kDma<MODE>)
     sloop_dma<MODE, G>(smem, (const TL*)a.zin, a.ldz, a.N, p0, (const TL*)a.w, a.ldw, c0,
-                       a.h_out, a.K, nsteps, s_of, epi);
+                       a.h_out, a.kz > 0 ? a.kz : a.K, nsteps, s_of, epi);
   else
     sloop<MODE, false, decltype(s_of), decltype(epi), TR>(
         *(typename Mainloop<MODE>::Smem*)smem, (const typename O::TA*)a.zin, a.ldz, a.N, p0,
@@ -817,6 +817,7 @@ __global__ void k_fwdlap_finish(FwdLayerArgs a, int nch) {
   if (c >= a.ldzo || p >= a.N) return;
   TZ* z = (TZ*)a.z;
   if (c >= a.h_out) {
+    if (a.padz > 0 && c >= a.padz) return;
     for (int s = 0; s < a.S; s++)
       z[((long)s * a.N + p) * a.ldzo + c] = cvt<TZ>((c == a.h_out && s == 0) ? 1.0 : 0.0);
     return;
@@ -862,7 +863,8 @@ __device__ __forceinline__ void finish4_at(const FwdLayerArgs& a, int nch, long 
   const long row = idx - nmain;   // s * N + p
   if (row >= (long)a.S * a.N) return;
   TZ* zr = z + row * a.ldzo;
-  for (int c = a.h_out; c < a.ldzo; c += 4) {
+  const long wz = a.padz > 0 ? a.padz : a.ldzo;
+  for (int c = a.h_out; c < wz; c += 4) {
     f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
     if (c == a.h_out && row < a.N) v[0] = 1.0f;
     store4(zr + c, v);
@@ -1377,14 +1379,15 @@ __device__ __forceinline__ void load8(const TC* src, TC (&v)[8]) {
   }
 }
 
-// The rows s >= 1 and the padding of the value rows, a thread per 8 consecutive
-// columns of a row, grid-stride over rows (wide rows) or over the rows' chunks
-// (narrow rows).  ldzo is a multiple of 8; the
+// The rows s >= 1 and the padding of the value rows (up to padz), a thread per 8
+// consecutive columns of a row, grid-stride over rows (wide rows) or over the
+// rows' chunks (narrow rows).  ldzo and padz are multiples of 8; the
 // vector path needs h_out to be one too (else every block takes the scalar path).
 template <typename TC, typename TZ>
 __device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* __restrict__ q,
                                               const TC* __restrict__ wt, long bx, long gx) {
   const long nrows = (long)a.S * a.N;
+  const long wz = a.padz > 0 ? a.padz : a.ldzo;   // columns written
   const bool vec = (a.h_out & 7) == 0;
   TZ* z = (TZ*)a.z;
   // one 8-column chunk (row r = s N + p, columns c0 .. c0+7) of the output
@@ -1434,20 +1437,20 @@ __device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* _
       z[r * a.ldzo + c] = cvt<TZ>((double)zv);
     }
   };
-  // Wide rows: a wave per row, 512 columns per pass.  Narrow rows (at most 256
-  // columns, where a wave per row would leave lanes idle): the rows' 8-column
-  // chunks in one flat grid-stride sequence (consecutive lanes take consecutive
-  // chunks, across row ends).
-  if (a.ldzo > 256) {
+  // Wide rows: a wave per row, 512 columns per pass.  Narrow rows (at most 512
+  // columns written, where a wave per row would leave lanes idle): the rows'
+  // 8-column chunks in one flat grid-stride sequence (consecutive lanes take
+  // consecutive chunks, across row ends).
+  if (wz > 512) {
     const int lane = threadIdx.x & 63;
     const long nwaves = (gx * blockDim.x) >> 6;
     for (long r = (bx * blockDim.x + threadIdx.x) >> 6; r < nrows; r += nwaves) {
       const int s = (int)(r / a.N), p = (int)(r - (long)s * a.N);
-      for (int c0 = lane * 8; c0 < a.ldzo; c0 += 512) chunk(r, s, p, c0);
+      for (int c0 = lane * 8; c0 < wz; c0 += 512) chunk(r, s, p, c0);
     }
     return;
   }
-  const int cpr = (int)(a.ldzo / 8);
+  const int cpr = (int)(wz / 8);
   const long nq = nrows * cpr;
   const long i0 = bx * blockDim.x + threadIdx.x, ni = gx * blockDim.x;
   if (nq < 0x7fffffffL) {   // 32-bit index arithmetic
@@ -1640,9 +1643,15 @@ static void launch_fwd(const FwdLayerArgs& a0, int nch, const FwdLayerArgs* a1, 
   k_fwdlap<MODE, TZ, A4><<<dim3(t0 + t1, nch), FwdGeo<MODE>::NT, 0, st>>>(a0, a1 ? *a1 : none, t0);
 }
 
+// padz: 0, or a multiple of 8 past the bias column and within the row
+static bool pad_args_ok(const FwdLayerArgs& a) {
+  return a.padz == 0 || (a.padz % 8 == 0 && a.padz > a.h_out && a.padz <= a.ldzo);
+}
+
 static bool fwd_args_ok(const FwdLayerArgs& a) {
   // the direct-to-LDS loop keeps per-point offsets in 32 bits
-  return (long)a.N * a.ldz < 0x7fffffffL && (long)a.h_out * a.ldw < 0x7fffffffL;
+  return (long)a.N * a.ldz < 0x7fffffffL && (long)a.h_out * a.ldw < 0x7fffffffL &&
+         pad_args_ok(a) && a.kz >= 0 && a.kz <= a.K && a.kz % 8 == 0;
 }
 
 hipError_t fwdlap_main(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
@@ -1685,6 +1694,7 @@ hipError_t fwdlap_pair(int mode, const FwdLayerArgs& a, int nch, const FwdLayerA
 
 hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
+  if (!pad_args_ok(a)) return hipErrorInvalidValue;
   if (mode != M_F64 && (a.h_out & 3) == 0 && (a.ldzo & 3) == 0) {
     const long items = (a.has_lap ? (long)a.N * (a.h_out / 4) : 0) + (long)a.S * a.N;
     const unsigned nb = (unsigned)((items + 255) / 256);
@@ -1709,7 +1719,7 @@ hipError_t fwdlap_finish(int mode, const FwdLayerArgs& a, int nch, hipStream_t s
 hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
   if (!a.has_lap || a.S != a.nd + 2) return hipErrorInvalidValue;
-  if (a.ldzo % 8) return hipErrorInvalidValue;
+  if (a.ldzo % 8 || !pad_args_ok(a)) return hipErrorInvalidValue;
   const int nq = (a.h_out + 63) / 64;
   const int nd256 = (a.h_out + 255) / 256;
   if (a.dirs && a.d <= 0) return hipErrorInvalidValue;
@@ -1882,7 +1892,8 @@ int fwd_geo_width(int geo) {
 }
 
 bool make_fin_job(const FwdLayerArgs& a, int nch, FinJob* j) {
-  if (a.N <= 0 || (a.h_out & 3) != 0 || (a.ldzo & 3) != 0 || nch < 1 || nch > kMaxChunks)
+  if (a.N <= 0 || (a.h_out & 3) != 0 || (a.ldzo & 3) != 0 || !pad_args_ok(a) || nch < 1 ||
+      nch > kMaxChunks)
     return false;
   j->a = a;
   j->nch = nch;
@@ -1890,7 +1901,8 @@ bool make_fin_job(const FwdLayerArgs& a, int nch, FinJob* j) {
 }
 
 bool make_input_jobs(const FwdLayerArgs& a, void* q, int max_blocks, InQJob* jq, InRowsJob* jr) {
-  if (a.N <= 0 || !a.has_lap || a.S != a.nd + 2 || a.ldzo % 8 || a.dirs || max_blocks < 1)
+  if (a.N <= 0 || !a.has_lap || a.S != a.nd + 2 || a.ldzo % 8 || !pad_args_ok(a) || a.dirs ||
+      max_blocks < 1)
     return false;
   jq->a = a;
   jq->q = (float*)q;
