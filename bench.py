@@ -359,13 +359,17 @@ def main():
     if not args.no_batch:
         log("64-instance batch")
         bp = args.precision if args.precision in ("bf16", "f16") else "bf16"
+        bw = args.warmup
         out["batch64"] = {"instances": 64, "note": "heterogeneous 64-instance recipe, mixed "
-                          "precision, grid line search; one step of every instance per call",
-                          "graph": run_batch(64, 3, 1, True, bp),
-                          "graph_tuned": run_batch(64, 3, 1, True, bp, tuned=True),
-                          "direct": run_batch(64, 3, 1, False, bp),
-                          "graph_per_instance_line_search": run_batch(64, 3, 1, True, bp,
-                                                                      grouped=False)}
+                          f"precision, grid line search; one step of every instance per call; "
+                          f"3 timed steps after {bw} warm-up steps (the headline's), and the "
+                          "first steps (after 1 warm-up, cold Jacobi start) for comparison",
+                          "graph": run_batch(64, 3, bw, True, bp),
+                          "graph_tuned": run_batch(64, 3, bw, True, bp, tuned=True),
+                          "direct": run_batch(64, 3, bw, False, bp),
+                          "graph_per_instance_line_search": run_batch(64, 3, bw, True, bp,
+                                                                      grouped=False),
+                          "graph_first_steps": run_batch(64, 3, 1, True, bp)}
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(problem)
