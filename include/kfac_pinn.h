@@ -16,8 +16,8 @@
  *   output, tanh between layers.  Parameters theta follow Section 2: layer l's
  *   augmented matrix [W | b] (h_out x (h_in+1)) is stacked column by column
  *   (bias is the last column), layers are concatenated; D = sum h_out (h_in+1).
- * Element type "real": double for KP_F64, float for KP_F32 and KP_MIXED_BF16
- *   (FP32 master parameters).  Points are row-major n x d reals, targets are n
+ * Element type "real": double for KP_F64, float for KP_F32, KP_MIXED_BF16 and
+ *   KP_MIXED_F16 (FP32 master parameters).  Points are row-major n x d reals, targets are n
  *   reals.  Factors, gradients and preconditioners are always double.
  * Residuals: interior r = c_t du/dx_t + c_lap sum_{i in mask} d2u/dx_i^2 - y
  *   (or c_lap sum_ij C_ij d2u/dx_i dx_j with a coefficient matrix, kp_problem),
