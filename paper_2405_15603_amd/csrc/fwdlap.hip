@@ -1379,6 +1379,69 @@ __device__ __forceinline__ void load8(const TC* src, TC (&v)[8]) {
   }
 }
 
+// The 8-element arithmetic of a full chunk of derivative (or Laplacian) rows:
+// z = s1 w (Laplacian row: -2 t s1 q), pre = w (0), s1 = 1 - t^2.
+template <typename TC>
+__device__ __forceinline__ void input_rows8(const TC (&t)[8], const TC (&w)[8], bool lap,
+                                            TC (&zo)[8], TC (&po)[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const TC s1 = (TC)1 - t[e] * t[e];
+    zo[e] = lap ? (TC)-2 * t[e] * s1 * w[e] : s1 * w[e];
+    po[e] = lap ? (TC)0 : w[e];
+  }
+}
+
+// One 8-column chunk (row r = s N + p, columns c0 .. c0+7) of the input layer's
+// rows without products: the derivative and Laplacian rows, and the padding of
+// every row (value rows: only the padding; their other columns are the products').
+template <typename TC, typename TZ>
+__device__ __forceinline__ void input_chunk(const FwdLayerArgs& a, const TC* __restrict__ q,
+                                            const TC* __restrict__ wt, long r, int s, int p,
+                                            int c0) {
+  const bool vec = (a.h_out & 7) == 0;
+  TZ* z = (TZ*)a.z;
+  const bool lap = s == a.S - 1;
+  const TC* trow = (const TC*)a.tab_t + (long)p * a.h_out;
+  TC zo[8], po[8];
+  if (s > 0 && vec && c0 + 8 <= a.h_out) {   // full block of real columns
+    TC t[8], w[8];
+    load8(trow + c0, t);
+    if (!lap) load8(wt + (long)(s - 1) * a.h_out + c0, w);
+    else load8(q + c0, w);
+    input_rows8(t, w, lap, zo, po);
+    store8(z + r * a.ldzo + c0, zo);
+    if (a.pre)
+#pragma unroll
+      for (int e = 0; e < 8; e++) ((TC*)a.pre)[r * a.ldp + c0 + e] = po[e];
+    if (lap && a.sq_out)
+#pragma unroll
+      for (int e = 0; e < 8; e++) ((TC*)a.sq_out)[(long)p * a.h_out + c0 + e] = w[e];
+    return;
+  }
+  // padding, a block straddling h_out, or the value row's padding
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int c = c0 + e;
+    if (s == 0 && c < a.h_out) continue;   // value row: from the products
+    TC zv = (c == a.h_out && s == 0) ? (TC)1 : (TC)0;
+    if (c < a.h_out) {
+      const TC t = trow[c];
+      const TC s1 = (TC)1 - t * t;
+      TC pv = 0;
+      if (!lap) {
+        pv = wt[(long)(s - 1) * a.h_out + c];
+        zv = s1 * pv;
+      } else {
+        zv = (TC)-2 * t * s1 * q[c];
+        if (a.sq_out) ((TC*)a.sq_out)[(long)p * a.h_out + c] = q[c];
+      }
+      if (a.pre) ((TC*)a.pre)[r * a.ldp + c] = pv;
+    }
+    z[r * a.ldzo + c] = cvt<TZ>((double)zv);
+  }
+}
+
 // The rows s >= 1 and the padding of the value rows (up to padz), a thread per 8
 // consecutive columns of a row, grid-stride over rows (wide rows) or over the
 // rows' chunks (narrow rows).  ldzo and padz are multiples of 8; the
@@ -1388,55 +1451,7 @@ __device__ __forceinline__ void input_rows_at(const FwdLayerArgs& a, const TC* _
                                               const TC* __restrict__ wt, long bx, long gx) {
   const long nrows = (long)a.S * a.N;
   const long wz = a.padz > 0 ? a.padz : a.ldzo;   // columns written
-  const bool vec = (a.h_out & 7) == 0;
-  TZ* z = (TZ*)a.z;
-  // one 8-column chunk (row r = s N + p, columns c0 .. c0+7) of the output
-  auto chunk = [&](long r, int s, int p, int c0) {
-    const bool lap = s == a.S - 1;
-    const TC* trow = (const TC*)a.tab_t + (long)p * a.h_out;
-    TC zo[8], po[8];
-    if (s > 0 && vec && c0 + 8 <= a.h_out) {   // full block of real columns
-      TC t[8], w[8];
-      load8(trow + c0, t);
-      if (!lap) load8(wt + (long)(s - 1) * a.h_out + c0, w);
-      else load8(q + c0, w);
-#pragma unroll
-      for (int e = 0; e < 8; e++) {
-        const TC s1 = (TC)1 - t[e] * t[e];
-        zo[e] = lap ? (TC)-2 * t[e] * s1 * w[e] : s1 * w[e];
-        po[e] = lap ? (TC)0 : w[e];
-      }
-      store8(z + r * a.ldzo + c0, zo);
-      if (a.pre)
-#pragma unroll
-        for (int e = 0; e < 8; e++) ((TC*)a.pre)[r * a.ldp + c0 + e] = po[e];
-      if (lap && a.sq_out)
-#pragma unroll
-        for (int e = 0; e < 8; e++) ((TC*)a.sq_out)[(long)p * a.h_out + c0 + e] = w[e];
-      return;
-    }
-    // padding, a block straddling h_out, or the value row's padding
-#pragma unroll
-    for (int e = 0; e < 8; e++) {
-      const int c = c0 + e;
-      if (s == 0 && c < a.h_out) continue;   // value row: from the products
-      TC zv = (c == a.h_out && s == 0) ? (TC)1 : (TC)0;
-      if (c < a.h_out) {
-        const TC t = trow[c];
-        const TC s1 = (TC)1 - t * t;
-        TC pv = 0;
-        if (!lap) {
-          pv = wt[(long)(s - 1) * a.h_out + c];
-          zv = s1 * pv;
-        } else {
-          zv = (TC)-2 * t * s1 * q[c];
-          if (a.sq_out) ((TC*)a.sq_out)[(long)p * a.h_out + c] = q[c];
-        }
-        if (a.pre) ((TC*)a.pre)[r * a.ldp + c] = pv;
-      }
-      z[r * a.ldzo + c] = cvt<TZ>((double)zv);
-    }
-  };
+  auto chunk = [&](long r, int s, int p, int c0) { input_chunk<TC, TZ>(a, q, wt, r, s, p, c0); };
   // Wide rows: a wave per row, 512 columns per pass.  Narrow rows (at most 512
   // columns written, where a wave per row would leave lanes idle): the rows'
   // 8-column chunks in one flat grid-stride sequence (consecutive lanes take
@@ -1470,6 +1485,83 @@ template <typename TC, typename TZ>
 __global__ __launch_bounds__(256) void k_input_rows(FwdLayerArgs a, const TC* __restrict__ q,
                                                     const TC* __restrict__ wt) {
   input_rows_at<TC, TZ>(a, q, wt, blockIdx.x, gridDim.x);
+}
+
+// The same rows point-major: workgroup (x, y) takes points [x P, x P + P) and the
+// rows s of group y of gridDim.y; thread i owns items i, i + 256, ... of the
+// P x (padded row / 8) grid of (point, 8-column chunk), keeps the tanh values of
+// its full chunks in registers for all its rows (the row-major order reads them
+// once per row), and each row's P point segments are contiguous.  Per element the
+// arithmetic of input_chunk.
+constexpr int kRowsPmItems = 4;   // items per thread
+template <typename TC, typename TZ>
+__global__ __launch_bounds__(256) void k_input_rows_pm(FwdLayerArgs a, const TC* __restrict__ q,
+                                                       const TC* __restrict__ wt, int P) {
+  constexpr int IT = kRowsPmItems;
+  const int p0 = blockIdx.x * P;
+  const int np = min(P, a.N - p0);
+  if (np <= 0) return;
+  const int cpr = (int)((a.padz > 0 ? a.padz : a.ldzo) / 8);
+  const int items = np * cpr;
+  const bool vec = (a.h_out & 7) == 0;
+  const int per = (a.S + gridDim.y - 1) / gridDim.y;
+  const int sb = blockIdx.y * per, se = min(a.S, sb + per);
+  TC tc[IT][8];
+  int col[IT], pt[IT];   // full chunk's first column (or -1) and point
+#pragma unroll
+  for (int k = 0; k < IT; k++) {
+    const int i = threadIdx.x + 256 * k;
+    const int pl = i / cpr, c0 = (i - pl * cpr) * 8;
+    col[k] = (i < items && vec && c0 + 8 <= a.h_out) ? c0 : -1;
+    pt[k] = p0 + pl;
+    if (col[k] >= 0 && se > max(sb, 1))
+      load8((const TC*)a.tab_t + (long)pt[k] * a.h_out + col[k], tc[k]);
+  }
+  TZ* z = (TZ*)a.z;
+  for (int s = max(sb, 1); s < se; s++) {
+    const bool lap = s == a.S - 1;
+    const TC* wrow = lap ? q : wt + (long)(s - 1) * a.h_out;
+#pragma unroll
+    for (int k = 0; k < IT; k++) {
+      if (col[k] < 0) continue;
+      const long r = (long)s * a.N + pt[k];
+      TC w[8], zo[8], po[8];
+      load8(wrow + col[k], w);
+      input_rows8(tc[k], w, lap, zo, po);
+      store8(z + r * a.ldzo + col[k], zo);
+      if (a.pre)
+#pragma unroll
+        for (int e = 0; e < 8; e++) ((TC*)a.pre)[r * a.ldp + col[k] + e] = po[e];
+      if (lap && a.sq_out)
+#pragma unroll
+        for (int e = 0; e < 8; e++) ((TC*)a.sq_out)[(long)pt[k] * a.h_out + col[k] + e] = w[e];
+    }
+  }
+  // the other chunks (padding, a chunk straddling h_out), value rows included
+  for (int i = threadIdx.x; i < items; i += 256) {
+    const int pl = i / cpr, c0 = (i - pl * cpr) * 8;
+    if (vec && c0 + 8 <= a.h_out) continue;
+#pragma unroll 1
+    for (int s = sb; s < se; s++)
+      input_chunk<TC, TZ>(a, q, wt, (long)s * a.N + p0 + pl, s, p0 + pl, c0);
+  }
+}
+
+// Point-major when a workgroup's items cover a padded row, else row-major over g
+// workgroups.  At least 2048 workgroups: rows split into groups when the points
+// alone give fewer.
+template <typename TC, typename TZ>
+static void launch_rows_pm(const FwdLayerArgs& a, const TC* q, const TC* wt, int g,
+                           hipStream_t st) {
+  const int cpr = (int)((a.padz > 0 ? a.padz : a.ldzo) / 8);
+  if (cpr > 256 * kRowsPmItems) {
+    k_input_rows<TC, TZ><<<g, 256, 0, st>>>(a, q, wt);
+    return;
+  }
+  const int P = std::max(1, std::min(64, 256 * kRowsPmItems / cpr));
+  const int nx = (a.N + P - 1) / P;
+  const int sg = std::max(1, std::min(a.S, (2048 + nx - 1) / nx));
+  k_input_rows_pm<TC, TZ><<<dim3(nx, sg), 256, 0, st>>>(a, q, wt, P);
 }
 
 __global__ __launch_bounds__(256) void k_fwdlap_finish4_group(const FinJob* __restrict__ jobs,
@@ -1750,7 +1842,7 @@ hipError_t input_layer_rows(int mode, const FwdLayerArgs& a, void* q, hipStream_
         k_input_q_dirs<bf16, float><<<nd256, 256, 0, st>>>(a, qq, qq + a.h_out);
       else
         k_input_q<bf16, float><<<nq, 256, 0, st>>>(a, qq, qq + a.h_out);
-      k_input_rows<float, bf16><<<g, 256, 0, st>>>(a, qq, qq + a.h_out);
+      launch_rows_pm<float, bf16>(a, qq, qq + a.h_out, g, st);
       break;
     }
     case M_BF16X3: {
